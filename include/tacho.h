@@ -1,0 +1,222 @@
+/*
+ * tacho.h -- C ABI of the MI355X (gfx950) supernodal multifrontal sparse
+ * Cholesky library.
+ *
+ * The library solves A x = b for a sparse symmetric positive definite A in
+ * the three phases of the paper's Trilinos section (symbolic analysis,
+ * numerical setup, solve), with the Tacho section's method: a multifrontal
+ * factorization P A P^T = L L^T scheduled by levels of the supernodal
+ * elimination tree, followed by supernodal forward and backward
+ * substitution scheduled by the same levels (solve variant 1 of that
+ * section).  Symbolic analysis runs on the host (it uses only the sparsity
+ * pattern and is reused across value changes); the numeric phase and the
+ * solves run in HIP kernels on the GPU.
+ *
+ * Conventions for every call:
+ *   - Return value: TACHO_OK (0) or one of the negative TACHO_ERR_* codes;
+ *     tacho_strerror() names them, tacho_last_error() gives a message for
+ *     the calling thread's most recent failure.
+ *   - Host pointers are read during the call only; the library copies what
+ *     it keeps.  Device pointers must be valid on the given stream until the
+ *     work queued by the call has finished.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  All device
+ *     work of a call is queued on it.
+ *   - A handle serves one call at a time; different handles may be used
+ *     concurrently from different threads on different streams.
+ *   - Dense blocks (right-hand sides, solutions) are column-major with a
+ *     leading dimension ld >= n.
+ */
+#ifndef TACHO_MI355X_H
+#define TACHO_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TACHO_OK 0
+#define TACHO_ERR_INVALID (-1) /* bad argument or malformed CSR */
+#define TACHO_ERR_PATTERN (-2) /* pattern not structurally symmetric */
+#define TACHO_ERR_NOT_SPD (-3) /* non-positive or NaN pivot */
+#define TACHO_ERR_NOMEM (-4)   /* out of device memory or over the HBM budget */
+#define TACHO_ERR_HIP (-5)     /* a HIP runtime call failed */
+
+/* Precision of the numeric factorization (the paper's templated scalar
+ * types, Trilinos section, and iterative refinement with computed factors,
+ * Basker section). */
+#define TACHO_FP64 0 /* FP64 fronts, FP64 solves */
+#define TACHO_FP32 1 /* FP32 fronts; tacho_solve refines in FP64 */
+
+typedef struct tacho_sym *tacho_sym_t;
+typedef struct tacho_num *tacho_num_t;
+
+typedef struct {
+  int32_t nd_leaf_size;      /* nested dissection stops at parts of at most this many
+                                vertices (default 8) */
+  int32_t small_front;       /* fronts with m <= small_front are assembled and factored
+                                in LDS by one workgroup (0 = library default) */
+  int32_t scale;             /* FP32 path: symmetric Jacobi scaling diag(C)^{-1/2} (default 1) */
+  int32_t refine_max;        /* FP32 path: at most this many corrections (default 10) */
+  double refine_tol;         /* FP32 path: stop when ||b - A x||_2 / ||b||_2 <= tol
+                                for every column (default 1e-10) */
+  double stall_ratio;        /* FP32 path: a step with rho_k > stall_ratio * rho_{k-1},
+                                twice in a row, counts as a stall (default 0.5) */
+  uint64_t hbm_budget_bytes; /* 0 = no limit; tacho_factorize returns TACHO_ERR_NOMEM
+                                when the factor plus workspace would exceed it */
+  int32_t block_size;        /* panel width of the blocked large-front path (0 = 64) */
+  int32_t reserved[7];
+} tacho_options;
+
+/* Fill `opt` with the defaults listed above. */
+void tacho_default_options(tacho_options *opt);
+
+typedef struct {
+  int64_t n;                /* order of A */
+  int64_t nnz_a;            /* stored entries of the full symmetric pattern (plus added
+                               diagonal entries) */
+  int64_t nnz_l;            /* sum_j eta_j: entries of L including the diagonal */
+  int64_t flops;            /* sum_j eta_j^2: algorithmic factorization flops */
+  int64_t nsuper;           /* fundamental supernodes */
+  int64_t nlevels;          /* height of the supernodal elimination forest + 1 */
+  int64_t max_front;        /* largest front order m */
+  int64_t max_width;        /* largest supernode width w */
+  int64_t factor_bytes_fp64; /* device bytes of the FP64 factor panels */
+  int64_t work_bytes_fp64;  /* peak device bytes of the FP64 update matrices */
+  int64_t device_bytes_fp64; /* all device memory of one FP64 numeric handle (nrhs = 1) */
+  int64_t nsystems;         /* independent systems (1 unless built by tacho_analyze_batch) */
+} tacho_sym_info;
+
+typedef struct {
+  int32_t iters;      /* FP32 path: refinement corrections applied (0 for FP64) */
+  int32_t fell_back;  /* FP32 path: 1 if refinement stalled and the solve was redone
+                         with an FP64 refactorization (still a success) */
+  double relres_max;  /* max over columns of ||b - A x||_2 / ||b||_2 (FP32 path) */
+  double *relres;     /* optional, caller-owned array of nrhs entries receiving the
+                         per-column relative residual (FP32 path), or NULL */
+} tacho_solve_info;
+
+/*
+ * Symbolic analysis (Trilinos section, step 1: pattern only, done once per
+ * pattern on one host core; Tacho section: nested-dissection reordering, as
+ * the land-ice runs use METIS).
+ *   n        order of A (n >= 0)
+ *   rowptr   host int64[n+1], 0-based CSR row pointers, rowptr[0] = 0
+ *   colind   host int32[rowptr[n]], column indices of the FULL symmetric
+ *            pattern; unsorted rows are accepted, duplicates are rejected
+ *            (TACHO_ERR_INVALID), a structurally unsymmetric pattern gives
+ *            TACHO_ERR_PATTERN; a missing diagonal entry is added
+ *   opt      options or NULL for the defaults
+ *   out      receives the symbolic handle (owned by the caller, released with
+ *            tacho_free_symbolic)
+ * The handle holds: the fill-reducing permutation (own nested dissection,
+ * composed with an elimination-tree postorder), the elimination tree, the
+ * column counts, fundamental supernodes, their row structures, the
+ * child-to-parent relative maps, the A-entry-to-front maps, the level
+ * schedule and the device memory plan.  No device work is queued.
+ */
+int tacho_analyze(int64_t n, const int64_t *rowptr, const int32_t *colind,
+                  const tacho_options *opt, tacho_sym_t *out);
+
+/*
+ * Symbolic analysis of `nsys` independent systems solved together (the
+ * single-GPU analogue of the many MPI ranks per GPU of the paper's land-ice
+ * runs).  System k has order n[k] and CSR arrays rowptr[k], colind[k] as in
+ * tacho_analyze.  The handle represents the block-diagonal matrix of all
+ * systems in order; values, right-hand sides and solutions are the
+ * concatenation of the systems' arrays.  Each level of the merged
+ * elimination forest is factored by one launch sequence for all systems.
+ */
+int tacho_analyze_batch(int64_t nsys, const int64_t *n, const int64_t *const *rowptr,
+                        const int32_t *const *colind, const tacho_options *opt,
+                        tacho_sym_t *out);
+
+/* Scalars of a symbolic handle. */
+int tacho_query_symbolic(tacho_sym_t sym, tacho_sym_info *info);
+
+/*
+ * Copies of the symbolic arrays (any pointer may be NULL):
+ *   perm[n]          new -> old: row/column i of P A P^T is row/column perm[i] of A
+ *   parent[n]        elimination tree of P A P^T, -1 for roots
+ *   colcount[n]      eta_j, nonzeros of column j of L including the diagonal
+ *   super_ptr[ns+1]  first column of each fundamental supernode
+ *   super_parent[ns] supernodal parent, -1 for roots
+ *   level[ns]        level (height) of each supernode, leaves are 0
+ */
+int tacho_get_symbolic(tacho_sym_t sym, int32_t *perm, int32_t *parent, int64_t *colcount,
+                       int32_t *super_ptr, int32_t *super_parent, int32_t *level);
+
+/*
+ * Numerical factorization (Trilinos section, step 2; Tacho section:
+ * multifrontal Cholesky with level-set scheduling).
+ *   sym               symbolic handle (must outlive the numeric handle)
+ *   values            float64[nnz] aligned with the colind given to
+ *                     tacho_analyze (concatenated per system for a batch);
+ *                     only entries with row >= column are read, numerical
+ *                     symmetry is the caller's contract
+ *   values_on_device  0: host pointer; 1: device pointer used on hip_stream
+ *   precision         TACHO_FP64 or TACHO_FP32
+ *   out               receives the numeric handle, which owns the device factor
+ *   fail_index        optional; on TACHO_ERR_NOT_SPD receives the original
+ *                     index of the first column (in elimination order) whose
+ *                     pivot was not positive; no handle is created then
+ * Blocks the calling thread until the device work is finished (one
+ * device-to-host read of the failure flag).
+ */
+int tacho_factorize(tacho_sym_t sym, const double *values, int values_on_device, int precision,
+                    void *hip_stream, tacho_num_t *out, int64_t *fail_index);
+
+/*
+ * Refactorization with new values on the same pattern (Trilinos section:
+ * the symbolic analysis is amortized across value changes).  Same arguments
+ * as tacho_factorize; the handle keeps its precision and device memory.  On
+ * TACHO_ERR_NOT_SPD the handle stays valid but holds no usable factor.
+ * With `sync` = 0 the call returns without waiting and the failure flag is
+ * read by the next tacho_solve or tacho_check_factor.
+ */
+int tacho_refactorize(tacho_num_t num, const double *values, int values_on_device,
+                      void *hip_stream, int sync, int64_t *fail_index);
+
+/* Wait for the last factorization of `num` and report its failure flag. */
+int tacho_check_factor(tacho_num_t num, int64_t *fail_index);
+
+/*
+ * Solve A X = B (Trilinos section, step 3; Tacho section, SpTRSV variant 1:
+ * level-set scheduled supernodal forward and backward substitution; several
+ * right-hand sides at once use block operations).
+ *   b, x        n x nrhs column-major blocks with leading dimension ld >= n;
+ *               x may equal b (in place)
+ *   on_device   0: host pointers; 1: device pointers used on hip_stream
+ *   info        optional refinement report (see tacho_solve_info)
+ * For an FP32 factor the solve refines in FP64: x = solve32(b), then
+ * r = b - A x (FP64 sparse product), x += solve32(r) until the relative
+ * residual of every column is <= refine_tol; when refinement stalls the
+ * handle is refactored in FP64 and the solve is repeated (info->fell_back).
+ * Blocks until the result is available when on_device = 0 or for the FP32
+ * path; the FP64 device path only queues work.
+ */
+int tacho_solve(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64_t ld,
+                int on_device, void *hip_stream, tacho_solve_info *info);
+
+/*
+ * Copy the factor L (of P A P^T, FP64 or FP32 widened to FP64) to host CSC
+ * arrays: Lp int64[n+1], Li int32[nnz_l], Lx float64[nnz_l]; every column
+ * sorted ascending with the diagonal first.  Synchronizes the handle.
+ */
+int tacho_get_factor(tacho_num_t num, int64_t *Lp, int32_t *Li, double *Lx);
+
+/* Device milliseconds of the last factorization and solve (hipEvent timing on the
+ * caller's stream; valid once that work has finished). */
+int tacho_last_times(tacho_num_t num, double *factor_ms, double *solve_ms);
+
+int tacho_free_symbolic(tacho_sym_t sym);
+int tacho_free_numeric(tacho_num_t num);
+const char *tacho_strerror(int code);
+const char *tacho_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TACHO_MI355X_H */

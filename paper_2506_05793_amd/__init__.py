@@ -1,0 +1,336 @@
+"""Python binding of the MI355X supernodal multifrontal Cholesky library.
+
+Argument marshalling only: every step of the factorization and the solves
+runs in the HIP library ``libtacho_mi355x.so`` (built by ``build.py``).  The
+functions carry the names of the C ABI in ``include/tacho.h``.  Host arrays
+are numpy arrays; device arrays are torch tensors on the current ROCm device,
+used on torch's current stream.  There is no CPU fallback: if the library is
+missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtacho_mi355x.so")
+
+TACHO_OK = 0
+TACHO_ERR_INVALID = -1
+TACHO_ERR_PATTERN = -2
+TACHO_ERR_NOT_SPD = -3
+TACHO_ERR_NOMEM = -4
+TACHO_ERR_HIP = -5
+TACHO_FP64 = 0
+TACHO_FP32 = 1
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class tacho_options(ctypes.Structure):
+    _fields_ = [
+        ("nd_leaf_size", ctypes.c_int32),
+        ("small_front", ctypes.c_int32),
+        ("scale", ctypes.c_int32),
+        ("refine_max", ctypes.c_int32),
+        ("refine_tol", ctypes.c_double),
+        ("stall_ratio", ctypes.c_double),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("block_size", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class tacho_sym_info(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n", "nnz_a", "nnz_l", "flops", "nsuper", "nlevels", "max_front", "max_width",
+        "factor_bytes_fp64", "work_bytes_fp64", "device_bytes_fp64", "nsystems")]
+
+
+class tacho_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("fell_back", ctypes.c_int32),
+        ("relres_max", ctypes.c_double),
+        ("relres", _f64p),
+    ]
+
+
+class TachoError(RuntimeError):
+    def __init__(self, code: int, message: str, fail_index: int = -1):
+        super().__init__(f"{message} (code {code})")
+        self.code = code
+        self.fail_index = fail_index
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_2506_05793_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "tacho_default_options": (None, [ctypes.POINTER(tacho_options)]),
+        "tacho_analyze": (ctypes.c_int, [ctypes.c_int64, _i64p, _i32p,
+                                         ctypes.POINTER(tacho_options), ctypes.POINTER(_vp)]),
+        "tacho_analyze_batch": (ctypes.c_int, [ctypes.c_int64, _i64p, ctypes.POINTER(_i64p),
+                                               ctypes.POINTER(_i32p),
+                                               ctypes.POINTER(tacho_options),
+                                               ctypes.POINTER(_vp)]),
+        "tacho_query_symbolic": (ctypes.c_int, [_vp, ctypes.POINTER(tacho_sym_info)]),
+        "tacho_get_symbolic": (ctypes.c_int, [_vp, _i32p, _i32p, _i64p, _i32p, _i32p, _i32p]),
+        "tacho_factorize": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp,
+                                           ctypes.POINTER(_vp), _i64p]),
+        "tacho_refactorize": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _i64p]),
+        "tacho_check_factor": (ctypes.c_int, [_vp, _i64p]),
+        "tacho_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                       _vp, ctypes.POINTER(tacho_solve_info)]),
+        "tacho_get_factor": (ctypes.c_int, [_vp, _i64p, _i32p, _f64p]),
+        "tacho_last_times": (ctypes.c_int, [_vp, _f64p, _f64p]),
+        "tacho_free_symbolic": (ctypes.c_int, [_vp]),
+        "tacho_free_numeric": (ctypes.c_int, [_vp]),
+        "tacho_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "tacho_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> list[str]:
+    """Names of the C ABI entry points this binding resolves."""
+    _load()
+    return [n for n in dir(_lib) if n.startswith("tacho_")]
+
+
+def _check(rc: int, fail_index: int = -1):
+    if rc != TACHO_OK:
+        lib = _load()
+        msg = lib.tacho_last_error().decode() or lib.tacho_strerror(rc).decode()
+        raise TachoError(rc, msg, fail_index)
+
+
+def tacho_default_options(**overrides) -> tacho_options:
+    opt = tacho_options()
+    _load().tacho_default_options(ctypes.byref(opt))
+    for k, v in overrides.items():
+        setattr(opt, k, v)
+    return opt
+
+
+class SymbolicHandle:
+    """Owner of a ``tacho_sym_t``."""
+
+    def __init__(self, ptr: int):
+        self.ptr = ptr
+        self._lib = _load()
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            self._lib.tacho_free_symbolic(self.ptr)
+            self.ptr = None
+
+
+class NumericHandle:
+    """Owner of a ``tacho_num_t``; keeps its symbolic handle alive."""
+
+    def __init__(self, ptr: int, sym: SymbolicHandle, precision: int):
+        self.ptr = ptr
+        self.sym = sym
+        self.precision = precision
+        self._lib = _load()
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            self._lib.tacho_free_numeric(self.ptr)
+            self.ptr = None
+
+
+def tacho_analyze(n, rowptr, colind, options: tacho_options | None = None) -> SymbolicHandle:
+    lib = _load()
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colind = np.ascontiguousarray(colind, dtype=np.int32)
+    out = _vp()
+    rc = lib.tacho_analyze(int(n), rowptr.ctypes.data_as(_i64p), colind.ctypes.data_as(_i32p),
+                           ctypes.byref(options) if options is not None else None,
+                           ctypes.byref(out))
+    _check(rc)
+    return SymbolicHandle(out.value)
+
+
+def tacho_analyze_batch(systems, options: tacho_options | None = None) -> SymbolicHandle:
+    """``systems``: sequence of (n, rowptr, colind)."""
+    lib = _load()
+    k = len(systems)
+    ns = np.array([int(s[0]) for s in systems], dtype=np.int64)
+    rps = [np.ascontiguousarray(s[1], dtype=np.int64) for s in systems]
+    cis = [np.ascontiguousarray(s[2], dtype=np.int32) for s in systems]
+    rp_arr = (_i64p * k)(*[r.ctypes.data_as(_i64p) for r in rps])
+    ci_arr = (_i32p * k)(*[c.ctypes.data_as(_i32p) for c in cis])
+    out = _vp()
+    rc = lib.tacho_analyze_batch(k, ns.ctypes.data_as(_i64p), rp_arr, ci_arr,
+                                 ctypes.byref(options) if options is not None else None,
+                                 ctypes.byref(out))
+    _check(rc)
+    return SymbolicHandle(out.value)
+
+
+def tacho_query_symbolic(sym: SymbolicHandle) -> dict:
+    info = tacho_sym_info()
+    _check(_load().tacho_query_symbolic(sym.ptr, ctypes.byref(info)))
+    return {name: int(getattr(info, name)) for name, _ in tacho_sym_info._fields_}
+
+
+@dataclass
+class SymbolicArrays:
+    perm: np.ndarray
+    parent: np.ndarray
+    colcount: np.ndarray
+    super_ptr: np.ndarray
+    super_parent: np.ndarray
+    level: np.ndarray
+
+
+def tacho_get_symbolic(sym: SymbolicHandle) -> SymbolicArrays:
+    q = tacho_query_symbolic(sym)
+    n, ns = q["n"], q["nsuper"]
+    perm = np.empty(n, np.int32)
+    parent = np.empty(n, np.int32)
+    cc = np.empty(n, np.int64)
+    sp = np.empty(ns + 1, np.int32)
+    spar = np.empty(ns, np.int32)
+    lev = np.empty(ns, np.int32)
+    _check(_load().tacho_get_symbolic(sym.ptr, perm.ctypes.data_as(_i32p),
+                                      parent.ctypes.data_as(_i32p), cc.ctypes.data_as(_i64p),
+                                      sp.ctypes.data_as(_i32p), spar.ctypes.data_as(_i32p),
+                                      lev.ctypes.data_as(_i32p)))
+    return SymbolicArrays(perm, parent, cc, sp, spar, lev)
+
+
+def _stream_ptr(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr_of(arr):
+    """(address, on_device) of a numpy array or a torch tensor."""
+    if isinstance(arr, np.ndarray):
+        return arr.ctypes.data, 0
+    import torch
+    if isinstance(arr, torch.Tensor):
+        if arr.device.type == "cuda":
+            return arr.data_ptr(), 1
+        return arr.data_ptr(), 0
+    raise TypeError("expected a numpy array or a torch tensor")
+
+
+def tacho_factorize(sym: SymbolicHandle, values, precision: int = TACHO_FP64,
+                    stream=None) -> NumericHandle:
+    lib = _load()
+    if isinstance(values, np.ndarray):
+        values = np.ascontiguousarray(values, dtype=np.float64)
+    addr, on_dev = _ptr_of(values)
+    out = _vp()
+    fi = ctypes.c_int64(-1)
+    rc = lib.tacho_factorize(sym.ptr, addr, on_dev, int(precision), _stream_ptr(stream),
+                             ctypes.byref(out), ctypes.byref(fi))
+    _check(rc, fi.value)
+    return NumericHandle(out.value, sym, precision)
+
+
+def tacho_refactorize(num: NumericHandle, values, stream=None, sync: bool = True) -> None:
+    lib = _load()
+    if isinstance(values, np.ndarray):
+        values = np.ascontiguousarray(values, dtype=np.float64)
+    addr, on_dev = _ptr_of(values)
+    fi = ctypes.c_int64(-1)
+    rc = lib.tacho_refactorize(num.ptr, addr, on_dev, _stream_ptr(stream), int(bool(sync)),
+                               ctypes.byref(fi))
+    _check(rc, fi.value)
+
+
+def tacho_check_factor(num: NumericHandle) -> None:
+    fi = ctypes.c_int64(-1)
+    rc = _load().tacho_check_factor(num.ptr, ctypes.byref(fi))
+    _check(rc, fi.value)
+
+
+def tacho_solve(num: NumericHandle, b, x=None, stream=None, with_info: bool = False):
+    """Solve A X = B.  ``b`` (n or n x nrhs, column-major) is a numpy array or a
+    device tensor; ``x`` defaults to a new array of the same kind."""
+    lib = _load()
+    vec = b.ndim == 1
+    n = b.shape[0]
+    nrhs = 1 if vec else b.shape[1]
+    if isinstance(b, np.ndarray):
+        b = np.asfortranarray(b, dtype=np.float64)
+        if x is None:
+            x = np.empty_like(b, order="F")
+        ld = n
+    else:
+        import torch
+        if b.dim() == 2:
+            if b.stride(0) != 1:
+                b = b.t().contiguous().t()
+            ld = b.stride(1) if nrhs > 1 else n
+        else:
+            ld = n
+        if x is None:
+            x = torch.empty_strided(b.shape, b.stride(), dtype=torch.float64, device=b.device)
+    ba, on_dev = _ptr_of(b)
+    xa, _ = _ptr_of(x)
+    info = tacho_solve_info()
+    rr = np.zeros(max(nrhs, 1), np.float64)
+    info.relres = rr.ctypes.data_as(_f64p)
+    rc = lib.tacho_solve(num.ptr, ba, xa, int(nrhs), int(ld), on_dev, _stream_ptr(stream),
+                         ctypes.byref(info))
+    _check(rc)
+    if with_info:
+        return x, {"iters": info.iters, "fell_back": info.fell_back,
+                   "relres_max": info.relres_max, "relres": rr[:nrhs].copy()}
+    return x
+
+
+def tacho_get_factor(num: NumericHandle):
+    """Factor L of P A P^T as CSC arrays (Lp, Li, Lx) on the host."""
+    q = tacho_query_symbolic(num.sym)
+    n, nnz = q["n"], q["nnz_l"]
+    Lp = np.empty(n + 1, np.int64)
+    Li = np.empty(max(nnz, 1), np.int32)
+    Lx = np.empty(max(nnz, 1), np.float64)
+    _check(_load().tacho_get_factor(num.ptr, Lp.ctypes.data_as(_i64p), Li.ctypes.data_as(_i32p),
+                                    Lx.ctypes.data_as(_f64p)))
+    return Lp, Li[:nnz], Lx[:nnz]
+
+
+def tacho_last_times(num: NumericHandle):
+    """(factor_ms, solve_ms) of the last factorization and solve, hipEvent timed."""
+    a = ctypes.c_double(0)
+    b = ctypes.c_double(0)
+    _check(_load().tacho_last_times(num.ptr, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def tacho_factor_ms(num: NumericHandle) -> float:
+    a = ctypes.c_double(0)
+    _check(_load().tacho_last_times(num.ptr, ctypes.byref(a), None))
+    return a.value

@@ -1,0 +1,747 @@
+// C ABI of the library: handles, device memory, launch sequences.
+//
+// Three phases as in the paper's Trilinos section: tacho_analyze (pattern
+// only, host), tacho_factorize / tacho_refactorize (numeric, GPU, level by
+// level of the supernodal elimination tree), tacho_solve (forward and
+// backward supernodal substitution by levels, Tacho section variant 1), plus
+// FP32 factors with FP64 iterative refinement (templated precisions,
+// Trilinos section; refinement with computed factors, Basker section).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tacho.h"
+#include "device.hpp"
+#include "plan.hpp"
+#include "symbolic.hpp"
+
+using namespace tacho;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      if (e_ == hipErrorOutOfMemory)                                                   \
+        return fail(TACHO_ERR_NOMEM, std::string("out of device memory: ") + #expr);  \
+      return fail(TACHO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    }                                                                                  \
+  } while (0)
+
+// Owning device allocation.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t b) {
+    reset();
+    if (b == 0) b = 64;
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    else p = nullptr;
+    return e;
+  }
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+hipError_t upload(DBuf& d, const std::vector<T>& v) {
+  hipError_t e = d.alloc(v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+}  // namespace
+
+struct tacho_sym {
+  tacho_options opt;
+  Symbolic S;
+  Plan P;
+  std::vector<int64_t> mirror;    // per pattern entry: caller index of the lower twin (-1: none)
+  std::vector<int32_t> a_prc;     // per assembly entry: permuted row, permuted column
+  std::vector<int32_t> solve_levels;  // level_list copy (supernodes by level)
+  // device copies
+  bool uploaded = false;
+  int device = -1;
+  DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
+      d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q;
+  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_levels;
+  DBuf d_rowptr, d_colind, d_mirror;
+  DevSym view{};
+  std::mutex mu;
+};
+
+struct tacho_num {
+  tacho_sym* sym = nullptr;
+  int precision = TACHO_FP64;
+  DBuf L, U, avals, vals, fullvals, scale, fail;
+  DBuf y, uvec;             // solve workspace (kRhs columns)
+  DBuf bdev, xdev, r, dx, norms;  // host-pointer staging and refinement buffers
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool pending = false;     // factorization queued, flag not yet read
+  int last_status = TACHO_OK;
+  int64_t last_fail = -1;
+  hipStream_t last_stream = nullptr;
+  tacho_num* fallback = nullptr;  // FP64 refactorization after a refinement stall
+  ~tacho_num() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    delete fallback;
+  }
+};
+
+namespace {
+
+constexpr int kRhs = 16;  // right-hand sides per solve sweep
+
+tacho_options defaults() {
+  tacho_options o;
+  std::memset(&o, 0, sizeof(o));
+  o.nd_leaf_size = 8;
+  o.small_front = 0;
+  o.scale = 1;
+  o.refine_max = 10;
+  o.refine_tol = 1e-10;
+  o.stall_ratio = 0.5;
+  o.hbm_budget_bytes = 0;
+  o.block_size = 0;
+  return o;
+}
+
+int finish_analysis(tacho_sym* h, int64_t nnz_input) {
+  std::string err;
+  h->S.nnz_input = nnz_input;
+  SymOptions so;
+  so.nd_leaf_size = h->opt.nd_leaf_size > 0 ? h->opt.nd_leaf_size : 8;
+  int rc = analyze_pattern(h->S, so, err);
+  if (rc != kOk) return fail(rc, err);
+  rc = build_plan(h->S, h->P, err);
+  if (rc != kOk) return fail(rc, err);
+  const Symbolic& S = h->S;
+  // lower-twin index of every pattern entry, for the refinement residual
+  const Pattern& A = S.A;
+  h->mirror.assign(A.colind.size(), -1);
+  for (int64_t i = 0; i < A.n; ++i)
+    for (int64_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+      const int32_t j = A.colind[k];
+      if (i >= j) {
+        h->mirror[k] = A.src[k];
+      } else {
+        // twin (j, i) lies in row j, sorted
+        const int32_t* b = A.colind.data() + A.rowptr[j];
+        const int32_t* e = A.colind.data() + A.rowptr[j + 1];
+        const int32_t* p = std::lower_bound(b, e, (int32_t)i);
+        h->mirror[k] = A.src[A.rowptr[j] + (p - b)];
+      }
+    }
+  h->a_prc.resize(2 * S.a_src.size());
+  for (int32_t s = 0; s < S.ns; ++s)
+    for (int32_t j = S.sptr[s]; j < S.sptr[s + 1]; ++j)
+      for (int64_t q = S.acol_ptr[j]; q < S.acol_ptr[j + 1]; ++q) {
+        h->a_prc[2 * q] = S.rows[S.rows_ptr[s] + S.a_row[q]];
+        h->a_prc[2 * q + 1] = j;
+      }
+  return TACHO_OK;
+}
+
+int ensure_uploaded(tacho_sym* h) {
+  std::lock_guard<std::mutex> lock(h->mu);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (h->uploaded) {
+    if (dev != h->device) return fail(TACHO_ERR_INVALID, "symbolic handle used on another device");
+    return TACHO_OK;
+  }
+  const Symbolic& S = h->S;
+  const Plan& P = h->P;
+  HIP_TRY(upload(h->d_sptr, S.sptr));
+  HIP_TRY(upload(h->d_front_m, S.front_m));
+  HIP_TRY(upload(h->d_rows_ptr, S.rows_ptr));
+  HIP_TRY(upload(h->d_rows, S.rows));
+  HIP_TRY(upload(h->d_rmap, S.rmap));
+  HIP_TRY(upload(h->d_child_ptr, S.child_ptr));
+  HIP_TRY(upload(h->d_child_list, S.child_list));
+  HIP_TRY(upload(h->d_acol_ptr, S.acol_ptr));
+  HIP_TRY(upload(h->d_a_pos, P.a_pos));
+  HIP_TRY(upload(h->d_a_src, S.a_src));
+  HIP_TRY(upload(h->d_a_prc, h->a_prc));
+  HIP_TRY(upload(h->d_L_off, P.L_off));
+  HIP_TRY(upload(h->d_ldL, P.ldL));
+  HIP_TRY(upload(h->d_U_off, P.U_off));
+  HIP_TRY(upload(h->d_ldU, P.ldU));
+  HIP_TRY(upload(h->d_u_off, P.u_off));
+  HIP_TRY(upload(h->d_perm, S.perm));
+  HIP_TRY(upload(h->d_diag_q, P.diag_q));
+  HIP_TRY(upload(h->d_small, P.small_list));
+  HIP_TRY(upload(h->d_asm, P.asm_items));
+  HIP_TRY(upload(h->d_diag, P.diag_items));
+  HIP_TRY(upload(h->d_panel, P.panel_items));
+  HIP_TRY(upload(h->d_probs, P.probs));
+  HIP_TRY(upload(h->d_tiles, P.tiles));
+  HIP_TRY(upload(h->d_levels, S.level_list));
+  HIP_TRY(upload(h->d_rowptr, S.A.rowptr));
+  HIP_TRY(upload(h->d_colind, S.A.colind));
+  HIP_TRY(upload(h->d_mirror, h->mirror));
+  DevSym& v = h->view;
+  v.n = S.n;
+  v.sptr = h->d_sptr.as<int32_t>();
+  v.front_m = h->d_front_m.as<int32_t>();
+  v.rows_ptr = h->d_rows_ptr.as<int64_t>();
+  v.rows = h->d_rows.as<int32_t>();
+  v.rmap = h->d_rmap.as<int32_t>();
+  v.child_ptr = h->d_child_ptr.as<int32_t>();
+  v.child_list = h->d_child_list.as<int32_t>();
+  v.acol_ptr = h->d_acol_ptr.as<int64_t>();
+  v.a_pos = h->d_a_pos.as<int32_t>();
+  v.a_src = h->d_a_src.as<int64_t>();
+  v.a_prc = h->d_a_prc.as<int32_t>();
+  v.L_off = h->d_L_off.as<int64_t>();
+  v.ldL = h->d_ldL.as<int32_t>();
+  v.U_off = h->d_U_off.as<int64_t>();
+  v.ldU = h->d_ldU.as<int32_t>();
+  v.u_off = h->d_u_off.as<int64_t>();
+  v.perm = h->d_perm.as<int32_t>();
+  v.diag_q = h->d_diag_q.as<int32_t>();
+  h->device = dev;
+  h->uploaded = true;
+  return TACHO_OK;
+}
+
+size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
+
+// Device bytes a numeric handle needs (factor, update workspace, values,
+// solve workspace for kRhs columns).
+int64_t numeric_bytes(const tacho_sym* h, int precision) {
+  const size_t es = elem_size(precision);
+  const Symbolic& S = h->S;
+  const Plan& P = h->P;
+  int64_t b = 0;
+  b += (int64_t)es * P.L_elems + (int64_t)es * P.U_elems + (int64_t)es * (int64_t)S.a_src.size();
+  b += 8 * S.nnz_input + 4;
+  b += (int64_t)es * (S.n + P.u_elems) * kRhs;
+  if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;
+  return b;
+}
+
+template <typename T>
+DevNum<T> num_view(tacho_num* f) {
+  DevNum<T> N;
+  N.L = f->L.as<T>();
+  N.U = f->U.as<T>();
+  N.avals = f->avals.as<T>();
+  N.scale = f->precision == TACHO_FP32 && f->sym->opt.scale ? f->scale.as<double>() : nullptr;
+  N.fail = f->fail.as<int32_t>();
+  return N;
+}
+
+template <typename T>
+void run_factor_steps(tacho_num* f, hipStream_t st) {
+  tacho_sym* h = f->sym;
+  const DevSym& S = h->view;
+  const Plan& P = h->P;
+  DevNum<T> N = num_view<T>(f);
+  const int32_t* small = h->d_small.as<int32_t>();
+  const AsmItem* asmi = h->d_asm.as<AsmItem>();
+  const PanelItem* dia = h->d_diag.as<PanelItem>();
+  const PanelItem* pan = h->d_panel.as<PanelItem>();
+  const GemmProb* probs = h->d_probs.as<GemmProb>();
+  const GemmTile* tiles = h->d_tiles.as<GemmTile>();
+  for (const Step& s : P.steps) {
+    const int64_t cnt = s.end - s.begin;
+    switch (s.kind) {
+      case kStepSmall: launch_small<T>(S, N, small + s.begin, cnt, st); break;
+      case kStepAssemble: launch_assemble<T>(S, N, asmi + s.begin, cnt, st); break;
+      case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, st); break;
+      case kStepPanel: launch_panel<T>(S, N, pan + s.begin, cnt, st); break;
+      case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, st); break;
+    }
+  }
+}
+
+int read_fail_flag(tacho_num* f, int64_t* fail_index) {
+  int32_t flag = INT32_MAX;
+  HIP_TRY(hipMemcpyAsync(&flag, f->fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, f->last_stream));
+  HIP_TRY(hipStreamSynchronize(f->last_stream));
+  f->pending = false;
+  if (flag != INT32_MAX) {
+    f->last_fail = f->sym->S.perm[flag];
+    f->last_status = TACHO_ERR_NOT_SPD;
+    if (fail_index) *fail_index = f->last_fail;
+    return fail(TACHO_ERR_NOT_SPD, "matrix is not positive definite (pivot " +
+                                       std::to_string(f->last_fail) + ")");
+  }
+  f->last_fail = -1;
+  f->last_status = TACHO_OK;
+  if (fail_index) *fail_index = -1;
+  return TACHO_OK;
+}
+
+int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, int sync,
+             int64_t* fail_index) {
+  tacho_sym* h = f->sym;
+  const Symbolic& S = h->S;
+  const int64_t nv = S.nnz_input;
+  if (nv > 0 && !values) return fail(TACHO_ERR_INVALID, "values is NULL");
+  if (nv > 0)
+    HIP_TRY(hipMemcpyAsync(f->vals.p, values, nv * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(f->ev[0], st));
+  launch_fill_i32(f->fail.as<int32_t>(), INT32_MAX, 1, st);
+  const double* vals = f->vals.as<double>();
+  const int64_t nq = (int64_t)S.a_src.size();
+  if (f->precision == TACHO_FP32) {
+    // full symmetric FP64 values (lower twins) for the refinement residual
+    launch_mirror(h->d_mirror.as<int64_t>(), vals, f->fullvals.as<double>(),
+                  (int64_t)S.A.colind.size(), st);
+    if (h->opt.scale) launch_scale(h->view, vals, f->scale.as<double>(), st);
+    launch_gather<float>(h->view, num_view<float>(f), vals, nq, st);
+    run_factor_steps<float>(f, st);
+  } else {
+    launch_gather<double>(h->view, num_view<double>(f), vals, nq, st);
+    run_factor_steps<double>(f, st);
+  }
+  HIP_TRY(hipEventRecord(f->ev[1], st));
+  HIP_TRY(hipGetLastError());
+  f->pending = true;
+  f->last_stream = st;
+  if (sync) return read_fail_flag(f, fail_index);
+  return TACHO_OK;
+}
+
+int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
+  int rc = ensure_uploaded(h);
+  if (rc != TACHO_OK) return rc;
+  const Symbolic& S = h->S;
+  const Plan& P = h->P;
+  const int64_t need = numeric_bytes(h, precision);
+  if (h->opt.hbm_budget_bytes > 0 && (uint64_t)need > h->opt.hbm_budget_bytes)
+    return fail(TACHO_ERR_NOMEM, "numeric handle needs " + std::to_string(need) +
+                                     " bytes, over the HBM budget");
+  std::unique_ptr<tacho_num> f(new tacho_num());
+  f->sym = h;
+  f->precision = precision;
+  const size_t es = elem_size(precision);
+  HIP_TRY(f->L.alloc(es * P.L_elems));
+  HIP_TRY(f->U.alloc(es * P.U_elems));
+  HIP_TRY(f->avals.alloc(es * S.a_src.size()));
+  HIP_TRY(f->vals.alloc(sizeof(double) * S.nnz_input));
+  HIP_TRY(f->fail.alloc(sizeof(int32_t)));
+  HIP_TRY(f->y.alloc(es * S.n * kRhs));
+  HIP_TRY(f->uvec.alloc(es * P.u_elems * kRhs));
+  if (precision == TACHO_FP32) {
+    HIP_TRY(f->scale.alloc(sizeof(double) * S.n));
+    HIP_TRY(f->fullvals.alloc(sizeof(double) * S.A.colind.size()));
+  }
+  for (auto& e : f->ev) HIP_TRY(hipEventCreate(&e));
+  *out = f.release();
+  return TACHO_OK;
+}
+
+// One sweep of forward + backward substitution for up to kRhs columns,
+// b (FP64, ld ldb) -> x (FP64, ld ldx), x += result when accumulate.
+template <typename T>
+void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                 int accumulate, hipStream_t st) {
+  tacho_sym* h = f->sym;
+  const Symbolic& S = h->S;
+  const DevSym& V = h->view;
+  const double* scale = f->precision == TACHO_FP32 && h->opt.scale ? f->scale.as<double>() : nullptr;
+  T* y = f->y.as<T>();
+  T* uv = f->uvec.as<T>();
+  const T* L = f->L.as<T>();
+  const int32_t* lv = h->d_levels.as<int32_t>();
+  launch_permute_in<T>(V, b, ldb, y, nrhs, scale, st);
+  for (int32_t lvl = 0; lvl < S.nlevels; ++lvl)
+    launch_fwd<T>(V, L, y, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
+                  nrhs, st);
+  for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl)
+    launch_bwd<T>(V, L, y, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl], nrhs,
+                  st);
+  launch_permute_out<T>(V, y, x, ldx, nrhs, scale, accumulate, st);
+}
+
+template <typename T>
+void solve_all(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t ldx, int64_t nrhs,
+               int accumulate, hipStream_t st) {
+  for (int64_t c = 0; c < nrhs; c += kRhs) {
+    const int nb = (int)std::min<int64_t>(kRhs, nrhs - c);
+    solve_sweep<T>(f, b + c * ldb, ldb, x + c * ldx, ldx, nb, accumulate, st);
+  }
+}
+
+// FP32 factor + FP64 refinement on device buffers b (ld n) -> x (ld n).
+int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStream_t st,
+                 tacho_solve_info* info) {
+  tacho_sym* h = f->sym;
+  const Symbolic& S = h->S;
+  const int64_t n = S.n;
+  if (!f->r.p || f->r.bytes < sizeof(double) * n * nrhs) HIP_TRY(f->r.alloc(sizeof(double) * n * nrhs));
+  if (!f->norms.p || f->norms.bytes < sizeof(double) * 2 * nrhs)
+    HIP_TRY(f->norms.alloc(sizeof(double) * 2 * nrhs));
+  double* r = f->r.as<double>();
+  double* nrm = f->norms.as<double>();
+  std::vector<double> hn(2 * nrhs), rho(nrhs), prev(nrhs, INFINITY);
+  std::vector<int> stalls(nrhs, 0), done(nrhs, 0);
+  launch_colnorms(n, b, n, nrhs, nrm + nrhs, st);
+  solve_all<float>(f, b, n, x, n, nrhs, 0, st);
+  const double tol = h->opt.refine_tol > 0 ? h->opt.refine_tol : 1e-10;
+  const int maxit = h->opt.refine_max > 0 ? h->opt.refine_max : 10;
+  const double ratio = h->opt.stall_ratio > 0 ? h->opt.stall_ratio : 0.5;
+  int iters = 0;
+  bool stalled = false;
+  for (;;) {
+    launch_residual(n, h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(),
+                    f->fullvals.as<double>(), b, n, x, n, r, nrhs, st);
+    launch_colnorms(n, r, n, nrhs, nrm, st);
+    HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    bool all = true;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      const double bn = hn[nrhs + c];
+      rho[c] = bn > 0 ? hn[c] / bn : hn[c];
+      if (!(rho[c] == rho[c])) rho[c] = INFINITY;
+      if (done[c]) continue;
+      if (rho[c] <= tol) {
+        done[c] = 1;
+        continue;
+      }
+      all = false;
+      if (rho[c] > ratio * prev[c]) {
+        if (++stalls[c] >= 2) stalled = true;
+      } else {
+        stalls[c] = 0;
+      }
+      prev[c] = rho[c];
+    }
+    if (all) break;
+    if (stalled || iters >= maxit) {
+      stalled = true;
+      break;
+    }
+    // converged columns get a zero correction: clear their residual
+    for (int64_t c = 0; c < nrhs; ++c)
+      if (done[c]) HIP_TRY(hipMemsetAsync(r + c * n, 0, sizeof(double) * n, st));
+    solve_all<float>(f, r, n, x, n, nrhs, 1, st);
+    ++iters;
+  }
+  if (stalled) {
+    // FP64 refactorization with the same values, then an FP64 solve.
+    if (!f->fallback) {
+      tacho_num* g = nullptr;
+      int rc = create_numeric(h, TACHO_FP64, &g);
+      if (rc != TACHO_OK) return rc;
+      f->fallback = g;
+    }
+    int64_t fi = -1;
+    int rc = refactor(f->fallback, f->vals.as<double>(), 1, st, 1, &fi);
+    if (rc != TACHO_OK) return rc;
+    solve_all<double>(f->fallback, b, n, x, n, nrhs, 0, st);
+    launch_residual(n, h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(),
+                    f->fullvals.as<double>(), b, n, x, n, r, nrhs, st);
+    launch_colnorms(n, r, n, nrhs, nrm, st);
+    HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t c = 0; c < nrhs; ++c) {
+      const double bn = hn[nrhs + c];
+      rho[c] = bn > 0 ? hn[c] / bn : hn[c];
+    }
+  }
+  if (info) {
+    info->iters = iters;
+    info->fell_back = stalled ? 1 : 0;
+    double mx = 0;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      mx = std::max(mx, rho[c]);
+      if (info->relres) info->relres[c] = rho[c];
+    }
+    info->relres_max = mx;
+  }
+  return TACHO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tacho_default_options(tacho_options* opt) {
+  if (opt) *opt = defaults();
+}
+
+const char* tacho_strerror(int code) {
+  switch (code) {
+    case TACHO_OK: return "success";
+    case TACHO_ERR_INVALID: return "invalid argument";
+    case TACHO_ERR_PATTERN: return "pattern is not structurally symmetric";
+    case TACHO_ERR_NOT_SPD: return "matrix is not positive definite";
+    case TACHO_ERR_NOMEM: return "out of device memory or over the HBM budget";
+    case TACHO_ERR_HIP: return "HIP runtime error";
+    default: return "unknown error";
+  }
+}
+
+const char* tacho_last_error(void) { return g_last_error.c_str(); }
+
+int tacho_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                  const tacho_options* opt, tacho_sym_t* out) {
+  if (!out) return fail(TACHO_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || (n > 0 && (!rowptr || (!colind && rowptr[n] > 0))))
+    return fail(TACHO_ERR_INVALID, "invalid CSR arguments");
+  std::unique_ptr<tacho_sym> h(new tacho_sym());
+  h->opt = opt ? *opt : defaults();
+  std::string err;
+  int rc = build_pattern(n, rowptr, colind, h->S.A, err);
+  if (rc != kOk) return fail(rc, err);
+  h->S.nsys = 1;
+  h->S.sys_ptr = {0, n};
+  rc = finish_analysis(h.get(), n > 0 ? rowptr[n] : 0);
+  if (rc != TACHO_OK) return rc;
+  *out = h.release();
+  return TACHO_OK;
+}
+
+int tacho_analyze_batch(int64_t nsys, const int64_t* n, const int64_t* const* rowptr,
+                        const int32_t* const* colind, const tacho_options* opt,
+                        tacho_sym_t* out) {
+  if (!out) return fail(TACHO_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (nsys < 1 || !n || !rowptr || !colind) return fail(TACHO_ERR_INVALID, "invalid batch");
+  int64_t ntot = 0, nnz = 0;
+  for (int64_t k = 0; k < nsys; ++k) {
+    if (n[k] < 0 || (n[k] > 0 && !rowptr[k])) return fail(TACHO_ERR_INVALID, "invalid system");
+    ntot += n[k];
+    nnz += n[k] > 0 ? rowptr[k][n[k]] : 0;
+  }
+  if (ntot > INT32_MAX - 1) return fail(TACHO_ERR_INVALID, "batch too large");
+  std::vector<int64_t> rp(ntot + 1, 0);
+  std::vector<int32_t> ci;
+  ci.reserve(nnz);
+  std::vector<int64_t> sys_ptr(nsys + 1, 0);
+  int64_t roff = 0, koff = 0;
+  for (int64_t k = 0; k < nsys; ++k) {
+    for (int64_t i = 0; i < n[k]; ++i) {
+      for (int64_t q = rowptr[k][i]; q < rowptr[k][i + 1]; ++q) {
+        const int32_t c = colind[k][q];
+        if (c < 0 || c >= n[k]) return fail(TACHO_ERR_INVALID, "column index out of range");
+        ci.push_back((int32_t)(c + roff));
+      }
+      rp[roff + i + 1] = koff + rowptr[k][i + 1];
+    }
+    roff += n[k];
+    koff += n[k] > 0 ? rowptr[k][n[k]] : 0;
+    sys_ptr[k + 1] = roff;
+  }
+  std::unique_ptr<tacho_sym> h(new tacho_sym());
+  h->opt = opt ? *opt : defaults();
+  std::string err;
+  int rc = build_pattern(ntot, rp.data(), ci.data(), h->S.A, err);
+  if (rc != kOk) return fail(rc, err);
+  h->S.nsys = nsys;
+  h->S.sys_ptr = sys_ptr;
+  rc = finish_analysis(h.get(), nnz);
+  if (rc != TACHO_OK) return rc;
+  *out = h.release();
+  return TACHO_OK;
+}
+
+int tacho_query_symbolic(tacho_sym_t h, tacho_sym_info* info) {
+  if (!h || !info) return fail(TACHO_ERR_INVALID, "NULL argument");
+  const Symbolic& S = h->S;
+  info->n = S.n;
+  info->nnz_a = (int64_t)S.A.colind.size();
+  info->nnz_l = S.nnzL;
+  info->flops = S.flops;
+  info->nsuper = S.ns;
+  info->nlevels = S.nlevels;
+  info->max_front = S.max_m;
+  info->max_width = S.max_w;
+  info->factor_bytes_fp64 = 8 * h->P.L_elems;
+  info->work_bytes_fp64 = 8 * h->P.U_elems;
+  info->device_bytes_fp64 = numeric_bytes(h, TACHO_FP64);
+  info->nsystems = S.nsys;
+  return TACHO_OK;
+}
+
+int tacho_get_symbolic(tacho_sym_t h, int32_t* perm, int32_t* parent, int64_t* colcount,
+                       int32_t* super_ptr, int32_t* super_parent, int32_t* level) {
+  if (!h) return fail(TACHO_ERR_INVALID, "NULL handle");
+  const Symbolic& S = h->S;
+  if (perm) std::copy(S.perm.begin(), S.perm.end(), perm);
+  if (parent) std::copy(S.parent.begin(), S.parent.end(), parent);
+  if (colcount) std::copy(S.colcount.begin(), S.colcount.end(), colcount);
+  if (super_ptr) std::copy(S.sptr.begin(), S.sptr.end(), super_ptr);
+  if (super_parent) std::copy(S.sparent.begin(), S.sparent.end(), super_parent);
+  if (level) std::copy(S.height.begin(), S.height.end(), level);
+  return TACHO_OK;
+}
+
+int tacho_factorize(tacho_sym_t h, const double* values, int values_on_device, int precision,
+                    void* hip_stream, tacho_num_t* out, int64_t* fail_index) {
+  if (!h || !out) return fail(TACHO_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (fail_index) *fail_index = -1;
+  if (precision != TACHO_FP64 && precision != TACHO_FP32)
+    return fail(TACHO_ERR_INVALID, "unknown precision");
+  tacho_num* f = nullptr;
+  int rc = create_numeric(h, precision, &f);
+  if (rc != TACHO_OK) return rc;
+  rc = refactor(f, values, values_on_device, (hipStream_t)hip_stream, 1, fail_index);
+  if (rc != TACHO_OK) {
+    delete f;
+    return rc;
+  }
+  *out = f;
+  return TACHO_OK;
+}
+
+int tacho_refactorize(tacho_num_t f, const double* values, int values_on_device, void* hip_stream,
+                      int sync, int64_t* fail_index) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  if (fail_index) *fail_index = -1;
+  return refactor(f, values, values_on_device, (hipStream_t)hip_stream, sync, fail_index);
+}
+
+int tacho_check_factor(tacho_num_t f, int64_t* fail_index) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  if (f->pending) return read_fail_flag(f, fail_index);
+  if (fail_index) *fail_index = f->last_fail;
+  return f->last_status;
+}
+
+int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t ld, int on_device,
+                void* hip_stream, tacho_solve_info* info) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  tacho_sym* h = f->sym;
+  const int64_t n = h->S.n;
+  if (nrhs < 0 || ld < std::max<int64_t>(n, 1) || (nrhs > 0 && n > 0 && (!b || !x)))
+    return fail(TACHO_ERR_INVALID, "invalid solve arguments");
+  if (info) {
+    info->iters = 0;
+    info->fell_back = 0;
+    info->relres_max = 0;
+  }
+  if (f->pending) {
+    int rc = read_fail_flag(f, nullptr);
+    if (rc != TACHO_OK) return rc;
+  } else if (f->last_status != TACHO_OK) {
+    return fail(f->last_status, "no valid factor in this handle");
+  }
+  if (nrhs == 0 || n == 0) return TACHO_OK;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const double* bd = b;
+  double* xd = x;
+  const bool dense_ld = ld == n;
+  const bool refine = f->precision == TACHO_FP32;
+  // the refinement path works on dense (ld = n) device blocks
+  if (!on_device || (refine && !dense_ld) || (refine && b == x)) {
+    const size_t bytes = sizeof(double) * n * nrhs;
+    if (f->bdev.bytes < bytes) HIP_TRY(f->bdev.alloc(bytes));
+    if (f->xdev.bytes < bytes) HIP_TRY(f->xdev.alloc(bytes));
+    HIP_TRY(hipMemcpy2DAsync(f->bdev.p, n * sizeof(double), b, ld * sizeof(double),
+                             n * sizeof(double), nrhs,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    bd = f->bdev.as<double>();
+    xd = f->xdev.as<double>();
+  }
+  const int64_t ldi = (bd == b) ? ld : n;
+  HIP_TRY(hipEventRecord(f->ev[2], st));
+  if (refine) {
+    int rc = TACHO_OK;
+    rc = refine_solve(f, bd, xd, nrhs, st, info);
+    if (rc != TACHO_OK) return rc;
+  } else {
+    solve_all<double>(f, bd, ldi, xd, (xd == x) ? ld : n, nrhs, 0, st);
+  }
+  HIP_TRY(hipEventRecord(f->ev[3], st));
+  if (xd != x) {
+    HIP_TRY(hipMemcpy2DAsync(x, ld * sizeof(double), xd, n * sizeof(double), n * sizeof(double),
+                             nrhs, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             st));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(st));
+  }
+  HIP_TRY(hipGetLastError());
+  return TACHO_OK;
+}
+
+int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
+  if (!f || !Lp || !Li || !Lx) return fail(TACHO_ERR_INVALID, "NULL argument");
+  if (f->pending) {
+    int rc = read_fail_flag(f, nullptr);
+    if (rc != TACHO_OK) return rc;
+  }
+  const Symbolic& S = f->sym->S;
+  const Plan& P = f->sym->P;
+  const size_t es = elem_size(f->precision);
+  std::vector<char> host(es * P.L_elems);
+  HIP_TRY(hipDeviceSynchronize());
+  if (!host.empty()) HIP_TRY(hipMemcpy(host.data(), f->L.p, host.size(), hipMemcpyDeviceToHost));
+  Lp[0] = 0;
+  for (int64_t j = 0; j < S.n; ++j) Lp[j + 1] = Lp[j] + S.colcount[j];
+  for (int32_t s = 0; s < S.ns; ++s) {
+    const int32_t f0 = S.sptr[s], w = S.sptr[s + 1] - f0, m = S.front_m[s];
+    for (int32_t c = 0; c < w; ++c) {
+      int64_t q = Lp[f0 + c];
+      for (int32_t i = c; i < m; ++i, ++q) {
+        const int64_t off = P.L_off[s] + (int64_t)c * P.ldL[s] + i;
+        Li[q] = S.rows[S.rows_ptr[s] + i];
+        Lx[q] = f->precision == TACHO_FP32 ? (double)reinterpret_cast<const float*>(host.data())[off]
+                                           : reinterpret_cast<const double*>(host.data())[off];
+      }
+    }
+  }
+  return TACHO_OK;
+}
+
+int tacho_last_times(tacho_num_t f, double* factor_ms, double* solve_ms) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  float a = 0, b = 0;
+  if (factor_ms) {
+    HIP_TRY(hipEventSynchronize(f->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&a, f->ev[0], f->ev[1]));
+    *factor_ms = a;
+  }
+  if (solve_ms) {
+    HIP_TRY(hipEventSynchronize(f->ev[3]));
+    HIP_TRY(hipEventElapsedTime(&b, f->ev[2], f->ev[3]));
+    *solve_ms = b;
+  }
+  return TACHO_OK;
+}
+
+int tacho_free_symbolic(tacho_sym_t h) {
+  delete h;
+  return TACHO_OK;
+}
+
+int tacho_free_numeric(tacho_num_t f) {
+  if (f && f->last_stream) (void)hipStreamSynchronize(f->last_stream);
+  delete f;
+  return TACHO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+// Memory layout and launch plan of the numeric phase (host).
+//
+// Factor storage: one dense column-major panel of m_s x w_s per supernode
+// (the paper's dense supernodal blocks L_ii / L_ki, Tacho section), leading
+// dimension m_s rounded up to kLdAlign elements.  Update matrices U_s
+// (r_s x r_s, r_s = m_s - w_s) live in a workspace whose blocks are reused
+// across levels: U_s is created at its own level and released once its
+// parent's level has assembled it, placed first-fit.
+//
+// Launch plan, per level of the supernodal elimination tree (level-set
+// scheduling, Tacho section), leaves first:
+//   small fronts (m <= kSmallMax): one launch, one workgroup per front, the
+//     whole front assembled and partially factored in LDS;
+//   large fronts: assembly into the panels / update matrices, then for every
+//     panel of kPanel columns a diagonal-block Cholesky launch, a triangular
+//     solve launch for the rows below and an update launch of the remaining
+//     panel columns, then one update launch U -= L21 L21^T.
+#include <algorithm>
+#include <map>
+
+#include "plan.hpp"
+
+namespace tacho {
+namespace {
+
+class FirstFit {
+ public:
+  int64_t alloc(int64_t size) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= size) {
+        int64_t off = it->first;
+        int64_t rest = it->second - size;
+        free_.erase(it);
+        if (rest > 0) free_[off + size] = rest;
+        return off;
+      }
+    }
+    int64_t off = top_;
+    top_ += size;
+    return off;
+  }
+  void release(int64_t off, int64_t size) {
+    auto it = free_.emplace(off, size).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t peak() const { return top_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+  int64_t top_ = 0;
+};
+
+}  // namespace
+
+int build_plan(const Symbolic& S, Plan& P, std::string& err) {
+  const int32_t ns = S.ns;
+  P.L_off.assign(ns, 0);
+  P.U_off.assign(ns, -1);
+  P.u_off.assign(ns, 0);
+  P.ldL.assign(ns, 0);
+  P.ldU.assign(ns, 0);
+  int64_t off = 0, uoff = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    const int64_t m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s], r = m - w;
+    if (m > 46000) {
+      err = "front of order " + std::to_string(m) + " exceeds the supported maximum";
+      return kInvalid;
+    }
+    P.ldL[s] = (int32_t)round_up(m, kLdAlign);
+    P.ldU[s] = (int32_t)round_up(std::max<int64_t>(r, 1), kLdAlign);
+    P.L_off[s] = off;
+    off += (int64_t)P.ldL[s] * w;
+    P.u_off[s] = uoff;
+    uoff += r;
+  }
+  P.L_elems = off;
+  P.u_elems = uoff;
+
+  // update-matrix workspace, first-fit by level
+  FirstFit ff;
+  for (int32_t h = 0; h < S.nlevels; ++h) {
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      int32_t s = S.level_list[q];
+      int64_t r = S.front_m[s] - (S.sptr[s + 1] - S.sptr[s]);
+      if (r > 0) P.U_off[s] = ff.alloc(round_up((int64_t)P.ldU[s] * r, 64));
+    }
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      int32_t s = S.level_list[q];
+      for (int32_t c = S.child_ptr[s]; c < S.child_ptr[s + 1]; ++c) {
+        int32_t ch = S.child_list[c];
+        int64_t r = S.front_m[ch] - (S.sptr[ch + 1] - S.sptr[ch]);
+        if (r > 0) ff.release(P.U_off[ch], round_up((int64_t)P.ldU[ch] * r, 64));
+      }
+    }
+  }
+  P.U_elems = ff.peak();
+
+  // A-entry positions inside front panels, diagonal entry per column
+  P.a_pos.assign(S.a_row.size(), 0);
+  P.diag_q.assign(S.n, -1);
+  for (int32_t s = 0; s < ns; ++s) {
+    const int32_t f = S.sptr[s];
+    for (int32_t j = f; j < S.sptr[s + 1]; ++j)
+      for (int64_t q = S.acol_ptr[j]; q < S.acol_ptr[j + 1]; ++q) {
+        P.a_pos[q] = S.a_row[q] + (j - f) * P.ldL[s];
+        if (S.a_row[q] == j - f && S.a_src[q] >= 0) P.diag_q[j] = (int32_t)q;
+      }
+  }
+
+  // launch sequence
+  P.steps.clear();
+  P.small_list.clear();
+  P.asm_items.clear();
+  P.diag_items.clear();
+  P.panel_items.clear();
+  P.probs.clear();
+  P.tiles.clear();
+  auto add_gemm = [&](const GemmProb& g) {
+    int32_t pid = (int32_t)P.probs.size();
+    P.probs.push_back(g);
+    const int T = kGemmTile;
+    int32_t nti = (g.M + T - 1) / T, ntj = (g.N + T - 1) / T;
+    for (int32_t tj = 0; tj < ntj; ++tj)
+      for (int32_t ti = 0; ti < nti; ++ti)
+        if ((int64_t)ti * T + T - 1 >= (int64_t)tj * T) P.tiles.push_back({pid, ti, tj, 0});
+  };
+  std::vector<int32_t> big;
+  for (int32_t h = 0; h < S.nlevels; ++h) {
+    big.clear();
+    int64_t b0 = (int64_t)P.small_list.size();
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      int32_t s = S.level_list[q];
+      if (S.front_m[s] <= kSmallMax)
+        P.small_list.push_back(s);
+      else
+        big.push_back(s);
+    }
+    if ((int64_t)P.small_list.size() > b0)
+      P.steps.push_back({kStepSmall, h, b0, (int64_t)P.small_list.size()});
+    if (big.empty()) continue;
+    int64_t a0 = (int64_t)P.asm_items.size();
+    int32_t wmax = 0;
+    for (int32_t s : big) {
+      int32_t m = S.front_m[s];
+      for (int32_t c = 0; c < m; c += kAsmCols) P.asm_items.push_back({s, c, std::min(m, c + kAsmCols), 0});
+      wmax = std::max(wmax, S.sptr[s + 1] - S.sptr[s]);
+    }
+    P.steps.push_back({kStepAssemble, h, a0, (int64_t)P.asm_items.size()});
+    for (int32_t k = 0; k < wmax; k += kPanel) {
+      int64_t d0 = (int64_t)P.diag_items.size();
+      for (int32_t s : big) {
+        const int32_t w = S.sptr[s + 1] - S.sptr[s];
+        if (w > k) P.diag_items.push_back({s, k, std::min(kPanel, w - k), 0});
+      }
+      P.steps.push_back({kStepDiag, h, d0, (int64_t)P.diag_items.size()});
+      int64_t p0 = (int64_t)P.panel_items.size();
+      int64_t t0 = (int64_t)P.tiles.size();
+      for (int32_t s : big) {
+        const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+        if (w <= k) continue;
+        const int32_t kb = std::min(kPanel, w - k);
+        const int32_t below = m - k - kb;
+        const int32_t chunks = (below + kPanelRows - 1) / kPanelRows;
+        for (int32_t c = 0; c < chunks; ++c) P.panel_items.push_back({s, k, kb, c});
+      }
+      if ((int64_t)P.panel_items.size() > p0)
+        P.steps.push_back({kStepPanel, h, p0, (int64_t)P.panel_items.size()});
+      for (int32_t s : big) {
+        const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+        if (w <= k + kPanel) continue;
+        const int32_t kb = kPanel;
+        GemmProb g;
+        g.a_off = P.L_off[s] + (int64_t)k * P.ldL[s] + (k + kb);
+        g.c_off = P.L_off[s] + (int64_t)(k + kb) * P.ldL[s] + (k + kb);
+        g.lda = g.ldc = P.ldL[s];
+        g.M = m - k - kb;
+        g.N = w - k - kb;
+        g.K = kb;
+        g.c_in_u = 0;
+        add_gemm(g);
+      }
+      if ((int64_t)P.tiles.size() > t0) P.steps.push_back({kStepGemm, h, t0, (int64_t)P.tiles.size()});
+    }
+    int64_t t0 = (int64_t)P.tiles.size();
+    for (int32_t s : big) {
+      const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], r = m - w;
+      if (r <= 0) continue;
+      GemmProb g;
+      g.a_off = P.L_off[s] + w;
+      g.c_off = P.U_off[s];
+      g.lda = P.ldL[s];
+      g.ldc = P.ldU[s];
+      g.M = g.N = r;
+      g.K = w;
+      g.c_in_u = 1;
+      add_gemm(g);
+    }
+    if ((int64_t)P.tiles.size() > t0) P.steps.push_back({kStepGemm, h, t0, (int64_t)P.tiles.size()});
+  }
+  return kOk;
+}
+
+}  // namespace tacho

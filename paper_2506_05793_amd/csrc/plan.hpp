@@ -1,0 +1,82 @@
+// Device memory layout and per-level launch plan of the numeric phase.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "symbolic.hpp"
+
+namespace tacho {
+
+// Work item of the large-front assembly: columns [c0, c1) of front s.
+struct AsmItem {
+  int32_t s, c0, c1, pad;
+};
+
+// Work item of the panel kernels: diagonal block [k, k+kb) of front s (one
+// item per front for the diagonal Cholesky), rows below it handled in chunks
+// of kPanelRows (one item per chunk for the triangular solve).
+struct PanelItem {
+  int32_t s, k, kb, chunk;
+};
+
+// Update C[M x N] -= A[M x K] * A[0:N, :]^T, lower part (row >= col) only.
+// A lives in the factor panels; C in the panels (c_in_u = 0) or in the
+// update matrices (c_in_u = 1).  Offsets are in elements.
+struct GemmProb {
+  int64_t a_off, c_off;
+  int32_t lda, ldc, M, N, K, c_in_u;
+};
+
+struct GemmTile {
+  int32_t prob, ti, tj, pad;
+};
+
+enum StepKind : int32_t {
+  kStepSmall = 0,
+  kStepAssemble = 1,
+  kStepDiag = 2,
+  kStepPanel = 3,
+  kStepGemm = 4,
+};
+
+// One kernel launch: [begin, end) into the matching item array; for
+// kStepGemm, [begin, end) indexes tiles and the problems are those tiles' own.
+struct Step {
+  int32_t kind;
+  int32_t level;
+  int64_t begin, end;
+};
+
+constexpr int kSmallMax = 64;     // fronts with m <= kSmallMax go to the LDS kernel
+constexpr int kPanel = 64;        // panel width of the blocked large-front path
+constexpr int kPanelRows = 256;   // rows per panel workgroup (one per thread)
+constexpr int kAsmCols = 8;       // front columns per assembly workgroup
+constexpr int kGemmTile = 64;     // output tile of the update kernel
+constexpr int kLdAlign = 4;       // leading dimensions rounded to this many elements
+
+struct Plan {
+  // memory layout (elements; identical for FP32 and FP64)
+  std::vector<int64_t> L_off, U_off, u_off;
+  std::vector<int32_t> ldL, ldU;
+  int64_t L_elems = 0, U_elems = 0, u_elems = 0;  // u_elems per right-hand side
+  std::vector<int32_t> a_pos;   // per A entry: row + col*ldL inside the front panel
+  std::vector<int32_t> diag_q;  // per permuted column: A entry of the diagonal (-1: absent)
+
+  // launch sequence
+  std::vector<int32_t> small_list;  // supernodes factored in LDS, grouped by level
+  std::vector<AsmItem> asm_items;
+  std::vector<PanelItem> diag_items;
+  std::vector<PanelItem> panel_items;
+  std::vector<GemmProb> probs;
+  std::vector<GemmTile> tiles;
+  std::vector<Step> steps;
+
+  // solve: supernodes of each level (the level lists of the symbolic handle)
+  int64_t max_rhs_block = 0;
+};
+
+int build_plan(const Symbolic& S, Plan& P, std::string& err);
+
+}  // namespace tacho

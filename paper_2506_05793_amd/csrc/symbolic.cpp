@@ -1,0 +1,429 @@
+// Host symbolic analysis of the supernodal multifrontal Cholesky.
+//
+// Paper, Trilinos section (step 1): the analysis uses only the pattern,
+// reorders to reduce fill and expose parallelism, and sets up the data
+// structures of the factors; it runs on one host core and is reused across
+// value changes.  Tacho section: the factorization is multifrontal and
+// level-set scheduled, over dense supernodal blocks.
+//
+// Steps: validate the CSR pattern and add missing diagonals; nested
+// dissection; elimination tree (Liu) of the reordered pattern; postorder and
+// composition into the final permutation; column counts by the
+// Gilbert-Ng-Peyton skeleton/least-common-ancestor method; fundamental
+// supernodes; supernodal row structures by merging children; child-to-parent
+// relative maps; A-entry-to-front maps; height levels.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "symbolic.hpp"
+
+namespace tacho {
+
+int build_pattern(int64_t n, const int64_t* rowptr, const int32_t* colind, Pattern& P,
+                  std::string& err) {
+  if (n < 0 || (n > 0 && (!rowptr || !colind && rowptr[n] > 0))) {
+    err = "invalid CSR arguments";
+    return kInvalid;
+  }
+  if (n > INT32_MAX - 1) {
+    err = "n exceeds the int32 index range";
+    return kInvalid;
+  }
+  P.n = n;
+  if (n == 0) {
+    P.rowptr.assign(1, 0);
+    return kOk;
+  }
+  if (rowptr[0] != 0) {
+    err = "rowptr[0] must be 0";
+    return kInvalid;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) {
+      err = "rowptr is not monotone";
+      return kInvalid;
+    }
+  const int64_t nnz = rowptr[n];
+  // Rows sorted with their source positions, diagonal added where missing.
+  P.rowptr.assign(n + 1, 0);
+  std::vector<std::pair<int32_t, int64_t>> row;
+  std::vector<int32_t> cols;
+  std::vector<int64_t> srcs;
+  cols.reserve(nnz + n);
+  srcs.reserve(nnz + n);
+  for (int64_t i = 0; i < n; ++i) {
+    row.clear();
+    bool diag = false;
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+      int32_t c = colind[k];
+      if (c < 0 || c >= n) {
+        err = "column index out of range in row " + std::to_string(i);
+        return kInvalid;
+      }
+      diag |= c == i;
+      row.emplace_back(c, k);
+    }
+    if (!diag) row.emplace_back((int32_t)i, -1);
+    std::sort(row.begin(), row.end());
+    for (size_t q = 1; q < row.size(); ++q)
+      if (row[q].first == row[q - 1].first) {
+        err = "duplicate entry (" + std::to_string(i) + ", " + std::to_string(row[q].first) + ")";
+        return kInvalid;
+      }
+    for (auto& e : row) {
+      cols.push_back(e.first);
+      srcs.push_back(e.second);
+    }
+    P.rowptr[i + 1] = (int64_t)cols.size();
+  }
+  P.colind = std::move(cols);
+  P.src = std::move(srcs);
+  // Structural symmetry: every (i, j) needs (j, i).  Count per column and
+  // compare sorted transposes row by row.
+  std::vector<int64_t> tptr(n + 1, 0);
+  for (int64_t k = 0; k < P.rowptr[n]; ++k) tptr[P.colind[k] + 1]++;
+  for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+  for (int64_t i = 0; i < n; ++i)
+    if (tptr[i + 1] - tptr[i] != P.rowptr[i + 1] - P.rowptr[i]) {
+      err = "pattern is not structurally symmetric (row " + std::to_string(i) + ")";
+      return kPattern;
+    }
+  std::vector<int32_t> tind(P.rowptr[n]);
+  std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = P.rowptr[i]; k < P.rowptr[i + 1]; ++k) tind[fill[P.colind[k]]++] = (int32_t)i;
+  // tind rows are produced in ascending i, hence sorted; compare with colind.
+  if (!std::equal(tind.begin(), tind.end(), P.colind.begin())) {
+    err = "pattern is not structurally symmetric";
+    return kPattern;
+  }
+  return kOk;
+}
+
+namespace {
+
+// Upper-triangle adjacency of C = P A P^T by columns: for column j the rows i < j.
+void upper_by_column(const Pattern& A, const std::vector<int32_t>& pinv, std::vector<int64_t>& ptr,
+                     std::vector<int32_t>& ind) {
+  const int64_t n = A.n;
+  ptr.assign(n + 1, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      int32_t i = pinv[r], j = pinv[A.colind[k]];
+      if (i < j) ptr[j + 1]++;
+    }
+  for (int64_t j = 0; j < n; ++j) ptr[j + 1] += ptr[j];
+  ind.resize(ptr[n]);
+  std::vector<int64_t> pos(ptr.begin(), ptr.end() - 1);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      int32_t i = pinv[r], j = pinv[A.colind[k]];
+      if (i < j) ind[pos[j]++] = i;
+    }
+}
+
+// Elimination tree: for each column j, climb from every i < j adjacent to j
+// through the current forest roots (with path halving) and hang the root under j.
+std::vector<int32_t> etree(int64_t n, const std::vector<int64_t>& ptr,
+                           const std::vector<int32_t>& ind) {
+  std::vector<int32_t> parent(n, -1), root(n);
+  for (int64_t j = 0; j < n; ++j) {
+    root[j] = (int32_t)j;
+    for (int64_t q = ptr[j]; q < ptr[j + 1]; ++q) {
+      int32_t v = ind[q];
+      // find the representative of v's current tree with path halving
+      while (root[v] != v) {
+        root[v] = root[root[v]];
+        v = root[v];
+      }
+      if (v != j) {
+        parent[v] = (int32_t)j;
+        root[v] = (int32_t)j;
+      }
+    }
+  }
+  return parent;
+}
+
+// Postorder of a forest; children visited in ascending order, roots ascending.
+std::vector<int32_t> postorder(const std::vector<int32_t>& parent) {
+  const int64_t n = (int64_t)parent.size();
+  std::vector<int32_t> head(n, -1), next(n, -1), post;
+  post.reserve(n);
+  for (int64_t j = n - 1; j >= 0; --j)
+    if (parent[j] >= 0) {
+      next[j] = head[parent[j]];
+      head[parent[j]] = (int32_t)j;
+    }
+  std::vector<int32_t> stack;
+  for (int64_t r = 0; r < n; ++r) {
+    if (parent[r] >= 0) continue;
+    stack.push_back((int32_t)r);
+    while (!stack.empty()) {
+      int32_t v = stack.back();
+      int32_t c = head[v];
+      if (c >= 0) {
+        head[v] = next[c];
+        stack.push_back(c);
+      } else {
+        stack.pop_back();
+        post.push_back(v);
+      }
+    }
+  }
+  return post;
+}
+
+// Column counts of L for a postordered etree (descendants of j are the
+// contiguous labels [first[j], j]).  Each row subtree T_i (rows of L that
+// column j contributes to, plus i itself) is encoded by +1 at its leaves,
+// -1 at the least common ancestor of consecutive leaves and -1 at parent(i);
+// subtree sums of that weight give eta_j.
+std::vector<int64_t> column_counts(int64_t n, const std::vector<int32_t>& parent,
+                                   const std::vector<int64_t>& lptr,
+                                   const std::vector<int32_t>& lind) {
+  std::vector<int32_t> first(n), prev_nbr(n, -1), prev_leaf(n, -1), uf(n);
+  std::vector<int64_t> w(n, 0);
+  for (int64_t j = 0; j < n; ++j) first[j] = (int32_t)j;
+  for (int64_t j = 0; j < n; ++j)
+    if (parent[j] >= 0) first[parent[j]] = std::min(first[parent[j]], first[j]);
+  for (int64_t j = 0; j < n; ++j) {
+    uf[j] = (int32_t)j;
+    if (first[j] == j) w[j] = 1;  // etree leaf: T_j = {j}
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    if (parent[j] >= 0) w[parent[j]] -= 1;
+    // rows i > j with C_ij != 0: j may be a leaf of T_i
+    for (int64_t q = lptr[j]; q < lptr[j + 1]; ++q) {
+      int32_t i = lind[q];
+      if (first[j] > prev_nbr[i]) {
+        w[j] += 1;
+        int32_t pl = prev_leaf[i];
+        if (pl >= 0) {
+          int32_t a = pl;
+          while (uf[a] != a) a = uf[a];
+          for (int32_t v = pl; v != a;) {  // compress
+            int32_t nx = uf[v];
+            uf[v] = a;
+            v = nx;
+          }
+          w[a] -= 1;
+        }
+        prev_leaf[i] = (int32_t)j;
+      }
+      prev_nbr[i] = (int32_t)j;
+    }
+    if (parent[j] >= 0) uf[j] = parent[j];
+  }
+  for (int64_t j = 0; j < n; ++j)
+    if (parent[j] >= 0) w[parent[j]] += w[j];
+  return w;
+}
+
+}  // namespace
+
+int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
+  const Pattern& A = S.A;
+  const int64_t n = A.n;
+  S.n = n;
+
+  // 1. fill-reducing order: nested dissection, then etree postorder.
+  std::vector<int32_t> perm0 = nested_dissection(A, opt.nd_leaf_size);
+  std::vector<int32_t> pinv0(n);
+  for (int64_t k = 0; k < n; ++k) pinv0[perm0[k]] = (int32_t)k;
+  std::vector<int64_t> uptr;
+  std::vector<int32_t> uind;
+  upper_by_column(A, pinv0, uptr, uind);
+  std::vector<int32_t> par0 = etree(n, uptr, uind);
+  std::vector<int32_t> post = postorder(par0);
+  S.perm.resize(n);
+  S.pinv.resize(n);
+  for (int64_t k = 0; k < n; ++k) S.perm[k] = perm0[post[k]];
+  for (int64_t k = 0; k < n; ++k) S.pinv[S.perm[k]] = (int32_t)k;
+  {
+    std::vector<int32_t> postinv(n);
+    for (int64_t k = 0; k < n; ++k) postinv[post[k]] = (int32_t)k;
+    S.parent.assign(n, -1);
+    for (int64_t k = 0; k < n; ++k) {
+      int32_t p = par0[post[k]];
+      S.parent[k] = p < 0 ? -1 : postinv[p];
+    }
+  }
+  uptr.clear();
+  uind.clear();
+
+  // 2. lower triangle of C by columns (rows i > j) with source entries.
+  std::vector<int64_t> lptr(n + 1, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      int32_t i = S.pinv[r], j = S.pinv[A.colind[k]];
+      if (i > j) lptr[j + 1]++;
+    }
+  for (int64_t j = 0; j < n; ++j) lptr[j + 1] += lptr[j];
+  std::vector<int32_t> lind(lptr[n]);
+  {
+    std::vector<int64_t> pos(lptr.begin(), lptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+        int32_t i = S.pinv[r], j = S.pinv[A.colind[k]];
+        if (i > j) lind[pos[j]++] = i;
+      }
+  }
+
+  // 3. column counts.
+  S.colcount = column_counts(n, S.parent, lptr, lind);
+  S.nnzL = 0;
+  S.flops = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    S.nnzL += S.colcount[j];
+    S.flops += S.colcount[j] * S.colcount[j];
+  }
+
+  // 4. fundamental supernodes.
+  std::vector<int32_t> nkids(n, 0);
+  for (int64_t j = 0; j < n; ++j)
+    if (S.parent[j] >= 0) nkids[S.parent[j]]++;
+  S.sptr.clear();
+  S.col2sn.assign(n, 0);
+  for (int64_t j = 0; j < n; ++j) {
+    bool extend = j > 0 && S.parent[j - 1] == j && nkids[j] == 1 &&
+                  S.colcount[j - 1] == S.colcount[j] + 1;
+    if (!extend) S.sptr.push_back((int32_t)j);
+    S.col2sn[j] = (int32_t)S.sptr.size() - 1;
+  }
+  S.ns = (int32_t)S.sptr.size();
+  S.sptr.push_back((int32_t)n);
+  const int32_t ns = S.ns;
+  S.sparent.assign(ns, -1);
+  for (int32_t s = 0; s < ns; ++s) {
+    int32_t last = S.sptr[s + 1] - 1;
+    S.sparent[s] = S.parent[last] < 0 ? -1 : S.col2sn[S.parent[last]];
+  }
+  S.child_ptr.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s)
+    if (S.sparent[s] >= 0) S.child_ptr[S.sparent[s] + 1]++;
+  for (int32_t s = 0; s < ns; ++s) S.child_ptr[s + 1] += S.child_ptr[s];
+  S.child_list.resize(S.child_ptr[ns]);
+  {
+    std::vector<int32_t> pos(S.child_ptr.begin(), S.child_ptr.end() - 1);
+    for (int32_t s = 0; s < ns; ++s)  // ascending child ids
+      if (S.sparent[s] >= 0) S.child_list[pos[S.sparent[s]]++] = s;
+  }
+
+  // 5. row structures: pivots, A's rows below the supernode, children's update rows.
+  S.front_m.assign(ns, 0);
+  S.rows_ptr.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) S.front_m[s] = (int32_t)S.colcount[S.sptr[s]];
+  for (int32_t s = 0; s < ns; ++s) S.rows_ptr[s + 1] = S.rows_ptr[s] + S.front_m[s];
+  S.rows.assign(S.rows_ptr[ns], 0);
+  S.rmap.assign(S.rows_ptr[ns], -1);
+  {
+    std::vector<int32_t> mark(n, -1);
+    std::vector<int32_t> tmp;
+    for (int32_t s = 0; s < ns; ++s) {
+      const int32_t f = S.sptr[s], l = S.sptr[s + 1];
+      tmp.clear();
+      for (int32_t j = f; j < l; ++j) { mark[j] = s; tmp.push_back(j); }
+      for (int32_t j = f; j < l; ++j)
+        for (int64_t q = lptr[j]; q < lptr[j + 1]; ++q) {
+          int32_t i = lind[q];
+          if (mark[i] != s) { mark[i] = s; tmp.push_back(i); }
+        }
+      for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+        int32_t c = S.child_list[q];
+        int32_t wc = S.sptr[c + 1] - S.sptr[c];
+        for (int64_t k = S.rows_ptr[c] + wc; k < S.rows_ptr[c + 1]; ++k) {
+          int32_t i = S.rows[k];
+          if (mark[i] != s) { mark[i] = s; tmp.push_back(i); }
+        }
+      }
+      std::sort(tmp.begin(), tmp.end());
+      if ((int64_t)tmp.size() != S.front_m[s]) {
+        err = "internal error: row structure of supernode " + std::to_string(s) +
+              " disagrees with the column count";
+        return kInvalid;
+      }
+      std::copy(tmp.begin(), tmp.end(), S.rows.begin() + S.rows_ptr[s]);
+    }
+  }
+  // relative maps of each child's update rows into the parent's rows
+  {
+    std::vector<int32_t> where(n, -1);
+    for (int32_t s = 0; s < ns; ++s) {
+      for (int64_t k = S.rows_ptr[s]; k < S.rows_ptr[s + 1]; ++k)
+        where[S.rows[k]] = (int32_t)(k - S.rows_ptr[s]);
+      for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+        int32_t c = S.child_list[q];
+        int32_t wc = S.sptr[c + 1] - S.sptr[c];
+        for (int64_t k = S.rows_ptr[c] + wc; k < S.rows_ptr[c + 1]; ++k) {
+          int32_t pos = where[S.rows[k]];
+          if (pos < 0) {
+            err = "internal error: child row missing from parent front";
+            return kInvalid;
+          }
+          S.rmap[k] = pos;
+        }
+      }
+      for (int64_t k = S.rows_ptr[s]; k < S.rows_ptr[s + 1]; ++k) where[S.rows[k]] = -1;
+    }
+  }
+
+  // 6. A-entry -> front maps: lower triangle of C by permuted column, values
+  // from the original lower triangle (row >= col).
+  S.acol_ptr.assign(n + 1, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k)
+      if (r >= A.colind[k]) {
+        int32_t a = S.pinv[r], b = S.pinv[A.colind[k]];
+        S.acol_ptr[std::min(a, b) + 1]++;
+      }
+  for (int64_t j = 0; j < n; ++j) S.acol_ptr[j + 1] += S.acol_ptr[j];
+  S.a_src.assign(S.acol_ptr[n], -1);
+  S.a_row.assign(S.acol_ptr[n], 0);
+  {
+    std::vector<int64_t> pos(S.acol_ptr.begin(), S.acol_ptr.end() - 1);
+    std::vector<int32_t> rowat(n, -1);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k)
+        if (r >= A.colind[k]) {
+          int32_t a = S.pinv[r], b = S.pinv[A.colind[k]];
+          int32_t col = std::min(a, b), row = std::max(a, b);
+          S.a_src[pos[col]] = A.src[k];
+          S.a_row[pos[col]] = row;  // global row for now
+          pos[col]++;
+        }
+    for (int32_t s = 0; s < ns; ++s) {
+      for (int64_t k = S.rows_ptr[s]; k < S.rows_ptr[s + 1]; ++k)
+        rowat[S.rows[k]] = (int32_t)(k - S.rows_ptr[s]);
+      for (int32_t j = S.sptr[s]; j < S.sptr[s + 1]; ++j)
+        for (int64_t q = S.acol_ptr[j]; q < S.acol_ptr[j + 1]; ++q) S.a_row[q] = rowat[S.a_row[q]];
+      for (int64_t k = S.rows_ptr[s]; k < S.rows_ptr[s + 1]; ++k) rowat[S.rows[k]] = -1;
+    }
+  }
+
+  // 7. levels by height (leaves 0); children have smaller ids than parents.
+  S.height.assign(ns, 0);
+  for (int32_t s = 0; s < ns; ++s)
+    if (S.sparent[s] >= 0)
+      S.height[S.sparent[s]] = std::max(S.height[S.sparent[s]], S.height[s] + 1);
+  S.nlevels = 0;
+  for (int32_t s = 0; s < ns; ++s) S.nlevels = std::max(S.nlevels, S.height[s] + 1);
+  S.level_ptr.assign(S.nlevels + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) S.level_ptr[S.height[s] + 1]++;
+  for (int32_t h = 0; h < S.nlevels; ++h) S.level_ptr[h + 1] += S.level_ptr[h];
+  S.level_list.resize(ns);
+  {
+    std::vector<int32_t> pos(S.level_ptr.begin(), S.level_ptr.end() - 1);
+    for (int32_t s = 0; s < ns; ++s) S.level_list[pos[S.height[s]]++] = s;
+  }
+  S.max_m = S.max_w = S.max_child_r = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    S.max_m = std::max<int64_t>(S.max_m, S.front_m[s]);
+    S.max_w = std::max<int64_t>(S.max_w, S.sptr[s + 1] - S.sptr[s]);
+  }
+  return kOk;
+}
+
+}  // namespace tacho

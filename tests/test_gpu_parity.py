@@ -1,0 +1,214 @@
+"""GPU path vs the oracle, through the C ABI (HIP kernels on gfx950).
+
+Bars: symbolic arrays bit-exact; FP64 factor column-max-normalized error
+<= 1e-10 with the oracle's exact pattern; FP64 relative residual <= 1e-12;
+FP32 factor + FP64 refinement relative residual <= 1e-10; the first
+non-positive pivot reported at the oracle's index; results bitwise equal
+run to run and alone vs in a batch.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+import paper_2506_05793_amd as T
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a ROCm GPU")]
+
+FP64_FACTOR_TOL = 1e-10
+FP64_RESID_TOL = 1e-12
+MIXED_RESID_TOL = 1e-10
+
+
+def analyze(A, **opt):
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**opt) if opt else None)
+    return s, T.tacho_get_symbolic(s)
+
+
+def colnorm_error(Lx, F):
+    """max_j max_i |dL_ij| / max_i |L_ij| over the oracle's columns."""
+    err = 0.0
+    d = np.abs(Lx - F.Lx)
+    a = np.abs(F.Lx)
+    cm = np.maximum.reduceat(a, F.Lp[:-1]) if F.n else np.zeros(0)
+    dm = np.maximum.reduceat(d, F.Lp[:-1]) if F.n else np.zeros(0)
+    if F.n:
+        err = float(np.max(dm / cm))
+    return err
+
+
+CASES = [
+    ("lap2d_32", lambda: gen.laplace2d(32)),
+    ("fv3d_12", lambda: gen.fv3d(12, seed=1)),
+    ("fv3d_17x13x11", lambda: gen.fv3d(17, 13, 11, seed=7)),
+    ("fv2d_45x37", lambda: gen.fv2d(45, 37, seed=3)),
+    ("landice_9x8x4", lambda: gen.landice(9, 8, 4, seed=3)),
+    ("random_500", lambda: gen.random_spd_pattern(500, 0.01, seed=5)),
+    ("tridiag_300", lambda: gen.laplace1d(300)),
+    ("dense_300", lambda: gen.random_spd_pattern(300, 1.0, seed=9)),
+    ("dense_130", lambda: gen.random_spd_pattern(130, 1.0, seed=10)),
+    ("single", lambda: gen.dense_to_csr(np.array([[4.0]]))),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_fp64_factor_and_solve_parity(name, make):
+    A = make()
+    s, a = analyze(A)
+    F = oracle.factor(A, a.perm)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    Lp, Li, Lx = T.tacho_get_factor(num)
+    np.testing.assert_array_equal(Lp, F.Lp)
+    np.testing.assert_array_equal(Li, F.Li)
+    err = colnorm_error(Lx, F)
+    print(f"{name}: column-normalized factor error {err:.3e}")
+    assert err <= FP64_FACTOR_TOL
+    for nrhs in (1, 16, 19):
+        b = gen.rhs(A.n, nrhs, seed=2)
+        x = T.tacho_solve(num, b)
+        xo = oracle.solve(F, b)
+        rho = oracle.rel_residual(A, x, b)
+        assert rho.max() <= FP64_RESID_TOL, (nrhs, rho.max())
+        rel = np.linalg.norm(x - xo, axis=0) / np.linalg.norm(xo, axis=0)
+        print(f"  nrhs={nrhs} rho={rho.max():.2e} |x-x_oracle|/|x_oracle|={rel.max():.2e}")
+
+
+def test_logdet_closed_form_c1():
+    A = gen.laplace2d(32)
+    s, a = analyze(A)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    Lp, Li, Lx = T.tacho_get_factor(num)
+    logdet = 2 * np.sum(np.log(Lx[Lp[:-1]]))
+    assert abs(logdet - 1210.72312053205) / 1210.72312053205 < 1e-12
+
+
+def test_device_pointers_and_in_place():
+    A = gen.fv3d(10, 9, 8, seed=3)
+    s, a = analyze(A)
+    vals = torch.from_numpy(A.values).cuda()
+    num = T.tacho_factorize(s, vals, T.TACHO_FP64)
+    b = gen.rhs(A.n, 5, seed=4)
+    x_host = T.tacho_solve(num, b)
+    bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()  # column-major view
+    xd = T.tacho_solve(num, bd)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(xd.cpu().numpy(), x_host)
+    bd2 = bd.clone()
+    T.tacho_solve(num, bd2, bd2)  # x aliases b
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(bd2.cpu().numpy(), x_host)
+
+
+def test_multi_rhs_equals_column_by_column():
+    A = gen.fv3d(11, 10, 9, seed=5)
+    s, _ = analyze(A)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    b = gen.rhs(A.n, 16, seed=6)
+    X = T.tacho_solve(num, b)
+    for c in (0, 7, 15):
+        xc = T.tacho_solve(num, np.asfortranarray(b[:, c:c + 1]))
+        assert np.max(np.abs(xc[:, 0] - X[:, c])) <= 1e-13 * np.max(np.abs(X[:, c]))
+
+
+def test_run_to_run_bitwise():
+    A = gen.fv3d(14, 12, 10, seed=8)
+    s, _ = analyze(A)
+    n1 = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    n2 = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    assert np.array_equal(T.tacho_get_factor(n1)[2], T.tacho_get_factor(n2)[2])
+    b = gen.rhs(A.n, 3, seed=1)
+    assert np.array_equal(T.tacho_solve(n1, b), T.tacho_solve(n2, b))
+
+
+def test_refactorize_new_values():
+    A = gen.fv3d(9, 9, 9, seed=1)
+    B = gen.fv3d(9, 9, 9, seed=11)  # same pattern, other coefficients
+    assert np.array_equal(A.colind, B.colind)
+    s, a = analyze(A)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    T.tacho_refactorize(num, B.values)
+    F = oracle.factor(B, a.perm)
+    assert colnorm_error(T.tacho_get_factor(num)[2], F) <= FP64_FACTOR_TOL
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_not_spd_reports_first_pivot(seed):
+    A = gen.fv3d(8, 7, 6, seed=seed)
+    M = A.to_scipy().tolil()
+    bad = int(np.random.default_rng(seed).integers(0, A.n))
+    M[bad, bad] = -1.0
+    B = gen.matrices._from_scipy(M.tocsr())
+    s, a = analyze(B)
+    with pytest.raises(oracle.NotSPD) as eo:
+        oracle.factor(B, a.perm)
+    with pytest.raises(T.TachoError) as eg:
+        T.tacho_factorize(s, B.values, T.TACHO_FP64)
+    assert eg.value.code == T.TACHO_ERR_NOT_SPD
+    assert eg.value.fail_index == eo.value.index
+
+
+@pytest.mark.parametrize("name,make", [
+    ("fv3d_16", lambda: gen.fv3d(16, seed=2)),
+    ("landice_10x9x5", lambda: gen.landice(10, 9, 5, seed=3)),
+    ("dense_200", lambda: gen.random_spd_pattern(200, 1.0, seed=3)),
+])
+def test_fp32_refinement(name, make):
+    A = make()
+    s, a = analyze(A)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP32)
+    b = gen.rhs(A.n, 4, seed=2)
+    x, info = T.tacho_solve(num, b, with_info=True)
+    rho = oracle.rel_residual(A, x, b)
+    xo = oracle.solve(oracle.factor(A, a.perm), b)
+    fwd = np.linalg.norm(x - xo, axis=0) / np.linalg.norm(xo, axis=0)
+    print(f"{name}: iters={info['iters']} fell_back={info['fell_back']} rho={rho.max():.2e} "
+          f"err_vs_oracle={fwd.max():.2e}")
+    assert rho.max() <= MIXED_RESID_TOL
+    assert info["relres_max"] <= MIXED_RESID_TOL
+
+
+def test_batch_alone_equals_batched():
+    mats = gen.batch_fv3d(6, seed=4, lo=4, hi=9)
+    sb = T.tacho_analyze_batch([(m.n, m.rowptr, m.colind) for m in mats])
+    vals = np.concatenate([m.values for m in mats])
+    nb = T.tacho_factorize(sb, vals, T.TACHO_FP64)
+    rhs = [gen.rhs(m.n, 2, seed=10 + k) for k, m in enumerate(mats)]
+    xb = T.tacho_solve(nb, np.asfortranarray(np.concatenate(rhs, axis=0)))
+    off = 0
+    for k, m in enumerate(mats):
+        s, _ = analyze(m)
+        num = T.tacho_factorize(s, m.values, T.TACHO_FP64)
+        x = T.tacho_solve(num, rhs[k])
+        assert np.array_equal(x, xb[off:off + m.n]), k
+        off += m.n
+
+
+@pytest.mark.slow
+def test_full_size_3d_64():
+    """64^3 lognormal workload: residual and sampled (L L^T)_ij = C_ij."""
+    A = gen.fv3d(64, seed=1)
+    s, a = analyze(A)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    for nrhs in (1, 16):
+        b = gen.rhs(A.n, nrhs, seed=2)
+        x = T.tacho_solve(num, b)
+        rho = oracle.rel_residual(A, x, b)
+        print(f"64^3 nrhs={nrhs}: rho={rho.max():.2e}")
+        assert rho.max() <= FP64_RESID_TOL
+    Lp, Li, Lx = T.tacho_get_factor(num)
+    L = __import__("scipy.sparse", fromlist=["csc_matrix"]).csc_matrix((Lx, Li, Lp), shape=(A.n, A.n))
+    Lr = L.tocsr()
+    C = oracle.oracle.permuted_lower(A, a.perm).tocoo()
+    rng = np.random.default_rng(0)
+    pick = rng.choice(C.nnz, size=2000, replace=False)
+    diag = C.tocsr().diagonal()
+    worst = 0.0
+    for k in pick:
+        i, j = C.row[k], C.col[k]
+        v = Lr.getrow(i).multiply(Lr.getrow(j)).sum()
+        # Cholesky backward error is bounded entrywise by (|L||L^T|)_ij <= sqrt(C_ii C_jj)
+        worst = max(worst, abs(v - C.data[k]) / np.sqrt(diag[i] * diag[j]))
+    print(f"64^3 sampled |(LL^T)_ij - C_ij|/sqrt(C_ii C_jj) max {worst:.2e}")
+    assert worst <= 1e-12
