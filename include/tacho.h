@@ -66,7 +66,10 @@ typedef struct {
   uint64_t hbm_budget_bytes; /* 0 = no limit; tacho_factorize returns TACHO_ERR_NOMEM
                                 when the factor plus workspace would exceed it */
   int32_t block_size;        /* panel width of the blocked large-front path (0 = 64) */
-  int32_t reserved[7];
+  int32_t ordering;          /* 0 (default): both orderings below, keep the one with
+                                fewer factorization flops; 1: multilevel nested
+                                dissection; 2: level-structure nested dissection */
+  int32_t reserved[6];
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -78,7 +81,7 @@ typedef struct {
                                diagonal entries) */
   int64_t nnz_l;            /* sum_j eta_j: entries of L including the diagonal */
   int64_t flops;            /* sum_j eta_j^2: algorithmic factorization flops */
-  int64_t nsuper;           /* fundamental supernodes */
+  int64_t nsuper;           /* relaxed supernodes */
   int64_t nlevels;          /* height of the supernodal elimination forest + 1 */
   int64_t max_front;        /* largest front order m */
   int64_t max_width;        /* largest supernode width w */
@@ -86,6 +89,9 @@ typedef struct {
   int64_t work_bytes_fp64;  /* peak device bytes of the FP64 update matrices */
   int64_t device_bytes_fp64; /* all device memory of one FP64 numeric handle (nrhs = 1) */
   int64_t nsystems;         /* independent systems (1 unless built by tacho_analyze_batch) */
+  int64_t nnz_factor;       /* stored factor entries: nnz_l plus the explicit zeros of
+                               relaxed supernodes */
+  int64_t ordering;         /* ordering used: 1 multilevel, 2 level-structure */
 } tacho_sym_info;
 
 typedef struct {
@@ -112,7 +118,10 @@ typedef struct {
  *            tacho_free_symbolic)
  * The handle holds: the fill-reducing permutation (own nested dissection,
  * composed with an elimination-tree postorder), the elimination tree, the
- * column counts, fundamental supernodes, their row structures, the
+ * column counts, relaxed supernodes (fundamental supernodes merged up a
+ * chain while the explicit zeros of the merged dense block stay under a
+ * size-dependent fraction: 1/2 for fronts of order <= 16, 1/5 up to 64,
+ * 1/20 above), their row structures, the
  * child-to-parent relative maps, the A-entry-to-front maps, the level
  * schedule and the device memory plan.  No device work is queued.
  */
@@ -201,14 +210,45 @@ int tacho_solve(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64
 
 /*
  * Copy the factor L (of P A P^T, FP64 or FP32 widened to FP64) to host CSC
- * arrays: Lp int64[n+1], Li int32[nnz_l], Lx float64[nnz_l]; every column
- * sorted ascending with the diagonal first.  Synchronizes the handle.
+ * arrays as stored: Lp int64[n+1], Li int32[nnz_factor], Lx
+ * float64[nnz_factor]; every column sorted ascending with the diagonal
+ * first; rows that are structurally zero in L but stored in a relaxed
+ * supernode hold exact zeros.  Synchronizes the handle.
  */
 int tacho_get_factor(tacho_num_t num, int64_t *Lp, int32_t *Li, double *Lx);
 
 /* Device milliseconds of the last factorization and solve (hipEvent timing on the
  * caller's stream; valid once that work has finished). */
 int tacho_last_times(tacho_num_t num, double *factor_ms, double *solve_ms);
+
+/*
+ * Kernel profiling.  While enabled, every kernel launch of the handle's
+ * factorizations and solves is bracketed by hipEvents on the caller's stream
+ * (adding a little launch overhead), and its algorithmic flops and bytes are
+ * taken from the launch plan: dense partial factorization sum_{j<w}(m-j)^2
+ * per front, lower-triangle updates 2*K*(outputs with row >= col), solves
+ * 2 flops per factor entry and right-hand side, bytes counting each factor
+ * entry, A entry and update-matrix entry once.  Kinds:
+ */
+#define TACHO_K_SMALL_FRONT 0 /* fronts assembled and factored in LDS */
+#define TACHO_K_ASSEMBLE 1    /* large-front assembly and extend-add */
+#define TACHO_K_DIAG 2        /* diagonal-block Cholesky of a panel */
+#define TACHO_K_PANEL 3       /* triangular solve of the rows below a panel */
+#define TACHO_K_UPDATE 4      /* matrix-core lower-triangular updates (SYRK/GEMM) */
+#define TACHO_K_GATHER 5      /* A values into assembly order */
+#define TACHO_K_FORWARD 6     /* forward substitution, one launch per level */
+#define TACHO_K_BACKWARD 7    /* backward substitution, one launch per level */
+#define TACHO_K_PERMUTE 8     /* right-hand side / solution permutation */
+#define TACHO_K_REFINE 9      /* FP64 residual and norms of the refinement */
+#define TACHO_PROFILE_KINDS 10
+
+/* enable = 1 clears the counters and starts recording; 0 stops. */
+int tacho_profile(tacho_num_t num, int enable);
+/* Totals for one kind since profiling was enabled (waits for the events). */
+int tacho_profile_read(tacho_num_t num, int kind, int64_t *launches, double *ms, double *flops,
+                       double *bytes);
+/* Name of the HIP kernel behind a profiling kind. */
+const char *tacho_kernel_name(int kind);
 
 int tacho_free_symbolic(tacho_sym_t sym);
 int tacho_free_numeric(tacho_num_t num);

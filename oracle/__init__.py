@@ -13,6 +13,7 @@ from .oracle import (  # noqa: F401
     lib_path,
     symbolic,
     supernodes,
+    relaxed_supernodes,
     factor,
     solve,
     factor_error,

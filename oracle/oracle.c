@@ -17,7 +17,8 @@
  *   parent(j) = min{ i > j : L_ij != 0 }, -1 for a root   (elimination tree)
  *   eta_j     = #{ i >= j : L_ij != 0 }                      (column count)
  *   fundamental supernodes: j and j+1 share one iff parent(j) = j+1,
- *   eta_j = eta_{j+1} + 1 and j+1 has exactly one child.
+ *   eta_j = eta_{j+1} + 1 and j+1 has exactly one child; relaxed supernodes
+ *   merge those along chains while few explicit zeros are added (below).
  *
  * Numeric values are read from the original lower triangle (row >= col).
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no FMA contraction, so
@@ -158,6 +159,60 @@ int oracle_supernodes(int64_t n, const int32_t *parent, const int64_t *colcount,
     }
     *nsuper_out = ns;
     free(nchild);
+    free(col2super);
+    return ORACLE_OK;
+}
+
+/* Relaxed supernodes: the reading taken of the paper's "dense supernodal
+ * blocks" (Tacho section).  Walk the fundamental supernodes in column order;
+ * supernode p joins the group that ends at column f_p - 1 when that group's
+ * last column has parent f_p and the merged dense block (w columns, order
+ * m = w + eta_{l_p - 1} - 1, padded = sum over its columns of the rows at or
+ * below the column) has at most padded/2 (m <= 16), padded/5 (m <= 64) or
+ * padded/20 entries that are structurally zero. */
+int oracle_relaxed_supernodes(int64_t n, const int32_t *parent, const int64_t *colcount,
+                              int32_t *super_ptr, int32_t *super_parent, int64_t *nsuper_out) {
+    if (n < 0) return ORACLE_EINVAL;
+    int32_t *fptr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    int32_t *fpar = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *col2super = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!fptr || !fpar || !col2super) { free(fptr); free(fpar); free(col2super); return ORACLE_ENOMEM; }
+    int64_t nf = 0;
+    int rc = oracle_supernodes(n, parent, colcount, fptr, fpar, &nf);
+    if (rc) { free(fptr); free(fpar); free(col2super); return rc; }
+    int64_t ns = 0;
+    long long group_true = 0; /* structural entries of the open group */
+    for (int64_t p = 0; p < nf; ++p) {
+        int64_t f = fptr[p], l = fptr[p + 1];
+        long long ptrue = 0;
+        for (int64_t j = f; j < l; ++j) ptrue += colcount[j];
+        int merge = 0;
+        if (ns > 0 && parent[f - 1] == f) {
+            int64_t g = super_ptr[ns - 1];
+            long long m = (long long)(l - g) + colcount[l - 1] - 1;
+            long long padded = 0;
+            for (int64_t j = g; j < l; ++j) padded += m - (j - g);
+            long long zeros = padded - (group_true + ptrue);
+            long long div = m <= 16 ? 2 : (m <= 64 ? 5 : 20);
+            merge = zeros * div <= padded;
+        }
+        if (merge) {
+            group_true += ptrue;
+        } else {
+            super_ptr[ns++] = (int32_t)f;
+            group_true = ptrue;
+        }
+    }
+    super_ptr[ns] = (int32_t)n;
+    for (int64_t s = 0; s < ns; ++s)
+        for (int32_t j = super_ptr[s]; j < super_ptr[s + 1]; ++j) col2super[j] = (int32_t)s;
+    for (int64_t s = 0; s < ns; ++s) {
+        int32_t last = super_ptr[s + 1] - 1;
+        super_parent[s] = parent[last] < 0 ? -1 : col2super[parent[last]];
+    }
+    *nsuper_out = ns;
+    free(fptr);
+    free(fpar);
     free(col2super);
     return ORACLE_OK;
 }

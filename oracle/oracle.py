@@ -50,6 +50,9 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.oracle_symbolic.argtypes = [ctypes.c_int64, _i64p, _i32p, _i32p, _i32p, _i64p]
         lib.oracle_supernodes.argtypes = [ctypes.c_int64, _i32p, _i64p, _i32p, _i32p, _i64p]
+        lib.oracle_relaxed_supernodes.argtypes = [ctypes.c_int64, _i32p, _i64p, _i32p, _i32p,
+                                                  _i64p]
+        lib.oracle_relaxed_supernodes.restype = ctypes.c_int
         lib.oracle_factor.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _i32p, _i32p, _i64p,
                                       _i32p, _f64p, _i64p]
         lib.oracle_solve.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _i32p, ctypes.c_int64,
@@ -122,6 +125,24 @@ def supernodes(parent, colcount):
                                _p(spar, _i32p), ctypes.byref(ns))
     if rc != 0:
         raise ValueError(f"oracle_supernodes failed ({rc})")
+    k = ns.value
+    return sptr[:k + 1].copy(), spar[:k].copy()
+
+
+def relaxed_supernodes(parent, colcount):
+    """(super_ptr, super_parent) of the relaxed supernodes (chains merged while the
+    explicit zeros of the merged dense block stay small)."""
+    lib = _load()
+    n = len(parent)
+    parent = np.ascontiguousarray(parent, np.int32)
+    colcount = np.ascontiguousarray(colcount, np.int64)
+    sptr = np.empty(n + 1, np.int32)
+    spar = np.empty(max(n, 1), np.int32)
+    ns = ctypes.c_int64(0)
+    rc = lib.oracle_relaxed_supernodes(n, _p(parent, _i32p), _p(colcount, _i64p), _p(sptr, _i32p),
+                                       _p(spar, _i32p), ctypes.byref(ns))
+    if rc != 0:
+        raise ValueError(f"oracle_relaxed_supernodes failed ({rc})")
     k = ns.value
     return sptr[:k + 1].copy(), spar[:k].copy()
 

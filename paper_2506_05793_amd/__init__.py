@@ -26,6 +26,7 @@ TACHO_ERR_NOMEM = -4
 TACHO_ERR_HIP = -5
 TACHO_FP64 = 0
 TACHO_FP32 = 1
+TACHO_PROFILE_KINDS = 10
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -43,14 +44,16 @@ class tacho_options(ctypes.Structure):
         ("stall_ratio", ctypes.c_double),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("block_size", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("ordering", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
 class tacho_sym_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "nnz_a", "nnz_l", "flops", "nsuper", "nlevels", "max_front", "max_width",
-        "factor_bytes_fp64", "work_bytes_fp64", "device_bytes_fp64", "nsystems")]
+        "factor_bytes_fp64", "work_bytes_fp64", "device_bytes_fp64", "nsystems", "nnz_factor",
+        "ordering")]
 
 
 class tacho_solve_info(ctypes.Structure):
@@ -101,6 +104,9 @@ def _load():
                                        _vp, ctypes.POINTER(tacho_solve_info)]),
         "tacho_get_factor": (ctypes.c_int, [_vp, _i64p, _i32p, _f64p]),
         "tacho_last_times": (ctypes.c_int, [_vp, _f64p, _f64p]),
+        "tacho_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "tacho_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, _i64p, _f64p, _f64p, _f64p]),
+        "tacho_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
         "tacho_free_symbolic": (ctypes.c_int, [_vp]),
         "tacho_free_numeric": (ctypes.c_int, [_vp]),
         "tacho_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -313,7 +319,7 @@ def tacho_solve(num: NumericHandle, b, x=None, stream=None, with_info: bool = Fa
 def tacho_get_factor(num: NumericHandle):
     """Factor L of P A P^T as CSC arrays (Lp, Li, Lx) on the host."""
     q = tacho_query_symbolic(num.sym)
-    n, nnz = q["n"], q["nnz_l"]
+    n, nnz = q["n"], q["nnz_factor"]
     Lp = np.empty(n + 1, np.int64)
     Li = np.empty(max(nnz, 1), np.int32)
     Lx = np.empty(max(nnz, 1), np.float64)
@@ -334,3 +340,23 @@ def tacho_factor_ms(num: NumericHandle) -> float:
     a = ctypes.c_double(0)
     _check(_load().tacho_last_times(num.ptr, ctypes.byref(a), None))
     return a.value
+
+
+def tacho_profile(num: NumericHandle, enable: bool = True) -> None:
+    _check(_load().tacho_profile(num.ptr, int(bool(enable))))
+
+
+def tacho_profile_read(num: NumericHandle) -> dict:
+    """Per kernel: launches, total ms, algorithmic flops and bytes since enabling."""
+    lib = _load()
+    out = {}
+    for k in range(TACHO_PROFILE_KINDS):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0)
+        fl = ctypes.c_double(0)
+        by = ctypes.c_double(0)
+        _check(lib.tacho_profile_read(num.ptr, k, ctypes.byref(n), ctypes.byref(ms),
+                                      ctypes.byref(fl), ctypes.byref(by)))
+        out[lib.tacho_kernel_name(k).decode()] = {
+            "launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+    return out

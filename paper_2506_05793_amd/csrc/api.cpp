@@ -90,16 +90,76 @@ struct tacho_sym {
   int device = -1;
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
       d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q;
-  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_levels;
+  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_levels, d_fwd_items, d_bwd_items;
   DBuf d_rowptr, d_colind, d_mirror;
   DevSym view{};
   std::mutex mu;
 };
 
+// Per-launch timing of the library's kernels on the caller's stream (hipEvents
+// around each launch while profiling is enabled), with the algorithmic flops
+// and bytes of each launch taken from the plan.
+struct KernelProfile {
+  struct Rec {
+    int kind;
+    int ev;
+    double flops, bytes;
+  };
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> recs;
+  int64_t launches[TACHO_PROFILE_KINDS] = {};
+  double ms[TACHO_PROFILE_KINDS] = {}, flops[TACHO_PROFILE_KINDS] = {},
+         bytes[TACHO_PROFILE_KINDS] = {};
+  ~KernelProfile() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+  void clear() {
+    recs.clear();
+    for (int k = 0; k < TACHO_PROFILE_KINDS; ++k) {
+      launches[k] = 0;
+      ms[k] = flops[k] = bytes[k] = 0;
+    }
+  }
+  int begin(hipStream_t st) {
+    if (!on) return -1;
+    const size_t e = recs.size() * 2;
+    while (pool.size() < e + 2) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return -1;
+      pool.push_back(ev);
+    }
+    if (hipEventRecord(pool[e], st) != hipSuccess) return -1;
+    return (int)e;
+  }
+  void end(int e, hipStream_t st, int kind, double fl, double by) {
+    if (e < 0) return;
+    if (hipEventRecord(pool[e + 1], st) != hipSuccess) return;
+    recs.push_back({kind, e, fl, by});
+  }
+  hipError_t collect() {
+    if (recs.empty()) return hipSuccess;
+    hipError_t err = hipEventSynchronize(pool[recs.back().ev + 1]);
+    if (err != hipSuccess) return err;
+    for (const Rec& r : recs) {
+      float t = 0;
+      err = hipEventElapsedTime(&t, pool[r.ev], pool[r.ev + 1]);
+      if (err != hipSuccess) return err;
+      launches[r.kind] += 1;
+      ms[r.kind] += t;
+      flops[r.kind] += r.flops;
+      bytes[r.kind] += r.bytes;
+    }
+    recs.clear();
+    return hipSuccess;
+  }
+};
+
 struct tacho_num {
   tacho_sym* sym = nullptr;
+  KernelProfile prof;
   int precision = TACHO_FP64;
-  DBuf L, U, avals, vals, fullvals, scale, fail;
+  DBuf L, U, avals, vals, fullvals, scale, fail, winv;
   DBuf y, uvec;             // solve workspace (kRhs columns)
   DBuf bdev, xdev, r, dx, norms;  // host-pointer staging and refinement buffers
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -138,6 +198,7 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   h->S.nnz_input = nnz_input;
   SymOptions so;
   so.nd_leaf_size = h->opt.nd_leaf_size > 0 ? h->opt.nd_leaf_size : 8;
+  so.ordering = h->opt.ordering;
   int rc = analyze_pattern(h->S, so, err);
   if (rc != kOk) return fail(rc, err);
   rc = build_plan(h->S, h->P, err);
@@ -204,6 +265,8 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_probs, P.probs));
   HIP_TRY(upload(h->d_tiles, P.tiles));
   HIP_TRY(upload(h->d_levels, S.level_list));
+  HIP_TRY(upload(h->d_fwd_items, P.fwd_items));
+  HIP_TRY(upload(h->d_bwd_items, P.bwd_items));
   HIP_TRY(upload(h->d_rowptr, S.A.rowptr));
   HIP_TRY(upload(h->d_colind, S.A.colind));
   HIP_TRY(upload(h->d_mirror, h->mirror));
@@ -244,6 +307,7 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += (int64_t)es * P.L_elems + (int64_t)es * P.U_elems + (int64_t)es * (int64_t)S.a_src.size();
   b += 8 * S.nnz_input + 4;
   b += (int64_t)es * (S.n + P.u_elems) * kRhs;
+  b += (int64_t)es * P.max_wslots * kPanel * kPanel;
   if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;
   return b;
 }
@@ -257,6 +321,16 @@ DevNum<T> num_view(tacho_num* f) {
   N.scale = f->precision == TACHO_FP32 && f->sym->opt.scale ? f->scale.as<double>() : nullptr;
   N.fail = f->fail.as<int32_t>();
   return N;
+}
+
+int step_kind(int kind) {
+  switch (kind) {
+    case kStepSmall: return TACHO_K_SMALL_FRONT;
+    case kStepAssemble: return TACHO_K_ASSEMBLE;
+    case kStepDiag: return TACHO_K_DIAG;
+    case kStepPanel: return TACHO_K_PANEL;
+    default: return TACHO_K_UPDATE;
+  }
 }
 
 template <typename T>
@@ -273,13 +347,15 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
   const GemmTile* tiles = h->d_tiles.as<GemmTile>();
   for (const Step& s : P.steps) {
     const int64_t cnt = s.end - s.begin;
+    const int pe = f->prof.begin(st);
     switch (s.kind) {
       case kStepSmall: launch_small<T>(S, N, small + s.begin, cnt, st); break;
       case kStepAssemble: launch_assemble<T>(S, N, asmi + s.begin, cnt, st); break;
-      case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, st); break;
-      case kStepPanel: launch_panel<T>(S, N, pan + s.begin, cnt, st); break;
+      case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, f->winv.as<T>(), st); break;
+      case kStepPanel: launch_panel<T>(S, N, pan + s.begin, cnt, f->winv.as<T>(), st); break;
       case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, st); break;
     }
+    f->prof.end(pe, st, step_kind(s.kind), s.flops, s.elems * sizeof(T));
   }
 }
 
@@ -319,10 +395,14 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
     launch_mirror(h->d_mirror.as<int64_t>(), vals, f->fullvals.as<double>(),
                   (int64_t)S.A.colind.size(), st);
     if (h->opt.scale) launch_scale(h->view, vals, f->scale.as<double>(), st);
+    const int pe = f->prof.begin(st);
     launch_gather<float>(h->view, num_view<float>(f), vals, nq, st);
+    f->prof.end(pe, st, TACHO_K_GATHER, 0, nq * (8.0 + 8.0 + 4.0));
     run_factor_steps<float>(f, st);
   } else {
+    const int pe = f->prof.begin(st);
     launch_gather<double>(h->view, num_view<double>(f), vals, nq, st);
+    f->prof.end(pe, st, TACHO_K_GATHER, 0, nq * (8.0 + 8.0 + 8.0));
     run_factor_steps<double>(f, st);
   }
   HIP_TRY(hipEventRecord(f->ev[1], st));
@@ -351,6 +431,7 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   HIP_TRY(f->avals.alloc(es * S.a_src.size()));
   HIP_TRY(f->vals.alloc(sizeof(double) * S.nnz_input));
   HIP_TRY(f->fail.alloc(sizeof(int32_t)));
+  HIP_TRY(f->winv.alloc(es * std::max<int64_t>(P.max_wslots, 1) * kPanel * kPanel));
   HIP_TRY(f->y.alloc(es * S.n * kRhs));
   HIP_TRY(f->uvec.alloc(es * P.u_elems * kRhs));
   if (precision == TACHO_FP32) {
@@ -375,14 +456,34 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   T* uv = f->uvec.as<T>();
   const T* L = f->L.as<T>();
   const int32_t* lv = h->d_levels.as<int32_t>();
+  const Plan& P = h->P;
+  const double es = sizeof(T);
+  int pe = f->prof.begin(st);
   launch_permute_in<T>(V, b, ldb, y, nrhs, scale, st);
-  for (int32_t lvl = 0; lvl < S.nlevels; ++lvl)
+  f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * nrhs * (8.0 + es) + 4.0 * S.n);
+  const SolveItem* fwi = h->d_fwd_items.as<SolveItem>();
+  const SolveItem* bwi = h->d_bwd_items.as<SolveItem>();
+  for (int32_t lvl = 0; lvl < S.nlevels; ++lvl) {
+    pe = f->prof.begin(st);
     launch_fwd<T>(V, L, y, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
                   nrhs, st);
-  for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl)
+    launch_fwd_gemv<T>(V, L, y, uv, fwi + P.fwd_ptr[lvl], P.fwd_ptr[lvl + 1] - P.fwd_ptr[lvl],
+                       nrhs, st);
+    f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * P.level_lentries[lvl] * nrhs,
+                es * (P.level_lentries[lvl] + 2.0 * P.level_rows[lvl] * nrhs));
+  }
+  for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl) {
+    pe = f->prof.begin(st);
+    launch_bwd_gemv<T>(V, L, y, bwi + P.bwd_ptr[lvl], P.bwd_ptr[lvl + 1] - P.bwd_ptr[lvl], nrhs,
+                       st);
     launch_bwd<T>(V, L, y, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl], nrhs,
                   st);
+    f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * P.level_lentries[lvl] * nrhs,
+                es * (P.level_lentries[lvl] + 2.0 * P.level_rows[lvl] * nrhs));
+  }
+  pe = f->prof.begin(st);
   launch_permute_out<T>(V, y, x, ldx, nrhs, scale, accumulate, st);
+  f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * nrhs * (8.0 + es) + 4.0 * S.n);
 }
 
 template <typename T>
@@ -414,10 +515,14 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
   const double ratio = h->opt.stall_ratio > 0 ? h->opt.stall_ratio : 0.5;
   int iters = 0;
   bool stalled = false;
+  const double nnz = (double)S.A.colind.size();
   for (;;) {
+    const int pe = f->prof.begin(st);
     launch_residual(n, h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(),
                     f->fullvals.as<double>(), b, n, x, n, r, nrhs, st);
     launch_colnorms(n, r, n, nrhs, nrm, st);
+    f->prof.end(pe, st, TACHO_K_REFINE, (2.0 * nnz + 2.0 * n) * nrhs,
+                nnz * 12.0 + 8.0 * n + 8.0 * 3.0 * n * nrhs);
     HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     bool all = true;
@@ -584,6 +689,8 @@ int tacho_query_symbolic(tacho_sym_t h, tacho_sym_info* info) {
   info->work_bytes_fp64 = 8 * h->P.U_elems;
   info->device_bytes_fp64 = numeric_bytes(h, TACHO_FP64);
   info->nsystems = S.nsys;
+  info->nnz_factor = S.nnz_front;
+  info->ordering = S.ordering_used;
   return TACHO_OK;
 }
 
@@ -701,7 +808,9 @@ int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
   HIP_TRY(hipDeviceSynchronize());
   if (!host.empty()) HIP_TRY(hipMemcpy(host.data(), f->L.p, host.size(), hipMemcpyDeviceToHost));
   Lp[0] = 0;
-  for (int64_t j = 0; j < S.n; ++j) Lp[j + 1] = Lp[j] + S.colcount[j];
+  for (int32_t s = 0; s < S.ns; ++s)
+    for (int32_t j = S.sptr[s]; j < S.sptr[s + 1]; ++j)
+      Lp[j + 1] = Lp[j] + (S.front_m[s] - (j - S.sptr[s]));
   for (int32_t s = 0; s < S.ns; ++s) {
     const int32_t f0 = S.sptr[s], w = S.sptr[s + 1] - f0, m = S.front_m[s];
     for (int32_t c = 0; c < w; ++c) {
@@ -731,6 +840,34 @@ int tacho_last_times(tacho_num_t f, double* factor_ms, double* solve_ms) {
     *solve_ms = b;
   }
   return TACHO_OK;
+}
+
+int tacho_profile(tacho_num_t f, int enable) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  if (enable) {
+    HIP_TRY(f->prof.collect());
+    f->prof.clear();
+  }
+  f->prof.on = enable != 0;
+  return TACHO_OK;
+}
+
+int tacho_profile_read(tacho_num_t f, int kind, int64_t* launches, double* ms, double* flops,
+                       double* bytes) {
+  if (!f || kind < 0 || kind >= TACHO_PROFILE_KINDS) return fail(TACHO_ERR_INVALID, "bad kind");
+  HIP_TRY(f->prof.collect());
+  if (launches) *launches = f->prof.launches[kind];
+  if (ms) *ms = f->prof.ms[kind];
+  if (flops) *flops = f->prof.flops[kind];
+  if (bytes) *bytes = f->prof.bytes[kind];
+  return TACHO_OK;
+}
+
+const char* tacho_kernel_name(int kind) {
+  static const char* names[TACHO_PROFILE_KINDS] = {
+      "k_small", "k_assemble", "k_diag", "k_panel", "k_gemm",
+      "k_gather", "k_fwd", "k_bwd", "k_permute", "k_residual"};
+  return kind >= 0 && kind < TACHO_PROFILE_KINDS ? names[kind] : "unknown";
 }
 
 int tacho_free_symbolic(tacho_sym_t h) {

@@ -57,10 +57,10 @@ void launch_assemble(const DevSym& S, const DevNum<T>& N, const AsmItem* items, 
                      hipStream_t st);
 template <typename T>
 void launch_diag(const DevSym& S, const DevNum<T>& N, const PanelItem* items, int64_t count,
-                 hipStream_t st);
+                 T* winv, hipStream_t st);
 template <typename T>
 void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, int64_t count,
-                  hipStream_t st);
+                  const T* winv, hipStream_t st);
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
                  hipStream_t st);
@@ -78,6 +78,13 @@ void launch_fwd(const DevSym& S, const T* L, T* y, T* uvec, const int32_t* list,
 template <typename T>
 void launch_bwd(const DevSym& S, const T* L, T* y, const int32_t* list, int64_t count,
                 int32_t nrhs, hipStream_t st);
+
+template <typename T>
+void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* uvec, const SolveItem* items,
+                     int64_t count, int32_t nrhs, hipStream_t st);
+template <typename T>
+void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const SolveItem* items, int64_t count,
+                     int32_t nrhs, hipStream_t st);
 
 // FP64 refinement helpers: r = b - A x (original numbering, CSR), column norms.
 void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,

@@ -213,96 +213,200 @@ __global__ __launch_bounds__(kThreads) void k_assemble(DevSym S, DevNum<T> N,
 }
 
 // ---------------------------------------------------------------------------
-// Large fronts, panel step 1: Cholesky of the diagonal block [k, k+kb) in LDS,
-// one workgroup per front, written back in place; a non-positive or NaN
-// pivot is reported through the failure flag.
+// Large fronts, panel step 1 (one workgroup per front): Cholesky of the
+// diagonal block [k, k+kb) in LDS, blocked by 16 columns (a 16x16 block by
+// one wave, its rows below by one thread each, a rank-16 update of the rest),
+// written back in place, and its inverse W = L_kk^{-1} (identity-padded to
+// kPanel) written to the scratch slot of the item for the triangular solve
+// of the rows below.  Non-positive or NaN pivots go to the failure flag.
+constexpr int kSub = 16;
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const PanelItem* items) {
-  __shared__ T D[kPanel * kDiagLd];
+__global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const PanelItem* items,
+                                                   T* winv) {
+  __shared__ T D[kPanel * kDiagLd];  // column-major, D[c * kDiagLd + r]
+  __shared__ T W[kPanel * kDiagLd];
   const PanelItem it = items[blockIdx.x];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = it.s, k = it.k, kb = it.kb;
   const int f = S.sptr[s], ld = S.ldL[s];
   T* Lp = N.L + S.L_off[s];
-  for (int t = tid; t < kb * kb; t += kThreads) {
-    const int c = t / kb, rr = t - c * kb;
-    D[c * kDiagLd + rr] = rr >= c ? Lp[(k + rr) + (int64_t)(k + c) * ld] : T(0);
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    T v;
+    if (r < kb && c < kb)
+      v = r >= c ? Lp[(k + r) + (int64_t)(k + c) * ld] : T(0);
+    else
+      v = r == c ? T(1) : T(0);
+    D[c * kDiagLd + r] = v;
   }
   __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    const T d = D[j * kDiagLd + j];
-    __syncthreads();
-    const T ljj = sqrt(d);
-    if (tid == 0) {
-      D[j * kDiagLd + j] = ljj;
-      if (!(d > T(0))) atomicMin(N.fail, f + k + j);
+  for (int jb = 0; jb < kPanel; jb += kSub) {
+    // (1) 16x16 diagonal block by wave 0; lanes own rows jb + (lane & 15)
+    if (wave == 0) {
+      for (int j = jb; j < jb + kSub; ++j) {
+        const T d = D[j * kDiagLd + j];
+        const T ljj = sqrt(d);
+        __builtin_amdgcn_wave_barrier();
+        if (lane == 0) {
+          if (j < kb && !(d > T(0))) atomicMin(N.fail, f + k + j);
+          D[j * kDiagLd + j] = ljj;
+        }
+        const int i = jb + (lane & 15);
+        if (lane < kSub && i > j) D[j * kDiagLd + i] = D[j * kDiagLd + i] / ljj;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // rank-1 update inside the 16x16 block: lanes cover (row, col) pairs
+        for (int t = lane; t < kSub * kSub; t += 64) {
+          const int r = jb + (t & 15), c = jb + (t >> 4);
+          if (c > j && r >= c) D[c * kDiagLd + r] -= D[j * kDiagLd + r] * D[j * kDiagLd + c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
     }
-    for (int i = j + 1 + tid; i < kb; i += kThreads) D[j * kDiagLd + i] = D[j * kDiagLd + i] / ljj;
     __syncthreads();
-    const int nt = kb - j - 1;
-    for (int t = tid; t < nt * nt; t += kThreads) {
-      const int cc = t / nt, rr = t - cc * nt;
+    // (2) rows below the block: one thread per row, forward substitution
+    const int below = kPanel - jb - kSub;
+    if (tid < below) {
+      const int r = jb + kSub + tid;
+      T x[kSub];
+#pragma unroll
+      for (int c = 0; c < kSub; ++c) x[c] = D[(jb + c) * kDiagLd + r];
+#pragma unroll
+      for (int c = 0; c < kSub; ++c) {
+        T acc = x[c];
+#pragma unroll
+        for (int c2 = 0; c2 < c; ++c2) acc -= x[c2] * D[(jb + c2) * kDiagLd + jb + c];
+        x[c] = acc / D[(jb + c) * kDiagLd + jb + c];
+      }
+#pragma unroll
+      for (int c = 0; c < kSub; ++c) D[(jb + c) * kDiagLd + r] = x[c];
+    }
+    __syncthreads();
+    // (3) rank-16 update of the trailing lower triangle
+    for (int t = tid; t < below * below; t += kThreads) {
+      const int cc = t / below, rr = t - cc * below;
       if (rr >= cc) {
-        const int i = j + 1 + rr, c = j + 1 + cc;
-        D[c * kDiagLd + i] -= D[j * kDiagLd + i] * D[j * kDiagLd + c];
+        const int r = jb + kSub + rr, c = jb + kSub + cc;
+        T acc = D[c * kDiagLd + r];
+#pragma unroll
+        for (int q = 0; q < kSub; ++q) acc -= D[(jb + q) * kDiagLd + r] * D[(jb + q) * kDiagLd + c];
+        D[c * kDiagLd + r] = acc;
       }
     }
     __syncthreads();
   }
   for (int t = tid; t < kb * kb; t += kThreads) {
-    const int c = t / kb, rr = t - c * kb;
-    if (rr >= c) Lp[(k + rr) + (int64_t)(k + c) * ld] = D[c * kDiagLd + rr];
+    const int c = t / kb, r = t - c * kb;
+    if (r >= c) Lp[(k + r) + (int64_t)(k + c) * ld] = D[c * kDiagLd + r];
+  }
+  // W = L^{-1} by 16x16 blocks.  Diagonal blocks first (one thread per
+  // column of each block, forward substitution down its own column), then
+  // the off-diagonal blocks by distance d = 1..3 from the diagonal:
+  // W_ib = -W_ii * sum_{q=b}^{i-1} L_iq W_qb.
+  __shared__ T rd[kPanel];
+  __shared__ T Tmp[3][kSub * kSub];
+  if (tid < kPanel) rd[tid] = T(1) / D[tid * kDiagLd + tid];
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    W[c * kDiagLd + r] = T(0);
+  }
+  __syncthreads();
+  if (tid < kPanel) {
+    const int col = tid, b0 = (col / kSub) * kSub;
+    for (int r = col; r < b0 + kSub; ++r) {
+      T acc = r == col ? T(1) : T(0);
+      for (int q = col; q < r; ++q) acc -= D[q * kDiagLd + r] * W[col * kDiagLd + q];
+      W[col * kDiagLd + r] = acc * rd[r];
+    }
+  }
+  __syncthreads();
+  for (int d = 1; d < kPanel / kSub; ++d) {
+    const int nblk = kPanel / kSub - d;  // blocks (b + d, b), b < nblk
+    for (int t = tid; t < nblk * kSub * kSub; t += kThreads) {
+      const int bb = t / (kSub * kSub), e = t - bb * kSub * kSub;
+      const int rr = e % kSub, cc = e / kSub;
+      const int i0 = (bb + d) * kSub, c = bb * kSub + cc;
+      T acc = T(0);
+      for (int q = bb * kSub; q < i0; ++q) acc += D[q * kDiagLd + i0 + rr] * W[c * kDiagLd + q];
+      Tmp[bb][rr + cc * kSub] = acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < nblk * kSub * kSub; t += kThreads) {
+      const int bb = t / (kSub * kSub), e = t - bb * kSub * kSub;
+      const int rr = e % kSub, cc = e / kSub;
+      const int i0 = (bb + d) * kSub, c = bb * kSub + cc;
+      T acc = T(0);
+      for (int q = 0; q < kSub; ++q) acc += W[(i0 + q) * kDiagLd + i0 + rr] * Tmp[bb][q + cc * kSub];
+      W[c * kDiagLd + i0 + rr] = -acc;
+    }
+    __syncthreads();
+  }
+  T* Wout = winv + (int64_t)it.wslot * kPanel * kPanel;
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    Wout[t] = W[c * kDiagLd + r];
   }
 }
 
-// Large fronts, panel step 2: L_below = F_below * L_kk^{-T} for kPanelRows
-// rows per workgroup, one row per thread held in registers; L_kk is the
-// factored diagonal block (identity-padded to kPanel in LDS).
+// Large fronts, panel step 2: the rows below the diagonal block, 64 per
+// workgroup, X = B W^T on the matrix cores (W = L_kk^{-1} from step 1),
+// written in place.  B's columns past kb are read as zeros.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_panel(DevSym S, DevNum<T> N,
-                                                    const PanelItem* items) {
-  __shared__ T D[kPanel * kDiagLd];
+__global__ __launch_bounds__(kThreads) void k_panel(DevSym S, DevNum<T> N, const PanelItem* items,
+                                                    const T* winv) {
+  constexpr int PAD = 4;
+  __shared__ T Bs[kPanel][kPanel + PAD];  // Bs[c][r] = B[r][c]
+  __shared__ T Ws[kPanel][kPanel + PAD];  // Ws[c'][c] = W[c][c']
   const PanelItem it = items[blockIdx.x];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = it.s, k = it.k, kb = it.kb;
   const int m = S.front_m[s], ld = S.ldL[s];
   T* Lp = N.L + S.L_off[s];
+  const int r0 = k + kb + it.chunk * kPanel;
+  const T* Win = winv + (int64_t)it.wslot * kPanel * kPanel;
   for (int t = tid; t < kPanel * kPanel; t += kThreads) {
-    const int c = t / kPanel, rr = t - c * kPanel;
-    T v;
-    if (rr < kb && c < kb)
-      v = rr >= c ? Lp[(k + rr) + (int64_t)(k + c) * ld] : T(0);
-    else
-      v = rr == c ? T(1) : T(0);
-    D[c * kDiagLd + rr] = v;
+    const int c = t / kPanel, r = t - c * kPanel;  // W stored column-major: Win[c * 64 + r] = W[r][c]
+    Ws[c][r] = Win[t];
+    const int row = r0 + r;
+    Bs[c][r] = (row < m && c < kb) ? Lp[row + (int64_t)(k + c) * ld] : T(0);
   }
   __syncthreads();
-  // Row of this thread, clamped so that every load stays inside the panel;
-  // columns past kb read column k and meet the identity padding of D.
-  const int row_raw = k + kb + it.chunk * kPanelRows + tid;
-  const bool valid = row_raw < m;
-  const int row = valid ? row_raw : m - 1;
-  T* base = Lp + row + (int64_t)k * ld;
-  T x[kPanel];
+  typedef typename Vec4<T>::type V4;
+  V4 acc[2][2];
 #pragma unroll
-  for (int c = 0; c < kPanel; ++c) x[c] = base[(int64_t)(c < kb ? c : 0) * ld];
-  for (int c = 0; c < kb; ++c) {
-    T xc = T(0);
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int q = 0; q < kPanel; ++q)
-      if (q == c) xc = x[q];
-    xc = xc / D[c * kDiagLd + c];
+    for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+  const int wr = wave >> 1, wc = wave & 1;
 #pragma unroll
-    for (int c2 = 0; c2 < kPanel; ++c2) {
-      const T l = D[c * kDiagLd + c2];
-      x[c2] = c2 > c ? x[c2] - xc * l : (c2 == c ? xc : x[c2]);
-    }
+  for (int ks = 0; ks < kPanel / 4; ++ks) {
+    const int kk = ks * 4 + (lane >> 4);
+    T av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = Bs[kk][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = Ws[kk][wc * 32 + b * 16 + (lane & 15)];
+    // D[m][n] = sum_kk W[m][kk] B[n][kk] = X[n][m]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
   }
-  if (valid) {
 #pragma unroll
-    for (int c = 0; c < kPanel; ++c)
-      if (c < kb) base[(int64_t)c * ld] = x[c];
-  }
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr * 32 + a * 16 + (lane & 15);
+        const int c = wc * 32 + b * 16 + mfma_row<T>(lane, v);
+        const int row = r0 + r;
+        if (row < m && c < kb) Lp[row + (int64_t)(k + c) * ld] = acc[a][b][v];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -407,6 +511,10 @@ __global__ __launch_bounds__(kThreads) void k_permute_out(DevSym S, const T* y, 
   }
 }
 
+// Fronts with r_s * w_s >= kSolveSplit leave the L21 products of the solves
+// to the multi-workgroup kernels k_fwd_gemv / k_bwd_gemv.
+__device__ inline bool solve_split(int w, int r) { return (int64_t)r * w >= kSolveSplit; }
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T* uvec,
                                                   const int32_t* list, int nrhs) {
@@ -419,6 +527,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T*
   const int64_t n = S.n;
   const T* Lp = L + S.L_off[s];
   T* us = uvec + S.u_off[s] * nrhs;
+  const int mrow = solve_split(w, r) ? w : m;  // rows updated here
   for (int t = tid; t < r * nrhs; t += kThreads) us[t] = T(0);
   __syncthreads();
   for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
@@ -463,7 +572,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T*
       }
     }
     __syncthreads();
-    for (int i = jb + kb + tid; i < m; i += kThreads) {
+    for (int i = jb + kb + tid; i < mrow; i += kThreads) {
       T acc[kRhsBlock];
 #pragma unroll
       for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
@@ -487,6 +596,57 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T*
   }
 }
 
+// Forward solve, L21 part of a split front: u_s[rows] -= L21[rows, :] x_s for
+// kPanel rows per workgroup; lanes own rows, the four waves split the
+// columns, x_s is staged through LDS kSolveChunk columns at a time.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fwd_gemv(DevSym S, const T* L, const T* y, T* uvec,
+                                                       const SolveItem* items, int nrhs) {
+  __shared__ T X[kSolveChunk * kRhsBlock];
+  __shared__ T part[kThreads / 64][kPanel * kRhsBlock];
+  const SolveItem it = items[blockIdx.x];
+  const int s = it.s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int ldl = S.ldL[s];
+  const int64_t n = S.n;
+  const T* Lp = L + S.L_off[s];
+  const int row = w + it.chunk * kPanel + lane;
+  const bool valid = row < m;
+  T acc[kRhsBlock];
+#pragma unroll
+  for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
+  for (int cb = 0; cb < w; cb += kSolveChunk) {
+    const int cw = min(kSolveChunk, w - cb);
+    __syncthreads();
+    for (int t = tid; t < cw * nrhs; t += kThreads) {
+      const int col = t / cw, c = t - col * cw;
+      X[c + col * kSolveChunk] = y[f + cb + c + col * n];
+    }
+    __syncthreads();
+    if (valid) {
+      for (int c = wave; c < cw; c += kThreads / 64) {
+        const T l = Lp[row + (int64_t)(cb + c) * ldl];
+#pragma unroll
+        for (int col = 0; col < kRhsBlock; ++col)
+          if (col < nrhs) acc[col] += l * X[c + col * kSolveChunk];
+      }
+    }
+  }
+#pragma unroll
+  for (int col = 0; col < kRhsBlock; ++col) part[wave][lane + col * kPanel] = acc[col];
+  __syncthreads();
+  if (wave == 0 && valid) {
+    T* us = uvec + S.u_off[s] * nrhs;
+    for (int col = 0; col < nrhs; ++col) {
+      T t = T(0);
+#pragma unroll
+      for (int q = 0; q < kThreads / 64; ++q) t += part[q][lane + col * kPanel];
+      us[(row - w) + col * r] -= t;
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_bwd(DevSym S, const T* L, T* y, const int32_t* list,
                                                   int nrhs) {
@@ -500,6 +660,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd(DevSym S, const T* L, T* y, co
   const T* Lp = L + S.L_off[s];
   const int32_t* rws = S.rows + S.rows_ptr[s];
   if (w == 0) return;
+  const int mrow = solve_split(w, m - w) ? w : m;  // L21^T x already applied when split
   for (int jb = ((w - 1) / kPanel) * kPanel; jb >= 0; jb -= kPanel) {
     const int kb = min(kPanel, w - jb);
     for (int t = tid; t < kb * kb; t += kThreads) {
@@ -510,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_bwd(DevSym S, const T* L, T* y, co
       const int col = p / kb, j = p - col * kb;
       T acc = T(0);
       const T* lc = Lp + (int64_t)(jb + j) * ldl;
-      for (int i = jb + kb + lane; i < m; i += 64) {
+      for (int i = jb + kb + lane; i < mrow; i += 64) {
         const int64_t gi = i < w ? (int64_t)(f + i) : (int64_t)rws[i];
         acc += lc[i] * y[gi + col * n];
       }
@@ -530,6 +691,59 @@ __global__ __launch_bounds__(kThreads) void k_bwd(DevSym S, const T* L, T* y, co
       if (lane < kb) y[f + jb + lane + col * n] = z;
     }
     __syncthreads();
+  }
+}
+
+// Backward solve, L21 part of a split front: y_s[cols] -= L21[:, cols]^T x[rows(s)[w:]]
+// for kPanel columns per workgroup; lanes own columns (each lane walks its
+// column down, the 64 columns of a wave share cache lines), the four waves
+// split the rows, the gathered x is staged through LDS.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_gemv(DevSym S, const T* L, T* y,
+                                                       const SolveItem* items, int nrhs) {
+  __shared__ T XG[kSolveChunk * kRhsBlock];
+  __shared__ T part[kThreads / 64][kPanel * kRhsBlock];
+  const SolveItem it = items[blockIdx.x];
+  const int s = it.s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int ldl = S.ldL[s];
+  const int64_t n = S.n;
+  const T* Lp = L + S.L_off[s];
+  const int32_t* rws = S.rows + S.rows_ptr[s] + w;
+  const int j = it.chunk * kPanel + lane;
+  const bool valid = j < w;
+  const T* lc = Lp + (int64_t)(valid ? j : 0) * ldl + w;
+  T acc[kRhsBlock];
+#pragma unroll
+  for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
+  for (int rb = 0; rb < r; rb += kSolveChunk) {
+    const int rw = min(kSolveChunk, r - rb);
+    __syncthreads();
+    for (int t = tid; t < rw * nrhs; t += kThreads) {
+      const int col = t / rw, i = t - col * rw;
+      XG[i + col * kSolveChunk] = y[(int64_t)rws[rb + i] + col * n];
+    }
+    __syncthreads();
+    if (valid) {
+      for (int i = wave; i < rw; i += kThreads / 64) {
+        const T l = lc[rb + i];
+#pragma unroll
+        for (int col = 0; col < kRhsBlock; ++col)
+          if (col < nrhs) acc[col] += l * XG[i + col * kSolveChunk];
+      }
+    }
+  }
+#pragma unroll
+  for (int col = 0; col < kRhsBlock; ++col) part[wave][lane + col * kPanel] = acc[col];
+  __syncthreads();
+  if (wave == 0 && valid) {
+    for (int col = 0; col < nrhs; ++col) {
+      T t = T(0);
+#pragma unroll
+      for (int q = 0; q < kThreads / 64; ++q) t += part[q][lane + col * kPanel];
+      y[f + j + col * n] -= t;
+    }
   }
 }
 
@@ -608,14 +822,14 @@ void launch_assemble(const DevSym& S, const DevNum<T>& N, const AsmItem* items, 
 
 template <typename T>
 void launch_diag(const DevSym& S, const DevNum<T>& N, const PanelItem* items, int64_t count,
-                 hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_diag<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, items);
+                 T* winv, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_diag<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, items, winv);
 }
 
 template <typename T>
 void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, int64_t count,
-                  hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_panel<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, items);
+                  const T* winv, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_panel<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, items, winv);
 }
 
 template <typename T>
@@ -640,6 +854,18 @@ template <typename T>
 void launch_fwd(const DevSym& S, const T* L, T* y, T* uvec, const int32_t* list, int64_t count,
                 int32_t nrhs, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_fwd<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, uvec, list, nrhs);
+}
+
+template <typename T>
+void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* uvec, const SolveItem* items,
+                     int64_t count, int32_t nrhs, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, uvec, items, nrhs);
+}
+
+template <typename T>
+void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const SolveItem* items, int64_t count,
+                     int32_t nrhs, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, items, nrhs);
 }
 
 template <typename T>
@@ -668,10 +894,10 @@ void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, doub
                                 hipStream_t);                                                    \
   template void launch_assemble<T>(const DevSym&, const DevNum<T>&, const AsmItem*, int64_t,      \
                                    hipStream_t);                                                 \
-  template void launch_diag<T>(const DevSym&, const DevNum<T>&, const PanelItem*, int64_t,        \
+  template void launch_diag<T>(const DevSym&, const DevNum<T>&, const PanelItem*, int64_t, T*,    \
                                hipStream_t);                                                     \
   template void launch_panel<T>(const DevSym&, const DevNum<T>&, const PanelItem*, int64_t,       \
-                                hipStream_t);                                                    \
+                                const T*, hipStream_t);                                          \
   template void launch_gemm<T>(const DevNum<T>&, const GemmProb*, const GemmTile*, int64_t,       \
                                hipStream_t);                                                     \
   template void launch_permute_in<T>(const DevSym&, const double*, int64_t, T*, int64_t,          \
@@ -681,7 +907,11 @@ void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, doub
   template void launch_fwd<T>(const DevSym&, const T*, T*, T*, const int32_t*, int64_t, int32_t,  \
                               hipStream_t);                                                      \
   template void launch_bwd<T>(const DevSym&, const T*, T*, const int32_t*, int64_t, int32_t,      \
-                              hipStream_t);
+                              hipStream_t);                                                      \
+  template void launch_fwd_gemv<T>(const DevSym&, const T*, const T*, T*, const SolveItem*,       \
+                                   int64_t, int32_t, hipStream_t);                               \
+  template void launch_bwd_gemv<T>(const DevSym&, const T*, T*, const SolveItem*, int64_t,        \
+                                   int32_t, hipStream_t);
 
 TACHO_INSTANTIATE(double)
 TACHO_INSTANTIATE(float)

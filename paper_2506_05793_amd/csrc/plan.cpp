@@ -61,6 +61,29 @@ class FirstFit {
   int64_t top_ = 0;
 };
 
+// Algorithmic flops of the partial factorization of front s: sum_{j<w} (m-j)^2.
+double front_flops(const Symbolic& S, int32_t s) {
+  const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s];
+  double f = 0;
+  for (double j = 0; j < w; ++j) f += (m - j) * (m - j);
+  return f;
+}
+
+// Algorithmic element traffic of assembling and writing front s: its A
+// entries, its children's update matrices (lower triangles), the L
+// trapezoid and its own update matrix written once.
+double front_io(const Symbolic& S, int32_t s) {
+  const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s], r = m - w;
+  double e = (double)(S.acol_ptr[S.sptr[s + 1]] - S.acol_ptr[S.sptr[s]]);
+  for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+    const int32_t c = S.child_list[q];
+    const double rc = S.front_m[c] - (S.sptr[c + 1] - S.sptr[c]);
+    e += rc * (rc + 1) / 2;
+  }
+  e += w * m - w * (w - 1) / 2 + r * (r + 1) / 2;
+  return e;
+}
+
 }  // namespace
 
 int build_plan(const Symbolic& S, Plan& P, std::string& err) {
@@ -124,6 +147,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
   P.asm_items.clear();
   P.diag_items.clear();
   P.panel_items.clear();
+  P.max_wslots = 0;
   P.probs.clear();
   P.tiles.clear();
   auto add_gemm = [&](const GemmProb& g) {
@@ -134,6 +158,19 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
     for (int32_t tj = 0; tj < ntj; ++tj)
       for (int32_t ti = 0; ti < nti; ++ti)
         if ((int64_t)ti * T + T - 1 >= (int64_t)tj * T) P.tiles.push_back({pid, ti, tj, 0});
+  };
+  // one update launch over the tiles [t0, end) of problems added since t0
+  auto add_gemm_step = [&](int32_t h, int64_t t0, int32_t p0) {
+    if ((int64_t)P.tiles.size() <= t0) return;
+    Step st{kStepGemm, h, t0, (int64_t)P.tiles.size()};
+    for (int32_t pid = p0; pid < (int32_t)P.probs.size(); ++pid) {
+      const GemmProb& g = P.probs[pid];
+      const double N = g.N, M = g.M, K = g.K;
+      const double lower = N * (N + 1) / 2 + (M - N) * N;  // outputs with row >= col
+      st.flops += 2.0 * K * lower;
+      st.elems += M * K + 2.0 * lower;
+    }
+    P.steps.push_back(st);
   };
   std::vector<int32_t> big;
   for (int32_t h = 0; h < S.nlevels; ++h) {
@@ -146,8 +183,15 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
       else
         big.push_back(s);
     }
-    if ((int64_t)P.small_list.size() > b0)
-      P.steps.push_back({kStepSmall, h, b0, (int64_t)P.small_list.size()});
+    if ((int64_t)P.small_list.size() > b0) {
+      Step st{kStepSmall, h, b0, (int64_t)P.small_list.size()};
+      for (int64_t q = b0; q < st.end; ++q) {
+        const int32_t s = P.small_list[q];
+        st.flops += front_flops(S, s);
+        st.elems += front_io(S, s);
+      }
+      P.steps.push_back(st);
+    }
     if (big.empty()) continue;
     int64_t a0 = (int64_t)P.asm_items.size();
     int32_t wmax = 0;
@@ -156,26 +200,56 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
       for (int32_t c = 0; c < m; c += kAsmCols) P.asm_items.push_back({s, c, std::min(m, c + kAsmCols), 0});
       wmax = std::max(wmax, S.sptr[s + 1] - S.sptr[s]);
     }
-    P.steps.push_back({kStepAssemble, h, a0, (int64_t)P.asm_items.size()});
+    {
+      Step st{kStepAssemble, h, a0, (int64_t)P.asm_items.size()};
+      for (int32_t s : big) st.elems += front_io(S, s);
+      P.steps.push_back(st);
+    }
     for (int32_t k = 0; k < wmax; k += kPanel) {
       int64_t d0 = (int64_t)P.diag_items.size();
-      for (int32_t s : big) {
+      std::vector<int32_t> slot_of;  // per big front: its slot in this step
+      slot_of.assign(big.size(), -1);
+      for (size_t bi = 0; bi < big.size(); ++bi) {
+        const int32_t s = big[bi];
         const int32_t w = S.sptr[s + 1] - S.sptr[s];
-        if (w > k) P.diag_items.push_back({s, k, std::min(kPanel, w - k), 0});
+        if (w <= k) continue;
+        const int32_t slot = (int32_t)(P.diag_items.size() - d0);
+        slot_of[bi] = slot;
+        P.diag_items.push_back({s, k, std::min(kPanel, w - k), 0, slot, 0});
       }
-      P.steps.push_back({kStepDiag, h, d0, (int64_t)P.diag_items.size()});
+      P.max_wslots = std::max<int64_t>(P.max_wslots, (int64_t)P.diag_items.size() - d0);
+      {
+        Step st{kStepDiag, h, d0, (int64_t)P.diag_items.size()};
+        for (int64_t q = d0; q < st.end; ++q) {
+          const double kb = P.diag_items[q].kb;
+          st.flops += kb * (kb + 1) * (2 * kb + 1) / 6.0;
+          st.elems += kb * (kb + 1) + (double)kPanel * kPanel;
+        }
+        P.steps.push_back(st);
+      }
       int64_t p0 = (int64_t)P.panel_items.size();
       int64_t t0 = (int64_t)P.tiles.size();
-      for (int32_t s : big) {
+      const int32_t g0 = (int32_t)P.probs.size();
+      for (size_t bi = 0; bi < big.size(); ++bi) {
+        const int32_t s = big[bi];
         const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
         if (w <= k) continue;
         const int32_t kb = std::min(kPanel, w - k);
         const int32_t below = m - k - kb;
         const int32_t chunks = (below + kPanelRows - 1) / kPanelRows;
-        for (int32_t c = 0; c < chunks; ++c) P.panel_items.push_back({s, k, kb, c});
+        for (int32_t c = 0; c < chunks; ++c) P.panel_items.push_back({s, k, kb, c, slot_of[bi], 0});
       }
-      if ((int64_t)P.panel_items.size() > p0)
-        P.steps.push_back({kStepPanel, h, p0, (int64_t)P.panel_items.size()});
+      if ((int64_t)P.panel_items.size() > p0) {
+        Step st{kStepPanel, h, p0, (int64_t)P.panel_items.size()};
+        for (int32_t s : big) {
+          const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+          if (w <= k) continue;
+          const double kb = std::min(kPanel, w - k), rows = m - k - kb;
+          st.flops += rows * kb * kb;
+          st.elems += 2 * rows * kb + (double)kPanel * kPanel;
+        }
+        P.steps.push_back(st);
+      }
       for (int32_t s : big) {
         const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
         if (w <= k + kPanel) continue;
@@ -190,9 +264,10 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
         g.c_in_u = 0;
         add_gemm(g);
       }
-      if ((int64_t)P.tiles.size() > t0) P.steps.push_back({kStepGemm, h, t0, (int64_t)P.tiles.size()});
+      add_gemm_step(h, t0, g0);
     }
     int64_t t0 = (int64_t)P.tiles.size();
+    const int32_t g0 = (int32_t)P.probs.size();
     for (int32_t s : big) {
       const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], r = m - w;
       if (r <= 0) continue;
@@ -206,7 +281,29 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
       g.c_in_u = 1;
       add_gemm(g);
     }
-    if ((int64_t)P.tiles.size() > t0) P.steps.push_back({kStepGemm, h, t0, (int64_t)P.tiles.size()});
+    add_gemm_step(h, t0, g0);
+  }
+  P.fwd_items.clear();
+  P.bwd_items.clear();
+  P.fwd_ptr.assign(S.nlevels + 1, 0);
+  P.bwd_ptr.assign(S.nlevels + 1, 0);
+  for (int32_t h = 0; h < S.nlevels; ++h) {
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      const int32_t s = S.level_list[q];
+      const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+      if ((int64_t)r * w < kSolveSplit) continue;
+      for (int32_t c = 0; c * kPanel < r; ++c) P.fwd_items.push_back({s, c});
+      for (int32_t c = 0; c * kPanel < w; ++c) P.bwd_items.push_back({s, c});
+    }
+    P.fwd_ptr[h + 1] = (int64_t)P.fwd_items.size();
+    P.bwd_ptr[h + 1] = (int64_t)P.bwd_items.size();
+  }
+  P.level_lentries.assign(S.nlevels, 0.0);
+  P.level_rows.assign(S.nlevels, 0.0);
+  for (int32_t s = 0; s < ns; ++s) {
+    const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s];
+    P.level_lentries[S.height[s]] += w * m - w * (w - 1) / 2;
+    P.level_rows[S.height[s]] += m;
   }
   return kOk;
 }

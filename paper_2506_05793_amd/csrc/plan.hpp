@@ -16,9 +16,10 @@ struct AsmItem {
 
 // Work item of the panel kernels: diagonal block [k, k+kb) of front s (one
 // item per front for the diagonal Cholesky), rows below it handled in chunks
-// of kPanelRows (one item per chunk for the triangular solve).
+// of kPanelRows (one item per chunk for the triangular solve).  `wslot` is
+// the scratch slot holding the inverse of the diagonal block in that step.
 struct PanelItem {
-  int32_t s, k, kb, chunk;
+  int32_t s, k, kb, chunk, wslot, pad;
 };
 
 // Update C[M x N] -= A[M x K] * A[0:N, :]^T, lower part (row >= col) only.
@@ -27,6 +28,12 @@ struct PanelItem {
 struct GemmProb {
   int64_t a_off, c_off;
   int32_t lda, ldc, M, N, K, c_in_u;
+};
+
+// Work item of the split solve kernels: row chunk (forward) or column chunk
+// (backward) of kPanel of front s.
+struct SolveItem {
+  int32_t s, chunk;
 };
 
 struct GemmTile {
@@ -47,20 +54,25 @@ struct Step {
   int32_t kind;
   int32_t level;
   int64_t begin, end;
+  double flops = 0;  // algorithmic flops of the launch
+  double elems = 0;  // algorithmic element traffic (reads + writes) of the launch
 };
 
 constexpr int kSmallMax = 64;     // fronts with m <= kSmallMax go to the LDS kernel
 constexpr int kPanel = 64;        // panel width of the blocked large-front path
-constexpr int kPanelRows = 256;   // rows per panel workgroup (one per thread)
+constexpr int kPanelRows = 64;    // rows per triangular-solve workgroup
 constexpr int kAsmCols = 8;       // front columns per assembly workgroup
 constexpr int kGemmTile = 64;     // output tile of the update kernel
 constexpr int kLdAlign = 4;       // leading dimensions rounded to this many elements
+constexpr int64_t kSolveSplit = 16384;  // r*w at which the solves split off the L21 part
+constexpr int kSolveChunk = 256;  // vector entries staged per LDS round in the split solves
 
 struct Plan {
   // memory layout (elements; identical for FP32 and FP64)
   std::vector<int64_t> L_off, U_off, u_off;
   std::vector<int32_t> ldL, ldU;
   int64_t L_elems = 0, U_elems = 0, u_elems = 0;  // u_elems per right-hand side
+  int64_t max_wslots = 0;  // diagonal-block inverses live at once (one panel step)
   std::vector<int32_t> a_pos;   // per A entry: row + col*ldL inside the front panel
   std::vector<int32_t> diag_q;  // per permuted column: A entry of the diagonal (-1: absent)
 
@@ -73,8 +85,12 @@ struct Plan {
   std::vector<GemmTile> tiles;
   std::vector<Step> steps;
 
-  // solve: supernodes of each level (the level lists of the symbolic handle)
-  int64_t max_rhs_block = 0;
+  // solve, per level: factor entries read (sum over fronts of the lower
+  // trapezoid of the panel) and front rows touched
+  std::vector<double> level_lentries, level_rows;
+  // split solves: per level [ptr[h], ptr[h+1]) into the item arrays
+  std::vector<SolveItem> fwd_items, bwd_items;
+  std::vector<int64_t> fwd_ptr, bwd_ptr;
 };
 
 int build_plan(const Symbolic& S, Plan& P, std::string& err);

@@ -9,10 +9,11 @@
 // Steps: validate the CSR pattern and add missing diagonals; nested
 // dissection; elimination tree (Liu) of the reordered pattern; postorder and
 // composition into the final permutation; column counts by the
-// Gilbert-Ng-Peyton skeleton/least-common-ancestor method; fundamental
+// Gilbert-Ng-Peyton skeleton/least-common-ancestor method; relaxed
 // supernodes; supernodal row structures by merging children; child-to-parent
 // relative maps; A-entry-to-front maps; height levels.
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -224,77 +225,149 @@ std::vector<int64_t> column_counts(int64_t n, const std::vector<int32_t>& parent
 
 }  // namespace
 
+// The permuted pattern and its elimination quantities for one candidate order.
+struct Ordered {
+  std::vector<int32_t> perm, pinv, parent;
+  std::vector<int64_t> lptr;  // lower triangle of C by columns (rows i > j)
+  std::vector<int32_t> lind;
+  std::vector<int64_t> colcount;
+  int64_t nnzL = 0, flops = 0;
+};
+
+// Etree of the reordered pattern, postorder composed into the final
+// permutation, lower-triangle adjacency and column counts.
+Ordered order_and_count(const Pattern& A, const std::vector<int32_t>& perm0) {
+  const int64_t n = A.n;
+  Ordered O;
+  std::vector<int32_t> pinv0(n);
+  for (int64_t k = 0; k < n; ++k) pinv0[perm0[k]] = (int32_t)k;
+  std::vector<int32_t> par0;
+  {
+    std::vector<int64_t> uptr;
+    std::vector<int32_t> uind;
+    upper_by_column(A, pinv0, uptr, uind);
+    par0 = etree(n, uptr, uind);
+  }
+  std::vector<int32_t> post = postorder(par0);
+  O.perm.resize(n);
+  O.pinv.resize(n);
+  for (int64_t k = 0; k < n; ++k) O.perm[k] = perm0[post[k]];
+  for (int64_t k = 0; k < n; ++k) O.pinv[O.perm[k]] = (int32_t)k;
+  {
+    std::vector<int32_t> postinv(n);
+    for (int64_t k = 0; k < n; ++k) postinv[post[k]] = (int32_t)k;
+    O.parent.assign(n, -1);
+    for (int64_t k = 0; k < n; ++k) {
+      const int32_t p = par0[post[k]];
+      O.parent[k] = p < 0 ? -1 : postinv[p];
+    }
+  }
+  O.lptr.assign(n + 1, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      const int32_t i = O.pinv[r], j = O.pinv[A.colind[k]];
+      if (i > j) O.lptr[j + 1]++;
+    }
+  for (int64_t j = 0; j < n; ++j) O.lptr[j + 1] += O.lptr[j];
+  O.lind.resize(O.lptr[n]);
+  {
+    std::vector<int64_t> pos(O.lptr.begin(), O.lptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+        const int32_t i = O.pinv[r], j = O.pinv[A.colind[k]];
+        if (i > j) O.lind[pos[j]++] = i;
+      }
+  }
+  O.colcount = column_counts(n, O.parent, O.lptr, O.lind);
+  for (int64_t j = 0; j < n; ++j) {
+    O.nnzL += O.colcount[j];
+    O.flops += O.colcount[j] * O.colcount[j];
+  }
+  return O;
+}
+
+// Relaxed supernodes.  Start from the fundamental supernodes (j, j+1 share
+// one iff parent(j) = j+1, j+1 has one child and eta_j = eta_{j+1} + 1) and,
+// in column order, merge a supernode p into the group that ends right
+// before it when that group is p's child, provided the explicit zeros of
+// the merged dense block stay small: with w and m the merged width and
+// order, padded = w*m - w(w-1)/2 entries against sum eta_j true ones, merge
+// when zeros <= padded/2 (m <= 16), padded/5 (m <= 64) or padded/20.
+std::vector<int32_t> relaxed_supernodes(int64_t n, const std::vector<int32_t>& parent,
+                                        const std::vector<int64_t>& colcount) {
+  std::vector<int32_t> nkids(n, 0);
+  for (int64_t j = 0; j < n; ++j)
+    if (parent[j] >= 0) nkids[parent[j]]++;
+  std::vector<int32_t> fund;
+  for (int64_t j = 0; j < n; ++j) {
+    const bool extend = j > 0 && parent[j - 1] == j && nkids[j] == 1 &&
+                        colcount[j - 1] == colcount[j] + 1;
+    if (!extend) fund.push_back((int32_t)j);
+  }
+  fund.push_back((int32_t)n);
+  std::vector<int32_t> start;  // group starts
+  int64_t g_true = 0;          // true entries of the last group
+  for (size_t p = 0; p + 1 < fund.size(); ++p) {
+    const int64_t f = fund[p], l = fund[p + 1];
+    int64_t true_p = 0;
+    for (int64_t j = f; j < l; ++j) true_p += colcount[j];
+    if (!start.empty() && parent[f - 1] == f) {
+      const int64_t w = l - start.back();
+      const int64_t m = w + colcount[l - 1] - 1;  // rows below l are the last column's
+      const int64_t padded = w * m - w * (w - 1) / 2;
+      const int64_t zeros = padded - (g_true + true_p);
+      const int64_t div = m <= 16 ? 2 : (m <= 64 ? 5 : 20);
+      if (zeros * div <= padded) {
+        g_true += true_p;
+        continue;
+      }
+    }
+    start.push_back((int32_t)f);
+    g_true = true_p;
+  }
+  start.push_back((int32_t)n);
+  return start;
+}
+
 int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
   const Pattern& A = S.A;
   const int64_t n = A.n;
   S.n = n;
 
-  // 1. fill-reducing order: nested dissection, then etree postorder.
-  std::vector<int32_t> perm0 = nested_dissection(A, opt.nd_leaf_size);
-  std::vector<int32_t> pinv0(n);
-  for (int64_t k = 0; k < n; ++k) pinv0[perm0[k]] = (int32_t)k;
-  std::vector<int64_t> uptr;
-  std::vector<int32_t> uind;
-  upper_by_column(A, pinv0, uptr, uind);
-  std::vector<int32_t> par0 = etree(n, uptr, uind);
-  std::vector<int32_t> post = postorder(par0);
-  S.perm.resize(n);
-  S.pinv.resize(n);
-  for (int64_t k = 0; k < n; ++k) S.perm[k] = perm0[post[k]];
-  for (int64_t k = 0; k < n; ++k) S.pinv[S.perm[k]] = (int32_t)k;
-  {
-    std::vector<int32_t> postinv(n);
-    for (int64_t k = 0; k < n; ++k) postinv[post[k]] = (int32_t)k;
-    S.parent.assign(n, -1);
-    for (int64_t k = 0; k < n; ++k) {
-      int32_t p = par0[post[k]];
-      S.parent[k] = p < 0 ? -1 : postinv[p];
+  // 1. fill-reducing order: nested dissection (multilevel and/or level
+  // structure), composed with an etree postorder; with both candidates the
+  // one with fewer factorization flops is kept.
+  Ordered O;
+  if (opt.ordering == 1) {
+    O = order_and_count(A, nested_dissection(A, opt.nd_leaf_size));
+    S.ordering_used = 1;
+  } else if (opt.ordering == 2) {
+    O = order_and_count(A, levelset_dissection(A, opt.nd_leaf_size));
+    S.ordering_used = 2;
+  } else {
+    O = order_and_count(A, nested_dissection(A, opt.nd_leaf_size));
+    S.ordering_used = 1;
+    Ordered O2 = order_and_count(A, levelset_dissection(A, opt.nd_leaf_size));
+    if (O2.flops < O.flops) {
+      O = std::move(O2);
+      S.ordering_used = 2;
     }
   }
-  uptr.clear();
-  uind.clear();
+  S.perm = std::move(O.perm);
+  S.pinv = std::move(O.pinv);
+  S.parent = std::move(O.parent);
+  S.colcount = std::move(O.colcount);
+  S.nnzL = O.nnzL;
+  S.flops = O.flops;
+  std::vector<int64_t> lptr = std::move(O.lptr);
+  std::vector<int32_t> lind = std::move(O.lind);
 
-  // 2. lower triangle of C by columns (rows i > j) with source entries.
-  std::vector<int64_t> lptr(n + 1, 0);
-  for (int64_t r = 0; r < n; ++r)
-    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
-      int32_t i = S.pinv[r], j = S.pinv[A.colind[k]];
-      if (i > j) lptr[j + 1]++;
-    }
-  for (int64_t j = 0; j < n; ++j) lptr[j + 1] += lptr[j];
-  std::vector<int32_t> lind(lptr[n]);
-  {
-    std::vector<int64_t> pos(lptr.begin(), lptr.end() - 1);
-    for (int64_t r = 0; r < n; ++r)
-      for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
-        int32_t i = S.pinv[r], j = S.pinv[A.colind[k]];
-        if (i > j) lind[pos[j]++] = i;
-      }
-  }
-
-  // 3. column counts.
-  S.colcount = column_counts(n, S.parent, lptr, lind);
-  S.nnzL = 0;
-  S.flops = 0;
-  for (int64_t j = 0; j < n; ++j) {
-    S.nnzL += S.colcount[j];
-    S.flops += S.colcount[j] * S.colcount[j];
-  }
-
-  // 4. fundamental supernodes.
-  std::vector<int32_t> nkids(n, 0);
-  for (int64_t j = 0; j < n; ++j)
-    if (S.parent[j] >= 0) nkids[S.parent[j]]++;
-  S.sptr.clear();
+  // 2. relaxed supernodes and the supernodal tree.
+  S.sptr = relaxed_supernodes(n, S.parent, S.colcount);
+  S.ns = (int32_t)S.sptr.size() - 1;
   S.col2sn.assign(n, 0);
-  for (int64_t j = 0; j < n; ++j) {
-    bool extend = j > 0 && S.parent[j - 1] == j && nkids[j] == 1 &&
-                  S.colcount[j - 1] == S.colcount[j] + 1;
-    if (!extend) S.sptr.push_back((int32_t)j);
-    S.col2sn[j] = (int32_t)S.sptr.size() - 1;
-  }
-  S.ns = (int32_t)S.sptr.size();
-  S.sptr.push_back((int32_t)n);
+  for (int32_t s = 0; s < S.ns; ++s)
+    for (int32_t j = S.sptr[s]; j < S.sptr[s + 1]; ++j) S.col2sn[j] = s;
   const int32_t ns = S.ns;
   S.sparent.assign(ns, -1);
   for (int32_t s = 0; s < ns; ++s) {
@@ -313,10 +386,19 @@ int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
   }
 
   // 5. row structures: pivots, A's rows below the supernode, children's update rows.
+  // A supernode's rows below its last pivot are those of its last column, so
+  // m_s = w_s + eta_{l_s - 1} - 1 (explicit zeros of relaxed supernodes
+  // included).
   S.front_m.assign(ns, 0);
   S.rows_ptr.assign(ns + 1, 0);
-  for (int32_t s = 0; s < ns; ++s) S.front_m[s] = (int32_t)S.colcount[S.sptr[s]];
-  for (int32_t s = 0; s < ns; ++s) S.rows_ptr[s + 1] = S.rows_ptr[s] + S.front_m[s];
+  for (int32_t s = 0; s < ns; ++s)
+    S.front_m[s] = (S.sptr[s + 1] - S.sptr[s]) + (int32_t)S.colcount[S.sptr[s + 1] - 1] - 1;
+  S.nnz_front = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    S.rows_ptr[s + 1] = S.rows_ptr[s] + S.front_m[s];
+    const int64_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+    S.nnz_front += w * m - w * (w - 1) / 2;
+  }
   S.rows.assign(S.rows_ptr[ns], 0);
   S.rmap.assign(S.rows_ptr[ns], -1);
   {

@@ -12,6 +12,7 @@ namespace tacho {
 
 struct SymOptions {
   int nd_leaf_size = 8;
+  int ordering = 0;  // 0: the better of 1 and 2 (fewer flops), 1: multilevel ND, 2: level-structure ND
 };
 
 // Pattern of the full symmetric matrix, validated, diagonal present.
@@ -33,6 +34,8 @@ struct Symbolic {
   std::vector<int32_t> parent;      // etree of P A P^T
   std::vector<int64_t> colcount;    // eta_j
   int64_t nnzL = 0, flops = 0;
+  int64_t nnz_front = 0;  // stored factor entries incl. explicit zeros of relaxed supernodes
+  int ordering_used = 0;  // 1 multilevel, 2 level-structure
 
   // supernodes
   int32_t ns = 0;
@@ -66,6 +69,7 @@ int build_pattern(int64_t n, const int64_t* rowptr, const int32_t* colind, Patte
 // Fill-reducing ordering (new -> old) by nested dissection on the adjacency
 // graph of P (self loops ignored).
 std::vector<int32_t> nested_dissection(const Pattern& P, int leaf_size);
+std::vector<int32_t> levelset_dissection(const Pattern& P, int leaf_size);
 
 int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err);
 

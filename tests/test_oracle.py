@@ -47,6 +47,30 @@ def brute_symbolic(G):
     return parent, counts, np.array(starts, np.int32)
 
 
+def brute_relaxed(G, starts, parent):
+    """Relaxed supernodes computed from the dense pattern: merged row sets are
+    unions of the columns' patterns, zeros counted entry by entry."""
+    n = G.shape[0]
+    groups = []
+    for p in range(len(starts) - 1):
+        f, l = int(starts[p]), int(starts[p + 1])
+        if groups and groups[-1][1] == f and parent[f - 1] == f:
+            cols = range(groups[-1][0], l)
+            rowset = np.zeros(n, dtype=bool)
+            for j in cols:
+                rowset |= G[:, j]
+            rows = np.nonzero(rowset)[0]
+            padded = sum(int(np.sum(rows >= j)) for j in cols)
+            true = int(sum(G[:, j].sum() for j in cols))
+            m = rows.size
+            div = 2 if m <= 16 else (5 if m <= 64 else 20)
+            if (padded - true) * div <= padded:
+                groups[-1][1] = l
+                continue
+        groups.append([f, l])
+    return np.array([g[0] for g in groups] + [n], np.int32)
+
+
 def random_perm(n, seed):
     return np.random.default_rng(seed).permutation(n).astype(np.int32)
 
@@ -73,12 +97,15 @@ def test_symbolic_vs_brute_force(oracle_lib, name, make, pseed):
     np.testing.assert_array_equal(counts, bcounts)
     sptr, spar = oracle_lib.supernodes(parent, counts)
     np.testing.assert_array_equal(sptr, bstarts)
+    rptr, rpar = oracle_lib.relaxed_supernodes(parent, counts)
+    np.testing.assert_array_equal(rptr, brute_relaxed(G, bstarts, bparent))
     # supernodal parent: supernode that holds parent(last column)
-    col2s = np.repeat(np.arange(len(sptr) - 1), np.diff(sptr))
-    for s in range(len(sptr) - 1):
-        last = sptr[s + 1] - 1
-        want = -1 if bparent[last] < 0 else col2s[bparent[last]]
-        assert spar[s] == want
+    for ptr, par in ((sptr, spar), (rptr, rpar)):
+        col2s = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))
+        for s in range(len(ptr) - 1):
+            last = ptr[s + 1] - 1
+            want = -1 if bparent[last] < 0 else col2s[bparent[last]]
+            assert par[s] == want
     # the numeric factor has exactly the brute-force pattern
     F = oracle_lib.factor(A, perm)
     Ld = F.L().toarray()
@@ -161,6 +188,7 @@ def test_dense_pattern_one_supernode(oracle_lib):
     sptr, spar = oracle_lib.supernodes(parent, counts)
     np.testing.assert_array_equal(sptr, [0, n])
     np.testing.assert_array_equal(spar, [-1])
+    np.testing.assert_array_equal(oracle_lib.relaxed_supernodes(parent, counts)[0], [0, n])
 
 
 def test_diagonal_forest(oracle_lib):
@@ -281,3 +309,16 @@ def test_explicit_zeros_count_in_pattern(oracle_lib):
     np.testing.assert_array_equal(parent, bparent)
     np.testing.assert_array_equal(counts, bcounts)
     assert parent[0] == 5 and counts[0] == 2
+
+
+@pytest.mark.parametrize("m,pseed", [(6, None), (9, 4), (12, None)])
+def test_relaxed_supernodes_on_grids(oracle_lib, m, pseed):
+    """Grids with crossing separators: relaxed groups vs brute force, and the
+    merge never adds more than the allowed share of zeros per group."""
+    A = gen.fv3d(m, m, max(2, m // 2), seed=1)
+    perm = np.arange(A.n, dtype=np.int32) if pseed is None else random_perm(A.n, pseed)
+    G = brute_pattern(A, perm)
+    bparent, bcounts, bstarts = brute_symbolic(G)
+    rptr, _ = oracle_lib.relaxed_supernodes(bparent, bcounts)
+    np.testing.assert_array_equal(rptr, brute_relaxed(G, bstarts, bparent))
+    assert len(rptr) <= len(bstarts)
