@@ -69,7 +69,11 @@ typedef struct {
   int32_t ordering;          /* 0 (default): both orderings below, keep the one with
                                 fewer factorization flops; 1: multilevel nested
                                 dissection; 2: level-structure nested dissection */
-  int32_t reserved[6];
+  int32_t graphs;            /* 1 (default): the factorization's launch sequence is
+                                captured once per numeric handle into a hipGraph and
+                                replayed; 0: launched eagerly.  Kernel profiling
+                                always launches eagerly. */
+  int32_t reserved[5];
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -177,6 +181,19 @@ int tacho_factorize(tacho_sym_t sym, const double *values, int values_on_device,
                     void *hip_stream, tacho_num_t *out, int64_t *fail_index);
 
 /*
+ * Allocate a numeric handle without factoring (for callers that queue the
+ * factorization asynchronously with tacho_refactorize(..., sync = 0), such as
+ * a request server).  The handle holds no factor until then; solving before
+ * gives TACHO_ERR_INVALID.
+ */
+int tacho_numeric_create(tacho_sym_t sym, int precision, tacho_num_t *out);
+
+/* Device bytes a numeric handle of this precision allocates (factor, update
+ * workspace, values, solve workspace for 16 right-hand sides); the quantity an
+ * HBM budget is checked against. */
+int tacho_numeric_bytes(tacho_sym_t sym, int precision, int64_t *bytes);
+
+/*
  * Refactorization with new values on the same pattern (Trilinos section:
  * the symbolic analysis is amortized across value changes).  Same arguments
  * as tacho_factorize; the handle keeps its precision and device memory.  On
@@ -203,7 +220,8 @@ int tacho_check_factor(tacho_num_t num, int64_t *fail_index);
  * residual of every column is <= refine_tol; when refinement stalls the
  * handle is refactored in FP64 and the solve is repeated (info->fell_back).
  * Blocks until the result is available when on_device = 0 or for the FP32
- * path; the FP64 device path only queues work.
+ * path; the FP64 device path only queues work, also behind a factorization
+ * queued with sync = 0 (whose failure flag tacho_check_factor then reports).
  */
 int tacho_solve(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64_t ld,
                 int on_device, void *hip_stream, tacho_solve_info *info);

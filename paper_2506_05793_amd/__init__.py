@@ -45,7 +45,8 @@ class tacho_options(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("block_size", ctypes.c_int32),
         ("ordering", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("graphs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -99,6 +100,8 @@ def _load():
         "tacho_factorize": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, _vp,
                                            ctypes.POINTER(_vp), _i64p]),
         "tacho_refactorize": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, _i64p]),
+        "tacho_numeric_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_vp)]),
+        "tacho_numeric_bytes": (ctypes.c_int, [_vp, ctypes.c_int, _i64p]),
         "tacho_check_factor": (ctypes.c_int, [_vp, _i64p]),
         "tacho_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                        _vp, ctypes.POINTER(tacho_solve_info)]),
@@ -261,6 +264,18 @@ def tacho_factorize(sym: SymbolicHandle, values, precision: int = TACHO_FP64,
                              ctypes.byref(out), ctypes.byref(fi))
     _check(rc, fi.value)
     return NumericHandle(out.value, sym, precision)
+
+
+def tacho_numeric_create(sym: SymbolicHandle, precision: int = TACHO_FP64) -> NumericHandle:
+    out = _vp()
+    _check(_load().tacho_numeric_create(sym.ptr, int(precision), ctypes.byref(out)))
+    return NumericHandle(out.value, sym, precision)
+
+
+def tacho_numeric_bytes(sym: SymbolicHandle, precision: int = TACHO_FP64) -> int:
+    b = ctypes.c_int64(0)
+    _check(_load().tacho_numeric_bytes(sym.ptr, int(precision), ctypes.byref(b)))
+    return b.value
 
 
 def tacho_refactorize(num: NumericHandle, values, stream=None, sync: bool = True) -> None:

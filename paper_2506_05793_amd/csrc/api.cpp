@@ -89,8 +89,10 @@ struct tacho_sym {
   bool uploaded = false;
   int device = -1;
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
-      d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q;
-  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_levels, d_fwd_items, d_bwd_items;
+      d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
+      d_wbase, d_woff, d_gather;
+  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_levels, d_fwd_items, d_bwd_items,
+      d_tri_fwd, d_tri_bwd;
   DBuf d_rowptr, d_colind, d_mirror;
   DevSym view{};
   std::mutex mu;
@@ -161,6 +163,7 @@ struct tacho_num {
   int precision = TACHO_FP64;
   DBuf L, U, avals, vals, fullvals, scale, fail, winv;
   DBuf y, uvec;             // solve workspace (kRhs columns)
+  DBuf sync;                // solve tickets (2 per level) and block ready flags
   DBuf bdev, xdev, r, dx, norms;  // host-pointer staging and refinement buffers
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool pending = false;     // factorization queued, flag not yet read
@@ -168,7 +171,9 @@ struct tacho_num {
   int64_t last_fail = -1;
   hipStream_t last_stream = nullptr;
   tacho_num* fallback = nullptr;  // FP64 refactorization after a refinement stall
+  hipGraphExec_t fgraph = nullptr;  // captured factorization launch sequence
   ~tacho_num() {
+    if (fgraph) (void)hipGraphExecDestroy(fgraph);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     delete fallback;
@@ -190,6 +195,8 @@ tacho_options defaults() {
   o.stall_ratio = 0.5;
   o.hbm_budget_bytes = 0;
   o.block_size = 0;
+  o.ordering = 0;
+  o.graphs = 1;
   return o;
 }
 
@@ -258,6 +265,9 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_u_off, P.u_off));
   HIP_TRY(upload(h->d_perm, S.perm));
   HIP_TRY(upload(h->d_diag_q, P.diag_q));
+  HIP_TRY(upload(h->d_wbase, P.wbase));
+  HIP_TRY(upload(h->d_woff, P.woff));
+  HIP_TRY(upload(h->d_gather, P.gather_list));
   HIP_TRY(upload(h->d_small, P.small_list));
   HIP_TRY(upload(h->d_asm, P.asm_items));
   HIP_TRY(upload(h->d_diag, P.diag_items));
@@ -267,6 +277,8 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_levels, S.level_list));
   HIP_TRY(upload(h->d_fwd_items, P.fwd_items));
   HIP_TRY(upload(h->d_bwd_items, P.bwd_items));
+  HIP_TRY(upload(h->d_tri_fwd, P.tri_fwd));
+  HIP_TRY(upload(h->d_tri_bwd, P.tri_bwd));
   HIP_TRY(upload(h->d_rowptr, S.A.rowptr));
   HIP_TRY(upload(h->d_colind, S.A.colind));
   HIP_TRY(upload(h->d_mirror, h->mirror));
@@ -290,6 +302,8 @@ int ensure_uploaded(tacho_sym* h) {
   v.u_off = h->d_u_off.as<int64_t>();
   v.perm = h->d_perm.as<int32_t>();
   v.diag_q = h->d_diag_q.as<int32_t>();
+  v.wbase = h->d_wbase.as<int32_t>();
+  v.woff = h->d_woff.as<int64_t>();
   h->device = dev;
   h->uploaded = true;
   return TACHO_OK;
@@ -307,7 +321,8 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += (int64_t)es * P.L_elems + (int64_t)es * P.U_elems + (int64_t)es * (int64_t)S.a_src.size();
   b += 8 * S.nnz_input + 4;
   b += (int64_t)es * (S.n + P.u_elems) * kRhs;
-  b += (int64_t)es * P.max_wslots * kPanel * kPanel;
+  b += (int64_t)es * P.W_elems;
+  b += 4 * (2 * S.nlevels + P.tri_flags + 1);
   if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;
   return b;
 }
@@ -353,7 +368,7 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
       case kStepAssemble: launch_assemble<T>(S, N, asmi + s.begin, cnt, st); break;
       case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, f->winv.as<T>(), st); break;
       case kStepPanel: launch_panel<T>(S, N, pan + s.begin, cnt, f->winv.as<T>(), st); break;
-      case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, st); break;
+      case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, s.tile, st); break;
     }
     f->prof.end(pe, st, step_kind(s.kind), s.flops, s.elems * sizeof(T));
   }
@@ -377,21 +392,16 @@ int read_fail_flag(tacho_num* f, int64_t* fail_index) {
   return TACHO_OK;
 }
 
-int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, int sync,
-             int64_t* fail_index) {
+// Device work of one factorization after the values are resident: failure
+// flag reset, value gather (and for FP32 the scaling and the FP64 values of
+// the refinement residual), then every level's launches.
+void enqueue_factor(tacho_num* f, hipStream_t st) {
   tacho_sym* h = f->sym;
   const Symbolic& S = h->S;
-  const int64_t nv = S.nnz_input;
-  if (nv > 0 && !values) return fail(TACHO_ERR_INVALID, "values is NULL");
-  if (nv > 0)
-    HIP_TRY(hipMemcpyAsync(f->vals.p, values, nv * sizeof(double),
-                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(f->ev[0], st));
   launch_fill_i32(f->fail.as<int32_t>(), INT32_MAX, 1, st);
   const double* vals = f->vals.as<double>();
   const int64_t nq = (int64_t)S.a_src.size();
   if (f->precision == TACHO_FP32) {
-    // full symmetric FP64 values (lower twins) for the refinement residual
     launch_mirror(h->d_mirror.as<int64_t>(), vals, f->fullvals.as<double>(),
                   (int64_t)S.A.colind.size(), st);
     if (h->opt.scale) launch_scale(h->view, vals, f->scale.as<double>(), st);
@@ -404,6 +414,48 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
     launch_gather<double>(h->view, num_view<double>(f), vals, nq, st);
     f->prof.end(pe, st, TACHO_K_GATHER, 0, nq * (8.0 + 8.0 + 8.0));
     run_factor_steps<double>(f, st);
+  }
+}
+
+// The factorization's launch sequence captured once into a graph on a
+// private stream; replays go to the caller's stream.
+int build_factor_graph(tacho_num* f) {
+  hipStream_t cs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    enqueue_factor(f, cs);
+    e = hipStreamEndCapture(cs, &g);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&f->fgraph, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    f->fgraph = nullptr;
+    return fail(TACHO_ERR_HIP, std::string("factorization graph: ") + hipGetErrorString(e));
+  }
+  return TACHO_OK;
+}
+
+int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, int sync,
+             int64_t* fail_index) {
+  tacho_sym* h = f->sym;
+  const Symbolic& S = h->S;
+  const int64_t nv = S.nnz_input;
+  if (nv > 0 && !values) return fail(TACHO_ERR_INVALID, "values is NULL");
+  if (nv > 0)
+    HIP_TRY(hipMemcpyAsync(f->vals.p, values, nv * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(f->ev[0], st));
+  if (h->opt.graphs != 0 && !f->prof.on) {
+    if (!f->fgraph) {
+      const int rc = build_factor_graph(f);
+      if (rc != TACHO_OK) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(f->fgraph, st));
+  } else {
+    enqueue_factor(f, st);
   }
   HIP_TRY(hipEventRecord(f->ev[1], st));
   HIP_TRY(hipGetLastError());
@@ -431,9 +483,10 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   HIP_TRY(f->avals.alloc(es * S.a_src.size()));
   HIP_TRY(f->vals.alloc(sizeof(double) * S.nnz_input));
   HIP_TRY(f->fail.alloc(sizeof(int32_t)));
-  HIP_TRY(f->winv.alloc(es * std::max<int64_t>(P.max_wslots, 1) * kPanel * kPanel));
+  HIP_TRY(f->winv.alloc(es * std::max<int64_t>(P.W_elems, 1)));
   HIP_TRY(f->y.alloc(es * S.n * kRhs));
   HIP_TRY(f->uvec.alloc(es * P.u_elems * kRhs));
+  HIP_TRY(f->sync.alloc(sizeof(int32_t) * (2 * S.nlevels + P.tri_flags + 1)));
   if (precision == TACHO_FP32) {
     HIP_TRY(f->scale.alloc(sizeof(double) * S.n));
     HIP_TRY(f->fullvals.alloc(sizeof(double) * S.A.colind.size()));
@@ -463,19 +516,32 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * nrhs * (8.0 + es) + 4.0 * S.n);
   const SolveItem* fwi = h->d_fwd_items.as<SolveItem>();
   const SolveItem* bwi = h->d_bwd_items.as<SolveItem>();
+  const TriItem* tfw = h->d_tri_fwd.as<TriItem>();
+  const TriItem* tbw = h->d_tri_bwd.as<TriItem>();
+  int32_t* counters = f->sync.as<int32_t>();
+  int32_t* flags = counters + 2 * S.nlevels;
+  launch_fill_i32(counters, 0, 2 * S.nlevels + P.tri_flags, st);
   for (int32_t lvl = 0; lvl < S.nlevels; ++lvl) {
+    const int64_t t0 = P.tri_ptr[lvl], t1 = P.tri_ptr[lvl + 1];
     pe = f->prof.begin(st);
     launch_fwd<T>(V, L, y, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
                   nrhs, st);
+    launch_fwd_tri<T>(V, L, f->winv.as<T>(), y, tfw + t0, t1 - t0, counters + 2 * lvl, flags,
+                      nrhs, st);
     launch_fwd_gemv<T>(V, L, y, uv, fwi + P.fwd_ptr[lvl], P.fwd_ptr[lvl + 1] - P.fwd_ptr[lvl],
                        nrhs, st);
     f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * P.level_lentries[lvl] * nrhs,
                 es * (P.level_lentries[lvl] + 2.0 * P.level_rows[lvl] * nrhs));
   }
   for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl) {
+    const int64_t t0 = P.tri_ptr[lvl], t1 = P.tri_ptr[lvl + 1];
     pe = f->prof.begin(st);
-    launch_bwd_gemv<T>(V, L, y, bwi + P.bwd_ptr[lvl], P.bwd_ptr[lvl + 1] - P.bwd_ptr[lvl], nrhs,
-                       st);
+    launch_bwd_gather<T>(V, y, uv, h->d_gather.as<int32_t>() + P.gather_ptr[lvl],
+                         P.gather_ptr[lvl + 1] - P.gather_ptr[lvl], nrhs, st);
+    launch_bwd_gemv<T>(V, L, y, uv, bwi + P.bwd_ptr[lvl], P.bwd_ptr[lvl + 1] - P.bwd_ptr[lvl],
+                       nrhs, st);
+    launch_bwd_tri<T>(V, L, f->winv.as<T>(), y, tbw + t0, t1 - t0, counters + 2 * lvl + 1, flags,
+                      nrhs, st);
     launch_bwd<T>(V, L, y, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl], nrhs,
                   st);
     f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * P.level_lentries[lvl] * nrhs,
@@ -726,6 +792,25 @@ int tacho_factorize(tacho_sym_t h, const double* values, int values_on_device, i
   return TACHO_OK;
 }
 
+int tacho_numeric_create(tacho_sym_t h, int precision, tacho_num_t* out) {
+  if (!h || !out) return fail(TACHO_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  if (precision != TACHO_FP64 && precision != TACHO_FP32)
+    return fail(TACHO_ERR_INVALID, "unknown precision");
+  tacho_num* f = nullptr;
+  const int rc = create_numeric(h, precision, &f);
+  if (rc != TACHO_OK) return rc;
+  f->last_status = TACHO_ERR_INVALID;  // no factor until the first refactorization
+  *out = f;
+  return TACHO_OK;
+}
+
+int tacho_numeric_bytes(tacho_sym_t h, int precision, int64_t* bytes) {
+  if (!h || !bytes) return fail(TACHO_ERR_INVALID, "NULL argument");
+  *bytes = numeric_bytes(h, precision);
+  return TACHO_OK;
+}
+
 int tacho_refactorize(tacho_num_t f, const double* values, int values_on_device, void* hip_stream,
                       int sync, int64_t* fail_index) {
   if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
@@ -752,10 +837,14 @@ int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t
     info->fell_back = 0;
     info->relres_max = 0;
   }
-  if (f->pending) {
+  // A factorization queued without waiting is not checked here when the solve
+  // stays on the device in FP64: the solve is queued behind it and
+  // tacho_check_factor tells whether the result is valid.
+  const bool queue_only = on_device && f->precision == TACHO_FP64;
+  if (f->pending && !queue_only) {
     int rc = read_fail_flag(f, nullptr);
     if (rc != TACHO_OK) return rc;
-  } else if (f->last_status != TACHO_OK) {
+  } else if (!f->pending && f->last_status != TACHO_OK) {
     return fail(f->last_status, "no valid factor in this handle");
   }
   if (nrhs == 0 || n == 0) return TACHO_OK;

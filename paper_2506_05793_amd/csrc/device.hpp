@@ -30,6 +30,8 @@ struct DevSym {
   const int64_t* u_off;
   const int32_t* perm;       // new -> old
   const int32_t* diag_q;     // per permuted column: A entry of the diagonal or -1
+  const int32_t* wbase;      // per supernode: first diagonal-inverse block (-1: none)
+  const int64_t* woff;       // per diagonal-inverse block: element offset
 };
 
 template <typename T>
@@ -63,7 +65,7 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
                   const T* winv, hipStream_t st);
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
-                 hipStream_t st);
+                 int tile, hipStream_t st);
 
 // Solves: y is the permuted right-hand side / solution (n x nrhs, ld n).
 template <typename T>
@@ -83,8 +85,18 @@ template <typename T>
 void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* uvec, const SolveItem* items,
                      int64_t count, int32_t nrhs, hipStream_t st);
 template <typename T>
-void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const SolveItem* items, int64_t count,
-                     int32_t nrhs, hipStream_t st);
+void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const T* uvec, const SolveItem* items,
+                     int64_t count, int32_t nrhs, hipStream_t st);
+template <typename T>
+void launch_bwd_gather(const DevSym& S, const T* y, T* uvec, const int32_t* list, int64_t count,
+                       int32_t nrhs, hipStream_t st);
+
+template <typename T>
+void launch_fwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
+                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st);
+template <typename T>
+void launch_bwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
+                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st);
 
 // FP64 refinement helpers: r = b - A x (original numbering, CSR), column norms.
 void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,

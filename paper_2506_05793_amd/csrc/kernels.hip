@@ -53,6 +53,21 @@ __device__ inline int mfma_row<double>(int lane, int v) { return (lane >> 4) + 4
 template <>
 __device__ inline int mfma_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
 
+// Value of `v` in lane `l` (uniform result).
+__device__ inline double readlane(double v, int l) {
+  union {
+    double d;
+    int i[2];
+  } u;
+  u.d = v;
+  u.i[0] = __builtin_amdgcn_readlane(u.i[0], l);
+  u.i[1] = __builtin_amdgcn_readlane(u.i[1], l);
+  return u.d;
+}
+__device__ inline float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -226,6 +241,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
                                                    T* winv) {
   __shared__ T D[kPanel * kDiagLd];  // column-major, D[c * kDiagLd + r]
   __shared__ T W[kPanel * kDiagLd];
+  __shared__ T rd[kPanel];           // 1 / L_jj
   const PanelItem it = items[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = it.s, k = it.k, kb = it.kb;
@@ -242,30 +258,29 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
   }
   __syncthreads();
   for (int jb = 0; jb < kPanel; jb += kSub) {
-    // (1) 16x16 diagonal block by wave 0; lanes own rows jb + (lane & 15)
-    if (wave == 0) {
-      for (int j = jb; j < jb + kSub; ++j) {
-        const T d = D[j * kDiagLd + j];
-        const T ljj = sqrt(d);
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-          if (j < kb && !(d > T(0))) atomicMin(N.fail, f + k + j);
-          D[j * kDiagLd + j] = ljj;
+    // (1) 16x16 diagonal block in registers: lane i < 16 holds row jb + i;
+    // pivots and column entries are broadcast with readlane.
+    if (wave == 0 && lane < kSub) {
+      T a[kSub];
+#pragma unroll
+      for (int c = 0; c < kSub; ++c) a[c] = D[(jb + c) * kDiagLd + jb + lane];
+#pragma unroll
+      for (int j = 0; j < kSub; ++j) {
+        const T piv = readlane(a[j], j);
+        if (lane == 0 && jb + j < kb && !(piv > T(0))) atomicMin(N.fail, f + k + jb + j);
+        const T ljj = sqrt(piv);
+        const T rinv = T(1) / ljj;
+        if (lane == 0) rd[jb + j] = rinv;
+        a[j] = lane == j ? ljj : (lane > j ? a[j] * rinv : a[j]);
+#pragma unroll
+        for (int c = j + 1; c < kSub; ++c) {
+          const T lcj = readlane(a[j], c);
+          if (lane >= c) a[c] -= a[j] * lcj;
         }
-        const int i = jb + (lane & 15);
-        if (lane < kSub && i > j) D[j * kDiagLd + i] = D[j * kDiagLd + i] / ljj;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // rank-1 update inside the 16x16 block: lanes cover (row, col) pairs
-        for (int t = lane; t < kSub * kSub; t += 64) {
-          const int r = jb + (t & 15), c = jb + (t >> 4);
-          if (c > j && r >= c) D[c * kDiagLd + r] -= D[j * kDiagLd + r] * D[j * kDiagLd + c];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
+#pragma unroll
+      for (int c = 0; c < kSub; ++c)
+        if (c <= lane) D[(jb + c) * kDiagLd + jb + lane] = a[c];
     }
     __syncthreads();
     // (2) rows below the block: one thread per row, forward substitution
@@ -280,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
         T acc = x[c];
 #pragma unroll
         for (int c2 = 0; c2 < c; ++c2) acc -= x[c2] * D[(jb + c2) * kDiagLd + jb + c];
-        x[c] = acc / D[(jb + c) * kDiagLd + jb + c];
+        x[c] = acc * rd[jb + c];
       }
 #pragma unroll
       for (int c = 0; c < kSub; ++c) D[(jb + c) * kDiagLd + r] = x[c];
@@ -307,9 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
   // column of each block, forward substitution down its own column), then
   // the off-diagonal blocks by distance d = 1..3 from the diagonal:
   // W_ib = -W_ii * sum_{q=b}^{i-1} L_iq W_qb.
-  __shared__ T rd[kPanel];
   __shared__ T Tmp[3][kSub * kSub];
-  if (tid < kPanel) rd[tid] = T(1) / D[tid * kDiagLd + tid];
   for (int t = tid; t < kPanel * kPanel; t += kThreads) {
     const int c = t / kPanel, r = t - c * kPanel;
     W[c * kDiagLd + r] = T(0);
@@ -345,9 +358,9 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
     }
     __syncthreads();
   }
-  T* Wout = winv + (int64_t)it.wslot * kPanel * kPanel;
-  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
-    const int c = t / kPanel, r = t - c * kPanel;
+  T* Wout = winv + S.woff[it.wblk];  // kb x kb, column-major
+  for (int t = tid; t < kb * kb; t += kThreads) {
+    const int c = t / kb, r = t - c * kb;
     Wout[t] = W[c * kDiagLd + r];
   }
 }
@@ -367,10 +380,10 @@ __global__ __launch_bounds__(kThreads) void k_panel(DevSym S, DevNum<T> N, const
   const int m = S.front_m[s], ld = S.ldL[s];
   T* Lp = N.L + S.L_off[s];
   const int r0 = k + kb + it.chunk * kPanel;
-  const T* Win = winv + (int64_t)it.wslot * kPanel * kPanel;
+  const T* Win = winv + S.woff[it.wblk];  // kb x kb column-major: Win[c * kb + r] = W[r][c]
   for (int t = tid; t < kPanel * kPanel; t += kThreads) {
-    const int c = t / kPanel, r = t - c * kPanel;  // W stored column-major: Win[c * 64 + r] = W[r][c]
-    Ws[c][r] = Win[t];
+    const int c = t / kPanel, r = t - c * kPanel;
+    Ws[c][r] = (r < kb && c < kb) ? Win[c * kb + r] : T(0);
     const int row = r0 + r;
     Bs[c][r] = (row < m && c < kb) ? Lp[row + (int64_t)(k + c) * ld] : T(0);
   }
@@ -411,16 +424,21 @@ __global__ __launch_bounds__(kThreads) void k_panel(DevSym S, DevNum<T> N, const
 
 // ---------------------------------------------------------------------------
 // Update on the matrix cores: C[M x N] -= A[M x K] * A[0:N, :]^T for the
-// elements with row >= col.  One 64x64 output tile per workgroup, four waves
-// of 32x32 (2x2 blocks of 16x16x4 MFMA), K staged through LDS 16 at a time.
-// The MFMA computes the transposed tile so that a lane's outputs run down a
-// column of the column-major C (coalesced read-modify-write).
-template <typename T>
+// elements with row >= col.  One TT x TT output tile per workgroup, four
+// waves of (TT/2) x (TT/2) built from 16x16x4 MFMA blocks, K staged through
+// double-buffered LDS 16 at a time with the next stage prefetched into
+// registers while the current one is multiplied.  The MFMA computes the
+// transposed tile so that a lane's outputs run down a column of the
+// column-major C (coalesced read-modify-write).
+template <typename T, int TT>
 __global__ __launch_bounds__(kThreads) void k_gemm(DevNum<T> N, const GemmProb* probs,
                                                    const GemmTile* tiles) {
-  constexpr int TT = kGemmTile, KT = 16, PAD = 4;
-  __shared__ T As[KT][TT + PAD];
-  __shared__ T Bs[KT][TT + PAD];
+  constexpr int KT = 16, PAD = 4;
+  constexpr int BL = TT / 32;               // 16x16 blocks per wave dimension
+  constexpr int LPT = TT * KT / kThreads;   // elements per thread per stage and operand
+  constexpr int RSTEP = kThreads / TT;      // k rows covered per load round
+  __shared__ T As[2][KT][TT + PAD];
+  __shared__ T Bs[2][KT][TT + PAD];
   const GemmTile tl = tiles[blockIdx.x];
   const GemmProb g = probs[tl.prob];
   const T* A = N.L + g.a_off;
@@ -429,45 +447,63 @@ __global__ __launch_bounds__(kThreads) void k_gemm(DevNum<T> N, const GemmProb* 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   typedef typename Vec4<T>::type V4;
-  V4 acc[2][2];
+  V4 acc[BL][BL];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < BL; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
-  const int lrow = tid & 63, lk = tid >> 6;
+    for (int b = 0; b < BL; ++b) acc[a][b] = V4{0, 0, 0, 0};
+  const int lrow = tid % TT, lk = tid / TT;
   const bool arow_ok = i0 + lrow < g.M, brow_ok = j0 + lrow < g.N;
-  for (int k0 = 0; k0 < g.K; k0 += KT) {
+  const T* pa = A + (i0 + lrow);
+  const T* pb = A + (j0 + lrow);
+  T ra[LPT], rb[LPT];
+  auto load_stage = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < KT / 4; ++u) {
-      const int kk = lk + 4 * u, kg = k0 + kk;
+    for (int u = 0; u < LPT; ++u) {
+      const int kg = k0 + lk + RSTEP * u;
       const bool kok = kg < g.K;
-      As[kk][lrow] = (arow_ok && kok) ? A[(i0 + lrow) + (int64_t)kg * g.lda] : T(0);
-      Bs[kk][lrow] = (brow_ok && kok) ? A[(j0 + lrow) + (int64_t)kg * g.lda] : T(0);
+      ra[u] = (arow_ok && kok) ? pa[(int64_t)kg * g.lda] : T(0);
+      rb[u] = (brow_ok && kok) ? pb[(int64_t)kg * g.lda] : T(0);
     }
-    __syncthreads();
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      As[buf][lk + RSTEP * u][lrow] = ra[u];
+      Bs[buf][lk + RSTEP * u][lrow] = rb[u];
+    }
+  };
+  const int nstage = (g.K + KT - 1) / KT;
+  load_stage(0);
+  store_stage(0);
+  __syncthreads();
+  for (int st = 0; st < nstage; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nstage) load_stage((st + 1) * KT);
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
       const int kr = ks * 4 + (lane >> 4);
-      T av[2], bv[2];
+      T av[BL], bv[BL];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[kr][wr * 32 + a * 16 + (lane & 15)];
+      for (int a = 0; a < BL; ++a) av[a] = As[buf][kr][wr * (TT / 2) + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = Bs[kr][wc * 32 + b * 16 + (lane & 15)];
+      for (int b = 0; b < BL; ++b) bv[b] = Bs[buf][kr][wc * (TT / 2) + b * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < BL; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+        for (int b = 0; b < BL; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
     }
+    if (st + 1 < nstage) store_stage(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < BL; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BL; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wr * 32 + a * 16 + (lane & 15);
-        const int j = j0 + wc * 32 + b * 16 + mfma_row<T>(lane, v);
+        const int i = i0 + wr * (TT / 2) + a * 16 + (lane & 15);
+        const int j = j0 + wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
         if (i < g.M && j < g.N && i >= j) {
           T* p = C + i + (int64_t)j * g.ldc;
           *p = *p - acc[a][b][v];
@@ -511,9 +547,28 @@ __global__ __launch_bounds__(kThreads) void k_permute_out(DevSym S, const T* y, 
   }
 }
 
-// Fronts with r_s * w_s >= kSolveSplit leave the L21 products of the solves
-// to the multi-workgroup kernels k_fwd_gemv / k_bwd_gemv.
-__device__ inline bool solve_split(int w, int r) { return (int64_t)r * w >= kSolveSplit; }
+// Split fronts (solve_split_front) leave their L11 solves to the pipelined
+// kernels k_fwd_tri / k_bwd_tri and their L21 products to k_fwd_gemv /
+// k_bwd_gemv.
+__device__ inline bool solve_split(int w, int r) { return solve_split_front(w, r); }
+
+// Ready flags of the pipelined L11 solves.  A workgroup waits only for blocks
+// whose tickets are smaller than its own, and tickets are taken from an
+// atomic counter by running workgroups, so every awaited block belongs to a
+// workgroup that is already resident; the spin is bounded all the same.
+constexpr int kSpinLimit = 1 << 25;
+
+__device__ inline void wait_flag(const int32_t* flag, int32_t value) {
+  int spins = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < value) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) break;
+  }
+}
+
+__device__ inline void set_flag(int32_t* flag, int32_t value) {
+  __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T* uvec,
@@ -527,7 +582,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T*
   const int64_t n = S.n;
   const T* Lp = L + S.L_off[s];
   T* us = uvec + S.u_off[s] * nrhs;
-  const int mrow = solve_split(w, r) ? w : m;  // rows updated here
+  const bool split = solve_split(w, r);
   for (int t = tid; t < r * nrhs; t += kThreads) us[t] = T(0);
   __syncthreads();
   for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
@@ -546,6 +601,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T*
     }
     __syncthreads();
   }
+  if (split) return;  // L11 and L21 parts follow in k_fwd_tri / k_fwd_gemv
   for (int jb = 0; jb < w; jb += kPanel) {
     const int kb = min(kPanel, w - jb);
     for (int t = tid; t < kb * kb; t += kThreads) {
@@ -572,7 +628,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T*
       }
     }
     __syncthreads();
-    for (int i = jb + kb + tid; i < mrow; i += kThreads) {
+    for (int i = jb + kb + tid; i < m; i += kThreads) {
       T acc[kRhsBlock];
 #pragma unroll
       for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
@@ -659,8 +715,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd(DevSym S, const T* L, T* y, co
   const int64_t n = S.n;
   const T* Lp = L + S.L_off[s];
   const int32_t* rws = S.rows + S.rows_ptr[s];
-  if (w == 0) return;
-  const int mrow = solve_split(w, m - w) ? w : m;  // L21^T x already applied when split
+  if (w == 0 || solve_split(w, m - w)) return;  // split fronts: k_bwd_gemv + k_bwd_tri
+  const int mrow = m;
   for (int jb = ((w - 1) / kPanel) * kPanel; jb >= 0; jb -= kPanel) {
     const int kb = min(kPanel, w - jb);
     for (int t = tid; t < kb * kb; t += kThreads) {
@@ -694,55 +750,217 @@ __global__ __launch_bounds__(kThreads) void k_bwd(DevSym S, const T* L, T* y, co
   }
 }
 
-// Backward solve, L21 part of a split front: y_s[cols] -= L21[:, cols]^T x[rows(s)[w:]]
-// for kPanel columns per workgroup; lanes own columns (each lane walks its
-// column down, the 64 columns of a wave share cache lines), the four waves
-// split the rows, the gathered x is staged through LDS.
+// Pipelined L11 solves of split fronts, one workgroup per 64-row block.
+// Forward: block b accumulates L_bj x_j for j < b as the blocks' flags
+// become ready, then applies the inverse of its diagonal block kept from the
+// factorization (x_b = W_bb z, the explicit diagonal-block inverse of the
+// paper's solve variant 2) and publishes x_b.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_gemv(DevSym S, const T* L, T* y,
-                                                       const SolveItem* items, int nrhs) {
-  __shared__ T XG[kSolveChunk * kRhsBlock];
+__global__ __launch_bounds__(kThreads) void k_fwd_tri(DevSym S, const T* L, const T* winv, T* y,
+                                                      const TriItem* items, int count,
+                                                      int32_t* counter, int32_t* flags, int nrhs) {
+  __shared__ T D[kPanel * kDiagLd];
+  __shared__ T X[kPanel * kRhsBlock];
   __shared__ T part[kThreads / 64][kPanel * kRhsBlock];
-  const SolveItem it = items[blockIdx.x];
-  const int s = it.s;
+  __shared__ int s_ticket;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  if (tid == 0) s_ticket = atomicAdd(counter, 1);
+  __syncthreads();
+  const int ticket = s_ticket;
+  if (ticket >= count) return;
+  const TriItem it = items[ticket];
+  const int s = it.s, b = it.b;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f;
   const int ldl = S.ldL[s];
   const int64_t n = S.n;
   const T* Lp = L + S.L_off[s];
-  const int32_t* rws = S.rows + S.rows_ptr[s] + w;
-  const int j = it.chunk * kPanel + lane;
-  const bool valid = j < w;
-  const T* lc = Lp + (int64_t)(valid ? j : 0) * ldl + w;
+  const int r0 = b * kPanel, kb = min(kPanel, w - r0);
+  const bool valid = lane < kb;
+  const int row = r0 + (valid ? lane : 0);
   T acc[kRhsBlock];
 #pragma unroll
   for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
-  for (int rb = 0; rb < r; rb += kSolveChunk) {
-    const int rw = min(kSolveChunk, r - rb);
+  for (int j = 0; j < b; ++j) {
+    if (tid == 0) wait_flag(flags + it.flag - b + j, 1);
     __syncthreads();
-    for (int t = tid; t < rw * nrhs; t += kThreads) {
-      const int col = t / rw, i = t - col * rw;
-      XG[i + col * kSolveChunk] = y[(int64_t)rws[rb + i] + col * n];
+    for (int t = tid; t < kPanel * nrhs; t += kThreads) {
+      const int col = t / kPanel, c = t - col * kPanel;
+      X[c + col * kPanel] = y[f + j * kPanel + c + col * n];
     }
     __syncthreads();
     if (valid) {
-      for (int i = wave; i < rw; i += kThreads / 64) {
-        const T l = lc[rb + i];
+      for (int c = wave; c < kPanel; c += kThreads / 64) {
+        const T l = Lp[row + (int64_t)(j * kPanel + c) * ldl];
 #pragma unroll
         for (int col = 0; col < kRhsBlock; ++col)
-          if (col < nrhs) acc[col] += l * XG[i + col * kSolveChunk];
+          if (col < nrhs) acc[col] += l * X[c + col * kPanel];
       }
     }
+    __syncthreads();
   }
 #pragma unroll
   for (int col = 0; col < kRhsBlock; ++col) part[wave][lane + col * kPanel] = acc[col];
+  {
+    const T* Wb = winv + S.woff[S.wbase[s] + b];  // W_bb = L_bb^{-1}, kb x kb column-major
+    for (int t = tid; t < kb * kb; t += kThreads) {
+      const int c = t / kb, rr = t - c * kb;
+      D[c * kDiagLd + rr] = Wb[t];
+    }
+  }
   __syncthreads();
   if (wave == 0 && valid) {
     for (int col = 0; col < nrhs; ++col) {
       T t = T(0);
 #pragma unroll
       for (int q = 0; q < kThreads / 64; ++q) t += part[q][lane + col * kPanel];
-      y[f + j + col * n] -= t;
+      X[lane + col * kPanel] = y[f + r0 + lane + col * n] - t;
+    }
+  }
+  __syncthreads();
+  // x_b = W_bb z: lane = row, waves split the right-hand sides
+  for (int col = wave; col < nrhs; col += kThreads / 64) {
+    if (lane < kb) {
+      T acc = T(0);
+      for (int c = 0; c <= lane; ++c) acc += D[c * kDiagLd + lane] * X[c + col * kPanel];
+      y[f + r0 + lane + col * n] = acc;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) set_flag(flags + it.flag, 1);
+}
+
+// Backward: block b (taken from the bottom) subtracts L_cb^T x_c for c > b
+// as those blocks' flags become ready, then x_b = W_bb^T t_b.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_tri(DevSym S, const T* L, const T* winv, T* y,
+                                                      const TriItem* items, int count,
+                                                      int32_t* counter, int32_t* flags, int nrhs) {
+  __shared__ T D[kPanel * kDiagLd];
+  __shared__ T X[kPanel * kRhsBlock];
+  __shared__ T part[kThreads / 64][kPanel * kRhsBlock];
+  __shared__ int s_ticket;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) s_ticket = atomicAdd(counter, 1);
+  __syncthreads();
+  const int ticket = s_ticket;
+  if (ticket >= count) return;
+  const TriItem it = items[ticket];
+  const int s = it.s, b = it.b;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f;
+  const int ldl = S.ldL[s];
+  const int64_t n = S.n;
+  const T* Lp = L + S.L_off[s];
+  const int nb = (w + kPanel - 1) / kPanel;
+  const int r0 = b * kPanel, kb = min(kPanel, w - r0);
+  const bool valid = lane < kb;
+  const int colj = r0 + (valid ? lane : 0);  // this lane's column of block b
+  T acc[kRhsBlock];
+#pragma unroll
+  for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
+  for (int c = nb - 1; c > b; --c) {
+    if (tid == 0) wait_flag(flags + it.flag - b + c, 2);
+    __syncthreads();
+    const int kc = min(kPanel, w - c * kPanel);
+    for (int t = tid; t < kc * nrhs; t += kThreads) {
+      const int col = t / kc, q = t - col * kc;
+      X[q + col * kPanel] = y[f + c * kPanel + q + col * n];
+    }
+    __syncthreads();
+    if (valid) {
+      const T* lc = Lp + (int64_t)colj * ldl + c * kPanel;
+      for (int q = wave; q < kc; q += kThreads / 64) {
+        const T l = lc[q];
+#pragma unroll
+        for (int col = 0; col < kRhsBlock; ++col)
+          if (col < nrhs) acc[col] += l * X[q + col * kPanel];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int col = 0; col < kRhsBlock; ++col) part[wave][lane + col * kPanel] = acc[col];
+  {
+    const T* Wb = winv + S.woff[S.wbase[s] + b];  // W_bb = L_bb^{-1}, kb x kb column-major
+    for (int t = tid; t < kb * kb; t += kThreads) {
+      const int c = t / kb, rr = t - c * kb;
+      D[c * kDiagLd + rr] = Wb[t];
+    }
+  }
+  __syncthreads();
+  if (wave == 0 && valid) {
+    for (int col = 0; col < nrhs; ++col) {
+      T t = T(0);
+#pragma unroll
+      for (int q = 0; q < kThreads / 64; ++q) t += part[q][lane + col * kPanel];
+      X[lane + col * kPanel] = y[f + r0 + lane + col * n] - t;
+    }
+  }
+  __syncthreads();
+  // x_b = W_bb^T t: lane = row, waves split the right-hand sides
+  for (int col = wave; col < nrhs; col += kThreads / 64) {
+    if (lane < kb) {
+      T acc = T(0);
+      for (int c = lane; c < kb; ++c) acc += D[lane * kDiagLd + c] * X[c + col * kPanel];
+      y[f + r0 + lane + col * n] = acc;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) set_flag(flags + it.flag, 2);
+}
+
+// Backward solve of a split front, gather step: u_s = x[rows(s)[w:]] (the
+// update-vector slot of s is free again in the backward sweep).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_gather(DevSym S, const T* y, T* uvec,
+                                                         const int32_t* list, int nrhs) {
+  const int s = list[blockIdx.x];
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, r = S.front_m[s] - w;
+  const int32_t* rws = S.rows + S.rows_ptr[s] + w;
+  T* us = uvec + S.u_off[s] * nrhs;
+  for (int t = threadIdx.x; t < r * nrhs; t += kThreads) {
+    const int col = t / r, i = t - col * r;
+    us[t] = y[(int64_t)rws[i] + col * S.n];
+  }
+}
+
+// Backward solve, L21 part of a split front: y_s[cols] -= L21[:, cols]^T u_s
+// for kPanel columns per workgroup; each wave takes 16 columns one at a time,
+// lanes stride down the column (coalesced), one wave reduction per column
+// and right-hand side.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_gemv(DevSym S, const T* L, T* y, const T* uvec,
+                                                       const SolveItem* items, int nrhs) {
+  const SolveItem it = items[blockIdx.x];
+  const int s = it.s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  if (r == 0) return;
+  const int ldl = S.ldL[s];
+  const int64_t n = S.n;
+  const T* Lp = L + S.L_off[s] + w;
+  const T* xg = uvec + S.u_off[s] * nrhs;
+  constexpr int kCols = kPanel / (kThreads / 64);
+  for (int jj = 0; jj < kCols; ++jj) {
+    const int j = it.chunk * kPanel + wave * kCols + jj;
+    if (j >= w) break;
+    const T* lc = Lp + (int64_t)j * ldl;
+    T acc[kRhsBlock];
+#pragma unroll
+    for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
+    for (int i = lane; i < r; i += 64) {
+      const T l = lc[i];
+#pragma unroll
+      for (int col = 0; col < kRhsBlock; ++col)
+        if (col < nrhs) acc[col] += l * xg[i + col * r];
+    }
+#pragma unroll
+    for (int col = 0; col < kRhsBlock; ++col) {
+      if (col < nrhs) {
+        const T v = wave_sum(acc[col]);
+        if (lane == 0) y[f + j + col * n] -= v;
+      }
     }
   }
 }
@@ -834,8 +1052,12 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
 
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
-                 hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_gemm<T>, dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles);
+                 int tile, hipStream_t st) {
+  if (count <= 0) return;
+  if (tile == kGemmTileBig)
+    hipLaunchKernelGGL((k_gemm<T, kGemmTileBig>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles);
+  else
+    hipLaunchKernelGGL((k_gemm<T, kGemmTile>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles);
 }
 
 template <typename T>
@@ -863,9 +1085,27 @@ void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* uvec, const Sol
 }
 
 template <typename T>
-void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const SolveItem* items, int64_t count,
-                     int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, items, nrhs);
+void launch_fwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
+                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_fwd_tri<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, items, (int)count, counter, flags, nrhs);
+}
+
+template <typename T>
+void launch_bwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
+                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_bwd_tri<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, items, (int)count, counter, flags, nrhs);
+}
+
+template <typename T>
+void launch_bwd_gather(const DevSym& S, const T* y, T* uvec, const int32_t* list, int64_t count,
+                       int32_t nrhs, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_bwd_gather<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, y, uvec, list, nrhs);
+}
+
+template <typename T>
+void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const T* uvec, const SolveItem* items,
+                     int64_t count, int32_t nrhs, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, uvec, items, nrhs);
 }
 
 template <typename T>
@@ -898,7 +1138,7 @@ void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, doub
                                hipStream_t);                                                     \
   template void launch_panel<T>(const DevSym&, const DevNum<T>&, const PanelItem*, int64_t,       \
                                 const T*, hipStream_t);                                          \
-  template void launch_gemm<T>(const DevNum<T>&, const GemmProb*, const GemmTile*, int64_t,       \
+  template void launch_gemm<T>(const DevNum<T>&, const GemmProb*, const GemmTile*, int64_t, int,  \
                                hipStream_t);                                                     \
   template void launch_permute_in<T>(const DevSym&, const double*, int64_t, T*, int64_t,          \
                                      const double*, hipStream_t);                                \
@@ -910,8 +1150,14 @@ void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, doub
                               hipStream_t);                                                      \
   template void launch_fwd_gemv<T>(const DevSym&, const T*, const T*, T*, const SolveItem*,       \
                                    int64_t, int32_t, hipStream_t);                               \
-  template void launch_bwd_gemv<T>(const DevSym&, const T*, T*, const SolveItem*, int64_t,        \
-                                   int32_t, hipStream_t);
+  template void launch_bwd_gemv<T>(const DevSym&, const T*, T*, const T*, const SolveItem*,       \
+                                   int64_t, int32_t, hipStream_t);                               \
+  template void launch_bwd_gather<T>(const DevSym&, const T*, T*, const int32_t*, int64_t,        \
+                                     int32_t, hipStream_t);                                      \
+  template void launch_fwd_tri<T>(const DevSym&, const T*, const T*, T*, const TriItem*, int64_t, \
+                                  int32_t*, int32_t*, int32_t, hipStream_t);                     \
+  template void launch_bwd_tri<T>(const DevSym&, const T*, const T*, T*, const TriItem*, int64_t, \
+                                  int32_t*, int32_t*, int32_t, hipStream_t);
 
 TACHO_INSTANTIATE(double)
 TACHO_INSTANTIATE(float)

@@ -147,30 +147,51 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
   P.asm_items.clear();
   P.diag_items.clear();
   P.panel_items.clear();
-  P.max_wslots = 0;
+  // diagonal-block inverse storage of every large front
+  P.wbase.assign(ns, -1);
+  P.woff.clear();
+  P.W_elems = 0;
+  for (int32_t s = 0; s < ns; ++s) {
+    if (S.front_m[s] <= kSmallMax) continue;
+    const int32_t w = S.sptr[s + 1] - S.sptr[s];
+    P.wbase[s] = (int32_t)P.woff.size();
+    for (int32_t k = 0; k < w; k += kPanel) {
+      const int64_t kb = std::min(kPanel, w - k);
+      P.woff.push_back(P.W_elems);
+      P.W_elems += kb * kb;
+    }
+  }
   P.probs.clear();
   P.tiles.clear();
+  // Problems of one update launch group; tiles are emitted per tile size so
+  // that every launch uses a single tile shape.
+  std::vector<int32_t> group;
   auto add_gemm = [&](const GemmProb& g) {
-    int32_t pid = (int32_t)P.probs.size();
+    group.push_back((int32_t)P.probs.size());
     P.probs.push_back(g);
-    const int T = kGemmTile;
-    int32_t nti = (g.M + T - 1) / T, ntj = (g.N + T - 1) / T;
-    for (int32_t tj = 0; tj < ntj; ++tj)
-      for (int32_t ti = 0; ti < nti; ++ti)
-        if ((int64_t)ti * T + T - 1 >= (int64_t)tj * T) P.tiles.push_back({pid, ti, tj, 0});
   };
-  // one update launch over the tiles [t0, end) of problems added since t0
-  auto add_gemm_step = [&](int32_t h, int64_t t0, int32_t p0) {
-    if ((int64_t)P.tiles.size() <= t0) return;
-    Step st{kStepGemm, h, t0, (int64_t)P.tiles.size()};
-    for (int32_t pid = p0; pid < (int32_t)P.probs.size(); ++pid) {
-      const GemmProb& g = P.probs[pid];
-      const double N = g.N, M = g.M, K = g.K;
-      const double lower = N * (N + 1) / 2 + (M - N) * N;  // outputs with row >= col
-      st.flops += 2.0 * K * lower;
-      st.elems += M * K + 2.0 * lower;
+  auto add_gemm_step = [&](int32_t h) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const int T = pass == 0 ? kGemmTileBig : kGemmTile;
+      Step st{kStepGemm, h, (int64_t)P.tiles.size(), 0};
+      st.tile = T;
+      for (int32_t pid : group) {
+        const GemmProb& g = P.probs[pid];
+        const bool big = (int64_t)g.M * g.N >= kGemmBigMin;
+        if (big != (pass == 0)) continue;
+        const int32_t nti = (g.M + T - 1) / T, ntj = (g.N + T - 1) / T;
+        for (int32_t tj = 0; tj < ntj; ++tj)
+          for (int32_t ti = 0; ti < nti; ++ti)
+            if ((int64_t)ti * T + T - 1 >= (int64_t)tj * T) P.tiles.push_back({pid, ti, tj, T});
+        const double Nn = g.N, Mm = g.M, Kk = g.K;
+        const double lower = Nn * (Nn + 1) / 2 + (Mm - Nn) * Nn;  // outputs with row >= col
+        st.flops += 2.0 * Kk * lower;
+        st.elems += Mm * Kk + 2.0 * lower;
+      }
+      st.end = (int64_t)P.tiles.size();
+      if (st.end > st.begin) P.steps.push_back(st);
     }
-    P.steps.push_back(st);
+    group.clear();
   };
   std::vector<int32_t> big;
   for (int32_t h = 0; h < S.nlevels; ++h) {
@@ -207,29 +228,21 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
     }
     for (int32_t k = 0; k < wmax; k += kPanel) {
       int64_t d0 = (int64_t)P.diag_items.size();
-      std::vector<int32_t> slot_of;  // per big front: its slot in this step
-      slot_of.assign(big.size(), -1);
-      for (size_t bi = 0; bi < big.size(); ++bi) {
-        const int32_t s = big[bi];
+      for (int32_t s : big) {
         const int32_t w = S.sptr[s + 1] - S.sptr[s];
         if (w <= k) continue;
-        const int32_t slot = (int32_t)(P.diag_items.size() - d0);
-        slot_of[bi] = slot;
-        P.diag_items.push_back({s, k, std::min(kPanel, w - k), 0, slot, 0});
+        P.diag_items.push_back({s, k, std::min(kPanel, w - k), 0, P.wbase[s] + k / kPanel, 0});
       }
-      P.max_wslots = std::max<int64_t>(P.max_wslots, (int64_t)P.diag_items.size() - d0);
       {
         Step st{kStepDiag, h, d0, (int64_t)P.diag_items.size()};
         for (int64_t q = d0; q < st.end; ++q) {
           const double kb = P.diag_items[q].kb;
           st.flops += kb * (kb + 1) * (2 * kb + 1) / 6.0;
-          st.elems += kb * (kb + 1) + (double)kPanel * kPanel;
+          st.elems += kb * (kb + 1) + kb * kb;
         }
         P.steps.push_back(st);
       }
       int64_t p0 = (int64_t)P.panel_items.size();
-      int64_t t0 = (int64_t)P.tiles.size();
-      const int32_t g0 = (int32_t)P.probs.size();
       for (size_t bi = 0; bi < big.size(); ++bi) {
         const int32_t s = big[bi];
         const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
@@ -237,7 +250,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
         const int32_t kb = std::min(kPanel, w - k);
         const int32_t below = m - k - kb;
         const int32_t chunks = (below + kPanelRows - 1) / kPanelRows;
-        for (int32_t c = 0; c < chunks; ++c) P.panel_items.push_back({s, k, kb, c, slot_of[bi], 0});
+        for (int32_t c = 0; c < chunks; ++c)
+          P.panel_items.push_back({s, k, kb, c, P.wbase[s] + k / kPanel, 0});
       }
       if ((int64_t)P.panel_items.size() > p0) {
         Step st{kStepPanel, h, p0, (int64_t)P.panel_items.size()};
@@ -246,7 +260,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
           if (w <= k) continue;
           const double kb = std::min(kPanel, w - k), rows = m - k - kb;
           st.flops += rows * kb * kb;
-          st.elems += 2 * rows * kb + (double)kPanel * kPanel;
+          st.elems += 2 * rows * kb + kb * kb;
         }
         P.steps.push_back(st);
       }
@@ -264,10 +278,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
         g.c_in_u = 0;
         add_gemm(g);
       }
-      add_gemm_step(h, t0, g0);
+      add_gemm_step(h);
     }
-    int64_t t0 = (int64_t)P.tiles.size();
-    const int32_t g0 = (int32_t)P.probs.size();
     for (int32_t s : big) {
       const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], r = m - w;
       if (r <= 0) continue;
@@ -281,22 +293,36 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
       g.c_in_u = 1;
       add_gemm(g);
     }
-    add_gemm_step(h, t0, g0);
+    add_gemm_step(h);
   }
   P.fwd_items.clear();
   P.bwd_items.clear();
+  P.gather_list.clear();
+  P.gather_ptr.assign(S.nlevels + 1, 0);
+  P.tri_fwd.clear();
+  P.tri_bwd.clear();
   P.fwd_ptr.assign(S.nlevels + 1, 0);
   P.bwd_ptr.assign(S.nlevels + 1, 0);
+  P.tri_ptr.assign(S.nlevels + 1, 0);
+  P.tri_flags = 0;
   for (int32_t h = 0; h < S.nlevels; ++h) {
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       const int32_t s = S.level_list[q];
       const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
-      if ((int64_t)r * w < kSolveSplit) continue;
+      if (!solve_split_front(w, r)) continue;
       for (int32_t c = 0; c * kPanel < r; ++c) P.fwd_items.push_back({s, c});
+      if (r > 0) P.gather_list.push_back(s);
       for (int32_t c = 0; c * kPanel < w; ++c) P.bwd_items.push_back({s, c});
+      const int32_t nb = (w + kPanel - 1) / kPanel;
+      const int32_t base = (int32_t)P.tri_flags;
+      for (int32_t b = 0; b < nb; ++b) P.tri_fwd.push_back({s, b, base + b, 0});
+      for (int32_t b = nb - 1; b >= 0; --b) P.tri_bwd.push_back({s, b, base + b, 0});
+      P.tri_flags += nb;
     }
     P.fwd_ptr[h + 1] = (int64_t)P.fwd_items.size();
     P.bwd_ptr[h + 1] = (int64_t)P.bwd_items.size();
+    P.tri_ptr[h + 1] = (int64_t)P.tri_fwd.size();
+    P.gather_ptr[h + 1] = (int64_t)P.gather_list.size();
   }
   P.level_lentries.assign(S.nlevels, 0.0);
   P.level_rows.assign(S.nlevels, 0.0);

@@ -16,10 +16,10 @@ struct AsmItem {
 
 // Work item of the panel kernels: diagonal block [k, k+kb) of front s (one
 // item per front for the diagonal Cholesky), rows below it handled in chunks
-// of kPanelRows (one item per chunk for the triangular solve).  `wslot` is
-// the scratch slot holding the inverse of the diagonal block in that step.
+// of kPanelRows (one item per chunk for the triangular solve).  `wblk` is the
+// global index of the diagonal block, whose inverse is kept for the solves.
 struct PanelItem {
-  int32_t s, k, kb, chunk, wslot, pad;
+  int32_t s, k, kb, chunk, wblk, pad;
 };
 
 // Update C[M x N] -= A[M x K] * A[0:N, :]^T, lower part (row >= col) only.
@@ -36,8 +36,25 @@ struct SolveItem {
   int32_t s, chunk;
 };
 
+// Block b (kPanel rows / columns) of the L11 solve of a split front; `flag`
+// is the index of the block's ready flag.
+struct TriItem {
+  int32_t s, b, flag, pad;
+};
+
+// Fronts whose solves are split into a pipelined multi-workgroup L11 part
+// and multi-workgroup L21 products.
+#if defined(__HIP__)
+#define TACHO_HOST_DEVICE __host__ __device__
+#else
+#define TACHO_HOST_DEVICE
+#endif
+TACHO_HOST_DEVICE inline bool solve_split_front(int64_t w, int64_t r) {
+  return w >= 192 || r * w >= 16384;
+}
+
 struct GemmTile {
-  int32_t prob, ti, tj, pad;
+  int32_t prob, ti, tj, size;  // size: kGemmTile or kGemmTileBig
 };
 
 enum StepKind : int32_t {
@@ -49,13 +66,15 @@ enum StepKind : int32_t {
 };
 
 // One kernel launch: [begin, end) into the matching item array; for
-// kStepGemm, [begin, end) indexes tiles and the problems are those tiles' own.
+// kStepGemm, [begin, end) indexes tiles (all of size `tile`) and the problems
+// are those tiles' own.
 struct Step {
   int32_t kind;
   int32_t level;
   int64_t begin, end;
   double flops = 0;  // algorithmic flops of the launch
   double elems = 0;  // algorithmic element traffic (reads + writes) of the launch
+  int32_t tile = 0;  // update steps: tile size
 };
 
 constexpr int kSmallMax = 64;     // fronts with m <= kSmallMax go to the LDS kernel
@@ -63,8 +82,9 @@ constexpr int kPanel = 64;        // panel width of the blocked large-front path
 constexpr int kPanelRows = 64;    // rows per triangular-solve workgroup
 constexpr int kAsmCols = 8;       // front columns per assembly workgroup
 constexpr int kGemmTile = 64;     // output tile of the update kernel
+constexpr int kGemmTileBig = 128; // output tile for large updates
+constexpr int64_t kGemmBigMin = 256 * 256;  // M*N from which the large tile is used
 constexpr int kLdAlign = 4;       // leading dimensions rounded to this many elements
-constexpr int64_t kSolveSplit = 16384;  // r*w at which the solves split off the L21 part
 constexpr int kSolveChunk = 256;  // vector entries staged per LDS round in the split solves
 
 struct Plan {
@@ -72,7 +92,12 @@ struct Plan {
   std::vector<int64_t> L_off, U_off, u_off;
   std::vector<int32_t> ldL, ldU;
   int64_t L_elems = 0, U_elems = 0, u_elems = 0;  // u_elems per right-hand side
-  int64_t max_wslots = 0;  // diagonal-block inverses live at once (one panel step)
+  // inverses of the kPanel diagonal blocks of large fronts (kb x kb each,
+  // column-major): per supernode its first block (-1: none), per block the
+  // element offset
+  std::vector<int32_t> wbase;
+  std::vector<int64_t> woff;
+  int64_t W_elems = 0;
   std::vector<int32_t> a_pos;   // per A entry: row + col*ldL inside the front panel
   std::vector<int32_t> diag_q;  // per permuted column: A entry of the diagonal (-1: absent)
 
@@ -91,6 +116,11 @@ struct Plan {
   // split solves: per level [ptr[h], ptr[h+1]) into the item arrays
   std::vector<SolveItem> fwd_items, bwd_items;
   std::vector<int64_t> fwd_ptr, bwd_ptr;
+  std::vector<TriItem> tri_fwd, tri_bwd;  // per level, blocks in ticket order
+  std::vector<int32_t> gather_list;       // split fronts with r > 0, per level
+  std::vector<int64_t> gather_ptr;
+  std::vector<int64_t> tri_ptr;
+  int64_t tri_flags = 0;                  // ready flags (one per block)
 };
 
 int build_plan(const Symbolic& S, Plan& P, std::string& err);

@@ -223,3 +223,25 @@ def test_full_size_3d_64():
         worst = max(worst, abs(v - C.data[k]) / np.sqrt(diag[i] * diag[j]))
     print(f"64^3 sampled |(LL^T)_ij - C_ij|/sqrt(C_ii C_jj) max {worst:.2e}")
     assert worst <= 1e-12
+
+
+def test_graph_replays_match_eager():
+    """The captured factorization graph, replayed several times with other
+    values and eager work in between, gives the eager result bitwise."""
+    A = gen.fv3d(13, 12, 11, seed=21)
+    B = gen.fv3d(13, 12, 11, seed=22)
+    s_e = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(graphs=0))
+    s_g = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(graphs=1))
+    want = {}
+    for name, M in (("A", A), ("B", B)):
+        ne = T.tacho_factorize(s_e, M.values, T.TACHO_FP64)
+        want[name] = T.tacho_get_factor(ne)[2]
+    ng = T.tacho_factorize(s_g, A.values, T.TACHO_FP64)
+    b = gen.rhs(A.n, 2, seed=3)
+    for name in ("A", "B", "A", "B"):
+        M = A if name == "A" else B
+        T.tacho_refactorize(ng, M.values)
+        x = T.tacho_solve(ng, b)  # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(T.tacho_get_factor(ng)[2], want[name]), name
+        assert oracle.rel_residual(M, x, b).max() <= FP64_RESID_TOL
