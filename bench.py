@@ -23,7 +23,10 @@ a CPU baseline (the oracle on a bounded sample).
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
+import re
 import os
 import platform
 import sys
@@ -38,6 +41,16 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+
+# Measured HBM traffic per launch of the factorization kernels (rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs, calibrated on a copy kernel of known size),
+# written by --traffic-summary and read back by the roofline.  The file records
+# a hash of the kernel and launch-plan sources; when they change the recorded
+# figures no longer describe the kernel and the roofline reports traffic null.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "factor_kernels_fv3d64_hbm_traffic.md")
+TRAFFIC_SOURCES = ("paper_2506_05793_amd/csrc/kernels.hip", "paper_2506_05793_amd/csrc/plan.cpp",
+                   "paper_2506_05793_amd/csrc/plan.hpp")
+COPY_PROBE_ELEMS = 1 << 27  # FP64 elements: 1 GiB read + 1 GiB written
 
 
 def log(*a):
@@ -194,13 +207,124 @@ def roofline(prof):
     else:
         achieved = p["bytes"] / (p["ms"] * 1e-3) / 1e9
         out = {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    traffic = recorded_traffic().get(name)
     out.update({"kernel": name, "achieved": achieved, "frac": achieved / out["peak"],
-                "traffic": None, "launches": p["launches"], "avg_launch_ms": avg_ms,
+                "traffic": traffic, "algorithmic_bytes_per_launch": p["bytes"] / p["launches"],
+                "launches": p["launches"], "avg_launch_ms": avg_ms,
                 "share_of_factor_time": p["ms"] / sum(v["ms"] for v in factor.values())})
     return out
 
 
-def cpu_baseline(side=40):
+def sources_hash():
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """{kernel: HBM bytes per launch} from the traffic summary, if it matches the sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return {}
+    m = re.search(r"sources hash: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != sources_hash():
+        return {}
+    out = {}
+    for row in re.finditer(r"^\| (k_\w+) \| (\d+) \| [^|]+\| [^|]+\| ([0-9.e+]+) \|", text, re.M):
+        out[row.group(1)] = float(row.group(3))
+    return out
+
+
+def short_kernel(name):
+    m = re.search(r"::(k_[a-z0-9_]+)", name)
+    return m.group(1) if m else None
+
+
+def read_counters(path, counter):
+    """{dispatch id: (kernel name, value)} from a rocprofv3 counter_collection csv."""
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            name, v = out.get(d, (r["Kernel_Name"], 0.0))
+            out[d] = (name, v + float(r["Counter_Value"]))
+    return out
+
+
+def traffic_summary(fetch_csv, write_csv, command):
+    """Write the per-kernel HBM traffic summary from the two counter runs."""
+    fetch = read_counters(fetch_csv, "FETCH_SIZE")
+    write = read_counters(write_csv, "WRITE_SIZE")
+    probe_kib = COPY_PROBE_ELEMS * 8 / 1024
+
+    def per_kernel(counts):
+        agg, probe = {}, []
+        for name, v in counts.values():
+            if "neg_kernel" in name:
+                probe.append(v)
+                continue
+            k = short_kernel(name)
+            if k:
+                agg.setdefault(k, []).append(v)
+        return agg, max(probe)
+
+    fa, fprobe = per_kernel(fetch)
+    wa, wprobe = per_kernel(write)
+    ff, fw = probe_kib / fprobe, probe_kib / wprobe
+    lines = [
+        "# HBM traffic per launch, factorization kernels, 3D 7-point lognormal 64^3, FP64",
+        "",
+        "Two `rocprofv3 --pmc` runs of the same command (one counter each), eager launches.",
+        f"Calibration: a plain FP64 negation kernel over {COPY_PROBE_ELEMS} elements "
+        f"({probe_kib:.0f} KiB read, {probe_kib:.0f} KiB written) read FETCH_SIZE {fprobe:.0f} KiB "
+        f"and WRITE_SIZE {wprobe:.0f} KiB; factors {ff:.4f} (fetch) and {fw:.4f} (write) are "
+        "applied below.",
+        "",
+        f"sources hash: `{sources_hash()}`",
+        "",
+        "Commands:",
+        "",
+        "```",
+        command,
+        "```",
+        "",
+        "| kernel | dispatches | fetch KiB/launch | write KiB/launch | HBM bytes/launch (scaled) |",
+        "|---|---|---|---|---|",
+    ]
+    for k in sorted(fa, key=lambda k: -sum(fa[k])):
+        f = sum(fa[k]) / len(fa[k])
+        w = sum(wa.get(k, [0.0])) / max(1, len(wa.get(k, [])))
+        lines.append(f"| {k} | {len(fa[k])} | {f:.1f} | {w:.1f} | {(f * ff + w * fw) * 1024:.4e} |")
+    text = "\n".join(lines) + "\n"
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write(text)
+    print(text)
+
+
+def kernel_stats_summary(stats_csv, out_md, title, command, top=16):
+    """Short markdown table from a rocprofv3 --stats kernel_stats.csv."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# {title}", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        name = short_kernel(r["Name"]) or r["Name"][:60]
+        m = re.search(r"<([^<>]*)>\(", r["Name"])
+        if m and short_kernel(r["Name"]):
+            name += f"<{m.group(1)}>"
+        lines.append(f"| {name} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def cpu_baseline(side=46):
     """The oracle (plain left-looking FP64 Cholesky, 1 thread) on a bounded sample."""
     import gen
     import oracle
@@ -228,10 +352,30 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--side", type=int, default=64, help="grid side of the 3D workload")
+    ap.add_argument("--workload", default="3d", choices=["3d", "2d", "landice", "batch", "serve"],
+                    help="3d: 64^3 lognormal (default, the metric's workload); 2d: 32x32 "
+                         "Laplacian; landice: extruded 2-DOF mesh (--li-side); batch: 256 "
+                         "subdomain systems; serve: request stream")
+    ap.add_argument("--li-side", type=int, default=200, help="land-ice base grid side")
+    ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the factorization kernels one by one instead of a graph")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB FP64 negation kernel first (counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="write the HBM traffic summary from two counter runs and exit")
+    ap.add_argument("--kernel-summary", nargs=4, metavar=("STATS_CSV", "OUT_MD", "TITLE", "COMMAND"),
+                    help="write a markdown kernel summary from rocprofv3 stats and exit")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary)
+        return
+    if args.kernel_summary:
+        kernel_stats_summary(*args.kernel_summary)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the single-system workload is measured on one "
               "MI355X (multi-GPU sharding is a design note only).", file=sys.stderr)
@@ -247,13 +391,23 @@ def main():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        x = torch.ones(COPY_PROBE_ELEMS, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
+    if args.workload != "3d":
+        other_workload(args, T, torch)
+        return
     side = args.side
     log(f"[bench] building 3D lognormal {side}^3 workload")
     A = gen.fv3d(side, seed=1)
     b1 = gen.rhs(A.n, 1, seed=2)
     b16 = gen.rhs(A.n, 16, seed=2)
     t0 = time.perf_counter()
-    sym = T.tacho_analyze(A.n, A.rowptr, A.colind)
+    sym = T.tacho_analyze(A.n, A.rowptr, A.colind,
+                          T.tacho_default_options(graphs=0) if args.eager else None)
     analyze_s = time.perf_counter() - t0
     q = T.tacho_query_symbolic(sym)
     log(f"[bench] analyze {analyze_s:.2f}s nnz(L)={q['nnz_l']:.3e} flops={q['flops']:.3e} "
@@ -317,6 +471,140 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def line_for(args, metric_value, unit, dtype, config, extra):
+    out = {"metric": METRIC, "value": metric_value, "unit": unit, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def other_workload(args, T, torch):
+    """C1 (2d), C3 (landice), C4 (batch) and C5 (serve) measurements."""
+    import numpy as np
+
+    import gen
+    if args.workload == "serve":
+        from paper_2506_05793_amd.serve import Request, Server, summarize
+        specs = gen.serving_requests(args.requests, seed=5, rate=200.0, n2d=(1000, 250000),
+                                     n3d=(4000, 300000))
+        reqs, mats = [], {}
+        log(f"[bench] building {len(specs)} requests")
+        for i, sp in enumerate(specs):
+            if sp["kind"] == "factor":
+                A = gen.fv2d(*sp["side"], seed=sp["seed"]) if sp["dim"] == 2 else \
+                    gen.fv3d(*sp["side"], seed=sp["seed"])
+                mats[i] = A
+                reqs.append(Request(i, sp["t"], "factor", gen.rhs(A.n, sp["nrhs"], seed=sp["seed"] + 1),
+                                    matrix=A))
+            else:
+                A = mats[sp["target"]]
+                reqs.append(Request(i, sp["t"], "repeat", gen.rhs(A.n, sp["nrhs"], seed=sp["seed"]),
+                                    target=sp["target"]))
+        free, _ = torch.cuda.mem_get_info()
+        srv = Server(int(0.8 * free), slots=4, analysis_workers=8)
+        t0 = time.perf_counter()
+        res = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        srv.close()
+        summ = summarize(res, wall)
+        worst = 0.0
+        for out in res[:: max(1, len(res) // 20)]:
+            r = reqs[out.rid]
+            A = r.matrix if r.kind == "factor" else mats[r.target]
+            worst = max(worst, float(residual(A, out.x, r.rhs).max()))
+        summ.update({"admitted_while_busy": srv.admitted_while_busy, "peak_bytes": srv.peak_used,
+                     "sampled_max_rel_residual": worst})
+        log(f"[bench] serve {summ}")
+        line_for(args, summ["rhs_solves_per_s"], "RHS solves/s", "f64",
+                 {"workload": f"Poisson request stream, {len(reqs)} requests, 2D n 1k-250k and "
+                              f"3D n 4k-300k lognormal, 1-16 RHS, 30% repeat"}, {"serve": summ})
+        return
+    if args.workload == "batch":
+        mats = gen.batch_fv3d(256, seed=4)
+        log(f"[bench] batch of {len(mats)} systems, n total {sum(m.n for m in mats)}")
+        t0 = time.perf_counter()
+        sym = T.tacho_analyze_batch([(m.n, m.rowptr, m.colind) for m in mats])
+        analyze_s = time.perf_counter() - t0
+        vals_np = np.concatenate([m.values for m in mats])
+        n = sum(m.n for m in mats)
+        b = np.asfortranarray(np.concatenate([gen.rhs(m.n, 1, seed=10 + k)
+                                              for k, m in enumerate(mats)], axis=0))
+        A = gen.csr_block_diag(mats)
+        precisions = [("mixed", T.TACHO_FP32, 1e-10), ("fp64", T.TACHO_FP64, 1e-12)]
+    elif args.workload == "2d":
+        A = gen.laplace2d(32)
+        t0 = time.perf_counter()
+        sym = T.tacho_analyze(A.n, A.rowptr, A.colind)
+        analyze_s = time.perf_counter() - t0
+        vals_np = A.values
+        n = A.n
+        b = gen.rhs(n, 1, seed=0)
+        precisions = [("fp64", T.TACHO_FP64, 1e-12), ("mixed", T.TACHO_FP32, 1e-10)]
+    else:
+        s = args.li_side
+        log(f"[bench] building land-ice {s}x{s}x11x2")
+        A = gen.landice(s, s, 11, seed=3)
+        t0 = time.perf_counter()
+        sym = T.tacho_analyze(A.n, A.rowptr, A.colind)
+        analyze_s = time.perf_counter() - t0
+        vals_np = A.values
+        n = A.n
+        b = gen.rhs(n, 1, seed=2)
+        precisions = [("mixed", T.TACHO_FP32, 1e-10), ("fp64", T.TACHO_FP64, 1e-12)]
+    q = T.tacho_query_symbolic(sym)
+    log(f"[bench] analyze {analyze_s:.2f}s n={n} nnz(L)={q['nnz_l']:.3e} flops={q['flops']:.3e} "
+        f"levels={q['nlevels']}")
+    vals = torch.from_numpy(vals_np).cuda()
+    B = dev_colmajor(torch, np.asarray(b).reshape(n, -1))
+    X = torch.empty_like(B)
+    results = {}
+    for name, prec, tol in precisions:
+        num = T.tacho_factorize(sym, vals, prec)
+        fms, sms, rows = [], [], []
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            T.tacho_refactorize(num, vals, sync=False)
+            e1.record()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, info = T.tacho_solve(num, B, X, with_info=True)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if it >= args.warmup:
+                fms.append(e0.elapsed_time(e1))
+                sms.append((t2 - t1) * 1e3)
+                rows.append(info)
+        rho = float(residual(A, X.cpu().numpy(), np.asarray(b).reshape(n, -1)).max())
+        f50 = float(np.median(fms))
+        s50 = float(np.median(sms))
+        results[name] = {
+            "factor_ms_p50": f50, "factor_ms_p99": pct(fms, 99),
+            "factor_tflops": q["flops"] / (f50 * 1e-3) / 1e12,
+            "solve_ms_p50": s50, "solve_ms_p99": pct(sms, 99),
+            "request_factor_solve_ms_p50": pct([a + c for a, c in zip(fms, sms)], 50),
+            "request_factor_solve_ms_p99": pct([a + c for a, c in zip(fms, sms)], 99),
+            "rel_residual": rho, "residual_tol": tol, "meets_tol": rho <= tol,
+            "refine_iters": max(r["iters"] for r in rows), "fell_back": max(r["fell_back"] for r in rows),
+        }
+        if args.workload == "batch":
+            results[name]["systems_per_s"] = 256 / ((f50 + s50) * 1e-3)
+        log(f"[bench] {name}: {results[name]}")
+        del num
+    main_name = precisions[0][0]
+    line_for(args, results[main_name]["factor_tflops"], "TFLOP/s",
+             "f32+f64-refine" if main_name == "mixed" else "f64",
+             {"workload": {"2d": "2D 5-point Laplacian 32x32",
+                           "landice": f"land-ice {args.li_side}x{args.li_side}x11 nodes x 2 DOF",
+                           "batch": "256 3D lognormal subdomain systems, sides in [8,32]"}[args.workload],
+              "n": n, "nnz_l": q["nnz_l"], "flops": q["flops"], "levels": q["nlevels"],
+              "analyze_s_host": analyze_s}, results)
 
 
 if __name__ == "__main__":

@@ -96,6 +96,9 @@ typedef struct {
   int64_t nnz_factor;       /* stored factor entries: nnz_l plus the explicit zeros of
                                relaxed supernodes */
   int64_t ordering;         /* ordering used: 1 multilevel, 2 level-structure */
+  int64_t t_order_us;       /* host microseconds of the analysis: fill-reducing ordering */
+  int64_t t_structure_us;   /* etree, counts, supernodes, row structures, maps, levels */
+  int64_t t_plan_us;        /* launch plan, memory plan and refinement maps */
 } tacho_sym_info;
 
 typedef struct {

@@ -54,7 +54,7 @@ class tacho_sym_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "nnz_a", "nnz_l", "flops", "nsuper", "nlevels", "max_front", "max_width",
         "factor_bytes_fp64", "work_bytes_fp64", "device_bytes_fp64", "nsystems", "nnz_factor",
-        "ordering")]
+        "ordering", "t_order_us", "t_structure_us", "t_plan_us")]
 
 
 class tacho_solve_info(ctypes.Structure):

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -93,7 +94,7 @@ struct tacho_sym {
       d_wbase, d_woff, d_gather;
   DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_levels, d_fwd_items, d_bwd_items,
       d_tri_fwd, d_tri_bwd;
-  DBuf d_rowptr, d_colind, d_mirror;
+  DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
   DevSym view{};
   std::mutex mu;
 };
@@ -208,6 +209,7 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   so.ordering = h->opt.ordering;
   int rc = analyze_pattern(h->S, so, err);
   if (rc != kOk) return fail(rc, err);
+  const auto t_plan = std::chrono::steady_clock::now();
   rc = build_plan(h->S, h->P, err);
   if (rc != kOk) return fail(rc, err);
   const Symbolic& S = h->S;
@@ -234,6 +236,8 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
         h->a_prc[2 * q] = S.rows[S.rows_ptr[s] + S.a_row[q]];
         h->a_prc[2 * q + 1] = j;
       }
+  h->S.t_plan_us = std::chrono::duration_cast<std::chrono::microseconds>(
+                       std::chrono::steady_clock::now() - t_plan).count();
   return TACHO_OK;
 }
 
@@ -282,6 +286,7 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_rowptr, S.A.rowptr));
   HIP_TRY(upload(h->d_colind, S.A.colind));
   HIP_TRY(upload(h->d_mirror, h->mirror));
+  HIP_TRY(upload(h->d_sys_ptr, S.sys_ptr));
   DevSym& v = h->view;
   v.n = S.n;
   v.sptr = h->d_sptr.as<int32_t>();
@@ -323,7 +328,7 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += (int64_t)es * (S.n + P.u_elems) * kRhs;
   b += (int64_t)es * P.W_elems;
   b += 4 * (2 * S.nlevels + P.tri_flags + 1);
-  if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;
+  if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;  // values, scaling
   return b;
 }
 
@@ -562,19 +567,27 @@ void solve_all(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t ld
 }
 
 // FP32 factor + FP64 refinement on device buffers b (ld n) -> x (ld n).
+// Convergence is tracked per independent system and right-hand side (one
+// unit each): a converged unit gets a zero correction from then on, so a
+// system's result does not depend on the other systems of a batch.
 int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStream_t st,
                  tacho_solve_info* info) {
   tacho_sym* h = f->sym;
   const Symbolic& S = h->S;
   const int64_t n = S.n;
+  const int64_t nsys = S.nsys;
+  const int64_t units = nsys * nrhs;
   if (!f->r.p || f->r.bytes < sizeof(double) * n * nrhs) HIP_TRY(f->r.alloc(sizeof(double) * n * nrhs));
-  if (!f->norms.p || f->norms.bytes < sizeof(double) * 2 * nrhs)
-    HIP_TRY(f->norms.alloc(sizeof(double) * 2 * nrhs));
+  if (!f->norms.p || f->norms.bytes < sizeof(double) * 2 * units + units)
+    HIP_TRY(f->norms.alloc(sizeof(double) * 2 * units + units));
   double* r = f->r.as<double>();
   double* nrm = f->norms.as<double>();
-  std::vector<double> hn(2 * nrhs), rho(nrhs), prev(nrhs, INFINITY);
-  std::vector<int> stalls(nrhs, 0), done(nrhs, 0);
-  launch_colnorms(n, b, n, nrhs, nrm + nrhs, st);
+  uint8_t* mask = reinterpret_cast<uint8_t*>(nrm + 2 * units);
+  const int64_t* sysp = h->d_sys_ptr.as<int64_t>();
+  std::vector<double> hn(2 * units), rho(units), prev(units, INFINITY);
+  std::vector<int> stalls(units, 0);
+  std::vector<uint8_t> done(units, 0);
+  launch_segnorms(nsys, sysp, b, n, nrhs, nrm + units, st);
   solve_all<float>(f, b, n, x, n, nrhs, 0, st);
   const double tol = h->opt.refine_tol > 0 ? h->opt.refine_tol : 1e-10;
   const int maxit = h->opt.refine_max > 0 ? h->opt.refine_max : 10;
@@ -582,41 +595,48 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
   int iters = 0;
   bool stalled = false;
   const double nnz = (double)S.A.colind.size();
-  for (;;) {
+  auto residual_norms = [&]() -> int {
     const int pe = f->prof.begin(st);
     launch_residual(n, h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(),
                     f->fullvals.as<double>(), b, n, x, n, r, nrhs, st);
-    launch_colnorms(n, r, n, nrhs, nrm, st);
+    launch_segnorms(nsys, sysp, r, n, nrhs, nrm, st);
     f->prof.end(pe, st, TACHO_K_REFINE, (2.0 * nnz + 2.0 * n) * nrhs,
                 nnz * 12.0 + 8.0 * n + 8.0 * 3.0 * n * nrhs);
-    HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * units, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    for (int64_t u = 0; u < units; ++u) {
+      const double bn = hn[units + u];
+      rho[u] = bn > 0 ? hn[u] / bn : hn[u];
+      if (!(rho[u] == rho[u])) rho[u] = INFINITY;
+    }
+    return TACHO_OK;
+  };
+  for (;;) {
+    int rc = residual_norms();
+    if (rc != TACHO_OK) return rc;
     bool all = true;
-    for (int64_t c = 0; c < nrhs; ++c) {
-      const double bn = hn[nrhs + c];
-      rho[c] = bn > 0 ? hn[c] / bn : hn[c];
-      if (!(rho[c] == rho[c])) rho[c] = INFINITY;
-      if (done[c]) continue;
-      if (rho[c] <= tol) {
-        done[c] = 1;
+    for (int64_t u = 0; u < units; ++u) {
+      if (done[u]) continue;
+      if (rho[u] <= tol) {
+        done[u] = 1;
         continue;
       }
       all = false;
-      if (rho[c] > ratio * prev[c]) {
-        if (++stalls[c] >= 2) stalled = true;
+      if (rho[u] > ratio * prev[u]) {
+        if (++stalls[u] >= 2) stalled = true;
       } else {
-        stalls[c] = 0;
+        stalls[u] = 0;
       }
-      prev[c] = rho[c];
+      prev[u] = rho[u];
     }
     if (all) break;
     if (stalled || iters >= maxit) {
       stalled = true;
       break;
     }
-    // converged columns get a zero correction: clear their residual
-    for (int64_t c = 0; c < nrhs; ++c)
-      if (done[c]) HIP_TRY(hipMemsetAsync(r + c * n, 0, sizeof(double) * n, st));
+    // converged units get a zero correction: clear their residual
+    HIP_TRY(hipMemcpyAsync(mask, done.data(), units, hipMemcpyHostToDevice, st));
+    launch_zero_units(nsys, sysp, r, n, nrhs, mask, st);
     solve_all<float>(f, r, n, x, n, nrhs, 1, st);
     ++iters;
   }
@@ -632,23 +652,18 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
     int rc = refactor(f->fallback, f->vals.as<double>(), 1, st, 1, &fi);
     if (rc != TACHO_OK) return rc;
     solve_all<double>(f->fallback, b, n, x, n, nrhs, 0, st);
-    launch_residual(n, h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(),
-                    f->fullvals.as<double>(), b, n, x, n, r, nrhs, st);
-    launch_colnorms(n, r, n, nrhs, nrm, st);
-    HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    for (int64_t c = 0; c < nrhs; ++c) {
-      const double bn = hn[nrhs + c];
-      rho[c] = bn > 0 ? hn[c] / bn : hn[c];
-    }
+    rc = residual_norms();
+    if (rc != TACHO_OK) return rc;
   }
   if (info) {
     info->iters = iters;
     info->fell_back = stalled ? 1 : 0;
     double mx = 0;
     for (int64_t c = 0; c < nrhs; ++c) {
-      mx = std::max(mx, rho[c]);
-      if (info->relres) info->relres[c] = rho[c];
+      double col = 0;
+      for (int64_t k = 0; k < nsys; ++k) col = std::max(col, rho[k + c * nsys]);
+      mx = std::max(mx, col);
+      if (info->relres) info->relres[c] = col;
     }
     info->relres_max = mx;
   }
@@ -757,6 +772,9 @@ int tacho_query_symbolic(tacho_sym_t h, tacho_sym_info* info) {
   info->nsystems = S.nsys;
   info->nnz_factor = S.nnz_front;
   info->ordering = S.ordering_used;
+  info->t_order_us = S.t_order_us;
+  info->t_structure_us = S.t_structure_us;
+  info->t_plan_us = S.t_plan_us;
   return TACHO_OK;
 }
 

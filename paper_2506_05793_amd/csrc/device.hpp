@@ -104,5 +104,11 @@ void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, co
                      int64_t nrhs, hipStream_t st);
 void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, double* out,
                      hipStream_t st);
+// out[k + c*nsys] = || v[sys_ptr[k]:sys_ptr[k+1], c] ||_2
+void launch_segnorms(int64_t nsys, const int64_t* sys_ptr, const double* v, int64_t ldv,
+                     int64_t nrhs, double* out, hipStream_t st);
+// v[sys k rows, c] = 0 where mask[k + c*nsys] != 0
+void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t ldv, int64_t nrhs,
+                       const uint8_t* mask, hipStream_t st);
 
 }  // namespace tacho

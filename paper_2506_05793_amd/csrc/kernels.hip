@@ -1000,6 +1000,33 @@ __global__ __launch_bounds__(kThreads) void k_colnorms(int64_t n, const double* 
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_segnorms(const int64_t* sys_ptr, const double* v,
+                                                       int64_t ldv, int64_t nsys, double* out) {
+  __shared__ double part[kThreads / 64];
+  const int64_t k = blockIdx.x, c = blockIdx.y;
+  double acc = 0.0;
+  for (int64_t i = sys_ptr[k] + threadIdx.x; i < sys_ptr[k + 1]; i += kThreads) {
+    const double t = v[i + c * ldv];
+    acc += t * t;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) t += part[q];
+    out[k + c * nsys] = sqrt(t);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_units(const int64_t* sys_ptr, double* v,
+                                                         int64_t ldv, int64_t nsys,
+                                                         const uint8_t* mask) {
+  const int64_t k = blockIdx.x, c = blockIdx.y;
+  if (!mask[k + c * nsys]) return;
+  for (int64_t i = sys_ptr[k] + threadIdx.x; i < sys_ptr[k + 1]; i += kThreads) v[i + c * ldv] = 0.0;
+}
+
 inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -1125,6 +1152,20 @@ void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, co
 void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, double* out,
                      hipStream_t st) {
   if (nrhs > 0) hipLaunchKernelGGL(k_colnorms, dim3((unsigned)nrhs), dim3(kThreads), 0, st, n, v, ldv, out);
+}
+
+void launch_segnorms(int64_t nsys, const int64_t* sys_ptr, const double* v, int64_t ldv,
+                     int64_t nrhs, double* out, hipStream_t st) {
+  if (nsys > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_segnorms, dim3((unsigned)nsys, (unsigned)nrhs), dim3(kThreads), 0, st,
+                       sys_ptr, v, ldv, nsys, out);
+}
+
+void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t ldv, int64_t nrhs,
+                       const uint8_t* mask, hipStream_t st) {
+  if (nsys > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_zero_units, dim3((unsigned)nsys, (unsigned)nrhs), dim3(kThreads), 0, st,
+                       sys_ptr, v, ldv, nsys, mask);
 }
 
 #define TACHO_INSTANTIATE(T)                                                                     \

@@ -5,7 +5,7 @@
 // dimension m_s rounded up to kLdAlign elements.  Update matrices U_s
 // (r_s x r_s, r_s = m_s - w_s) live in a workspace whose blocks are reused
 // across levels: U_s is created at its own level and released once its
-// parent's level has assembled it, placed first-fit.
+// parent's level has assembled it, placed best-fit.
 //
 // Launch plan, per level of the supernodal elimination tree (level-set
 // scheduling, Tacho section), leaves first:
@@ -14,50 +14,75 @@
 //   large fronts: assembly into the panels / update matrices, then for every
 //     panel of kPanel columns a diagonal-block Cholesky launch, a triangular
 //     solve launch for the rows below and an update launch of the remaining
-//     panel columns, then one update launch U -= L21 L21^T.
+//     columns of its kOuter-wide outer panel; after each outer panel one
+//     update launch with K = kOuter of the remaining pivot columns; finally
+//     one update launch U -= L21 L21^T.
 #include <algorithm>
+#include <climits>
 #include <map>
+#include <set>
 
 #include "plan.hpp"
 
 namespace tacho {
 namespace {
 
-class FirstFit {
+// Best-fit allocator over a growing arena: a request takes the smallest free
+// block that holds it (lowest offset among equals), freed blocks coalesce
+// with their neighbours.  O(log blocks) per call.
+class BestFit {
  public:
   int64_t alloc(int64_t size) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= size) {
-        int64_t off = it->first;
-        int64_t rest = it->second - size;
-        free_.erase(it);
-        if (rest > 0) free_[off + size] = rest;
-        return off;
+    auto it = by_size_.lower_bound({size, INT64_MIN});
+    if (it == by_size_.end()) {
+      // grow: a free block at the top of the arena is extended
+      if (!by_off_.empty()) {
+        auto last = std::prev(by_off_.end());
+        if (last->first + last->second == top_) {
+          const int64_t off = last->first;
+          by_size_.erase({last->second, off});
+          by_off_.erase(last);
+          top_ = off + size;
+          return off;
+        }
       }
+      const int64_t off = top_;
+      top_ += size;
+      return off;
     }
-    int64_t off = top_;
-    top_ += size;
+    const int64_t bsize = it->first, off = it->second;
+    by_size_.erase(it);
+    by_off_.erase(off);
+    if (bsize > size) insert(off + size, bsize - size);
     return off;
   }
   void release(int64_t off, int64_t size) {
-    auto it = free_.emplace(off, size).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
+    auto nx = by_off_.lower_bound(off);
+    if (nx != by_off_.end() && off + size == nx->first) {
+      size += nx->second;
+      by_size_.erase({nx->second, nx->first});
+      nx = by_off_.erase(nx);
     }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
+    if (nx != by_off_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        size += pv->second;
+        by_size_.erase({pv->second, pv->first});
+        by_off_.erase(pv);
       }
     }
+    insert(off, size);
   }
   int64_t peak() const { return top_; }
 
  private:
-  std::map<int64_t, int64_t> free_;
+  void insert(int64_t off, int64_t size) {
+    by_off_.emplace(off, size);
+    by_size_.insert({size, off});
+  }
+  std::map<int64_t, int64_t> by_off_;
+  std::set<std::pair<int64_t, int64_t>> by_size_;
   int64_t top_ = 0;
 };
 
@@ -110,8 +135,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
   P.L_elems = off;
   P.u_elems = uoff;
 
-  // update-matrix workspace, first-fit by level
-  FirstFit ff;
+  // update-matrix workspace, best-fit by level
+  BestFit ff;
   for (int32_t h = 0; h < S.nlevels; ++h) {
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       int32_t s = S.level_list[q];
@@ -264,21 +289,45 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
         }
         P.steps.push_back(st);
       }
+      // Two-level blocking: a kPanel step updates only the columns of its
+      // kOuter-wide outer panel (all rows below); once an outer panel is
+      // done, one update with K = kOuter covers the rest of the front's
+      // pivot columns.
+      const int32_t k_outer = (k / kOuter) * kOuter;
+      const bool outer_end = k + kPanel >= k_outer + kOuter;
       for (int32_t s : big) {
         const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
-        if (w <= k + kPanel) continue;
+        const int32_t panel_end = std::min(w, k_outer + kOuter);
+        if (panel_end <= k + kPanel) continue;
         const int32_t kb = kPanel;
         GemmProb g;
         g.a_off = P.L_off[s] + (int64_t)k * P.ldL[s] + (k + kb);
         g.c_off = P.L_off[s] + (int64_t)(k + kb) * P.ldL[s] + (k + kb);
         g.lda = g.ldc = P.ldL[s];
         g.M = m - k - kb;
-        g.N = w - k - kb;
+        g.N = panel_end - k - kb;
         g.K = kb;
         g.c_in_u = 0;
         add_gemm(g);
       }
       add_gemm_step(h);
+      if (outer_end) {
+        const int32_t k1 = k_outer + kOuter;
+        for (int32_t s : big) {
+          const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+          if (w <= k1) continue;
+          GemmProb g;
+          g.a_off = P.L_off[s] + (int64_t)k_outer * P.ldL[s] + k1;
+          g.c_off = P.L_off[s] + (int64_t)k1 * P.ldL[s] + k1;
+          g.lda = g.ldc = P.ldL[s];
+          g.M = m - k1;
+          g.N = w - k1;
+          g.K = kOuter;
+          g.c_in_u = 0;
+          add_gemm(g);
+        }
+        add_gemm_step(h);
+      }
     }
     for (int32_t s : big) {
       const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], r = m - w;

@@ -79,6 +79,7 @@ struct Step {
 
 constexpr int kSmallMax = 64;     // fronts with m <= kSmallMax go to the LDS kernel
 constexpr int kPanel = 64;        // panel width of the blocked large-front path
+constexpr int kOuter = 256;       // outer panel width (trailing updates with K = kOuter)
 constexpr int kPanelRows = 64;    // rows per triangular-solve workgroup
 constexpr int kAsmCols = 8;       // front columns per assembly workgroup
 constexpr int kGemmTile = 64;     // output tile of the update kernel

@@ -13,9 +13,13 @@
 // supernodes; supernodal row structures by merging children; child-to-parent
 // relative maps; A-entry-to-front maps; height levels.
 #include <algorithm>
+#include <chrono>
 #include <cstdint>
 #include <cstring>
+#include <exception>
 #include <numeric>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "symbolic.hpp"
@@ -329,25 +333,144 @@ std::vector<int32_t> relaxed_supernodes(int64_t n, const std::vector<int32_t>& p
   return start;
 }
 
+// Indistinguishable vertices: u and v with the same closed adjacency set
+// (row u of the pattern, diagonal included, equals row v).  Multi-DOF
+// meshes have one such class per node (both DOFs couple to the same nodes).
+// The quotient graph has one vertex per class, numbered by ascending smallest
+// member; ordering it and expanding each class into its members (ascending,
+// consecutive) gives an order of the full graph at a fraction of the cost.
+// Returns false when every class is a single vertex.
+bool compress_indistinguishable(const Pattern& A, Pattern& Q, std::vector<int32_t>& cls_ptr,
+                                std::vector<int32_t>& cls_members) {
+  const int64_t n = A.n;
+  auto mix = [](uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  std::vector<uint64_t> h(n);
+  for (int64_t v = 0; v < n; ++v) {
+    uint64_t s = (uint64_t)(A.rowptr[v + 1] - A.rowptr[v]) * 0x100000001B3ull;
+    for (int64_t k = A.rowptr[v]; k < A.rowptr[v + 1]; ++k) s += mix((uint64_t)A.colind[k]);
+    h[v] = s;
+  }
+  auto same_row = [&](int64_t u, int64_t v) {
+    const int64_t du = A.rowptr[u + 1] - A.rowptr[u];
+    if (du != A.rowptr[v + 1] - A.rowptr[v]) return false;
+    return std::equal(A.colind.begin() + A.rowptr[u], A.colind.begin() + A.rowptr[u + 1],
+                      A.colind.begin() + A.rowptr[v]);
+  };
+  // class representative = smallest member; candidates share the hash
+  std::vector<int32_t> rep(n, -1);
+  std::unordered_map<uint64_t, std::vector<int32_t>> seen;
+  seen.reserve((size_t)n);
+  int64_t ncls = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    std::vector<int32_t>& reps = seen[h[v]];
+    for (int32_t r : reps)
+      if (same_row(r, v)) {
+        rep[v] = r;
+        break;
+      }
+    if (rep[v] < 0) {
+      rep[v] = (int32_t)v;
+      reps.push_back((int32_t)v);
+      ++ncls;
+    }
+  }
+  if (ncls == n) return false;
+  std::vector<int32_t> cls(n);
+  cls_ptr.assign(ncls + 1, 0);
+  std::vector<int32_t> reps_in_order;
+  reps_in_order.reserve(ncls);
+  {
+    std::vector<int32_t> id(n, -1);
+    for (int64_t v = 0; v < n; ++v) {
+      if (rep[v] == v) {
+        id[v] = (int32_t)reps_in_order.size();
+        reps_in_order.push_back((int32_t)v);
+      }
+      cls[v] = id[rep[v]];
+      cls_ptr[cls[v] + 1]++;
+    }
+  }
+  for (int64_t c = 0; c < ncls; ++c) cls_ptr[c + 1] += cls_ptr[c];
+  cls_members.resize(n);
+  {
+    std::vector<int32_t> pos(cls_ptr.begin(), cls_ptr.end() - 1);
+    for (int64_t v = 0; v < n; ++v) cls_members[pos[cls[v]]++] = (int32_t)v;
+  }
+  Q = Pattern();
+  Q.n = ncls;
+  Q.rowptr.assign(ncls + 1, 0);
+  std::vector<int32_t> row;
+  for (int64_t c = 0; c < ncls; ++c) {
+    const int32_t r = reps_in_order[c];
+    row.clear();
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) row.push_back(cls[A.colind[k]]);
+    std::sort(row.begin(), row.end());
+    row.erase(std::unique(row.begin(), row.end()), row.end());
+    Q.colind.insert(Q.colind.end(), row.begin(), row.end());
+    Q.rowptr[c + 1] = (int64_t)Q.colind.size();
+  }
+  return true;
+}
+
+namespace {
+
+// Order with one of the dissection methods, on the quotient graph when the
+// pattern has indistinguishable vertices.
+std::vector<int32_t> dissect(const Pattern& A, int method, int leaf) {
+  Pattern Q;
+  std::vector<int32_t> cptr, cmem;
+  if (!compress_indistinguishable(A, Q, cptr, cmem))
+    return method == 1 ? nested_dissection(A, leaf) : levelset_dissection(A, leaf);
+  const int qleaf = std::max(1, (int)(leaf * (int64_t)Q.n / std::max<int64_t>(1, A.n)));
+  std::vector<int32_t> pq = method == 1 ? nested_dissection(Q, qleaf) : levelset_dissection(Q, qleaf);
+  std::vector<int32_t> perm;
+  perm.reserve(A.n);
+  for (int32_t c : pq)
+    for (int32_t k = cptr[c]; k < cptr[c + 1]; ++k) perm.push_back(cmem[k]);
+  return perm;
+}
+
+}  // namespace
+
 int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
   const Pattern& A = S.A;
   const int64_t n = A.n;
   S.n = n;
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
 
   // 1. fill-reducing order: nested dissection (multilevel and/or level
   // structure), composed with an etree postorder; with both candidates the
   // one with fewer factorization flops is kept.
   Ordered O;
-  if (opt.ordering == 1) {
-    O = order_and_count(A, nested_dissection(A, opt.nd_leaf_size));
-    S.ordering_used = 1;
-  } else if (opt.ordering == 2) {
-    O = order_and_count(A, levelset_dissection(A, opt.nd_leaf_size));
-    S.ordering_used = 2;
+  if (opt.ordering == 1 || opt.ordering == 2) {
+    O = order_and_count(A, dissect(A, opt.ordering, opt.nd_leaf_size));
+    S.ordering_used = opt.ordering;
   } else {
-    O = order_and_count(A, nested_dissection(A, opt.nd_leaf_size));
+    // both candidates, concurrently (they share only the read-only pattern)
+    Ordered O2;
+    std::exception_ptr failed;
+    std::thread t2([&] {
+      try {
+        O2 = order_and_count(A, dissect(A, 2, opt.nd_leaf_size));
+      } catch (...) {
+        failed = std::current_exception();
+      }
+    });
+    try {
+      O = order_and_count(A, dissect(A, 1, opt.nd_leaf_size));
+    } catch (...) {
+      t2.join();
+      throw;
+    }
+    t2.join();
+    if (failed) std::rethrow_exception(failed);
     S.ordering_used = 1;
-    Ordered O2 = order_and_count(A, levelset_dissection(A, opt.nd_leaf_size));
     if (O2.flops < O.flops) {
       O = std::move(O2);
       S.ordering_used = 2;
@@ -361,6 +484,8 @@ int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
   S.flops = O.flops;
   std::vector<int64_t> lptr = std::move(O.lptr);
   std::vector<int32_t> lind = std::move(O.lind);
+  const auto t1 = clk::now();
+  S.t_order_us = std::chrono::duration_cast<std::chrono::microseconds>(t1 - t0).count();
 
   // 2. relaxed supernodes and the supernodal tree.
   S.sptr = relaxed_supernodes(n, S.parent, S.colcount);
@@ -505,6 +630,8 @@ int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
     S.max_m = std::max<int64_t>(S.max_m, S.front_m[s]);
     S.max_w = std::max<int64_t>(S.max_w, S.sptr[s + 1] - S.sptr[s]);
   }
+  S.t_structure_us =
+      std::chrono::duration_cast<std::chrono::microseconds>(clk::now() - t1).count();
   return kOk;
 }
 

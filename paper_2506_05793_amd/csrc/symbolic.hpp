@@ -36,6 +36,7 @@ struct Symbolic {
   int64_t nnzL = 0, flops = 0;
   int64_t nnz_front = 0;  // stored factor entries incl. explicit zeros of relaxed supernodes
   int ordering_used = 0;  // 1 multilevel, 2 level-structure
+  int64_t t_order_us = 0, t_structure_us = 0, t_plan_us = 0;  // analysis phase times
 
   // supernodes
   int32_t ns = 0;
@@ -70,6 +71,11 @@ int build_pattern(int64_t n, const int64_t* rowptr, const int32_t* colind, Patte
 // graph of P (self loops ignored).
 std::vector<int32_t> nested_dissection(const Pattern& P, int leaf_size);
 std::vector<int32_t> levelset_dissection(const Pattern& P, int leaf_size);
+
+// Classes of indistinguishable vertices (equal rows of the pattern) and the
+// quotient pattern; false when there is nothing to compress.
+bool compress_indistinguishable(const Pattern& A, Pattern& Q, std::vector<int32_t>& cls_ptr,
+                                std::vector<int32_t>& cls_members);
 
 int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err);
 

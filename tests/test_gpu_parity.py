@@ -245,3 +245,22 @@ def test_graph_replays_match_eager():
         torch.cuda.synchronize()
         assert np.array_equal(T.tacho_get_factor(ng)[2], want[name]), name
         assert oracle.rel_residual(M, x, b).max() <= FP64_RESID_TOL
+
+
+def test_batch_fp32_refinement_alone_equals_batched():
+    """Refinement converges per system, so a batched FP32+IR result equals the
+    system's result alone, bitwise."""
+    mats = gen.batch_fv3d(5, seed=7, lo=5, hi=10)
+    sb = T.tacho_analyze_batch([(m.n, m.rowptr, m.colind) for m in mats])
+    nb = T.tacho_factorize(sb, np.concatenate([m.values for m in mats]), T.TACHO_FP32)
+    rhs = [gen.rhs(m.n, 3, seed=30 + k) for k, m in enumerate(mats)]
+    xb, info = T.tacho_solve(nb, np.asfortranarray(np.concatenate(rhs, axis=0)), with_info=True)
+    assert info["relres_max"] <= MIXED_RESID_TOL
+    off = 0
+    for k, m in enumerate(mats):
+        s, _ = analyze(m)
+        num = T.tacho_factorize(s, m.values, T.TACHO_FP32)
+        x = T.tacho_solve(num, rhs[k])
+        assert np.array_equal(x, xb[off:off + m.n]), k
+        assert oracle.rel_residual(m, x, rhs[k]).max() <= MIXED_RESID_TOL
+        off += m.n

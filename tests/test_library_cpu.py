@@ -147,3 +147,15 @@ def test_batch_is_block_diagonal_union():
     alone = np.concatenate([T.tacho_get_symbolic(T.tacho_analyze(m.n, m.rowptr, m.colind)).colcount
                             for m in mats])
     assert sorted(alone.tolist()) == sorted(a.colcount.tolist())
+
+
+@pytest.mark.parametrize("ordering", [0, 1, 2])
+def test_indistinguishable_dofs_stay_consecutive(ordering):
+    """Both DOFs of a mesh node have equal pattern rows; the ordering works on
+    the node graph and keeps each node's DOFs next to each other."""
+    A = gen.landice(9, 8, 4, seed=3)
+    s, a, q = symbolic_matches_oracle(A, T.tacho_default_options(ordering=ordering))
+    pinv = np.empty(A.n, np.int64)
+    pinv[a.perm] = np.arange(A.n)
+    assert np.all(pinv[1::2] == pinv[0::2] + 1)
+
