@@ -175,7 +175,7 @@ def summarize(r, flops, tol):
     return out
 
 
-FACTOR_KERNELS = ("k_small", "k_assemble", "k_diag", "k_panel", "k_gemm", "k_gather")
+FACTOR_KERNELS = ("k_small", "k_assemble", "k_diag", "k_panel", "k_gemm", "k_gather", "k_front")
 
 
 def kernel_profile(T, torch, num, vals, b1, b16):
@@ -198,7 +198,7 @@ def roofline(prof):
     name = max(factor, key=lambda k: factor[k]["ms"])
     p = factor[name]
     avg_ms = p["ms"] / p["launches"]
-    if name == "k_gemm":
+    if name in ("k_gemm", "k_front"):
         achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12
         out = {"bound": "mfma", "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s"}
     elif name in ("k_small", "k_diag", "k_panel"):

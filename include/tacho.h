@@ -73,7 +73,11 @@ typedef struct {
                                 captured once per numeric handle into a hipGraph and
                                 replayed; 0: launched eagerly.  Kernel profiling
                                 always launches eagerly. */
-  int32_t reserved[5];
+  int32_t front_kernel;      /* large fronts (m > 64): 0 (default) one dataflow launch
+                                per level (tile tasks over 64-column pivot blocks with
+                                completion counters); 1: stepwise launches per pivot
+                                block (diagonal block, rows below, trailing update) */
+  int32_t reserved[4];
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -103,8 +107,9 @@ typedef struct {
 
 typedef struct {
   int32_t iters;      /* FP32 path: refinement corrections applied (0 for FP64) */
-  int32_t fell_back;  /* FP32 path: 1 if refinement stalled and the solve was redone
-                         with an FP64 refactorization (still a success) */
+  int32_t fell_back;  /* FP32 path: 1 if the FP32 factorization broke down or
+                         refinement stalled, and the solve was done with an FP64
+                         refactorization of the same values (still a success) */
   double relres_max;  /* max over columns of ||b - A x||_2 / ||b||_2 (FP32 path) */
   double *relres;     /* optional, caller-owned array of nrhs entries receiving the
                          per-column relative residual (FP32 path), or NULL */
@@ -178,7 +183,11 @@ int tacho_get_symbolic(tacho_sym_t sym, int32_t *perm, int32_t *parent, int64_t 
  *                     index of the first column (in elimination order) whose
  *                     pivot was not positive; no handle is created then
  * Blocks the calling thread until the device work is finished (one
- * device-to-host read of the failure flag).
+ * device-to-host read of the failure flag).  With TACHO_FP32 a pivot
+ * breakdown of the FP32 factorization is not an error: the same values are
+ * refactored in FP64 on the same symbolic handle and the solves use that
+ * factor (info->fell_back = 1); TACHO_ERR_NOT_SPD is returned only when the
+ * FP64 factorization fails too.
  */
 int tacho_factorize(tacho_sym_t sym, const double *values, int values_on_device, int precision,
                     void *hip_stream, tacho_num_t *out, int64_t *fail_index);
@@ -261,7 +270,8 @@ int tacho_last_times(tacho_num_t num, double *factor_ms, double *solve_ms);
 #define TACHO_K_BACKWARD 7    /* backward substitution, one launch per level */
 #define TACHO_K_PERMUTE 8     /* right-hand side / solution permutation */
 #define TACHO_K_REFINE 9      /* FP64 residual and norms of the refinement */
-#define TACHO_PROFILE_KINDS 10
+#define TACHO_K_FRONT 10      /* dataflow factorization of a level's large fronts */
+#define TACHO_PROFILE_KINDS 11
 
 /* enable = 1 clears the counters and starts recording; 0 stops. */
 int tacho_profile(tacho_num_t num, int enable);

@@ -26,7 +26,7 @@ TACHO_ERR_NOMEM = -4
 TACHO_ERR_HIP = -5
 TACHO_FP64 = 0
 TACHO_FP32 = 1
-TACHO_PROFILE_KINDS = 10
+TACHO_PROFILE_KINDS = 11
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -46,7 +46,8 @@ class tacho_options(ctypes.Structure):
         ("block_size", ctypes.c_int32),
         ("ordering", ctypes.c_int32),
         ("graphs", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("front_kernel", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 

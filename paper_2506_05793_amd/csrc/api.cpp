@@ -92,8 +92,8 @@ struct tacho_sym {
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
       d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
       d_wbase, d_woff, d_gather;
-  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_levels, d_fwd_items, d_bwd_items,
-      d_tri_fwd, d_tri_bwd;
+  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fwd_items,
+      d_bwd_items, d_tri_fwd, d_tri_bwd;
   DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
   DevSym view{};
   std::mutex mu;
@@ -165,6 +165,7 @@ struct tacho_num {
   DBuf L, U, avals, vals, fullvals, scale, fail, winv;
   DBuf y, uvec;             // solve workspace (kRhs columns)
   DBuf sync;                // solve tickets (2 per level) and block ready flags
+  DBuf flow;                // dataflow factorization counters, flags, tickets, hang flag
   DBuf bdev, xdev, r, dx, norms;  // host-pointer staging and refinement buffers
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool pending = false;     // factorization queued, flag not yet read
@@ -172,6 +173,7 @@ struct tacho_num {
   int64_t last_fail = -1;
   hipStream_t last_stream = nullptr;
   tacho_num* fallback = nullptr;  // FP64 refactorization after a refinement stall
+  bool fp32_broken = false;       // FP32 pivot breakdown: solves use `fallback`
   hipGraphExec_t fgraph = nullptr;  // captured factorization launch sequence
   ~tacho_num() {
     if (fgraph) (void)hipGraphExecDestroy(fgraph);
@@ -198,6 +200,7 @@ tacho_options defaults() {
   o.block_size = 0;
   o.ordering = 0;
   o.graphs = 1;
+  o.front_kernel = 0;
   return o;
 }
 
@@ -210,7 +213,7 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   int rc = analyze_pattern(h->S, so, err);
   if (rc != kOk) return fail(rc, err);
   const auto t_plan = std::chrono::steady_clock::now();
-  rc = build_plan(h->S, h->P, err);
+  rc = build_plan(h->S, h->P, err, h->opt.front_kernel == 1 ? 1 : 0);
   if (rc != kOk) return fail(rc, err);
   const Symbolic& S = h->S;
   // lower-twin index of every pattern entry, for the refinement residual
@@ -278,6 +281,7 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_panel, P.panel_items));
   HIP_TRY(upload(h->d_probs, P.probs));
   HIP_TRY(upload(h->d_tiles, P.tiles));
+  HIP_TRY(upload(h->d_ftasks, P.ftasks));
   HIP_TRY(upload(h->d_levels, S.level_list));
   HIP_TRY(upload(h->d_fwd_items, P.fwd_items));
   HIP_TRY(upload(h->d_bwd_items, P.bwd_items));
@@ -318,6 +322,12 @@ size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
 
 // Device bytes a numeric handle needs (factor, update workspace, values,
 // solve workspace for kRhs columns).
+// Dataflow factorization: per pivot block a counter and a ready flag, one
+// ticket counter per level, one hang flag.
+int64_t flow_ints(const tacho_sym* h) {
+  return 2 * (int64_t)h->P.woff.size() + h->S.nlevels + 1;
+}
+
 int64_t numeric_bytes(const tacho_sym* h, int precision) {
   const size_t es = elem_size(precision);
   const Symbolic& S = h->S;
@@ -328,6 +338,7 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += (int64_t)es * (S.n + P.u_elems) * kRhs;
   b += (int64_t)es * P.W_elems;
   b += 4 * (2 * S.nlevels + P.tri_flags + 1);
+  b += 4 * flow_ints(h);
   if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;  // values, scaling
   return b;
 }
@@ -349,6 +360,7 @@ int step_kind(int kind) {
     case kStepAssemble: return TACHO_K_ASSEMBLE;
     case kStepDiag: return TACHO_K_DIAG;
     case kStepPanel: return TACHO_K_PANEL;
+    case kStepFront: return TACHO_K_FRONT;
     default: return TACHO_K_UPDATE;
   }
 }
@@ -365,6 +377,8 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
   const PanelItem* pan = h->d_panel.as<PanelItem>();
   const GemmProb* probs = h->d_probs.as<GemmProb>();
   const GemmTile* tiles = h->d_tiles.as<GemmTile>();
+  const FrontTask* ftasks = h->d_ftasks.as<FrontTask>();
+  const int64_t nblk = (int64_t)P.woff.size();
   for (const Step& s : P.steps) {
     const int64_t cnt = s.end - s.begin;
     const int pe = f->prof.begin(st);
@@ -374,16 +388,42 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
       case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, f->winv.as<T>(), st); break;
       case kStepPanel: launch_panel<T>(S, N, pan + s.begin, cnt, f->winv.as<T>(), st); break;
       case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, s.tile, st); break;
+      case kStepFront:
+        launch_front<T>(S, N, f->winv.as<T>(), ftasks + s.begin, cnt, f->flow.as<int32_t>(), nblk,
+                        s.level, (int)h->S.nlevels, st);
+        break;
     }
     f->prof.end(pe, st, step_kind(s.kind), s.flops, s.elems * sizeof(T));
   }
 }
 
+int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, int sync,
+             int64_t* fail_index);
+int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index);
+
 int read_fail_flag(tacho_num* f, int64_t* fail_index) {
-  int32_t flag = INT32_MAX;
+  int32_t flag = INT32_MAX, hang = 0;
   HIP_TRY(hipMemcpyAsync(&flag, f->fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, f->last_stream));
+  if (!f->sym->P.ftasks.empty())
+    HIP_TRY(hipMemcpyAsync(&hang, f->flow.as<int32_t>() + flow_ints(f->sym) - 1, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, f->last_stream));
   HIP_TRY(hipStreamSynchronize(f->last_stream));
   f->pending = false;
+  if (hang != 0) {
+    f->last_status = TACHO_ERR_HIP;
+    return fail(TACHO_ERR_HIP, "dataflow factorization: a dependency wait timed out");
+  }
+  if (flag != INT32_MAX && f->precision == TACHO_FP32) {
+    // FP32 pivot breakdown: the FP64 factorization of the same values on the
+    // same symbolic handle serves this handle's solves (reported as a fallback).
+    int64_t fi = -1;
+    const int rc = fp64_fallback(f, f->last_stream, &fi);
+    f->last_status = rc;
+    f->last_fail = rc == TACHO_OK ? -1 : fi;
+    if (fail_index) *fail_index = f->last_fail;
+    if (rc == TACHO_OK) f->fp32_broken = true;
+    return rc;
+  }
   if (flag != INT32_MAX) {
     f->last_fail = f->sym->S.perm[flag];
     f->last_status = TACHO_ERR_NOT_SPD;
@@ -404,6 +444,7 @@ void enqueue_factor(tacho_num* f, hipStream_t st) {
   tacho_sym* h = f->sym;
   const Symbolic& S = h->S;
   launch_fill_i32(f->fail.as<int32_t>(), INT32_MAX, 1, st);
+  if (!h->P.ftasks.empty()) launch_fill_i32(f->flow.as<int32_t>(), 0, flow_ints(h), st);
   const double* vals = f->vals.as<double>();
   const int64_t nq = (int64_t)S.a_src.size();
   if (f->precision == TACHO_FP32) {
@@ -449,6 +490,7 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
   const Symbolic& S = h->S;
   const int64_t nv = S.nnz_input;
   if (nv > 0 && !values) return fail(TACHO_ERR_INVALID, "values is NULL");
+  f->fp32_broken = false;
   if (nv > 0)
     HIP_TRY(hipMemcpyAsync(f->vals.p, values, nv * sizeof(double),
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
@@ -492,6 +534,7 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   HIP_TRY(f->y.alloc(es * S.n * kRhs));
   HIP_TRY(f->uvec.alloc(es * P.u_elems * kRhs));
   HIP_TRY(f->sync.alloc(sizeof(int32_t) * (2 * S.nlevels + P.tri_flags + 1)));
+  HIP_TRY(f->flow.alloc(sizeof(int32_t) * flow_ints(h)));
   if (precision == TACHO_FP32) {
     HIP_TRY(f->scale.alloc(sizeof(double) * S.n));
     HIP_TRY(f->fullvals.alloc(sizeof(double) * S.A.colind.size()));
@@ -499,6 +542,18 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   for (auto& e : f->ev) HIP_TRY(hipEventCreate(&e));
   *out = f.release();
   return TACHO_OK;
+}
+
+// FP64 refactorization of an FP32 handle's values on the same symbolic
+// handle, used after an FP32 pivot breakdown or a refinement stall.
+int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index) {
+  if (!f->fallback) {
+    tacho_num* g = nullptr;
+    const int rc = create_numeric(f->sym, TACHO_FP64, &g);
+    if (rc != TACHO_OK) return rc;
+    f->fallback = g;
+  }
+  return refactor(f->fallback, f->vals.as<double>(), 1, st, 1, fail_index);
 }
 
 // One sweep of forward + backward substitution for up to kRhs columns,
@@ -588,12 +643,12 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
   std::vector<int> stalls(units, 0);
   std::vector<uint8_t> done(units, 0);
   launch_segnorms(nsys, sysp, b, n, nrhs, nrm + units, st);
-  solve_all<float>(f, b, n, x, n, nrhs, 0, st);
+  if (!f->fp32_broken) solve_all<float>(f, b, n, x, n, nrhs, 0, st);
   const double tol = h->opt.refine_tol > 0 ? h->opt.refine_tol : 1e-10;
   const int maxit = h->opt.refine_max > 0 ? h->opt.refine_max : 10;
   const double ratio = h->opt.stall_ratio > 0 ? h->opt.stall_ratio : 0.5;
   int iters = 0;
-  bool stalled = false;
+  bool stalled = f->fp32_broken;
   const double nnz = (double)S.A.colind.size();
   auto residual_norms = [&]() -> int {
     const int pe = f->prof.begin(st);
@@ -611,7 +666,7 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
     }
     return TACHO_OK;
   };
-  for (;;) {
+  while (!f->fp32_broken) {
     int rc = residual_norms();
     if (rc != TACHO_OK) return rc;
     bool all = true;
@@ -641,16 +696,14 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
     ++iters;
   }
   if (stalled) {
-    // FP64 refactorization with the same values, then an FP64 solve.
-    if (!f->fallback) {
-      tacho_num* g = nullptr;
-      int rc = create_numeric(h, TACHO_FP64, &g);
+    // FP64 refactorization with the same values (already done after an FP32
+    // pivot breakdown), then an FP64 solve.
+    int rc = TACHO_OK;
+    if (!f->fp32_broken) {
+      int64_t fi = -1;
+      rc = fp64_fallback(f, st, &fi);
       if (rc != TACHO_OK) return rc;
-      f->fallback = g;
     }
-    int64_t fi = -1;
-    int rc = refactor(f->fallback, f->vals.as<double>(), 1, st, 1, &fi);
-    if (rc != TACHO_OK) return rc;
     solve_all<double>(f->fallback, b, n, x, n, nrhs, 0, st);
     rc = residual_norms();
     if (rc != TACHO_OK) return rc;
@@ -973,7 +1026,7 @@ int tacho_profile_read(tacho_num_t f, int kind, int64_t* launches, double* ms, d
 const char* tacho_kernel_name(int kind) {
   static const char* names[TACHO_PROFILE_KINDS] = {
       "k_small", "k_assemble", "k_diag", "k_panel", "k_gemm",
-      "k_gather", "k_fwd", "k_bwd", "k_permute", "k_residual"};
+      "k_gather", "k_fwd", "k_bwd", "k_permute", "k_residual", "k_front"};
   return kind >= 0 && kind < TACHO_PROFILE_KINDS ? names[kind] : "unknown";
 }
 

@@ -66,6 +66,14 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
                  int tile, hipStream_t st);
+// Dataflow factorization of one level's large fronts.  flow holds, for the
+// nblocks pivot blocks of all large fronts, the finished-row-tile counters,
+// then the diagonal-block ready flags, then one ticket counter per level and
+// the hang flag; all zero before the factorization starts.
+template <typename T>
+void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
+                  int64_t count, int32_t* flow, int64_t nblocks, int level, int nlevels,
+                  hipStream_t st);
 
 // Solves: y is the permuted right-hand side / solution (n x nrhs, ld n).
 template <typename T>

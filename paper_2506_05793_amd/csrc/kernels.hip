@@ -228,36 +228,25 @@ __global__ __launch_bounds__(kThreads) void k_assemble(DevSym S, DevNum<T> N,
 }
 
 // ---------------------------------------------------------------------------
-// Large fronts, panel step 1 (one workgroup per front): Cholesky of the
-// diagonal block [k, k+kb) in LDS, blocked by 16 columns (a 16x16 block by
-// one wave, its rows below by one thread each, a rank-16 update of the rest),
-// written back in place, and its inverse W = L_kk^{-1} (identity-padded to
-// kPanel) written to the scratch slot of the item for the triangular solve
-// of the rows below.  Non-positive or NaN pivots go to the failure flag.
+// Diagonal blocks of large fronts: Cholesky of a 64 x 64 block in LDS,
+// blocked by 16 columns (a 16x16 block by one wave, its rows below by one
+// thread each, a rank-16 update of the rest), and its inverse W = L_kk^{-1},
+// kept per block for the triangular solves of the rows below and for the
+// solve phase.  Non-positive or NaN pivots go to the failure flag.
 constexpr int kSub = 16;
 
+// Cholesky of the kb x kb diagonal block held in D (column-major, ld
+// kDiagLd, entries past kb set to the identity), in place, and its inverse W
+// = L^{-1} (same layout, computed by 16x16 blocks).  rd receives the
+// reciprocal pivots.  A non-positive or NaN pivot j records col0 + j in
+// *fail.  Every thread of the workgroup takes part.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const PanelItem* items,
-                                                   T* winv) {
-  __shared__ T D[kPanel * kDiagLd];  // column-major, D[c * kDiagLd + r]
-  __shared__ T W[kPanel * kDiagLd];
-  __shared__ T rd[kPanel];           // 1 / L_jj
-  const PanelItem it = items[blockIdx.x];
+__device__ void diag_factor_inverse(T* D, T* W, T* rd, T (*Tmp)[kSub * kSub], int kb, int col0,
+                                    int32_t* fail) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int s = it.s, k = it.k, kb = it.kb;
-  const int f = S.sptr[s], ld = S.ldL[s];
-  T* Lp = N.L + S.L_off[s];
-  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
-    const int c = t / kPanel, r = t - c * kPanel;
-    T v;
-    if (r < kb && c < kb)
-      v = r >= c ? Lp[(k + r) + (int64_t)(k + c) * ld] : T(0);
-    else
-      v = r == c ? T(1) : T(0);
-    D[c * kDiagLd + r] = v;
-  }
-  __syncthreads();
-  for (int jb = 0; jb < kPanel; jb += kSub) {
+  // blocks past kb hold the identity padding: only [0, kr) is worked on
+  const int kr = (kb + kSub - 1) / kSub * kSub;
+  for (int jb = 0; jb < kr; jb += kSub) {
     // (1) 16x16 diagonal block in registers: lane i < 16 holds row jb + i;
     // pivots and column entries are broadcast with readlane.
     if (wave == 0 && lane < kSub) {
@@ -267,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
 #pragma unroll
       for (int j = 0; j < kSub; ++j) {
         const T piv = readlane(a[j], j);
-        if (lane == 0 && jb + j < kb && !(piv > T(0))) atomicMin(N.fail, f + k + jb + j);
+        if (lane == 0 && jb + j < kb && !(piv > T(0))) atomicMin(fail, col0 + jb + j);
         const T ljj = sqrt(piv);
         const T rinv = T(1) / ljj;
         if (lane == 0) rd[jb + j] = rinv;
@@ -284,7 +273,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
     }
     __syncthreads();
     // (2) rows below the block: one thread per row, forward substitution
-    const int below = kPanel - jb - kSub;
+    const int below = kr - jb - kSub;
     if (tid < below) {
       const int r = jb + kSub + tid;
       T x[kSub];
@@ -314,21 +303,16 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
     }
     __syncthreads();
   }
-  for (int t = tid; t < kb * kb; t += kThreads) {
-    const int c = t / kb, r = t - c * kb;
-    if (r >= c) Lp[(k + r) + (int64_t)(k + c) * ld] = D[c * kDiagLd + r];
-  }
   // W = L^{-1} by 16x16 blocks.  Diagonal blocks first (one thread per
   // column of each block, forward substitution down its own column), then
   // the off-diagonal blocks by distance d = 1..3 from the diagonal:
   // W_ib = -W_ii * sum_{q=b}^{i-1} L_iq W_qb.
-  __shared__ T Tmp[3][kSub * kSub];
   for (int t = tid; t < kPanel * kPanel; t += kThreads) {
     const int c = t / kPanel, r = t - c * kPanel;
-    W[c * kDiagLd + r] = T(0);
+    W[c * kDiagLd + r] = (r == c && r >= kr) ? T(1) : T(0);
   }
   __syncthreads();
-  if (tid < kPanel) {
+  if (tid < kr) {
     const int col = tid, b0 = (col / kSub) * kSub;
     for (int r = col; r < b0 + kSub; ++r) {
       T acc = r == col ? T(1) : T(0);
@@ -337,8 +321,8 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
     }
   }
   __syncthreads();
-  for (int d = 1; d < kPanel / kSub; ++d) {
-    const int nblk = kPanel / kSub - d;  // blocks (b + d, b), b < nblk
+  for (int d = 1; d < kr / kSub; ++d) {
+    const int nblk = kr / kSub - d;  // blocks (b + d, b), b < nblk
     for (int t = tid; t < nblk * kSub * kSub; t += kThreads) {
       const int bb = t / (kSub * kSub), e = t - bb * kSub * kSub;
       const int rr = e % kSub, cc = e / kSub;
@@ -357,6 +341,37 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
       W[c * kDiagLd + i0 + rr] = -acc;
     }
     __syncthreads();
+  }
+}
+
+// Large fronts, panel step 1 (stepwise path): Cholesky of the diagonal
+// block [k, k+kb) of front s and its inverse, kept for the solves.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const PanelItem* items,
+                                                   T* winv) {
+  __shared__ T D[kPanel * kDiagLd];  // column-major, D[c * kDiagLd + r]
+  __shared__ T W[kPanel * kDiagLd];
+  __shared__ T rd[kPanel];           // 1 / L_jj
+  __shared__ T Tmp[3][kSub * kSub];
+  const PanelItem it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int s = it.s, k = it.k, kb = it.kb;
+  const int f = S.sptr[s], ld = S.ldL[s];
+  T* Lp = N.L + S.L_off[s];
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    T v;
+    if (r < kb && c < kb)
+      v = r >= c ? Lp[(k + r) + (int64_t)(k + c) * ld] : T(0);
+    else
+      v = r == c ? T(1) : T(0);
+    D[c * kDiagLd + r] = v;
+  }
+  __syncthreads();
+  diag_factor_inverse<T>(D, W, rd, Tmp, kb, f + k, N.fail);
+  for (int t = tid; t < kb * kb; t += kThreads) {
+    const int c = t / kb, r = t - c * kb;
+    if (r >= c) Lp[(k + r) + (int64_t)(k + c) * ld] = D[c * kDiagLd + r];
   }
   T* Wout = winv + S.woff[it.wblk];  // kb x kb, column-major
   for (int t = tid; t < kb * kb; t += kThreads) {
@@ -558,16 +573,269 @@ __device__ inline bool solve_split(int w, int r) { return solve_split_front(w, r
 // workgroup that is already resident; the spin is bounded all the same.
 constexpr int kSpinLimit = 1 << 25;
 
+// Waits poll with relaxed atomic loads and order the caller's later loads
+// with one acquire fence once the value is seen, so that polling does not
+// invalidate caches that other workgroups are using.
 __device__ inline void wait_flag(const int32_t* flag, int32_t value) {
   int spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < value) {
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
     __builtin_amdgcn_s_sleep(1);
     if (++spins > kSpinLimit) break;
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __device__ inline void set_flag(int32_t* flag, int32_t value) {
   __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait for *flag >= value (acquire).  A dependency of the dataflow
+// factorization is satisfied within one level's run time, far below the
+// bound; on timeout the hang flag is raised (the host reports it as an
+// error) and every other wait of the launch gives up as soon as it sees the
+// flag, so the launch drains.
+constexpr int kFlowSpinLimit = 1 << 21;
+
+__device__ inline void wait_at_least(const int32_t* flag, int32_t value, int32_t* hang) {
+  int spins = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
+    __builtin_amdgcn_s_sleep(1);
+    ++spins;
+    if ((spins & 255) == 0 && __hip_atomic_load(hang, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      break;
+    if (spins > kFlowSpinLimit) {
+      __hip_atomic_store(hang, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// ---------------------------------------------------------------------------
+// Dataflow factorization of the large fronts of one level (one launch).
+// Left-looking over 64-column pivot blocks: the task of pivot block j, row
+// tile t accumulates L(rows, p) L(block j rows, p)^T over the completed
+// blocks p < j in registers on the matrix cores, subtracts it from the
+// assembled front, then either factors the diagonal block (t = 0: Cholesky
+// and inverse W_j, published through a ready flag) or solves its rows
+// against it (X = C W_j^T on the matrix cores).  Update-matrix tiles
+// accumulate over all pivot blocks of their front, each as soon as it is
+// complete, and subtract the sum from the assembled U.  A per-block counter
+// of finished row tiles tells a consumer that a pivot block is complete.
+//
+// Workgroups take tasks from a ticket counter in the plan's order, in which
+// every task depends only on tasks with smaller tickets; those belong to
+// workgroups that already run, so the waits end (and are bounded anyway).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_front(DevSym S, DevNum<T> N, T* winv,
+                                                    const FrontTask* tasks, int count,
+                                                    int32_t* col_done, int32_t* diag_ready,
+                                                    int32_t* counter, int32_t* hang) {
+  constexpr int TT = kPanel, KT = 16, PAD = 4, BL = 2;
+  constexpr int LPT = TT * KT / kThreads;  // staged elements per thread and operand
+  constexpr int RSTEP = kThreads / TT;     // k rows covered per load round
+  constexpr int STAGE = 2 * KT * (TT + PAD);
+  constexpr int POST = 2 * kPanel * kDiagLd + 3 * kSub * kSub + kPanel;
+  constexpr int LDS = POST > 2 * STAGE ? POST : 2 * STAGE;
+  __shared__ T lds[LDS];
+  __shared__ int s_ticket;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  if (tid == 0) s_ticket = atomicAdd(counter, 1);
+  __syncthreads();
+  const int ticket = s_ticket;
+  if (ticket >= count) return;
+  const FrontTask tk = tasks[ticket];
+  const int s = tk.s;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], ld = S.ldL[s];
+  const int wb = S.wbase[s];
+  T* Lp = N.L + S.L_off[s];
+  const bool utile = tk.kind != 0;
+  const int c0 = tk.j * TT;
+  const int kb = utile ? TT : min(TT, w - c0);
+  // output rows [a0, a0 + arows) x columns (operand rows) [b0, b0 + bcols)
+  int a0, arows, b0, bcols, K;
+  if (utile) {
+    a0 = w + tk.t * TT;
+    b0 = w + tk.j * TT;
+    arows = min(TT, m - a0);
+    bcols = min(TT, m - b0);
+    K = w;
+  } else {
+    a0 = tk.t == 0 ? c0 : c0 + kb + (tk.t - 1) * TT;
+    arows = tk.t == 0 ? kb : min(TT, m - a0);
+    b0 = c0;
+    bcols = kb;
+    K = c0;
+  }
+
+  typedef typename Vec4<T>::type V4;
+  V4 acc[BL][BL];
+#pragma unroll
+  for (int a = 0; a < BL; ++a)
+#pragma unroll
+    for (int b = 0; b < BL; ++b) acc[a][b] = V4{0, 0, 0, 0};
+  {
+    T* As = lds;          // [2][KT][TT + PAD]
+    T* Bs = lds + STAGE;  // [2][KT][TT + PAD]
+    const int lrow = tid % TT, lk = tid / TT;
+    const bool aok = lrow < arows, bok = lrow < bcols;
+    const T* pa = Lp + a0 + lrow;
+    const T* pb = Lp + b0 + lrow;
+    T ra[LPT], rb[LPT];
+    int ready = 0;  // pivot blocks [0, ready) known complete
+    auto load_stage = [&](int k0) {
+      if (k0 % TT == 0 && k0 / TT >= ready) {
+        const int p = k0 / TT;
+        wait_at_least(col_done + wb + p, front_block_tiles(m, w, p), hang);
+        ready = p + 1;
+      }
+#pragma unroll
+      for (int u = 0; u < LPT; ++u) {
+        const int kg = k0 + lk + RSTEP * u;
+        const bool kok = kg < K;
+        ra[u] = (aok && kok) ? pa[(int64_t)kg * ld] : T(0);
+        rb[u] = (bok && kok) ? pb[(int64_t)kg * ld] : T(0);
+      }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < LPT; ++u) {
+        As[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = ra[u];
+        Bs[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = rb[u];
+      }
+    };
+    const int nstage = (K + KT - 1) / KT;
+    if (nstage > 0) {
+      load_stage(0);
+      store_stage(0);
+      __syncthreads();
+    }
+    for (int st = 0; st < nstage; ++st) {
+      const int buf = st & 1;
+      if (st + 1 < nstage) load_stage((st + 1) * KT);
+#pragma unroll
+      for (int ks = 0; ks < KT / 4; ++ks) {
+        const int kr = buf * KT + ks * 4 + (lane >> 4);
+        T av[BL], bv[BL];
+#pragma unroll
+        for (int a = 0; a < BL; ++a) av[a] = As[kr * (TT + PAD) + wr * (TT / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < BL; ++b) bv[b] = Bs[kr * (TT + PAD) + wc * (TT / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < BL; ++a)
+#pragma unroll
+          for (int b = 0; b < BL; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+      }
+      if (st + 1 < nstage) store_stage(buf ^ 1);
+      __syncthreads();
+    }
+  }
+
+  if (utile) {
+    T* C = N.U + S.U_off[s];
+    const int ldc = S.ldU[s];
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = wr * (TT / 2) + a * 16 + (lane & 15);
+          const int jj = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+          const int gi = tk.t * TT + i, gj = tk.j * TT + jj;
+          if (i < arows && jj < bcols && gi >= gj) {
+            T* p = C + gi + (int64_t)gj * ldc;
+            *p = *p - acc[a][b][v];
+          }
+        }
+    return;
+  }
+
+  // C = F - acc for the tile, column-major in LDS (ld kDiagLd)
+  T* Cs = lds;
+  T* Ws = lds + kPanel * kDiagLd;
+  T(*Tmp)[kSub * kSub] = reinterpret_cast<T(*)[kSub * kSub]>(lds + 2 * kPanel * kDiagLd);
+  T* rd = lds + 2 * kPanel * kDiagLd + 3 * kSub * kSub;
+  const bool diag = tk.t == 0;
+#pragma unroll
+  for (int a = 0; a < BL; ++a)
+#pragma unroll
+    for (int b = 0; b < BL; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr * (TT / 2) + a * 16 + (lane & 15);
+        const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+        T val;
+        if (r < arows && c < kb && (!diag || r >= c))
+          val = Lp[(a0 + r) + (int64_t)(c0 + c) * ld] - acc[a][b][v];
+        else
+          val = (diag && r == c && r >= kb) ? T(1) : T(0);
+        Cs[c * kDiagLd + r] = val;
+      }
+  __syncthreads();
+  int32_t* done = col_done + wb + tk.j;
+  if (diag) {
+    diag_factor_inverse<T>(Cs, Ws, rd, Tmp, kb, f + c0, N.fail);
+    for (int t = tid; t < kb * kb; t += kThreads) {
+      const int c = t / kb, r = t - c * kb;
+      if (r >= c) Lp[(c0 + r) + (int64_t)(c0 + c) * ld] = Cs[c * kDiagLd + r];
+    }
+    T* Wout = winv + S.woff[wb + tk.j];  // kb x kb, column-major
+    for (int t = tid; t < kb * kb; t += kThreads) {
+      const int c = t / kb, r = t - c * kb;
+      Wout[t] = Ws[c * kDiagLd + r];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+      set_flag(diag_ready + wb + tk.j, 1);
+      __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  // rows below the diagonal block: X = C W_j^T
+  if (tid == 0) wait_at_least(diag_ready + wb + tk.j, 1, hang);
+  __syncthreads();
+  {
+    const T* Win = winv + S.woff[wb + tk.j];  // Win[c * kb + r] = W[r][c]
+    for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+      const int kk = t / kPanel, c = t - kk * kPanel;
+      Ws[kk * kDiagLd + c] = (kk < kb && c < kb) ? Win[kk * kb + c] : T(0);  // W[c][kk]
+    }
+  }
+  __syncthreads();
+  V4 x[BL][BL];
+#pragma unroll
+  for (int a = 0; a < BL; ++a)
+#pragma unroll
+    for (int b = 0; b < BL; ++b) x[a][b] = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < kPanel / 4; ++ks) {
+    const int kk = ks * 4 + (lane >> 4);
+    T av[BL], bv[BL];
+#pragma unroll
+    for (int a = 0; a < BL; ++a) av[a] = Cs[kk * kDiagLd + wr * (TT / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+    for (int b = 0; b < BL; ++b) bv[b] = Ws[kk * kDiagLd + wc * (TT / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b) x[a][b] = mfma16(bv[b], av[a], x[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < BL; ++a)
+#pragma unroll
+    for (int b = 0; b < BL; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr * (TT / 2) + a * 16 + (lane & 15);
+        const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+        if (r < arows && c < kb) Lp[(a0 + r) + (int64_t)(c0 + c) * ld] = x[a][b][v];
+      }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T>
@@ -1078,6 +1346,16 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
 }
 
 template <typename T>
+void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
+                  int64_t count, int32_t* flow, int64_t nblocks, int level, int nlevels,
+                  hipStream_t st) {
+  if (count <= 0) return;
+  k_front<T><<<(unsigned)count, kThreads, 0, st>>>(S, N, winv, tasks, (int)count, flow,
+                                                   flow + nblocks, flow + 2 * nblocks + level,
+                                                   flow + 2 * nblocks + nlevels);
+}
+
+template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
                  int tile, hipStream_t st) {
   if (count <= 0) return;
@@ -1181,6 +1459,8 @@ void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t 
                                 const T*, hipStream_t);                                          \
   template void launch_gemm<T>(const DevNum<T>&, const GemmProb*, const GemmTile*, int64_t, int,  \
                                hipStream_t);                                                     \
+  template void launch_front<T>(const DevSym&, const DevNum<T>&, T*, const FrontTask*, int64_t,   \
+                                int32_t*, int64_t, int, int, hipStream_t);                       \
   template void launch_permute_in<T>(const DevSym&, const double*, int64_t, T*, int64_t,          \
                                      const double*, hipStream_t);                                \
   template void launch_permute_out<T>(const DevSym&, const T*, double*, int64_t, int64_t,         \

@@ -111,8 +111,10 @@ double front_io(const Symbolic& S, int32_t s) {
 
 }  // namespace
 
-int build_plan(const Symbolic& S, Plan& P, std::string& err) {
+int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
   const int32_t ns = S.ns;
+  P.front_mode = front_mode;
+  static_assert(kPanel == 64, "front task tiling assumes 64-column pivot blocks");
   P.L_off.assign(ns, 0);
   P.U_off.assign(ns, -1);
   P.u_off.assign(ns, 0);
@@ -188,6 +190,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
   }
   P.probs.clear();
   P.tiles.clear();
+  P.ftasks.clear();
   // Problems of one update launch group; tiles are emitted per tile size so
   // that every launch uses a single tile shape.
   std::vector<int32_t> group;
@@ -250,6 +253,34 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err) {
       Step st{kStepAssemble, h, a0, (int64_t)P.asm_items.size()};
       for (int32_t s : big) st.elems += front_io(S, s);
       P.steps.push_back(st);
+    }
+    if (front_mode == 0) {
+      // Dataflow: pivot blocks in column order across the level's fronts,
+      // then the update-matrix tiles.  Every task depends only on tasks
+      // with smaller tickets.
+      Step st{kStepFront, h, (int64_t)P.ftasks.size(), 0};
+      for (int32_t j = 0; j * kPanel < wmax; ++j)
+        for (int32_t s : big) {
+          const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+          if (j * kPanel >= w) continue;
+          const int nt = front_block_tiles(m, w, j);
+          for (int t = 0; t < nt; ++t) P.ftasks.push_back({s, j, t, 0});
+        }
+      for (int32_t s : big) {
+        const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], r = m - w;
+        const int32_t nt = (r + kPanel - 1) / kPanel;
+        for (int32_t j = 0; j < nt; ++j)
+          for (int32_t t = j; t < nt; ++t) P.ftasks.push_back({s, j, t, 1});
+      }
+      st.end = (int64_t)P.ftasks.size();
+      for (int32_t s : big) {
+        const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s], r = m - w;
+        st.flops += front_flops(S, s);
+        // front read once (panel trapezoid + update triangle), written once
+        st.elems += 2.0 * ((w * m - w * (w - 1) / 2) + r * (r + 1) / 2);
+      }
+      P.steps.push_back(st);
+      continue;
     }
     for (int32_t k = 0; k < wmax; k += kPanel) {
       int64_t d0 = (int64_t)P.diag_items.size();

@@ -57,12 +57,22 @@ struct GemmTile {
   int32_t prob, ti, tj, size;  // size: kGemmTile or kGemmTileBig
 };
 
+// Task of the dataflow large-front kernel (one workgroup each, taken in
+// ticket order).  kind 0: pivot block j of front s (columns [64j, 64j+kb)),
+// row tile t: t = 0 is the diagonal block (kb rows), t >= 1 the 64 rows
+// starting at 64j + kb + 64(t-1).  kind 1: tile (t, j) of the update
+// matrix U_s (rows 64t.., columns 64j..), t >= j.
+struct FrontTask {
+  int32_t s, j, t, kind;
+};
+
 enum StepKind : int32_t {
   kStepSmall = 0,
   kStepAssemble = 1,
   kStepDiag = 2,
   kStepPanel = 3,
   kStepGemm = 4,
+  kStepFront = 5,
 };
 
 // One kernel launch: [begin, end) into the matching item array; for
@@ -109,7 +119,9 @@ struct Plan {
   std::vector<PanelItem> panel_items;
   std::vector<GemmProb> probs;
   std::vector<GemmTile> tiles;
+  std::vector<FrontTask> ftasks;  // dataflow large-front tasks, per level in ticket order
   std::vector<Step> steps;
+  int front_mode = 0;             // 0: dataflow large-front kernel, 1: stepwise launches
 
   // solve, per level: factor entries read (sum over fronts of the lower
   // trapezoid of the panel) and front rows touched
@@ -124,6 +136,13 @@ struct Plan {
   int64_t tri_flags = 0;                  // ready flags (one per block)
 };
 
-int build_plan(const Symbolic& S, Plan& P, std::string& err);
+// Rows of pivot block j of a front of order m and width w: the diagonal
+// block plus 64-row tiles below it.
+TACHO_HOST_DEVICE inline int front_block_tiles(int m, int w, int j) {
+  const int c0 = j * 64, kb = (w - c0 < 64) ? (w - c0) : 64;
+  return 1 + (m - c0 - kb + 63) / 64;
+}
+
+int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode = 0);
 
 }  // namespace tacho

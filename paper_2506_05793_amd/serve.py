@@ -86,7 +86,10 @@ class Server:
         self.torch = torch
         self.budget = int(hbm_budget_bytes)
         self.precision = precision
-        self.options = options if options is not None else tacho_default_options()
+        # Level-structure dissection only: on the grid operators of the request
+        # mix it gives fewer flops than the multilevel one and analyses several
+        # times faster, and analysis time is part of a factor request's latency.
+        self.options = options if options is not None else tacho_default_options(ordering=2)
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.pool = cf.ThreadPoolExecutor(max_workers=analysis_workers)
         self.resident: "collections.OrderedDict[int, _Resident]" = collections.OrderedDict()

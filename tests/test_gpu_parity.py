@@ -57,6 +57,7 @@ CASES = [
     ("lap2d_32", lambda: gen.laplace2d(32)),
     ("fv3d_12", lambda: gen.fv3d(12, seed=1)),
     ("fv3d_17x13x11", lambda: gen.fv3d(17, 13, 11, seed=7)),
+    ("fv3d_24", lambda: gen.fv3d(24, seed=8)),
     ("fv2d_45x37", lambda: gen.fv2d(45, 37, seed=3)),
     ("landice_9x8x4", lambda: gen.landice(9, 8, 4, seed=3)),
     ("random_500", lambda: gen.random_spd_pattern(500, 0.01, seed=5)),
@@ -67,10 +68,11 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("front", [0, 1], ids=["dataflow", "stepwise"])
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
-def test_fp64_factor_and_solve_parity(name, make):
+def test_fp64_factor_and_solve_parity(name, make, front):
     A = make()
-    s, a = analyze(A)
+    s, a = analyze(A, front_kernel=front)
     F = oracle.factor(A, a.perm)
     num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
     err = colnorm_error(T.tacho_get_factor(num), F)
@@ -165,9 +167,10 @@ def test_not_spd_reports_first_pivot(seed):
     ("landice_10x9x5", lambda: gen.landice(10, 9, 5, seed=3)),
     ("dense_200", lambda: gen.random_spd_pattern(200, 1.0, seed=3)),
 ])
-def test_fp32_refinement(name, make):
+@pytest.mark.parametrize("front", [0, 1], ids=["dataflow", "stepwise"])
+def test_fp32_refinement(name, make, front):
     A = make()
-    s, a = analyze(A)
+    s, a = analyze(A, front_kernel=front)
     num = T.tacho_factorize(s, A.values, T.TACHO_FP32)
     b = gen.rhs(A.n, 4, seed=2)
     x, info = T.tacho_solve(num, b, with_info=True)
@@ -264,3 +267,44 @@ def test_batch_fp32_refinement_alone_equals_batched():
         assert np.array_equal(x, xb[off:off + m.n]), k
         assert oracle.rel_residual(m, x, rhs[k]).max() <= MIXED_RESID_TOL
         off += m.n
+
+
+def _ill_conditioned_dense(n, cond, seed):
+    """Q diag(lambda) Q^T with lambda log-spaced over [1/cond, 1] (SPD)."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.logspace(0, -np.log10(cond), n)
+    M = (Q * lam) @ Q.T
+    return gen.dense_to_csr((M + M.T) / 2)
+
+
+def _shifted_tridiagonal(n, gap):
+    """1D Laplacian shifted so that its smallest eigenvalue is `gap`."""
+    lam_min = 4 * np.sin(np.pi / (2 * (n + 1))) ** 2
+    M = (np.diag(np.full(n, 2.0 - lam_min + gap)) - np.diag(np.ones(n - 1), 1)
+         - np.diag(np.ones(n - 1), -1))
+    return gen.dense_to_csr(M)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("dense_150_cond1e12", lambda: _ill_conditioned_dense(150, 1e12, seed=1)),
+    ("tridiag_200_gap1e-10", lambda: _shifted_tridiagonal(200, 1e-10)),
+])
+@pytest.mark.parametrize("front", [0, 1], ids=["dataflow", "stepwise"])
+def test_fp32_breakdown_or_stall_falls_back_to_fp64(name, make, front):
+    """FP32 cannot resolve these (kappa * u_fp32 >> 1): the FP32 path must end
+    in the FP64 factorization of the same values, bitwise equal to a direct
+    FP64 factorization and solve."""
+    A = make()
+    s, a = analyze(A, front_kernel=front)
+    b = gen.rhs(A.n, 3, seed=4)
+    num32 = T.tacho_factorize(s, A.values, T.TACHO_FP32)
+    x32, info = T.tacho_solve(num32, b, with_info=True)
+    num64 = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    x64 = T.tacho_solve(num64, b)
+    print(f"{name}: iters={info['iters']} fell_back={info['fell_back']} "
+          f"relres={info['relres_max']:.2e}")
+    assert info["fell_back"] == 1
+    assert np.array_equal(x32, x64)
+    rho = oracle.rel_residual(A, x64, b).max()
+    assert abs(info["relres_max"] - rho) <= 1e-3 * rho + 1e-300

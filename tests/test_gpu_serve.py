@@ -53,7 +53,7 @@ def test_serving_mix_equals_alone():
     for out in res:
         r = by_id[out.rid]
         A = r.matrix if r.kind == "factor" else mats[r.target]
-        s = T.tacho_analyze(A.n, A.rowptr, A.colind)
+        s = T.tacho_analyze(A.n, A.rowptr, A.colind, srv.options)
         num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
         alone = T.tacho_solve(num, r.rhs)
         assert np.array_equal(alone, out.x), out.rid
