@@ -91,7 +91,7 @@ struct tacho_sym {
   int device = -1;
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
       d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
-      d_wbase, d_woff, d_gather;
+      d_wbase, d_woff, d_tbase, d_gather;
   DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fwd_items,
       d_bwd_items, d_tri_fwd, d_tri_bwd;
   DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
@@ -274,6 +274,7 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_diag_q, P.diag_q));
   HIP_TRY(upload(h->d_wbase, P.wbase));
   HIP_TRY(upload(h->d_woff, P.woff));
+  HIP_TRY(upload(h->d_tbase, P.tbase));
   HIP_TRY(upload(h->d_gather, P.gather_list));
   HIP_TRY(upload(h->d_small, P.small_list));
   HIP_TRY(upload(h->d_asm, P.asm_items));
@@ -313,6 +314,7 @@ int ensure_uploaded(tacho_sym* h) {
   v.diag_q = h->d_diag_q.as<int32_t>();
   v.wbase = h->d_wbase.as<int32_t>();
   v.woff = h->d_woff.as<int64_t>();
+  v.tbase = h->d_tbase.as<int32_t>();
   h->device = dev;
   h->uploaded = true;
   return TACHO_OK;
@@ -322,11 +324,10 @@ size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
 
 // Device bytes a numeric handle needs (factor, update workspace, values,
 // solve workspace for kRhs columns).
-// Dataflow factorization: per pivot block a counter and a ready flag, one
-// ticket counter per level, one hang flag.
-int64_t flow_ints(const tacho_sym* h) {
-  return 2 * (int64_t)h->P.woff.size() + h->S.nlevels + 1;
-}
+// Dataflow factorization: one completion flag per row tile, one ticket
+// counter per level, one hang flag.
+int64_t flow_ntiles(const tacho_sym* h) { return h->P.tbase.empty() ? 0 : h->P.tbase.back(); }
+int64_t flow_ints(const tacho_sym* h) { return flow_ntiles(h) + h->S.nlevels + 1; }
 
 int64_t numeric_bytes(const tacho_sym* h, int precision) {
   const size_t es = elem_size(precision);
@@ -378,7 +379,7 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
   const GemmProb* probs = h->d_probs.as<GemmProb>();
   const GemmTile* tiles = h->d_tiles.as<GemmTile>();
   const FrontTask* ftasks = h->d_ftasks.as<FrontTask>();
-  const int64_t nblk = (int64_t)P.woff.size();
+  const int64_t ntiles = flow_ntiles(h);
   for (const Step& s : P.steps) {
     const int64_t cnt = s.end - s.begin;
     const int pe = f->prof.begin(st);
@@ -389,7 +390,7 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
       case kStepPanel: launch_panel<T>(S, N, pan + s.begin, cnt, f->winv.as<T>(), st); break;
       case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, s.tile, st); break;
       case kStepFront:
-        launch_front<T>(S, N, f->winv.as<T>(), ftasks + s.begin, cnt, f->flow.as<int32_t>(), nblk,
+        launch_front<T>(S, N, f->winv.as<T>(), ftasks + s.begin, cnt, f->flow.as<int32_t>(), ntiles,
                         s.level, (int)h->S.nlevels, st);
         break;
     }

@@ -32,6 +32,7 @@ struct DevSym {
   const int32_t* diag_q;     // per permuted column: A entry of the diagonal or -1
   const int32_t* wbase;      // per supernode: first diagonal-inverse block (-1: none)
   const int64_t* woff;       // per diagonal-inverse block: element offset
+  const int32_t* tbase;      // per pivot block: first row-tile completion flag
 };
 
 template <typename T>
@@ -66,13 +67,13 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
                  int tile, hipStream_t st);
-// Dataflow factorization of one level's large fronts.  flow holds, for the
-// nblocks pivot blocks of all large fronts, the finished-row-tile counters,
-// then the diagonal-block ready flags, then one ticket counter per level and
-// the hang flag; all zero before the factorization starts.
+// Dataflow factorization of one level's large fronts.  flow holds one
+// completion flag per row tile of every pivot block (ntiles, indexed through
+// DevSym::tbase), then one ticket counter per level and the hang flag; all
+// zero before the factorization starts.
 template <typename T>
 void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
-                  int64_t count, int32_t* flow, int64_t nblocks, int level, int nlevels,
+                  int64_t count, int32_t* flow, int64_t ntiles, int level, int nlevels,
                   hipStream_t st);
 
 // Solves: y is the permuted right-hand side / solution (n x nrhs, ld n).

@@ -235,31 +235,56 @@ __global__ __launch_bounds__(kThreads) void k_assemble(DevSym S, DevNum<T> N,
 // solve phase.  Non-positive or NaN pivots go to the failure flag.
 constexpr int kSub = 16;
 
+// 16x16x16 product on the matrix cores: acc += A B, with lane l supplying
+// A(l % 16, k) and B(k, l % 16) for k = l / 16 + 4 s through the accessors.
+template <typename T, typename FA, typename FB>
+__device__ inline typename Vec4<T>::type mm16(FA a, FB b, typename Vec4<T>::type acc) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = mfma16(a(i, 4 * s + kq), b(4 * s + kq, i), acc);
+  return acc;
+}
+
 // Cholesky of the kb x kb diagonal block held in D (column-major, ld
 // kDiagLd, entries past kb set to the identity), in place, and its inverse W
-// = L^{-1} (same layout, computed by 16x16 blocks).  rd receives the
-// reciprocal pivots.  A non-positive or NaN pivot j records col0 + j in
-// *fail.  Every thread of the workgroup takes part.
+// = L^{-1} (same layout).  Blocked by 16 columns up to kb rounded to 16:
+// per block, one wave factors the 16x16 diagonal block in registers (rows
+// in lanes, pivots and column entries broadcast with readlane) and inverts
+// it (one lane per column); the rows below are solved as a product with
+// that inverse and the trailing lower triangle is updated, both on the
+// matrix cores.  The off-diagonal blocks of W follow by distance from the
+// diagonal: W_ib = -W_ii sum_{q=b}^{i-1} L_iq W_qb.  A non-positive or NaN
+// pivot j records col0 + j in *fail.  Every thread of the workgroup takes
+// part; Tmp holds 3 x 256 scratch elements.
 template <typename T>
-__device__ void diag_factor_inverse(T* D, T* W, T* rd, T (*Tmp)[kSub * kSub], int kb, int col0,
+__device__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * kSub], int kb, int col0,
                                     int32_t* fail) {
+  typedef typename Vec4<T>::type V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // blocks past kb hold the identity padding: only [0, kr) is worked on
   const int kr = (kb + kSub - 1) / kSub * kSub;
+  const int nb = kr / kSub;
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    W[c * kDiagLd + r] = (r == c && r >= kr) ? T(1) : T(0);
+  }
+  __syncthreads();
   for (int jb = 0; jb < kr; jb += kSub) {
-    // (1) 16x16 diagonal block in registers: lane i < 16 holds row jb + i;
-    // pivots and column entries are broadcast with readlane.
+    // (1) 16x16 diagonal block: Cholesky and inverse, lanes 0..15 of wave 0
+    // (lane i holds row i of L in a[] and, afterwards, row i of W in x[])
     if (wave == 0 && lane < kSub) {
       T a[kSub];
 #pragma unroll
       for (int c = 0; c < kSub; ++c) a[c] = D[(jb + c) * kDiagLd + jb + lane];
+      T myinv = T(0);
+      uint32_t bad = 0;  // pivots that are not positive (or NaN), bit j
 #pragma unroll
       for (int j = 0; j < kSub; ++j) {
         const T piv = readlane(a[j], j);
-        if (lane == 0 && jb + j < kb && !(piv > T(0))) atomicMin(fail, col0 + jb + j);
+        bad |= (piv > T(0)) ? 0u : (1u << j);
         const T ljj = sqrt(piv);
         const T rinv = T(1) / ljj;
-        if (lane == 0) rd[jb + j] = rinv;
+        if (lane == j) myinv = rinv;
         a[j] = lane == j ? ljj : (lane > j ? a[j] * rinv : a[j]);
 #pragma unroll
         for (int c = j + 1; c < kSub; ++c) {
@@ -267,78 +292,82 @@ __device__ void diag_factor_inverse(T* D, T* W, T* rd, T (*Tmp)[kSub * kSub], in
           if (lane >= c) a[c] -= a[j] * lcj;
         }
       }
+      if (kb - jb < kSub) bad &= (1u << (kb - jb)) - 1u;  // identity padding past kb
+      if (lane == 0 && bad != 0) atomicMin(fail, col0 + jb + __builtin_ctz(bad));
 #pragma unroll
       for (int c = 0; c < kSub; ++c)
         if (c <= lane) D[(jb + c) * kDiagLd + jb + lane] = a[c];
-    }
-    __syncthreads();
-    // (2) rows below the block: one thread per row, forward substitution
-    const int below = kr - jb - kSub;
-    if (tid < below) {
-      const int r = jb + kSub + tid;
+      // W = L^{-1} by rows: row q is final once rows < q are subtracted;
+      // it is scaled by 1 / L_qq and subtracted from the rows below.
       T x[kSub];
 #pragma unroll
-      for (int c = 0; c < kSub; ++c) x[c] = D[(jb + c) * kDiagLd + r];
+      for (int k = 0; k < kSub; ++k) x[k] = lane == k ? T(1) : T(0);
 #pragma unroll
-      for (int c = 0; c < kSub; ++c) {
-        T acc = x[c];
+      for (int q = 0; q < kSub; ++q) {
+        if (lane == q) {
 #pragma unroll
-        for (int c2 = 0; c2 < c; ++c2) acc -= x[c2] * D[(jb + c2) * kDiagLd + jb + c];
-        x[c] = acc * rd[jb + c];
+          for (int k = 0; k <= q; ++k) x[k] *= myinv;
+        }
+#pragma unroll
+        for (int k = 0; k <= q; ++k) {
+          const T wqk = readlane(x[k], q);
+          if (lane > q) x[k] -= a[q] * wqk;
+        }
       }
 #pragma unroll
-      for (int c = 0; c < kSub; ++c) D[(jb + c) * kDiagLd + r] = x[c];
+      for (int k = 0; k < kSub; ++k) W[(jb + k) * kDiagLd + jb + lane] = x[k];
     }
     __syncthreads();
-    // (3) rank-16 update of the trailing lower triangle
-    for (int t = tid; t < below * below; t += kThreads) {
-      const int cc = t / below, rr = t - cc * below;
-      if (rr >= cc) {
-        const int r = jb + kSub + rr, c = jb + kSub + cc;
-        T acc = D[c * kDiagLd + r];
+    const int below = (kr - jb - kSub) / kSub;  // 16-row blocks below
+    // (2) rows below: X = B W_bb^T, one wave per 16-row block
+    if (wave < below) {
+      const int r0 = jb + kSub + wave * kSub;
+      V4 acc = V4{0, 0, 0, 0};
+      acc = mm16<T>([&](int m, int k) { return D[(jb + k) * kDiagLd + r0 + m]; },
+                    [&](int k, int n) { return W[(jb + k) * kDiagLd + jb + n]; }, acc);
+      // acc holds X(r0 + mfma_row, jb + lane % 16); W_bb^T(k, n) = W_bb(n, k)
 #pragma unroll
-        for (int q = 0; q < kSub; ++q) acc -= D[(jb + q) * kDiagLd + r] * D[(jb + q) * kDiagLd + c];
-        D[c * kDiagLd + r] = acc;
+      for (int v = 0; v < 4; ++v) D[(jb + (lane & 15)) * kDiagLd + r0 + mfma_row<T>(lane, v)] = acc[v];
+    }
+    __syncthreads();
+    // (3) trailing lower triangle: D_ij -= X_i X_j^T over 16x16 blocks i >= j
+    for (int q = wave; q < below * (below + 1) / 2; q += kThreads / 64) {
+      int bi = 0;
+      while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
+      const int bj = q - bi * (bi + 1) / 2;
+      const int ri = jb + kSub + bi * kSub, rj = jb + kSub + bj * kSub;
+      V4 acc = V4{0, 0, 0, 0};
+      acc = mm16<T>([&](int m, int k) { return D[(jb + k) * kDiagLd + ri + m]; },
+                    [&](int k, int n) { return D[(jb + k) * kDiagLd + rj + n]; }, acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        T* p = D + (rj + (lane & 15)) * kDiagLd + ri + mfma_row<T>(lane, v);
+        *p -= acc[v];
       }
     }
     __syncthreads();
   }
-  // W = L^{-1} by 16x16 blocks.  Diagonal blocks first (one thread per
-  // column of each block, forward substitution down its own column), then
-  // the off-diagonal blocks by distance d = 1..3 from the diagonal:
-  // W_ib = -W_ii * sum_{q=b}^{i-1} L_iq W_qb.
-  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
-    const int c = t / kPanel, r = t - c * kPanel;
-    W[c * kDiagLd + r] = (r == c && r >= kr) ? T(1) : T(0);
-  }
-  __syncthreads();
-  if (tid < kr) {
-    const int col = tid, b0 = (col / kSub) * kSub;
-    for (int r = col; r < b0 + kSub; ++r) {
-      T acc = r == col ? T(1) : T(0);
-      for (int q = col; q < r; ++q) acc -= D[q * kDiagLd + r] * W[col * kDiagLd + q];
-      W[col * kDiagLd + r] = acc * rd[r];
-    }
-  }
-  __syncthreads();
-  for (int d = 1; d < kr / kSub; ++d) {
-    const int nblk = kr / kSub - d;  // blocks (b + d, b), b < nblk
-    for (int t = tid; t < nblk * kSub * kSub; t += kThreads) {
-      const int bb = t / (kSub * kSub), e = t - bb * kSub * kSub;
-      const int rr = e % kSub, cc = e / kSub;
-      const int i0 = (bb + d) * kSub, c = bb * kSub + cc;
-      T acc = T(0);
-      for (int q = bb * kSub; q < i0; ++q) acc += D[q * kDiagLd + i0 + rr] * W[c * kDiagLd + q];
-      Tmp[bb][rr + cc * kSub] = acc;
+  // off-diagonal blocks of W, by distance d from the diagonal
+  for (int d = 1; d < nb; ++d) {
+    const int b = wave, i = wave + d;
+    const bool act = b + d < nb;
+    if (act) {
+      V4 acc = V4{0, 0, 0, 0};
+      for (int q = b; q < i; ++q)
+        acc = mm16<T>([&](int m, int k) { return D[(kSub * q + k) * kDiagLd + kSub * i + m]; },
+                      [&](int k, int n) { return W[(kSub * b + n) * kDiagLd + kSub * q + k]; },
+                      acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tmp[wave][mfma_row<T>(lane, v) * kSub + (lane & 15)] = acc[v];
     }
     __syncthreads();
-    for (int t = tid; t < nblk * kSub * kSub; t += kThreads) {
-      const int bb = t / (kSub * kSub), e = t - bb * kSub * kSub;
-      const int rr = e % kSub, cc = e / kSub;
-      const int i0 = (bb + d) * kSub, c = bb * kSub + cc;
-      T acc = T(0);
-      for (int q = 0; q < kSub; ++q) acc += W[(i0 + q) * kDiagLd + i0 + rr] * Tmp[bb][q + cc * kSub];
-      W[c * kDiagLd + i0 + rr] = -acc;
+    if (act) {
+      V4 acc = V4{0, 0, 0, 0};
+      acc = mm16<T>([&](int m, int k) { return W[(kSub * i + k) * kDiagLd + kSub * i + m]; },
+                    [&](int k, int n) { return Tmp[wave][k * kSub + n]; }, acc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        W[(kSub * b + (lane & 15)) * kDiagLd + kSub * i + mfma_row<T>(lane, v)] = -acc[v];
     }
     __syncthreads();
   }
@@ -347,11 +376,10 @@ __device__ void diag_factor_inverse(T* D, T* W, T* rd, T (*Tmp)[kSub * kSub], in
 // Large fronts, panel step 1 (stepwise path): Cholesky of the diagonal
 // block [k, k+kb) of front s and its inverse, kept for the solves.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const PanelItem* items,
+__global__ __launch_bounds__(kThreads, 2) void k_diag(DevSym S, DevNum<T> N, const PanelItem* items,
                                                    T* winv) {
   __shared__ T D[kPanel * kDiagLd];  // column-major, D[c * kDiagLd + r]
   __shared__ T W[kPanel * kDiagLd];
-  __shared__ T rd[kPanel];           // 1 / L_jj
   __shared__ T Tmp[3][kSub * kSub];
   const PanelItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
@@ -368,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void k_diag(DevSym S, DevNum<T> N, const 
     D[c * kDiagLd + r] = v;
   }
   __syncthreads();
-  diag_factor_inverse<T>(D, W, rd, Tmp, kb, f + k, N.fail);
+  diag_factor_inverse<T>(D, W, Tmp, kb, f + k, N.fail);
   for (int t = tid; t < kb * kb; t += kThreads) {
     const int c = t / kb, r = t - c * kb;
     if (r >= c) Lp[(k + r) + (int64_t)(k + c) * ld] = D[c * kDiagLd + r];
@@ -620,22 +648,24 @@ __device__ inline void wait_at_least(const int32_t* flag, int32_t value, int32_t
 // and inverse W_j, published through a ready flag) or solves its rows
 // against it (X = C W_j^T on the matrix cores).  Update-matrix tiles
 // accumulate over all pivot blocks of their front, each as soon as it is
-// complete, and subtract the sum from the assembled U.  A per-block counter
-// of finished row tiles tells a consumer that a pivot block is complete.
+// complete, and subtract the sum from the assembled U.  Every row tile has a
+// completion flag; a consumer of rows [r0, r1) of pivot block p waits for
+// the (at most three) tiles of p that hold them, so the next diagonal block
+// waits only for the one tile that holds its rows, not for a whole column.
 //
 // Workgroups take tasks from a ticket counter in the plan's order, in which
 // every task depends only on tasks with smaller tickets; those belong to
 // workgroups that already run, so the waits end (and are bounded anyway).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_front(DevSym S, DevNum<T> N, T* winv,
+__global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T* winv,
                                                     const FrontTask* tasks, int count,
-                                                    int32_t* col_done, int32_t* diag_ready,
-                                                    int32_t* counter, int32_t* hang) {
+                                                    int32_t* tile_done, int32_t* counter,
+                                                    int32_t* hang) {
   constexpr int TT = kPanel, KT = 16, PAD = 4, BL = 2;
   constexpr int LPT = TT * KT / kThreads;  // staged elements per thread and operand
   constexpr int RSTEP = kThreads / TT;     // k rows covered per load round
   constexpr int STAGE = 2 * KT * (TT + PAD);
-  constexpr int POST = 2 * kPanel * kDiagLd + 3 * kSub * kSub + kPanel;
+  constexpr int POST = 2 * kPanel * kDiagLd + 3 * kSub * kSub;
   constexpr int LDS = POST > 2 * STAGE ? POST : 2 * STAGE;
   __shared__ T lds[LDS];
   __shared__ int s_ticket;
@@ -683,12 +713,17 @@ __global__ __launch_bounds__(kThreads) void k_front(DevSym S, DevNum<T> N, T* wi
     const T* pa = Lp + a0 + lrow;
     const T* pb = Lp + b0 + lrow;
     T ra[LPT], rb[LPT];
-    int ready = 0;  // pivot blocks [0, ready) known complete
+    // wait for the row tiles of pivot block p holding rows [r0, r0 + nr)
+    auto wait_rows = [&](int p, int r0, int nr) {
+      const int32_t* fl = tile_done + S.tbase[wb + p];
+      const int t1 = front_row_tile(w, p, r0 + nr - 1);
+      for (int t = front_row_tile(w, p, r0); t <= t1; ++t) wait_at_least(fl + t, 1, hang);
+    };
     auto load_stage = [&](int k0) {
-      if (k0 % TT == 0 && k0 / TT >= ready) {
+      if (k0 % TT == 0) {
         const int p = k0 / TT;
-        wait_at_least(col_done + wb + p, front_block_tiles(m, w, p), hang);
-        ready = p + 1;
+        wait_rows(p, a0, arows);
+        wait_rows(p, b0, bcols);
       }
 #pragma unroll
       for (int u = 0; u < LPT; ++u) {
@@ -756,7 +791,6 @@ __global__ __launch_bounds__(kThreads) void k_front(DevSym S, DevNum<T> N, T* wi
   T* Cs = lds;
   T* Ws = lds + kPanel * kDiagLd;
   T(*Tmp)[kSub * kSub] = reinterpret_cast<T(*)[kSub * kSub]>(lds + 2 * kPanel * kDiagLd);
-  T* rd = lds + 2 * kPanel * kDiagLd + 3 * kSub * kSub;
   const bool diag = tk.t == 0;
 #pragma unroll
   for (int a = 0; a < BL; ++a)
@@ -774,9 +808,9 @@ __global__ __launch_bounds__(kThreads) void k_front(DevSym S, DevNum<T> N, T* wi
         Cs[c * kDiagLd + r] = val;
       }
   __syncthreads();
-  int32_t* done = col_done + wb + tk.j;
+  int32_t* done = tile_done + S.tbase[wb + tk.j];  // flags of pivot block j's row tiles
   if (diag) {
-    diag_factor_inverse<T>(Cs, Ws, rd, Tmp, kb, f + c0, N.fail);
+    diag_factor_inverse<T>(Cs, Ws, Tmp, kb, f + c0, N.fail);
     for (int t = tid; t < kb * kb; t += kThreads) {
       const int c = t / kb, r = t - c * kb;
       if (r >= c) Lp[(c0 + r) + (int64_t)(c0 + c) * ld] = Cs[c * kDiagLd + r];
@@ -788,14 +822,11 @@ __global__ __launch_bounds__(kThreads) void k_front(DevSym S, DevNum<T> N, T* wi
     }
     __threadfence();
     __syncthreads();
-    if (tid == 0) {
-      set_flag(diag_ready + wb + tk.j, 1);
-      __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (tid == 0) set_flag(done, 1);
     return;
   }
   // rows below the diagonal block: X = C W_j^T
-  if (tid == 0) wait_at_least(diag_ready + wb + tk.j, 1, hang);
+  if (tid == 0) wait_at_least(done, 1, hang);
   __syncthreads();
   {
     const T* Win = winv + S.woff[wb + tk.j];  // Win[c * kb + r] = W[r][c]
@@ -835,7 +866,7 @@ __global__ __launch_bounds__(kThreads) void k_front(DevSym S, DevNum<T> N, T* wi
       }
   __threadfence();
   __syncthreads();
-  if (tid == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0) set_flag(done + tk.t, 1);
 }
 
 template <typename T>
@@ -1347,12 +1378,11 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
 
 template <typename T>
 void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
-                  int64_t count, int32_t* flow, int64_t nblocks, int level, int nlevels,
+                  int64_t count, int32_t* flow, int64_t ntiles, int level, int nlevels,
                   hipStream_t st) {
   if (count <= 0) return;
   k_front<T><<<(unsigned)count, kThreads, 0, st>>>(S, N, winv, tasks, (int)count, flow,
-                                                   flow + nblocks, flow + 2 * nblocks + level,
-                                                   flow + 2 * nblocks + nlevels);
+                                                   flow + ntiles + level, flow + ntiles + nlevels);
 }
 
 template <typename T>

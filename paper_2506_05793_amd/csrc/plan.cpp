@@ -178,14 +178,21 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
   P.wbase.assign(ns, -1);
   P.woff.clear();
   P.W_elems = 0;
+  P.tbase.assign(1, 0);
   for (int32_t s = 0; s < ns; ++s) {
     if (S.front_m[s] <= kSmallMax) continue;
-    const int32_t w = S.sptr[s + 1] - S.sptr[s];
+    const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
     P.wbase[s] = (int32_t)P.woff.size();
     for (int32_t k = 0; k < w; k += kPanel) {
       const int64_t kb = std::min(kPanel, w - k);
       P.woff.push_back(P.W_elems);
       P.W_elems += kb * kb;
+      const int64_t next = (int64_t)P.tbase.back() + front_block_tiles(m, w, k / kPanel);
+      if (next > INT32_MAX) {
+        err = "too many factorization tiles";
+        return kInvalid;
+      }
+      P.tbase.push_back((int32_t)next);
     }
   }
   P.probs.clear();

@@ -109,6 +109,9 @@ struct Plan {
   std::vector<int32_t> wbase;
   std::vector<int64_t> woff;
   int64_t W_elems = 0;
+  // dataflow factorization: per pivot block the index of its first row tile's
+  // completion flag (prefix sums of front_block_tiles; one entry past the end)
+  std::vector<int32_t> tbase;
   std::vector<int32_t> a_pos;   // per A entry: row + col*ldL inside the front panel
   std::vector<int32_t> diag_q;  // per permuted column: A entry of the diagonal (-1: absent)
 
@@ -141,6 +144,12 @@ struct Plan {
 TACHO_HOST_DEVICE inline int front_block_tiles(int m, int w, int j) {
   const int c0 = j * 64, kb = (w - c0 < 64) ? (w - c0) : 64;
   return 1 + (m - c0 - kb + 63) / 64;
+}
+
+// Row tile of pivot block j that holds front row r (r >= 64 j).
+TACHO_HOST_DEVICE inline int front_row_tile(int w, int j, int r) {
+  const int c0 = j * 64, kb = (w - c0 < 64) ? (w - c0) : 64;
+  return r < c0 + kb ? 0 : 1 + (r - c0 - kb) / 64;
 }
 
 int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode = 0);
