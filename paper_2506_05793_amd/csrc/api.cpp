@@ -93,7 +93,7 @@ struct tacho_sym {
       d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
       d_wbase, d_woff, d_tbase, d_gather;
   DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fwd_items,
-      d_bwd_items, d_tri_fwd, d_tri_bwd;
+      d_bwd_items, d_fwd_red, d_bwd_red, d_tri_fwd, d_tri_bwd;
   DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
   DevSym view{};
   std::mutex mu;
@@ -164,6 +164,7 @@ struct tacho_num {
   int precision = TACHO_FP64;
   DBuf L, U, avals, vals, fullvals, scale, fail, winv;
   DBuf y, uvec;             // solve workspace (kRhs columns)
+  DBuf part;                // partial L21 products of the split solves
   DBuf sync;                // solve tickets (2 per level) and block ready flags
   DBuf flow;                // dataflow factorization counters, flags, tickets, hang flag
   DBuf bdev, xdev, r, dx, norms;  // host-pointer staging and refinement buffers
@@ -286,6 +287,8 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_levels, S.level_list));
   HIP_TRY(upload(h->d_fwd_items, P.fwd_items));
   HIP_TRY(upload(h->d_bwd_items, P.bwd_items));
+  HIP_TRY(upload(h->d_fwd_red, P.fwd_red));
+  HIP_TRY(upload(h->d_bwd_red, P.bwd_red));
   HIP_TRY(upload(h->d_tri_fwd, P.tri_fwd));
   HIP_TRY(upload(h->d_tri_bwd, P.tri_bwd));
   HIP_TRY(upload(h->d_rowptr, S.A.rowptr));
@@ -337,6 +340,7 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += (int64_t)es * P.L_elems + (int64_t)es * P.U_elems + (int64_t)es * (int64_t)S.a_src.size();
   b += 8 * S.nnz_input + 4;
   b += (int64_t)es * (S.n + P.u_elems) * kRhs;
+  b += (int64_t)es * std::max<int64_t>(P.part_slots, 1) * kPanel * kRhs;
   b += (int64_t)es * P.W_elems;
   b += 4 * (2 * S.nlevels + P.tri_flags + 1);
   b += 4 * flow_ints(h);
@@ -534,6 +538,7 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   HIP_TRY(f->winv.alloc(es * std::max<int64_t>(P.W_elems, 1)));
   HIP_TRY(f->y.alloc(es * S.n * kRhs));
   HIP_TRY(f->uvec.alloc(es * P.u_elems * kRhs));
+  HIP_TRY(f->part.alloc(es * std::max<int64_t>(P.part_slots, 1) * kPanel * kRhs));
   HIP_TRY(f->sync.alloc(sizeof(int32_t) * (2 * S.nlevels + P.tri_flags + 1)));
   HIP_TRY(f->flow.alloc(sizeof(int32_t) * flow_ints(h)));
   if (precision == TACHO_FP32) {
@@ -575,8 +580,11 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   int pe = f->prof.begin(st);
   launch_permute_in<T>(V, b, ldb, y, nrhs, scale, st);
   f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * nrhs * (8.0 + es) + 4.0 * S.n);
-  const SolveItem* fwi = h->d_fwd_items.as<SolveItem>();
-  const SolveItem* bwi = h->d_bwd_items.as<SolveItem>();
+  const GemvItem* fwi = h->d_fwd_items.as<GemvItem>();
+  const GemvItem* bwi = h->d_bwd_items.as<GemvItem>();
+  const ReduceItem* fri = h->d_fwd_red.as<ReduceItem>();
+  const ReduceItem* bri = h->d_bwd_red.as<ReduceItem>();
+  T* part = f->part.as<T>();
   const TriItem* tfw = h->d_tri_fwd.as<TriItem>();
   const TriItem* tbw = h->d_tri_bwd.as<TriItem>();
   int32_t* counters = f->sync.as<int32_t>();
@@ -589,8 +597,8 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
                   nrhs, st);
     launch_fwd_tri<T>(V, L, f->winv.as<T>(), y, tfw + t0, t1 - t0, counters + 2 * lvl, flags,
                       nrhs, st);
-    launch_fwd_gemv<T>(V, L, y, uv, fwi + P.fwd_ptr[lvl], P.fwd_ptr[lvl + 1] - P.fwd_ptr[lvl],
-                       nrhs, st);
+    launch_fwd_gemv<T>(V, L, y, part, fwi + P.fwd_ptr[lvl], P.fwd_ptr[lvl + 1] - P.fwd_ptr[lvl],
+                       fri + P.fred_ptr[lvl], P.fred_ptr[lvl + 1] - P.fred_ptr[lvl], uv, nrhs, st);
     f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * P.level_lentries[lvl] * nrhs,
                 es * (P.level_lentries[lvl] + 2.0 * P.level_rows[lvl] * nrhs));
   }
@@ -599,8 +607,8 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
     pe = f->prof.begin(st);
     launch_bwd_gather<T>(V, y, uv, h->d_gather.as<int32_t>() + P.gather_ptr[lvl],
                          P.gather_ptr[lvl + 1] - P.gather_ptr[lvl], nrhs, st);
-    launch_bwd_gemv<T>(V, L, y, uv, bwi + P.bwd_ptr[lvl], P.bwd_ptr[lvl + 1] - P.bwd_ptr[lvl],
-                       nrhs, st);
+    launch_bwd_gemv<T>(V, L, uv, part, bwi + P.bwd_ptr[lvl], P.bwd_ptr[lvl + 1] - P.bwd_ptr[lvl],
+                       bri + P.bred_ptr[lvl], P.bred_ptr[lvl + 1] - P.bred_ptr[lvl], y, nrhs, st);
     launch_bwd_tri<T>(V, L, f->winv.as<T>(), y, tbw + t0, t1 - t0, counters + 2 * lvl + 1, flags,
                       nrhs, st);
     launch_bwd<T>(V, L, y, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl], nrhs,

@@ -90,12 +90,16 @@ template <typename T>
 void launch_bwd(const DevSym& S, const T* L, T* y, const int32_t* list, int64_t count,
                 int32_t nrhs, hipStream_t st);
 
+// L21 products of split fronts (matrix-core tiles into `part`, then a
+// fixed-order reduction): forward uvec -= L21 x_s, backward y_s -= L21^T u_s.
 template <typename T>
-void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* uvec, const SolveItem* items,
-                     int64_t count, int32_t nrhs, hipStream_t st);
+void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* part, const GemvItem* items,
+                     int64_t count, const ReduceItem* red, int64_t nred, T* uvec, int32_t nrhs,
+                     hipStream_t st);
 template <typename T>
-void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const T* uvec, const SolveItem* items,
-                     int64_t count, int32_t nrhs, hipStream_t st);
+void launch_bwd_gemv(const DevSym& S, const T* L, const T* uvec, T* part, const GemvItem* items,
+                     int64_t count, const ReduceItem* red, int64_t nred, T* y, int32_t nrhs,
+                     hipStream_t st);
 template <typename T>
 void launch_bwd_gather(const DevSym& S, const T* y, T* uvec, const int32_t* list, int64_t count,
                        int32_t nrhs, hipStream_t st);

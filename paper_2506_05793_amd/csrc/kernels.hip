@@ -258,8 +258,8 @@ __device__ inline typename Vec4<T>::type mm16(FA a, FB b, typename Vec4<T>::type
 // pivot j records col0 + j in *fail.  Every thread of the workgroup takes
 // part; Tmp holds 3 x 256 scratch elements.
 template <typename T>
-__device__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * kSub], int kb, int col0,
-                                    int32_t* fail) {
+__device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * kSub], int kb,
+                                                    int col0, int32_t* fail) {
   typedef typename Vec4<T>::type V4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kr = (kb + kSub - 1) / kSub * kSub;
@@ -667,6 +667,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   constexpr int STAGE = 2 * KT * (TT + PAD);
   constexpr int POST = 2 * kPanel * kDiagLd + 3 * kSub * kSub;
   constexpr int LDS = POST > 2 * STAGE ? POST : 2 * STAGE;
+  typedef typename Vec4<T>::type V4;
   __shared__ T lds[LDS];
   __shared__ int s_ticket;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -681,9 +682,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   const int wb = S.wbase[s];
   T* Lp = N.L + S.L_off[s];
   const bool utile = tk.kind != 0;
+  const bool diag = !utile && tk.t == 0;
   const int c0 = tk.j * TT;
   const int kb = utile ? TT : min(TT, w - c0);
-  // output rows [a0, a0 + arows) x columns (operand rows) [b0, b0 + bcols)
+  // Output rows [a0, a0 + arows) against operand rows [b0, b0 + bcols); a
+  // diagonal task also produces row tile 1 (rows [c0 + kb, ...)) when it
+  // exists, so the next diagonal block does not wait for another workgroup.
   int a0, arows, b0, bcols, K;
   if (utile) {
     a0 = w + tk.t * TT;
@@ -692,19 +696,26 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     bcols = min(TT, m - b0);
     K = w;
   } else {
-    a0 = tk.t == 0 ? c0 : c0 + kb + (tk.t - 1) * TT;
-    arows = tk.t == 0 ? kb : min(TT, m - a0);
     b0 = c0;
     bcols = kb;
     K = c0;
+    if (diag) {
+      a0 = c0 + kb;  // row tile 1 (empty when the front ends here)
+      arows = min(TT, m - a0);
+    } else {
+      a0 = c0 + kb + (tk.t - 1) * TT;
+      arows = min(TT, m - a0);
+    }
   }
+  const bool fuse1 = diag && arows > 0;
 
-  typedef typename Vec4<T>::type V4;
-  V4 acc[BL][BL];
+  // acc = X Y^T over the completed pivot blocks (X: rows a0.., Y: rows b0..);
+  // a diagonal task accumulates Y Y^T in dacc as well.
+  V4 acc[BL][BL], dacc[BL][BL];
 #pragma unroll
   for (int a = 0; a < BL; ++a)
 #pragma unroll
-    for (int b = 0; b < BL; ++b) acc[a][b] = V4{0, 0, 0, 0};
+    for (int b = 0; b < BL; ++b) acc[a][b] = dacc[a][b] = V4{0, 0, 0, 0};
   {
     T* As = lds;          // [2][KT][TT + PAD]
     T* Bs = lds + STAGE;  // [2][KT][TT + PAD]
@@ -722,7 +733,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     auto load_stage = [&](int k0) {
       if (k0 % TT == 0) {
         const int p = k0 / TT;
-        wait_rows(p, a0, arows);
+        if (arows > 0) wait_rows(p, a0, arows);
         wait_rows(p, b0, bcols);
       }
 #pragma unroll
@@ -752,15 +763,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
       for (int ks = 0; ks < KT / 4; ++ks) {
         const int kr = buf * KT + ks * 4 + (lane >> 4);
-        T av[BL], bv[BL];
+        T av[BL], bv[BL], yv[BL];
 #pragma unroll
         for (int a = 0; a < BL; ++a) av[a] = As[kr * (TT + PAD) + wr * (TT / 2) + a * 16 + (lane & 15)];
 #pragma unroll
         for (int b = 0; b < BL; ++b) bv[b] = Bs[kr * (TT + PAD) + wc * (TT / 2) + b * 16 + (lane & 15)];
+        if (!diag || fuse1) {
 #pragma unroll
-        for (int a = 0; a < BL; ++a)
+          for (int a = 0; a < BL; ++a)
 #pragma unroll
-          for (int b = 0; b < BL; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+            for (int b = 0; b < BL; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+        }
+        if (diag) {
+#pragma unroll
+          for (int a = 0; a < BL; ++a) yv[a] = Bs[kr * (TT + PAD) + wr * (TT / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+          for (int a = 0; a < BL; ++a)
+#pragma unroll
+            for (int b = 0; b < BL; ++b) dacc[a][b] = mfma16(bv[b], yv[a], dacc[a][b]);
+        }
       }
       if (st + 1 < nstage) store_stage(buf ^ 1);
       __syncthreads();
@@ -787,29 +808,93 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     return;
   }
 
-  // C = F - acc for the tile, column-major in LDS (ld kDiagLd)
-  T* Cs = lds;
-  T* Ws = lds + kPanel * kDiagLd;
+  T* Cs = lds;                      // C tile, column-major, ld kDiagLd
+  T* Ws = lds + kPanel * kDiagLd;   // W_j, column-major, ld kDiagLd
   T(*Tmp)[kSub * kSub] = reinterpret_cast<T(*)[kSub * kSub]>(lds + 2 * kPanel * kDiagLd);
-  const bool diag = tk.t == 0;
-#pragma unroll
-  for (int a = 0; a < BL; ++a)
-#pragma unroll
-    for (int b = 0; b < BL; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = wr * (TT / 2) + a * 16 + (lane & 15);
-        const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
-        T val;
-        if (r < arows && c < kb && (!diag || r >= c))
-          val = Lp[(a0 + r) + (int64_t)(c0 + c) * ld] - acc[a][b][v];
-        else
-          val = (diag && r == c && r >= kb) ? T(1) : T(0);
-        Cs[c * kDiagLd + r] = val;
-      }
-  __syncthreads();
   int32_t* done = tile_done + S.tbase[wb + tk.j];  // flags of pivot block j's row tiles
+
+  // rows [a0, a0 + arows): X = (F - acc) W_j^T with Cs = F - acc, Ws = W_j
+  auto trsm_rows = [&]() {
+    V4 x[BL][BL];
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b) x[a][b] = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < kPanel / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      T av[BL], bv[BL];
+#pragma unroll
+      for (int a = 0; a < BL; ++a) av[a] = Cs[kk * kDiagLd + wr * (TT / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < BL; ++b) bv[b] = Ws[kk * kDiagLd + wc * (TT / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b) x[a][b] = mfma16(bv[b], av[a], x[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = wr * (TT / 2) + a * 16 + (lane & 15);
+          const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+          if (r < arows && c < kb) Lp[(a0 + r) + (int64_t)(c0 + c) * ld] = x[a][b][v];
+        }
+  };
+  // F - acc of the row tile into Cs (zero outside the tile)
+  auto stage_rows = [&]() {
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = wr * (TT / 2) + a * 16 + (lane & 15);
+          const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+          Cs[c * kDiagLd + r] = (r < arows && c < kb)
+                                    ? Lp[(a0 + r) + (int64_t)(c0 + c) * ld] - acc[a][b][v]
+                                    : T(0);
+        }
+  };
+
   if (diag) {
+    // row tile 1 waits in place in the factor storage while the diagonal
+    // block is factored
+    if (fuse1) {
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = wr * (TT / 2) + a * 16 + (lane & 15);
+            const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+            if (r < arows && c < kb) {
+              T* p = Lp + (a0 + r) + (int64_t)(c0 + c) * ld;
+              *p = *p - acc[a][b][v];
+            }
+          }
+    }
+    // diagonal block: F - Y Y^T, identity past kb, zero above the diagonal
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = wr * (TT / 2) + a * 16 + (lane & 15);
+          const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+          T val;
+          if (r < kb && c < kb && r >= c)
+            val = Lp[(c0 + r) + (int64_t)(c0 + c) * ld] - dacc[a][b][v];
+          else
+            val = (r == c && r >= kb) ? T(1) : T(0);
+          Cs[c * kDiagLd + r] = val;
+        }
+    __syncthreads();
     diag_factor_inverse<T>(Cs, Ws, Tmp, kb, f + c0, N.fail);
     for (int t = tid; t < kb * kb; t += kThreads) {
       const int c = t / kb, r = t - c * kb;
@@ -823,9 +908,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     __threadfence();
     __syncthreads();
     if (tid == 0) set_flag(done, 1);
+    if (!fuse1) return;
+    // row tile 1 against the inverse still in LDS
+    for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+      const int c = t / kPanel, r = t - c * kPanel;
+      Cs[c * kDiagLd + r] = (r < arows && c < kb) ? Lp[(a0 + r) + (int64_t)(c0 + c) * ld] : T(0);
+    }
+    __syncthreads();
+    trsm_rows();
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) set_flag(done + 1, 1);
     return;
   }
-  // rows below the diagonal block: X = C W_j^T
+  // rows below the diagonal block and row tile 1: X = C W_j^T
+  stage_rows();
   if (tid == 0) wait_at_least(done, 1, hang);
   __syncthreads();
   {
@@ -836,34 +933,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     }
   }
   __syncthreads();
-  V4 x[BL][BL];
-#pragma unroll
-  for (int a = 0; a < BL; ++a)
-#pragma unroll
-    for (int b = 0; b < BL; ++b) x[a][b] = V4{0, 0, 0, 0};
-#pragma unroll
-  for (int ks = 0; ks < kPanel / 4; ++ks) {
-    const int kk = ks * 4 + (lane >> 4);
-    T av[BL], bv[BL];
-#pragma unroll
-    for (int a = 0; a < BL; ++a) av[a] = Cs[kk * kDiagLd + wr * (TT / 2) + a * 16 + (lane & 15)];
-#pragma unroll
-    for (int b = 0; b < BL; ++b) bv[b] = Ws[kk * kDiagLd + wc * (TT / 2) + b * 16 + (lane & 15)];
-#pragma unroll
-    for (int a = 0; a < BL; ++a)
-#pragma unroll
-      for (int b = 0; b < BL; ++b) x[a][b] = mfma16(bv[b], av[a], x[a][b]);
-  }
-#pragma unroll
-  for (int a = 0; a < BL; ++a)
-#pragma unroll
-    for (int b = 0; b < BL; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = wr * (TT / 2) + a * 16 + (lane & 15);
-        const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
-        if (r < arows && c < kb) Lp[(a0 + r) + (int64_t)(c0 + c) * ld] = x[a][b][v];
-      }
+  trsm_rows();
   __threadfence();
   __syncthreads();
   if (tid == 0) set_flag(done + tk.t, 1);
@@ -951,54 +1021,72 @@ __global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T*
   }
 }
 
-// Forward solve, L21 part of a split front: u_s[rows] -= L21[rows, :] x_s for
-// kPanel rows per workgroup; lanes own rows, the four waves split the
-// columns, x_s is staged through LDS kSolveChunk columns at a time.
+// L21 products of split fronts on the matrix cores.  A workgroup takes one
+// 64 x 64 block row (forward) or block column (backward) of L21 over a
+// reduction chunk of kGemvChunk, staging 64 x 64 panels of L21 (coalesced
+// column reads) and 64 x 16 panels of the vector block through LDS; each
+// wave owns 16 of the 64 outputs for all 16 right-hand sides (unused ones
+// are zero).  Partial products go to a slot of `part` (64 x 16, row-major)
+// and are summed in a fixed order by the reduce kernels, so the result does
+// not depend on the launch.
+//
+// Forward: part[slot][i][n] = sum_{k in chunk} L21[64 blk + i][k] x_s[k][n].
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_gemv(DevSym S, const T* L, const T* y, T* uvec,
-                                                       const SolveItem* items, int nrhs) {
-  __shared__ T X[kSolveChunk * kRhsBlock];
-  __shared__ T part[kThreads / 64][kPanel * kRhsBlock];
-  const SolveItem it = items[blockIdx.x];
+__global__ __launch_bounds__(kThreads) void k_fwd_gemv(DevSym S, const T* L, const T* y, T* part,
+                                                       const GemvItem* items, int nrhs) {
+  __shared__ T Ls[kPanel * kDiagLd];    // Ls[k * kDiagLd + i] = L21[row0 + i][k0 + k]
+  __shared__ T Vs[kPanel * kRhsBlock];  // Vs[k * kRhsBlock + n] = x_s[k0 + k][n]
+  typedef typename Vec4<T>::type V4;
+  const GemvItem it = items[blockIdx.x];
   const int s = it.s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
   const int ldl = S.ldL[s];
   const int64_t n = S.n;
   const T* Lp = L + S.L_off[s];
-  const int row = w + it.chunk * kPanel + lane;
-  const bool valid = row < m;
-  T acc[kRhsBlock];
-#pragma unroll
-  for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
-  for (int cb = 0; cb < w; cb += kSolveChunk) {
-    const int cw = min(kSolveChunk, w - cb);
-    __syncthreads();
-    for (int t = tid; t < cw * nrhs; t += kThreads) {
-      const int col = t / cw, c = t - col * cw;
-      X[c + col * kSolveChunk] = y[f + cb + c + col * n];
+  const int row0 = w + it.blk * kPanel, nrows = min(kPanel, m - row0);
+  const int kbeg = it.chunk * kGemvChunk, kend = min(w, kbeg + kGemvChunk);
+  V4 acc = V4{0, 0, 0, 0};
+  for (int k0 = kbeg; k0 < kend; k0 += kPanel) {
+    const int kw = min(kPanel, kend - k0);
+#pragma unroll 4
+    for (int cc = 0; cc < kPanel / 4; ++cc) {
+      const int k = wave * (kPanel / 4) + cc;
+      Ls[k * kDiagLd + lane] = (lane < nrows && k < kw) ? Lp[(row0 + lane) + (int64_t)(k0 + k) * ldl] : T(0);
+    }
+    for (int t = tid; t < kPanel * kRhsBlock; t += kThreads) {
+      const int nn = t / kPanel, k = t - nn * kPanel;
+      Vs[k * kRhsBlock + nn] = (k < kw && nn < nrhs) ? y[f + k0 + k + nn * n] : T(0);
     }
     __syncthreads();
-    if (valid) {
-      for (int c = wave; c < cw; c += kThreads / 64) {
-        const T l = Lp[row + (int64_t)(cb + c) * ldl];
 #pragma unroll
-        for (int col = 0; col < kRhsBlock; ++col)
-          if (col < nrhs) acc[col] += l * X[c + col * kSolveChunk];
-      }
+    for (int s4 = 0; s4 < kPanel / 4; ++s4) {
+      const int k = 4 * s4 + (lane >> 4);
+      acc = mfma16(Ls[k * kDiagLd + wave * 16 + (lane & 15)], Vs[k * kRhsBlock + (lane & 15)], acc);
     }
+    __syncthreads();
   }
+  T* P = part + (int64_t)it.slot * (kPanel * kRhsBlock);
 #pragma unroll
-  for (int col = 0; col < kRhsBlock; ++col) part[wave][lane + col * kPanel] = acc[col];
-  __syncthreads();
-  if (wave == 0 && valid) {
-    T* us = uvec + S.u_off[s] * nrhs;
-    for (int col = 0; col < nrhs; ++col) {
-      T t = T(0);
-#pragma unroll
-      for (int q = 0; q < kThreads / 64; ++q) t += part[q][lane + col * kPanel];
-      us[(row - w) + col * r] -= t;
-    }
+  for (int v = 0; v < 4; ++v) P[(wave * 16 + mfma_row<T>(lane, v)) * kRhsBlock + (lane & 15)] = acc[v];
+}
+
+// Forward: u_s[64 blk + i][n] -= sum over the block row's chunks, in order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fwd_reduce(DevSym S, T* uvec, const T* part,
+                                                         const ReduceItem* items, int nrhs) {
+  const ReduceItem it = items[blockIdx.x];
+  const int s = it.s;
+  const int w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+  T* us = uvec + S.u_off[s] * nrhs;
+  for (int t = threadIdx.x; t < kPanel * nrhs; t += kThreads) {
+    const int nn = t / kPanel, i = t - nn * kPanel;
+    const int row = it.blk * kPanel + i;
+    if (row >= r) continue;
+    T sum = T(0);
+    for (int c = 0; c < it.nchunk; ++c)
+      sum += part[(int64_t)(it.first + c) * (kPanel * kRhsBlock) + i * kRhsBlock + nn];
+    us[row + (int64_t)nn * r] -= sum;
   }
 }
 
@@ -1224,43 +1312,63 @@ __global__ __launch_bounds__(kThreads) void k_bwd_gather(DevSym S, const T* y, T
   }
 }
 
-// Backward solve, L21 part of a split front: y_s[cols] -= L21[:, cols]^T u_s
-// for kPanel columns per workgroup; each wave takes 16 columns one at a time,
-// lanes stride down the column (coalesced), one wave reduction per column
-// and right-hand side.
+// Backward: part[slot][c][n] = sum_{i in chunk} L21[i][64 blk + c] u_s[i][n].
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_gemv(DevSym S, const T* L, T* y, const T* uvec,
-                                                       const SolveItem* items, int nrhs) {
-  const SolveItem it = items[blockIdx.x];
+__global__ __launch_bounds__(kThreads) void k_bwd_gemv(DevSym S, const T* L, const T* uvec, T* part,
+                                                       const GemvItem* items, int nrhs) {
+  __shared__ T Ls[kPanel * kDiagLd];    // Ls[c * kDiagLd + i] = L21[i0 + i][col0 + c]
+  __shared__ T Vs[kPanel * kRhsBlock];  // Vs[i * kRhsBlock + n] = u_s[i0 + i][n]
+  typedef typename Vec4<T>::type V4;
+  const GemvItem it = items[blockIdx.x];
   const int s = it.s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
-  if (r == 0) return;
   const int ldl = S.ldL[s];
+  const T* Lp = L + S.L_off[s] + w;  // L21, row 0 = front row w
+  const T* us = uvec + S.u_off[s] * nrhs;
+  const int col0 = it.blk * kPanel, ncols = min(kPanel, w - col0);
+  const int ibeg = it.chunk * kGemvChunk, iend = min(r, ibeg + kGemvChunk);
+  V4 acc = V4{0, 0, 0, 0};
+  for (int i0 = ibeg; i0 < iend; i0 += kPanel) {
+    const int iw = min(kPanel, iend - i0);
+#pragma unroll 4
+    for (int cc = 0; cc < kPanel / 4; ++cc) {
+      const int c = wave * (kPanel / 4) + cc;
+      Ls[c * kDiagLd + lane] = (lane < iw && c < ncols) ? Lp[(i0 + lane) + (int64_t)(col0 + c) * ldl] : T(0);
+    }
+    for (int t = tid; t < kPanel * kRhsBlock; t += kThreads) {
+      const int nn = t / kPanel, i = t - nn * kPanel;
+      Vs[i * kRhsBlock + nn] = (i < iw && nn < nrhs) ? us[i0 + i + (int64_t)nn * r] : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s4 = 0; s4 < kPanel / 4; ++s4) {
+      const int i = 4 * s4 + (lane >> 4);
+      acc = mfma16(Ls[(wave * 16 + (lane & 15)) * kDiagLd + i], Vs[i * kRhsBlock + (lane & 15)], acc);
+    }
+    __syncthreads();
+  }
+  T* P = part + (int64_t)it.slot * (kPanel * kRhsBlock);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) P[(wave * 16 + mfma_row<T>(lane, v)) * kRhsBlock + (lane & 15)] = acc[v];
+}
+
+// Backward: y_s[64 blk + c][n] -= sum over the block column's chunks, in order.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_bwd_reduce(DevSym S, T* y, const T* part,
+                                                         const ReduceItem* items, int nrhs) {
+  const ReduceItem it = items[blockIdx.x];
+  const int s = it.s;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f;
   const int64_t n = S.n;
-  const T* Lp = L + S.L_off[s] + w;
-  const T* xg = uvec + S.u_off[s] * nrhs;
-  constexpr int kCols = kPanel / (kThreads / 64);
-  for (int jj = 0; jj < kCols; ++jj) {
-    const int j = it.chunk * kPanel + wave * kCols + jj;
-    if (j >= w) break;
-    const T* lc = Lp + (int64_t)j * ldl;
-    T acc[kRhsBlock];
-#pragma unroll
-    for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
-    for (int i = lane; i < r; i += 64) {
-      const T l = lc[i];
-#pragma unroll
-      for (int col = 0; col < kRhsBlock; ++col)
-        if (col < nrhs) acc[col] += l * xg[i + col * r];
-    }
-#pragma unroll
-    for (int col = 0; col < kRhsBlock; ++col) {
-      if (col < nrhs) {
-        const T v = wave_sum(acc[col]);
-        if (lane == 0) y[f + j + col * n] -= v;
-      }
-    }
+  for (int t = threadIdx.x; t < kPanel * nrhs; t += kThreads) {
+    const int nn = t / kPanel, c = t - nn * kPanel;
+    const int col = it.blk * kPanel + c;
+    if (col >= w) continue;
+    T sum = T(0);
+    for (int q = 0; q < it.nchunk; ++q)
+      sum += part[(int64_t)(it.first + q) * (kPanel * kRhsBlock) + c * kRhsBlock + nn];
+    y[f + col + nn * n] -= sum;
   }
 }
 
@@ -1414,9 +1522,12 @@ void launch_fwd(const DevSym& S, const T* L, T* y, T* uvec, const int32_t* list,
 }
 
 template <typename T>
-void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* uvec, const SolveItem* items,
-                     int64_t count, int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, uvec, items, nrhs);
+void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* part, const GemvItem* items,
+                     int64_t count, const ReduceItem* red, int64_t nred, T* uvec, int32_t nrhs,
+                     hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, part, items, nrhs);
+  hipLaunchKernelGGL(k_fwd_reduce<T>, dim3((unsigned)nred), dim3(kThreads), 0, st, S, uvec, (const T*)part, red, nrhs);
 }
 
 template <typename T>
@@ -1438,9 +1549,12 @@ void launch_bwd_gather(const DevSym& S, const T* y, T* uvec, const int32_t* list
 }
 
 template <typename T>
-void launch_bwd_gemv(const DevSym& S, const T* L, T* y, const T* uvec, const SolveItem* items,
-                     int64_t count, int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, uvec, items, nrhs);
+void launch_bwd_gemv(const DevSym& S, const T* L, const T* uvec, T* part, const GemvItem* items,
+                     int64_t count, const ReduceItem* red, int64_t nred, T* y, int32_t nrhs,
+                     hipStream_t st) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, uvec, part, items, nrhs);
+  hipLaunchKernelGGL(k_bwd_reduce<T>, dim3((unsigned)nred), dim3(kThreads), 0, st, S, y, (const T*)part, red, nrhs);
 }
 
 template <typename T>
@@ -1499,10 +1613,12 @@ void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t 
                               hipStream_t);                                                      \
   template void launch_bwd<T>(const DevSym&, const T*, T*, const int32_t*, int64_t, int32_t,      \
                               hipStream_t);                                                      \
-  template void launch_fwd_gemv<T>(const DevSym&, const T*, const T*, T*, const SolveItem*,       \
-                                   int64_t, int32_t, hipStream_t);                               \
-  template void launch_bwd_gemv<T>(const DevSym&, const T*, T*, const T*, const SolveItem*,       \
-                                   int64_t, int32_t, hipStream_t);                               \
+  template void launch_fwd_gemv<T>(const DevSym&, const T*, const T*, T*, const GemvItem*,        \
+                                   int64_t, const ReduceItem*, int64_t, T*, int32_t,             \
+                                   hipStream_t);                                                 \
+  template void launch_bwd_gemv<T>(const DevSym&, const T*, const T*, T*, const GemvItem*,        \
+                                   int64_t, const ReduceItem*, int64_t, T*, int32_t,             \
+                                   hipStream_t);                                                 \
   template void launch_bwd_gather<T>(const DevSym&, const T*, T*, const int32_t*, int64_t,        \
                                      int32_t, hipStream_t);                                      \
   template void launch_fwd_tri<T>(const DevSym&, const T*, const T*, T*, const TriItem*, int64_t, \

@@ -270,8 +270,10 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
         for (int32_t s : big) {
           const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
           if (j * kPanel >= w) continue;
+          // the diagonal task (t = 0) also produces row tile 1
           const int nt = front_block_tiles(m, w, j);
-          for (int t = 0; t < nt; ++t) P.ftasks.push_back({s, j, t, 0});
+          for (int t = 0; t < nt; ++t)
+            if (t != 1) P.ftasks.push_back({s, j, t, 0});
         }
       for (int32_t s : big) {
         const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], r = m - w;
@@ -384,8 +386,13 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
   }
   P.fwd_items.clear();
   P.bwd_items.clear();
+  P.fwd_red.clear();
+  P.bwd_red.clear();
+  P.part_slots = 0;
   P.gather_list.clear();
   P.gather_ptr.assign(S.nlevels + 1, 0);
+  P.fred_ptr.assign(S.nlevels + 1, 0);
+  P.bred_ptr.assign(S.nlevels + 1, 0);
   P.tri_fwd.clear();
   P.tri_bwd.clear();
   P.fwd_ptr.assign(S.nlevels + 1, 0);
@@ -393,13 +400,24 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
   P.tri_ptr.assign(S.nlevels + 1, 0);
   P.tri_flags = 0;
   for (int32_t h = 0; h < S.nlevels; ++h) {
+    int32_t fslot = 0, bslot = 0;
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       const int32_t s = S.level_list[q];
       const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
       if (!solve_split_front(w, r)) continue;
-      for (int32_t c = 0; c * kPanel < r; ++c) P.fwd_items.push_back({s, c});
-      if (r > 0) P.gather_list.push_back(s);
-      for (int32_t c = 0; c * kPanel < w; ++c) P.bwd_items.push_back({s, c});
+      if (r > 0) {
+        P.gather_list.push_back(s);
+        const int32_t fch = (w + kGemvChunk - 1) / kGemvChunk;
+        for (int32_t b = 0; b * kPanel < r; ++b) {
+          P.fwd_red.push_back({s, b, fslot, fch});
+          for (int32_t c = 0; c < fch; ++c) P.fwd_items.push_back({s, b, c, fslot++});
+        }
+        const int32_t bch = (r + kGemvChunk - 1) / kGemvChunk;
+        for (int32_t b = 0; b * kPanel < w; ++b) {
+          P.bwd_red.push_back({s, b, bslot, bch});
+          for (int32_t c = 0; c < bch; ++c) P.bwd_items.push_back({s, b, c, bslot++});
+        }
+      }
       const int32_t nb = (w + kPanel - 1) / kPanel;
       const int32_t base = (int32_t)P.tri_flags;
       for (int32_t b = 0; b < nb; ++b) P.tri_fwd.push_back({s, b, base + b, 0});
@@ -408,6 +426,9 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
     }
     P.fwd_ptr[h + 1] = (int64_t)P.fwd_items.size();
     P.bwd_ptr[h + 1] = (int64_t)P.bwd_items.size();
+    P.fred_ptr[h + 1] = (int64_t)P.fwd_red.size();
+    P.bred_ptr[h + 1] = (int64_t)P.bwd_red.size();
+    P.part_slots = std::max<int64_t>(P.part_slots, std::max(fslot, bslot));
     P.tri_ptr[h + 1] = (int64_t)P.tri_fwd.size();
     P.gather_ptr[h + 1] = (int64_t)P.gather_list.size();
   }

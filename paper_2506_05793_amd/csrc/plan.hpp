@@ -30,10 +30,18 @@ struct GemmProb {
   int32_t lda, ldc, M, N, K, c_in_u;
 };
 
-// Work item of the split solve kernels: row chunk (forward) or column chunk
-// (backward) of kPanel of front s.
-struct SolveItem {
-  int32_t s, chunk;
+// Tile of the L21 products of a split front's solves: 64-row block (forward,
+// u -= L21 x) or 64-column block (backward, x -= L21^T u) `blk`, reduction
+// chunk `chunk` of kGemvChunk columns (forward) or rows (backward); the
+// partial product goes to slot `slot` of the level's partial-sum buffer.
+struct GemvItem {
+  int32_t s, blk, chunk, slot;
+};
+
+// Fixed-order sum of the partial products of block `blk` of front s: slots
+// [first, first + nchunk).
+struct ReduceItem {
+  int32_t s, blk, first, nchunk;
 };
 
 // Block b (kPanel rows / columns) of the L11 solve of a split front; `flag`
@@ -59,9 +67,9 @@ struct GemmTile {
 
 // Task of the dataflow large-front kernel (one workgroup each, taken in
 // ticket order).  kind 0: pivot block j of front s (columns [64j, 64j+kb)),
-// row tile t: t = 0 is the diagonal block (kb rows), t >= 1 the 64 rows
-// starting at 64j + kb + 64(t-1).  kind 1: tile (t, j) of the update
-// matrix U_s (rows 64t.., columns 64j..), t >= j.
+// row tile t: t = 0 is the diagonal block (kb rows) together with row tile
+// 1, t >= 2 the 64 rows starting at 64j + kb + 64(t-1).  kind 1: tile (t, j)
+// of the update matrix U_s (rows 64t.., columns 64j..), t >= j.
 struct FrontTask {
   int32_t s, j, t, kind;
 };
@@ -96,7 +104,7 @@ constexpr int kGemmTile = 64;     // output tile of the update kernel
 constexpr int kGemmTileBig = 128; // output tile for large updates
 constexpr int64_t kGemmBigMin = 256 * 256;  // M*N from which the large tile is used
 constexpr int kLdAlign = 4;       // leading dimensions rounded to this many elements
-constexpr int kSolveChunk = 256;  // vector entries staged per LDS round in the split solves
+constexpr int kGemvChunk = 512;   // reduction length of one L21 product tile in the split solves
 
 struct Plan {
   // memory layout (elements; identical for FP32 and FP64)
@@ -130,8 +138,11 @@ struct Plan {
   // trapezoid of the panel) and front rows touched
   std::vector<double> level_lentries, level_rows;
   // split solves: per level [ptr[h], ptr[h+1]) into the item arrays
-  std::vector<SolveItem> fwd_items, bwd_items;
+  std::vector<GemvItem> fwd_items, bwd_items;
   std::vector<int64_t> fwd_ptr, bwd_ptr;
+  std::vector<ReduceItem> fwd_red, bwd_red;
+  std::vector<int64_t> fred_ptr, bred_ptr;
+  int64_t part_slots = 0;  // partial-product slots (64 x 16 each) of the busiest level
   std::vector<TriItem> tri_fwd, tri_bwd;  // per level, blocks in ticket order
   std::vector<int32_t> gather_list;       // split fronts with r > 0, per level
   std::vector<int64_t> gather_ptr;
