@@ -68,6 +68,22 @@ __device__ inline float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
+// 1/sqrt(x) from the hardware estimate refined by two Newton steps
+// (r <- r + r (1 - x r^2) / 2); accurate to about an ulp for normal x > 0,
+// NaN or infinite otherwise (the caller flags non-positive pivots).
+__device__ inline double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  double e = __builtin_fma(-x * r, r, 1.0);
+  r = __builtin_fma(0.5 * r, e, r);
+  e = __builtin_fma(-x * r, r, 1.0);
+  return __builtin_fma(0.5 * r, e, r);
+}
+__device__ inline float rsqrt_nr(float x) {
+  float r = __builtin_amdgcn_rsqf(x);
+  const float e = __builtin_fmaf(-x * r, r, 1.0f);
+  return __builtin_fmaf(0.5f * r, e, r);
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -271,7 +287,10 @@ __device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * 
   __syncthreads();
   for (int jb = 0; jb < kr; jb += kSub) {
     // (1) 16x16 diagonal block: Cholesky and inverse, lanes 0..15 of wave 0
-    // (lane i holds row i of L in a[] and, afterwards, row i of W in x[])
+    // (lane i holds row i of L in a[] and, afterwards, row i of W in x[]).
+    // Updates run on every lane: entries above the diagonal become garbage
+    // that is never broadcast or stored, which keeps the pivot chain free of
+    // lane masks.
     if (wave == 0 && lane < kSub) {
       T a[kSub];
 #pragma unroll
@@ -282,15 +301,11 @@ __device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * 
       for (int j = 0; j < kSub; ++j) {
         const T piv = readlane(a[j], j);
         bad |= (piv > T(0)) ? 0u : (1u << j);
-        const T ljj = sqrt(piv);
-        const T rinv = T(1) / ljj;
+        const T rinv = rsqrt_nr(piv);
         if (lane == j) myinv = rinv;
-        a[j] = lane == j ? ljj : (lane > j ? a[j] * rinv : a[j]);
+        a[j] = lane == j ? piv * rinv : a[j] * rinv;
 #pragma unroll
-        for (int c = j + 1; c < kSub; ++c) {
-          const T lcj = readlane(a[j], c);
-          if (lane >= c) a[c] -= a[j] * lcj;
-        }
+        for (int c = j + 1; c < kSub; ++c) a[c] -= a[j] * readlane(a[j], c);
       }
       if (kb - jb < kSub) bad &= (1u << (kb - jb)) - 1u;  // identity padding past kb
       if (lane == 0 && bad != 0) atomicMin(fail, col0 + jb + __builtin_ctz(bad));
@@ -304,15 +319,10 @@ __device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * 
       for (int k = 0; k < kSub; ++k) x[k] = lane == k ? T(1) : T(0);
 #pragma unroll
       for (int q = 0; q < kSub; ++q) {
-        if (lane == q) {
 #pragma unroll
-          for (int k = 0; k <= q; ++k) x[k] *= myinv;
-        }
+        for (int k = 0; k <= q; ++k) x[k] = lane == q ? x[k] * myinv : x[k];
 #pragma unroll
-        for (int k = 0; k <= q; ++k) {
-          const T wqk = readlane(x[k], q);
-          if (lane > q) x[k] -= a[q] * wqk;
-        }
+        for (int k = 0; k <= q; ++k) x[k] -= (lane > q ? a[q] : T(0)) * readlane(x[k], q);
       }
 #pragma unroll
       for (int k = 0; k < kSub; ++k) W[(jb + k) * kDiagLd + jb + lane] = x[k];
@@ -624,6 +634,8 @@ __device__ inline void set_flag(int32_t* flag, int32_t value) {
 // flag, so the launch drains.
 constexpr int kFlowSpinLimit = 1 << 21;
 
+// Relaxed polling only: the caller issues one acquire fence after its last
+// wait, then a workgroup barrier hands the ordering to the other threads.
 __device__ inline void wait_at_least(const int32_t* flag, int32_t value, int32_t* hang) {
   int spins = 0;
   while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
@@ -636,7 +648,10 @@ __device__ inline void wait_at_least(const int32_t* flag, int32_t value, int32_t
       break;
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ inline bool flag_set(const int32_t* flag) {
+  return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -669,7 +684,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   constexpr int LDS = POST > 2 * STAGE ? POST : 2 * STAGE;
   typedef typename Vec4<T>::type V4;
   __shared__ T lds[LDS];
-  __shared__ int s_ticket;
+  __shared__ int s_ticket, s_ready;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   if (tid == 0) s_ticket = atomicAdd(counter, 1);
@@ -724,17 +739,38 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     const T* pa = Lp + a0 + lrow;
     const T* pb = Lp + b0 + lrow;
     T ra[LPT], rb[LPT];
-    // wait for the row tiles of pivot block p holding rows [r0, r0 + nr)
-    auto wait_rows = [&](int p, int r0, int nr) {
+    // Pivot blocks [0, ready) are known complete.  Before reading block p,
+    // thread 0 waits for the row tiles of p that hold the operand rows, then
+    // extends `ready` over the following blocks that are already complete,
+    // and issues one acquire fence for all of them.
+    int ready = 0;
+    const int pend = (K + TT - 1) / TT;
+    auto rows_done = [&](int p, int r0, int nr, bool wait) {
       const int32_t* fl = tile_done + S.tbase[wb + p];
       const int t1 = front_row_tile(w, p, r0 + nr - 1);
-      for (int t = front_row_tile(w, p, r0); t <= t1; ++t) wait_at_least(fl + t, 1, hang);
+      for (int t = front_row_tile(w, p, r0); t <= t1; ++t) {
+        if (wait)
+          wait_at_least(fl + t, 1, hang);
+        else if (!flag_set(fl + t))
+          return false;
+      }
+      return true;
+    };
+    auto block_done = [&](int p, bool wait) {
+      return (arows <= 0 || rows_done(p, a0, arows, wait)) && rows_done(p, b0, bcols, wait);
     };
     auto load_stage = [&](int k0) {
-      if (k0 % TT == 0) {
-        const int p = k0 / TT;
-        if (arows > 0) wait_rows(p, a0, arows);
-        wait_rows(p, b0, bcols);
+      if (k0 % TT == 0 && k0 / TT >= ready) {
+        if (tid == 0) {
+          int p = k0 / TT;
+          block_done(p, true);
+          ++p;
+          while (p < pend && block_done(p, false)) ++p;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          s_ready = p;
+        }
+        __syncthreads();
+        ready = s_ready;
       }
 #pragma unroll
       for (int u = 0; u < LPT; ++u) {
@@ -905,9 +941,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       const int c = t / kb, r = t - c * kb;
       Wout[t] = Ws[c * kDiagLd + r];
     }
-    __threadfence();
     __syncthreads();
-    if (tid == 0) set_flag(done, 1);
+    if (tid == 0) set_flag(done, 1);  // release: the workgroup's stores are in L2 after the barrier
     if (!fuse1) return;
     // row tile 1 against the inverse still in LDS
     for (int t = tid; t < kPanel * kPanel; t += kThreads) {
@@ -916,14 +951,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     }
     __syncthreads();
     trsm_rows();
-    __threadfence();
     __syncthreads();
     if (tid == 0) set_flag(done + 1, 1);
     return;
   }
   // rows below the diagonal block and row tile 1: X = C W_j^T
   stage_rows();
-  if (tid == 0) wait_at_least(done, 1, hang);
+  if (tid == 0) {
+    wait_at_least(done, 1, hang);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
   __syncthreads();
   {
     const T* Win = winv + S.woff[wb + tk.j];  // Win[c * kb + r] = W[r][c]
@@ -934,7 +971,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   }
   __syncthreads();
   trsm_rows();
-  __threadfence();
   __syncthreads();
   if (tid == 0) set_flag(done + tk.t, 1);
 }
@@ -1212,9 +1248,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_tri(DevSym S, const T* L, cons
       y[f + r0 + lane + col * n] = acc;
     }
   }
-  __threadfence();
   __syncthreads();
-  if (tid == 0) set_flag(flags + it.flag, 1);
+  if (tid == 0) set_flag(flags + it.flag, 1);  // release after the workgroup's stores
 }
 
 // Backward: block b (taken from the bottom) subtracts L_cb^T x_c for c > b
@@ -1292,9 +1327,8 @@ __global__ __launch_bounds__(kThreads) void k_bwd_tri(DevSym S, const T* L, cons
       y[f + r0 + lane + col * n] = acc;
     }
   }
-  __threadfence();
   __syncthreads();
-  if (tid == 0) set_flag(flags + it.flag, 2);
+  if (tid == 0) set_flag(flags + it.flag, 2);  // release after the workgroup's stores
 }
 
 // Backward solve of a split front, gather step: u_s = x[rows(s)[w:]] (the
