@@ -349,8 +349,8 @@ def cpu_baseline(side=46):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--side", type=int, default=64, help="grid side of the 3D workload")
     ap.add_argument("--workload", default="3d", choices=["3d", "2d", "landice", "batch", "serve"],
                     help="3d: 64^3 lognormal (default, the metric's workload); 2d: 32x32 "

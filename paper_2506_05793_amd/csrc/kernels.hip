@@ -676,10 +676,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
                                                     const FrontTask* tasks, int count,
                                                     int32_t* tile_done, int32_t* counter,
                                                     int32_t* hang) {
-  constexpr int TT = kPanel, KT = 16, PAD = 4, BL = 2;
-  constexpr int LPT = TT * KT / kThreads;  // staged elements per thread and operand
+  constexpr int TT = kPanel, PAD = 4, BL = 2;
   constexpr int RSTEP = kThreads / TT;     // k rows covered per load round
-  constexpr int STAGE = 2 * KT * (TT + PAD);
+  constexpr int STAGE = TT * (TT + PAD);   // one operand, double-buffered half blocks
   constexpr int POST = 2 * kPanel * kDiagLd + 3 * kSub * kSub;
   constexpr int LDS = POST > 2 * STAGE ? POST : 2 * STAGE;
   typedef typename Vec4<T>::type V4;
@@ -714,37 +713,67 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     b0 = c0;
     bcols = kb;
     K = c0;
-    if (diag) {
-      a0 = c0 + kb;  // row tile 1 (empty when the front ends here)
-      arows = min(TT, m - a0);
-    } else {
-      a0 = c0 + kb + (tk.t - 1) * TT;
-      arows = min(TT, m - a0);
-    }
+    a0 = diag ? c0 + kb : c0 + kb + (tk.t - 1) * TT;  // diagonal: row tile 1 (may be empty)
+    arows = min(TT, m - a0);
   }
   const bool fuse1 = diag && arows > 0;
+  T* Cu = N.U + (utile ? S.U_off[s] : 0);
+  const int ldc = utile ? S.ldU[s] : 0;
+
+  // Output element (a, b, v) of this thread: row i(a) of the tile, column j(b, v).
+  auto oi = [&](int a) { return wr * (TT / 2) + a * 16 + (lane & 15); };
+  auto oj = [&](int b, int v) { return wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v); };
+  // Assembled front values of the outputs: fa for rows a0.. (or the U tile),
+  // fd for the diagonal block.  Branch-free: masked-off elements read the
+  // front's first entry.
+  V4 fa[BL][BL], fd[BL][BL];
+  const T* fbase = utile ? Cu + tk.t * TT + (int64_t)(tk.j * TT) * ldc : Lp + a0 + (int64_t)c0 * ld;
+  const int fld = utile ? ldc : ld;
+  const int fcols = utile ? bcols : kb;
+  const int tri_off = utile ? (tk.t - tk.j) * TT : INT_MAX / 2;  // U: keep gi >= gj
+  const T* dbase = Lp + c0 + (int64_t)c0 * ld;
+  auto load_f = [&]() {
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = oi(a), jj = oj(b, v);
+          const bool ma = i < arows && jj < fcols && i + tri_off >= jj;
+          const T va = ma ? fbase[i + (int64_t)jj * fld] : Lp[0];
+          fa[a][b][v] = ma ? va : T(0);
+          const bool md = diag && i < kb && jj < kb && i >= jj;
+          const T vd = md ? dbase[i + (int64_t)jj * ld] : Lp[0];
+          fd[a][b][v] = md ? vd : T(0);
+        }
+  };
 
   // acc = X Y^T over the completed pivot blocks (X: rows a0.., Y: rows b0..);
-  // a diagonal task accumulates Y Y^T in dacc as well.
+  // a diagonal task accumulates Y Y^T in dacc as well.  Half a pivot block
+  // (32 columns of both operands) per stage through double-buffered LDS, the
+  // next stage prefetched into registers while the current one is multiplied.
   V4 acc[BL][BL], dacc[BL][BL];
 #pragma unroll
   for (int a = 0; a < BL; ++a)
 #pragma unroll
     for (int b = 0; b < BL; ++b) acc[a][b] = dacc[a][b] = V4{0, 0, 0, 0};
   {
-    T* As = lds;          // [2][KT][TT + PAD]
-    T* Bs = lds + STAGE;  // [2][KT][TT + PAD]
+    constexpr int KT = TT / 2;
+    constexpr int SLPT = TT * KT / kThreads;  // staged elements per thread and operand
+    T* As = lds;                  // [2][KT][TT + PAD]: As[buf][k][row]
+    T* Bs = lds + 2 * KT * (TT + PAD);
     const int lrow = tid % TT, lk = tid / TT;
     const bool aok = lrow < arows, bok = lrow < bcols;
     const T* pa = Lp + a0 + lrow;
     const T* pb = Lp + b0 + lrow;
-    T ra[LPT], rb[LPT];
+    T ra[SLPT], rb[SLPT];
     // Pivot blocks [0, ready) are known complete.  Before reading block p,
     // thread 0 waits for the row tiles of p that hold the operand rows, then
     // extends `ready` over the following blocks that are already complete,
     // and issues one acquire fence for all of them.
     int ready = 0;
-    const int pend = (K + TT - 1) / TT;
+    const int nblk = (K + TT - 1) / TT;
     auto rows_done = [&](int p, int r0, int nr, bool wait) {
       const int32_t* fl = tile_done + S.tbase[wb + p];
       const int t1 = front_row_tile(w, p, r0 + nr - 1);
@@ -759,21 +788,22 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     auto block_done = [&](int p, bool wait) {
       return (arows <= 0 || rows_done(p, a0, arows, wait)) && rows_done(p, b0, bcols, wait);
     };
-    auto load_stage = [&](int k0) {
+    auto load_stage = [&](int st) {
+      const int k0 = st * KT;
       if (k0 % TT == 0 && k0 / TT >= ready) {
         if (tid == 0) {
-          int p = k0 / TT;
-          block_done(p, true);
-          ++p;
-          while (p < pend && block_done(p, false)) ++p;
+          int q = k0 / TT;
+          block_done(q, true);
+          ++q;
+          while (q < nblk && block_done(q, false)) ++q;
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          s_ready = p;
+          s_ready = q;
         }
         __syncthreads();
         ready = s_ready;
       }
 #pragma unroll
-      for (int u = 0; u < LPT; ++u) {
+      for (int u = 0; u < SLPT; ++u) {
         const int kg = k0 + lk + RSTEP * u;
         const bool kok = kg < K;
         ra[u] = (aok && kok) ? pa[(int64_t)kg * ld] : T(0);
@@ -782,7 +812,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-      for (int u = 0; u < LPT; ++u) {
+      for (int u = 0; u < SLPT; ++u) {
         As[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = ra[u];
         Bs[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = rb[u];
       }
@@ -795,11 +825,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     }
     for (int st = 0; st < nstage; ++st) {
       const int buf = st & 1;
-      if (st + 1 < nstage) load_stage((st + 1) * KT);
-#pragma unroll
+      if (st + 1 < nstage) load_stage(st + 1);
+#pragma unroll 4
       for (int ks = 0; ks < KT / 4; ++ks) {
         const int kr = buf * KT + ks * 4 + (lane >> 4);
-        T av[BL], bv[BL], yv[BL];
+        T av[BL], bv[BL];
 #pragma unroll
         for (int a = 0; a < BL; ++a) av[a] = As[kr * (TT + PAD) + wr * (TT / 2) + a * 16 + (lane & 15)];
 #pragma unroll
@@ -811,6 +841,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
             for (int b = 0; b < BL; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
         }
         if (diag) {
+          T yv[BL];
 #pragma unroll
           for (int a = 0; a < BL; ++a) yv[a] = Bs[kr * (TT + PAD) + wr * (TT / 2) + a * 16 + (lane & 15)];
 #pragma unroll
@@ -823,23 +854,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       __syncthreads();
     }
   }
+  load_f();
 
   if (utile) {
-    T* C = N.U + S.U_off[s];
-    const int ldc = S.ldU[s];
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
       for (int b = 0; b < BL; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = wr * (TT / 2) + a * 16 + (lane & 15);
-          const int jj = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+          const int i = oi(a), jj = oj(b, v);
           const int gi = tk.t * TT + i, gj = tk.j * TT + jj;
-          if (i < arows && jj < bcols && gi >= gj) {
-            T* p = C + gi + (int64_t)gj * ldc;
-            *p = *p - acc[a][b][v];
-          }
+          if (i < arows && jj < bcols && gi >= gj) Cu[gi + (int64_t)gj * ldc] = fa[a][b][v] - acc[a][b][v];
         }
     return;
   }
@@ -849,14 +875,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   T(*Tmp)[kSub * kSub] = reinterpret_cast<T(*)[kSub * kSub]>(lds + 2 * kPanel * kDiagLd);
   int32_t* done = tile_done + S.tbase[wb + tk.j];  // flags of pivot block j's row tiles
 
-  // rows [a0, a0 + arows): X = (F - acc) W_j^T with Cs = F - acc, Ws = W_j
+  // rows [a0, a0 + arows): X = C W_j^T with C in Cs and W_j in Ws
   auto trsm_rows = [&]() {
     V4 x[BL][BL];
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
       for (int b = 0; b < BL; ++b) x[a][b] = V4{0, 0, 0, 0};
-#pragma unroll
+#pragma unroll 4
     for (int ks = 0; ks < kPanel / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
       T av[BL], bv[BL];
@@ -875,45 +901,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       for (int b = 0; b < BL; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = wr * (TT / 2) + a * 16 + (lane & 15);
-          const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+          const int r = oi(a), c = oj(b, v);
           if (r < arows && c < kb) Lp[(a0 + r) + (int64_t)(c0 + c) * ld] = x[a][b][v];
         }
   };
-  // F - acc of the row tile into Cs (zero outside the tile)
+  // C = F - acc of the row tile into Cs (zero outside the tile)
   auto stage_rows = [&]() {
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
       for (int b = 0; b < BL; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = wr * (TT / 2) + a * 16 + (lane & 15);
-          const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
-          Cs[c * kDiagLd + r] = (r < arows && c < kb)
-                                    ? Lp[(a0 + r) + (int64_t)(c0 + c) * ld] - acc[a][b][v]
-                                    : T(0);
-        }
+        for (int v = 0; v < 4; ++v) Cs[oj(b, v) * kDiagLd + oi(a)] = fa[a][b][v] - acc[a][b][v];
   };
 
   if (diag) {
-    // row tile 1 waits in place in the factor storage while the diagonal
-    // block is factored
-    if (fuse1) {
-#pragma unroll
-      for (int a = 0; a < BL; ++a)
-#pragma unroll
-        for (int b = 0; b < BL; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = wr * (TT / 2) + a * 16 + (lane & 15);
-            const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
-            if (r < arows && c < kb) {
-              T* p = Lp + (a0 + r) + (int64_t)(c0 + c) * ld;
-              *p = *p - acc[a][b][v];
-            }
-          }
-    }
     // diagonal block: F - Y Y^T, identity past kb, zero above the diagonal
 #pragma unroll
     for (int a = 0; a < BL; ++a)
@@ -921,11 +923,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       for (int b = 0; b < BL; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int r = wr * (TT / 2) + a * 16 + (lane & 15);
-          const int c = wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v);
+          const int r = oi(a), c = oj(b, v);
           T val;
           if (r < kb && c < kb && r >= c)
-            val = Lp[(c0 + r) + (int64_t)(c0 + c) * ld] - dacc[a][b][v];
+            val = fd[a][b][v] - dacc[a][b][v];
           else
             val = (r == c && r >= kb) ? T(1) : T(0);
           Cs[c * kDiagLd + r] = val;
@@ -944,18 +945,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     __syncthreads();
     if (tid == 0) set_flag(done, 1);  // release: the workgroup's stores are in L2 after the barrier
     if (!fuse1) return;
-    // row tile 1 against the inverse still in LDS
-    for (int t = tid; t < kPanel * kPanel; t += kThreads) {
-      const int c = t / kPanel, r = t - c * kPanel;
-      Cs[c * kDiagLd + r] = (r < arows && c < kb) ? Lp[(a0 + r) + (int64_t)(c0 + c) * ld] : T(0);
-    }
+    // row tile 1 (still in registers) against the inverse in LDS
+    stage_rows();
     __syncthreads();
     trsm_rows();
     __syncthreads();
     if (tid == 0) set_flag(done + 1, 1);
     return;
   }
-  // rows below the diagonal block and row tile 1: X = C W_j^T
+  // rows below the diagonal block: X = C W_j^T
   stage_rows();
   if (tid == 0) {
     wait_at_least(done, 1, hang);
