@@ -327,10 +327,13 @@ size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
 
 // Device bytes a numeric handle needs (factor, update workspace, values,
 // solve workspace for kRhs columns).
-// Dataflow factorization: one completion flag per row tile, one ticket
-// counter per level, one hang flag.
+// Dataflow factorization: one completion flag per row tile, one
+// pre-accumulation flag per pivot block, one counter per update-matrix tile,
+// one ticket counter per level, one hang flag.
 int64_t flow_ntiles(const tacho_sym* h) { return h->P.tbase.empty() ? 0 : h->P.tbase.back(); }
-int64_t flow_ints(const tacho_sym* h) { return flow_ntiles(h) + h->S.nlevels + 1; }
+int64_t flow_ints(const tacho_sym* h) {
+  return flow_ntiles(h) + (int64_t)h->P.woff.size() + h->P.nucount + h->S.nlevels + 1;
+}
 
 int64_t numeric_bytes(const tacho_sym* h, int precision) {
   const size_t es = elem_size(precision);
@@ -395,7 +398,7 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
       case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, s.tile, st); break;
       case kStepFront:
         launch_front<T>(S, N, f->winv.as<T>(), ftasks + s.begin, cnt, f->flow.as<int32_t>(), ntiles,
-                        s.level, (int)h->S.nlevels, st);
+                        (int64_t)P.woff.size(), P.nucount, s.level, (int)h->S.nlevels, st);
         break;
     }
     f->prof.end(pe, st, step_kind(s.kind), s.flops, s.elems * sizeof(T));

@@ -69,12 +69,13 @@ void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tile
                  int tile, hipStream_t st);
 // Dataflow factorization of one level's large fronts.  flow holds one
 // completion flag per row tile of every pivot block (ntiles, indexed through
-// DevSym::tbase), then one ticket counter per level and the hang flag; all
-// zero before the factorization starts.
+// DevSym::tbase), one pre-accumulation flag per pivot block (nblocks), one
+// range counter per update-matrix tile (nucount), one ticket counter per
+// level and the hang flag; all zero before the factorization starts.
 template <typename T>
 void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
-                  int64_t count, int32_t* flow, int64_t ntiles, int level, int nlevels,
-                  hipStream_t st);
+                  int64_t count, int32_t* flow, int64_t ntiles, int64_t nblocks, int64_t nucount,
+                  int level, int nlevels, hipStream_t st);
 
 // Solves: y is the permuted right-hand side / solution (n x nrhs, ld n).
 template <typename T>

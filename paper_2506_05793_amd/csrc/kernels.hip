@@ -674,7 +674,8 @@ __device__ inline bool flag_set(const int32_t* flag) {
 template <typename T>
 __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T* winv,
                                                     const FrontTask* tasks, int count,
-                                                    int32_t* tile_done, int32_t* counter,
+                                                    int32_t* tile_done, int32_t* pd_done,
+                                                    int32_t* ucount, int32_t* counter,
                                                     int32_t* hang) {
   constexpr int TT = kPanel, PAD = 4, BL = 2;
   constexpr int RSTEP = kThreads / TT;     // k rows covered per load round
@@ -695,44 +696,54 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], ld = S.ldL[s];
   const int wb = S.wbase[s];
   T* Lp = N.L + S.L_off[s];
-  const bool utile = tk.kind != 0;
-  const bool diag = !utile && tk.t == 0;
-  const int c0 = tk.j * TT;
+  // One task step.  mode 0: row tile tt of pivot block tj (tt = 0: the
+  // diagonal block with row tile 1); mode 1: update-matrix tile (tt, tj);
+  // mode 3: pre-accumulation of the diagonal block tj and its row tile 1
+  // (no factorization).  Pivot blocks [kstart / 64, K / 64) are applied.
+  auto step = [&](int mode, int tj, int tt, int kstart, int K) {
+  const bool utile = mode == 1;
+  const bool pre = mode == 3;
+  const bool diag = (mode == 0 && tt == 0) || pre;
+  const int c0 = tj * TT;
   const int kb = utile ? TT : min(TT, w - c0);
   // Output rows [a0, a0 + arows) against operand rows [b0, b0 + bcols); a
   // diagonal task also produces row tile 1 (rows [c0 + kb, ...)) when it
   // exists, so the next diagonal block does not wait for another workgroup.
-  int a0, arows, b0, bcols, K;
+  int a0, arows, b0, bcols;
   if (utile) {
-    a0 = w + tk.t * TT;
-    b0 = w + tk.j * TT;
+    a0 = w + tt * TT;
+    b0 = w + tj * TT;
     arows = min(TT, m - a0);
     bcols = min(TT, m - b0);
-    K = w;
   } else {
     b0 = c0;
     bcols = kb;
-    K = c0;
-    a0 = diag ? c0 + kb : c0 + kb + (tk.t - 1) * TT;  // diagonal: row tile 1 (may be empty)
+    a0 = diag ? c0 + kb : c0 + kb + (tt - 1) * TT;  // diagonal: row tile 1 (may be empty)
     arows = min(TT, m - a0);
   }
   const bool fuse1 = diag && arows > 0;
+  T* Lc0 = Lp + (int64_t)c0 * ld;  // pivot block j's columns (32-bit offsets from here)
   T* Cu = N.U + (utile ? S.U_off[s] : 0);
   const int ldc = utile ? S.ldU[s] : 0;
 
   // Output element (a, b, v) of this thread: row i(a) of the tile, column j(b, v).
   auto oi = [&](int a) { return wr * (TT / 2) + a * 16 + (lane & 15); };
   auto oj = [&](int b, int v) { return wc * (TT / 2) + b * 16 + mfma_row<T>(lane, v); };
-  // Assembled front values of the outputs: fa for rows a0.. (or the U tile),
-  // fd for the diagonal block.  Branch-free: masked-off elements read the
-  // front's first entry.
-  V4 fa[BL][BL], fd[BL][BL];
-  const T* fbase = utile ? Cu + tk.t * TT + (int64_t)(tk.j * TT) * ldc : Lp + a0 + (int64_t)c0 * ld;
+  V4 acc[BL][BL], dacc[BL][BL];
+#pragma unroll
+  for (int a = 0; a < BL; ++a)
+#pragma unroll
+    for (int b = 0; b < BL; ++b) acc[a][b] = dacc[a][b] = V4{0, 0, 0, 0};
+  // Assembled front values F of the outputs are folded into the
+  // accumulators after the products: acc <- F - acc for rows a0.. (or the U
+  // tile), dacc <- F - dacc for the diagonal block.  Branch-free:
+  // masked-off elements read the front's first entry and give zero.
+  const T* fbase = utile ? Cu + tt * TT + (int64_t)(tj * TT) * ldc : Lp + a0 + (int64_t)c0 * ld;
   const int fld = utile ? ldc : ld;
   const int fcols = utile ? bcols : kb;
-  const int tri_off = utile ? (tk.t - tk.j) * TT : INT_MAX / 2;  // U: keep gi >= gj
+  const int tri_off = utile ? (tt - tj) * TT : INT_MAX / 2;  // U: keep gi >= gj
   const T* dbase = Lp + c0 + (int64_t)c0 * ld;
-  auto load_f = [&]() {
+  auto fold_f = [&]() {
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
@@ -740,12 +751,26 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = oi(a), jj = oj(b, v);
+          // unconditional loads from a selected address (masked-off ones read
+          // the front's first entry): the loads of one thread all issue
+          // before the first use instead of one branch and wait each
+          // (a multiplicative mask keeps the compiler from turning them
+          // back into branches around each load)
           const bool ma = i < arows && jj < fcols && i + tri_off >= jj;
-          const T va = ma ? fbase[i + (int64_t)jj * fld] : Lp[0];
-          fa[a][b][v] = ma ? va : T(0);
-          const bool md = diag && i < kb && jj < kb && i >= jj;
-          const T vd = md ? dbase[i + (int64_t)jj * ld] : Lp[0];
-          fd[a][b][v] = md ? vd : T(0);
+          const T va = *(ma ? fbase + (i + jj * fld) : (const T*)Lp);
+          acc[a][b][v] = (ma ? T(1) : T(0)) * (va - acc[a][b][v]);
+        }
+    if (!diag) return;
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = oi(a), jj = oj(b, v);
+          const bool md = i < kb && jj < kb && i >= jj;
+          const T vd = *(md ? dbase + (i + jj * ld) : (const T*)Lp);
+          dacc[a][b][v] = (md ? T(1) : T(0)) * (vd - dacc[a][b][v]);
         }
   };
 
@@ -753,11 +778,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   // a diagonal task accumulates Y Y^T in dacc as well.  Half a pivot block
   // (32 columns of both operands) per stage through double-buffered LDS, the
   // next stage prefetched into registers while the current one is multiplied.
-  V4 acc[BL][BL], dacc[BL][BL];
-#pragma unroll
-  for (int a = 0; a < BL; ++a)
-#pragma unroll
-    for (int b = 0; b < BL; ++b) acc[a][b] = dacc[a][b] = V4{0, 0, 0, 0};
   {
     constexpr int KT = TT / 2;
     constexpr int SLPT = TT * KT / kThreads;  // staged elements per thread and operand
@@ -772,7 +792,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     // thread 0 waits for the row tiles of p that hold the operand rows, then
     // extends `ready` over the following blocks that are already complete,
     // and issues one acquire fence for all of them.
-    int ready = 0;
+    int ready = kstart / TT;
     const int nblk = (K + TT - 1) / TT;
     auto rows_done = [&](int p, int r0, int nr, bool wait) {
       const int32_t* fl = tile_done + S.tbase[wb + p];
@@ -789,7 +809,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       return (arows <= 0 || rows_done(p, a0, arows, wait)) && rows_done(p, b0, bcols, wait);
     };
     auto load_stage = [&](int st) {
-      const int k0 = st * KT;
+      const int k0 = kstart + st * KT;
       if (k0 % TT == 0 && k0 / TT >= ready) {
         if (tid == 0) {
           int q = k0 / TT;
@@ -806,8 +826,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       for (int u = 0; u < SLPT; ++u) {
         const int kg = k0 + lk + RSTEP * u;
         const bool kok = kg < K;
-        ra[u] = (aok && kok) ? pa[(int64_t)kg * ld] : T(0);
-        rb[u] = (bok && kok) ? pb[(int64_t)kg * ld] : T(0);
+        const T xa = *((aok && kok) ? pa + (int64_t)kg * ld : (const T*)Lp);
+        const T xb = *((bok && kok) ? pb + (int64_t)kg * ld : (const T*)Lp);
+        ra[u] = ((aok && kok) ? T(1) : T(0)) * xa;
+        rb[u] = ((bok && kok) ? T(1) : T(0)) * xb;
       }
     };
     auto store_stage = [&](int buf) {
@@ -817,7 +839,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
         Bs[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = rb[u];
       }
     };
-    const int nstage = (K + KT - 1) / KT;
+    const int nstage = (K - kstart + KT - 1) / KT;
     if (nstage > 0) {
       load_stage(0);
       store_stage(0);
@@ -854,7 +876,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       __syncthreads();
     }
   }
-  load_f();
+  if (utile && tk.rk > 0) {
+    // ranges of one update-matrix tile are applied in order
+    if (tid == 0) {
+      wait_at_least(ucount + tk.ui, tk.rk, hang);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+  }
+  fold_f();
 
   if (utile) {
 #pragma unroll
@@ -864,16 +894,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = oi(a), jj = oj(b, v);
-          const int gi = tk.t * TT + i, gj = tk.j * TT + jj;
-          if (i < arows && jj < bcols && gi >= gj) Cu[gi + (int64_t)gj * ldc] = fa[a][b][v] - acc[a][b][v];
+          const int gi = tt * TT + i, gj = tj * TT + jj;
+          if (i < arows && jj < bcols && gi >= gj) Cu[gi + (int64_t)gj * ldc] = acc[a][b][v];
         }
+    if (tk.p1 * TT < w) {  // a later range of this tile follows
+      __syncthreads();
+      if (tid == 0) set_flag(ucount + tk.ui, tk.rk + 1);
+    }
     return;
   }
 
   T* Cs = lds;                      // C tile, column-major, ld kDiagLd
   T* Ws = lds + kPanel * kDiagLd;   // W_j, column-major, ld kDiagLd
   T(*Tmp)[kSub * kSub] = reinterpret_cast<T(*)[kSub * kSub]>(lds + 2 * kPanel * kDiagLd);
-  int32_t* done = tile_done + S.tbase[wb + tk.j];  // flags of pivot block j's row tiles
+  int32_t* done = tile_done + S.tbase[wb + tj];  // flags of pivot block j's row tiles
 
   // rows [a0, a0 + arows): X = C W_j^T with C in Cs and W_j in Ws
   auto trsm_rows = [&]() {
@@ -902,7 +936,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = oi(a), c = oj(b, v);
-          if (r < arows && c < kb) Lp[(a0 + r) + (int64_t)(c0 + c) * ld] = x[a][b][v];
+          if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = x[a][b][v];
         }
   };
   // C = F - acc of the row tile into Cs (zero outside the tile)
@@ -912,9 +946,26 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
       for (int b = 0; b < BL; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Cs[oj(b, v) * kDiagLd + oi(a)] = fa[a][b][v] - acc[a][b][v];
+        for (int v = 0; v < 4; ++v) Cs[oj(b, v) * kDiagLd + oi(a)] = acc[a][b][v];
   };
 
+  if (pre) {
+    // pre-accumulated diagonal block and row tile 1 go back in place; the
+    // chain applies the last pivot block and factors
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = oi(a), c = oj(b, v);
+          if (r < kb && c < kb && r >= c) Lc0[(c0 + r) + c * ld] = dacc[a][b][v];
+          if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = acc[a][b][v];
+        }
+    __syncthreads();
+    if (tid == 0) set_flag(pd_done + wb + tj, 1);
+    return;
+  }
   if (diag) {
     // diagonal block: F - Y Y^T, identity past kb, zero above the diagonal
 #pragma unroll
@@ -926,7 +977,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
           const int r = oi(a), c = oj(b, v);
           T val;
           if (r < kb && c < kb && r >= c)
-            val = fd[a][b][v] - dacc[a][b][v];
+            val = dacc[a][b][v];
           else
             val = (r == c && r >= kb) ? T(1) : T(0);
           Cs[c * kDiagLd + r] = val;
@@ -935,9 +986,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     diag_factor_inverse<T>(Cs, Ws, Tmp, kb, f + c0, N.fail);
     for (int t = tid; t < kb * kb; t += kThreads) {
       const int c = t / kb, r = t - c * kb;
-      if (r >= c) Lp[(c0 + r) + (int64_t)(c0 + c) * ld] = Cs[c * kDiagLd + r];
+      if (r >= c) Lc0[(c0 + r) + c * ld] = Cs[c * kDiagLd + r];
     }
-    T* Wout = winv + S.woff[wb + tk.j];  // kb x kb, column-major
+    T* Wout = winv + S.woff[wb + tj];  // kb x kb, column-major
     for (int t = tid; t < kb * kb; t += kThreads) {
       const int c = t / kb, r = t - c * kb;
       Wout[t] = Ws[c * kDiagLd + r];
@@ -961,7 +1012,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   }
   __syncthreads();
   {
-    const T* Win = winv + S.woff[wb + tk.j];  // Win[c * kb + r] = W[r][c]
+    const T* Win = winv + S.woff[wb + tj];  // Win[c * kb + r] = W[r][c]
     for (int t = tid; t < kPanel * kPanel; t += kThreads) {
       const int kk = t / kPanel, c = t - kk * kPanel;
       Ws[kk * kDiagLd + c] = (kk < kb && c < kb) ? Win[kk * kb + c] : T(0);  // W[c][kk]
@@ -970,7 +1021,39 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   __syncthreads();
   trsm_rows();
   __syncthreads();
-  if (tid == 0) set_flag(done + tk.t, 1);
+  if (tid == 0) set_flag(done + tt, 1);
+  };
+
+  // Chain of the diagonal blocks of one front (kind 2): block j applies
+  // only block j - 1 (the rest was pre-accumulated in place), factors, and
+  // solves its row tile 1, which is block j + 1's last operand.  Other
+  // kinds run one step.  (One call site keeps a single inlined copy.)
+  const int nsteps = tk.kind == 2 ? (w + TT - 1) / TT : 1;
+  for (int it = 0; it < nsteps; ++it) {
+    int mode = 0, tj = tk.j, tt = tk.t, kstart = 0, kend = tk.j * TT;
+    if (tk.kind == 2) {
+      tj = it;
+      tt = 0;
+      kstart = it > 0 ? (it - 1) * TT : 0;
+      kend = it * TT;
+      if (it >= 2) {
+        if (tid == 0) {
+          wait_at_least(pd_done + wb + it, 1, hang);
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+      }
+    } else if (tk.kind == 1) {
+      mode = 1;
+      kstart = tk.p0 * TT;
+      kend = min(w, tk.p1 * TT);
+    } else if (tk.kind == 3) {
+      mode = 3;
+      tt = 0;
+      kend = (tk.j - 1) * TT;
+    }
+    step(mode, tj, tt, kstart, kend);
+  }
 }
 
 template <typename T>
@@ -1518,11 +1601,14 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
 
 template <typename T>
 void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
-                  int64_t count, int32_t* flow, int64_t ntiles, int level, int nlevels,
-                  hipStream_t st) {
+                  int64_t count, int32_t* flow, int64_t ntiles, int64_t nblocks, int64_t nucount,
+                  int level, int nlevels, hipStream_t st) {
   if (count <= 0) return;
-  k_front<T><<<(unsigned)count, kThreads, 0, st>>>(S, N, winv, tasks, (int)count, flow,
-                                                   flow + ntiles + level, flow + ntiles + nlevels);
+  int32_t* pd_done = flow + ntiles;
+  int32_t* ucount = pd_done + nblocks;
+  int32_t* tickets = ucount + nucount;
+  k_front<T><<<(unsigned)count, kThreads, 0, st>>>(S, N, winv, tasks, (int)count, flow, pd_done,
+                                                   ucount, tickets + level, tickets + nlevels);
 }
 
 template <typename T>
@@ -1636,7 +1722,7 @@ void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t 
   template void launch_gemm<T>(const DevNum<T>&, const GemmProb*, const GemmTile*, int64_t, int,  \
                                hipStream_t);                                                     \
   template void launch_front<T>(const DevSym&, const DevNum<T>&, T*, const FrontTask*, int64_t,   \
-                                int32_t*, int64_t, int, int, hipStream_t);                       \
+                                int32_t*, int64_t, int64_t, int64_t, int, int, hipStream_t);     \
   template void launch_permute_in<T>(const DevSym&, const double*, int64_t, T*, int64_t,          \
                                      const double*, hipStream_t);                                \
   template void launch_permute_out<T>(const DevSym&, const T*, double*, int64_t, int64_t,         \

@@ -198,6 +198,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
   P.probs.clear();
   P.tiles.clear();
   P.ftasks.clear();
+  P.nucount = 0;
   // Problems of one update launch group; tiles are emitted per tile size so
   // that every launch uses a single tile shape.
   std::vector<int32_t> group;
@@ -262,25 +263,88 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
       P.steps.push_back(st);
     }
     if (front_mode == 0) {
-      // Dataflow: pivot blocks in column order across the level's fronts,
-      // then the update-matrix tiles.  Every task depends only on tasks
-      // with smaller tickets.
+      // Dataflow: pivot blocks in column order across the level's fronts;
+      // the update-matrix tiles of a front in ranges of kURange pivot
+      // blocks, each range right after the last column it needs.  Every task
+      // depends only on tasks with smaller tickets.
       Step st{kStepFront, h, (int64_t)P.ftasks.size(), 0};
-      for (int32_t j = 0; j * kPanel < wmax; ++j)
-        for (int32_t s : big) {
+      std::vector<int32_t> ubase(big.size());
+      for (size_t bi = 0; bi < big.size(); ++bi) {
+        const int32_t s = big[bi];
+        const int32_t r = S.front_m[s] - (S.sptr[s + 1] - S.sptr[s]);
+        const int32_t nt = (r + kPanel - 1) / kPanel;
+        ubase[bi] = (int32_t)P.nucount;
+        P.nucount += (int64_t)nt * (nt + 1) / 2;
+      }
+      // Range k of a front (pivot blocks [8k, 8k+8)) is emitted in kURange
+      // chunks after the columns 8k+8 ... 8k+15, so that its tasks take
+      // workgroup slots when their inputs are complete and interleave with
+      // the pivot-block tasks that carry the critical path; what is left
+      // when the level's columns end is emitted then.
+      std::vector<std::vector<FrontTask>> pending(big.size());
+      std::vector<size_t> pending_pos(big.size(), 0);
+      auto emit_u = [&](size_t bi, size_t upto) {
+        upto = std::min(upto, pending[bi].size());
+        for (; pending_pos[bi] < upto; ++pending_pos[bi]) P.ftasks.push_back(pending[bi][pending_pos[bi]]);
+      };
+      const int32_t ncols = (wmax + kPanel - 1) / kPanel;
+      // Fronts with at least kChainMin pivot blocks run their diagonal blocks
+      // as one chain task (first in ticket order) when the level has few
+      // of them; their block j >= 2 is pre-accumulated by a task issued
+      // right after column j - 2.
+      std::vector<char> chain(big.size(), 0);
+      {
+        int nchain = 0;
+        for (int32_t s : big)
+          if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= kChainMin) ++nchain;
+        if (nchain <= kMaxChains)
+          for (size_t bi = 0; bi < big.size(); ++bi) {
+            const int32_t s = big[bi];
+            if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= kChainMin) {
+              chain[bi] = 1;
+              P.ftasks.push_back({s, 0, 0, 2, 0, 0, 0, 0});
+            }
+          }
+      }
+      for (int32_t j = 0; j < ncols; ++j) {
+        for (size_t bi = 0; bi < big.size(); ++bi) {
+          const int32_t s = big[bi];
           const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
           if (j * kPanel >= w) continue;
           // the diagonal task (t = 0) also produces row tile 1
           const int nt = front_block_tiles(m, w, j);
-          for (int t = 0; t < nt; ++t)
-            if (t != 1) P.ftasks.push_back({s, j, t, 0});
+          for (int t = chain[bi] ? 2 : 0; t < nt; ++t)
+            if (t != 1) P.ftasks.push_back({s, j, t, 0, 0, 0, 0, 0});
+          if (chain[bi] && (j + 2) * kPanel < w) P.ftasks.push_back({s, j + 2, 0, 3, 0, 0, 0, 0});
         }
-      for (int32_t s : big) {
-        const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], r = m - w;
-        const int32_t nt = (r + kPanel - 1) / kPanel;
-        for (int32_t j = 0; j < nt; ++j)
-          for (int32_t t = j; t < nt; ++t) P.ftasks.push_back({s, j, t, 1});
+        for (size_t bi = 0; bi < big.size(); ++bi) {
+          const int32_t s = big[bi];
+          const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+          const int32_t pb = (w + kPanel - 1) / kPanel;
+          if (r <= 0) continue;
+          if (j < pb && ((j + 1) % kURange == 0 || j + 1 == pb)) {
+            // range ending at column j: queue its tasks
+            const int32_t rk = j / kURange, p0 = rk * kURange, p1 = j + 1;
+            const int32_t nt = (r + kPanel - 1) / kPanel;
+            for (int32_t b = 0; b < nt; ++b)
+              for (int32_t a = b; a < nt; ++a) {
+                const int32_t ui = ubase[bi] + a * (a + 1) / 2 + b;
+                pending[bi].push_back({s, b, a, 1, p0, p1, ui, rk});
+              }
+          }
+          // release the queued tasks of the range that ended kURange columns
+          // ago in proportion to the columns passed since
+          const int32_t per = (int32_t)((r + kPanel - 1) / kPanel);
+          const size_t range_tasks = (size_t)per * (per + 1) / 2;
+          if (j >= kURange) {
+            const int32_t rk = (j - kURange) / kURange;       // range being released
+            const int32_t q = (j - kURange) % kURange + 1;    // chunks released so far
+            const size_t base = (size_t)rk * range_tasks;
+            if (rk * kURange < pb) emit_u(bi, base + range_tasks * q / kURange);
+          }
+        }
       }
+      for (size_t bi = 0; bi < big.size(); ++bi) emit_u(bi, pending[bi].size());
       st.end = (int64_t)P.ftasks.size();
       for (int32_t s : big) {
         const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s], r = m - w;

@@ -69,10 +69,20 @@ struct GemmTile {
 // ticket order).  kind 0: pivot block j of front s (columns [64j, 64j+kb)),
 // row tile t: t = 0 is the diagonal block (kb rows) together with row tile
 // 1, t >= 2 the 64 rows starting at 64j + kb + 64(t-1).  kind 1: tile (t, j)
-// of the update matrix U_s (rows 64t.., columns 64j..), t >= j.
+// of the update matrix U_s (rows 64t.., columns 64j..), t >= j, for the
+// pivot blocks [p0, p1): the rk-th such range of the tile, applied after
+// range rk-1 (counter ui of the tile orders them).  kind 2: the chain of
+// diagonal blocks of front s (all its t = 0 work, in order).  kind 3:
+// pre-accumulation of diagonal block j and row tile 1 of front s over the
+// pivot blocks before j - 1, for the chain.
 struct FrontTask {
   int32_t s, j, t, kind;
+  int32_t p0, p1, ui, rk;
 };
+
+constexpr int kURange = 8;     // pivot blocks per update-matrix task
+constexpr int kChainMin = 3;   // pivot blocks from which a front's diagonal blocks form a chain
+constexpr int kMaxChains = 32; // chains per level (each holds one workgroup slot for the level)
 
 enum StepKind : int32_t {
   kStepSmall = 0,
@@ -120,6 +130,7 @@ struct Plan {
   // dataflow factorization: per pivot block the index of its first row tile's
   // completion flag (prefix sums of front_block_tiles; one entry past the end)
   std::vector<int32_t> tbase;
+  int64_t nucount = 0;  // update-matrix tile counters (one per tile of every large front)
   std::vector<int32_t> a_pos;   // per A entry: row + col*ldL inside the front panel
   std::vector<int32_t> diag_q;  // per permuted column: A entry of the diagonal (-1: absent)
 

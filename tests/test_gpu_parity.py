@@ -58,6 +58,7 @@ CASES = [
     ("fv3d_12", lambda: gen.fv3d(12, seed=1)),
     ("fv3d_17x13x11", lambda: gen.fv3d(17, 13, 11, seed=7)),
     ("fv3d_24", lambda: gen.fv3d(24, seed=8)),
+    ("fv3d_36", lambda: gen.fv3d(36, seed=8)),  # fronts wider than 512 with update matrices
     ("fv2d_45x37", lambda: gen.fv2d(45, 37, seed=3)),
     ("landice_9x8x4", lambda: gen.landice(9, 8, 4, seed=3)),
     ("random_500", lambda: gen.random_spd_pattern(500, 0.01, seed=5)),
