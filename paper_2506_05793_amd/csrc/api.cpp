@@ -91,9 +91,9 @@ struct tacho_sym {
   int device = -1;
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
       d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
-      d_wbase, d_woff, d_tbase, d_gather;
-  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fwd_items,
-      d_bwd_items, d_fwd_red, d_bwd_red, d_tri_fwd, d_tri_bwd;
+      d_wbase, d_woff, d_tbase, d_sparent, d_pull_ptr, d_pull_src, d_part_base;
+  DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fsolve, d_bsolve,
+      d_wave_list, d_lwave, d_llarge;
   DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
   DevSym view{};
   std::mutex mu;
@@ -187,6 +187,7 @@ struct tacho_num {
 namespace {
 
 constexpr int kRhs = 16;  // right-hand sides per solve sweep
+constexpr int kRowBytes = 128;  // bytes per row of the solve vectors (one cache line, >= kRhs doubles)
 
 tacho_options defaults() {
   tacho_options o;
@@ -276,7 +277,10 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_wbase, P.wbase));
   HIP_TRY(upload(h->d_woff, P.woff));
   HIP_TRY(upload(h->d_tbase, P.tbase));
-  HIP_TRY(upload(h->d_gather, P.gather_list));
+  HIP_TRY(upload(h->d_sparent, S.sparent));
+  HIP_TRY(upload(h->d_pull_ptr, P.pull_ptr));
+  HIP_TRY(upload(h->d_pull_src, P.pull_src));
+  HIP_TRY(upload(h->d_part_base, P.part_base));
   HIP_TRY(upload(h->d_small, P.small_list));
   HIP_TRY(upload(h->d_asm, P.asm_items));
   HIP_TRY(upload(h->d_diag, P.diag_items));
@@ -285,12 +289,11 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_tiles, P.tiles));
   HIP_TRY(upload(h->d_ftasks, P.ftasks));
   HIP_TRY(upload(h->d_levels, S.level_list));
-  HIP_TRY(upload(h->d_fwd_items, P.fwd_items));
-  HIP_TRY(upload(h->d_bwd_items, P.bwd_items));
-  HIP_TRY(upload(h->d_fwd_red, P.fwd_red));
-  HIP_TRY(upload(h->d_bwd_red, P.bwd_red));
-  HIP_TRY(upload(h->d_tri_fwd, P.tri_fwd));
-  HIP_TRY(upload(h->d_tri_bwd, P.tri_bwd));
+  HIP_TRY(upload(h->d_fsolve, P.fsolve));
+  HIP_TRY(upload(h->d_bsolve, P.bsolve));
+  HIP_TRY(upload(h->d_wave_list, P.wave_list));
+  HIP_TRY(upload(h->d_lwave, P.lwave));
+  HIP_TRY(upload(h->d_llarge, P.llarge));
   HIP_TRY(upload(h->d_rowptr, S.A.rowptr));
   HIP_TRY(upload(h->d_colind, S.A.colind));
   HIP_TRY(upload(h->d_mirror, h->mirror));
@@ -318,6 +321,10 @@ int ensure_uploaded(tacho_sym* h) {
   v.wbase = h->d_wbase.as<int32_t>();
   v.woff = h->d_woff.as<int64_t>();
   v.tbase = h->d_tbase.as<int32_t>();
+  v.sparent = h->d_sparent.as<int32_t>();
+  v.pull_ptr = h->d_pull_ptr.as<int32_t>();
+  v.pull_src = h->d_pull_src.as<int32_t>();
+  v.part_base = h->d_part_base.as<int32_t>();
   h->device = dev;
   h->uploaded = true;
   return TACHO_OK;
@@ -335,6 +342,11 @@ int64_t flow_ints(const tacho_sym* h) {
   return flow_ntiles(h) + (int64_t)h->P.woff.size() + h->P.nucount + h->S.nlevels + 1;
 }
 
+// Dataflow solves: three completion counters per supernode, one
+// partial-product counter per diagonal block, two tickets, then the hang
+// flag (cleared once, when the handle is created).
+int64_t solve_counters(const tacho_sym* h) { return 3 * (int64_t)h->S.ns + (int64_t)h->P.woff.size() + 2; }
+
 int64_t numeric_bytes(const tacho_sym* h, int precision) {
   const size_t es = elem_size(precision);
   const Symbolic& S = h->S;
@@ -342,10 +354,10 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   int64_t b = 0;
   b += (int64_t)es * P.L_elems + (int64_t)es * P.U_elems + (int64_t)es * (int64_t)S.a_src.size();
   b += 8 * S.nnz_input + 4;
-  b += (int64_t)es * (S.n + P.u_elems) * kRhs;
+  b += (int64_t)kRowBytes * (S.n + P.u_elems);
   b += (int64_t)es * std::max<int64_t>(P.part_slots, 1) * kPanel * kRhs;
   b += (int64_t)es * P.W_elems;
-  b += 4 * (2 * S.nlevels + P.tri_flags + 1);
+  b += 4 * (solve_counters(h) + 1);
   b += 4 * flow_ints(h);
   if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;  // values, scaling
   return b;
@@ -539,10 +551,11 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   HIP_TRY(f->vals.alloc(sizeof(double) * S.nnz_input));
   HIP_TRY(f->fail.alloc(sizeof(int32_t)));
   HIP_TRY(f->winv.alloc(es * std::max<int64_t>(P.W_elems, 1)));
-  HIP_TRY(f->y.alloc(es * S.n * kRhs));
-  HIP_TRY(f->uvec.alloc(es * P.u_elems * kRhs));
+  HIP_TRY(f->y.alloc((size_t)kRowBytes * S.n));
+  HIP_TRY(f->uvec.alloc((size_t)kRowBytes * std::max<int64_t>(P.u_elems, 1)));
   HIP_TRY(f->part.alloc(es * std::max<int64_t>(P.part_slots, 1) * kPanel * kRhs));
-  HIP_TRY(f->sync.alloc(sizeof(int32_t) * (2 * S.nlevels + P.tri_flags + 1)));
+  HIP_TRY(f->sync.alloc(sizeof(int32_t) * (solve_counters(h) + 1)));
+  HIP_TRY(hipMemset(f->sync.p, 0, sizeof(int32_t) * (solve_counters(h) + 1)));
   HIP_TRY(f->flow.alloc(sizeof(int32_t) * flow_ints(h)));
   if (precision == TACHO_FP32) {
     HIP_TRY(f->scale.alloc(sizeof(double) * S.n));
@@ -565,6 +578,20 @@ int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index) {
   return refactor(f->fallback, f->vals.as<double>(), 1, st, 1, fail_index);
 }
 
+// Error if a wait of this handle's dataflow solves (or of its FP64
+// fallback's) timed out; the flag stays raised.  Synchronizes st.
+int check_solve_hang(tacho_num* f, hipStream_t st) {
+  int32_t hang[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&hang[0], f->sync.as<int32_t>() + solve_counters(f->sym), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, st));
+  if (f->fallback)
+    HIP_TRY(hipMemcpyAsync(&hang[1], f->fallback->sync.as<int32_t>() + solve_counters(f->sym),
+                           sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hang[0] || hang[1]) return fail(TACHO_ERR_HIP, "dataflow solve: a dependency wait timed out");
+  return TACHO_OK;
+}
+
 // One sweep of forward + backward substitution for up to kRhs columns,
 // b (FP64, ld ldb) -> x (FP64, ld ldx), x += result when accumulate.
 template <typename T>
@@ -573,55 +600,48 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   tacho_sym* h = f->sym;
   const Symbolic& S = h->S;
   const DevSym& V = h->view;
+  const Plan& P = h->P;
   const double* scale = f->precision == TACHO_FP32 && h->opt.scale ? f->scale.as<double>() : nullptr;
   T* y = f->y.as<T>();
-  T* uv = f->uvec.as<T>();
   const T* L = f->L.as<T>();
-  const int32_t* lv = h->d_levels.as<int32_t>();
-  const Plan& P = h->P;
+  const T* winv = f->winv.as<T>();
   const double es = sizeof(T);
-  int pe = f->prof.begin(st);
-  launch_permute_in<T>(V, b, ldb, y, nrhs, scale, st);
-  f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * nrhs * (8.0 + es) + 4.0 * S.n);
-  const GemvItem* fwi = h->d_fwd_items.as<GemvItem>();
-  const GemvItem* bwi = h->d_bwd_items.as<GemvItem>();
-  const ReduceItem* fri = h->d_fwd_red.as<ReduceItem>();
-  const ReduceItem* bri = h->d_bwd_red.as<ReduceItem>();
-  T* part = f->part.as<T>();
-  const TriItem* tfw = h->d_tri_fwd.as<TriItem>();
-  const TriItem* tbw = h->d_tri_bwd.as<TriItem>();
+  const int width = nrhs == 1 ? 1 : kRhs;  // values per row of y and of the update vectors
+  const int64_t ns = S.ns, nblk = (int64_t)P.woff.size();
   int32_t* counters = f->sync.as<int32_t>();
-  int32_t* flags = counters + 2 * S.nlevels;
-  launch_fill_i32(counters, 0, 2 * S.nlevels + P.tri_flags, st);
+  int32_t* hang = counters + solve_counters(h);
+  const int32_t* waves = h->d_wave_list.as<int32_t>();
+  double lentries = 0, rows = 0;
   for (int32_t lvl = 0; lvl < S.nlevels; ++lvl) {
-    const int64_t t0 = P.tri_ptr[lvl], t1 = P.tri_ptr[lvl + 1];
-    pe = f->prof.begin(st);
-    launch_fwd<T>(V, L, y, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
-                  nrhs, st);
-    launch_fwd_tri<T>(V, L, f->winv.as<T>(), y, tfw + t0, t1 - t0, counters + 2 * lvl, flags,
-                      nrhs, st);
-    launch_fwd_gemv<T>(V, L, y, part, fwi + P.fwd_ptr[lvl], P.fwd_ptr[lvl + 1] - P.fwd_ptr[lvl],
-                       fri + P.fred_ptr[lvl], P.fred_ptr[lvl + 1] - P.fred_ptr[lvl], uv, nrhs, st);
-    f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * P.level_lentries[lvl] * nrhs,
-                es * (P.level_lentries[lvl] + 2.0 * P.level_rows[lvl] * nrhs));
+    lentries += P.level_lentries[lvl];
+    rows += P.level_rows[lvl];
   }
-  for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl) {
-    const int64_t t0 = P.tri_ptr[lvl], t1 = P.tri_ptr[lvl + 1];
-    pe = f->prof.begin(st);
-    launch_bwd_gather<T>(V, y, uv, h->d_gather.as<int32_t>() + P.gather_ptr[lvl],
-                         P.gather_ptr[lvl + 1] - P.gather_ptr[lvl], nrhs, st);
-    launch_bwd_gemv<T>(V, L, uv, part, bwi + P.bwd_ptr[lvl], P.bwd_ptr[lvl + 1] - P.bwd_ptr[lvl],
-                       bri + P.bred_ptr[lvl], P.bred_ptr[lvl + 1] - P.bred_ptr[lvl], y, nrhs, st);
-    launch_bwd_tri<T>(V, L, f->winv.as<T>(), y, tbw + t0, t1 - t0, counters + 2 * lvl + 1, flags,
-                      nrhs, st);
-    launch_bwd<T>(V, L, y, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl], nrhs,
-                  st);
-    f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * P.level_lentries[lvl] * nrhs,
-                es * (P.level_lentries[lvl] + 2.0 * P.level_rows[lvl] * nrhs));
-  }
+  int pe = f->prof.begin(st);
+  launch_solve_in<T>(V, b, ldb, y, nrhs, scale, counters, ns, nblk, st);
+  f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
+  const WaveItem* items = h->d_lwave.as<WaveItem>();
+  const int32_t* large = h->d_llarge.as<int32_t>();
   pe = f->prof.begin(st);
-  launch_permute_out<T>(V, y, x, ldx, nrhs, scale, accumulate, st);
-  f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * nrhs * (8.0 + es) + 4.0 * S.n);
+  for (int32_t lvl = 0; lvl < P.solve_split; ++lvl)
+    launch_level_fwd<T>(V, L, winv, y, f->uvec.as<T>(), items + P.lwave_ptr[lvl],
+                        P.lwave_ptr[lvl + 1] - P.lwave_ptr[lvl], large + P.llarge_ptr[lvl],
+                        P.llarge_ptr[lvl + 1] - P.llarge_ptr[lvl], waves, nrhs, counters, ns, nblk,
+                        hang, st);
+  launch_solve_fwd<T>(V, L, winv, y, f->uvec.as<T>(), h->d_fsolve.as<SolveTask>(),
+                      (int64_t)P.fsolve.size(), waves, nrhs, counters, ns, nblk, hang, st);
+  f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
+  pe = f->prof.begin(st);
+  launch_solve_bwd<T>(V, L, winv, y, f->part.as<T>(), h->d_bsolve.as<SolveTask>(),
+                      (int64_t)P.bsolve.size(), waves, nrhs, counters, ns, nblk, hang, st);
+  for (int32_t lvl = P.solve_split - 1; lvl >= 0; --lvl)
+    launch_level_bwd<T>(V, L, winv, y, f->part.as<T>(), items + P.lwave_ptr[lvl],
+                        P.lwave_ptr[lvl + 1] - P.lwave_ptr[lvl], large + P.llarge_ptr[lvl],
+                        P.llarge_ptr[lvl + 1] - P.llarge_ptr[lvl], waves, nrhs, counters, ns, nblk,
+                        hang, st);
+  f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
+  pe = f->prof.begin(st);
+  launch_solve_out<T>(V, y, x, ldx, nrhs, scale, accumulate, st);
+  f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
 }
 
 template <typename T>
@@ -732,7 +752,7 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
     }
     info->relres_max = mx;
   }
-  return TACHO_OK;
+  return check_solve_hang(f, st);
 }
 
 }  // namespace
@@ -904,6 +924,10 @@ int tacho_refactorize(tacho_num_t f, const double* values, int values_on_device,
 int tacho_check_factor(tacho_num_t f, int64_t* fail_index) {
   if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
   if (f->pending) return read_fail_flag(f, fail_index);
+  if (f->sync.p) {
+    const int rc = check_solve_hang(f, f->last_stream);
+    if (rc != TACHO_OK) return rc;
+  }
   if (fail_index) *fail_index = f->last_fail;
   return f->last_status;
 }
@@ -962,6 +986,10 @@ int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t
                              nrhs, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                              st));
     if (!on_device) HIP_TRY(hipStreamSynchronize(st));
+  }
+  if (!on_device) {
+    const int rc = check_solve_hang(f, st);
+    if (rc != TACHO_OK) return rc;
   }
   HIP_TRY(hipGetLastError());
   return TACHO_OK;

@@ -33,6 +33,10 @@ struct DevSym {
   const int32_t* wbase;      // per supernode: first diagonal-inverse block (-1: none)
   const int64_t* woff;       // per diagonal-inverse block: element offset
   const int32_t* tbase;      // per pivot block: first row-tile completion flag
+  const int32_t* sparent;    // per supernode: parent (-1: root)
+  const int32_t* pull_ptr;   // per front row (rows_ptr indexing): first extend-add source
+  const int32_t* pull_src;   // update-vector entry of each source
+  const int32_t* part_base;  // per diagonal block: first backward partial-product slot
 };
 
 template <typename T>
@@ -77,40 +81,40 @@ void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask*
                   int64_t count, int32_t* flow, int64_t ntiles, int64_t nblocks, int64_t nucount,
                   int level, int nlevels, hipStream_t st);
 
-// Solves: y is the permuted right-hand side / solution (n x nrhs, ld n).
+// Dataflow solves of nrhs <= 16 right-hand sides.  y (n rows of 1 value
+// when nrhs = 1, else of 16) receives P b in solve_in, is solved forward and
+// backward in place, and x = P^T y leaves in solve_out.  uvec holds the
+// update vectors (u_elems rows of the same width), part the backward partial
+// products (part_slots x 64 x 16).  counters: 3 ns + nblk + 2 ints, cleared
+// by solve_in; hang is raised (never cleared here) if a wait times out.
 template <typename T>
-void launch_permute_in(const DevSym& S, const double* b, int64_t ldb, T* y, int64_t nrhs,
-                       const double* scale, hipStream_t st);
-template <typename T>
-void launch_permute_out(const DevSym& S, const T* y, double* x, int64_t ldx, int64_t nrhs,
-                        const double* scale, int accumulate, hipStream_t st);
-template <typename T>
-void launch_fwd(const DevSym& S, const T* L, T* y, T* uvec, const int32_t* list, int64_t count,
-                int32_t nrhs, hipStream_t st);
-template <typename T>
-void launch_bwd(const DevSym& S, const T* L, T* y, const int32_t* list, int64_t count,
-                int32_t nrhs, hipStream_t st);
-
-// L21 products of split fronts (matrix-core tiles into `part`, then a
-// fixed-order reduction): forward uvec -= L21 x_s, backward y_s -= L21^T u_s.
-template <typename T>
-void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* part, const GemvItem* items,
-                     int64_t count, const ReduceItem* red, int64_t nred, T* uvec, int32_t nrhs,
+void launch_solve_in(const DevSym& S, const double* b, int64_t ldb, T* y, int nrhs,
+                     const double* scale, int32_t* counters, int64_t ns, int64_t nblk,
                      hipStream_t st);
 template <typename T>
-void launch_bwd_gemv(const DevSym& S, const T* L, const T* uvec, T* part, const GemvItem* items,
-                     int64_t count, const ReduceItem* red, int64_t nred, T* y, int32_t nrhs,
-                     hipStream_t st);
+void launch_solve_fwd(const DevSym& S, const T* L, const T* winv, T* y, T* uvec,
+                      const SolveTask* tasks, int64_t count, const int32_t* wave_list, int nrhs,
+                      int32_t* counters, int64_t ns, int64_t nblk, int32_t* hang, hipStream_t st);
 template <typename T>
-void launch_bwd_gather(const DevSym& S, const T* y, T* uvec, const int32_t* list, int64_t count,
-                       int32_t nrhs, hipStream_t st);
-
+void launch_solve_bwd(const DevSym& S, const T* L, const T* winv, T* y, T* part,
+                      const SolveTask* tasks, int64_t count, const int32_t* wave_list, int nrhs,
+                      int32_t* counters, int64_t ns, int64_t nblk, int32_t* hang, hipStream_t st);
+// Level-by-level phase of the solves: one launch per level (wave items and
+// large fronts of that level); forward before the dataflow launch, backward
+// after it.
 template <typename T>
-void launch_fwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
-                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st);
+void launch_level_fwd(const DevSym& S, const T* L, const T* winv, T* y, T* uvec,
+                      const WaveItem* items, int64_t nitems, const int32_t* large, int64_t nlarge,
+                      const int32_t* wave_list, int nrhs, int32_t* counters, int64_t ns,
+                      int64_t nblk, int32_t* hang, hipStream_t st);
 template <typename T>
-void launch_bwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
-                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st);
+void launch_level_bwd(const DevSym& S, const T* L, const T* winv, T* y, T* part,
+                      const WaveItem* items, int64_t nitems, const int32_t* large, int64_t nlarge,
+                      const int32_t* wave_list, int nrhs, int32_t* counters, int64_t ns,
+                      int64_t nblk, int32_t* hang, hipStream_t st);
+template <typename T>
+void launch_solve_out(const DevSym& S, const T* y, double* x, int64_t ldx, int nrhs,
+                      const double* scale, int accumulate, hipStream_t st);
 
 // FP64 refinement helpers: r = b - A x (original numbering, CSR), column norms.
 void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,

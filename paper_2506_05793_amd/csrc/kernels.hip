@@ -25,6 +25,15 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kDiagLd = kPanel + 1;  // LDS leading dimension of diagonal blocks
 
+// Row stride of the solve vectors (y and the update vectors): one 128-byte
+// cache line per row, whatever the number of right-hand sides, so that rows
+// written by different workgroups never share a line.  The L2 caches of the
+// XCDs are not coherent with each other, and with 8-byte rows (one
+// right-hand side) the dataflow solves gave intermittently wrong results,
+// which this layout removed.
+template <typename T>
+constexpr int kRowLd = 128 / (int)sizeof(T);
+
 template <typename T>
 struct Vec4;
 template <>
@@ -565,14 +574,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm(DevNum<T> N, const GemmProb* 
 }
 
 // ---------------------------------------------------------------------------
-// Solves.  y holds P b (n x nrhs, ld n) and receives P x.  Forward: each
-// front pulls its children's update vectors (ascending), solves its diagonal
-// block in 64-column blocks (one wave per right-hand side, register shuffles)
-// and subtracts L21 x from the rows below; rows >= w go to its own update
-// vector u_s (r x nrhs in uvec).  Backward: x_s = L11^{-T}(y_s - L21^T x[rows]).
-constexpr int kRhsBlock = 16;
-
-template <typename T>
+// Solve input and output: y (row-major, NR values per row) = P b, scaled by
+// the Jacobi factors on the FP32 path; x = P^T y (or x += P^T y).
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_permute_in(DevSym S, const double* b, int64_t ldb,
                                                          T* y, int64_t nrhs,
                                                          const double* scale) {
@@ -580,10 +584,11 @@ __global__ __launch_bounds__(kThreads) void k_permute_in(DevSym S, const double*
   if (i >= S.n) return;
   const int64_t src = S.perm[i];
   const double d = scale ? scale[i] : 1.0;
-  for (int64_t c = 0; c < nrhs; ++c) y[i + c * S.n] = (T)(b[src + c * ldb] * d);
+#pragma unroll
+  for (int c = 0; c < NR; ++c) y[i * kRowLd<T> + c] = c < nrhs ? (T)(b[src + c * ldb] * d) : T(0);
 }
 
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_permute_out(DevSym S, const T* y, double* x,
                                                           int64_t ldx, int64_t nrhs,
                                                           const double* scale, int accumulate) {
@@ -592,7 +597,7 @@ __global__ __launch_bounds__(kThreads) void k_permute_out(DevSym S, const T* y, 
   const int64_t dst = S.perm[i];
   const double d = scale ? scale[i] : 1.0;
   for (int64_t c = 0; c < nrhs; ++c) {
-    const double v = (double)y[i + c * S.n] * d;
+    const double v = (double)y[i * kRowLd<T> + c] * d;
     if (accumulate)
       x[dst + c * ldx] += v;
     else
@@ -600,31 +605,32 @@ __global__ __launch_bounds__(kThreads) void k_permute_out(DevSym S, const T* y, 
   }
 }
 
-// Split fronts (solve_split_front) leave their L11 solves to the pipelined
-// kernels k_fwd_tri / k_bwd_tri and their L21 products to k_fwd_gemv /
-// k_bwd_gemv.
-__device__ inline bool solve_split(int w, int r) { return solve_split_front(w, r); }
+// Cross-workgroup ordering at agent scope.  The L2 caches of the XCDs are
+// not coherent with each other: a producer writes its L2 back before
+// raising a flag, a consumer invalidates its caches after seeing one.  The
+// sequences are written out so that the wait after the writeback (or the
+// invalidate) is always there; the compiler drops that wait when the wave
+// has no stores of its own pending, and the flag could then overtake the
+// writeback.
+__device__ inline void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ inline void release_agent() {
+  asm volatile("buffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+__device__ inline void acquire_agent() {
+  asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
 
-// Ready flags of the pipelined L11 solves.  A workgroup waits only for blocks
-// whose tickets are smaller than its own, and tickets are taken from an
-// atomic counter by running workgroups, so every awaited block belongs to a
-// workgroup that is already resident; the spin is bounded all the same.
-constexpr int kSpinLimit = 1 << 25;
-
-// Waits poll with relaxed atomic loads and order the caller's later loads
-// with one acquire fence once the value is seen, so that polling does not
-// invalidate caches that other workgroups are using.
-__device__ inline void wait_flag(const int32_t* flag, int32_t value) {
-  int spins = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value) {
-    __builtin_amdgcn_s_sleep(1);
-    if (++spins > kSpinLimit) break;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// Workgroup barrier after which thread 0 publishes the workgroup's global
+// stores: every wave first waits until its stores have reached its L2, so
+// the one writeback that thread 0 issues after the barrier covers them all.
+__device__ inline void publish_barrier() {
+  wait_vm();
+  __syncthreads();
 }
 
 __device__ inline void set_flag(int32_t* flag, int32_t value) {
-  __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  release_agent();
+  __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Bounded wait for *flag >= value (acquire).  A dependency of the dataflow
@@ -816,7 +822,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
           block_done(q, true);
           ++q;
           while (q < nblk && block_done(q, false)) ++q;
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          acquire_agent();
           s_ready = q;
         }
         __syncthreads();
@@ -880,7 +886,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     // ranges of one update-matrix tile are applied in order
     if (tid == 0) {
       wait_at_least(ucount + tk.ui, tk.rk, hang);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      acquire_agent();
     }
     __syncthreads();
   }
@@ -898,7 +904,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
           if (i < arows && jj < bcols && gi >= gj) Cu[gi + (int64_t)gj * ldc] = acc[a][b][v];
         }
     if (tk.p1 * TT < w) {  // a later range of this tile follows
-      __syncthreads();
+      publish_barrier();
       if (tid == 0) set_flag(ucount + tk.ui, tk.rk + 1);
     }
     return;
@@ -962,7 +968,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
           if (r < kb && c < kb && r >= c) Lc0[(c0 + r) + c * ld] = dacc[a][b][v];
           if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = acc[a][b][v];
         }
-    __syncthreads();
+    publish_barrier();
     if (tid == 0) set_flag(pd_done + wb + tj, 1);
     return;
   }
@@ -993,14 +999,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       const int c = t / kb, r = t - c * kb;
       Wout[t] = Ws[c * kDiagLd + r];
     }
-    __syncthreads();
+    publish_barrier();
     if (tid == 0) set_flag(done, 1);  // release: the workgroup's stores are in L2 after the barrier
     if (!fuse1) return;
     // row tile 1 (still in registers) against the inverse in LDS
     stage_rows();
     __syncthreads();
     trsm_rows();
-    __syncthreads();
+    publish_barrier();
     if (tid == 0) set_flag(done + 1, 1);
     return;
   }
@@ -1008,7 +1014,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   stage_rows();
   if (tid == 0) {
     wait_at_least(done, 1, hang);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    acquire_agent();
   }
   __syncthreads();
   {
@@ -1020,7 +1026,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   }
   __syncthreads();
   trsm_rows();
-  __syncthreads();
+  publish_barrier();
   if (tid == 0) set_flag(done + tt, 1);
   };
 
@@ -1039,7 +1045,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       if (it >= 2) {
         if (tid == 0) {
           wait_at_least(pd_done + wb + it, 1, hang);
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          acquire_agent();
         }
         __syncthreads();
       }
@@ -1056,434 +1062,614 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd(DevSym S, const T* L, T* y, T* uvec,
-                                                  const int32_t* list, int nrhs) {
-  __shared__ T D[kPanel * kDiagLd];
-  __shared__ T X[kPanel * kRhsBlock];
-  const int s = list[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
-  const int ldl = S.ldL[s];
-  const int64_t n = S.n;
-  const T* Lp = L + S.L_off[s];
-  T* us = uvec + S.u_off[s] * nrhs;
-  const bool split = solve_split(w, r);
-  for (int t = tid; t < r * nrhs; t += kThreads) us[t] = T(0);
-  __syncthreads();
+// ---------------------------------------------------------------------------
+// Dataflow solves (forward L y = P b, backward L^T x = y; the paper's
+// supernodal triangular solves with the inverted diagonal blocks of the
+// factorization, ordered by dependencies instead of by levels).
+//
+// y holds P b and receives P x, row-major with NR values per row (NR = 1 or
+// 16, columns past the caller's count are zero); the update vector u_s of a
+// front (r_s rows of NR) sits at uvec + u_off[s] NR.  One launch per sweep:
+// workgroups take tasks in the plan's ticket order, and a task waits only on
+// tasks with smaller tickets (children before parents forward, parents
+// before children backward, earlier blocks of its own front), so every wait
+// ends; the waits are bounded all the same and raise the hang flag.
+//
+// Completion counters (zero when a solve starts): xcnt[s] forward diagonal
+// blocks of s solved, in order; ucnt[s] forward L21 row blocks of s done (a
+// wave-solved front counts one); bcnt[s] backward diagonal blocks of s
+// solved, from the last (a wave-solved front counts one); pcnt[blk] backward
+// partial products of diagonal block blk done.
+struct SolveFlags {
+  int32_t* xcnt;
+  int32_t* ucnt;
+  int32_t* bcnt;
+  int32_t* pcnt;
+  int32_t* ticket;
+  int32_t* hang;
+};
+
+// Forward results of front c are complete when ucnt[c] reaches this.
+__device__ inline int fwd_need(const DevSym& S, int c) {
+  const int m = S.front_m[c], w = S.sptr[c + 1] - S.sptr[c];
+  return m <= kSmallMax ? 1 : (m - w + kPanel - 1) / kPanel;
+}
+// Backward results of front p are complete when bcnt[p] reaches this.
+__device__ inline int bwd_need(const DevSym& S, int p) {
+  const int m = S.front_m[p], w = S.sptr[p + 1] - S.sptr[p];
+  return m <= kSmallMax ? 1 : (w + kPanel - 1) / kPanel;
+}
+
+// One thread: relaxed polls until every child of s has its update vector.
+__device__ inline void wait_children(const DevSym& S, int s, const int32_t* ucnt, int32_t* hang) {
   for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
     const int c = S.child_list[q];
-    const int wc = S.sptr[c + 1] - S.sptr[c], rc = S.front_m[c] - wc;
-    const T* uc = uvec + S.u_off[c] * nrhs;
-    const int32_t* rm = S.rmap + S.rows_ptr[c] + wc;
-    for (int t = tid; t < rc * nrhs; t += kThreads) {
-      const int col = t / rc, i = t - col * rc;
-      const int tr = rm[i];
-      const T v = uc[i + col * rc];
-      if (tr < w)
-        y[f + tr + col * n] += v;
-      else
-        us[(tr - w) + col * r] += v;
-    }
-    __syncthreads();
-  }
-  if (split) return;  // L11 and L21 parts follow in k_fwd_tri / k_fwd_gemv
-  for (int jb = 0; jb < w; jb += kPanel) {
-    const int kb = min(kPanel, w - jb);
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, rr = t - c * kb;
-      if (rr >= c) D[c * kDiagLd + rr] = Lp[(jb + rr) + (int64_t)(jb + c) * ldl];
-    }
-    for (int t = tid; t < kb * nrhs; t += kThreads) {
-      const int col = t / kb, rr = t - col * kb;
-      X[rr + col * kPanel] = y[f + jb + rr + col * n];
-    }
-    __syncthreads();
-    for (int col = wave; col < nrhs; col += kThreads / 64) {
-      T z = lane < kb ? X[lane + col * kPanel] : T(0);
-      for (int c = 0; c < kb; ++c) {
-        const T xc = __shfl(z, c, 64) / D[c * kDiagLd + c];
-        if (lane == c)
-          z = xc;
-        else if (lane > c && lane < kb)
-          z -= D[c * kDiagLd + lane] * xc;
-      }
-      if (lane < kb) {
-        X[lane + col * kPanel] = z;
-        y[f + jb + lane + col * n] = z;
-      }
-    }
-    __syncthreads();
-    for (int i = jb + kb + tid; i < m; i += kThreads) {
-      T acc[kRhsBlock];
-#pragma unroll
-      for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
-      for (int c = 0; c < kb; ++c) {
-        const T l = Lp[i + (int64_t)(jb + c) * ldl];
-#pragma unroll
-        for (int col = 0; col < kRhsBlock; ++col)
-          if (col < nrhs) acc[col] += l * X[c + col * kPanel];
-      }
-#pragma unroll
-      for (int col = 0; col < kRhsBlock; ++col) {
-        if (col < nrhs) {
-          if (i < w)
-            y[f + i + col * n] -= acc[col];
-          else
-            us[(i - w) + col * r] -= acc[col];
-        }
-      }
-    }
-    __syncthreads();
+    wait_at_least(ucnt + c, fwd_need(S, c), hang);
   }
 }
 
-// L21 products of split fronts on the matrix cores.  A workgroup takes one
-// 64 x 64 block row (forward) or block column (backward) of L21 over a
-// reduction chunk of kGemvChunk, staging 64 x 64 panels of L21 (coalesced
-// column reads) and 64 x 16 panels of the vector block through LDS; each
-// wave owns 16 of the 64 outputs for all 16 right-hand sides (unused ones
-// are zero).  Partial products go to a slot of `part` (64 x 16, row-major)
-// and are summed in a fixed order by the reduce kernels, so the result does
-// not depend on the launch.
-//
-// Forward: part[slot][i][n] = sum_{k in chunk} L21[64 blk + i][k] x_s[k][n].
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_gemv(DevSym S, const T* L, const T* y, T* part,
-                                                       const GemvItem* items, int nrhs) {
-  __shared__ T Ls[kPanel * kDiagLd];    // Ls[k * kDiagLd + i] = L21[row0 + i][k0 + k]
-  __shared__ T Vs[kPanel * kRhsBlock];  // Vs[k * kRhsBlock + n] = x_s[k0 + k][n]
-  typedef typename Vec4<T>::type V4;
-  const GemvItem it = items[blockIdx.x];
-  const int s = it.s;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ inline void add_release(int32_t* p) {
+  release_agent();
+  __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until *cnt >= need and publishes the value it saw in
+// s_ready[par] after one acquire fence; every thread returns that value.
+// The two LDS slots alternate, so a slow reader of one wait never sees the
+// next wait's write.
+__device__ inline int wait_ready(const int32_t* cnt, int need, int32_t* hang, int* s_ready,
+                                 int& par) {
+  if (threadIdx.x == 0) {
+    wait_at_least(cnt, need, hang);
+    const int v = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    acquire_agent();
+    s_ready[par] = v;
+  }
+  __syncthreads();
+  const int v = s_ready[par];
+  par ^= 1;
+  return v;
+}
+
+// Forward solve of a front with m <= kSmallMax by one wave, lane = front
+// row: gather the children's contributions, eliminate the w pivot columns
+// with register broadcasts, write x (rows < w) to y and the rest to u_s.
+template <typename T, int NR>
+__device__ __forceinline__ void fwd_wave(const DevSym& S, const T* L, T* y, T* uvec, int s,
+                                         const SolveFlags& F, int lane) {
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
   const int ldl = S.ldL[s];
-  const int64_t n = S.n;
   const T* Lp = L + S.L_off[s];
-  const int row0 = w + it.blk * kPanel, nrows = min(kPanel, m - row0);
-  const int kbeg = it.chunk * kGemvChunk, kend = min(w, kbeg + kGemvChunk);
-  V4 acc = V4{0, 0, 0, 0};
-  for (int k0 = kbeg; k0 < kend; k0 += kPanel) {
-    const int kw = min(kPanel, kend - k0);
-#pragma unroll 4
-    for (int cc = 0; cc < kPanel / 4; ++cc) {
-      const int k = wave * (kPanel / 4) + cc;
-      Ls[k * kDiagLd + lane] = (lane < nrows && k < kw) ? Lp[(row0 + lane) + (int64_t)(k0 + k) * ldl] : T(0);
-    }
-    for (int t = tid; t < kPanel * kRhsBlock; t += kThreads) {
-      const int nn = t / kPanel, k = t - nn * kPanel;
-      Vs[k * kRhsBlock + nn] = (k < kw && nn < nrhs) ? y[f + k0 + k + nn * n] : T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s4 = 0; s4 < kPanel / 4; ++s4) {
-      const int k = 4 * s4 + (lane >> 4);
-      acc = mfma16(Ls[k * kDiagLd + wave * 16 + (lane & 15)], Vs[k * kRhsBlock + (lane & 15)], acc);
-    }
-    __syncthreads();
-  }
-  T* P = part + (int64_t)it.slot * (kPanel * kRhsBlock);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) P[(wave * 16 + mfma_row<T>(lane, v)) * kRhsBlock + (lane & 15)] = acc[v];
-}
-
-// Forward: u_s[64 blk + i][n] -= sum over the block row's chunks, in order.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_reduce(DevSym S, T* uvec, const T* part,
-                                                         const ReduceItem* items, int nrhs) {
-  const ReduceItem it = items[blockIdx.x];
-  const int s = it.s;
-  const int w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
-  T* us = uvec + S.u_off[s] * nrhs;
-  for (int t = threadIdx.x; t < kPanel * nrhs; t += kThreads) {
-    const int nn = t / kPanel, i = t - nn * kPanel;
-    const int row = it.blk * kPanel + i;
-    if (row >= r) continue;
-    T sum = T(0);
-    for (int c = 0; c < it.nchunk; ++c)
-      sum += part[(int64_t)(it.first + c) * (kPanel * kRhsBlock) + i * kRhsBlock + nn];
-    us[row + (int64_t)nn * r] -= sum;
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd(DevSym S, const T* L, T* y, const int32_t* list,
-                                                  int nrhs) {
-  __shared__ T D[kPanel * kDiagLd];
-  __shared__ T X[kPanel * kRhsBlock];
-  const int s = list[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
-  const int ldl = S.ldL[s];
-  const int64_t n = S.n;
-  const T* Lp = L + S.L_off[s];
-  const int32_t* rws = S.rows + S.rows_ptr[s];
-  if (w == 0 || solve_split(w, m - w)) return;  // split fronts: k_bwd_gemv + k_bwd_tri
-  const int mrow = m;
-  for (int jb = ((w - 1) / kPanel) * kPanel; jb >= 0; jb -= kPanel) {
-    const int kb = min(kPanel, w - jb);
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, rr = t - c * kb;
-      if (rr >= c) D[c * kDiagLd + rr] = Lp[(jb + rr) + (int64_t)(jb + c) * ldl];
-    }
-    for (int p = wave; p < kb * nrhs; p += kThreads / 64) {
-      const int col = p / kb, j = p - col * kb;
-      T acc = T(0);
-      const T* lc = Lp + (int64_t)(jb + j) * ldl;
-      for (int i = jb + kb + lane; i < mrow; i += 64) {
-        const int64_t gi = i < w ? (int64_t)(f + i) : (int64_t)rws[i];
-        acc += lc[i] * y[gi + col * n];
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) X[j + col * kPanel] = y[f + jb + j + col * n] - acc;
-    }
-    __syncthreads();
-    for (int col = wave; col < nrhs; col += kThreads / 64) {
-      T z = lane < kb ? X[lane + col * kPanel] : T(0);
-      for (int c = kb - 1; c >= 0; --c) {
-        const T xc = __shfl(z, c, 64) / D[c * kDiagLd + c];
-        if (lane == c)
-          z = xc;
-        else if (lane < c)
-          z -= D[lane * kDiagLd + c] * xc;
-      }
-      if (lane < kb) y[f + jb + lane + col * n] = z;
-    }
-    __syncthreads();
-  }
-}
-
-// Pipelined L11 solves of split fronts, one workgroup per 64-row block.
-// Forward: block b accumulates L_bj x_j for j < b as the blocks' flags
-// become ready, then applies the inverse of its diagonal block kept from the
-// factorization (x_b = W_bb z, the explicit diagonal-block inverse of the
-// paper's solve variant 2) and publishes x_b.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fwd_tri(DevSym S, const T* L, const T* winv, T* y,
-                                                      const TriItem* items, int count,
-                                                      int32_t* counter, int32_t* flags, int nrhs) {
-  __shared__ T D[kPanel * kDiagLd];
-  __shared__ T X[kPanel * kRhsBlock];
-  __shared__ T part[kThreads / 64][kPanel * kRhsBlock];
-  __shared__ int s_ticket;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_ticket = atomicAdd(counter, 1);
-  __syncthreads();
-  const int ticket = s_ticket;
-  if (ticket >= count) return;
-  const TriItem it = items[ticket];
-  const int s = it.s, b = it.b;
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f;
-  const int ldl = S.ldL[s];
-  const int64_t n = S.n;
-  const T* Lp = L + S.L_off[s];
-  const int r0 = b * kPanel, kb = min(kPanel, w - r0);
-  const bool valid = lane < kb;
-  const int row = r0 + (valid ? lane : 0);
-  T acc[kRhsBlock];
-#pragma unroll
-  for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
-  for (int j = 0; j < b; ++j) {
-    if (tid == 0) wait_flag(flags + it.flag - b + j, 1);
-    __syncthreads();
-    for (int t = tid; t < kPanel * nrhs; t += kThreads) {
-      const int col = t / kPanel, c = t - col * kPanel;
-      X[c + col * kPanel] = y[f + j * kPanel + c + col * n];
-    }
-    __syncthreads();
-    if (valid) {
-      for (int c = wave; c < kPanel; c += kThreads / 64) {
-        const T l = Lp[row + (int64_t)(j * kPanel + c) * ldl];
-#pragma unroll
-        for (int col = 0; col < kRhsBlock; ++col)
-          if (col < nrhs) acc[col] += l * X[c + col * kPanel];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int col = 0; col < kRhsBlock; ++col) part[wave][lane + col * kPanel] = acc[col];
+  if (lane == 0) wait_children(S, s, F.ucnt, F.hang);
+  acquire_agent();
+  const int i = lane;
+  const int ic = i < m ? i : m - 1;
+  const int64_t q = S.rows_ptr[s] + ic;
+  const int p0 = S.pull_ptr[q], p1 = i < m ? S.pull_ptr[q + 1] : p0;
+  T z[NR];
   {
-    const T* Wb = winv + S.woff[S.wbase[s] + b];  // W_bb = L_bb^{-1}, kb x kb column-major
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, rr = t - c * kb;
-      D[c * kDiagLd + rr] = Wb[t];
-    }
-  }
-  __syncthreads();
-  if (wave == 0 && valid) {
-    for (int col = 0; col < nrhs; ++col) {
-      T t = T(0);
+    const T* yr = y + (int64_t)(f + (i < w ? i : 0)) * kRowLd<T>;
+    const T own = i < w ? T(1) : T(0);
 #pragma unroll
-      for (int q = 0; q < kThreads / 64; ++q) t += part[q][lane + col * kPanel];
-      X[lane + col * kPanel] = y[f + r0 + lane + col * n] - t;
+    for (int c = 0; c < NR; ++c) z[c] = yr[c] * own;
+  }
+  for (int p = p0; p < p1; ++p) {
+    const T* ur = uvec + (int64_t)S.pull_src[p] * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) z[c] += ur[c];
+  }
+#pragma unroll 2
+  for (int k = 0; k < w; ++k) {
+    const T inv = T(1) / Lp[k + (int64_t)k * ldl];
+    const T lik = Lp[(i > k && i < m ? i : k) + (int64_t)k * ldl];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const T xk = readlane(z[c], k) * inv;
+      z[c] = i == k ? xk : (i > k ? z[c] - lik * xk : z[c]);
     }
   }
-  __syncthreads();
-  // x_b = W_bb z: lane = row, waves split the right-hand sides
-  for (int col = wave; col < nrhs; col += kThreads / 64) {
-    if (lane < kb) {
-      T acc = T(0);
-      for (int c = 0; c <= lane; ++c) acc += D[c * kDiagLd + lane] * X[c + col * kPanel];
-      y[f + r0 + lane + col * n] = acc;
-    }
+  if (i < w) {
+    T* yr = y + (int64_t)(f + i) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) yr[c] = z[c];
+  } else if (i < m) {
+    T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) ur[c] = z[c];
   }
-  __syncthreads();
-  if (tid == 0) set_flag(flags + it.flag, 1);  // release after the workgroup's stores
+  release_agent();
+  if (lane == 0) __hip_atomic_store(F.ucnt + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Backward: block b (taken from the bottom) subtracts L_cb^T x_c for c > b
-// as those blocks' flags become ready, then x_b = W_bb^T t_b.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_tri(DevSym S, const T* L, const T* winv, T* y,
-                                                      const TriItem* items, int count,
-                                                      int32_t* counter, int32_t* flags, int nrhs) {
-  __shared__ T D[kPanel * kDiagLd];
-  __shared__ T X[kPanel * kRhsBlock];
-  __shared__ T part[kThreads / 64][kPanel * kRhsBlock];
-  __shared__ int s_ticket;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_ticket = atomicAdd(counter, 1);
-  __syncthreads();
-  const int ticket = s_ticket;
-  if (ticket >= count) return;
-  const TriItem it = items[ticket];
-  const int s = it.s, b = it.b;
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f;
+// Backward solve of a front with m <= kSmallMax by one wave, lane = pivot
+// column: subtract L21^T x[rows] (the rows' solutions are final once the
+// parent is done), then back-substitute through L11^T.
+template <typename T, int NR>
+__device__ __forceinline__ void bwd_wave(const DevSym& S, const T* L, T* y, int s,
+                                         const SolveFlags& F, int lane) {
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
   const int ldl = S.ldL[s];
-  const int64_t n = S.n;
   const T* Lp = L + S.L_off[s];
-  const int nb = (w + kPanel - 1) / kPanel;
-  const int r0 = b * kPanel, kb = min(kPanel, w - r0);
-  const bool valid = lane < kb;
-  const int colj = r0 + (valid ? lane : 0);  // this lane's column of block b
-  T acc[kRhsBlock];
-#pragma unroll
-  for (int col = 0; col < kRhsBlock; ++col) acc[col] = T(0);
-  for (int c = nb - 1; c > b; --c) {
-    if (tid == 0) wait_flag(flags + it.flag - b + c, 2);
-    __syncthreads();
-    const int kc = min(kPanel, w - c * kPanel);
-    for (int t = tid; t < kc * nrhs; t += kThreads) {
-      const int col = t / kc, q = t - col * kc;
-      X[q + col * kPanel] = y[f + c * kPanel + q + col * n];
-    }
-    __syncthreads();
-    if (valid) {
-      const T* lc = Lp + (int64_t)colj * ldl + c * kPanel;
-      for (int q = wave; q < kc; q += kThreads / 64) {
-        const T l = lc[q];
-#pragma unroll
-        for (int col = 0; col < kRhsBlock; ++col)
-          if (col < nrhs) acc[col] += l * X[q + col * kPanel];
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int col = 0; col < kRhsBlock; ++col) part[wave][lane + col * kPanel] = acc[col];
+  const int p = S.sparent[s];
+  if (lane == 0 && p >= 0) wait_at_least(F.bcnt + p, bwd_need(S, p), F.hang);
+  acquire_agent();
+  const int i = lane;
+  const int ic = i < w ? i : 0;
+  T z[NR];
   {
-    const T* Wb = winv + S.woff[S.wbase[s] + b];  // W_bb = L_bb^{-1}, kb x kb column-major
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, rr = t - c * kb;
-      D[c * kDiagLd + rr] = Wb[t];
-    }
-  }
-  __syncthreads();
-  if (wave == 0 && valid) {
-    for (int col = 0; col < nrhs; ++col) {
-      T t = T(0);
+    const T* yr = y + (int64_t)(f + ic) * kRowLd<T>;
 #pragma unroll
-      for (int q = 0; q < kThreads / 64; ++q) t += part[q][lane + col * kPanel];
-      X[lane + col * kPanel] = y[f + r0 + lane + col * n] - t;
-    }
+    for (int c = 0; c < NR; ++c) z[c] = yr[c];
   }
-  __syncthreads();
-  // x_b = W_bb^T t: lane = row, waves split the right-hand sides
-  for (int col = wave; col < nrhs; col += kThreads / 64) {
-    if (lane < kb) {
-      T acc = T(0);
-      for (int c = lane; c < kb; ++c) acc += D[lane * kDiagLd + c] * X[c + col * kPanel];
-      y[f + r0 + lane + col * n] = acc;
-    }
-  }
-  __syncthreads();
-  if (tid == 0) set_flag(flags + it.flag, 2);  // release after the workgroup's stores
-}
-
-// Backward solve of a split front, gather step: u_s = x[rows(s)[w:]] (the
-// update-vector slot of s is free again in the backward sweep).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_gather(DevSym S, const T* y, T* uvec,
-                                                         const int32_t* list, int nrhs) {
-  const int s = list[blockIdx.x];
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f, r = S.front_m[s] - w;
   const int32_t* rws = S.rows + S.rows_ptr[s] + w;
-  T* us = uvec + S.u_off[s] * nrhs;
-  for (int t = threadIdx.x; t < r * nrhs; t += kThreads) {
-    const int col = t / r, i = t - col * r;
-    us[t] = y[(int64_t)rws[i] + col * S.n];
+  const T* lc = Lp + (int64_t)ic * ldl + w;  // L21 column ic
+#pragma unroll 2
+  for (int k = 0; k < r; ++k) {
+    const T* xr = y + (int64_t)rws[k] * kRowLd<T>;
+    const T l = lc[k];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) z[c] -= l * xr[c];
+  }
+#pragma unroll 2
+  for (int k = w - 1; k >= 0; --k) {
+    const T inv = T(1) / Lp[k + (int64_t)k * ldl];
+    const T lki = Lp[k + (int64_t)ic * ldl];  // L11[k][i], used for i < k
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const T xk = readlane(z[c], k) * inv;
+      z[c] = i == k ? xk : (i < k ? z[c] - lki * xk : z[c]);
+    }
+  }
+  if (i < w) {
+    T* yr = y + (int64_t)(f + i) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) yr[c] = z[c];
+  }
+  release_agent();
+  if (lane == 0) __hip_atomic_store(F.bcnt + s, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Forward, one 64-row block of a front with m > kSmallMax.  Diagonal block
+// (tri): rows [64 blk, 64 blk + kb) of L11, z = y + pulled - sum_{j<blk}
+// L(blk, j) x_j, x_blk = W_blk z.  L21 block (!tri): rows w + 64 blk ...,
+// u = pulled - sum_j L21(blk, j) x_j over all diagonal blocks.  The products
+// run on the matrix cores, 16 rows x 16 right-hand sides per wave; the block
+// of x_j is taken as soon as xcnt says it is solved.
+template <typename T, int NR, bool DF>
+__device__ __forceinline__ void fwd_block(const DevSym& S, const T* L, const T* winv, T* y,
+                                          T* uvec, int s, bool tri, int blk, const SolveFlags& F,
+                                          T* Zs, int* s_ready) {
+  typedef typename Vec4<T>::type V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ldl = S.ldL[s];
+  const T* Lp = L + S.L_off[s];
+  const int row0 = tri ? blk * kPanel : w + blk * kPanel;
+  const int nrows = min(kPanel, (tri ? w : m) - row0);
+  const int nj = tri ? blk : (w + kPanel - 1) / kPanel;
+  const int li = 16 * wave + (lane & 15);  // A-operand row of this lane
+  const int lk = lane >> 4;                // k offset within a 4-step
+  const int col = lane & 15;               // B / result column
+  T wa[16];
+  if (tri) {  // W_blk (lower triangular, nrows x nrows, column-major)
+    const T* Wb = winv + S.woff[S.wbase[s] + blk];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lk;
+      const bool ok = k <= li && li < nrows;
+      wa[q] = Wb[ok ? li + k * nrows : 0] * (ok ? T(1) : T(0));
+    }
+  }
+  if (DF && tid == 0) {
+    wait_children(S, s, F.ucnt, F.hang);
+    acquire_agent();
+  }
+  __syncthreads();
+  {
+    const int64_t q0 = S.rows_ptr[s] + row0;
+    for (int t = tid; t < kPanel * 16; t += kThreads) {
+      const int i = t >> 4, c = t & 15;
+      T v = T(0);
+      if (i < nrows && c < NR) {
+        if (tri) v = y[(int64_t)(f + row0 + i) * kRowLd<T> + c];
+        for (int p = S.pull_ptr[q0 + i]; p < S.pull_ptr[q0 + i + 1]; ++p)
+          v += uvec[(int64_t)S.pull_src[p] * kRowLd<T> + c];
+      }
+      Zs[t] = v;
+    }
+  }
+  __syncthreads();
+  V4 acc = V4{0, 0, 0, 0};
+  const int arow = row0 + min(li, nrows - 1);
+  const T amask = li < nrows ? T(1) : T(0);
+  const int bcol = col < NR ? col : NR - 1;
+  const T cmask = col < NR ? T(1) : T(0);
+  int ready = 0, par = 0;
+  for (int j = 0; j < nj; ++j) {
+    const int kbj = min(kPanel, w - j * kPanel);
+    T a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lk;
+      a[q] = Lp[arow + (int64_t)(j * kPanel + min(k, kbj - 1)) * ldl] * (k < kbj ? amask : T(0));
+    }
+    if (DF && j >= ready) ready = wait_ready(F.xcnt + s, j + 1, F.hang, s_ready, par);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lk;
+      const T b = y[(int64_t)(f + j * kPanel + min(k, kbj - 1)) * kRowLd<T> + bcol] * (k < kbj ? cmask : T(0));
+      acc = mfma16(a[q], b, acc);
+    }
+  }
+  if (tri) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Zs[(16 * wave + mfma_row<T>(lane, v)) * 16 + col] -= acc[v];
+    __syncthreads();
+    V4 xv = V4{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) xv = mfma16(wa[q], Zs[(4 * q + lk) * 16 + col], xv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * wave + mfma_row<T>(lane, v);
+      if (i < nrows && col < NR) y[(int64_t)(f + row0 + i) * kRowLd<T> + col] = xv[v];
+    }
+    if (DF) {
+      publish_barrier();
+      if (tid == 0) set_flag(F.xcnt + s, blk + 1);
+    } else {
+      __syncthreads();
+    }
+  } else {
+    T* us = uvec + (S.u_off[s] + blk * kPanel) * kRowLd<T>;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * wave + mfma_row<T>(lane, v);
+      if (i < nrows && col < NR) us[(int64_t)i * kRowLd<T> + col] = Zs[i * 16 + col] - acc[v];
+    }
+    if (DF) {
+      publish_barrier();
+      if (tid == 0) add_release(F.ucnt + s);
+    } else {
+      __syncthreads();
+    }
   }
 }
 
-// Backward: part[slot][c][n] = sum_{i in chunk} L21[i][64 blk + c] u_s[i][n].
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_gemv(DevSym S, const T* L, const T* uvec, T* part,
-                                                       const GemvItem* items, int nrhs) {
-  __shared__ T Ls[kPanel * kDiagLd];    // Ls[c * kDiagLd + i] = L21[i0 + i][col0 + c]
-  __shared__ T Vs[kPanel * kRhsBlock];  // Vs[i * kRhsBlock + n] = u_s[i0 + i][n]
+// Backward partial product of a front with m > kSmallMax: column block blk
+// of L21 against the solutions of L21 rows [kBwdChunk ch, ...) (available
+// once the parent is done), written to the block's slot ch.  L21 tiles are
+// staged through LDS with coalesced column reads.
+template <typename T, int NR, bool DF>
+__device__ __forceinline__ void bwd_part(const DevSym& S, const T* L, const T* y, T* part, int s,
+                                         int blk, int ch, const SolveFlags& F, T* Ls, T* Vs) {
   typedef typename Vec4<T>::type V4;
-  const GemvItem it = items[blockIdx.x];
-  const int s = it.s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
   const int ldl = S.ldL[s];
-  const T* Lp = L + S.L_off[s] + w;  // L21, row 0 = front row w
-  const T* us = uvec + S.u_off[s] * nrhs;
-  const int col0 = it.blk * kPanel, ncols = min(kPanel, w - col0);
-  const int ibeg = it.chunk * kGemvChunk, iend = min(r, ibeg + kGemvChunk);
+  const T* Lp = L + S.L_off[s];
+  const int p = S.sparent[s];
+  if (DF && tid == 0) {
+    if (p >= 0) wait_at_least(F.bcnt + p, bwd_need(S, p), F.hang);
+    acquire_agent();
+  }
+  __syncthreads();
+  const int c0 = blk * kPanel, kb = min(kPanel, w - c0);
+  const int i0 = ch * kBwdChunk, i1 = min(r, i0 + kBwdChunk);
+  const int32_t* rws = S.rows + S.rows_ptr[s] + w;
+  const int li = 16 * wave + (lane & 15), lk = lane >> 4, col = lane & 15;
   V4 acc = V4{0, 0, 0, 0};
-  for (int i0 = ibeg; i0 < iend; i0 += kPanel) {
-    const int iw = min(kPanel, iend - i0);
-#pragma unroll 4
-    for (int cc = 0; cc < kPanel / 4; ++cc) {
-      const int c = wave * (kPanel / 4) + cc;
-      Ls[c * kDiagLd + lane] = (lane < iw && c < ncols) ? Lp[(i0 + lane) + (int64_t)(col0 + c) * ldl] : T(0);
+  for (int k0 = i0; k0 < i1; k0 += kPanel) {
+    const int kw = min(kPanel, i1 - k0);
+    const int rr = min(lane, kw - 1);
+    const T rmask = lane < kw ? T(1) : T(0);
+#pragma unroll
+    for (int c4 = 0; c4 < 16; ++c4) {
+      const int cc = wave * 16 + c4;
+      Ls[cc * kDiagLd + lane] =
+          Lp[(w + k0 + rr) + (int64_t)(c0 + min(cc, kb - 1)) * ldl] * (cc < kb ? rmask : T(0));
     }
-    for (int t = tid; t < kPanel * kRhsBlock; t += kThreads) {
-      const int nn = t / kPanel, i = t - nn * kPanel;
-      Vs[i * kRhsBlock + nn] = (i < iw && nn < nrhs) ? us[i0 + i + (int64_t)nn * r] : T(0);
+    for (int t = tid; t < kPanel * 16; t += kThreads) {
+      const int i = t >> 4, c = t & 15;
+      Vs[t] = (i < kw && c < NR) ? y[(int64_t)rws[k0 + i] * kRowLd<T> + c] : T(0);
     }
     __syncthreads();
 #pragma unroll
-    for (int s4 = 0; s4 < kPanel / 4; ++s4) {
-      const int i = 4 * s4 + (lane >> 4);
-      acc = mfma16(Ls[(wave * 16 + (lane & 15)) * kDiagLd + i], Vs[i * kRhsBlock + (lane & 15)], acc);
+    for (int q = 0; q < 16; ++q) {
+      const int i = 4 * q + lk;
+      acc = mfma16(Ls[li * kDiagLd + i], Vs[i * 16 + col], acc);
     }
     __syncthreads();
   }
-  T* P = part + (int64_t)it.slot * (kPanel * kRhsBlock);
+  T* P = part + ((int64_t)S.part_base[S.wbase[s] + blk] + ch) * (kPanel * 16);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) P[(wave * 16 + mfma_row<T>(lane, v)) * kRhsBlock + (lane & 15)] = acc[v];
+  for (int v = 0; v < 4; ++v) P[(16 * wave + mfma_row<T>(lane, v)) * 16 + col] = acc[v];
+  if (DF) {
+    publish_barrier();
+    if (tid == 0) add_release(F.pcnt + S.wbase[s] + blk);
+  } else {
+    __syncthreads();
+  }
 }
 
-// Backward: y_s[64 blk + c][n] -= sum over the block column's chunks, in order.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_bwd_reduce(DevSym S, T* y, const T* part,
-                                                         const ReduceItem* items, int nrhs) {
-  const ReduceItem it = items[blockIdx.x];
-  const int s = it.s;
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f;
-  const int64_t n = S.n;
-  for (int t = threadIdx.x; t < kPanel * nrhs; t += kThreads) {
-    const int nn = t / kPanel, c = t - nn * kPanel;
-    const int col = it.blk * kPanel + c;
-    if (col >= w) continue;
-    T sum = T(0);
-    for (int q = 0; q < it.nchunk; ++q)
-      sum += part[(int64_t)(it.first + q) * (kPanel * kRhsBlock) + c * kRhsBlock + nn];
-    y[f + col + nn * n] -= sum;
+// Backward, diagonal block blk of a front with m > kSmallMax (columns
+// [64 blk, 64 blk + kb)): z = y - sum of the block's partial products (in
+// slot order, taken before the chain since they need only the parent) -
+// sum_{c > blk} L(c, blk)^T x_c, x_blk = W_blk^T z.
+template <typename T, int NR, bool DF>
+__device__ __forceinline__ void bwd_tri(const DevSym& S, const T* L, const T* winv, T* y,
+                                        const T* part, int s, int blk, const SolveFlags& F,
+                                        T* Zs, int* s_ready) {
+  typedef typename Vec4<T>::type V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int ldl = S.ldL[s];
+  const T* Lp = L + S.L_off[s];
+  const int nb = (w + kPanel - 1) / kPanel;
+  const int c0 = blk * kPanel, kb = min(kPanel, w - c0);
+  const int li = 16 * wave + (lane & 15), lk = lane >> 4, col = lane & 15;
+  const int wblk = S.wbase[s] + blk;
+  T wa[16];  // A[i][k] = W_blk[k][i], nonzero for i <= k < kb
+  {
+    const T* Wb = winv + S.woff[wblk];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lk;
+      const bool ok = li <= k && k < kb;
+      wa[q] = Wb[ok ? k + li * kb : 0] * (ok ? T(1) : T(0));
+    }
+  }
+  int ready = 0, par = 0;
+  const int nch = (r + kBwdChunk - 1) / kBwdChunk;
+  if (DF && nch > 0) (void)wait_ready(F.pcnt + wblk, nch, F.hang, s_ready, par);
+  {
+    const T* P = part + (int64_t)S.part_base[wblk] * (kPanel * 16);
+    for (int t = tid; t < kPanel * 16; t += kThreads) {
+      const int i = t >> 4, c = t & 15;
+      T v = T(0);
+      if (i < kb && c < NR) {
+        v = y[(int64_t)(f + c0 + i) * kRowLd<T> + c];
+        int q = 0;
+        for (; q + 4 <= nch; q += 4) {
+          const T p0 = P[(int64_t)q * (kPanel * 16) + t], p1 = P[(int64_t)(q + 1) * (kPanel * 16) + t];
+          const T p2 = P[(int64_t)(q + 2) * (kPanel * 16) + t], p3 = P[(int64_t)(q + 3) * (kPanel * 16) + t];
+          v = (((v - p0) - p1) - p2) - p3;
+        }
+        for (; q < nch; ++q) v -= P[(int64_t)q * (kPanel * 16) + t];
+      }
+      Zs[t] = v;
+    }
+  }
+  V4 acc = V4{0, 0, 0, 0};
+  const int lcol = c0 + min(li, kb - 1);
+  const T amask = li < kb ? T(1) : T(0);
+  const int bcol = col < NR ? col : NR - 1;
+  const T cmask = col < NR ? T(1) : T(0);
+  for (int c = nb - 1; c > blk; --c) {
+    const int kc = min(kPanel, w - c * kPanel);
+    T a[16];  // A[i][k] = L(c, blk)[k][i]
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lk;
+      a[q] = Lp[(c * kPanel + min(k, kc - 1)) + (int64_t)lcol * ldl] * (k < kc ? amask : T(0));
+    }
+    if (DF && nb - c > ready) ready = wait_ready(F.bcnt + s, nb - c, F.hang, s_ready, par);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lk;
+      const T b = y[(int64_t)(f + c * kPanel + min(k, kc - 1)) * kRowLd<T> + bcol] * (k < kc ? cmask : T(0));
+      acc = mfma16(a[q], b, acc);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) Zs[(16 * wave + mfma_row<T>(lane, v)) * 16 + col] -= acc[v];
+  __syncthreads();
+  V4 xv = V4{0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 16; ++q) xv = mfma16(wa[q], Zs[(4 * q + lk) * 16 + col], xv);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * wave + mfma_row<T>(lane, v);
+    if (i < kb && col < NR) y[(int64_t)(f + c0 + i) * kRowLd<T> + col] = xv[v];
+  }
+  if (DF) {
+    publish_barrier();
+    if (tid == 0) set_flag(F.bcnt + s, nb - blk);
+  } else {
+    __syncthreads();
+  }
+}
+
+// Forward solve of small fronts (m <= g) several per wave in the
+// level-by-level phase: lane li of group grp handles row li of front
+// wave_list[first + grp]; pivots are broadcast inside the group.
+template <typename T, int NR>
+__device__ __forceinline__ void fwd_group(const DevSym& S, const T* L, T* y, T* uvec,
+                                          const int32_t* wave_list, const WaveItem it, int lane,
+                                          int32_t* ucnt) {
+  const int g = it.g;
+  const int grp = lane / g, i = lane - grp * g, base = grp * g;
+  const bool act = grp < it.count;
+  const int s = wave_list[it.first + (act ? grp : 0)];
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ldl = S.ldL[s];
+  const T* Lp = L + S.L_off[s];
+  const int ic = i < m ? i : m - 1;
+  const int64_t q = S.rows_ptr[s] + ic;
+  const int p0 = S.pull_ptr[q], p1 = (act && i < m) ? S.pull_ptr[q + 1] : p0;
+  T z[NR];
+  {
+    const T* yr = y + (int64_t)(f + (i < w ? i : 0)) * kRowLd<T>;
+    const T own = i < w ? T(1) : T(0);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) z[c] = yr[c] * own;
+  }
+  for (int p = p0; p < p1; ++p) {
+    const T* ur = uvec + (int64_t)S.pull_src[p] * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) z[c] += ur[c];
+  }
+  for (int k = 0; k < it.wmax; ++k) {
+    const bool kv = k < w;
+    const int kk = kv ? k : w - 1;
+    const T inv = T(1) / Lp[kk + (int64_t)kk * ldl];
+    const T lik = Lp[(i > kk && i < m ? i : kk) + (int64_t)kk * ldl];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const T xk = __shfl(z[c], base + kk, 64) * inv;
+      z[c] = !kv ? z[c] : (i == k ? xk : (i > k ? z[c] - lik * xk : z[c]));
+    }
+  }
+  if (act && i < w) {
+    T* yr = y + (int64_t)(f + i) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) yr[c] = z[c];
+  } else if (act && i < m) {
+    T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) ur[c] = z[c];
+  }
+  if (act && i == 0) ucnt[s] = 1;
+}
+
+// Backward counterpart of fwd_group: lane li of group grp handles pivot
+// column li of its front.
+template <typename T, int NR>
+__device__ __forceinline__ void bwd_group(const DevSym& S, const T* L, T* y,
+                                          const int32_t* wave_list, const WaveItem it, int lane) {
+  const int g = it.g;
+  const int grp = lane / g, i = lane - grp * g, base = grp * g;
+  const bool act = grp < it.count;
+  const int s = wave_list[it.first + (act ? grp : 0)];
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int ldl = S.ldL[s];
+  const T* Lp = L + S.L_off[s];
+  const int ic = i < w ? i : 0;
+  T z[NR];
+  {
+    const T* yr = y + (int64_t)(f + ic) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) z[c] = yr[c];
+  }
+  const int r0 = r > 0 ? w : 0;  // keeps the row pointer inside rows(s) when r = 0
+  const int32_t* rws = S.rows + S.rows_ptr[s] + r0;
+  const T* lc = Lp + (int64_t)ic * ldl + r0;
+  for (int k = 0; k < it.rmax; ++k) {
+    const bool kv = k < r;
+    const int kk = kv ? k : 0;
+    const T l = lc[kk] * (kv ? T(1) : T(0));
+    const T* xr = y + (int64_t)rws[kk] * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) z[c] -= l * xr[c];
+  }
+  for (int k = it.wmax - 1; k >= 0; --k) {
+    const bool kv = k < w;
+    const int kk = kv ? k : 0;
+    const T inv = T(1) / Lp[kk + (int64_t)kk * ldl];
+    const T lki = Lp[kk + (int64_t)ic * ldl];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      const T xk = __shfl(z[c], base + kk, 64) * inv;
+      z[c] = !kv ? z[c] : (i == k ? xk : (i < k ? z[c] - lki * xk : z[c]));
+    }
+  }
+  if (act && i < w) {
+    T* yr = y + (int64_t)(f + i) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) yr[c] = z[c];
+  }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_solve_fwd(DevSym S, const T* L, const T* winv, T* y,
+                                                        T* uvec, const SolveTask* tasks,
+                                                        int count, const int32_t* wave_list,
+                                                        SolveFlags F) {
+  __shared__ T Zs[kPanel * 16];
+  __shared__ int s_ready[2];
+  __shared__ int s_ticket;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(F.ticket, 1);
+  __syncthreads();
+  const int ticket = s_ticket;
+  if (ticket >= count) return;
+  const SolveTask tk = tasks[ticket];
+  if (tk.kind == kSolveWave) {
+    const int wave = threadIdx.x >> 6;
+    if (wave < tk.b) fwd_wave<T, NR>(S, L, y, uvec, wave_list[tk.a + wave], F, threadIdx.x & 63);
+  } else {
+    fwd_block<T, NR, true>(S, L, winv, y, uvec, tk.s, tk.kind == kSolveTri, tk.a, F, Zs, s_ready);
+  }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_solve_bwd(DevSym S, const T* L, const T* winv, T* y,
+                                                        T* part, const SolveTask* tasks,
+                                                        int count, const int32_t* wave_list,
+                                                        SolveFlags F) {
+  __shared__ T Ls[kPanel * kDiagLd];
+  __shared__ T Zs[kPanel * 16];
+  __shared__ int s_ready[2];
+  __shared__ int s_ticket;
+  if (threadIdx.x == 0) s_ticket = atomicAdd(F.ticket, 1);
+  __syncthreads();
+  const int ticket = s_ticket;
+  if (ticket >= count) return;
+  const SolveTask tk = tasks[ticket];
+  if (tk.kind == kSolveWave) {
+    const int wave = threadIdx.x >> 6;
+    if (wave < tk.b) bwd_wave<T, NR>(S, L, y, wave_list[tk.a + wave], F, threadIdx.x & 63);
+  } else if (tk.kind == kSolveRows) {
+    bwd_part<T, NR, true>(S, L, y, part, tk.s, tk.a, tk.b, F, Ls, Zs);
+  } else {
+    bwd_tri<T, NR, true>(S, L, winv, y, part, tk.s, tk.a, F, Zs, s_ready);
+  }
+}
+
+// Level-by-level phase: one launch per level; the first (nitems + 3) / 4
+// workgroups take four wave items each, the others one large front each,
+// whose blocks they solve in order (no flags: the launch boundaries order
+// the levels).  Forward also records the fronts as complete for the
+// dataflow phase.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_level_fwd(DevSym S, const T* L, const T* winv, T* y,
+                                                        T* uvec, const WaveItem* items, int nitems,
+                                                        const int32_t* large, const int32_t* wave_list,
+                                                        SolveFlags F) {
+  __shared__ T Zs[kPanel * 16];
+  __shared__ int s_ready[2];
+  const int nwg = (nitems + 3) / 4;
+  if ((int)blockIdx.x < nwg) {
+    const int it = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (it < nitems) fwd_group<T, NR>(S, L, y, uvec, wave_list, items[it], threadIdx.x & 63, F.ucnt);
+    return;
+  }
+  const int s = large[blockIdx.x - nwg];
+  const int w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+  for (int b = 0; b * kPanel < w; ++b) fwd_block<T, NR, false>(S, L, winv, y, uvec, s, true, b, F, Zs, s_ready);
+  for (int k = 0; k * kPanel < r; ++k) fwd_block<T, NR, false>(S, L, winv, y, uvec, s, false, k, F, Zs, s_ready);
+  if (threadIdx.x == 0) F.ucnt[s] = (r + kPanel - 1) / kPanel;
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_level_bwd(DevSym S, const T* L, const T* winv, T* y,
+                                                        T* part, const WaveItem* items, int nitems,
+                                                        const int32_t* large, const int32_t* wave_list,
+                                                        SolveFlags F) {
+  __shared__ T Ls[kPanel * kDiagLd];
+  __shared__ T Zs[kPanel * 16];
+  __shared__ int s_ready[2];
+  const int nwg = (nitems + 3) / 4;
+  if ((int)blockIdx.x < nwg) {
+    const int it = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (it < nitems) bwd_group<T, NR>(S, L, y, wave_list, items[it], threadIdx.x & 63);
+    return;
+  }
+  const int s = large[blockIdx.x - nwg];
+  const int w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+  const int nch = (r + kBwdChunk - 1) / kBwdChunk;
+  for (int b = (w + kPanel - 1) / kPanel - 1; b >= 0; --b) {
+    for (int c = 0; c < nch; ++c) bwd_part<T, NR, false>(S, L, y, part, s, b, c, F, Ls, Zs);
+    bwd_tri<T, NR, false>(S, L, winv, y, part, s, b, F, Zs, s_ready);
   }
 }
 
@@ -1621,64 +1807,90 @@ void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tile
     hipLaunchKernelGGL((k_gemm<T, kGemmTile>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles);
 }
 
-template <typename T>
-void launch_permute_in(const DevSym& S, const double* b, int64_t ldb, T* y, int64_t nrhs,
-                       const double* scale, hipStream_t st) {
-  if (S.n > 0) hipLaunchKernelGGL(k_permute_in<T>, dim3(blocks_for(S.n)), dim3(kThreads), 0, st, S, b, ldb, y, nrhs, scale);
+// Counters of the dataflow solves: [xcnt ns][ucnt ns][bcnt ns][pcnt nblk][2 tickets].
+inline SolveFlags solve_flags(int32_t* counters, int64_t ns, int64_t nblk, int32_t* hang, int bwd) {
+  SolveFlags F;
+  F.xcnt = counters;
+  F.ucnt = counters + ns;
+  F.bcnt = counters + 2 * ns;
+  F.pcnt = counters + 3 * ns;
+  F.ticket = counters + 3 * ns + nblk + bwd;
+  F.hang = hang;
+  return F;
 }
 
 template <typename T>
-void launch_permute_out(const DevSym& S, const T* y, double* x, int64_t ldx, int64_t nrhs,
-                        const double* scale, int accumulate, hipStream_t st) {
-  if (S.n > 0) hipLaunchKernelGGL(k_permute_out<T>, dim3(blocks_for(S.n)), dim3(kThreads), 0, st, S, y, x, ldx, nrhs, scale, accumulate);
-}
-
-template <typename T>
-void launch_fwd(const DevSym& S, const T* L, T* y, T* uvec, const int32_t* list, int64_t count,
-                int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_fwd<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, uvec, list, nrhs);
-}
-
-template <typename T>
-void launch_fwd_gemv(const DevSym& S, const T* L, const T* y, T* part, const GemvItem* items,
-                     int64_t count, const ReduceItem* red, int64_t nred, T* uvec, int32_t nrhs,
+void launch_solve_in(const DevSym& S, const double* b, int64_t ldb, T* y, int nrhs,
+                     const double* scale, int32_t* counters, int64_t ns, int64_t nblk,
                      hipStream_t st) {
+  launch_fill_i32(counters, 0, 3 * ns + nblk + 2, st);
+  if (S.n <= 0) return;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_permute_in<T, 1>), dim3(blocks_for(S.n)), dim3(kThreads), 0, st, S, b, ldb, y, (int64_t)nrhs, scale);
+  else
+    hipLaunchKernelGGL((k_permute_in<T, 16>), dim3(blocks_for(S.n)), dim3(kThreads), 0, st, S, b, ldb, y, (int64_t)nrhs, scale);
+}
+
+template <typename T>
+void launch_solve_fwd(const DevSym& S, const T* L, const T* winv, T* y, T* uvec,
+                      const SolveTask* tasks, int64_t count, const int32_t* wave_list, int nrhs,
+                      int32_t* counters, int64_t ns, int64_t nblk, int32_t* hang, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_fwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, part, items, nrhs);
-  hipLaunchKernelGGL(k_fwd_reduce<T>, dim3((unsigned)nred), dim3(kThreads), 0, st, S, uvec, (const T*)part, red, nrhs);
+  const SolveFlags F = solve_flags(counters, ns, nblk, hang, 0);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_solve_fwd<T, 1>), dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, uvec, tasks, (int)count, wave_list, F);
+  else
+    hipLaunchKernelGGL((k_solve_fwd<T, 16>), dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, uvec, tasks, (int)count, wave_list, F);
 }
 
 template <typename T>
-void launch_fwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
-                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_fwd_tri<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, items, (int)count, counter, flags, nrhs);
-}
-
-template <typename T>
-void launch_bwd_tri(const DevSym& S, const T* L, const T* winv, T* y, const TriItem* items,
-                    int64_t count, int32_t* counter, int32_t* flags, int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_bwd_tri<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, items, (int)count, counter, flags, nrhs);
-}
-
-template <typename T>
-void launch_bwd_gather(const DevSym& S, const T* y, T* uvec, const int32_t* list, int64_t count,
-                       int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_bwd_gather<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, y, uvec, list, nrhs);
-}
-
-template <typename T>
-void launch_bwd_gemv(const DevSym& S, const T* L, const T* uvec, T* part, const GemvItem* items,
-                     int64_t count, const ReduceItem* red, int64_t nred, T* y, int32_t nrhs,
-                     hipStream_t st) {
+void launch_solve_bwd(const DevSym& S, const T* L, const T* winv, T* y, T* part,
+                      const SolveTask* tasks, int64_t count, const int32_t* wave_list, int nrhs,
+                      int32_t* counters, int64_t ns, int64_t nblk, int32_t* hang, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_bwd_gemv<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, uvec, part, items, nrhs);
-  hipLaunchKernelGGL(k_bwd_reduce<T>, dim3((unsigned)nred), dim3(kThreads), 0, st, S, y, (const T*)part, red, nrhs);
+  const SolveFlags F = solve_flags(counters, ns, nblk, hang, 1);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_solve_bwd<T, 1>), dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, part, tasks, (int)count, wave_list, F);
+  else
+    hipLaunchKernelGGL((k_solve_bwd<T, 16>), dim3((unsigned)count), dim3(kThreads), 0, st, S, L, winv, y, part, tasks, (int)count, wave_list, F);
 }
 
 template <typename T>
-void launch_bwd(const DevSym& S, const T* L, T* y, const int32_t* list, int64_t count,
-                int32_t nrhs, hipStream_t st) {
-  if (count > 0) hipLaunchKernelGGL(k_bwd<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, L, y, list, nrhs);
+void launch_level_fwd(const DevSym& S, const T* L, const T* winv, T* y, T* uvec,
+                      const WaveItem* items, int64_t nitems, const int32_t* large, int64_t nlarge,
+                      const int32_t* wave_list, int nrhs, int32_t* counters, int64_t ns,
+                      int64_t nblk, int32_t* hang, hipStream_t st) {
+  const int64_t grid = (nitems + 3) / 4 + nlarge;
+  if (grid <= 0) return;
+  const SolveFlags F = solve_flags(counters, ns, nblk, hang, 0);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_level_fwd<T, 1>), dim3((unsigned)grid), dim3(kThreads), 0, st, S, L, winv, y, uvec, items, (int)nitems, large, wave_list, F);
+  else
+    hipLaunchKernelGGL((k_level_fwd<T, 16>), dim3((unsigned)grid), dim3(kThreads), 0, st, S, L, winv, y, uvec, items, (int)nitems, large, wave_list, F);
+}
+
+template <typename T>
+void launch_level_bwd(const DevSym& S, const T* L, const T* winv, T* y, T* part,
+                      const WaveItem* items, int64_t nitems, const int32_t* large, int64_t nlarge,
+                      const int32_t* wave_list, int nrhs, int32_t* counters, int64_t ns,
+                      int64_t nblk, int32_t* hang, hipStream_t st) {
+  const int64_t grid = (nitems + 3) / 4 + nlarge;
+  if (grid <= 0) return;
+  const SolveFlags F = solve_flags(counters, ns, nblk, hang, 1);
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_level_bwd<T, 1>), dim3((unsigned)grid), dim3(kThreads), 0, st, S, L, winv, y, part, items, (int)nitems, large, wave_list, F);
+  else
+    hipLaunchKernelGGL((k_level_bwd<T, 16>), dim3((unsigned)grid), dim3(kThreads), 0, st, S, L, winv, y, part, items, (int)nitems, large, wave_list, F);
+}
+
+template <typename T>
+void launch_solve_out(const DevSym& S, const T* y, double* x, int64_t ldx, int nrhs,
+                      const double* scale, int accumulate, hipStream_t st) {
+  if (S.n <= 0) return;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_permute_out<T, 1>), dim3(blocks_for(S.n)), dim3(kThreads), 0, st, S, y, x, ldx, (int64_t)nrhs, scale, accumulate);
+  else
+    hipLaunchKernelGGL((k_permute_out<T, 16>), dim3(blocks_for(S.n)), dim3(kThreads), 0, st, S, y, x, ldx, (int64_t)nrhs, scale, accumulate);
 }
 
 void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
@@ -1723,26 +1935,22 @@ void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t 
                                hipStream_t);                                                     \
   template void launch_front<T>(const DevSym&, const DevNum<T>&, T*, const FrontTask*, int64_t,   \
                                 int32_t*, int64_t, int64_t, int64_t, int, int, hipStream_t);     \
-  template void launch_permute_in<T>(const DevSym&, const double*, int64_t, T*, int64_t,          \
-                                     const double*, hipStream_t);                                \
-  template void launch_permute_out<T>(const DevSym&, const T*, double*, int64_t, int64_t,         \
-                                      const double*, int, hipStream_t);                          \
-  template void launch_fwd<T>(const DevSym&, const T*, T*, T*, const int32_t*, int64_t, int32_t,  \
-                              hipStream_t);                                                      \
-  template void launch_bwd<T>(const DevSym&, const T*, T*, const int32_t*, int64_t, int32_t,      \
-                              hipStream_t);                                                      \
-  template void launch_fwd_gemv<T>(const DevSym&, const T*, const T*, T*, const GemvItem*,        \
-                                   int64_t, const ReduceItem*, int64_t, T*, int32_t,             \
-                                   hipStream_t);                                                 \
-  template void launch_bwd_gemv<T>(const DevSym&, const T*, const T*, T*, const GemvItem*,        \
-                                   int64_t, const ReduceItem*, int64_t, T*, int32_t,             \
-                                   hipStream_t);                                                 \
-  template void launch_bwd_gather<T>(const DevSym&, const T*, T*, const int32_t*, int64_t,        \
-                                     int32_t, hipStream_t);                                      \
-  template void launch_fwd_tri<T>(const DevSym&, const T*, const T*, T*, const TriItem*, int64_t, \
-                                  int32_t*, int32_t*, int32_t, hipStream_t);                     \
-  template void launch_bwd_tri<T>(const DevSym&, const T*, const T*, T*, const TriItem*, int64_t, \
-                                  int32_t*, int32_t*, int32_t, hipStream_t);
+  template void launch_solve_in<T>(const DevSym&, const double*, int64_t, T*, int,              \
+                                   const double*, int32_t*, int64_t, int64_t, hipStream_t);      \
+  template void launch_solve_fwd<T>(const DevSym&, const T*, const T*, T*, T*, const SolveTask*,  \
+                                    int64_t, const int32_t*, int, int32_t*, int64_t, int64_t,    \
+                                    int32_t*, hipStream_t);                                      \
+  template void launch_solve_bwd<T>(const DevSym&, const T*, const T*, T*, T*, const SolveTask*,  \
+                                    int64_t, const int32_t*, int, int32_t*, int64_t, int64_t,    \
+                                    int32_t*, hipStream_t);                                      \
+  template void launch_solve_out<T>(const DevSym&, const T*, double*, int64_t, int,               \
+                                    const double*, int, hipStream_t);                            \
+  template void launch_level_fwd<T>(const DevSym&, const T*, const T*, T*, T*, const WaveItem*,   \
+                                    int64_t, const int32_t*, int64_t, const int32_t*, int,       \
+                                    int32_t*, int64_t, int64_t, int32_t*, hipStream_t);          \
+  template void launch_level_bwd<T>(const DevSym&, const T*, const T*, T*, T*, const WaveItem*,   \
+                                    int64_t, const int32_t*, int64_t, const int32_t*, int,       \
+                                    int32_t*, int64_t, int64_t, int32_t*, hipStream_t);
 
 TACHO_INSTANTIATE(double)
 TACHO_INSTANTIATE(float)

@@ -448,53 +448,149 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
     }
     add_gemm_step(h);
   }
-  P.fwd_items.clear();
-  P.bwd_items.clear();
-  P.fwd_red.clear();
-  P.bwd_red.clear();
+  // Solves: backward partial-product slots of every large front, the
+  // level-by-level phase, then the dataflow phase.
+  P.fsolve.clear();
+  P.bsolve.clear();
+  P.wave_list.clear();
+  P.lwave.clear();
+  P.llarge.clear();
+  P.part_base.assign(P.woff.size(), 0);
   P.part_slots = 0;
-  P.gather_list.clear();
-  P.gather_ptr.assign(S.nlevels + 1, 0);
-  P.fred_ptr.assign(S.nlevels + 1, 0);
-  P.bred_ptr.assign(S.nlevels + 1, 0);
-  P.tri_fwd.clear();
-  P.tri_bwd.clear();
-  P.fwd_ptr.assign(S.nlevels + 1, 0);
-  P.bwd_ptr.assign(S.nlevels + 1, 0);
-  P.tri_ptr.assign(S.nlevels + 1, 0);
-  P.tri_flags = 0;
-  for (int32_t h = 0; h < S.nlevels; ++h) {
-    int32_t fslot = 0, bslot = 0;
-    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
-      const int32_t s = S.level_list[q];
-      const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
-      if (!solve_split_front(w, r)) continue;
-      if (r > 0) {
-        P.gather_list.push_back(s);
-        const int32_t fch = (w + kGemvChunk - 1) / kGemvChunk;
-        for (int32_t b = 0; b * kPanel < r; ++b) {
-          P.fwd_red.push_back({s, b, fslot, fch});
-          for (int32_t c = 0; c < fch; ++c) P.fwd_items.push_back({s, b, c, fslot++});
+  for (int32_t s = 0; s < ns; ++s) {
+    if (S.front_m[s] <= kSmallMax) continue;
+    const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+    const int32_t nch = (r + kBwdChunk - 1) / kBwdChunk;
+    for (int32_t b = 0; b * kPanel < w; ++b) {
+      if (P.part_slots + nch > INT32_MAX) {
+        err = "too many partial products for the solve plan";
+        return kInvalid;
+      }
+      P.part_base[P.wbase[s] + b] = (int32_t)P.part_slots;
+      P.part_slots += nch;
+    }
+  }
+  {
+    int32_t H = 0;
+    for (int32_t h = S.nlevels - 1; h >= 0; --h)
+      if (S.level_ptr[h + 1] - S.level_ptr[h] > kLevelFronts) {
+        H = h + 1;
+        break;
+      }
+    P.solve_split = H;
+    P.lwave_ptr.assign(H + 1, 0);
+    P.llarge_ptr.assign(H + 1, 0);
+    for (int32_t h = 0; h < H; ++h) {
+      for (int g = 8; g <= 64; g *= 2) {
+        std::vector<int32_t> sel;
+        for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+          const int32_t s = S.level_list[q], m = S.front_m[s];
+          if (m <= g && (g == 8 || m > g / 2)) sel.push_back(s);
         }
-        const int32_t bch = (r + kGemvChunk - 1) / kGemvChunk;
-        for (int32_t b = 0; b * kPanel < w; ++b) {
-          P.bwd_red.push_back({s, b, bslot, bch});
-          for (int32_t c = 0; c < bch; ++c) P.bwd_items.push_back({s, b, c, bslot++});
+        const int per = 64 / g;
+        for (size_t i = 0; i < sel.size(); i += per) {
+          WaveItem it{};
+          it.first = (int32_t)P.wave_list.size();
+          it.count = (int32_t)std::min<size_t>(per, sel.size() - i);
+          it.g = (int16_t)g;
+          for (int32_t k = 0; k < it.count; ++k) {
+            const int32_t s = sel[i + k], w = S.sptr[s + 1] - S.sptr[s];
+            it.wmax = (int16_t)std::max<int32_t>(it.wmax, w);
+            it.rmax = (int16_t)std::max<int32_t>(it.rmax, S.front_m[s] - w);
+            P.wave_list.push_back(s);
+          }
+          P.lwave.push_back(it);
         }
       }
-      const int32_t nb = (w + kPanel - 1) / kPanel;
-      const int32_t base = (int32_t)P.tri_flags;
-      for (int32_t b = 0; b < nb; ++b) P.tri_fwd.push_back({s, b, base + b, 0});
-      for (int32_t b = nb - 1; b >= 0; --b) P.tri_bwd.push_back({s, b, base + b, 0});
-      P.tri_flags += nb;
+      for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q)
+        if (S.front_m[S.level_list[q]] > kSmallMax) P.llarge.push_back(S.level_list[q]);
+      P.lwave_ptr[h + 1] = (int64_t)P.lwave.size();
+      P.llarge_ptr[h + 1] = (int64_t)P.llarge.size();
     }
-    P.fwd_ptr[h + 1] = (int64_t)P.fwd_items.size();
-    P.bwd_ptr[h + 1] = (int64_t)P.bwd_items.size();
-    P.fred_ptr[h + 1] = (int64_t)P.fwd_red.size();
-    P.bred_ptr[h + 1] = (int64_t)P.bwd_red.size();
-    P.part_slots = std::max<int64_t>(P.part_slots, std::max(fslot, bslot));
-    P.tri_ptr[h + 1] = (int64_t)P.tri_fwd.size();
-    P.gather_ptr[h + 1] = (int64_t)P.gather_list.size();
+    // Dataflow phase.  Forward, per level from the split: the diagonal
+    // blocks of the large fronts, then the wave groups, then the L21 row
+    // blocks.  Backward, per level from the root: the L21 partial products,
+    // the diagonal blocks from the last, then the wave groups.  A task waits
+    // only on its front's children (forward) or parent (backward) and on
+    // earlier blocks of its own front, all of which have smaller tickets or
+    // belong to the level-by-level phase.
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> level_groups(S.nlevels);
+    for (int32_t h = H; h < S.nlevels; ++h) {
+      int64_t first = (int64_t)P.wave_list.size();
+      for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+        const int32_t s = S.level_list[q];
+        if (S.front_m[s] <= kSmallMax) P.wave_list.push_back(s);
+      }
+      const int64_t last = (int64_t)P.wave_list.size();
+      for (int64_t g = first; g < last; g += kWaveFronts)
+        level_groups[h].push_back({g, (int32_t)std::min<int64_t>(kWaveFronts, last - g)});
+    }
+    if ((int64_t)P.wave_list.size() > INT32_MAX) {
+      err = "too many fronts for the solve plan";
+      return kInvalid;
+    }
+    for (int32_t h = H; h < S.nlevels; ++h) {
+      for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+        const int32_t s = S.level_list[q];
+        if (S.front_m[s] <= kSmallMax) continue;
+        const int32_t w = S.sptr[s + 1] - S.sptr[s];
+        for (int32_t b = 0; b * kPanel < w; ++b) P.fsolve.push_back({s, kSolveTri, b, 0});
+      }
+      for (const auto& g : level_groups[h]) P.fsolve.push_back({-1, kSolveWave, (int32_t)g.first, g.second});
+      for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+        const int32_t s = S.level_list[q];
+        if (S.front_m[s] <= kSmallMax) continue;
+        const int32_t r = S.front_m[s] - (S.sptr[s + 1] - S.sptr[s]);
+        for (int32_t k = 0; k * kPanel < r; ++k) P.fsolve.push_back({s, kSolveRows, k, 0});
+      }
+    }
+    for (int32_t h = S.nlevels - 1; h >= H; --h) {
+      for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+        const int32_t s = S.level_list[q];
+        if (S.front_m[s] <= kSmallMax) continue;
+        const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+        const int32_t nb = (w + kPanel - 1) / kPanel, nch = (r + kBwdChunk - 1) / kBwdChunk;
+        for (int32_t b = nb - 1; b >= 0; --b)
+          for (int32_t c = 0; c < nch; ++c) P.bsolve.push_back({s, kSolveRows, b, c});
+      }
+      for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+        const int32_t s = S.level_list[q];
+        if (S.front_m[s] <= kSmallMax) continue;
+        const int32_t w = S.sptr[s + 1] - S.sptr[s];
+        for (int32_t b = (w + kPanel - 1) / kPanel - 1; b >= 0; --b) P.bsolve.push_back({s, kSolveTri, b, 0});
+      }
+      for (const auto& g : level_groups[h]) P.bsolve.push_back({-1, kSolveWave, (int32_t)g.first, g.second});
+    }
+    if ((int64_t)P.fsolve.size() > INT32_MAX || (int64_t)P.bsolve.size() > INT32_MAX) {
+      err = "too many solve tasks";
+      return kInvalid;
+    }
+  }
+  // forward extend-add sources, children in ascending order
+  {
+    const int64_t nrow = S.rows_ptr[ns];
+    std::vector<int64_t> cnt(nrow + 1, 0);
+    for (int32_t c = 0; c < ns; ++c) {
+      const int32_t p = S.sparent[c];
+      if (p < 0) continue;
+      const int32_t wc = S.sptr[c + 1] - S.sptr[c];
+      for (int64_t k = S.rows_ptr[c] + wc; k < S.rows_ptr[c + 1]; ++k) ++cnt[S.rows_ptr[p] + S.rmap[k] + 1];
+    }
+    for (int64_t q = 0; q < nrow; ++q) cnt[q + 1] += cnt[q];
+    if (cnt[nrow] > INT32_MAX || P.u_elems > INT32_MAX) {
+      err = "update vectors too large for the solve plan";
+      return kInvalid;
+    }
+    P.pull_ptr.assign(cnt.begin(), cnt.end());
+    P.pull_src.assign(cnt[nrow], 0);
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int32_t p = 0; p < ns; ++p)
+      for (int32_t q = S.child_ptr[p]; q < S.child_ptr[p + 1]; ++q) {
+        const int32_t c = S.child_list[q];
+        const int32_t wc = S.sptr[c + 1] - S.sptr[c];
+        for (int64_t k = S.rows_ptr[c] + wc; k < S.rows_ptr[c + 1]; ++k)
+          P.pull_src[fill[S.rows_ptr[p] + S.rmap[k]]++] = (int32_t)(P.u_off[c] + (k - S.rows_ptr[c] - wc));
+      }
   }
   P.level_lentries.assign(S.nlevels, 0.0);
   P.level_rows.assign(S.nlevels, 0.0);

@@ -30,36 +30,37 @@ struct GemmProb {
   int32_t lda, ldc, M, N, K, c_in_u;
 };
 
-// Tile of the L21 products of a split front's solves: 64-row block (forward,
-// u -= L21 x) or 64-column block (backward, x -= L21^T u) `blk`, reduction
-// chunk `chunk` of kGemvChunk columns (forward) or rows (backward); the
-// partial product goes to slot `slot` of the level's partial-sum buffer.
-struct GemvItem {
-  int32_t s, blk, chunk, slot;
+// Task of the dataflow solves (one workgroup each, taken in ticket order).
+// Fronts with m <= kSmallMax are solved by one wave each; a kSolveWave task
+// holds up to kWaveFronts of them: wave_list[a, a + b).  A larger front is
+// split into 64-row blocks: kSolveTri, block a of the diagonal part (forward:
+// rows [64a, 64a + kb) of L11, backward: columns of it); forward kSolveRows,
+// block a of L21 (rows w + 64a ...); backward kSolveRows, the partial product
+// of L21 rows [kBwdChunk b, ...) with column block a.
+struct SolveTask {
+  int32_t s, kind, a, b;
 };
+enum SolveKind : int32_t { kSolveWave = 0, kSolveTri = 1, kSolveRows = 2 };
+constexpr int kWaveFronts = 4;   // one per wave of a 256-thread workgroup
+constexpr int kBwdChunk = 256;   // L21 rows per backward partial product
 
-// Fixed-order sum of the partial products of block `blk` of front s: slots
-// [first, first + nchunk).
-struct ReduceItem {
-  int32_t s, blk, first, nchunk;
+// Solve levels below the last level with more than kLevelFronts fronts run
+// level by level (one launch each, no flags); the levels above run as one
+// dataflow launch.  In the level-by-level phase the fronts with m <=
+// kSmallMax share waves: a WaveItem is wave_list[first, first + count), each
+// front in its own group of g lanes (g = 8, 16, 32 or 64, at least its m),
+// with wmax / rmax the largest w / r among them.
+struct WaveItem {
+  int32_t first, count;
+  int16_t g, wmax, rmax, pad;
 };
+constexpr int kLevelFronts = 256;
 
-// Block b (kPanel rows / columns) of the L11 solve of a split front; `flag`
-// is the index of the block's ready flag.
-struct TriItem {
-  int32_t s, b, flag, pad;
-};
-
-// Fronts whose solves are split into a pipelined multi-workgroup L11 part
-// and multi-workgroup L21 products.
 #if defined(__HIP__)
 #define TACHO_HOST_DEVICE __host__ __device__
 #else
 #define TACHO_HOST_DEVICE
 #endif
-TACHO_HOST_DEVICE inline bool solve_split_front(int64_t w, int64_t r) {
-  return w >= 192 || r * w >= 16384;
-}
 
 struct GemmTile {
   int32_t prob, ti, tj, size;  // size: kGemmTile or kGemmTileBig
@@ -114,7 +115,6 @@ constexpr int kGemmTile = 64;     // output tile of the update kernel
 constexpr int kGemmTileBig = 128; // output tile for large updates
 constexpr int64_t kGemmBigMin = 256 * 256;  // M*N from which the large tile is used
 constexpr int kLdAlign = 4;       // leading dimensions rounded to this many elements
-constexpr int kGemvChunk = 512;   // reduction length of one L21 product tile in the split solves
 
 struct Plan {
   // memory layout (elements; identical for FP32 and FP64)
@@ -148,17 +148,26 @@ struct Plan {
   // solve, per level: factor entries read (sum over fronts of the lower
   // trapezoid of the panel) and front rows touched
   std::vector<double> level_lentries, level_rows;
-  // split solves: per level [ptr[h], ptr[h+1]) into the item arrays
-  std::vector<GemvItem> fwd_items, bwd_items;
-  std::vector<int64_t> fwd_ptr, bwd_ptr;
-  std::vector<ReduceItem> fwd_red, bwd_red;
-  std::vector<int64_t> fred_ptr, bred_ptr;
-  int64_t part_slots = 0;  // partial-product slots (64 x 16 each) of the busiest level
-  std::vector<TriItem> tri_fwd, tri_bwd;  // per level, blocks in ticket order
-  std::vector<int32_t> gather_list;       // split fronts with r > 0, per level
-  std::vector<int64_t> gather_ptr;
-  std::vector<int64_t> tri_ptr;
-  int64_t tri_flags = 0;                  // ready flags (one per block)
+  // dataflow solves: tasks of the forward and backward sweeps in ticket
+  // order, the fronts solved by one wave, and the forward extend-add
+  // sources: for row i of front s, entries [pull_ptr[q], pull_ptr[q + 1]) of
+  // pull_src with q = rows_ptr[s] + i, each the index of an update-vector
+  // entry of a child (children in ascending order)
+  std::vector<SolveTask> fsolve, bsolve;
+  std::vector<int32_t> wave_list;
+  // level-by-level phase of the solves: levels [0, solve_split); per level
+  // h its wave items [lwave_ptr[h], lwave_ptr[h + 1]) and its fronts with m >
+  // kSmallMax [llarge_ptr[h], llarge_ptr[h + 1]) (one workgroup each)
+  int32_t solve_split = 0;
+  std::vector<WaveItem> lwave;
+  std::vector<int64_t> lwave_ptr;
+  std::vector<int32_t> llarge;
+  std::vector<int64_t> llarge_ptr;
+  std::vector<int32_t> pull_ptr, pull_src;
+  // backward partial products: per diagonal block (woff indexing) the first
+  // of its ceil(r / kBwdChunk) slots of kPanel x 16 elements
+  std::vector<int32_t> part_base;
+  int64_t part_slots = 0;
 };
 
 // Rows of pivot block j of a front of order m and width w: the diagonal
