@@ -91,7 +91,7 @@ struct tacho_sym {
   int device = -1;
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
       d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
-      d_wbase, d_woff, d_tbase, d_sparent, d_pull_ptr, d_pull_src, d_part_base;
+      d_wbase, d_woff, d_tbase, d_sparent, d_pull_ptr, d_pull_src, d_part_base, d_pt1base;
   DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fsolve, d_bsolve,
       d_wave_list, d_lwave, d_llarge;
   DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
@@ -162,7 +162,7 @@ struct tacho_num {
   tacho_sym* sym = nullptr;
   KernelProfile prof;
   int precision = TACHO_FP64;
-  DBuf L, U, avals, vals, fullvals, scale, fail, winv;
+  DBuf L, U, avals, vals, fullvals, scale, fail, winv, pt1;
   DBuf y, uvec;             // solve workspace (kRhs columns)
   DBuf part;                // partial L21 products of the split solves
   DBuf sync;                // solve tickets (2 per level) and block ready flags
@@ -281,6 +281,7 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_pull_ptr, P.pull_ptr));
   HIP_TRY(upload(h->d_pull_src, P.pull_src));
   HIP_TRY(upload(h->d_part_base, P.part_base));
+  HIP_TRY(upload(h->d_pt1base, P.pt1base));
   HIP_TRY(upload(h->d_small, P.small_list));
   HIP_TRY(upload(h->d_asm, P.asm_items));
   HIP_TRY(upload(h->d_diag, P.diag_items));
@@ -325,6 +326,7 @@ int ensure_uploaded(tacho_sym* h) {
   v.pull_ptr = h->d_pull_ptr.as<int32_t>();
   v.pull_src = h->d_pull_src.as<int32_t>();
   v.part_base = h->d_part_base.as<int32_t>();
+  v.pt1base = h->d_pt1base.as<int32_t>();
   h->device = dev;
   h->uploaded = true;
   return TACHO_OK;
@@ -357,6 +359,7 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += (int64_t)kRowBytes * (S.n + P.u_elems);
   b += (int64_t)es * std::max<int64_t>(P.part_slots, 1) * kPanel * kRhs;
   b += (int64_t)es * P.W_elems;
+  b += (int64_t)es * kPanel * kPanel * P.pt1_slots;
   b += 4 * (solve_counters(h) + 1);
   b += 4 * flow_ints(h);
   if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;  // values, scaling
@@ -371,6 +374,7 @@ DevNum<T> num_view(tacho_num* f) {
   N.avals = f->avals.as<T>();
   N.scale = f->precision == TACHO_FP32 && f->sym->opt.scale ? f->scale.as<double>() : nullptr;
   N.fail = f->fail.as<int32_t>();
+  N.pt1 = f->pt1.as<T>();
   return N;
 }
 
@@ -551,6 +555,7 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   HIP_TRY(f->vals.alloc(sizeof(double) * S.nnz_input));
   HIP_TRY(f->fail.alloc(sizeof(int32_t)));
   HIP_TRY(f->winv.alloc(es * std::max<int64_t>(P.W_elems, 1)));
+  HIP_TRY(f->pt1.alloc(es * kPanel * kPanel * std::max<int64_t>(P.pt1_slots, 1)));
   HIP_TRY(f->y.alloc((size_t)kRowBytes * S.n));
   HIP_TRY(f->uvec.alloc((size_t)kRowBytes * std::max<int64_t>(P.u_elems, 1)));
   HIP_TRY(f->part.alloc(es * std::max<int64_t>(P.part_slots, 1) * kPanel * kRhs));

@@ -37,6 +37,7 @@ struct DevSym {
   const int32_t* pull_ptr;   // per front row (rows_ptr indexing): first extend-add source
   const int32_t* pull_src;   // update-vector entry of each source
   const int32_t* part_base;  // per diagonal block: first backward partial-product slot
+  const int32_t* pt1base;    // per pivot block of a chain front: 64 x 64 product slot (-1: none)
 };
 
 template <typename T>
@@ -46,6 +47,7 @@ struct DevNum {
   T* avals;         // A entries in assembly order (scaled for FP32)
   const double* scale;  // Jacobi scaling per permuted column (FP32 path) or nullptr
   int32_t* fail;    // smallest failing permuted column, INT32_MAX if none
+  T* pt1;           // chain products, 64 x 64 per slot (column-major)
 };
 
 // Host launchers (kernels.hip).

@@ -749,7 +749,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   const int fcols = utile ? bcols : kb;
   const int tri_off = utile ? (tt - tj) * TT : INT_MAX / 2;  // U: keep gi >= gj
   const T* dbase = Lp + c0 + (int64_t)c0 * ld;
-  auto fold_f = [&]() {
+  auto fold_acc = [&]() {
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
@@ -766,7 +766,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
           const T va = *(ma ? fbase + (i + jj * fld) : (const T*)Lp);
           acc[a][b][v] = (ma ? T(1) : T(0)) * (va - acc[a][b][v]);
         }
-    if (!diag) return;
+  };
+  auto fold_dacc = [&]() {
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
@@ -779,6 +780,203 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
           dacc[a][b][v] = (md ? T(1) : T(0)) * (vd - dacc[a][b][v]);
         }
   };
+  auto fold_f = [&]() {
+    fold_acc();
+    if (diag) fold_dacc();
+  };
+
+  T* Cs = lds;                      // C tile, column-major, ld kDiagLd
+  T* Ws = lds + kPanel * kDiagLd;   // W_j, column-major, ld kDiagLd
+  T(*Tmp)[kSub * kSub] = reinterpret_cast<T(*)[kSub * kSub]>(lds + 2 * kPanel * kDiagLd);
+  int32_t* done = tile_done + S.tbase[wb + tj];  // flags of pivot block j's row tiles
+
+  // rows [a0, a0 + arows): X = C W_j^T with C in Cs and W_j in Ws; with
+  // keep, X also replaces C in Cs (column-major, zero outside the tile)
+  auto trsm_rows = [&](bool keep) {
+    V4 x[BL][BL];
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b) x[a][b] = V4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int ks = 0; ks < kPanel / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      T av[BL], bv[BL];
+#pragma unroll
+      for (int a = 0; a < BL; ++a) av[a] = Cs[kk * kDiagLd + wr * (TT / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < BL; ++b) bv[b] = Ws[kk * kDiagLd + wc * (TT / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b) x[a][b] = mfma16(bv[b], av[a], x[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = oi(a), c = oj(b, v);
+          if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = x[a][b][v];
+        }
+    if (keep) {
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = oi(a), c = oj(b, v);
+            Cs[c * kDiagLd + r] = (r < arows && c < kb) ? x[a][b][v] : T(0);
+          }
+    }
+  };
+  // C = F - acc of the row tile into Cs (zero outside the tile)
+  auto stage_rows = [&]() {
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Cs[oj(b, v) * kDiagLd + oi(a)] = acc[a][b][v];
+  };
+  // diagonal block: F - Y Y^T into Cs (identity past kb, zero above the
+  // diagonal), Cholesky and inverse, L_jj and W_j stored and published
+  auto factor_diag = [&](bool publish) {
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = oi(a), c = oj(b, v);
+          T val;
+          if (r < kb && c < kb && r >= c)
+            val = dacc[a][b][v];
+          else
+            val = (r == c && r >= kb) ? T(1) : T(0);
+          Cs[c * kDiagLd + r] = val;
+        }
+    __syncthreads();
+    diag_factor_inverse<T>(Cs, Ws, Tmp, kb, f + c0, N.fail);
+    for (int t = tid; t < kb * kb; t += kThreads) {
+      const int c = t / kb, r = t - c * kb;
+      if (r >= c) Lc0[(c0 + r) + c * ld] = Cs[c * kDiagLd + r];
+    }
+    T* Wout = winv + S.woff[wb + tj];  // kb x kb, column-major
+    for (int t = tid; t < kb * kb; t += kThreads) {
+      const int c = t / kb, r = t - c * kb;
+      Wout[t] = Ws[c * kDiagLd + r];
+    }
+    if (publish) {
+      publish_barrier();
+      if (tid == 0) set_flag(done, 1);
+    } else {
+      __syncthreads();
+    }
+  };
+  // out[a][b] += sum_k B(rb0 + row, k) A(ra0 + row, k) over columns k in
+  // [k0, k1), both operands loaded from the front panel
+  auto gemm_direct = [&](V4 (&out)[BL][BL], int ra0, int na, int rb0, int nbr, int k0, int k1) {
+#pragma unroll 1
+    for (int k4 = k0; k4 < k1; k4 += 16) {
+      T av[4][BL], bv[4][BL];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k4 + 4 * u + (lane >> 4);
+        const int kc = min(k, k1 - 1);
+#pragma unroll
+        for (int a = 0; a < BL; ++a) {
+          const int r = wr * (TT / 2) + a * 16 + (lane & 15);
+          const bool ok = k < k1 && r < na;
+          av[u][a] = Lp[(ra0 + min(r, na - 1)) + (int64_t)kc * ld] * (ok ? T(1) : T(0));
+        }
+#pragma unroll
+        for (int b = 0; b < BL; ++b) {
+          const int r = wc * (TT / 2) + b * 16 + (lane & 15);
+          const bool ok = k < k1 && r < nbr;
+          bv[u][b] = Lp[(rb0 + min(r, nbr - 1)) + (int64_t)kc * ld] * (ok ? T(1) : T(0));
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int a = 0; a < BL; ++a)
+#pragma unroll
+          for (int b = 0; b < BL; ++b) out[a][b] = mfma16(bv[u][b], av[u][a], out[a][b]);
+    }
+  };
+
+  if (mode == 0 && tk.kind == 2) {
+    // Chain step: one pivot block (j - 1) to apply.  Its rows of block j
+    // (row tile 1 of block j - 1) are this workgroup's previous result,
+    // still in Cs; the product of its rows of row tile 1 of block j with
+    // them was formed by the tasks of block j - 1 that own those rows (slot
+    // pt1 of block j).  So the diagonal block is updated from LDS, factored,
+    // and only then is the other tasks' product awaited; both row tiles of
+    // block j are published together at the end.
+    if (K > kstart) {
+#pragma unroll 4
+      for (int ks = 0; ks < TT / 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        T yv[BL], bv[BL];
+#pragma unroll
+        for (int a = 0; a < BL; ++a) yv[a] = Cs[kk * kDiagLd + wr * (TT / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < BL; ++b) bv[b] = Cs[kk * kDiagLd + wc * (TT / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < BL; ++a)
+#pragma unroll
+          for (int b = 0; b < BL; ++b) dacc[a][b] = mfma16(bv[b], yv[a], dacc[a][b]);
+      }
+      __syncthreads();
+    }
+    fold_dacc();
+    factor_diag(false);
+    if (!fuse1) {
+      if (tid == 0) set_flag(done, 1);
+      return;
+    }
+    if (K > kstart) {
+      if (tid == 0) {
+        const int32_t* fl = tile_done + S.tbase[wb + tj - 1];
+        const int t1 = front_row_tile(w, tj - 1, a0 + arows - 1);
+        for (int t = front_row_tile(w, tj - 1, a0); t <= t1; ++t) wait_at_least(fl + t, 1, hang);
+        acquire_agent();
+      }
+      __syncthreads();
+      if (kb == TT) {
+        const T* P1 = N.pt1 + (int64_t)S.pt1base[wb + tj] * (TT * TT);
+#pragma unroll
+        for (int a = 0; a < BL; ++a)
+#pragma unroll
+          for (int b = 0; b < BL; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int r = oi(a), c = oj(b, v);
+              const bool ok = r < arows && c < kb;
+              acc[a][b][v] = P1[ok ? r + c * TT : 0] * (ok ? T(1) : T(0));
+            }
+      } else {
+        // last (partial) block: part of its row tile 1 lies in row tile 1
+        // of block j - 1, which no other task owns; apply block j - 1 here
+        gemm_direct(acc, a0, arows, b0, bcols, kstart, K);
+      }
+    }
+    fold_acc();
+    stage_rows();
+    __syncthreads();
+    trsm_rows(true);
+    publish_barrier();
+    if (tid == 0) {
+      release_agent();
+      __hip_atomic_store(done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(done + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
 
   // acc = X Y^T over the completed pivot blocks (X: rows a0.., Y: rows b0..);
   // a diagonal task accumulates Y Y^T in dacc as well.  Half a pivot block
@@ -910,51 +1108,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     return;
   }
 
-  T* Cs = lds;                      // C tile, column-major, ld kDiagLd
-  T* Ws = lds + kPanel * kDiagLd;   // W_j, column-major, ld kDiagLd
-  T(*Tmp)[kSub * kSub] = reinterpret_cast<T(*)[kSub * kSub]>(lds + 2 * kPanel * kDiagLd);
-  int32_t* done = tile_done + S.tbase[wb + tj];  // flags of pivot block j's row tiles
-
-  // rows [a0, a0 + arows): X = C W_j^T with C in Cs and W_j in Ws
-  auto trsm_rows = [&]() {
-    V4 x[BL][BL];
-#pragma unroll
-    for (int a = 0; a < BL; ++a)
-#pragma unroll
-      for (int b = 0; b < BL; ++b) x[a][b] = V4{0, 0, 0, 0};
-#pragma unroll 4
-    for (int ks = 0; ks < kPanel / 4; ++ks) {
-      const int kk = ks * 4 + (lane >> 4);
-      T av[BL], bv[BL];
-#pragma unroll
-      for (int a = 0; a < BL; ++a) av[a] = Cs[kk * kDiagLd + wr * (TT / 2) + a * 16 + (lane & 15)];
-#pragma unroll
-      for (int b = 0; b < BL; ++b) bv[b] = Ws[kk * kDiagLd + wc * (TT / 2) + b * 16 + (lane & 15)];
-#pragma unroll
-      for (int a = 0; a < BL; ++a)
-#pragma unroll
-        for (int b = 0; b < BL; ++b) x[a][b] = mfma16(bv[b], av[a], x[a][b]);
-    }
-#pragma unroll
-    for (int a = 0; a < BL; ++a)
-#pragma unroll
-      for (int b = 0; b < BL; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = oi(a), c = oj(b, v);
-          if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = x[a][b][v];
-        }
-  };
-  // C = F - acc of the row tile into Cs (zero outside the tile)
-  auto stage_rows = [&]() {
-#pragma unroll
-    for (int a = 0; a < BL; ++a)
-#pragma unroll
-      for (int b = 0; b < BL; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Cs[oj(b, v) * kDiagLd + oi(a)] = acc[a][b][v];
-  };
-
   if (pre) {
     // pre-accumulated diagonal block and row tile 1 go back in place; the
     // chain applies the last pivot block and factors
@@ -973,39 +1126,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     return;
   }
   if (diag) {
-    // diagonal block: F - Y Y^T, identity past kb, zero above the diagonal
-#pragma unroll
-    for (int a = 0; a < BL; ++a)
-#pragma unroll
-      for (int b = 0; b < BL; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = oi(a), c = oj(b, v);
-          T val;
-          if (r < kb && c < kb && r >= c)
-            val = dacc[a][b][v];
-          else
-            val = (r == c && r >= kb) ? T(1) : T(0);
-          Cs[c * kDiagLd + r] = val;
-        }
-    __syncthreads();
-    diag_factor_inverse<T>(Cs, Ws, Tmp, kb, f + c0, N.fail);
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, r = t - c * kb;
-      if (r >= c) Lc0[(c0 + r) + c * ld] = Cs[c * kDiagLd + r];
-    }
-    T* Wout = winv + S.woff[wb + tj];  // kb x kb, column-major
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, r = t - c * kb;
-      Wout[t] = Ws[c * kDiagLd + r];
-    }
-    publish_barrier();
-    if (tid == 0) set_flag(done, 1);  // release: the workgroup's stores are in L2 after the barrier
+    factor_diag(true);
     if (!fuse1) return;
     // row tile 1 (still in registers) against the inverse in LDS
     stage_rows();
     __syncthreads();
-    trsm_rows();
+    trsm_rows(false);
     publish_barrier();
     if (tid == 0) set_flag(done + 1, 1);
     return;
@@ -1025,7 +1151,38 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     }
   }
   __syncthreads();
-  trsm_rows();
+  trsm_rows(false);
+  if (tk.p0 && c0 + kb + TT <= w) {
+    // chain front: rows of this tile that are row tile 1 of block j + 1 also
+    // get their product with row tile 1 of block j (the chain's result), for
+    // the chain's step j + 1 (a full block j + 1; the last, partial one
+    // applies block j itself)
+    const int c1 = c0 + kb, kb1 = min(TT, w - c1);
+    const int t1lo = c1 + kb1, t1hi = min(m, t1lo + TT);
+    const int lo = max(a0, t1lo), hi = min(a0 + arows, t1hi);
+    if (lo < hi) {
+      if (tid == 0) {
+        wait_at_least(done + 1, 1, hang);
+        acquire_agent();
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b) acc[a][b] = V4{0, 0, 0, 0};
+      gemm_direct(acc, a0, arows, c1, kb1, c0, c0 + kb);
+      T* P1 = N.pt1 + (int64_t)S.pt1base[wb + tj + 1] * (TT * TT);
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = a0 + oi(a), c = oj(b, v);
+            if (r >= lo && r < hi && c < kb1) P1[(r - t1lo) + c * TT] = acc[a][b][v];
+          }
+    }
+  }
   publish_barrier();
   if (tid == 0) set_flag(done + tt, 1);
   };

@@ -199,6 +199,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
   P.tiles.clear();
   P.ftasks.clear();
   P.nucount = 0;
+  P.pt1base.assign(P.woff.size(), -1);
+  P.pt1_slots = 0;
   // Problems of one update launch group; tiles are emitted per tile size so
   // that every launch uses a single tile shape.
   std::vector<int32_t> group;
@@ -303,6 +305,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
             if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= kChainMin) {
               chain[bi] = 1;
               P.ftasks.push_back({s, 0, 0, 2, 0, 0, 0, 0});
+              const int32_t nbs = (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel;
+              for (int32_t b = 1; b < nbs; ++b) P.pt1base[P.wbase[s] + b] = (int32_t)P.pt1_slots++;
             }
           }
       }
@@ -314,7 +318,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
           // the diagonal task (t = 0) also produces row tile 1
           const int nt = front_block_tiles(m, w, j);
           for (int t = chain[bi] ? 2 : 0; t < nt; ++t)
-            if (t != 1) P.ftasks.push_back({s, j, t, 0, 0, 0, 0, 0});
+            if (t != 1) P.ftasks.push_back({s, j, t, 0, chain[bi], 0, 0, 0});
           if (chain[bi] && (j + 2) * kPanel < w) P.ftasks.push_back({s, j + 2, 0, 3, 0, 0, 0, 0});
         }
         for (size_t bi = 0; bi < big.size(); ++bi) {

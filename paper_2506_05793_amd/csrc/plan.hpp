@@ -75,7 +75,9 @@ struct GemmTile {
 // range rk-1 (counter ui of the tile orders them).  kind 2: the chain of
 // diagonal blocks of front s (all its t = 0 work, in order).  kind 3:
 // pre-accumulation of diagonal block j and row tile 1 of front s over the
-// pivot blocks before j - 1, for the chain.
+// pivot blocks before j - 1, for the chain.  A kind 0 task of a chain front
+// has p0 = 1: its rows that are row tile 1 of block j + 1 also get their
+// product with row tile 1 of block j, for the chain's step j + 1.
 struct FrontTask {
   int32_t s, j, t, kind;
   int32_t p0, p1, ui, rk;
@@ -131,6 +133,11 @@ struct Plan {
   // completion flag (prefix sums of front_block_tiles; one entry past the end)
   std::vector<int32_t> tbase;
   int64_t nucount = 0;  // update-matrix tile counters (one per tile of every large front)
+  // chain fronts: per pivot block j >= 1 (woff indexing) a 64 x 64 slot for the
+  // product of block j - 1's rows of row tile 1 of block j with row tile 1 of
+  // block j - 1 (-1: none)
+  std::vector<int32_t> pt1base;
+  int64_t pt1_slots = 0;
   std::vector<int32_t> a_pos;   // per A entry: row + col*ldL inside the front panel
   std::vector<int32_t> diag_q;  // per permuted column: A entry of the diagonal (-1: absent)
 
