@@ -359,6 +359,10 @@ def main():
     ap.add_argument("--li-side", type=int, default=200, help="land-ice base grid side")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the plan parameters of the 3D workload (FP64 and FP32) on the "
+                         "device and store them in the package's tuning table")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the tuning table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--eager", action="store_true",
@@ -405,10 +409,30 @@ def main():
     A = gen.fv3d(side, seed=1)
     b1 = gen.rhs(A.n, 1, seed=2)
     b16 = gen.rhs(A.n, 16, seed=2)
+    from paper_2506_05793_amd import autotune
+    if args.autotune:
+        tab = autotune.TuningTable(autotune.DEFAULT_TABLE)
+        out = {}
+        for prec, name in ((T.TACHO_FP64, "fp64"), (T.TACHO_FP32, "fp32")):
+            best, m, hist = autotune.tune(A.n, A.rowptr, A.colind, A.values, prec, log=log)
+            key = autotune.workload_key(A.n, A.nnz, 1, prec)
+            tab.put(key, best, {"workload": f"3D lognormal {side}^3", "device": "MI355X",
+                                "factor_ms": m["factor_ms"], "solve_ms": m["solve_ms"],
+                                "default_factor_ms": hist[0][1]["factor_ms"],
+                                "default_solve_ms": hist[0][1]["solve_ms"],
+                                "candidates": len(hist)})
+            out[name] = {"key": key, "best": best, "measured": m, "default": hist[0][1]}
+        tab.save()
+        print(json.dumps({"autotune": out}), flush=True)
+        return
+    plan64 = {} if args.no_tuning else autotune.tuned_params(A.n, A.nnz, 1, T.TACHO_FP64)
+    plan32 = {} if args.no_tuning else autotune.tuned_params(A.n, A.nnz, 1, T.TACHO_FP32)
+    extra = {"graphs": 0} if args.eager else {}
     t0 = time.perf_counter()
-    sym = T.tacho_analyze(A.n, A.rowptr, A.colind,
-                          T.tacho_default_options(graphs=0) if args.eager else None)
+    sym = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**plan64, **extra))
     analyze_s = time.perf_counter() - t0
+    sym32 = sym if plan32 == plan64 else T.tacho_analyze(
+        A.n, A.rowptr, A.colind, T.tacho_default_options(**plan32, **extra))
     q = T.tacho_query_symbolic(sym)
     log(f"[bench] analyze {analyze_s:.2f}s nnz(L)={q['nnz_l']:.3e} flops={q['flops']:.3e} "
         f"supernodes={q['nsuper']} levels={q['nlevels']}")
@@ -424,7 +448,7 @@ def main():
     mixed = None
     if not args.no_mixed:
         log("[bench] mixed FP32 factor + FP64 refinement")
-        num32, r32 = run_mixed(T, torch, A, sym, vals, b1, b16, max(3, args.steps // 2), 1)
+        num32, r32 = run_mixed(T, torch, A, sym32, vals, b1, b16, max(3, args.steps // 2), 1)
         mixed = summarize(r32, q["flops"], 1e-10)
         log(f"[bench] mixed factor {mixed['factor_ms_p50']:.2f} ms, solve1 "
             f"{mixed['solve_nrhs1_ms_p50']:.2f} ms, rho {mixed['rel_residual_nrhs1']:.1e}")
@@ -463,6 +487,7 @@ def main():
             "supernodes": q["nsuper"], "levels": q["nlevels"], "max_front": q["max_front"],
             "ordering": "own nested dissection + etree postorder",
             "analyze_s_host": analyze_s,
+            "plan_fp64": plan64 or "defaults", "plan_fp32": plan32 or "defaults",
         },
         "fp64": s64,
         "mixed": mixed,

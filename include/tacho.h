@@ -55,8 +55,9 @@ typedef struct tacho_num *tacho_num_t;
 typedef struct {
   int32_t nd_leaf_size;      /* nested dissection stops at parts of at most this many
                                 vertices (default 8) */
-  int32_t small_front;       /* fronts with m <= small_front are assembled and factored
-                                in LDS by one workgroup (0 = library default) */
+  int32_t small_front;       /* reserved, must be 0: fronts with m <= 64 are always
+                                assembled and factored in LDS by one workgroup (the
+                                class is fixed by the kernels' LDS layout) */
   int32_t scale;             /* FP32 path: symmetric Jacobi scaling diag(C)^{-1/2} (default 1) */
   int32_t refine_max;        /* FP32 path: at most this many corrections (default 10) */
   double refine_tol;         /* FP32 path: stop when ||b - A x||_2 / ||b||_2 <= tol
@@ -65,7 +66,8 @@ typedef struct {
                                 twice in a row, counts as a stall (default 0.5) */
   uint64_t hbm_budget_bytes; /* 0 = no limit; tacho_factorize returns TACHO_ERR_NOMEM
                                 when the factor plus workspace would exceed it */
-  int32_t block_size;        /* panel width of the blocked large-front path (0 = 64) */
+  int32_t block_size;        /* reserved, must be 0: the pivot-block width of the
+                                large-front kernels is 64 (their MFMA tiling) */
   int32_t ordering;          /* 0 (default): both orderings below, keep the one with
                                 fewer factorization flops; 1: multilevel nested
                                 dissection; 2: level-structure nested dissection */
@@ -77,7 +79,18 @@ typedef struct {
                                 per level (tile tasks over 64-column pivot blocks with
                                 completion counters); 1: stepwise launches per pivot
                                 block (diagonal block, rows below, trailing update) */
-  int32_t reserved[4];
+  /* Batching parameters of the launch plan (0 = default).  They change how
+   * work is grouped into tasks and launches, not which operations a front
+   * performs; u_range and chain_min change the order in which the same
+   * contributions are summed, so results agree to rounding.  The autotuner
+   * of the Python package times candidates on the device. */
+  int32_t u_range;           /* pivot blocks per update-matrix range task (default 8) */
+  int32_t chain_min;         /* fronts with at least this many 64-column pivot blocks
+                                run their diagonal blocks as one chain task (default 3;
+                                negative: never) */
+  int32_t solve_level_fronts; /* solve levels below the last level with more than
+                                this many fronts run level by level (default 256) */
+  int32_t asm_cols;          /* front columns per assembly workgroup (default 8) */
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */

@@ -47,7 +47,10 @@ class tacho_options(ctypes.Structure):
         ("ordering", ctypes.c_int32),
         ("graphs", ctypes.c_int32),
         ("front_kernel", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("u_range", ctypes.c_int32),
+        ("chain_min", ctypes.c_int32),
+        ("solve_level_fronts", ctypes.c_int32),
+        ("asm_cols", ctypes.c_int32),
     ]
 
 

@@ -1,0 +1,174 @@
+"""Autotuner of the launch plan's batching parameters.
+
+The numeric kernels have fixed tile shapes (64-column pivot blocks on the
+matrix cores, fronts of order <= 64 in LDS).  What the plan can vary is how
+work is grouped into tasks and launches (the paper's Tacho section batches
+the many small fronts of the low levels and gives the few large ones at the
+top their own kernels; where the boundary between the two regimes lies
+depends on the matrix and the device):
+
+* ``u_range`` - pivot blocks per update-matrix range task of the dataflow
+  front kernel;
+* ``chain_min`` - fronts with at least this many pivot blocks run their
+  diagonal blocks as one chain task (negative: never);
+* ``solve_level_fronts`` - solve levels below the last level with more than
+  this many fronts run level by level, the rest as one dataflow launch;
+* ``asm_cols`` - front columns per assembly workgroup.
+
+None of them changes which operations a front performs; ``u_range`` and
+``chain_min`` change the order in which the same contributions are summed,
+so results agree to rounding.
+
+``tune`` times candidates on the device by coordinate descent from the
+defaults (each candidate must reach the residual bound) and returns the
+best setting; ``TuningTable`` keeps settings per workload class in a JSON
+file; ``options_for`` turns a table entry into ``tacho_options``.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import (TACHO_FP64, tacho_analyze, tacho_default_options, tacho_factorize,
+               tacho_query_symbolic, tacho_refactorize, tacho_solve)
+
+DEFAULTS = {"u_range": 8, "chain_min": 3, "solve_level_fronts": 256, "asm_cols": 8}
+CANDIDATES = {
+    "u_range": (4, 8, 16),
+    "chain_min": (2, 3, 4, 6, -1),
+    "solve_level_fronts": (64, 256, 1024),
+    "asm_cols": (4, 8, 16),
+}
+
+
+def workload_key(n: int, nnz: int, nsys: int = 1, precision: int = TACHO_FP64) -> str:
+    """Coarse workload class: order (power of two), mean row degree, systems,
+    precision."""
+    lg = int(round(math.log2(max(n, 1))))
+    deg = int(round(nnz / max(n, 1)))
+    prec = "fp64" if precision == TACHO_FP64 else "fp32"
+    return f"n~2^{lg}/deg{deg}/sys{'1' if nsys <= 1 else 'many'}/{prec}"
+
+
+def _residual(rowptr, colind, values, x, b):
+    """Max over columns of ||b - A x||_2 / ||b||_2 (full symmetric CSR)."""
+    import scipy.sparse as sp
+    n = len(rowptr) - 1
+    A = sp.csr_matrix((values, colind, rowptr), shape=(n, n))
+    r = b - A @ x
+    return float(np.max(np.linalg.norm(r, axis=0) / np.linalg.norm(b, axis=0)))
+
+
+def measure(n, rowptr, colind, values, params, precision=TACHO_FP64, reps=7, ordering=0,
+            tol=None):
+    """Median device times (ms) of a refactorization and of a 1-RHS solve with
+    the given plan parameters; ``None`` if the residual bound is missed."""
+    import torch
+    opts = tacho_default_options(ordering=ordering, **params)
+    sym = tacho_analyze(n, rowptr, colind, opts)
+    vals = torch.from_numpy(np.ascontiguousarray(values)).cuda()
+    num = tacho_factorize(sym, vals, precision)
+    b = np.random.default_rng(0).standard_normal((n, 1))
+    bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()
+    xd = torch.empty_like(bd)
+    for _ in range(2):
+        tacho_refactorize(num, vals, sync=True)
+        tacho_solve(num, bd, xd)
+    torch.cuda.synchronize()
+    tf, ts = [], []
+    for _ in range(reps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        tacho_refactorize(num, vals, sync=False)
+        e[1].record()
+        tacho_solve(num, bd, xd)
+        e[2].record()
+        torch.cuda.synchronize()
+        tf.append(e[0].elapsed_time(e[1]))
+        ts.append(e[1].elapsed_time(e[2]))
+    tacho_refactorize(num, vals, sync=True)
+    rho = _residual(rowptr, colind, values, xd.cpu().numpy(), b)
+    bound = tol if tol is not None else (1e-12 if precision == TACHO_FP64 else 1e-10)
+    if not rho <= bound:
+        return None
+    return {"factor_ms": float(np.median(tf)), "solve_ms": float(np.median(ts)), "rho": rho}
+
+
+def tune(n, rowptr, colind, values, precision=TACHO_FP64, reps=7, passes=1,
+         objective="request", log=print):
+    """Coordinate descent over CANDIDATES from DEFAULTS.
+
+    objective "request": factor + 1-RHS solve time; "factor": factor time.
+    Returns (best parameters, best measurement, history)."""
+    sym = tacho_analyze(n, rowptr, colind)
+    ordering = int(tacho_query_symbolic(sym)["ordering"])
+    del sym
+
+    def score(m):
+        return m["factor_ms"] + (m["solve_ms"] if objective == "request" else 0.0)
+
+    best = dict(DEFAULTS)
+    best_m = measure(n, rowptr, colind, values, best, precision, reps, ordering)
+    if best_m is None:
+        raise RuntimeError("the default plan misses the residual bound")
+    history = [(dict(best), best_m)]
+    log(f"[autotune] defaults {best}: {best_m}")
+    for _ in range(passes):
+        for name, values_ in CANDIDATES.items():
+            for v in values_:
+                if v == best[name]:
+                    continue
+                cand = dict(best)
+                cand[name] = v
+                t0 = time.perf_counter()
+                m = measure(n, rowptr, colind, values, cand, precision, reps, ordering)
+                history.append((cand, m))
+                log(f"[autotune] {name}={v}: {m} ({time.perf_counter() - t0:.1f} s)")
+                if m is not None and score(m) < score(best_m):
+                    best, best_m = cand, m
+    log(f"[autotune] best {best}: {best_m}")
+    return best, best_m, history
+
+
+class TuningTable:
+    """Tuned parameters per workload class, stored as JSON."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self.entries = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                self.entries = json.load(fh)
+
+    def get(self, key: str):
+        e = self.entries.get(key)
+        return dict(e["params"]) if e else None
+
+    def put(self, key: str, params: dict, info: dict | None = None):
+        self.entries[key] = {"params": dict(params), "info": info or {}}
+
+    def save(self):
+        with open(self.path, "w") as fh:
+            json.dump(self.entries, fh, indent=1, sort_keys=True)
+
+
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
+
+def tuned_params(n: int, nnz: int, nsys: int = 1, precision: int = TACHO_FP64,
+                 table: str | None = None) -> dict:
+    """Tuned plan parameters of the workload class ({} when the table has none)."""
+    return TuningTable(table or DEFAULT_TABLE).get(workload_key(n, nnz, nsys, precision)) or {}
+
+
+def options_for(n: int, nnz: int, nsys: int = 1, precision: int = TACHO_FP64,
+                table: str | None = None, **overrides):
+    """tacho_options with the tuned plan parameters of the workload class (the
+    defaults when the table has no entry), then ``overrides``."""
+    params = tuned_params(n, nnz, nsys, precision, table)
+    params.update(overrides)
+    return tacho_default_options(**params)

@@ -208,6 +208,8 @@ tacho_options defaults() {
 
 int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   std::string err;
+  if (h->opt.small_front != 0 || h->opt.block_size != 0)
+    return fail(TACHO_ERR_INVALID, "small_front and block_size are reserved and must be 0");
   h->S.nnz_input = nnz_input;
   SymOptions so;
   so.nd_leaf_size = h->opt.nd_leaf_size > 0 ? h->opt.nd_leaf_size : 8;
@@ -215,7 +217,12 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   int rc = analyze_pattern(h->S, so, err);
   if (rc != kOk) return fail(rc, err);
   const auto t_plan = std::chrono::steady_clock::now();
-  rc = build_plan(h->S, h->P, err, h->opt.front_kernel == 1 ? 1 : 0);
+  PlanTuning tune;
+  tune.u_range = h->opt.u_range;
+  tune.chain_min = h->opt.chain_min;
+  tune.level_fronts = h->opt.solve_level_fronts;
+  tune.asm_cols = h->opt.asm_cols;
+  rc = build_plan(h->S, h->P, err, h->opt.front_kernel == 1 ? 1 : 0, tune);
   if (rc != kOk) return fail(rc, err);
   const Symbolic& S = h->S;
   // lower-twin index of every pattern entry, for the refinement residual

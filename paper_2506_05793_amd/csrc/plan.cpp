@@ -111,7 +111,12 @@ double front_io(const Symbolic& S, int32_t s) {
 
 }  // namespace
 
-int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
+int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
+               const PlanTuning& tune) {
+  const int32_t urange = tune.u_range > 0 ? tune.u_range : kURange;
+  const int32_t chain_min = tune.chain_min == 0 ? kChainMin : tune.chain_min;
+  const int32_t level_fronts = tune.level_fronts > 0 ? tune.level_fronts : kLevelFronts;
+  const int32_t asm_cols = tune.asm_cols > 0 ? tune.asm_cols : kAsmCols;
   const int32_t ns = S.ns;
   P.front_mode = front_mode;
   static_assert(kPanel == 64, "front task tiling assumes 64-column pivot blocks");
@@ -256,7 +261,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
     int32_t wmax = 0;
     for (int32_t s : big) {
       int32_t m = S.front_m[s];
-      for (int32_t c = 0; c < m; c += kAsmCols) P.asm_items.push_back({s, c, std::min(m, c + kAsmCols), 0});
+      for (int32_t c = 0; c < m; c += asm_cols) P.asm_items.push_back({s, c, std::min(m, c + asm_cols), 0});
       wmax = std::max(wmax, S.sptr[s + 1] - S.sptr[s]);
     }
     {
@@ -266,7 +271,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
     }
     if (front_mode == 0) {
       // Dataflow: pivot blocks in column order across the level's fronts;
-      // the update-matrix tiles of a front in ranges of kURange pivot
+      // the update-matrix tiles of a front in ranges of u_range pivot
       // blocks, each range right after the last column it needs.  Every task
       // depends only on tasks with smaller tickets.
       Step st{kStepFront, h, (int64_t)P.ftasks.size(), 0};
@@ -278,7 +283,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
         ubase[bi] = (int32_t)P.nucount;
         P.nucount += (int64_t)nt * (nt + 1) / 2;
       }
-      // Range k of a front (pivot blocks [8k, 8k+8)) is emitted in kURange
+      // Range k of a front (pivot blocks [8k, 8k+8)) is emitted in u_range
       // chunks after the columns 8k+8 ... 8k+15, so that its tasks take
       // workgroup slots when their inputs are complete and interleave with
       // the pivot-block tasks that carry the critical path; what is left
@@ -290,7 +295,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
         for (; pending_pos[bi] < upto; ++pending_pos[bi]) P.ftasks.push_back(pending[bi][pending_pos[bi]]);
       };
       const int32_t ncols = (wmax + kPanel - 1) / kPanel;
-      // Fronts with at least kChainMin pivot blocks run their diagonal blocks
+      // Fronts with at least chain_min pivot blocks run their diagonal blocks
       // as one chain task (first in ticket order) when the level has few
       // of them; their block j >= 2 is pre-accumulated by a task issued
       // right after column j - 2.
@@ -298,11 +303,11 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
       {
         int nchain = 0;
         for (int32_t s : big)
-          if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= kChainMin) ++nchain;
-        if (nchain <= kMaxChains)
+          if (chain_min > 0 && (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) ++nchain;
+        if (chain_min > 0 && nchain <= kMaxChains)
           for (size_t bi = 0; bi < big.size(); ++bi) {
             const int32_t s = big[bi];
-            if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= kChainMin) {
+            if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) {
               chain[bi] = 1;
               P.ftasks.push_back({s, 0, 0, 2, 0, 0, 0, 0});
               const int32_t nbs = (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel;
@@ -326,9 +331,9 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
           const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
           const int32_t pb = (w + kPanel - 1) / kPanel;
           if (r <= 0) continue;
-          if (j < pb && ((j + 1) % kURange == 0 || j + 1 == pb)) {
+          if (j < pb && ((j + 1) % urange == 0 || j + 1 == pb)) {
             // range ending at column j: queue its tasks
-            const int32_t rk = j / kURange, p0 = rk * kURange, p1 = j + 1;
+            const int32_t rk = j / urange, p0 = rk * urange, p1 = j + 1;
             const int32_t nt = (r + kPanel - 1) / kPanel;
             for (int32_t b = 0; b < nt; ++b)
               for (int32_t a = b; a < nt; ++a) {
@@ -336,15 +341,15 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
                 pending[bi].push_back({s, b, a, 1, p0, p1, ui, rk});
               }
           }
-          // release the queued tasks of the range that ended kURange columns
+          // release the queued tasks of the range that ended u_range columns
           // ago in proportion to the columns passed since
           const int32_t per = (int32_t)((r + kPanel - 1) / kPanel);
           const size_t range_tasks = (size_t)per * (per + 1) / 2;
-          if (j >= kURange) {
-            const int32_t rk = (j - kURange) / kURange;       // range being released
-            const int32_t q = (j - kURange) % kURange + 1;    // chunks released so far
+          if (j >= urange) {
+            const int32_t rk = (j - urange) / urange;       // range being released
+            const int32_t q = (j - urange) % urange + 1;    // chunks released so far
             const size_t base = (size_t)rk * range_tasks;
-            if (rk * kURange < pb) emit_u(bi, base + range_tasks * q / kURange);
+            if (rk * urange < pb) emit_u(bi, base + range_tasks * q / urange);
           }
         }
       }
@@ -477,7 +482,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode) {
   {
     int32_t H = 0;
     for (int32_t h = S.nlevels - 1; h >= 0; --h)
-      if (S.level_ptr[h + 1] - S.level_ptr[h] > kLevelFronts) {
+      if (S.level_ptr[h + 1] - S.level_ptr[h] > level_fronts) {
         H = h + 1;
         break;
       }

@@ -54,7 +54,7 @@ struct WaveItem {
   int32_t first, count;
   int16_t g, wmax, rmax, pad;
 };
-constexpr int kLevelFronts = 256;
+constexpr int kLevelFronts = 256;  // default of PlanTuning::level_fronts
 
 #if defined(__HIP__)
 #define TACHO_HOST_DEVICE __host__ __device__
@@ -83,9 +83,18 @@ struct FrontTask {
   int32_t p0, p1, ui, rk;
 };
 
-constexpr int kURange = 8;     // pivot blocks per update-matrix task
-constexpr int kChainMin = 3;   // pivot blocks from which a front's diagonal blocks form a chain
+constexpr int kURange = 8;     // default pivot blocks per update-matrix task
+constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
 constexpr int kMaxChains = 32; // chains per level (each holds one workgroup slot for the level)
+
+// Batching parameters of the plan (task grouping only; the arithmetic of a
+// front does not depend on them).
+struct PlanTuning {
+  int32_t u_range = 8;        // pivot blocks per update-matrix range
+  int32_t chain_min = 3;      // chain fronts: at least this many pivot blocks (<= 0: none)
+  int32_t level_fronts = 256; // solve level-by-level phase threshold
+  int32_t asm_cols = 8;       // front columns per assembly workgroup
+};
 
 enum StepKind : int32_t {
   kStepSmall = 0,
@@ -190,6 +199,7 @@ TACHO_HOST_DEVICE inline int front_row_tile(int w, int j, int r) {
   return r < c0 + kb ? 0 : 1 + (r - c0 - kb) / 64;
 }
 
-int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode = 0);
+int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode = 0,
+               const PlanTuning& tune = PlanTuning());
 
 }  // namespace tacho

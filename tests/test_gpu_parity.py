@@ -89,6 +89,30 @@ def test_fp64_factor_and_solve_parity(name, make, front):
         print(f"  nrhs={nrhs} rho={rho.max():.2e} |x-x_oracle|/|x_oracle|={rel.max():.2e}")
 
 
+PLAN_SETTINGS = [
+    {"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4},
+    {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 16},
+]
+
+
+@pytest.mark.parametrize("plan", PLAN_SETTINGS, ids=["fine", "coarse"])
+@pytest.mark.parametrize("name", ["fv3d_36", "landice_9x8x4", "dense_300"])
+def test_plan_parameters_keep_parity(name, plan):
+    """The autotuner's plan parameters regroup tasks and launches: every
+    setting must still match the oracle (factor and 1/16-RHS solves)."""
+    A = dict(CASES)[name]()
+    s, a = analyze(A, **plan)
+    F = oracle.factor(A, a.perm)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    err = colnorm_error(T.tacho_get_factor(num), F)
+    print(f"{name} {plan}: column-normalized factor error {err:.3e}")
+    assert err <= FP64_FACTOR_TOL
+    for nrhs in (1, 16):
+        b = gen.rhs(A.n, nrhs, seed=2)
+        x = T.tacho_solve(num, b)
+        assert oracle.rel_residual(A, x, b).max() <= FP64_RESID_TOL
+
+
 def test_logdet_closed_form_c1():
     A = gen.laplace2d(32)
     s, a = analyze(A)

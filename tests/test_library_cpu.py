@@ -159,3 +159,34 @@ def test_indistinguishable_dofs_stay_consecutive(ordering):
     pinv[a.perm] = np.arange(A.n)
     assert np.all(pinv[1::2] == pinv[0::2] + 1)
 
+
+
+def test_plan_parameters_accepted_and_reserved_rejected():
+    """The plan's batching parameters only regroup work: any setting analyses
+    to the same symbolic result; the reserved fields must stay 0."""
+    A = gen.fv3d(12, 11, 10, seed=7)
+    base = T.tacho_get_symbolic(T.tacho_analyze(A.n, A.rowptr, A.colind))
+    for params in ({"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4},
+                   {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 32}):
+        s = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**params))
+        a = T.tacho_get_symbolic(s)
+        assert np.array_equal(a.perm, base.perm) and np.array_equal(a.super_ptr, base.super_ptr)
+    for bad in ({"small_front": 32}, {"block_size": 32}):
+        with pytest.raises(T.TachoError):
+            T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**bad))
+
+
+def test_tuning_table_roundtrip(tmp_path):
+    from paper_2506_05793_amd import autotune
+    key = autotune.workload_key(262144, 1810432)
+    assert key == autotune.workload_key(262144, 1810432, 1, T.TACHO_FP64)
+    assert key != autotune.workload_key(262144, 1810432, 1, T.TACHO_FP32)
+    path = str(tmp_path / "t.json")
+    tab = autotune.TuningTable(path)
+    assert tab.get(key) is None
+    tab.put(key, {"u_range": 16, "chain_min": 4}, {"factor_ms": 1.0})
+    tab.save()
+    assert autotune.TuningTable(path).get(key) == {"u_range": 16, "chain_min": 4}
+    opt = autotune.options_for(262144, 1810432, table=path, asm_cols=4)
+    assert (opt.u_range, opt.chain_min, opt.asm_cols) == (16, 4, 4)
+    assert autotune.options_for(1000, 5000, table=path).u_range == 0  # library default
