@@ -49,7 +49,7 @@ PEAK_HBM_GBS = 8000.0
 # figures no longer describe the kernel and the roofline reports traffic null.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "factor_kernels_fv3d64_hbm_traffic.md")
 TRAFFIC_SOURCES = ("paper_2506_05793_amd/csrc/kernels.hip", "paper_2506_05793_amd/csrc/plan.cpp",
-                   "paper_2506_05793_amd/csrc/plan.hpp")
+                   "paper_2506_05793_amd/csrc/plan.hpp", "paper_2506_05793_amd/tuning.json")
 COPY_PROBE_ELEMS = 1 << 27  # FP64 elements: 1 GiB read + 1 GiB written
 
 
@@ -358,6 +358,8 @@ def main():
                          "subdomain systems; serve: request stream")
     ap.add_argument("--li-side", type=int, default=200, help="land-ice base grid side")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=200.0,
+                    help="serve: mean arrival rate (requests/s; 0: all at once, i.e. capacity)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the plan parameters of the 3D workload (FP64 and FP32) on the "
@@ -514,7 +516,8 @@ def other_workload(args, T, torch):
     import gen
     if args.workload == "serve":
         from paper_2506_05793_amd.serve import Request, Server, summarize
-        specs = gen.serving_requests(args.requests, seed=5, rate=200.0, n2d=(1000, 250000),
+        rate = args.rate if args.rate > 0 else 1e9
+        specs = gen.serving_requests(args.requests, seed=5, rate=rate, n2d=(1000, 250000),
                                      n3d=(4000, 300000))
         reqs, mats = [], {}
         log(f"[bench] building {len(specs)} requests")
@@ -541,12 +544,16 @@ def other_workload(args, T, torch):
             r = reqs[out.rid]
             A = r.matrix if r.kind == "factor" else mats[r.target]
             worst = max(worst, float(residual(A, out.x, r.rhs).max()))
-        summ.update({"admitted_while_busy": srv.admitted_while_busy, "peak_bytes": srv.peak_used,
+        summ.update({"offered_rate_per_s": args.rate if args.rate > 0 else None,
+                     "served_requests_per_s": len(res) / wall,
+                     "admitted_while_busy": srv.admitted_while_busy, "peak_bytes": srv.peak_used,
                      "sampled_max_rel_residual": worst})
         log(f"[bench] serve {summ}")
         line_for(args, summ["rhs_solves_per_s"], "RHS solves/s", "f64",
                  {"workload": f"Poisson request stream, {len(reqs)} requests, 2D n 1k-250k and "
-                              f"3D n 4k-300k lognormal, 1-16 RHS, 30% repeat"}, {"serve": summ})
+                              f"3D n 4k-300k lognormal, 1-16 RHS, 30% repeat",
+                  "offered_rate_per_s": args.rate if args.rate > 0 else "all at t=0"},
+                 {"serve": summ})
         return
     if args.workload == "batch":
         mats = gen.batch_fv3d(256, seed=4)
