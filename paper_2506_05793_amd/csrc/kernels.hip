@@ -274,14 +274,14 @@ __device__ inline typename Vec4<T>::type mm16(FA a, FB b, typename Vec4<T>::type
 // Cholesky of the kb x kb diagonal block held in D (column-major, ld
 // kDiagLd, entries past kb set to the identity), in place, and its inverse W
 // = L^{-1} (same layout).  Blocked by 16 columns up to kb rounded to 16:
-// per block, one wave factors the 16x16 diagonal block in registers (rows
-// in lanes, pivots and column entries broadcast with readlane) and inverts
-// it (one lane per column); the rows below are solved as a product with
-// that inverse and the trailing lower triangle is updated, both on the
-// matrix cores.  The off-diagonal blocks of W follow by distance from the
-// diagonal: W_ib = -W_ii sum_{q=b}^{i-1} L_iq W_qb.  A non-positive or NaN
-// pivot j records col0 + j in *fail.  Every thread of the workgroup takes
-// part; Tmp holds 3 x 256 scratch elements.
+// per block, one wave factors the 16-column panel in registers (all of its
+// rows, one per lane; pivots and column entries broadcast with readlane) and
+// the trailing lower triangle is updated on the matrix cores.  Then each
+// 16x16 diagonal block is inverted by its own wave (one lane per row), and
+// the off-diagonal blocks of W follow by distance from the diagonal: W_ib =
+// -W_ii sum_{q=b}^{i-1} L_iq W_qb.  A non-positive or NaN pivot j records
+// col0 + j in *fail.  Every thread of the workgroup takes part; Tmp holds
+// 3 x 256 scratch elements.
 template <typename T>
 __device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * kSub], int kb,
                                                     int col0, int32_t* fail) {
@@ -295,15 +295,17 @@ __device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * 
   }
   __syncthreads();
   for (int jb = 0; jb < kr; jb += kSub) {
-    // (1) 16x16 diagonal block: Cholesky and inverse, lanes 0..15 of wave 0
-    // (lane i holds row i of L in a[] and, afterwards, row i of W in x[]).
+    // (1) 16-column panel, rows jb..kr-1, wave 0: lane i holds row jb + i.
     // Updates run on every lane: entries above the diagonal become garbage
     // that is never broadcast or stored, which keeps the pivot chain free of
-    // lane masks.
-    if (wave == 0 && lane < kSub) {
+    // lane masks.  The reciprocal pivots go to the diagonal of W, where the
+    // inversion below picks them up.
+    if (wave == 0) {
+      const int row = jb + lane;
+      const bool valid = row < kr;
       T a[kSub];
 #pragma unroll
-      for (int c = 0; c < kSub; ++c) a[c] = D[(jb + c) * kDiagLd + jb + lane];
+      for (int c = 0; c < kSub; ++c) a[c] = valid ? D[(jb + c) * kDiagLd + row] : T(0);
       T myinv = T(0);
       uint32_t bad = 0;  // pivots that are not positive (or NaN), bit j
 #pragma unroll
@@ -318,38 +320,17 @@ __device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * 
       }
       if (kb - jb < kSub) bad &= (1u << (kb - jb)) - 1u;  // identity padding past kb
       if (lane == 0 && bad != 0) atomicMin(fail, col0 + jb + __builtin_ctz(bad));
+      if (valid) {
 #pragma unroll
-      for (int c = 0; c < kSub; ++c)
-        if (c <= lane) D[(jb + c) * kDiagLd + jb + lane] = a[c];
-      // W = L^{-1} by rows: row q is final once rows < q are subtracted;
-      // it is scaled by 1 / L_qq and subtracted from the rows below.
-      T x[kSub];
-#pragma unroll
-      for (int k = 0; k < kSub; ++k) x[k] = lane == k ? T(1) : T(0);
-#pragma unroll
-      for (int q = 0; q < kSub; ++q) {
-#pragma unroll
-        for (int k = 0; k <= q; ++k) x[k] = lane == q ? x[k] * myinv : x[k];
-#pragma unroll
-        for (int k = 0; k <= q; ++k) x[k] -= (lane > q ? a[q] : T(0)) * readlane(x[k], q);
+        for (int c = 0; c < kSub; ++c)
+          if (c <= lane) D[(jb + c) * kDiagLd + row] = a[c];
       }
-#pragma unroll
-      for (int k = 0; k < kSub; ++k) W[(jb + k) * kDiagLd + jb + lane] = x[k];
+      if (lane < kSub) W[row * kDiagLd + row] = myinv;
     }
     __syncthreads();
     const int below = (kr - jb - kSub) / kSub;  // 16-row blocks below
-    // (2) rows below: X = B W_bb^T, one wave per 16-row block
-    if (wave < below) {
-      const int r0 = jb + kSub + wave * kSub;
-      V4 acc = V4{0, 0, 0, 0};
-      acc = mm16<T>([&](int m, int k) { return D[(jb + k) * kDiagLd + r0 + m]; },
-                    [&](int k, int n) { return W[(jb + k) * kDiagLd + jb + n]; }, acc);
-      // acc holds X(r0 + mfma_row, jb + lane % 16); W_bb^T(k, n) = W_bb(n, k)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) D[(jb + (lane & 15)) * kDiagLd + r0 + mfma_row<T>(lane, v)] = acc[v];
-    }
-    __syncthreads();
-    // (3) trailing lower triangle: D_ij -= X_i X_j^T over 16x16 blocks i >= j
+    if (below == 0) break;
+    // (2) trailing lower triangle: D_ij -= X_i X_j^T over 16x16 blocks i >= j
     for (int q = wave; q < below * (below + 1) / 2; q += kThreads / 64) {
       int bi = 0;
       while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
@@ -366,6 +347,30 @@ __device__ __forceinline__ void diag_factor_inverse(T* D, T* W, T (*Tmp)[kSub * 
     }
     __syncthreads();
   }
+  // (3) inverses of the 16x16 diagonal blocks, wave b for block b (lane i
+  // holds row i of L_bb in a[] and, afterwards, row i of W_bb in x[]): row q
+  // of W_bb is final once rows < q are subtracted; it is scaled by 1 / L_qq
+  // and subtracted from the rows below.
+  if (wave < nb && lane < kSub) {
+    const int o = wave * kSub;
+    T a[kSub];
+#pragma unroll
+    for (int c = 0; c < kSub; ++c) a[c] = D[(o + c) * kDiagLd + o + lane];
+    const T myinv = W[(o + lane) * kDiagLd + o + lane];
+    T x[kSub];
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) x[k] = lane == k ? T(1) : T(0);
+#pragma unroll
+    for (int q = 0; q < kSub; ++q) {
+#pragma unroll
+      for (int k = 0; k <= q; ++k) x[k] = lane == q ? x[k] * myinv : x[k];
+#pragma unroll
+      for (int k = 0; k <= q; ++k) x[k] -= (lane > q ? a[q] : T(0)) * readlane(x[k], q);
+    }
+#pragma unroll
+    for (int k = 0; k < kSub; ++k) W[(o + k) * kDiagLd + o + lane] = x[k];
+  }
+  __syncthreads();
   // off-diagonal blocks of W, by distance d from the diagonal
   for (int d = 1; d < nb; ++d) {
     const int b = wave, i = wave + d;
