@@ -216,7 +216,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble(DevSym S, DevNum<T> N,
     if (c < w) {
       for (int i = tid; i < ldl; i += kThreads) Lp[i + (int64_t)c * ldl] = T(0);
     } else {
-      for (int i = tid; i < ldu; i += kThreads) Us[i + (int64_t)(c - w) * ldu] = T(0);
+      // U is used by 64 x 64 tiles on and below the diagonal only (the
+      // front kernel's update tiles, the parent's lower-triangle pull).
+      for (int i = ((c - w) & ~(kPanel - 1)) + tid; i < ldu; i += kThreads)
+        Us[i + (int64_t)(c - w) * ldu] = T(0);
     }
   }
   __syncthreads();
@@ -938,6 +941,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       }
       __syncthreads();
     }
+    if (tj >= 2) {
+      // the pre-accumulated part of the diagonal block and row tile 1
+      if (tid == 0) {
+        wait_at_least(pd_done + wb + tj, 1, hang);
+        acquire_agent();
+      }
+      __syncthreads();
+    }
     fold_dacc();
     factor_diag(false);
     if (!fuse1) {
@@ -1204,13 +1215,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       tt = 0;
       kstart = it > 0 ? (it - 1) * TT : 0;
       kend = it * TT;
-      if (it >= 2) {
-        if (tid == 0) {
-          wait_at_least(pd_done + wb + it, 1, hang);
-          acquire_agent();
-        }
-        __syncthreads();
-      }
     } else if (tk.kind == 1) {
       mode = 1;
       kstart = tk.p0 * TT;
