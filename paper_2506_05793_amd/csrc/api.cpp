@@ -91,7 +91,7 @@ struct tacho_sym {
   int device = -1;
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
       d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
-      d_wbase, d_woff, d_tbase, d_sparent, d_pull_ptr, d_pull_src, d_part_base, d_pt1base;
+      d_wbase, d_woff, d_tbase, d_sparent, d_pull_ptr, d_pull_src, d_part_base, d_pt1base, d_asm_rng;
   DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fsolve, d_bsolve,
       d_wave_list, d_lwave, d_llarge;
   DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
@@ -289,6 +289,7 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_pull_src, P.pull_src));
   HIP_TRY(upload(h->d_part_base, P.part_base));
   HIP_TRY(upload(h->d_pt1base, P.pt1base));
+  HIP_TRY(upload(h->d_asm_rng, P.asm_rng));
   HIP_TRY(upload(h->d_small, P.small_list));
   HIP_TRY(upload(h->d_asm, P.asm_items));
   HIP_TRY(upload(h->d_diag, P.diag_items));
@@ -334,6 +335,7 @@ int ensure_uploaded(tacho_sym* h) {
   v.pull_src = h->d_pull_src.as<int32_t>();
   v.part_base = h->d_part_base.as<int32_t>();
   v.pt1base = h->d_pt1base.as<int32_t>();
+  v.asm_rng = h->d_asm_rng.as<int32_t>();
   h->device = dev;
   h->uploaded = true;
   return TACHO_OK;

@@ -38,6 +38,7 @@ struct DevSym {
   const int32_t* pull_src;   // update-vector entry of each source
   const int32_t* part_base;  // per diagonal block: first backward partial-product slot
   const int32_t* pt1base;    // per pivot block of a chain front: 64 x 64 product slot (-1: none)
+  const int32_t* asm_rng;    // per assembly item and child: child column range
 };
 
 template <typename T>

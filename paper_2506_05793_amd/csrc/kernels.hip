@@ -228,27 +228,40 @@ __global__ __launch_bounds__(kThreads) void k_assemble(DevSym S, DevNum<T> N,
     for (int64_t q = q0 + tid; q < q1; q += kThreads) Lp[S.a_pos[q]] = N.avals[q];
   }
   __syncthreads();
-  for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+  // children's update matrices, ascending child order: the columns of child
+  // c that land in [c0, c1) come from the plan; one wave per child column,
+  // rows in lanes, four rows per lane fetched before their sums are stored
+  // (the row map is injective, so they are distinct targets)
+  const int32_t* rg = S.asm_rng + 2 * (int64_t)it.rbase;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q, rg += 2) {
+    const int lo = rg[0], hi = rg[1];
+    if (lo >= hi) continue;  // same for the whole workgroup
     const int c = S.child_list[q];
     const int wc = S.sptr[c + 1] - S.sptr[c], rc = S.front_m[c] - wc;
     const T* Uc = N.U + S.U_off[c];
     const int ldc = S.ldU[c];
     const int32_t* rm = S.rmap + S.rows_ptr[c] + wc;
-    int lo = 0, hi = rc;  // first jj with rm[jj] >= c0
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (rm[mid] < it.c0) lo = mid + 1; else hi = mid;
-    }
-    for (int jj = lo; jj < rc; ++jj) {
+    for (int jj = lo + wave; jj < hi; jj += kThreads / 64) {
       const int tc = rm[jj];
-      if (tc >= it.c1) break;
-      for (int ii = jj + tid; ii < rc; ii += kThreads) {
-        const int tr = rm[ii];
-        const T v = Uc[ii + (int64_t)jj * ldc];
-        if (tc < w)
-          Lp[tr + (int64_t)tc * ldl] += v;
-        else
-          Us[(tr - w) + (int64_t)(tc - w) * ldu] += v;
+      // target column: front rows [0, m) of L, or rows [w, m) of U
+      T* col = tc < w ? Lp + (int64_t)tc * ldl : Us + (int64_t)(tc - w) * ldu;
+      const int roff = tc < w ? 0 : w;
+      const T* src = Uc + (int64_t)jj * ldc;
+      for (int i0 = jj + lane; i0 < rc; i0 += 4 * 64) {
+        int tr[4];
+        T v[4], old[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ii = i0 + 64 * u;
+          tr[u] = ii < rc ? rm[ii] - roff : -1;
+          v[u] = ii < rc ? src[ii] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) old[u] = tr[u] >= 0 ? col[tr[u]] : T(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (tr[u] >= 0) col[tr[u]] = old[u] + v[u];
       }
     }
     __syncthreads();
@@ -942,9 +955,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       __syncthreads();
     }
     if (tj >= 2) {
-      // the pre-accumulated part of the diagonal block and row tile 1
+      // the pre-accumulated part of the diagonal block and row tile 1: all
+      // ranges of block j applied (tk.p1 blocks per range before [j-2, j-1))
       if (tid == 0) {
-        wait_at_least(pd_done + wb + tj, 1, hang);
+        wait_at_least(pd_done + wb + tj, (tj - 2 + tk.p1 - 1) / tk.p1 + 1, hang);
         acquire_agent();
       }
       __syncthreads();
@@ -1096,10 +1110,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       __syncthreads();
     }
   }
-  if (utile && tk.rk > 0) {
-    // ranges of one update-matrix tile are applied in order
+  if ((utile || pre) && tk.rk > 0) {
+    // ranges of one update-matrix tile, or of one pre-accumulated diagonal
+    // block, are applied in order
     if (tid == 0) {
-      wait_at_least(ucount + tk.ui, tk.rk, hang);
+      wait_at_least(utile ? ucount + tk.ui : pd_done + wb + tj, tk.rk, hang);
       acquire_agent();
     }
     __syncthreads();
@@ -1138,7 +1153,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
           if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = acc[a][b][v];
         }
     publish_barrier();
-    if (tid == 0) set_flag(pd_done + wb + tj, 1);
+    if (tid == 0) set_flag(pd_done + wb + tj, tk.rk + 1);
     return;
   }
   if (diag) {
@@ -1222,7 +1237,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     } else if (tk.kind == 3) {
       mode = 3;
       tt = 0;
-      kend = (tk.j - 1) * TT;
+      kstart = tk.p0 * TT;
+      kend = tk.p1 * TT;
     }
     step(mode, tj, tt, kstart, kend);
   }

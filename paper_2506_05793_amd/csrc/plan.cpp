@@ -177,6 +177,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
   P.steps.clear();
   P.small_list.clear();
   P.asm_items.clear();
+  P.asm_rng.clear();
   P.diag_items.clear();
   P.panel_items.clear();
   // diagonal-block inverse storage of every large front
@@ -261,7 +262,20 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
     int32_t wmax = 0;
     for (int32_t s : big) {
       int32_t m = S.front_m[s];
-      for (int32_t c = 0; c < m; c += asm_cols) P.asm_items.push_back({s, c, std::min(m, c + asm_cols), 0});
+      for (int32_t c = 0; c < m; c += asm_cols) {
+        const int32_t c1 = std::min(m, c + asm_cols);
+        const int32_t rbase = (int32_t)(P.asm_rng.size() / 2);
+        for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+          // child rows (front positions in s, ascending) past its pivots
+          const int32_t ch = S.child_list[q];
+          const int32_t wc = S.sptr[ch + 1] - S.sptr[ch];
+          const int32_t* rm = S.rmap.data() + S.rows_ptr[ch] + wc;
+          const int32_t rc = S.front_m[ch] - wc;
+          P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, c) - rm));
+          P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, c1) - rm));
+        }
+        P.asm_items.push_back({s, c, c1, rbase});
+      }
       wmax = std::max(wmax, S.sptr[s + 1] - S.sptr[s]);
     }
     {
@@ -309,7 +323,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
             const int32_t s = big[bi];
             if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) {
               chain[bi] = 1;
-              P.ftasks.push_back({s, 0, 0, 2, 0, 0, 0, 0});
+              P.ftasks.push_back({s, 0, 0, 2, 0, kPdRange, 0, 0});
               const int32_t nbs = (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel;
               for (int32_t b = 1; b < nbs; ++b) P.pt1base[P.wbase[s] + b] = (int32_t)P.pt1_slots++;
             }
@@ -324,7 +338,29 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
           const int nt = front_block_tiles(m, w, j);
           for (int t = chain[bi] ? 2 : 0; t < nt; ++t)
             if (t != 1) P.ftasks.push_back({s, j, t, 0, chain[bi], 0, 0, 0});
-          if (chain[bi] && (j + 2) * kPanel < w) P.ftasks.push_back({s, j + 2, 0, 3, 0, 0, 0, 0});
+          if (chain[bi]) {
+            // pre-accumulation ranges that end with pivot block j: for block
+            // b >= 2, [b - 2, b - 1) and before it [e - kPdRange, e) for e =
+            // b - 2, b - 2 - kPdRange, ... (the first one cut at 0), applied
+            // in order of their start (rk)
+            const int32_t nbs = (w + kPanel - 1) / kPanel;
+            for (int32_t b = j + 2; b < nbs; ++b) {
+              const int32_t e = b - 2, before = (e + kPdRange - 1) / kPdRange;
+              int32_t p0, p1, rk;
+              if (b == j + 2) {
+                p0 = j;
+                p1 = j + 1;
+                rk = before;
+              } else {
+                const int32_t d = e - (j + 1);  // distance of this end below b - 2
+                if (d % kPdRange != 0) continue;
+                p1 = j + 1;
+                p0 = std::max(0, p1 - kPdRange);
+                rk = before - 1 - d / kPdRange;
+              }
+              P.ftasks.push_back({s, b, 0, 3, p0, p1, 0, rk});
+            }
+          }
         }
         for (size_t bi = 0; bi < big.size(); ++bi) {
           const int32_t s = big[bi];

@@ -9,9 +9,11 @@
 
 namespace tacho {
 
-// Work item of the large-front assembly: columns [c0, c1) of front s.
+// Work item of the large-front assembly: columns [c0, c1) of front s; for
+// the q-th child of s, the child's update-matrix columns that land in
+// [c0, c1) are [asm_rng[2 (rbase + q)], asm_rng[2 (rbase + q) + 1]).
 struct AsmItem {
-  int32_t s, c0, c1, pad;
+  int32_t s, c0, c1, rbase;
 };
 
 // Work item of the panel kernels: diagonal block [k, k+kb) of front s (one
@@ -73,9 +75,12 @@ struct GemmTile {
 // of the update matrix U_s (rows 64t.., columns 64j..), t >= j, for the
 // pivot blocks [p0, p1): the rk-th such range of the tile, applied after
 // range rk-1 (counter ui of the tile orders them).  kind 2: the chain of
-// diagonal blocks of front s (all its t = 0 work, in order).  kind 3:
-// pre-accumulation of diagonal block j and row tile 1 of front s over the
-// pivot blocks before j - 1, for the chain.  A kind 0 task of a chain front
+// diagonal blocks of front s (all its t = 0 work, in order; p1 holds the
+// pre-accumulation range length).  kind 3: pre-accumulation of diagonal
+// block j and row tile 1 of front s over the pivot blocks [p0, p1), the
+// rk-th such range of block j (ranges cover the blocks before j - 1, the
+// last one is [j - 2, j - 1) and they are applied in order), for the chain.
+// A kind 0 task of a chain front
 // has p0 = 1: its rows that are row tile 1 of block j + 1 also get their
 // product with row tile 1 of block j, for the chain's step j + 1.
 struct FrontTask {
@@ -85,6 +90,7 @@ struct FrontTask {
 
 constexpr int kURange = 8;     // default pivot blocks per update-matrix task
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
+constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
 constexpr int kMaxChains = 32; // chains per level (each holds one workgroup slot for the level)
 
 // Batching parameters of the plan (task grouping only; the arithmetic of a
@@ -180,6 +186,8 @@ struct Plan {
   std::vector<int32_t> llarge;
   std::vector<int64_t> llarge_ptr;
   std::vector<int32_t> pull_ptr, pull_src;
+  // assembly: per item and child, the child's column range (see AsmItem)
+  std::vector<int32_t> asm_rng;
   // backward partial products: per diagonal block (woff indexing) the first
   // of its ceil(r / kBwdChunk) slots of kPanel x 16 elements
   std::vector<int32_t> part_base;
