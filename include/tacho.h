@@ -91,6 +91,9 @@ typedef struct {
   int32_t solve_level_fronts; /* solve levels below the last level with more than
                                 this many fronts run level by level (default 256) */
   int32_t asm_cols;          /* front columns per assembly workgroup (default 8) */
+  int32_t solo_m;            /* fronts with one pivot block (w <= 64) and at most this
+                                many rows run as one task each, without completion
+                                flags (default 192; negative: never) */
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */

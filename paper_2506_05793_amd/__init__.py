@@ -51,6 +51,7 @@ class tacho_options(ctypes.Structure):
         ("chain_min", ctypes.c_int32),
         ("solve_level_fronts", ctypes.c_int32),
         ("asm_cols", ctypes.c_int32),
+        ("solo_m", ctypes.c_int32),
     ]
 
 

@@ -649,6 +649,14 @@ __device__ inline void publish_barrier() {
   __syncthreads();
 }
 
+// Stores of this workgroup visible to its own later loads: every wave waits
+// for its stores, then (after the barrier) drops its stale L1 lines.
+__device__ inline void local_publish() {
+  wait_vm();
+  __syncthreads();
+  asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+
 __device__ inline void set_flag(int32_t* flag, int32_t value) {
   release_agent();
   __hip_atomic_store(flag, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -730,6 +738,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   auto step = [&](int mode, int tj, int tt, int kstart, int K) {
   const bool utile = mode == 1;
   const bool pre = mode == 3;
+  // whole-front task: every operand comes from this workgroup's own earlier
+  // steps, so there are no flags to wait for or raise
+  const bool solo = tk.kind == 4;
   const bool diag = (mode == 0 && tt == 0) || pre;
   const int c0 = tj * TT;
   const int kb = utile ? TT : min(TT, w - c0);
@@ -1044,7 +1055,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     };
     auto load_stage = [&](int st) {
       const int k0 = kstart + st * KT;
-      if (k0 % TT == 0 && k0 / TT >= ready) {
+      if (!solo && k0 % TT == 0 && k0 / TT >= ready) {
         if (tid == 0) {
           int q = k0 / TT;
           block_done(q, true);
@@ -1157,18 +1168,29 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     return;
   }
   if (diag) {
-    factor_diag(true);
+    factor_diag(!solo);
     if (!fuse1) return;
     // row tile 1 (still in registers) against the inverse in LDS
     stage_rows();
     __syncthreads();
     trsm_rows(false);
-    publish_barrier();
-    if (tid == 0) set_flag(done + 1, 1);
+    if (solo) {
+      local_publish();
+    } else {
+      publish_barrier();
+      if (tid == 0) set_flag(done + 1, 1);
+    }
     return;
   }
   // rows below the diagonal block: X = C W_j^T
   stage_rows();
+  if (solo) {
+    // W_j is still in LDS from the diagonal step
+    __syncthreads();
+    trsm_rows(false);
+    local_publish();
+    return;
+  }
   if (tid == 0) {
     wait_at_least(done, 1, hang);
     acquire_agent();
@@ -1222,10 +1244,29 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   // only block j - 1 (the rest was pre-accumulated in place), factors, and
   // solves its row tile 1, which is block j + 1's last operand.  Other
   // kinds run one step.  (One call site keeps a single inlined copy.)
-  const int nsteps = tk.kind == 2 ? (w + TT - 1) / TT : 1;
+  // A whole-front task (kind 4, one pivot block) runs the diagonal step,
+  // the steps of row tiles 2.. and then the update-matrix tiles.
+  const int nrt = tk.kind == 4 ? max(1, front_block_tiles(m, w, 0) - 1) : 0;
+  const int nut = tk.kind == 4 ? (m - w + TT - 1) / TT : 0;
+  const int nsteps = tk.kind == 2 ? (w + TT - 1) / TT : tk.kind == 4 ? nrt + nut * (nut + 1) / 2 : 1;
   for (int it = 0; it < nsteps; ++it) {
     int mode = 0, tj = tk.j, tt = tk.t, kstart = 0, kend = tk.j * TT;
-    if (tk.kind == 2) {
+    if (tk.kind == 4) {
+      if (it < nrt) {
+        tj = 0;
+        tt = it == 0 ? 0 : it + 1;
+        kend = 0;
+      } else {
+        // update-matrix tile (a, b), a >= b, in row-major lower order
+        const int u = it - nrt;
+        int a = 0;
+        while ((a + 1) * (a + 2) / 2 <= u) ++a;
+        mode = 1;
+        tt = a;
+        tj = u - a * (a + 1) / 2;
+        kend = w;
+      }
+    } else if (tk.kind == 2) {
       tj = it;
       tt = 0;
       kstart = it > 0 ? (it - 1) * TT : 0;

@@ -117,6 +117,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
   const int32_t chain_min = tune.chain_min == 0 ? kChainMin : tune.chain_min;
   const int32_t level_fronts = tune.level_fronts > 0 ? tune.level_fronts : kLevelFronts;
   const int32_t asm_cols = tune.asm_cols > 0 ? tune.asm_cols : kAsmCols;
+  const int32_t solo_m = tune.solo_m == 0 ? kSoloM : tune.solo_m;  // negative: never
   const int32_t ns = S.ns;
   P.front_mode = front_mode;
   static_assert(kPanel == 64, "front task tiling assumes 64-column pivot blocks");
@@ -284,14 +285,20 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       P.steps.push_back(st);
     }
     if (front_mode == 0) {
+      // Fronts with one pivot block and at most solo_m rows run as one task
+      // each (diagonal block, row tiles, update-matrix tiles in order, no
+      // flags); the others as tile tasks below.
+      std::vector<int32_t> flow, solo;
+      for (int32_t s : big)
+        ((S.sptr[s + 1] - S.sptr[s] <= kPanel && S.front_m[s] <= solo_m) ? solo : flow).push_back(s);
       // Dataflow: pivot blocks in column order across the level's fronts;
       // the update-matrix tiles of a front in ranges of u_range pivot
       // blocks, each range right after the last column it needs.  Every task
       // depends only on tasks with smaller tickets.
       Step st{kStepFront, h, (int64_t)P.ftasks.size(), 0};
-      std::vector<int32_t> ubase(big.size());
-      for (size_t bi = 0; bi < big.size(); ++bi) {
-        const int32_t s = big[bi];
+      std::vector<int32_t> ubase(flow.size());
+      for (size_t bi = 0; bi < flow.size(); ++bi) {
+        const int32_t s = flow[bi];
         const int32_t r = S.front_m[s] - (S.sptr[s + 1] - S.sptr[s]);
         const int32_t nt = (r + kPanel - 1) / kPanel;
         ubase[bi] = (int32_t)P.nucount;
@@ -302,8 +309,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       // workgroup slots when their inputs are complete and interleave with
       // the pivot-block tasks that carry the critical path; what is left
       // when the level's columns end is emitted then.
-      std::vector<std::vector<FrontTask>> pending(big.size());
-      std::vector<size_t> pending_pos(big.size(), 0);
+      std::vector<std::vector<FrontTask>> pending(flow.size());
+      std::vector<size_t> pending_pos(flow.size(), 0);
       auto emit_u = [&](size_t bi, size_t upto) {
         upto = std::min(upto, pending[bi].size());
         for (; pending_pos[bi] < upto; ++pending_pos[bi]) P.ftasks.push_back(pending[bi][pending_pos[bi]]);
@@ -313,14 +320,14 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       // as one chain task (first in ticket order) when the level has few
       // of them; their block j >= 2 is pre-accumulated by a task issued
       // right after column j - 2.
-      std::vector<char> chain(big.size(), 0);
+      std::vector<char> chain(flow.size(), 0);
       {
         int nchain = 0;
-        for (int32_t s : big)
+        for (int32_t s : flow)
           if (chain_min > 0 && (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) ++nchain;
         if (chain_min > 0 && nchain <= kMaxChains)
-          for (size_t bi = 0; bi < big.size(); ++bi) {
-            const int32_t s = big[bi];
+          for (size_t bi = 0; bi < flow.size(); ++bi) {
+            const int32_t s = flow[bi];
             if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) {
               chain[bi] = 1;
               P.ftasks.push_back({s, 0, 0, 2, 0, kPdRange, 0, 0});
@@ -330,8 +337,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
           }
       }
       for (int32_t j = 0; j < ncols; ++j) {
-        for (size_t bi = 0; bi < big.size(); ++bi) {
-          const int32_t s = big[bi];
+        for (size_t bi = 0; bi < flow.size(); ++bi) {
+          const int32_t s = flow[bi];
           const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
           if (j * kPanel >= w) continue;
           // the diagonal task (t = 0) also produces row tile 1
@@ -362,8 +369,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
             }
           }
         }
-        for (size_t bi = 0; bi < big.size(); ++bi) {
-          const int32_t s = big[bi];
+        for (size_t bi = 0; bi < flow.size(); ++bi) {
+          const int32_t s = flow[bi];
           const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
           const int32_t pb = (w + kPanel - 1) / kPanel;
           if (r <= 0) continue;
@@ -389,7 +396,8 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
           }
         }
       }
-      for (size_t bi = 0; bi < big.size(); ++bi) emit_u(bi, pending[bi].size());
+      for (size_t bi = 0; bi < flow.size(); ++bi) emit_u(bi, pending[bi].size());
+      for (int32_t s : solo) P.ftasks.push_back({s, 0, 0, 4, 0, 1, 0, 0});
       st.end = (int64_t)P.ftasks.size();
       for (int32_t s : big) {
         const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s], r = m - w;

@@ -80,6 +80,8 @@ struct GemmTile {
 // block j and row tile 1 of front s over the pivot blocks [p0, p1), the
 // rk-th such range of block j (ranges cover the blocks before j - 1, the
 // last one is [j - 2, j - 1) and they are applied in order), for the chain.
+// kind 4: the whole front s (one pivot block): the diagonal block, its row
+// tiles and the update-matrix tiles, in order, by one workgroup.
 // A kind 0 task of a chain front
 // has p0 = 1: its rows that are row tile 1 of block j + 1 also get their
 // product with row tile 1 of block j, for the chain's step j + 1.
@@ -90,7 +92,8 @@ struct FrontTask {
 
 constexpr int kURange = 8;     // default pivot blocks per update-matrix task
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
-constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
+constexpr int kPdRange = 4;
+constexpr int kSoloM = 192;    // default: fronts with one pivot block and m <= this run as one task    // pivot blocks per pre-accumulation range of a chain's diagonal block
 constexpr int kMaxChains = 32; // chains per level (each holds one workgroup slot for the level)
 
 // Batching parameters of the plan (task grouping only; the arithmetic of a
@@ -100,6 +103,7 @@ struct PlanTuning {
   int32_t chain_min = 3;      // chain fronts: at least this many pivot blocks (<= 0: none)
   int32_t level_fronts = 256; // solve level-by-level phase threshold
   int32_t asm_cols = 8;       // front columns per assembly workgroup
+  int32_t solo_m = 0;         // one-task fronts: one pivot block, at most this many rows (0: default, < 0: none)
 };
 
 enum StepKind : int32_t {

@@ -90,8 +90,8 @@ def test_fp64_factor_and_solve_parity(name, make, front):
 
 
 PLAN_SETTINGS = [
-    {"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4},
-    {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 16},
+    {"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4, "solo_m": 2000},
+    {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 16, "solo_m": -1},
 ]
 
 

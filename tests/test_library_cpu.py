@@ -166,8 +166,10 @@ def test_plan_parameters_accepted_and_reserved_rejected():
     to the same symbolic result; the reserved fields must stay 0."""
     A = gen.fv3d(12, 11, 10, seed=7)
     base = T.tacho_get_symbolic(T.tacho_analyze(A.n, A.rowptr, A.colind))
-    for params in ({"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4},
-                   {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 32}):
+    for params in ({"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4,
+                    "solo_m": 2000},
+                   {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 32,
+                    "solo_m": -1}):
         s = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**params))
         a = T.tacho_get_symbolic(s)
         assert np.array_equal(a.perm, base.perm) and np.array_equal(a.super_ptr, base.super_ptr)
