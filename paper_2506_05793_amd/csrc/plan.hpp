@@ -92,8 +92,8 @@ struct FrontTask {
 
 constexpr int kURange = 8;     // default pivot blocks per update-matrix task
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
-constexpr int kPdRange = 4;
-constexpr int kSoloM = 192;    // default: fronts with one pivot block and m <= this run as one task    // pivot blocks per pre-accumulation range of a chain's diagonal block
+constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
+constexpr int kSoloM = 192;    // default: fronts with one pivot block and m <= this run as one task
 constexpr int kMaxChains = 32; // chains per level (each holds one workgroup slot for the level)
 
 // Batching parameters of the plan (task grouping only; the arithmetic of a
