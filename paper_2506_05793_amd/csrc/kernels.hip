@@ -736,6 +736,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   // mode 3: pre-accumulation of the diagonal block tj and its row tile 1
   // (no factorization).  Pivot blocks [kstart / 64, K / 64) are applied.
   auto step = [&](int mode, int tj, int tt, int kstart, int K) {
+  // Lane-dependent index arithmetic is redone in every step rather than
+  // kept in registers across the task loop (it would push the kernel past
+  // its register budget into scratch spills).
+  int lane = tid & 63;
+  asm volatile("" : "+v"(lane));
   const bool utile = mode == 1;
   const bool pre = mode == 3;
   // whole-front task: every operand comes from this workgroup's own earlier
