@@ -898,14 +898,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
         }
     __syncthreads();
     diag_factor_inverse<T>(Cs, Ws, Tmp, kb, f + c0, N.fail);
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, r = t - c * kb;
-      if (r >= c) Lc0[(c0 + r) + c * ld] = Cs[c * kDiagLd + r];
-    }
     T* Wout = winv + S.woff[wb + tj];  // kb x kb, column-major
-    for (int t = tid; t < kb * kb; t += kThreads) {
-      const int c = t / kb, r = t - c * kb;
-      Wout[t] = Ws[c * kDiagLd + r];
+    if (kb == TT) {
+      // full block: a column per wave and round, four rounds in flight
+#pragma unroll 4
+      for (int q = 0; q < TT / (kThreads / 64); ++q) {
+        const int c = wave + q * (kThreads / 64);
+        const T lv = Cs[c * kDiagLd + lane], wv = Ws[c * kDiagLd + lane];
+        if (lane >= c) Lc0[(c0 + lane) + c * ld] = lv;
+        Wout[c * TT + lane] = wv;
+      }
+    } else {
+      for (int t = tid; t < kb * kb; t += kThreads) {
+        const int c = t / kb, r = t - c * kb;
+        if (r >= c) Lc0[(c0 + r) + c * ld] = Cs[c * kDiagLd + r];
+      }
+      for (int t = tid; t < kb * kb; t += kThreads) {
+        const int c = t / kb, r = t - c * kb;
+        Wout[t] = Ws[c * kDiagLd + r];
+      }
     }
     if (publish) {
       publish_barrier();
