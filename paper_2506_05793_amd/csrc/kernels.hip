@@ -641,6 +641,15 @@ __device__ inline void acquire_agent() {
   asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
 }
 
+// Stores of the front kernel's results (factor tiles, inverses, update
+// tiles, pre-accumulations): agent-scope relaxed atomic stores, which write
+// through to memory, so that a publishing workgroup's L2 writeback has little
+// dirty data to flush.
+template <typename T>
+__device__ __forceinline__ void st_out(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Workgroup barrier after which thread 0 publishes the workgroup's global
 // stores: every wave first waits until its stores have reached its L2, so
 // the one writeback that thread 0 issues after the barrier covers them all.
@@ -855,7 +864,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = oi(a), c = oj(b, v);
-          if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = x[a][b][v];
+          if (r < arows && c < kb) st_out(&Lc0[(a0 + r) + c * ld], x[a][b][v]);
         }
     if (keep) {
       __syncthreads();
@@ -905,17 +914,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
       for (int q = 0; q < TT / (kThreads / 64); ++q) {
         const int c = wave + q * (kThreads / 64);
         const T lv = Cs[c * kDiagLd + lane], wv = Ws[c * kDiagLd + lane];
-        if (lane >= c) Lc0[(c0 + lane) + c * ld] = lv;
-        Wout[c * TT + lane] = wv;
+        if (lane >= c) st_out(&Lc0[(c0 + lane) + c * ld], lv);
+        st_out(&Wout[c * TT + lane], wv);
       }
     } else {
       for (int t = tid; t < kb * kb; t += kThreads) {
         const int c = t / kb, r = t - c * kb;
-        if (r >= c) Lc0[(c0 + r) + c * ld] = Cs[c * kDiagLd + r];
+        if (r >= c) st_out(&Lc0[(c0 + r) + c * ld], Cs[c * kDiagLd + r]);
       }
       for (int t = tid; t < kb * kb; t += kThreads) {
         const int c = t / kb, r = t - c * kb;
-        Wout[t] = Ws[c * kDiagLd + r];
+        st_out(&Wout[t], Ws[c * kDiagLd + r]);
       }
     }
     if (publish) {
@@ -1157,7 +1166,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
         for (int v = 0; v < 4; ++v) {
           const int i = oi(a), jj = oj(b, v);
           const int gi = tt * TT + i, gj = tj * TT + jj;
-          if (i < arows && jj < bcols && gi >= gj) Cu[gi + (int64_t)gj * ldc] = acc[a][b][v];
+          if (i < arows && jj < bcols && gi >= gj) st_out(&Cu[gi + (int64_t)gj * ldc], acc[a][b][v]);
         }
     if (tk.p1 * TT < w) {  // a later range of this tile follows
       publish_barrier();
@@ -1176,8 +1185,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = oi(a), c = oj(b, v);
-          if (r < kb && c < kb && r >= c) Lc0[(c0 + r) + c * ld] = dacc[a][b][v];
-          if (r < arows && c < kb) Lc0[(a0 + r) + c * ld] = acc[a][b][v];
+          if (r < kb && c < kb && r >= c) st_out(&Lc0[(c0 + r) + c * ld], dacc[a][b][v]);
+          if (r < arows && c < kb) st_out(&Lc0[(a0 + r) + c * ld], acc[a][b][v]);
         }
     publish_barrier();
     if (tid == 0) set_flag(pd_done + wb + tj, tk.rk + 1);
@@ -1248,7 +1257,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int r = a0 + oi(a), c = oj(b, v);
-            if (r >= lo && r < hi && c < kb1) P1[(r - t1lo) + c * TT] = acc[a][b][v];
+            if (r >= lo && r < hi && c < kb1) st_out(&P1[(r - t1lo) + c * TT], acc[a][b][v]);
           }
     }
   }
