@@ -360,6 +360,9 @@ def main():
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=200.0,
                     help="serve: mean arrival rate (requests/s; 0: all at once, i.e. capacity)")
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="serve: HBM budget in GB (0: 0.8 x free device memory)")
+    ap.add_argument("--workers", type=int, default=8, help="serve: host analysis workers")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the plan parameters of the 3D workload (FP64 and FP32) on the "
@@ -533,7 +536,8 @@ def other_workload(args, T, torch):
                 reqs.append(Request(i, sp["t"], "repeat", gen.rhs(A.n, sp["nrhs"], seed=sp["seed"]),
                                     target=sp["target"]))
         free, _ = torch.cuda.mem_get_info()
-        srv = Server(int(0.8 * free), slots=4, analysis_workers=8)
+        budget = int(args.budget_gb * 1e9) if args.budget_gb > 0 else int(0.8 * free)
+        srv = Server(budget, slots=4, analysis_workers=args.workers)
         t0 = time.perf_counter()
         res = srv.run(reqs)
         wall = time.perf_counter() - t0
@@ -545,6 +549,7 @@ def other_workload(args, T, torch):
             A = r.matrix if r.kind == "factor" else mats[r.target]
             worst = max(worst, float(residual(A, out.x, r.rhs).max()))
         summ.update({"offered_rate_per_s": args.rate if args.rate > 0 else None,
+                     "hbm_budget_bytes": budget, "analysis_workers": args.workers,
                      "served_requests_per_s": len(res) / wall,
                      "admitted_while_busy": srv.admitted_while_busy, "peak_bytes": srv.peak_used,
                      "sampled_max_rel_residual": worst})
