@@ -90,7 +90,7 @@ struct tacho_sym {
   bool uploaded = false;
   int device = -1;
   DBuf d_sptr, d_front_m, d_rows_ptr, d_rows, d_rmap, d_child_ptr, d_child_list, d_acol_ptr,
-      d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_diag_q,
+      d_a_pos, d_a_src, d_a_prc, d_L_off, d_ldL, d_U_off, d_ldU, d_u_off, d_perm, d_pinv, d_diag_q,
       d_wbase, d_woff, d_tbase, d_sparent, d_pull_ptr, d_pull_src, d_part_base, d_pt1base, d_asm_rng;
   DBuf d_small, d_asm, d_diag, d_panel, d_probs, d_tiles, d_ftasks, d_levels, d_fsolve, d_bsolve,
       d_wave_list, d_lwave, d_llarge;
@@ -281,6 +281,11 @@ int ensure_uploaded(tacho_sym* h) {
   HIP_TRY(upload(h->d_ldU, P.ldU));
   HIP_TRY(upload(h->d_u_off, P.u_off));
   HIP_TRY(upload(h->d_perm, S.perm));
+  {
+    std::vector<int32_t> pinv(S.perm.size());
+    for (size_t i = 0; i < S.perm.size(); ++i) pinv[S.perm[i]] = (int32_t)i;
+    HIP_TRY(upload(h->d_pinv, pinv));
+  }
   HIP_TRY(upload(h->d_diag_q, P.diag_q));
   HIP_TRY(upload(h->d_wbase, P.wbase));
   HIP_TRY(upload(h->d_woff, P.woff));
@@ -327,6 +332,7 @@ int ensure_uploaded(tacho_sym* h) {
   v.ldU = h->d_ldU.as<int32_t>();
   v.u_off = h->d_u_off.as<int64_t>();
   v.perm = h->d_perm.as<int32_t>();
+  v.pinv = h->d_pinv.as<int32_t>();
   v.diag_q = h->d_diag_q.as<int32_t>();
   v.wbase = h->d_wbase.as<int32_t>();
   v.woff = h->d_woff.as<int64_t>();

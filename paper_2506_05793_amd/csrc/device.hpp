@@ -29,6 +29,7 @@ struct DevSym {
   const int32_t* ldU;
   const int64_t* u_off;
   const int32_t* perm;       // new -> old
+  const int32_t* pinv;       // old -> new
   const int32_t* diag_q;     // per permuted column: A entry of the diagonal or -1
   const int32_t* wbase;      // per supernode: first diagonal-inverse block (-1: none)
   const int64_t* woff;       // per diagonal-inverse block: element offset

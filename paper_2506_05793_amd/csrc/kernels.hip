@@ -601,28 +601,32 @@ template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_permute_in(DevSym S, const double* b, int64_t ldb,
                                                          T* y, int64_t nrhs,
                                                          const double* scale) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= S.n) return;
-  const int64_t src = S.perm[i];
+  // thread per original row: coalesced reads of each column of b, one whole
+  // row of y (its own cache line) written per thread
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= S.n) return;
+  const int64_t i = S.pinv[j];
   const double d = scale ? scale[i] : 1.0;
 #pragma unroll
-  for (int c = 0; c < NR; ++c) y[i * kRowLd<T> + c] = c < nrhs ? (T)(b[src + c * ldb] * d) : T(0);
+  for (int c = 0; c < NR; ++c) y[i * kRowLd<T> + c] = c < nrhs ? (T)(b[j + c * ldb] * d) : T(0);
 }
 
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_permute_out(DevSym S, const T* y, double* x,
                                                           int64_t ldx, int64_t nrhs,
                                                           const double* scale, int accumulate) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= S.n) return;
-  const int64_t dst = S.perm[i];
+  // thread per original row: one row of y read, coalesced writes of each
+  // column of x
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= S.n) return;
+  const int64_t i = S.pinv[j];
   const double d = scale ? scale[i] : 1.0;
   for (int64_t c = 0; c < nrhs; ++c) {
     const double v = (double)y[i * kRowLd<T> + c] * d;
     if (accumulate)
-      x[dst + c * ldx] += v;
+      x[j + c * ldx] += v;
     else
-      x[dst + c * ldx] = v;
+      x[j + c * ldx] = v;
   }
 }
 
