@@ -225,10 +225,84 @@ def test_batch_alone_equals_batched():
 
 
 @pytest.mark.slow
-def test_full_size_3d_64():
-    """64^3 lognormal workload: residual and sampled (L L^T)_ij = C_ij."""
+def sampled_llt_error(num, A, perm, count=2000, seed=0):
+    """max over sampled pattern entries (i, j) of C = P A P^T of
+    |(L L^T)_ij - C_ij| / sqrt(C_ii C_jj); Cholesky's backward error is
+    bounded entrywise by (|L||L^T|)_ij <= sqrt(C_ii C_jj)."""
+    import scipy.sparse as sp
+    Lp, Li, Lx = T.tacho_get_factor(num)
+    Lr = sp.csc_matrix((Lx, Li, Lp), shape=(A.n, A.n)).tocsr()
+    C = oracle.oracle.permuted_lower(A, perm).tocoo()
+    pick = np.random.default_rng(seed).choice(C.nnz, size=min(count, C.nnz), replace=False)
+    diag = C.tocsr().diagonal()
+    worst = 0.0
+    for k in pick:
+        i, j = C.row[k], C.col[k]
+        v = Lr.getrow(i).multiply(Lr.getrow(j)).sum()
+        worst = max(worst, abs(v - C.data[k]) / np.sqrt(diag[i] * diag[j]))
+    return worst
+
+
+def bench_plan(A, precision):
+    """Plan options the bench times for this workload (tuning table)."""
+    from paper_2506_05793_amd import autotune
+    return autotune.options_for(A.n, A.nnz, 1, precision)
+
+
+def test_full_size_3d_64_mixed():
+    """64^3 lognormal workload, FP32 factor + FP64 refinement in the bench's
+    plan: residual within the metric's bound for 1 and 16 right-hand sides,
+    forward error against the FP64 path printed."""
     A = gen.fv3d(64, seed=1)
-    s, a = analyze(A)
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind, bench_plan(A, T.TACHO_FP32))
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP32)
+    s64 = T.tacho_analyze(A.n, A.rowptr, A.colind, bench_plan(A, T.TACHO_FP64))
+    num64 = T.tacho_factorize(s64, A.values, T.TACHO_FP64)
+    for nrhs in (1, 16):
+        b = gen.rhs(A.n, nrhs, seed=2)
+        x, info = T.tacho_solve(num, b, with_info=True)
+        x64 = T.tacho_solve(num64, b)
+        rho = oracle.rel_residual(A, x, b)
+        err = np.linalg.norm(x - x64, axis=0) / np.linalg.norm(x64, axis=0)
+        print(f"64^3 mixed nrhs={nrhs}: iters={info['iters']} fell_back={info['fell_back']} "
+              f"rho={rho.max():.2e} |x-x_fp64|/|x_fp64|={err.max():.2e}")
+        assert rho.max() <= MIXED_RESID_TOL
+        assert info["fell_back"] == 0
+
+
+def test_full_size_landice():
+    """Land-ice-shaped workload at full size (880,000 unknowns) in the bench's
+    plans: FP64 residual and sampled (L L^T)_ij = C_ij; FP32 + refinement
+    residual within the metric's bound."""
+    A = gen.landice(seed=3)
+    assert A.n == 880000
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind, bench_plan(A, T.TACHO_FP64))
+    a = T.tacho_get_symbolic(s)
+    num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    b = gen.rhs(A.n, 1, seed=2)
+    x = T.tacho_solve(num, b)
+    rho = oracle.rel_residual(A, x, b)
+    worst = sampled_llt_error(num, A, a.perm, count=500)
+    print(f"land-ice FP64: rho={rho.max():.2e} sampled LL^T error {worst:.2e}")
+    assert rho.max() <= FP64_RESID_TOL
+    assert worst <= 1e-12
+    del num
+    s32 = T.tacho_analyze(A.n, A.rowptr, A.colind, bench_plan(A, T.TACHO_FP32))
+    num32 = T.tacho_factorize(s32, A.values, T.TACHO_FP32)
+    x32, info = T.tacho_solve(num32, b, with_info=True)
+    rho32 = oracle.rel_residual(A, x32, b)
+    print(f"land-ice mixed: iters={info['iters']} fell_back={info['fell_back']} "
+          f"rho={rho32.max():.2e} |x-x_fp64|/|x_fp64|="
+          f"{np.linalg.norm(x32 - x) / np.linalg.norm(x):.2e}")
+    assert rho32.max() <= MIXED_RESID_TOL
+
+
+def test_full_size_3d_64():
+    """64^3 lognormal workload in the bench's plan: residual and sampled
+    (L L^T)_ij = C_ij."""
+    A = gen.fv3d(64, seed=1)
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind, bench_plan(A, T.TACHO_FP64))
+    a = T.tacho_get_symbolic(s)
     num = T.tacho_factorize(s, A.values, T.TACHO_FP64)
     for nrhs in (1, 16):
         b = gen.rhs(A.n, nrhs, seed=2)
@@ -240,19 +314,7 @@ def test_full_size_3d_64():
         # and require the same bits every time
         for _ in range(4):
             assert np.array_equal(T.tacho_solve(num, b), x)
-    Lp, Li, Lx = T.tacho_get_factor(num)
-    L = __import__("scipy.sparse", fromlist=["csc_matrix"]).csc_matrix((Lx, Li, Lp), shape=(A.n, A.n))
-    Lr = L.tocsr()
-    C = oracle.oracle.permuted_lower(A, a.perm).tocoo()
-    rng = np.random.default_rng(0)
-    pick = rng.choice(C.nnz, size=2000, replace=False)
-    diag = C.tocsr().diagonal()
-    worst = 0.0
-    for k in pick:
-        i, j = C.row[k], C.col[k]
-        v = Lr.getrow(i).multiply(Lr.getrow(j)).sum()
-        # Cholesky backward error is bounded entrywise by (|L||L^T|)_ij <= sqrt(C_ii C_jj)
-        worst = max(worst, abs(v - C.data[k]) / np.sqrt(diag[i] * diag[j]))
+    worst = sampled_llt_error(num, A, a.perm)
     print(f"64^3 sampled |(LL^T)_ij - C_ij|/sqrt(C_ii C_jj) max {worst:.2e}")
     assert worst <= 1e-12
 
