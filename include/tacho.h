@@ -94,6 +94,9 @@ typedef struct {
   int32_t solo_m;            /* fronts with one pivot block (w <= 64) and at most this
                                 many rows run as one task each, without completion
                                 flags (default 192; negative: never) */
+  int32_t chain_inplace;     /* chain fronts: the product for the next diagonal block's
+                                row tile is subtracted in place by the tasks that form
+                                it (>= 0, default) or left in a slot for the chain (< 0) */
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */

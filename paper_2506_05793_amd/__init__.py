@@ -52,6 +52,7 @@ class tacho_options(ctypes.Structure):
         ("solve_level_fronts", ctypes.c_int32),
         ("asm_cols", ctypes.c_int32),
         ("solo_m", ctypes.c_int32),
+        ("chain_inplace", ctypes.c_int32),
     ]
 
 

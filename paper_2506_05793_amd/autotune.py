@@ -15,7 +15,9 @@ depends on the matrix and the device):
   this many fronts run level by level, the rest as one dataflow launch;
 * ``asm_cols`` - front columns per assembly workgroup;
 * ``solo_m`` - fronts with one pivot block and at most this many rows run as
-  one task each (negative: never).
+  one task each (negative: never);
+* ``chain_inplace`` - chain fronts: the product for the next diagonal block's
+  row tile is subtracted in place (>= 0) or left in a slot (< 0).
 
 None of them changes which operations a front performs; ``u_range`` and
 ``chain_min`` change the order in which the same contributions are summed,
@@ -39,13 +41,14 @@ from . import (TACHO_FP64, tacho_analyze, tacho_default_options, tacho_factorize
                tacho_query_symbolic, tacho_refactorize, tacho_solve)
 
 DEFAULTS = {"u_range": 8, "chain_min": 3, "solve_level_fronts": 256, "asm_cols": 8,
-            "solo_m": 192}
+            "solo_m": 192, "chain_inplace": 0}
 CANDIDATES = {
     "u_range": (4, 8, 16),
     "chain_min": (2, 3, 4, 6, -1),
     "solve_level_fronts": (64, 256, 1024),
     "asm_cols": (4, 8, 16),
     "solo_m": (-1, 128, 192, 256, 320),
+    "chain_inplace": (0, -1),
 }
 
 

@@ -223,6 +223,7 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   tune.level_fronts = h->opt.solve_level_fronts;
   tune.asm_cols = h->opt.asm_cols;
   tune.solo_m = h->opt.solo_m;
+  tune.chain_inplace = h->opt.chain_inplace;
   rc = build_plan(h->S, h->P, err, h->opt.front_kernel == 1 ? 1 : 0, tune);
   if (rc != kOk) return fail(rc, err);
   const Symbolic& S = h->S;

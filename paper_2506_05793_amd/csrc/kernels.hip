@@ -974,10 +974,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
     // Chain step: one pivot block (j - 1) to apply.  Its rows of block j
     // (row tile 1 of block j - 1) are this workgroup's previous result,
     // still in Cs; the product of its rows of row tile 1 of block j with
-    // them was formed by the tasks of block j - 1 that own those rows (slot
-    // pt1 of block j).  So the diagonal block is updated from LDS, factored,
-    // and only then is the other tasks' product awaited; both row tiles of
-    // block j are published together at the end.
+    // them was formed by the tasks of block j - 1 that own those rows (for a
+    // full block j), into slot pt1 of block j or, with p0 = 1, subtracted
+    // in place.  So the diagonal block is updated from LDS, factored, and
+    // only then are those tasks awaited; both row tiles of block j are
+    // published together at the end.
     if (K > kstart) {
 #pragma unroll 4
       for (int ks = 0; ks < TT / 4; ++ks) {
@@ -1017,7 +1018,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
         acquire_agent();
       }
       __syncthreads();
-      if (kb == TT) {
+      if (kb == TT && tk.p0 == 0) {
         const T* P1 = N.pt1 + (int64_t)S.pt1base[wb + tj] * (TT * TT);
 #pragma unroll
         for (int a = 0; a < BL; ++a)
@@ -1029,7 +1030,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
               const bool ok = r < arows && c < kb;
               acc[a][b][v] = P1[ok ? r + c * TT : 0] * (ok ? T(1) : T(0));
             }
-      } else {
+      } else if (kb < TT) {
         // last (partial) block: part of its row tile 1 lies in row tile 1
         // of block j - 1, which no other task owns; apply block j - 1 here
         gemm_direct(acc, a0, arows, b0, bcols, kstart, K);
@@ -1253,16 +1254,41 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
 #pragma unroll
         for (int b = 0; b < BL; ++b) acc[a][b] = V4{0, 0, 0, 0};
       gemm_direct(acc, a0, arows, c1, kb1, c0, c0 + kb);
-      T* P1 = N.pt1 + (int64_t)S.pt1base[wb + tj + 1] * (TT * TT);
-#pragma unroll
-      for (int a = 0; a < BL; ++a)
-#pragma unroll
-        for (int b = 0; b < BL; ++b)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = a0 + oi(a), c = oj(b, v);
-            if (r >= lo && r < hi && c < kb1) st_out(&P1[(r - t1lo) + c * TT], acc[a][b][v]);
+      if (tk.p0 == 2) {
+        // in place, after the pre-accumulation of block j + 1 (its ranges
+        // have smaller tickets), so that the chain reads one value
+        if (tj + 1 >= 2) {
+          if (tid == 0) {
+            wait_at_least(pd_done + wb + tj + 1, (tj + 1 - 2 + kPdRange - 1) / kPdRange + 1, hang);
+            acquire_agent();
           }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int a = 0; a < BL; ++a)
+#pragma unroll
+          for (int b = 0; b < BL; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int r = a0 + oi(a), c = oj(b, v);
+              if (r >= lo && r < hi && c < kb1) {
+                T* p = Lp + r + (int64_t)(c1 + c) * ld;
+                st_out(p, *p - acc[a][b][v]);
+              }
+            }
+      } else {
+        // into block j + 1's slot
+        T* P1 = N.pt1 + (int64_t)S.pt1base[wb + tj + 1] * (TT * TT);
+#pragma unroll
+        for (int a = 0; a < BL; ++a)
+#pragma unroll
+          for (int b = 0; b < BL; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int r = a0 + oi(a), c = oj(b, v);
+              if (r >= lo && r < hi && c < kb1) st_out(&P1[(r - t1lo) + c * TT], acc[a][b][v]);
+            }
+      }
     }
   }
   publish_barrier();

@@ -118,6 +118,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
   const int32_t level_fronts = tune.level_fronts > 0 ? tune.level_fronts : kLevelFronts;
   const int32_t asm_cols = tune.asm_cols > 0 ? tune.asm_cols : kAsmCols;
   const int32_t solo_m = tune.solo_m == 0 ? kSoloM : tune.solo_m;  // negative: never
+  const bool inplace = tune.chain_inplace >= 0;  // default: in place
   const int32_t ns = S.ns;
   P.front_mode = front_mode;
   static_assert(kPanel == 64, "front task tiling assumes 64-column pivot blocks");
@@ -330,7 +331,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
             const int32_t s = flow[bi];
             if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) {
               chain[bi] = 1;
-              P.ftasks.push_back({s, 0, 0, 2, 0, kPdRange, 0, 0});
+              P.ftasks.push_back({s, 0, 0, 2, inplace ? 1 : 0, kPdRange, 0, 0});
               const int32_t nbs = (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel;
               for (int32_t b = 1; b < nbs; ++b) P.pt1base[P.wbase[s] + b] = (int32_t)P.pt1_slots++;
             }
@@ -344,7 +345,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
           // the diagonal task (t = 0) also produces row tile 1
           const int nt = front_block_tiles(m, w, j);
           for (int t = chain[bi] ? 2 : 0; t < nt; ++t)
-            if (t != 1) P.ftasks.push_back({s, j, t, 0, chain[bi], 0, 0, 0});
+            if (t != 1) P.ftasks.push_back({s, j, t, 0, chain[bi] ? (inplace ? 2 : 1) : 0, 0, 0, 0});
           if (chain[bi]) {
             // pre-accumulation ranges that end with pivot block j: for block
             // b >= 2, [b - 2, b - 1) and before it [e - kPdRange, e) for e =

@@ -83,8 +83,10 @@ struct GemmTile {
 // kind 4: the whole front s (one pivot block): the diagonal block, its row
 // tiles and the update-matrix tiles, in order, by one workgroup.
 // A kind 0 task of a chain front
-// has p0 = 1: its rows that are row tile 1 of block j + 1 also get their
-// product with row tile 1 of block j, for the chain's step j + 1.
+// has p0 = 1 or 2: its rows that are row tile 1 of block j + 1 also get
+// their product with row tile 1 of block j, for the chain's step j + 1,
+// stored in a slot (1) or subtracted in place (2, and the chain task has
+// p0 = 1).
 struct FrontTask {
   int32_t s, j, t, kind;
   int32_t p0, p1, ui, rk;
@@ -104,6 +106,7 @@ struct PlanTuning {
   int32_t level_fronts = 256; // solve level-by-level phase threshold
   int32_t asm_cols = 8;       // front columns per assembly workgroup
   int32_t solo_m = 0;         // one-task fronts: one pivot block, at most this many rows (0: default, < 0: none)
+  int32_t chain_inplace = 0;  // chain fronts: next-block product subtracted in place (>= 0) or via a slot (< 0)
 };
 
 enum StepKind : int32_t {

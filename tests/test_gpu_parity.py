@@ -90,12 +90,14 @@ def test_fp64_factor_and_solve_parity(name, make, front):
 
 
 PLAN_SETTINGS = [
-    {"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4, "solo_m": 2000},
+    {"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4, "solo_m": 2000,
+     "chain_inplace": -1},
     {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 16, "solo_m": -1},
+    {"chain_min": 2, "chain_inplace": 1},
 ]
 
 
-@pytest.mark.parametrize("plan", PLAN_SETTINGS, ids=["fine", "coarse"])
+@pytest.mark.parametrize("plan", PLAN_SETTINGS, ids=["fine", "coarse", "inplace"])
 @pytest.mark.parametrize("name", ["fv3d_36", "landice_9x8x4", "dense_300"])
 def test_plan_parameters_keep_parity(name, plan):
     """The autotuner's plan parameters regroup tasks and launches: every
