@@ -424,7 +424,10 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
     const int64_t cnt = s.end - s.begin;
     const int pe = f->prof.begin(st);
     switch (s.kind) {
-      case kStepSmall: launch_small<T>(S, N, small + s.begin, cnt, st); break;
+      case kStepSmall:
+        launch_leaf<T>(S, N, small + s.begin, s.tile, st);
+        launch_small<T>(S, N, small + s.begin + s.tile, cnt - s.tile, st);
+        break;
       case kStepAssemble: launch_assemble<T>(S, N, asmi + s.begin, cnt, st); break;
       case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, f->winv.as<T>(), st); break;
       case kStepPanel: launch_panel<T>(S, N, pan + s.begin, cnt, f->winv.as<T>(), st); break;

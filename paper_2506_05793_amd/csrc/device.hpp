@@ -61,6 +61,9 @@ void launch_mirror(const int64_t* idx, const double* src, double* dst, int64_t c
                    hipStream_t st);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
 template <typename T>
+void launch_leaf(const DevSym& S, const DevNum<T>& N, const int32_t* list, int64_t count,
+                 hipStream_t st);
+template <typename T>
 void launch_small(const DevSym& S, const DevNum<T>& N, const int32_t* list, int64_t count,
                   hipStream_t st);
 template <typename T>

@@ -197,6 +197,51 @@ __global__ __launch_bounds__(kThreads) void k_small(DevSym S, DevNum<T> N, const
   }
 }
 
+// Leaf fronts with one pivot column, no children and m <= kLeafMax, one
+// thread each: the same operations as k_small (A entries into a zero
+// column, pivot square root, column scaled by it, update matrix 0 - l l^T),
+// in registers.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_leaf(DevSym S, DevNum<T> N, const int32_t* list,
+                                                   int count) {
+  const int idx = blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= count) return;
+  const int s = list[idx];
+  const int f = S.sptr[s], m = S.front_m[s], r = m - 1;
+  const int ld = S.ldL[s];
+  T x[kLeafMax];
+#pragma unroll
+  for (int i = 0; i < kLeafMax; ++i) x[i] = T(0);
+  for (int64_t q = S.acol_ptr[f]; q < S.acol_ptr[f + 1]; ++q) {
+    const int pos = S.a_pos[q];
+    const T v = N.avals[q];
+#pragma unroll
+    for (int i = 0; i < kLeafMax; ++i) x[i] = pos == i ? v : x[i];
+  }
+  const T d = x[0];
+  const T l0 = sqrt(d);
+  if (!(d > T(0))) atomicMin(N.fail, f);
+  x[0] = l0;
+#pragma unroll
+  for (int i = 1; i < kLeafMax; ++i) x[i] = x[i] / l0;
+  T* Lp = N.L + S.L_off[s];
+#pragma unroll
+  for (int i = 0; i < kLeafMax; ++i)
+    if (i < ld) Lp[i] = i < m ? x[i] : T(0);
+  if (r > 0) {
+    T* Us = N.U + S.U_off[s];
+    const int ldu = S.ldU[s];
+#pragma unroll
+    for (int jj = 0; jj < kLeafMax - 1; ++jj) {
+      if (jj < r) {
+#pragma unroll
+        for (int ii = 0; ii < kLeafMax; ++ii)
+          if (ii < ldu) Us[ii + (int64_t)jj * ldu] = (ii < r && ii >= jj) ? T(0) - x[1 + ii] * x[1 + jj] : T(0);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Large fronts, assembly: the workgroup owns front columns [c0, c1).  It
 // zeroes them, writes the A entries, then adds every child's update matrix
@@ -2046,6 +2091,14 @@ void launch_small(const DevSym& S, const DevNum<T>& N, const int32_t* list, int6
 }
 
 template <typename T>
+void launch_leaf(const DevSym& S, const DevNum<T>& N, const int32_t* list, int64_t count,
+                 hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_leaf<T>, dim3((unsigned)((count + kThreads - 1) / kThreads)), dim3(kThreads), 0, st,
+                       S, N, list, (int)count);
+}
+
+template <typename T>
 void launch_assemble(const DevSym& S, const DevNum<T>& N, const AsmItem* items, int64_t count,
                      hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_assemble<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, items);
@@ -2203,6 +2256,8 @@ void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t 
                                  hipStream_t);                                                   \
   template void launch_small<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,         \
                                 hipStream_t);                                                    \
+  template void launch_leaf<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,          \
+                               hipStream_t);                                                     \
   template void launch_assemble<T>(const DevSym&, const DevNum<T>&, const AsmItem*, int64_t,      \
                                    hipStream_t);                                                 \
   template void launch_diag<T>(const DevSym&, const DevNum<T>&, const PanelItem*, int64_t, T*,    \

@@ -243,15 +243,26 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
   for (int32_t h = 0; h < S.nlevels; ++h) {
     big.clear();
     int64_t b0 = (int64_t)P.small_list.size();
+    // leaves with one pivot column first (one thread each), then the rest
+    auto leaf = [&](int32_t s) {
+      return S.sptr[s + 1] - S.sptr[s] == 1 && S.child_ptr[s] == S.child_ptr[s + 1] &&
+             S.front_m[s] <= kLeafMax;
+    };
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q)
+      if (leaf(S.level_list[q])) P.small_list.push_back(S.level_list[q]);
+    const int32_t nleaf = (int32_t)((int64_t)P.small_list.size() - b0);
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       int32_t s = S.level_list[q];
-      if (S.front_m[s] <= kSmallMax)
+      if (leaf(s))
+        continue;
+      else if (S.front_m[s] <= kSmallMax)
         P.small_list.push_back(s);
       else
         big.push_back(s);
     }
     if ((int64_t)P.small_list.size() > b0) {
       Step st{kStepSmall, h, b0, (int64_t)P.small_list.size()};
+      st.tile = nleaf;
       for (int64_t q = b0; q < st.end; ++q) {
         const int32_t s = P.small_list[q];
         st.flops += front_flops(S, s);

@@ -127,10 +127,11 @@ struct Step {
   int64_t begin, end;
   double flops = 0;  // algorithmic flops of the launch
   double elems = 0;  // algorithmic element traffic (reads + writes) of the launch
-  int32_t tile = 0;  // update steps: tile size
+  int32_t tile = 0;  // update steps: tile size; small-front steps: leading one-thread leaves
 };
 
 constexpr int kSmallMax = 64;     // fronts with m <= kSmallMax go to the LDS kernel
+constexpr int kLeafMax = 16;      // ... leaves with one pivot column and m <= kLeafMax to one thread each
 constexpr int kPanel = 64;        // panel width of the blocked large-front path
 constexpr int kOuter = 256;       // outer panel width (trailing updates with K = kOuter)
 constexpr int kPanelRows = 64;    // rows per triangular-solve workgroup
