@@ -90,7 +90,8 @@ typedef struct {
                                 negative: never) */
   int32_t solve_level_fronts; /* solve levels below the last level with more than
                                 this many fronts run level by level (default 256) */
-  int32_t asm_cols;          /* front columns per assembly workgroup (default 8) */
+  int32_t asm_cols;          /* front columns per assembly workgroup, at least (default 8;
+                                short fronts get up to 2048 / m columns, at most 64) */
   int32_t solo_m;            /* fronts with one pivot block (w <= 64) and at most this
                                 many rows run as one task each, without completion
                                 flags (default 192; negative: never) */

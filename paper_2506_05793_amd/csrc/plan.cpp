@@ -275,8 +275,11 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
     int32_t wmax = 0;
     for (int32_t s : big) {
       int32_t m = S.front_m[s];
-      for (int32_t c = 0; c < m; c += asm_cols) {
-        const int32_t c1 = std::min(m, c + asm_cols);
+      // at least asm_cols columns per workgroup, more for short fronts (about
+      // kAsmElems front entries, at most 64 columns)
+      const int32_t cols = std::max(asm_cols, std::min<int32_t>(64, kAsmElems / std::max(m, 1)));
+      for (int32_t c = 0; c < m; c += cols) {
+        const int32_t c1 = std::min(m, c + cols);
         const int32_t rbase = (int32_t)(P.asm_rng.size() / 2);
         for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
           // child rows (front positions in s, ascending) past its pivots

@@ -95,6 +95,7 @@ struct FrontTask {
 constexpr int kURange = 8;     // default pivot blocks per update-matrix task
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
 constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
+constexpr int kAsmElems = 2048;  // front entries per assembly workgroup of a short front
 constexpr int kSoloM = 192;    // default: fronts with one pivot block and m <= this run as one task
 constexpr int kMaxChains = 32; // chains per level (each holds one workgroup slot for the level)
 
