@@ -167,9 +167,9 @@ def test_plan_parameters_accepted_and_reserved_rejected():
     A = gen.fv3d(12, 11, 10, seed=7)
     base = T.tacho_get_symbolic(T.tacho_analyze(A.n, A.rowptr, A.colind))
     for params in ({"u_range": 4, "chain_min": 2, "solve_level_fronts": 16, "asm_cols": 4,
-                    "solo_m": 2000},
+                    "solo_m": 2000, "chain_inplace": -1},
                    {"u_range": 16, "chain_min": -1, "solve_level_fronts": 4096, "asm_cols": 32,
-                    "solo_m": -1}):
+                    "solo_m": -1, "chain_inplace": 1}):
         s = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**params))
         a = T.tacho_get_symbolic(s)
         assert np.array_equal(a.perm, base.perm) and np.array_equal(a.super_ptr, base.super_ptr)
