@@ -340,10 +340,19 @@ def cpu_baseline(side=46):
     b = gen.rhs(A.n, 1, seed=2)
     oracle.solve(F, b)
     t2 = time.perf_counter()
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": flops / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
             "sample": f"3D 7-point lognormal {side}^3 (n={A.n}), same ordering method, FP64 "
                       f"factor {t1 - t0:.2f} s ({flops:.3e} flops) + 1-RHS solve {t2 - t1:.2f} s, "
-                      f"1 thread of {os.cpu_count()} ({platform.processor() or platform.machine()})"}
+                      f"1 thread of {os.cpu_count()} ({model})"}
 
 
 def main():
