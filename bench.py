@@ -49,7 +49,7 @@ PEAK_HBM_GBS = 8000.0
 # figures no longer describe the kernel and the roofline reports traffic null.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "factor_kernels_fv3d64_hbm_traffic.md")
 TRAFFIC_SOURCES = ("paper_2506_05793_amd/csrc/kernels.hip", "paper_2506_05793_amd/csrc/plan.cpp",
-                   "paper_2506_05793_amd/csrc/plan.hpp", "paper_2506_05793_amd/tuning.json")
+                   "paper_2506_05793_amd/csrc/plan.hpp")
 COPY_PROBE_ELEMS = 1 << 27  # FP64 elements: 1 GiB read + 1 GiB written
 
 
@@ -216,10 +216,16 @@ def roofline(prof):
 
 
 def sources_hash():
+    """Hash of the kernel and plan sources and of the tuned FP64 plan of the 3D
+    workload (what the traffic summary's launches depend on)."""
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    from paper_2506_05793_amd import autotune
+    key = autotune.workload_key(262144, 1810432, 1, autotune.TACHO_FP64)  # 64^3: n, nnz(A)
+    h.update(json.dumps(autotune.TuningTable(autotune.DEFAULT_TABLE).get(key),
+                        sort_keys=True).encode())
     return h.hexdigest()[:16]
 
 
@@ -569,6 +575,7 @@ def other_workload(args, T, torch):
                   "offered_rate_per_s": args.rate if args.rate > 0 else "all at t=0"},
                  {"serve": summ})
         return
+    plans = None
     if args.workload == "batch":
         mats = gen.batch_fv3d(256, seed=4)
         log(f"[bench] batch of {len(mats)} systems, n total {sum(m.n for m in mats)}")
@@ -594,9 +601,36 @@ def other_workload(args, T, torch):
         s = args.li_side
         log(f"[bench] building land-ice {s}x{s}x11x2")
         A = gen.landice(s, s, 11, seed=3)
+        from paper_2506_05793_amd import autotune
+        if args.autotune:
+            # analysis takes seconds here: a reduced candidate set
+            cands = {"asm_cols": (4, 8), "chain_min": (2, 3, 4), "solo_m": (-1, 128, 192),
+                     "chain_inplace": (0, -1)}
+            tab = autotune.TuningTable(autotune.DEFAULT_TABLE)
+            out = {}
+            for prec, name in ((T.TACHO_FP64, "fp64"), (T.TACHO_FP32, "fp32")):
+                best, m, hist = autotune.tune(A.n, A.rowptr, A.colind, A.values, prec, reps=5,
+                                              log=log, candidates=cands)
+                key = autotune.workload_key(A.n, A.nnz, 1, prec)
+                tab.put(key, best, {"workload": f"land-ice {s}x{s}x11 nodes x 2 DOF",
+                                    "device": "MI355X", "factor_ms": m["factor_ms"],
+                                    "solve_ms": m["solve_ms"],
+                                    "default_factor_ms": hist[0][1]["factor_ms"],
+                                    "default_solve_ms": hist[0][1]["solve_ms"],
+                                    "candidates": len(hist)})
+                out[name] = {"key": key, "best": best, "measured": m, "default": hist[0][1]}
+            tab.save()
+            print(json.dumps({"autotune": out}), flush=True)
+            return
+        plans = {p: ({} if args.no_tuning else autotune.tuned_params(A.n, A.nnz, 1, p))
+                 for p in (T.TACHO_FP64, T.TACHO_FP32)}
         t0 = time.perf_counter()
-        sym = T.tacho_analyze(A.n, A.rowptr, A.colind)
+        sym = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**plans[T.TACHO_FP64]))
         analyze_s = time.perf_counter() - t0
+        sym_by_prec = {T.TACHO_FP64: sym,
+                       T.TACHO_FP32: sym if plans[T.TACHO_FP32] == plans[T.TACHO_FP64] else
+                       T.tacho_analyze(A.n, A.rowptr, A.colind,
+                                       T.tacho_default_options(**plans[T.TACHO_FP32]))}
         vals_np = A.values
         n = A.n
         b = gen.rhs(n, 1, seed=2)
@@ -609,7 +643,8 @@ def other_workload(args, T, torch):
     X = torch.empty_like(B)
     results = {}
     for name, prec, tol in precisions:
-        num = T.tacho_factorize(sym, vals, prec)
+        num = T.tacho_factorize(sym_by_prec.get(prec, sym) if args.workload == "landice" else sym,
+                                vals, prec)
         fms, sms, rows = [], [], []
         for it in range(args.warmup + args.steps):
             torch.cuda.synchronize()
@@ -650,7 +685,9 @@ def other_workload(args, T, torch):
                            "landice": f"land-ice {args.li_side}x{args.li_side}x11 nodes x 2 DOF",
                            "batch": "256 3D lognormal subdomain systems, sides in [8,32]"}[args.workload],
               "n": n, "nnz_l": q["nnz_l"], "flops": q["flops"], "levels": q["nlevels"],
-              "analyze_s_host": analyze_s}, results)
+              "analyze_s_host": analyze_s,
+              **({"plan_fp64": plans[T.TACHO_FP64] or "defaults",
+                  "plan_fp32": plans[T.TACHO_FP32] or "defaults"} if plans else {})}, results)
 
 
 if __name__ == "__main__":

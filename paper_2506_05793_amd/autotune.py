@@ -106,8 +106,8 @@ def measure(n, rowptr, colind, values, params, precision=TACHO_FP64, reps=7, ord
 
 
 def tune(n, rowptr, colind, values, precision=TACHO_FP64, reps=7, passes=1,
-         objective="request", log=print):
-    """Coordinate descent over CANDIDATES from DEFAULTS.
+         objective="request", log=print, candidates=None):
+    """Coordinate descent over ``candidates`` (default CANDIDATES) from DEFAULTS.
 
     objective "request": factor + 1-RHS solve time; "factor": factor time.
     Returns (best parameters, best measurement, history)."""
@@ -125,7 +125,7 @@ def tune(n, rowptr, colind, values, precision=TACHO_FP64, reps=7, passes=1,
     history = [(dict(best), best_m)]
     log(f"[autotune] defaults {best}: {best_m}")
     for _ in range(passes):
-        for name, values_ in CANDIDATES.items():
+        for name, values_ in (candidates or CANDIDATES).items():
             for v in values_:
                 if v == best[name]:
                     continue
