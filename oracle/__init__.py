@@ -17,6 +17,7 @@ from .oracle import (  # noqa: F401
     factor,
     solve,
     factor_error,
+    permuted_lower,
     rel_residual,
     logdet,
     flops_from_counts,

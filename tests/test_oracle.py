@@ -322,3 +322,103 @@ def test_relaxed_supernodes_on_grids(oracle_lib, m, pseed):
     rptr, _ = oracle_lib.relaxed_supernodes(bparent, bcounts)
     np.testing.assert_array_equal(rptr, brute_relaxed(G, bstarts, bparent))
     assert len(rptr) <= len(bstarts)
+
+
+# ---------------------------------------------------------------------------
+# Pins of the oracle's report functions.  Every GPU solve and factor check is
+# judged through them, so each is tied to a value fixed by hand arithmetic on
+# integer data (exact in floating point), chosen so that a wrong axis, a
+# wrong triangle, a transposed operand, a dropped factor of two or a zero
+# result changes the number.
+
+
+def test_rel_residual_closed_form(oracle_lib):
+    """tridiag(-1,2,-1) times the all-ones vector is e_1 + e_n exactly, so
+    ||b||_2 = sqrt(2); perturbing x_k by d gives r = -d A e_k, whose norm is
+    |d| sqrt(6) inside and |d| sqrt(5) at either end."""
+    n = 9
+    A = gen.laplace1d(n)
+    x = np.ones((n, 4))
+    b = np.zeros((n, 4))
+    b[0, :] = b[-1, :] = 1.0
+    np.testing.assert_array_equal(oracle_lib.rel_residual(A, x, b), np.zeros(4))
+    xp = x.copy()
+    xp[4, 0] += 0.5       # interior
+    xp[0, 1] -= 0.25      # first row: (2, -1)
+    xp[8, 2] += 2.0       # last row: (-1, 2)
+    # column 3 untouched
+    rho = oracle_lib.rel_residual(A, xp, b)
+    assert rho.shape == (4,)
+    want = np.array([0.5 * np.sqrt(6), 0.25 * np.sqrt(5), 2.0 * np.sqrt(5), 0.0]) / np.sqrt(2)
+    np.testing.assert_allclose(rho, want, rtol=1e-15, atol=0)
+    # one column given as a vector
+    assert oracle_lib.rel_residual(A, xp[:, 0], b[:, 0]).shape == (1,)
+
+
+def test_rel_residual_uses_both_triangles(oracle_lib):
+    """A nonsymmetric CSR whose upper triangle differs from the lower one: the
+    residual is the plain b - A x of the stored matrix (both triangles)."""
+    M = np.array([[3.0, 1.0, 0.0], [0.0, 5.0, 2.0], [4.0, 0.0, 7.0]])
+    A = gen.dense_to_csr(M)
+    x = np.array([[1.0], [2.0], [-1.0]])
+    b = M @ x  # [5, 8, -3] exactly
+    assert oracle_lib.rel_residual(A, x, b)[0] == 0.0
+    b2 = b + np.array([[0.0], [3.0], [4.0]])
+    assert oracle_lib.rel_residual(A, x, b2)[0] == 5.0 / np.linalg.norm(b2)
+
+
+def _integer_factor_problem(perm):
+    """An integer lower-triangular L (positive diagonal, with fill), C = L L^T
+    exactly, and A = P^T C P so that C = P A P^T."""
+    L = np.array([[2, 0, 0, 0, 0],
+                  [1, 1, 0, 0, 0],
+                  [0, 3, 2, 0, 0],
+                  [1, 0, 1, 1, 0],
+                  [0, 2, 0, 1, 3]], dtype=np.float64)
+    C = L @ L.T
+    A = np.empty_like(C)
+    A[np.ix_(perm, perm)] = C
+    return L, C, gen.dense_to_csr(A)
+
+
+@pytest.mark.parametrize("perm", [np.arange(5), np.array([3, 0, 4, 1, 2])])
+def test_factor_error_closed_form(oracle_lib, perm):
+    """||C - L'L'^T||_F / ||C||_F for L' = L + d e_i e_j^T: with v = L[:, j],
+    C - L'L'^T = -d (e_i v^T + v e_i^T) - d^2 e_i e_i^T, whose squared
+    Frobenius norm is (2 d v_i + d^2)^2 + 2 d^2 sum_{b != i} v_b^2."""
+    import scipy.sparse as sp
+    perm = perm.astype(np.int32)
+    L, C, A = _integer_factor_problem(perm)
+    assert oracle_lib.factor_error(A, perm, sp.csc_matrix(L)) == 0.0
+    cn = np.sqrt(np.sum(C * C))
+    for (i, j, d) in ((2, 1, 0.5), (4, 4, -1.0), (3, 0, 2.0)):
+        Lp = L.copy()
+        Lp[i, j] += d
+        v = L[:, j].copy()
+        rest = np.sum(v * v) - v[i] ** 2
+        want = np.sqrt((2 * d * v[i] + d * d) ** 2 + 2 * d * d * rest) / cn
+        got = oracle_lib.factor_error(A, perm, sp.csc_matrix(Lp))
+        assert abs(got - want) <= 1e-15 * want, (i, j, got, want)
+    # a transposed factor is not a factor of C
+    assert oracle_lib.factor_error(A, perm, sp.csc_matrix(L.T)) > 0.1
+
+
+def test_permuted_lower_definition(oracle_lib):
+    """Lower triangle of C[i][j] = S[p[i]][p[j]], where S is the symmetric
+    matrix defined by the stored lower triangle (the upper triangle's values
+    are not read)."""
+    rng = np.random.default_rng(17)
+    n = 11
+    M = rng.standard_normal((n, n))
+    M[np.abs(M) < 0.6] = 0.0
+    M += np.diag(np.full(n, 10.0))
+    # same pattern in both triangles, different values above the diagonal
+    pat = (M != 0) | (M.T != 0)
+    low = np.tril(np.where(pat, M, 0.0))
+    upper = np.triu(np.where(pat, 1000.0 + rng.standard_normal((n, n)), 0.0), 1)
+    A = gen.dense_to_csr(low + upper, keep_zeros_mask=pat)
+    S = low + np.tril(low, -1).T
+    perm = rng.permutation(n).astype(np.int32)
+    got = oracle_lib.permuted_lower(A, perm).toarray()
+    want = np.tril(S[np.ix_(perm, perm)])
+    np.testing.assert_array_equal(got, want)
