@@ -7,8 +7,9 @@
  * numerical setup, solve), with the Tacho section's method: a multifrontal
  * factorization P A P^T = L L^T scheduled by levels of the supernodal
  * elimination tree, followed by supernodal forward and backward
- * substitution scheduled by the same levels (solve variant 1 of that
- * section).  Symbolic analysis runs on the host (it uses only the sparsity
+ * substitution scheduled by the same levels, with the diagonal blocks applied
+ * through their explicit inverses (the inverted-diagonal-block solve variant
+ * of that section).  Symbolic analysis runs on the host (it uses only the sparsity
  * pattern and is reused across value changes); the numeric phase and the
  * solves run in HIP kernels on the GPU.
  *
@@ -46,8 +47,16 @@ extern "C" {
 /* Precision of the numeric factorization (the paper's templated scalar
  * types, Trilinos section, and iterative refinement with computed factors,
  * Basker section). */
-#define TACHO_FP64 0 /* FP64 fronts, FP64 solves */
-#define TACHO_FP32 1 /* FP32 fronts; tacho_solve refines in FP64 */
+#define TACHO_FP64 0    /* FP64 fronts, FP64 solves */
+#define TACHO_FP32_IR 1 /* FP32 fronts; tacho_solve refines in FP64 */
+#define TACHO_FP32 TACHO_FP32_IR
+
+/* Test hooks (tacho_options.debug_flags). */
+#define TACHO_DEBUG_SOLVE_GIVE_UP 1 /* every solve raises its own hang flag before its
+                                       launches, so each dependency wait gives up at once
+                                       (the kernels still run to the end, the result is
+                                       invalid); the error path is then reported like a
+                                       real timed-out wait */
 
 typedef struct tacho_sym *tacho_sym_t;
 typedef struct tacho_num *tacho_num_t;
@@ -58,7 +67,7 @@ typedef struct {
   int32_t small_front;       /* reserved, must be 0: fronts with m <= 64 are always
                                 assembled and factored in LDS by one workgroup (the
                                 class is fixed by the kernels' LDS layout) */
-  int32_t scale;             /* FP32 path: symmetric Jacobi scaling diag(C)^{-1/2} (default 1) */
+  int32_t scale_fp32;        /* FP32 path: symmetric Jacobi scaling diag(C)^{-1/2} (default 1) */
   int32_t refine_max;        /* FP32 path: at most this many corrections (default 10) */
   double refine_tol;         /* FP32 path: stop when ||b - A x||_2 / ||b||_2 <= tol
                                 for every column (default 1e-10) */
@@ -98,6 +107,7 @@ typedef struct {
   int32_t chain_inplace;     /* chain fronts: the product for the next diagonal block's
                                 row tile is subtracted in place by the tasks that form
                                 it (>= 0, default) or left in a slot for the chain (< 0) */
+  int32_t debug_flags;       /* TACHO_DEBUG_* test hooks (default 0) */
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -133,6 +143,9 @@ typedef struct {
   double relres_max;  /* max over columns of ||b - A x||_2 / ||b||_2 (FP32 path) */
   double *relres;     /* optional, caller-owned array of nrhs entries receiving the
                          per-column relative residual (FP32 path), or NULL */
+  int32_t *fell_back_units; /* optional, caller-owned array of nsystems * nrhs entries
+                         (system index fastest) receiving 1 where that system's
+                         column took the FP64 factor's solution, else 0 (FP32 path) */
 } tacho_solve_info;
 
 /*
@@ -181,7 +194,7 @@ int tacho_query_symbolic(tacho_sym_t sym, tacho_sym_info *info);
  *   perm[n]          new -> old: row/column i of P A P^T is row/column perm[i] of A
  *   parent[n]        elimination tree of P A P^T, -1 for roots
  *   colcount[n]      eta_j, nonzeros of column j of L including the diagonal
- *   super_ptr[ns+1]  first column of each fundamental supernode
+ *   super_ptr[ns+1]  first column of each (relaxed) supernode the factor is stored in
  *   super_parent[ns] supernodal parent, -1 for roots
  *   level[ns]        level (height) of each supernode, leaves are 0
  */
@@ -236,12 +249,20 @@ int tacho_numeric_bytes(tacho_sym_t sym, int precision, int64_t *bytes);
 int tacho_refactorize(tacho_num_t num, const double *values, int values_on_device,
                       void *hip_stream, int sync, int64_t *fail_index);
 
-/* Wait for the last factorization of `num` and report its failure flag. */
+/*
+ * Wait for the last factorization of `num` and report its failure flag, then
+ * wait for the last solve queued on the handle (on the stream it was queued
+ * on) and report TACHO_ERR_HIP if one of its dependency waits timed out (its
+ * result is then invalid).  A reported timeout is cleared, so the handle's
+ * next solve runs normally.
+ */
 int tacho_check_factor(tacho_num_t num, int64_t *fail_index);
 
 /*
- * Solve A X = B (Trilinos section, step 3; Tacho section, SpTRSV variant 1:
- * level-set scheduled supernodal forward and backward substitution; several
+ * Solve A X = B (Trilinos section, step 3; Tacho section, supernodal
+ * triangular solves: level-set scheduled forward and backward substitution
+ * over the dense supernodal blocks, each 64-column diagonal block applied
+ * through its explicit inverse, which the factorization keeps; several
  * right-hand sides at once use block operations).
  *   b, x        n x nrhs column-major blocks with leading dimension ld >= n;
  *               x may equal b (in place)
@@ -249,8 +270,11 @@ int tacho_check_factor(tacho_num_t num, int64_t *fail_index);
  *   info        optional refinement report (see tacho_solve_info)
  * For an FP32 factor the solve refines in FP64: x = solve32(b), then
  * r = b - A x (FP64 sparse product), x += solve32(r) until the relative
- * residual of every column is <= refine_tol; when refinement stalls the
- * handle is refactored in FP64 and the solve is repeated (info->fell_back).
+ * residual of every column is <= refine_tol.  Convergence is tracked per
+ * system and column; a column that stalls (or belongs to a system whose FP32
+ * factorization broke down) is refactored in FP64 on the same symbolic handle
+ * and takes the FP64 solution, while the other columns keep their refined
+ * results (info->fell_back, info->fell_back_units).
  * Blocks until the result is available when on_device = 0 or for the FP32
  * path; the FP64 device path only queues work, also behind a factorization
  * queued with sync = 0 (whose failure flag tacho_check_factor then reports).
@@ -263,7 +287,9 @@ int tacho_solve(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64
  * arrays as stored: Lp int64[n+1], Li int32[nnz_factor], Lx
  * float64[nnz_factor]; every column sorted ascending with the diagonal
  * first; rows that are structurally zero in L but stored in a relaxed
- * supernode hold exact zeros.  Synchronizes the handle.
+ * supernode hold exact zeros.  Synchronizes the handle.  After an FP32 pivot
+ * breakdown the FP32 factor is not valid and the FP64 factor of the same
+ * values (the one the solves fall back to) is returned.
  */
 int tacho_get_factor(tacho_num_t num, int64_t *Lp, int32_t *Li, double *Lx);
 

@@ -25,7 +25,9 @@ TACHO_ERR_NOT_SPD = -3
 TACHO_ERR_NOMEM = -4
 TACHO_ERR_HIP = -5
 TACHO_FP64 = 0
-TACHO_FP32 = 1
+TACHO_FP32_IR = 1
+TACHO_FP32 = TACHO_FP32_IR
+TACHO_DEBUG_SOLVE_GIVE_UP = 1
 TACHO_PROFILE_KINDS = 11
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
@@ -38,7 +40,7 @@ class tacho_options(ctypes.Structure):
     _fields_ = [
         ("nd_leaf_size", ctypes.c_int32),
         ("small_front", ctypes.c_int32),
-        ("scale", ctypes.c_int32),
+        ("scale_fp32", ctypes.c_int32),
         ("refine_max", ctypes.c_int32),
         ("refine_tol", ctypes.c_double),
         ("stall_ratio", ctypes.c_double),
@@ -53,6 +55,7 @@ class tacho_options(ctypes.Structure):
         ("asm_cols", ctypes.c_int32),
         ("solo_m", ctypes.c_int32),
         ("chain_inplace", ctypes.c_int32),
+        ("debug_flags", ctypes.c_int32),
     ]
 
 
@@ -69,6 +72,7 @@ class tacho_solve_info(ctypes.Structure):
         ("fell_back", ctypes.c_int32),
         ("relres_max", ctypes.c_double),
         ("relres", _f64p),
+        ("fell_back_units", _i32p),
     ]
 
 
@@ -151,10 +155,14 @@ def tacho_default_options(**overrides) -> tacho_options:
 
 
 class SymbolicHandle:
-    """Owner of a ``tacho_sym_t``."""
+    """Owner of a ``tacho_sym_t``; remembers the order and the number of
+    values the caller's CSR holds (what factorizations and solves expect)."""
 
-    def __init__(self, ptr: int):
+    def __init__(self, ptr: int, n: int = -1, nnz: int = -1, nsys: int = 1):
         self.ptr = ptr
+        self.n = n
+        self.nnz = nnz
+        self.nsys = nsys
         self._lib = _load()
 
     def __del__(self):
@@ -187,7 +195,7 @@ def tacho_analyze(n, rowptr, colind, options: tacho_options | None = None) -> Sy
                            ctypes.byref(options) if options is not None else None,
                            ctypes.byref(out))
     _check(rc)
-    return SymbolicHandle(out.value)
+    return SymbolicHandle(out.value, int(n), int(rowptr[-1]) if len(rowptr) else 0)
 
 
 def tacho_analyze_batch(systems, options: tacho_options | None = None) -> SymbolicHandle:
@@ -204,7 +212,7 @@ def tacho_analyze_batch(systems, options: tacho_options | None = None) -> Symbol
                                  ctypes.byref(options) if options is not None else None,
                                  ctypes.byref(out))
     _check(rc)
-    return SymbolicHandle(out.value)
+    return SymbolicHandle(out.value, int(ns.sum()), int(sum(int(r[-1]) for r in rps if len(r))), k)
 
 
 def tacho_query_symbolic(sym: SymbolicHandle) -> dict:
@@ -246,24 +254,47 @@ def _stream_ptr(stream):
     return torch.cuda.current_stream().cuda_stream
 
 
-def _ptr_of(arr):
-    """(address, on_device) of a numpy array or a torch tensor."""
-    if isinstance(arr, np.ndarray):
-        return arr.ctypes.data, 0
+def _is_torch(arr) -> bool:
+    mod = type(arr).__module__
+    return mod.startswith("torch")
+
+
+def _check_device(t):
+    """A device tensor must live on the current device (the library's stream)."""
     import torch
-    if isinstance(arr, torch.Tensor):
-        if arr.device.type == "cuda":
-            return arr.data_ptr(), 1
-        return arr.data_ptr(), 0
-    raise TypeError("expected a numpy array or a torch tensor")
+    if t.device.type != "cuda":
+        raise TypeError("expected a numpy array or a device (ROCm) tensor")
+    if t.device.index is not None and t.device.index != torch.cuda.current_device():
+        raise ValueError(f"tensor on device {t.device.index}, current device is "
+                         f"{torch.cuda.current_device()}")
+
+
+def _values_arg(sym: SymbolicHandle, values):
+    """(address, on_device, keep-alive) of the caller's values: float64, one per
+    stored CSR entry, contiguous."""
+    if isinstance(values, np.ndarray):
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        if v.ndim != 1 or (sym.nnz >= 0 and v.size != sym.nnz):
+            raise ValueError(f"values: expected {sym.nnz} entries, got shape {values.shape}")
+        return v.ctypes.data, 0, v
+    if _is_torch(values):
+        import torch
+        if values.dtype != torch.float64:
+            raise TypeError(f"values: expected float64, got {values.dtype}")
+        if values.dim() != 1 or not values.is_contiguous() or (
+                sym.nnz >= 0 and values.numel() != sym.nnz):
+            raise ValueError(f"values: expected a contiguous vector of {sym.nnz} entries")
+        if values.device.type == "cpu":
+            return values.data_ptr(), 0, values
+        _check_device(values)
+        return values.data_ptr(), 1, values
+    raise TypeError("values: expected a numpy array or a torch tensor")
 
 
 def tacho_factorize(sym: SymbolicHandle, values, precision: int = TACHO_FP64,
                     stream=None) -> NumericHandle:
     lib = _load()
-    if isinstance(values, np.ndarray):
-        values = np.ascontiguousarray(values, dtype=np.float64)
-    addr, on_dev = _ptr_of(values)
+    addr, on_dev, values = _values_arg(sym, values)
     out = _vp()
     fi = ctypes.c_int64(-1)
     rc = lib.tacho_factorize(sym.ptr, addr, on_dev, int(precision), _stream_ptr(stream),
@@ -286,9 +317,7 @@ def tacho_numeric_bytes(sym: SymbolicHandle, precision: int = TACHO_FP64) -> int
 
 def tacho_refactorize(num: NumericHandle, values, stream=None, sync: bool = True) -> None:
     lib = _load()
-    if isinstance(values, np.ndarray):
-        values = np.ascontiguousarray(values, dtype=np.float64)
-    addr, on_dev = _ptr_of(values)
+    addr, on_dev, values = _values_arg(num.sym, values)
     fi = ctypes.c_int64(-1)
     rc = lib.tacho_refactorize(num.ptr, addr, on_dev, _stream_ptr(stream), int(bool(sync)),
                                ctypes.byref(fi))
@@ -301,39 +330,80 @@ def tacho_check_factor(num: NumericHandle) -> None:
     _check(rc, fi.value)
 
 
+def _solve_args(num: NumericHandle, b, x):
+    """Checked (b, x, nrhs, ld, on_device) of a solve: float64 column-major
+    blocks of n rows, x of the same kind and layout as b (same leading
+    dimension), device tensors on the current device."""
+    n = num.sym.n
+    if isinstance(b, np.ndarray):
+        if b.ndim not in (1, 2) or (n >= 0 and b.shape[0] != n):
+            raise ValueError(f"b: expected {n} rows, got shape {b.shape}")
+        b = np.asfortranarray(b, dtype=np.float64)
+        if x is None:
+            x = np.empty_like(b, order="F")
+        elif not isinstance(x, np.ndarray):
+            raise TypeError("x: expected a numpy array like b")
+        elif x.dtype != np.float64 or x.shape != b.shape or not x.flags.f_contiguous:
+            raise ValueError("x: expected a column-major float64 array of b's shape")
+        nrhs = 1 if b.ndim == 1 else b.shape[1]
+        return b, x, nrhs, max(n, 1), 0
+    if not _is_torch(b):
+        raise TypeError("b: expected a numpy array or a device tensor")
+    import torch
+    if b.dtype != torch.float64:
+        raise TypeError(f"b: expected float64, got {b.dtype}")
+    _check_device(b)
+    if b.dim() not in (1, 2) or (n >= 0 and b.shape[0] != n):
+        raise ValueError(f"b: expected {n} rows, got shape {tuple(b.shape)}")
+    nrhs = 1 if b.dim() == 1 else b.shape[1]
+    if b.dim() == 1:
+        if b.stride(0) != 1:
+            b = b.contiguous()
+        ld = max(n, 1)
+    else:
+        if b.stride(0) != 1 or (nrhs > 1 and b.stride(1) < n):
+            b = b.t().contiguous().t()
+        ld = b.stride(1) if nrhs > 1 else max(n, 1)
+    if x is None:
+        x = torch.empty_strided(b.shape, b.stride(), dtype=torch.float64, device=b.device)
+    else:
+        if not _is_torch(x) or x.dtype != torch.float64:
+            raise TypeError("x: expected a float64 device tensor like b")
+        _check_device(x)
+        if tuple(x.shape) != tuple(b.shape) or x.stride(0) != 1 or (
+                nrhs > 1 and x.stride(1) != ld):
+            raise ValueError("x: expected b's shape and column-major layout with b's leading "
+                             f"dimension {ld}")
+    return b, x, nrhs, ld, 1
+
+
+def _solve_info(num: NumericHandle, nrhs: int):
+    info = tacho_solve_info()
+    rr = np.zeros(max(nrhs, 1), np.float64)
+    fb = np.zeros(max(nrhs * max(num.sym.nsys, 1), 1), np.int32)
+    info.relres = rr.ctypes.data_as(_f64p)
+    info.fell_back_units = fb.ctypes.data_as(_i32p)
+    return info, rr, fb
+
+
+def _info_dict(num, info, rr, fb, nrhs):
+    return {"iters": info.iters, "fell_back": info.fell_back, "relres_max": info.relres_max,
+            "relres": rr[:nrhs].copy(),
+            "fell_back_units": fb[:nrhs * max(num.sym.nsys, 1)].reshape(nrhs, -1).T.copy()}
+
+
 def tacho_solve(num: NumericHandle, b, x=None, stream=None, with_info: bool = False):
     """Solve A X = B.  ``b`` (n or n x nrhs, column-major) is a numpy array or a
     device tensor; ``x`` defaults to a new array of the same kind."""
     lib = _load()
-    vec = b.ndim == 1
-    n = b.shape[0]
-    nrhs = 1 if vec else b.shape[1]
-    if isinstance(b, np.ndarray):
-        b = np.asfortranarray(b, dtype=np.float64)
-        if x is None:
-            x = np.empty_like(b, order="F")
-        ld = n
-    else:
-        import torch
-        if b.dim() == 2:
-            if b.stride(0) != 1:
-                b = b.t().contiguous().t()
-            ld = b.stride(1) if nrhs > 1 else n
-        else:
-            ld = n
-        if x is None:
-            x = torch.empty_strided(b.shape, b.stride(), dtype=torch.float64, device=b.device)
-    ba, on_dev = _ptr_of(b)
-    xa, _ = _ptr_of(x)
-    info = tacho_solve_info()
-    rr = np.zeros(max(nrhs, 1), np.float64)
-    info.relres = rr.ctypes.data_as(_f64p)
-    rc = lib.tacho_solve(num.ptr, ba, xa, int(nrhs), int(ld), on_dev, _stream_ptr(stream),
-                         ctypes.byref(info))
+    b, x, nrhs, ld, on_dev = _solve_args(num, b, x)
+    info, rr, fb = _solve_info(num, nrhs)
+    addr = (lambda a: a.ctypes.data) if on_dev == 0 else (lambda a: a.data_ptr())
+    rc = lib.tacho_solve(num.ptr, addr(b), addr(x), int(nrhs), int(ld), on_dev,
+                         _stream_ptr(stream), ctypes.byref(info))
     _check(rc)
     if with_info:
-        return x, {"iters": info.iters, "fell_back": info.fell_back,
-                   "relres_max": info.relres_max, "relres": rr[:nrhs].copy()}
+        return x, _info_dict(num, info, rr, fb, nrhs)
     return x
 
 

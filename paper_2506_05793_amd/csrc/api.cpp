@@ -158,8 +158,25 @@ struct KernelProfile {
   }
 };
 
+// Host bookkeeping of one refinement, per unit (system x right-hand side).
+struct RefineHost {
+  std::vector<double> hn, rho, prev;
+  std::vector<int> stalls;
+  std::vector<uint8_t> done, bad, mask;
+  void resize(int64_t units) {
+    hn.resize(2 * units);
+    rho.resize(units);
+    prev.resize(units);
+    stalls.resize(units);
+    done.resize(units);
+    bad.resize(units);
+    mask.resize(units);
+  }
+};
+
 struct tacho_num {
   tacho_sym* sym = nullptr;
+  RefineHost rh;
   KernelProfile prof;
   int precision = TACHO_FP64;
   DBuf L, U, avals, vals, fullvals, scale, fail, winv, pt1;
@@ -167,14 +184,18 @@ struct tacho_num {
   DBuf part;                // partial L21 products of the split solves
   DBuf sync;                // solve tickets (2 per level) and block ready flags
   DBuf flow;                // dataflow factorization counters, flags, tickets, hang flag
-  DBuf bdev, xdev, r, dx, norms;  // host-pointer staging and refinement buffers
+  DBuf bdev, xdev;          // host-pointer staging
+  DBuf rws;                 // refinement scratch (residual, norms, mask)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool pending = false;     // factorization queued, flag not yet read
   int last_status = TACHO_OK;
   int64_t last_fail = -1;
   hipStream_t last_stream = nullptr;
   tacho_num* fallback = nullptr;  // FP64 refactorization after a refinement stall
-  bool fp32_broken = false;       // FP32 pivot breakdown: solves use `fallback`
+  bool fp32_broken = false;       // FP32 pivot breakdown: the breaking system uses `fallback`
+  int32_t fp32_fail_col = -1;     // permuted column of the first FP32 pivot breakdown
+  hipStream_t last_solve_stream = nullptr;  // stream of the last solve (queued or finished)
+  bool solve_queued = false;      // a solve was queued without reading its hang flag
   hipGraphExec_t fgraph = nullptr;  // captured factorization launch sequence
   ~tacho_num() {
     if (fgraph) (void)hipGraphExecDestroy(fgraph);
@@ -194,7 +215,7 @@ tacho_options defaults() {
   std::memset(&o, 0, sizeof(o));
   o.nd_leaf_size = 8;
   o.small_front = 0;
-  o.scale = 1;
+  o.scale_fp32 = 1;
   o.refine_max = 10;
   o.refine_tol = 1e-10;
   o.stall_ratio = 0.5;
@@ -389,7 +410,7 @@ DevNum<T> num_view(tacho_num* f) {
   N.L = f->L.as<T>();
   N.U = f->U.as<T>();
   N.avals = f->avals.as<T>();
-  N.scale = f->precision == TACHO_FP32 && f->sym->opt.scale ? f->scale.as<double>() : nullptr;
+  N.scale = f->precision == TACHO_FP32 && f->sym->opt.scale_fp32 ? f->scale.as<double>() : nullptr;
   N.fail = f->fail.as<int32_t>();
   N.pt1 = f->pt1.as<T>();
   return N;
@@ -459,7 +480,10 @@ int read_fail_flag(tacho_num* f, int64_t* fail_index) {
   }
   if (flag != INT32_MAX && f->precision == TACHO_FP32) {
     // FP32 pivot breakdown: the FP64 factorization of the same values on the
-    // same symbolic handle serves this handle's solves (reported as a fallback).
+    // same symbolic handle serves the solves of the system that broke down
+    // (reported as a fallback); the other systems of a batch keep their FP32
+    // factors, which do not depend on it.
+    f->fp32_fail_col = flag;
     int64_t fi = -1;
     const int rc = fp64_fallback(f, f->last_stream, &fi);
     f->last_status = rc;
@@ -494,7 +518,7 @@ void enqueue_factor(tacho_num* f, hipStream_t st) {
   if (f->precision == TACHO_FP32) {
     launch_mirror(h->d_mirror.as<int64_t>(), vals, f->fullvals.as<double>(),
                   (int64_t)S.A.colind.size(), st);
-    if (h->opt.scale) launch_scale(h->view, vals, f->scale.as<double>(), st);
+    if (h->opt.scale_fp32) launch_scale(h->view, vals, f->scale.as<double>(), st);
     const int pe = f->prof.begin(st);
     launch_gather<float>(h->view, num_view<float>(f), vals, nq, st);
     f->prof.end(pe, st, TACHO_K_GATHER, 0, nq * (8.0 + 8.0 + 4.0));
@@ -535,6 +559,7 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
   const int64_t nv = S.nnz_input;
   if (nv > 0 && !values) return fail(TACHO_ERR_INVALID, "values is NULL");
   f->fp32_broken = false;
+  f->fp32_fail_col = -1;
   if (nv > 0)
     HIP_TRY(hipMemcpyAsync(f->vals.p, values, nv * sizeof(double),
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
@@ -587,6 +612,7 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
     HIP_TRY(f->fullvals.alloc(sizeof(double) * S.A.colind.size()));
   }
   for (auto& e : f->ev) HIP_TRY(hipEventCreate(&e));
+  if (precision == TACHO_FP32) f->rh.resize(S.nsys * kRhs);
   *out = f.release();
   return TACHO_OK;
 }
@@ -604,16 +630,24 @@ int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index) {
 }
 
 // Error if a wait of this handle's dataflow solves (or of its FP64
-// fallback's) timed out; the flag stays raised.  Synchronizes st.
+// fallback's) timed out.  Synchronizes st.  A raised flag is reported once
+// and then cleared, so the handle's next solve waits normally again.
 int check_solve_hang(tacho_num* f, hipStream_t st) {
   int32_t hang[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(&hang[0], f->sync.as<int32_t>() + solve_counters(f->sym), sizeof(int32_t),
-                         hipMemcpyDeviceToHost, st));
-  if (f->fallback)
-    HIP_TRY(hipMemcpyAsync(&hang[1], f->fallback->sync.as<int32_t>() + solve_counters(f->sym),
-                           sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  int32_t* flags[2] = {f->sync.as<int32_t>() + solve_counters(f->sym),
+                       f->fallback ? f->fallback->sync.as<int32_t>() + solve_counters(f->sym)
+                                   : nullptr};
+  HIP_TRY(hipMemcpyAsync(&hang[0], flags[0], sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  if (flags[1])
+    HIP_TRY(hipMemcpyAsync(&hang[1], flags[1], sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (hang[0] || hang[1]) return fail(TACHO_ERR_HIP, "dataflow solve: a dependency wait timed out");
+  f->solve_queued = false;
+  if (hang[0] || hang[1]) {
+    for (int k = 0; k < 2; ++k)
+      if (hang[k]) launch_fill_i32(flags[k], 0, 1, st);
+    HIP_TRY(hipStreamSynchronize(st));
+    return fail(TACHO_ERR_HIP, "dataflow solve: a dependency wait timed out");
+  }
   return TACHO_OK;
 }
 
@@ -626,7 +660,7 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   const Symbolic& S = h->S;
   const DevSym& V = h->view;
   const Plan& P = h->P;
-  const double* scale = f->precision == TACHO_FP32 && h->opt.scale ? f->scale.as<double>() : nullptr;
+  const double* scale = f->precision == TACHO_FP32 && h->opt.scale_fp32 ? f->scale.as<double>() : nullptr;
   T* y = f->y.as<T>();
   const T* L = f->L.as<T>();
   const T* winv = f->winv.as<T>();
@@ -643,6 +677,9 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   }
   int pe = f->prof.begin(st);
   launch_solve_in<T>(V, b, ldb, y, nrhs, scale, counters, ns, nblk, st);
+  // test hook: raise the hang flag so that every dependency wait of this
+  // sweep gives up at once (the kernels still run to the end)
+  if (h->opt.debug_flags & TACHO_DEBUG_SOLVE_GIVE_UP) launch_fill_i32(hang, 1, 1, st);
   f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
   const WaveItem* items = h->d_lwave.as<WaveItem>();
   const int32_t* large = h->d_llarge.as<int32_t>();
@@ -678,34 +715,75 @@ void solve_all(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t ld
   }
 }
 
+// Device scratch of one refinement: residual r (n x nrhs), per-unit norms
+// (2 x units) and a per-unit byte mask.
+struct RefineScratch {
+  double* r = nullptr;
+  double* nrm = nullptr;
+  uint8_t* mask = nullptr;
+};
+
+int64_t refine_scratch_bytes(int64_t n, int64_t nrhs, int64_t nsys) {
+  const int64_t units = nsys * nrhs;
+  return (int64_t)sizeof(double) * (n * nrhs + 2 * units) + units;
+}
+
+RefineScratch carve_refine_scratch(void* base, int64_t n, int64_t nrhs, int64_t nsys) {
+  RefineScratch w;
+  w.r = static_cast<double*>(base);
+  w.nrm = w.r + n * nrhs;
+  w.mask = reinterpret_cast<uint8_t*>(w.nrm + 2 * nsys * nrhs);
+  return w;
+}
+
 // FP32 factor + FP64 refinement on device buffers b (ld n) -> x (ld n).
 // Convergence is tracked per independent system and right-hand side (one
-// unit each): a converged unit gets a zero correction from then on, so a
-// system's result does not depend on the other systems of a batch.
+// unit each): a converged unit gets a zero correction from then on, and a
+// unit that stalls (or whose system's FP32 factorization broke down) takes
+// the FP64 factor's solution while the others keep their refined FP32
+// results, so a system's result does not depend on the other systems of a
+// batch.  The host bookkeeping lives in the handle (sized for 16 columns when
+// the handle is created).
 int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStream_t st,
-                 tacho_solve_info* info) {
+                 tacho_solve_info* info, const RefineScratch& ws, bool may_allocate) {
   tacho_sym* h = f->sym;
   const Symbolic& S = h->S;
   const int64_t n = S.n;
   const int64_t nsys = S.nsys;
   const int64_t units = nsys * nrhs;
-  if (!f->r.p || f->r.bytes < sizeof(double) * n * nrhs) HIP_TRY(f->r.alloc(sizeof(double) * n * nrhs));
-  if (!f->norms.p || f->norms.bytes < sizeof(double) * 2 * units + units)
-    HIP_TRY(f->norms.alloc(sizeof(double) * 2 * units + units));
-  double* r = f->r.as<double>();
-  double* nrm = f->norms.as<double>();
-  uint8_t* mask = reinterpret_cast<uint8_t*>(nrm + 2 * units);
+  double* r = ws.r;
+  double* nrm = ws.nrm;
+  uint8_t* mask = ws.mask;
   const int64_t* sysp = h->d_sys_ptr.as<int64_t>();
-  std::vector<double> hn(2 * units), rho(units), prev(units, INFINITY);
-  std::vector<int> stalls(units, 0);
-  std::vector<uint8_t> done(units, 0);
+  RefineHost& H = f->rh;
+  if ((int64_t)H.rho.size() < units) {
+    if (!may_allocate) return fail(TACHO_ERR_INVALID, "too many right-hand sides for this call");
+    H.resize(units);
+  }
+  double* hn = H.hn.data();
+  double* rho = H.rho.data();
+  for (int64_t u = 0; u < units; ++u) {
+    H.prev[u] = INFINITY;
+    H.stalls[u] = 0;
+    H.done[u] = 0;
+    H.bad[u] = 0;
+  }
+  if (f->fp32_broken) {
+    // the system holding the first failing pivot goes to the FP64 factor at
+    // once; any other system that broke down shows a non-finite residual
+    const int32_t orig = S.perm[f->fp32_fail_col];
+    const int64_t k = std::upper_bound(S.sys_ptr.begin(), S.sys_ptr.end(), (int64_t)orig) -
+                      S.sys_ptr.begin() - 1;
+    for (int64_t c = 0; c < nrhs; ++c) H.bad[k + c * nsys] = 1;
+  }
+  int64_t active = 0;
+  for (int64_t u = 0; u < units; ++u) active += H.bad[u] ? 0 : 1;
   launch_segnorms(nsys, sysp, b, n, nrhs, nrm + units, st);
-  if (!f->fp32_broken) solve_all<float>(f, b, n, x, n, nrhs, 0, st);
+  if (active > 0) solve_all<float>(f, b, n, x, n, nrhs, 0, st);
   const double tol = h->opt.refine_tol > 0 ? h->opt.refine_tol : 1e-10;
   const int maxit = h->opt.refine_max > 0 ? h->opt.refine_max : 10;
   const double ratio = h->opt.stall_ratio > 0 ? h->opt.stall_ratio : 0.5;
   int iters = 0;
-  bool stalled = f->fp32_broken;
   const double nnz = (double)S.A.colind.size();
   auto residual_norms = [&]() -> int {
     const int pe = f->prof.begin(st);
@@ -714,7 +792,7 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
     launch_segnorms(nsys, sysp, r, n, nrhs, nrm, st);
     f->prof.end(pe, st, TACHO_K_REFINE, (2.0 * nnz + 2.0 * n) * nrhs,
                 nnz * 12.0 + 8.0 * n + 8.0 * 3.0 * n * nrhs);
-    HIP_TRY(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * 2 * units, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hn, nrm, sizeof(double) * 2 * units, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     for (int64_t u = 0; u < units; ++u) {
       const double bn = hn[units + u];
@@ -723,51 +801,68 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
     }
     return TACHO_OK;
   };
-  while (!f->fp32_broken) {
+  while (active > 0) {
     int rc = residual_norms();
     if (rc != TACHO_OK) return rc;
-    bool all = true;
     for (int64_t u = 0; u < units; ++u) {
-      if (done[u]) continue;
+      if (H.done[u] || H.bad[u]) continue;
       if (rho[u] <= tol) {
-        done[u] = 1;
+        H.done[u] = 1;
+        --active;
         continue;
       }
-      all = false;
-      if (rho[u] > ratio * prev[u]) {
-        if (++stalls[u] >= 2) stalled = true;
-      } else {
-        stalls[u] = 0;
+      if (!std::isfinite(rho[u])) {
+        H.bad[u] = 1;
+        --active;
+        continue;
       }
-      prev[u] = rho[u];
+      if (rho[u] > ratio * H.prev[u]) {
+        if (++H.stalls[u] >= 2) {
+          H.bad[u] = 1;
+          --active;
+        }
+      } else {
+        H.stalls[u] = 0;
+      }
+      H.prev[u] = rho[u];
     }
-    if (all) break;
-    if (stalled || iters >= maxit) {
-      stalled = true;
+    if (active == 0) break;
+    if (iters >= maxit) {
+      for (int64_t u = 0; u < units; ++u)
+        if (!H.done[u]) H.bad[u] = 1;
+      active = 0;
       break;
     }
-    // converged units get a zero correction: clear their residual
-    HIP_TRY(hipMemcpyAsync(mask, done.data(), units, hipMemcpyHostToDevice, st));
+    // finished units (converged or handed to FP64) get a zero correction
+    for (int64_t u = 0; u < units; ++u) H.mask[u] = H.done[u] | H.bad[u];
+    HIP_TRY(hipMemcpyAsync(mask, H.mask.data(), units, hipMemcpyHostToDevice, st));
     launch_zero_units(nsys, sysp, r, n, nrhs, mask, st);
     solve_all<float>(f, r, n, x, n, nrhs, 1, st);
     ++iters;
   }
-  if (stalled) {
+  int64_t nbad = 0;
+  for (int64_t u = 0; u < units; ++u) nbad += H.bad[u];
+  if (nbad > 0) {
     // FP64 refactorization with the same values (already done after an FP32
-    // pivot breakdown), then an FP64 solve.
-    int rc = TACHO_OK;
-    if (!f->fp32_broken) {
+    // pivot breakdown), an FP64 solve of every unit into r, and its columns
+    // copied into x for the units that fell back.
+    if (!f->fallback) {
+      if (!may_allocate)
+        return fail(TACHO_ERR_NOMEM, "refinement stalled and the FP64 fallback factor would "
+                                     "need device memory; use tacho_solve");
       int64_t fi = -1;
-      rc = fp64_fallback(f, st, &fi);
+      const int rc = fp64_fallback(f, st, &fi);
       if (rc != TACHO_OK) return rc;
     }
-    solve_all<double>(f->fallback, b, n, x, n, nrhs, 0, st);
-    rc = residual_norms();
+    solve_all<double>(f->fallback, b, n, r, n, nrhs, 0, st);
+    HIP_TRY(hipMemcpyAsync(mask, H.bad.data(), units, hipMemcpyHostToDevice, st));
+    launch_select_units(nsys, sysp, x, r, n, nrhs, mask, st);
+    const int rc = residual_norms();
     if (rc != TACHO_OK) return rc;
   }
   if (info) {
     info->iters = iters;
-    info->fell_back = stalled ? 1 : 0;
+    info->fell_back = nbad > 0 ? 1 : 0;
     double mx = 0;
     for (int64_t c = 0; c < nrhs; ++c) {
       double col = 0;
@@ -776,6 +871,8 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
       if (info->relres) info->relres[c] = col;
     }
     info->relres_max = mx;
+    if (info->fell_back_units)
+      for (int64_t u = 0; u < units; ++u) info->fell_back_units[u] = H.bad[u];
   }
   return check_solve_hang(f, st);
 }
@@ -830,6 +927,15 @@ int tacho_analyze_batch(int64_t nsys, const int64_t* n, const int64_t* const* ro
   int64_t ntot = 0, nnz = 0;
   for (int64_t k = 0; k < nsys; ++k) {
     if (n[k] < 0 || (n[k] > 0 && !rowptr[k])) return fail(TACHO_ERR_INVALID, "invalid system");
+    if (n[k] > 0) {
+      if (rowptr[k][0] != 0)
+        return fail(TACHO_ERR_INVALID, "system " + std::to_string(k) + ": rowptr[0] != 0");
+      for (int64_t i = 0; i < n[k]; ++i)
+        if (rowptr[k][i + 1] < rowptr[k][i])
+          return fail(TACHO_ERR_INVALID, "system " + std::to_string(k) + ": rowptr decreases");
+      if (rowptr[k][n[k]] > 0 && !colind[k])
+        return fail(TACHO_ERR_INVALID, "system " + std::to_string(k) + ": colind is NULL");
+    }
     ntot += n[k];
     nnz += n[k] > 0 ? rowptr[k][n[k]] : 0;
   }
@@ -948,9 +1054,13 @@ int tacho_refactorize(tacho_num_t f, const double* values, int values_on_device,
 
 int tacho_check_factor(tacho_num_t f, int64_t* fail_index) {
   if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
-  if (f->pending) return read_fail_flag(f, fail_index);
+  if (f->pending) {
+    const int rc = read_fail_flag(f, fail_index);
+    if (rc != TACHO_OK) return rc;
+  }
   if (f->sync.p) {
-    const int rc = check_solve_hang(f, f->last_stream);
+    // the last solve may have been queued on another stream than the factorization
+    const int rc = check_solve_hang(f, f->last_solve_stream ? f->last_solve_stream : f->last_stream);
     if (rc != TACHO_OK) return rc;
   }
   if (fail_index) *fail_index = f->last_fail;
@@ -981,6 +1091,8 @@ int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t
   }
   if (nrhs == 0 || n == 0) return TACHO_OK;
   hipStream_t st = (hipStream_t)hip_stream;
+  f->last_solve_stream = st;
+  f->solve_queued = true;
   const double* bd = b;
   double* xd = x;
   const bool dense_ld = ld == n;
@@ -999,8 +1111,10 @@ int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t
   const int64_t ldi = (bd == b) ? ld : n;
   HIP_TRY(hipEventRecord(f->ev[2], st));
   if (refine) {
-    int rc = TACHO_OK;
-    rc = refine_solve(f, bd, xd, nrhs, st, info);
+    const int64_t need = refine_scratch_bytes(n, nrhs, h->S.nsys);
+    if (f->rws.bytes < (size_t)need) HIP_TRY(f->rws.alloc(need));
+    const int rc = refine_solve(f, bd, xd, nrhs, st, info,
+                                carve_refine_scratch(f->rws.p, n, nrhs, h->S.nsys), true);
     if (rc != TACHO_OK) return rc;
   } else {
     solve_all<double>(f, bd, ldi, xd, (xd == x) ? ld : n, nrhs, 0, st);
@@ -1026,6 +1140,9 @@ int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
     int rc = read_fail_flag(f, nullptr);
     if (rc != TACHO_OK) return rc;
   }
+  // after an FP32 pivot breakdown the FP32 factor is not valid: the FP64
+  // factor of the same values is the one the solves fall back to
+  if (f->fp32_broken && f->fallback) f = f->fallback;
   const Symbolic& S = f->sym->S;
   const Plan& P = f->sym->P;
   const size_t es = elem_size(f->precision);

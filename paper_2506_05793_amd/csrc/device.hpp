@@ -136,4 +136,8 @@ void launch_segnorms(int64_t nsys, const int64_t* sys_ptr, const double* v, int6
 void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t ldv, int64_t nrhs,
                        const uint8_t* mask, hipStream_t st);
 
+// v[sys k rows, c] = src[sys k rows, c] where mask[k + c*nsys] != 0 (both with ld)
+void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const double* src,
+                         int64_t ld, int64_t nrhs, const uint8_t* mask, hipStream_t st);
+
 }  // namespace tacho

@@ -2058,6 +2058,15 @@ __global__ __launch_bounds__(kThreads) void k_zero_units(const int64_t* sys_ptr,
   for (int64_t i = sys_ptr[k] + threadIdx.x; i < sys_ptr[k + 1]; i += kThreads) v[i + c * ldv] = 0.0;
 }
 
+__global__ __launch_bounds__(kThreads) void k_select_units(const int64_t* sys_ptr, double* v,
+                                                           const double* src, int64_t ld,
+                                                           int64_t nsys, const uint8_t* mask) {
+  const int64_t k = blockIdx.x, c = blockIdx.y;
+  if (!mask[k + c * nsys]) return;
+  for (int64_t i = sys_ptr[k] + threadIdx.x; i < sys_ptr[k + 1]; i += kThreads)
+    v[i + c * ld] = src[i + c * ld];
+}
+
 inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -2249,6 +2258,13 @@ void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t 
   if (nsys > 0 && nrhs > 0)
     hipLaunchKernelGGL(k_zero_units, dim3((unsigned)nsys, (unsigned)nrhs), dim3(kThreads), 0, st,
                        sys_ptr, v, ldv, nsys, mask);
+}
+
+void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const double* src,
+                         int64_t ld, int64_t nrhs, const uint8_t* mask, hipStream_t st) {
+  if (nsys > 0 && nrhs > 0)
+    hipLaunchKernelGGL(k_select_units, dim3((unsigned)nsys, (unsigned)nrhs), dim3(kThreads), 0, st,
+                       sys_ptr, v, src, ld, nsys, mask);
 }
 
 #define TACHO_INSTANTIATE(T)                                                                     \

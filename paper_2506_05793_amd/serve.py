@@ -27,7 +27,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import (TACHO_FP64, tacho_analyze, tacho_check_factor, tacho_default_options,
+from . import (TACHO_FP64, TachoError, tacho_analyze, tacho_check_factor, tacho_default_options,
                tacho_numeric_bytes, tacho_numeric_create, tacho_refactorize, tacho_solve)
 
 
@@ -51,6 +51,7 @@ class Result:
     t_admit: float
     t_done: float
     x: np.ndarray
+    error: str | None = None    # library error of the request's factorization or solve
 
     @property
     def latency(self) -> float:
@@ -149,8 +150,14 @@ class Server:
                 if job.event.query():
                     t_done = time.perf_counter() - t0
                     r = job.req
-                    if r.kind == "factor":
+                    # every retired job: the factorization's failure flag (factor
+                    # requests) and the solve's timed-out-wait flag
+                    err = None
+                    try:
                         tacho_check_factor(job.num)
+                    except TachoError as e:
+                        err = str(e)
+                    if r.kind == "factor":
                         self.resident[r.rid].busy = False
                         self.resident.move_to_end(r.rid)
                     else:
@@ -158,7 +165,7 @@ class Server:
                         self.resident.move_to_end(r.target)
                     x = job.x_host.numpy().copy(order="F")
                     results.append(Result(r.rid, r.kind, x.shape[0], x.shape[1], r.t_arrival,
-                                          job.t_admit, t_done, x))
+                                          job.t_admit, t_done, x, err))
                     free.append(job.slot)
                 else:
                     still.append(job)
@@ -218,7 +225,7 @@ class Server:
                     if inflight:
                         self.admitted_while_busy += 1
                     res.busy = True
-                    job = _Job(r, slot, None, None, time.perf_counter() - t0)
+                    job = _Job(r, slot, None, None, time.perf_counter() - t0, num=res.num)
                     self._launch_solve(job, res.num, r.rhs, st)
                 ev = torch.cuda.Event()
                 ev.record(self.streams[job.slot])

@@ -406,3 +406,57 @@ def test_fp32_breakdown_or_stall_falls_back_to_fp64(name, make, front):
     bound = max(np.linalg.norm(M @ abs(x64[:, c]) + abs(b[:, c])) / np.linalg.norm(b[:, c])
                 for c in range(b.shape[1]))
     assert abs(info["relres_max"] - rho) <= 4 * A.n * np.finfo(float).eps * bound
+
+
+def test_solve_give_up_is_reported_and_cleared():
+    """With the test hook that raises the solve's hang flag before its launches,
+    every dependency wait gives up at once (the kernels still finish) and the
+    queued device solve must be reported by tacho_check_factor; the report
+    clears the flag, so a solve on a handle without the hook is normal."""
+    A = gen.fv3d(20, 18, 16, seed=4)
+    s_bad = T.tacho_analyze(A.n, A.rowptr, A.colind,
+                            T.tacho_default_options(debug_flags=T.TACHO_DEBUG_SOLVE_GIVE_UP))
+    num = T.tacho_factorize(s_bad, A.values, T.TACHO_FP64)
+    b = torch.from_numpy(np.ascontiguousarray(gen.rhs(A.n, 2, seed=1).T)).cuda().t()
+    x = T.tacho_solve(num, b)  # queued only
+    with pytest.raises(T.TachoError) as e:
+        T.tacho_check_factor(num)
+    assert e.value.code == T.TACHO_ERR_HIP and "timed out" in str(e.value)
+    T.tacho_check_factor(num)  # reported once, then cleared
+    with pytest.raises(T.TachoError):  # host path checks before returning
+        T.tacho_solve(num, gen.rhs(A.n, 1, seed=3))
+    del x
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind)
+    good = T.tacho_factorize(s, A.values, T.TACHO_FP64)
+    bh = gen.rhs(A.n, 2, seed=1)
+    xg = T.tacho_solve(good, bh)
+    T.tacho_check_factor(good)
+    assert oracle.rel_residual(A, xg, bh).max() <= FP64_RESID_TOL
+
+
+def test_batch_fallback_is_per_system():
+    """One system that FP32 cannot resolve (cond 1e12) batched with
+    well-conditioned ones: only its columns take the FP64 solution; the others
+    keep their refined FP32 results, bitwise equal to the systems alone."""
+    good = gen.batch_fv3d(3, seed=12, lo=5, hi=9)
+    bad = _ill_conditioned_dense(120, 1e12, seed=2)
+    mats = [good[0], bad, good[1], good[2]]
+    sb = T.tacho_analyze_batch([(m.n, m.rowptr, m.colind) for m in mats])
+    nb = T.tacho_factorize(sb, np.concatenate([m.values for m in mats]), T.TACHO_FP32)
+    rhs = [gen.rhs(m.n, 2, seed=40 + k) for k, m in enumerate(mats)]
+    xb, info = T.tacho_solve(nb, np.asfortranarray(np.concatenate(rhs, axis=0)), with_info=True)
+    print("fell back per unit (system x column):", info["fell_back_units"].tolist())
+    assert info["fell_back"] == 1
+    assert info["fell_back_units"].shape == (4, 2)
+    assert info["fell_back_units"][1].tolist() == [1, 1]
+    assert info["fell_back_units"][[0, 2, 3]].sum() == 0
+    off = 0
+    for k, m in enumerate(mats):
+        s, _ = analyze(m)
+        if k == 1:
+            x = T.tacho_solve(T.tacho_factorize(s, m.values, T.TACHO_FP64), rhs[k])
+        else:
+            x = T.tacho_solve(T.tacho_factorize(s, m.values, T.TACHO_FP32), rhs[k])
+        assert np.array_equal(x, xb[off:off + m.n]), k
+        assert oracle.rel_residual(m, xb[off:off + m.n], rhs[k]).max() <= MIXED_RESID_TOL
+        off += m.n

@@ -58,3 +58,19 @@ def test_serving_mix_equals_alone():
         alone = T.tacho_solve(num, r.rhs)
         assert np.array_equal(alone, out.x), out.rid
         assert oracle.rel_residual(A, out.x, r.rhs).max() <= 1e-12
+
+
+def test_serving_reports_solve_errors():
+    """Every retired job is checked, repeats included: with the solve test hook
+    (every dependency wait gives up at once) each result carries the error."""
+    from paper_2506_05793_amd.serve import Server
+    reqs, _ = build_requests(8, seed=9, rate=2000.0)
+    opts = T.tacho_default_options(ordering=2, debug_flags=T.TACHO_DEBUG_SOLVE_GIVE_UP)
+    srv = Server(1 << 30, slots=2, options=opts)
+    res = srv.run(reqs)
+    srv.close()
+    assert len(res) == len(reqs)
+    kinds = {r.kind for r in res}
+    assert "repeat" in kinds
+    for out in res:
+        assert out.error is not None and "timed out" in out.error, (out.rid, out.kind)

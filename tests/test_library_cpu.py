@@ -192,3 +192,52 @@ def test_tuning_table_roundtrip(tmp_path):
     opt = autotune.options_for(262144, 1810432, table=path, asm_cols=4)
     assert (opt.u_range, opt.chain_min, opt.asm_cols) == (16, 4, 4)
     assert autotune.options_for(1000, 5000, table=path).u_range == 0  # library default
+
+
+def test_binding_rejects_bad_arguments():
+    """The binding checks dtype, length and layout before any pointer reaches
+    the library (a wrong buffer would be read or written out of bounds)."""
+    import torch
+    A = gen.fv3d(5, 4, 3, seed=1)
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind)
+    assert s.n == A.n and s.nnz == A.nnz and s.nsys == 1
+    num = T.NumericHandle(None, s, T.TACHO_FP64)  # no library handle: calls must fail first
+    with pytest.raises(ValueError):
+        T._values_arg(s, A.values[:-1])
+    with pytest.raises(TypeError):
+        T._values_arg(s, torch.from_numpy(A.values).float())
+    with pytest.raises(ValueError):
+        T._values_arg(s, torch.from_numpy(np.concatenate([A.values, A.values]))[::2])
+    with pytest.raises(TypeError):
+        T._values_arg(s, list(A.values))
+    addr, on_dev, keep = T._values_arg(s, A.values.astype(np.float32))  # host arrays are converted
+    assert on_dev == 0 and keep.dtype == np.float64
+    b = gen.rhs(A.n, 3, seed=1)
+    with pytest.raises(ValueError):
+        T._solve_args(num, b[:-1], None)
+    with pytest.raises(ValueError):
+        T._solve_args(num, b, np.empty((A.n, 2)))
+    with pytest.raises(ValueError):
+        T._solve_args(num, b, np.empty((A.n, 3), order="C"))
+    with pytest.raises(TypeError):
+        T._solve_args(num, b, torch.empty(A.n, 3, dtype=torch.float64))
+    with pytest.raises(TypeError):
+        T._solve_args(num, torch.from_numpy(b).float(), None)
+    with pytest.raises(TypeError):  # host torch tensors are not device tensors
+        T._solve_args(num, torch.from_numpy(b), None)
+    bb, xx, nrhs, ld, on_dev = T._solve_args(num, b, None)
+    assert nrhs == 3 and ld == A.n and on_dev == 0 and xx.flags.f_contiguous
+
+
+def test_batch_csr_validation():
+    A = gen.fv3d(4, 4, 3, seed=1)
+    rp = A.rowptr.copy()
+    rp_bad = rp + 5  # rowptr[0] != 0
+    with pytest.raises(T.TachoError) as e:
+        T.tacho_analyze_batch([(A.n, A.rowptr, A.colind), (A.n, rp_bad, A.colind)])
+    assert e.value.code == T.TACHO_ERR_INVALID and "rowptr[0]" in str(e.value)
+    rp_dec = rp.copy()
+    rp_dec[3] = rp_dec[4] + 1
+    with pytest.raises(T.TachoError) as e:
+        T.tacho_analyze_batch([(A.n, rp_dec, A.colind)])
+    assert e.value.code == T.TACHO_ERR_INVALID
