@@ -88,9 +88,11 @@ typedef struct {
                                 per level (tile tasks over 64-column pivot blocks with
                                 completion counters); 1: stepwise launches per pivot
                                 block (diagonal block, rows below, trailing update) */
-  /* Batching parameters of the launch plan (0 = default).  They change how
-   * work is grouped into tasks and launches, not which operations a front
-   * performs; u_range and chain_min change the order in which the same
+  /* Batching parameters of the launch plan (0 = default, or the tuned value
+   * when autotune_path is set).  They change how work is grouped into tasks
+   * and launches, not which operations a front performs.  solve_level_fronts,
+   * asm_cols and solo_m give bitwise the same results for every setting;
+   * u_range, chain_min and chain_inplace change the order in which a front's
    * contributions are summed, so results agree to rounding.  The autotuner
    * of the Python package times candidates on the device. */
   int32_t u_range;           /* pivot blocks per update-matrix range task (default 8) */
@@ -108,6 +110,35 @@ typedef struct {
                                 row tile is subtracted in place by the tasks that form
                                 it (>= 0, default) or left in a slot for the chain (< 0) */
   int32_t debug_flags;       /* TACHO_DEBUG_* test hooks (default 0) */
+  const char *autotune_path; /* NULL (default) or the path of the autotuner's JSON table,
+                                read by tacho_analyze: batching parameters left at 0 take
+                                the table's values, the order-neutral ones (asm_cols,
+                                solo_m, solve_level_fronts) from the entry of the
+                                workload class "n~2^<lg>/deg<d>/<fp64|fp32>" (lg the
+                                integer nearest log2(n), d = nnz/n rounded), the
+                                order-changing ones (u_range, chain_min, chain_inplace)
+                                from the entry "order/<fp64|fp32>", which does not depend
+                                on the workload, so that a system factored alone and in a
+                                batch gets the same arithmetic.  Absent entries leave the
+                                defaults; an unreadable or malformed file is
+                                TACHO_ERR_INVALID.  The string is read during the call. */
+  int32_t autotune_precision; /* which precision's table entries to take (TACHO_FP64,
+                                default, or TACHO_FP32): a symbolic handle holds one
+                                launch plan, used by numeric handles of either precision */
+  /* Condensed graph of the symbolic analysis (Tacho section: analysis on a
+   * graph compressed by the DOFs of each grid point).  The ordering runs on the
+   * condensed graph and keeps each condensed vertex's rows consecutive, so
+   * they share a supernode; when every condensed vertex's rows are
+   * indistinguishable (equal pattern rows), the elimination tree and column
+   * counts are derived from the condensed graph's (weighted by the number of
+   * rows), otherwise they are computed on the full pattern.  Either way the
+   * symbolic result is that of P A P^T with the resulting P. */
+  int32_t dof_block;         /* 0 (default): condense indistinguishable rows found in the
+                                pattern; 1: no condensation; b >= 2: rows [k b, (k+1) b)
+                                form condensed vertex k (b must divide n) */
+  const int32_t *dof_map;    /* NULL (default) or n entries: the condensed vertex of each
+                                row, ids 0..nc-1 all used; overrides dof_block; not
+                                accepted by tacho_analyze_batch.  Read during the call. */
 } tacho_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -129,10 +160,15 @@ typedef struct {
   int64_t nsystems;         /* independent systems (1 unless built by tacho_analyze_batch) */
   int64_t nnz_factor;       /* stored factor entries: nnz_l plus the explicit zeros of
                                relaxed supernodes */
-  int64_t ordering;         /* ordering used: 1 multilevel, 2 level-structure */
+  int64_t ordering;         /* ordering used: 1 multilevel, 2 level-structure; a batch
+                               orders each system alone (3: its systems used both) */
   int64_t t_order_us;       /* host microseconds of the analysis: fill-reducing ordering */
   int64_t t_structure_us;   /* etree, counts, supernodes, row structures, maps, levels */
   int64_t t_plan_us;        /* launch plan, memory plan and refinement maps */
+  /* batching parameters of the launch plan in effect (defaults and table resolved;
+     plan_chain_inplace 1 = in place, -1 = slot) */
+  int64_t plan_u_range, plan_chain_min, plan_solve_level_fronts, plan_asm_cols, plan_solo_m,
+      plan_chain_inplace;
 } tacho_sym_info;
 
 typedef struct {

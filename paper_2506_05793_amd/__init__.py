@@ -56,6 +56,10 @@ class tacho_options(ctypes.Structure):
         ("solo_m", ctypes.c_int32),
         ("chain_inplace", ctypes.c_int32),
         ("debug_flags", ctypes.c_int32),
+        ("autotune_path", ctypes.c_char_p),
+        ("autotune_precision", ctypes.c_int32),
+        ("dof_block", ctypes.c_int32),
+        ("dof_map", _i32p),
     ]
 
 
@@ -63,7 +67,9 @@ class tacho_sym_info(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "nnz_a", "nnz_l", "flops", "nsuper", "nlevels", "max_front", "max_width",
         "factor_bytes_fp64", "work_bytes_fp64", "device_bytes_fp64", "nsystems", "nnz_factor",
-        "ordering", "t_order_us", "t_structure_us", "t_plan_us")]
+        "ordering", "t_order_us", "t_structure_us", "t_plan_us", "plan_u_range",
+        "plan_chain_min", "plan_solve_level_fronts", "plan_asm_cols", "plan_solo_m",
+        "plan_chain_inplace")]
 
 
 class tacho_solve_info(ctypes.Structure):
@@ -150,6 +156,12 @@ def tacho_default_options(**overrides) -> tacho_options:
     opt = tacho_options()
     _load().tacho_default_options(ctypes.byref(opt))
     for k, v in overrides.items():
+        if k == "autotune_path" and isinstance(v, str):
+            v = v.encode()
+        if k == "dof_map" and v is not None:
+            arr = np.ascontiguousarray(v, dtype=np.int32)
+            opt._dof_map = arr  # kept alive with the options
+            v = arr.ctypes.data_as(_i32p)
         setattr(opt, k, v)
     return opt
 
@@ -190,6 +202,9 @@ def tacho_analyze(n, rowptr, colind, options: tacho_options | None = None) -> Sy
     lib = _load()
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     colind = np.ascontiguousarray(colind, dtype=np.int32)
+    dmap = getattr(options, "_dof_map", None)
+    if options is not None and options.dof_map and (dmap is None or dmap.size != int(n)):
+        raise ValueError(f"dof_map: expected {int(n)} entries")
     out = _vp()
     rc = lib.tacho_analyze(int(n), rowptr.ctypes.data_as(_i64p), colind.ctypes.data_as(_i32p),
                            ctypes.byref(options) if options is not None else None,

@@ -19,14 +19,20 @@ depends on the matrix and the device):
 * ``chain_inplace`` - chain fronts: the product for the next diagonal block's
   row tile is subtracted in place (>= 0) or left in a slot (< 0).
 
-None of them changes which operations a front performs; ``u_range`` and
-``chain_min`` change the order in which the same contributions are summed,
-so results agree to rounding.
+``asm_cols``, ``solo_m`` and ``solve_level_fronts`` only regroup work: every
+setting gives bitwise the same factor and solution.  ``u_range``,
+``chain_min`` and ``chain_inplace`` change the order in which a front's
+contributions are summed (results agree to rounding).  The table therefore
+keeps the order-neutral parameters per workload class and the order-changing
+ones per precision only ("order/fp64", "order/fp32"), tuned on one workload
+and used for all: a system then gets the same arithmetic alone, in a batch,
+or in a larger problem of another class.
 
 ``tune`` times candidates on the device by coordinate descent from the
 defaults (each candidate must reach the residual bound) and returns the
-best setting; ``TuningTable`` keeps settings per workload class in a JSON
-file; ``options_for`` turns a table entry into ``tacho_options``.
+best setting; ``TuningTable`` keeps settings in a JSON file, which the
+library reads itself (``tacho_options.autotune_path``); ``options_for``
+returns options that point the library at the table.
 """
 from __future__ import annotations
 
@@ -52,13 +58,30 @@ CANDIDATES = {
 }
 
 
-def workload_key(n: int, nnz: int, nsys: int = 1, precision: int = TACHO_FP64) -> str:
-    """Coarse workload class: order (power of two), mean row degree, systems,
-    precision."""
-    lg = int(round(math.log2(max(n, 1))))
-    deg = int(round(nnz / max(n, 1)))
-    prec = "fp64" if precision == TACHO_FP64 else "fp32"
-    return f"n~2^{lg}/deg{deg}/sys{'1' if nsys <= 1 else 'many'}/{prec}"
+ORDER_NEUTRAL = ("asm_cols", "solo_m", "solve_level_fronts")
+ORDER_CHANGING = ("u_range", "chain_min", "chain_inplace")
+
+
+def _prec(precision: int) -> str:
+    return "fp64" if precision == TACHO_FP64 else "fp32"
+
+
+def workload_key(n: int, nnz: int, precision: int = TACHO_FP64) -> str:
+    """Workload class of the order-neutral parameters: lg = the integer
+    nearest log2(n) (2^lg <= n < 2^(lg+1), plus one when n^2 >= 2^(2 lg + 1)),
+    mean row degree nnz / n rounded half up, precision.  The library computes
+    the same key from the same integers."""
+    nn = max(int(n), 1)
+    lg = nn.bit_length() - 1
+    if nn * nn >= 1 << (2 * lg + 1):
+        lg += 1
+    deg = (2 * int(nnz) + nn) // (2 * nn)
+    return f"n~2^{lg}/deg{deg}/{_prec(precision)}"
+
+
+def order_key(precision: int = TACHO_FP64) -> str:
+    """Entry of the order-changing parameters (one per precision)."""
+    return f"order/{_prec(precision)}"
 
 
 def _residual(rowptr, colind, values, x, b):
@@ -106,8 +129,10 @@ def measure(n, rowptr, colind, values, params, precision=TACHO_FP64, reps=7, ord
 
 
 def tune(n, rowptr, colind, values, precision=TACHO_FP64, reps=7, passes=1,
-         objective="request", log=print, candidates=None):
-    """Coordinate descent over ``candidates`` (default CANDIDATES) from DEFAULTS.
+         objective="request", log=print, candidates=None, start=None):
+    """Coordinate descent over ``candidates`` (default CANDIDATES) from DEFAULTS
+    updated with ``start`` (e.g. the precision's order-changing parameters,
+    held fixed when they are not among the candidates).
 
     objective "request": factor + 1-RHS solve time; "factor": factor time.
     Returns (best parameters, best measurement, history)."""
@@ -119,6 +144,7 @@ def tune(n, rowptr, colind, values, precision=TACHO_FP64, reps=7, passes=1,
         return m["factor_ms"] + (m["solve_ms"] if objective == "request" else 0.0)
 
     best = dict(DEFAULTS)
+    best.update(start or {})
     best_m = measure(n, rowptr, colind, values, best, precision, reps, ordering)
     if best_m is None:
         raise RuntimeError("the default plan misses the residual bound")
@@ -166,16 +192,32 @@ class TuningTable:
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 
-def tuned_params(n: int, nnz: int, nsys: int = 1, precision: int = TACHO_FP64,
-                 table: str | None = None) -> dict:
-    """Tuned plan parameters of the workload class ({} when the table has none)."""
-    return TuningTable(table or DEFAULT_TABLE).get(workload_key(n, nnz, nsys, precision)) or {}
+def tuned_params(n: int, nnz: int, precision: int = TACHO_FP64, table: str | None = None) -> dict:
+    """Parameters the library takes from the table for this workload class and
+    precision ({} when the table has neither entry)."""
+    tab = TuningTable(table or DEFAULT_TABLE)
+    out = {}
+    w = tab.get(workload_key(n, nnz, precision)) or {}
+    o = tab.get(order_key(precision)) or {}
+    out.update({k: v for k, v in w.items() if k in ORDER_NEUTRAL})
+    out.update({k: v for k, v in o.items() if k in ORDER_CHANGING})
+    return out
 
 
-def options_for(n: int, nnz: int, nsys: int = 1, precision: int = TACHO_FP64,
-                table: str | None = None, **overrides):
-    """tacho_options with the tuned plan parameters of the workload class (the
-    defaults when the table has no entry), then ``overrides``."""
-    params = tuned_params(n, nnz, nsys, precision, table)
-    params.update(overrides)
-    return tacho_default_options(**params)
+def options_for(n: int, nnz: int, precision: int = TACHO_FP64, table: str | None = None,
+                **overrides):
+    """tacho_options that let the library read the tuning table (parameters
+    left at 0 take the table's values for this workload class and precision),
+    then ``overrides``."""
+    return tacho_default_options(autotune_path=table or DEFAULT_TABLE,
+                                 autotune_precision=precision, **overrides)
+
+
+def store(tab: "TuningTable", n: int, nnz: int, precision: int, best: dict, info: dict,
+          order_too: bool):
+    """Put a tuned setting into the table: the order-neutral parameters under
+    the workload class, the order-changing ones (when ``order_too``) under the
+    precision's entry."""
+    tab.put(workload_key(n, nnz, precision), {k: best[k] for k in ORDER_NEUTRAL if k in best}, info)
+    if order_too:
+        tab.put(order_key(precision), {k: best[k] for k in ORDER_CHANGING if k in best}, info)

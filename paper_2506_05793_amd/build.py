@@ -18,7 +18,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtacho_mi355x.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["symbolic.cpp", "ordering.cpp", "ordering_levelset.cpp", "plan.cpp", "api.cpp", "kernels.hip"]
+SOURCES = ["symbolic.cpp", "ordering.cpp", "ordering_levelset.cpp", "plan.cpp", "tuning.cpp", "api.cpp", "kernels.hip"]
 ARCH = os.environ.get("TACHO_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

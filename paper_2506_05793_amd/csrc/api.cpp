@@ -15,6 +15,8 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -22,6 +24,7 @@
 #include "device.hpp"
 #include "plan.hpp"
 #include "symbolic.hpp"
+#include "tuning.hpp"
 
 using namespace tacho;
 
@@ -83,6 +86,7 @@ struct tacho_sym {
   tacho_options opt;
   Symbolic S;
   Plan P;
+  PlanTuning tune;                // plan parameters in effect (defaults resolved)
   std::vector<int64_t> mirror;    // per pattern entry: caller index of the lower twin (-1: none)
   std::vector<int32_t> a_prc;     // per assembly entry: permuted row, permuted column
   std::vector<int32_t> solve_levels;  // level_list copy (supernodes by level)
@@ -235,7 +239,21 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   SymOptions so;
   so.nd_leaf_size = h->opt.nd_leaf_size > 0 ? h->opt.nd_leaf_size : 8;
   so.ordering = h->opt.ordering;
-  int rc = analyze_pattern(h->S, so, err);
+  if (h->opt.dof_block < 0) return fail(TACHO_ERR_INVALID, "dof_block must be >= 0");
+  so.dof_block = h->opt.dof_block;
+  if (h->opt.dof_map) {
+    if (h->S.nsys > 1) return fail(TACHO_ERR_INVALID, "dof_map is not accepted for a batch");
+    so.dof_map = h->opt.dof_map;
+    so.dof_map_n = h->S.A.n;
+  }
+  int rc;
+  try {
+    rc = analyze_pattern(h->S, so, err);
+  } catch (const std::bad_alloc&) {
+    return fail(TACHO_ERR_NOMEM, "host memory exhausted during the analysis");
+  } catch (const std::exception& e) {
+    return fail(TACHO_ERR_INVALID, e.what());
+  }
   if (rc != kOk) return fail(rc, err);
   const auto t_plan = std::chrono::steady_clock::now();
   PlanTuning tune;
@@ -245,6 +263,27 @@ int finish_analysis(tacho_sym* h, int64_t nnz_input) {
   tune.asm_cols = h->opt.asm_cols;
   tune.solo_m = h->opt.solo_m;
   tune.chain_inplace = h->opt.chain_inplace;
+  if (h->opt.autotune_path && h->opt.autotune_path[0]) {
+    // parameters left at 0 take the table's value for this workload class
+    // and precision (order-changing ones from the precision's entry)
+    TunedParams tp;
+    if (load_tuned(h->opt.autotune_path, h->S.n, nnz_input,
+                   h->opt.autotune_precision == TACHO_FP32 ? 1 : 0, tp, err) != 0)
+      return fail(TACHO_ERR_INVALID, err);
+    if (tune.u_range == 0) tune.u_range = tp.u_range;
+    if (tune.chain_min == 0) tune.chain_min = tp.chain_min;
+    if (tune.level_fronts == 0) tune.level_fronts = tp.solve_level_fronts;
+    if (tune.asm_cols == 0) tune.asm_cols = tp.asm_cols;
+    if (tune.solo_m == 0) tune.solo_m = tp.solo_m;
+    if (tune.chain_inplace == 0) tune.chain_inplace = tp.chain_inplace;
+  }
+  // effective values (0 = the plan's default)
+  h->tune.u_range = tune.u_range > 0 ? tune.u_range : kURange;
+  h->tune.chain_min = tune.chain_min == 0 ? kChainMin : tune.chain_min;
+  h->tune.level_fronts = tune.level_fronts > 0 ? tune.level_fronts : kLevelFronts;
+  h->tune.asm_cols = tune.asm_cols > 0 ? tune.asm_cols : kAsmCols;
+  h->tune.solo_m = tune.solo_m == 0 ? kSoloM : tune.solo_m;
+  h->tune.chain_inplace = tune.chain_inplace >= 0 ? 1 : -1;
   rc = build_plan(h->S, h->P, err, h->opt.front_kernel == 1 ? 1 : 0, tune);
   if (rc != kOk) return fail(rc, err);
   const Symbolic& S = h->S;
@@ -991,6 +1030,12 @@ int tacho_query_symbolic(tacho_sym_t h, tacho_sym_info* info) {
   info->t_order_us = S.t_order_us;
   info->t_structure_us = S.t_structure_us;
   info->t_plan_us = S.t_plan_us;
+  info->plan_u_range = h->tune.u_range;
+  info->plan_chain_min = h->tune.chain_min;
+  info->plan_solve_level_fronts = h->tune.level_fronts;
+  info->plan_asm_cols = h->tune.asm_cols;
+  info->plan_solo_m = h->tune.solo_m;
+  info->plan_chain_inplace = h->tune.chain_inplace;
   return TACHO_OK;
 }
 

@@ -1,4 +1,5 @@
-// Nested-dissection ordering of the adjacency graph (host, one core).
+// Nested-dissection ordering of the adjacency graph (host; the independent
+// parts below the top separators are ordered in parallel threads).
 //
 // The paper's land-ice runs reorder each subdomain matrix with METIS nested
 // dissection before the factorization (Tacho section; the nested-dissection
@@ -23,7 +24,9 @@
 // not depend on what else is in the graph.
 #include <algorithm>
 #include <cstdint>
+#include <exception>
 #include <queue>
+#include <thread>
 #include <vector>
 
 #include "symbolic.hpp"
@@ -439,70 +442,104 @@ std::vector<uint8_t> separator_from_cut(const Graph& g, const std::vector<uint8_
   return cover;
 }
 
+// Per-thread scratch: local ids of induced() and component marks (indexed by
+// global vertex; a part touches only its own vertices and reads its
+// neighbours', so concurrent parts need their own copies).
+struct Work {
+  std::vector<int32_t> local, mark;
+  int32_t epoch = 0;
+  explicit Work(int32_t n) : local(n, -1), mark(n, 0) {}
+};
+
+// The order of a part is a function of the part alone: its components are
+// ordered one by one (the component holding the largest vertex first) and the
+// separator comes last.  Large parts near the top of the recursion hand one of
+// their components to another thread; the result does not depend on it.
 class Dissector {
  public:
-  Dissector(const Graph& G, int leaf) : G_(G), leaf_(std::max(leaf, 1)) {
-    perm_.assign(G.n, -1);
-    local_.assign(G.n, -1);
-    mark_.assign(G.n, 0);
-  }
+  Dissector(const Graph& G, int leaf) : G_(G), leaf_(std::max(leaf, 1)) {}
 
   std::vector<int32_t> run() {
-    hi_ = G_.n;
+    Work w(G_.n);
     std::vector<int32_t> all(G_.n);
     for (int32_t v = 0; v < G_.n; ++v) all[v] = v;
-    push_components(all);
-    while (!stack_.empty()) {
-      std::vector<int32_t> verts = std::move(stack_.back());
-      stack_.pop_back();
-      dissect(verts);
-    }
-    return perm_;
+    std::vector<int32_t> out;
+    out.reserve(G_.n);
+    order_components(all, w, 0, out);
+    return out;
   }
 
  private:
-  // Number `verts` (ascending) into the highest free positions.
-  void number(const std::vector<int32_t>& verts) {
-    const int64_t base = hi_ - (int64_t)verts.size();
-    for (size_t k = 0; k < verts.size(); ++k) perm_[base + k] = verts[k];
-    hi_ = base;
-  }
+  static constexpr int32_t kParallelMin = 20000;  // vertices of a part worth a thread
+  static constexpr int kParallelDepth = 4;        // at most 2^4 concurrent parts
 
-  void dissect(const std::vector<int32_t>& verts) {
+  // Append the order of `verts` (ascending, one connected component).
+  void order_part(const std::vector<int32_t>& verts, Work& w, int depth,
+                  std::vector<int32_t>& out) const {
     if ((int64_t)verts.size() <= leaf_) {
-      number(verts);
+      out.insert(out.end(), verts.begin(), verts.end());
       return;
     }
-    Graph g = induced(G_, verts, local_);
+    Graph g = induced(G_, verts, w.local);
     Rng rng(0x5eed0000ull ^ (uint64_t)verts.size() * 0x9E3779B97F4A7C15ull);
     std::vector<uint8_t> side = bisect(g, rng);
     std::vector<uint8_t> cover = separator_from_cut(g, side);
     std::vector<int32_t> sep, rest;
     for (int32_t i = 0; i < g.n; ++i) (cover[i] ? sep : rest).push_back(verts[i]);
     if (sep.empty() || rest.empty()) {  // no split found: treat as a leaf
-      number(verts);
+      out.insert(out.end(), verts.begin(), verts.end());
       return;
     }
-    number(sep);
-    push_components(rest);
+    order_components(rest, w, depth + 1, out);
+    out.insert(out.end(), sep.begin(), sep.end());
   }
 
-  // Split `verts` (ascending, still unnumbered) into connected components and
-  // push them so that the component holding the smallest vertex is dissected first.
-  void push_components(const std::vector<int32_t>& verts) {
-    ++epoch_;
-    for (int32_t v : verts) mark_[v] = epoch_;  // members of this set
+  // Append the orders of the connected components of `verts` (ascending),
+  // the component holding the largest smallest vertex first.
+  void order_components(const std::vector<int32_t>& verts, Work& w, int depth,
+                        std::vector<int32_t>& out) const {
+    std::vector<std::vector<int32_t>> comps = components(verts, w);
+    std::vector<std::vector<int32_t>> parts(comps.size());
+    std::vector<std::thread> helpers;
+    std::vector<std::exception_ptr> errs(comps.size());
+    for (size_t c = comps.size(); c-- > 0;) {
+      const bool spawn = depth < kParallelDepth && c > 0 &&
+                         (int32_t)comps[c].size() >= kParallelMin;
+      if (spawn) {
+        helpers.emplace_back([this, &comps, &parts, &errs, c, depth]() {
+          try {
+            Work wc(G_.n);
+            order_part(comps[c], wc, depth, parts[c]);
+          } catch (...) {
+            errs[c] = std::current_exception();
+          }
+        });
+      } else {
+        order_part(comps[c], w, depth, parts[c]);
+      }
+    }
+    for (auto& t : helpers) t.join();
+    for (auto& e : errs)
+      if (e) std::rethrow_exception(e);
+    for (size_t c = comps.size(); c-- > 0;) out.insert(out.end(), parts[c].begin(), parts[c].end());
+  }
+
+  // Connected components of the subgraph induced by `verts`, each ascending,
+  // in the order of their smallest vertex.
+  std::vector<std::vector<int32_t>> components(const std::vector<int32_t>& verts, Work& w) const {
+    ++w.epoch;
+    for (int32_t v : verts) w.mark[v] = w.epoch;  // members of this set
     std::vector<std::vector<int32_t>> comps;
     for (int32_t s : verts) {
-      if (mark_[s] != epoch_) continue;
+      if (w.mark[s] != w.epoch) continue;
       std::vector<int32_t> comp{s};
-      mark_[s] = -epoch_;
+      w.mark[s] = -w.epoch;
       for (size_t h = 0; h < comp.size(); ++h) {
         const int32_t v = comp[h];
         for (int64_t k = G_.xadj[v]; k < G_.xadj[v + 1]; ++k) {
           const int32_t u = G_.adj[k];
-          if (mark_[u] == epoch_) {
-            mark_[u] = -epoch_;
+          if (w.mark[u] == w.epoch) {
+            w.mark[u] = -w.epoch;
             comp.push_back(u);
           }
         }
@@ -510,15 +547,11 @@ class Dissector {
       std::sort(comp.begin(), comp.end());
       comps.push_back(std::move(comp));
     }
-    for (size_t c = comps.size(); c-- > 0;) stack_.push_back(std::move(comps[c]));
+    return comps;
   }
 
   const Graph& G_;
   int leaf_;
-  int64_t hi_ = 0;
-  int32_t epoch_ = 0;
-  std::vector<int32_t> perm_, local_, mark_;
-  std::vector<std::vector<int32_t>> stack_;
 };
 
 }  // namespace

@@ -13,11 +13,14 @@
 // supernodes; supernodal row structures by merging children; child-to-parent
 // relative maps; A-entry-to-front maps; height levels.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdint>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <numeric>
+#include <stdexcept>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -186,25 +189,29 @@ std::vector<int32_t> postorder(const std::vector<int32_t>& parent) {
 // column j contributes to, plus i itself) is encoded by +1 at its leaves,
 // -1 at the least common ancestor of consecutive leaves and -1 at parent(i);
 // subtree sums of that weight give eta_j.
+// With vertex weights wt (row i standing for wt[i] rows), the same encoding
+// with +-wt[i] in place of +-1 gives sum over the rows i of column j of wt[i].
 std::vector<int64_t> column_counts(int64_t n, const std::vector<int32_t>& parent,
                                    const std::vector<int64_t>& lptr,
-                                   const std::vector<int32_t>& lind) {
+                                   const std::vector<int32_t>& lind,
+                                   const std::vector<int32_t>* wt = nullptr) {
   std::vector<int32_t> first(n), prev_nbr(n, -1), prev_leaf(n, -1), uf(n);
   std::vector<int64_t> w(n, 0);
+  auto weight = [&](int64_t i) -> int64_t { return wt ? (*wt)[i] : 1; };
   for (int64_t j = 0; j < n; ++j) first[j] = (int32_t)j;
   for (int64_t j = 0; j < n; ++j)
     if (parent[j] >= 0) first[parent[j]] = std::min(first[parent[j]], first[j]);
   for (int64_t j = 0; j < n; ++j) {
     uf[j] = (int32_t)j;
-    if (first[j] == j) w[j] = 1;  // etree leaf: T_j = {j}
+    if (first[j] == j) w[j] = weight(j);  // etree leaf: T_j = {j}
   }
   for (int64_t j = 0; j < n; ++j) {
-    if (parent[j] >= 0) w[parent[j]] -= 1;
+    if (parent[j] >= 0) w[parent[j]] -= weight(j);
     // rows i > j with C_ij != 0: j may be a leaf of T_i
     for (int64_t q = lptr[j]; q < lptr[j + 1]; ++q) {
       int32_t i = lind[q];
       if (first[j] > prev_nbr[i]) {
-        w[j] += 1;
+        w[j] += weight(i);
         int32_t pl = prev_leaf[i];
         if (pl >= 0) {
           int32_t a = pl;
@@ -214,7 +221,7 @@ std::vector<int64_t> column_counts(int64_t n, const std::vector<int32_t>& parent
             uf[v] = a;
             v = nx;
           }
-          w[a] -= 1;
+          w[a] -= weight(i);
         }
         prev_leaf[i] = (int32_t)j;
       }
@@ -238,9 +245,31 @@ struct Ordered {
   int64_t nnzL = 0, flops = 0;
 };
 
+// Lower-triangle adjacency of C = P A P^T by columns: for column j the rows i > j.
+void lower_by_column(const Pattern& A, const std::vector<int32_t>& pinv, std::vector<int64_t>& lptr,
+                     std::vector<int32_t>& lind) {
+  const int64_t n = A.n;
+  lptr.assign(n + 1, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      const int32_t i = pinv[r], j = pinv[A.colind[k]];
+      if (i > j) lptr[j + 1]++;
+    }
+  for (int64_t j = 0; j < n; ++j) lptr[j + 1] += lptr[j];
+  lind.resize(lptr[n]);
+  std::vector<int64_t> pos(lptr.begin(), lptr.end() - 1);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      const int32_t i = pinv[r], j = pinv[A.colind[k]];
+      if (i > j) lind[pos[j]++] = i;
+    }
+}
+
 // Etree of the reordered pattern, postorder composed into the final
-// permutation, lower-triangle adjacency and column counts.
-Ordered order_and_count(const Pattern& A, const std::vector<int32_t>& perm0) {
+// permutation, lower-triangle adjacency and column counts (weighted by wt,
+// indexed by original vertex, when given).
+Ordered order_and_count(const Pattern& A, const std::vector<int32_t>& perm0,
+                        const std::vector<int32_t>* wt = nullptr) {
   const int64_t n = A.n;
   Ordered O;
   std::vector<int32_t> pinv0(n);
@@ -266,23 +295,13 @@ Ordered order_and_count(const Pattern& A, const std::vector<int32_t>& perm0) {
       O.parent[k] = p < 0 ? -1 : postinv[p];
     }
   }
-  O.lptr.assign(n + 1, 0);
-  for (int64_t r = 0; r < n; ++r)
-    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
-      const int32_t i = O.pinv[r], j = O.pinv[A.colind[k]];
-      if (i > j) O.lptr[j + 1]++;
-    }
-  for (int64_t j = 0; j < n; ++j) O.lptr[j + 1] += O.lptr[j];
-  O.lind.resize(O.lptr[n]);
-  {
-    std::vector<int64_t> pos(O.lptr.begin(), O.lptr.end() - 1);
-    for (int64_t r = 0; r < n; ++r)
-      for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
-        const int32_t i = O.pinv[r], j = O.pinv[A.colind[k]];
-        if (i > j) O.lind[pos[j]++] = i;
-      }
+  lower_by_column(A, O.pinv, O.lptr, O.lind);
+  std::vector<int32_t> wpost;
+  if (wt) {  // weights in permuted numbering
+    wpost.resize(n);
+    for (int64_t k = 0; k < n; ++k) wpost[k] = (*wt)[O.perm[k]];
   }
-  O.colcount = column_counts(n, O.parent, O.lptr, O.lind);
+  O.colcount = column_counts(n, O.parent, O.lptr, O.lind, wt ? &wpost : nullptr);
   for (int64_t j = 0; j < n; ++j) {
     O.nnzL += O.colcount[j];
     O.flops += O.colcount[j] * O.colcount[j];
@@ -417,25 +436,226 @@ bool compress_indistinguishable(const Pattern& A, Pattern& Q, std::vector<int32_
   return true;
 }
 
+// Quotient pattern of a partition of the vertices into classes (members
+// ascending, classes numbered by ascending smallest member when the partition
+// comes from indistinguishable vertices, by the caller's ids otherwise), and
+// whether every class is a set of indistinguishable vertices (equal rows of
+// the pattern, diagonal included).
+struct Condensed {
+  Pattern Q;
+  std::vector<int32_t> cptr, cmem, size;
+  bool exact = false;
+};
+
 namespace {
 
-// Order with one of the dissection methods, on the quotient graph when the
-// pattern has indistinguishable vertices.
-std::vector<int32_t> dissect(const Pattern& A, int method, int leaf) {
-  Pattern Q;
-  std::vector<int32_t> cptr, cmem;
-  if (!compress_indistinguishable(A, Q, cptr, cmem))
-    return method == 1 ? nested_dissection(A, leaf) : levelset_dissection(A, leaf);
+bool quotient_by_map(const Pattern& A, const std::vector<int32_t>& cls, int64_t ncls,
+                     Condensed& C, std::string& err) {
+  const int64_t n = A.n;
+  C.cptr.assign(ncls + 1, 0);
+  for (int64_t v = 0; v < n; ++v) C.cptr[cls[v] + 1]++;
+  for (int64_t c = 0; c < ncls; ++c) {
+    if (C.cptr[c + 1] == 0) {
+      err = "dof map: condensed vertex " + std::to_string(c) + " has no DOF";
+      return false;
+    }
+    C.cptr[c + 1] += C.cptr[c];
+  }
+  C.cmem.resize(n);
+  {
+    std::vector<int32_t> pos(C.cptr.begin(), C.cptr.end() - 1);
+    for (int64_t v = 0; v < n; ++v) C.cmem[pos[cls[v]]++] = (int32_t)v;
+  }
+  C.Q = Pattern();
+  C.Q.n = ncls;
+  C.Q.rowptr.assign(ncls + 1, 0);
+  std::vector<int32_t> row;
+  C.exact = true;
+  for (int64_t c = 0; c < ncls; ++c) {
+    row.clear();
+    const int32_t r0 = C.cmem[C.cptr[c]];
+    for (int32_t q = C.cptr[c]; q < C.cptr[c + 1]; ++q) {
+      const int32_t r = C.cmem[q];
+      for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) row.push_back(cls[A.colind[k]]);
+      if (C.exact && r != r0 &&
+          !(A.rowptr[r + 1] - A.rowptr[r] == A.rowptr[r0 + 1] - A.rowptr[r0] &&
+            std::equal(A.colind.begin() + A.rowptr[r], A.colind.begin() + A.rowptr[r + 1],
+                       A.colind.begin() + A.rowptr[r0])))
+        C.exact = false;
+    }
+    std::sort(row.begin(), row.end());
+    row.erase(std::unique(row.begin(), row.end()), row.end());
+    C.Q.colind.insert(C.Q.colind.end(), row.begin(), row.end());
+    C.Q.rowptr[c + 1] = (int64_t)C.Q.colind.size();
+  }
+  return true;
+}
+
+// The condensed graph the options ask for: indistinguishable vertices
+// (dof_block 0), none (1), blocks of dof_block consecutive rows, or the
+// caller's DOF map.  Returns false when there is nothing to condense (or on
+// an error, with err set).
+bool condense(const Pattern& A, const SymOptions& opt, Condensed& C, std::string& err) {
+  const int64_t n = A.n;
+  if (opt.dof_map) {
+    if (opt.dof_map_n != n) {
+      err = "dof map has " + std::to_string(opt.dof_map_n) + " entries for " + std::to_string(n) +
+            " rows";
+      return false;
+    }
+    int64_t ncls = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      if (opt.dof_map[v] < 0 || opt.dof_map[v] >= n) {
+        err = "dof map entry " + std::to_string(v) + " out of range";
+        return false;
+      }
+      ncls = std::max<int64_t>(ncls, opt.dof_map[v] + 1);
+    }
+    if (ncls == n) return false;
+    std::vector<int32_t> cls(opt.dof_map, opt.dof_map + n);
+    if (!quotient_by_map(A, cls, ncls, C, err)) return false;
+  } else if (opt.dof_block >= 2) {
+    const int64_t b = opt.dof_block;
+    if (n % b != 0) {
+      err = "dof_block " + std::to_string(b) + " does not divide n = " + std::to_string(n);
+      return false;
+    }
+    std::vector<int32_t> cls(n);
+    for (int64_t v = 0; v < n; ++v) cls[v] = (int32_t)(v / b);
+    if (!quotient_by_map(A, cls, n / b, C, err)) return false;
+  } else if (opt.dof_block == 1) {
+    return false;
+  } else {
+    if (!compress_indistinguishable(A, C.Q, C.cptr, C.cmem)) return false;
+    C.exact = true;
+  }
+  C.size.resize(C.Q.n);
+  for (int64_t c = 0; c < C.Q.n; ++c) C.size[c] = C.cptr[c + 1] - C.cptr[c];
+  return true;
+}
+
+std::vector<int32_t> dissection(const Pattern& P, int method, int leaf) {
+  return method == 1 ? nested_dissection(P, leaf) : levelset_dissection(P, leaf);
+}
+
+// One ordering candidate.  On a condensed graph the dissection runs on the
+// quotient and each class's members stay consecutive (ascending), and the
+// elimination tree, postorder and column counts follow from the quotient's
+// (counts weighted by class sizes): the t-th member of class v has eta =
+// W_v - t with W_v the weighted count of v, its parent is the next member,
+// and the last member's parent is the first member of v's parent class.
+// That is the exact structure of P A P^T when the classes are
+// indistinguishable, and otherwise the structure of the class-expanded
+// pattern (every member's row the union of its class's rows), whose extra
+// entries the factorization stores as exact zeros.  The full lower adjacency
+// is built once, for the candidate that is kept.
+Ordered order_candidate(const Pattern& A, const Condensed* C, int method, int leaf) {
+  if (!C) return order_and_count(A, dissection(A, method, leaf));
+  const Pattern& Q = C->Q;
   const int qleaf = std::max(1, (int)(leaf * (int64_t)Q.n / std::max<int64_t>(1, A.n)));
-  std::vector<int32_t> pq = method == 1 ? nested_dissection(Q, qleaf) : levelset_dissection(Q, qleaf);
-  std::vector<int32_t> perm;
-  perm.reserve(A.n);
-  for (int32_t c : pq)
-    for (int32_t k = cptr[c]; k < cptr[c + 1]; ++k) perm.push_back(cmem[k]);
-  return perm;
+  std::vector<int32_t> pq = dissection(Q, method, qleaf);
+  Ordered Oq = order_and_count(Q, pq, &C->size);
+  const int64_t nq = Q.n, n = A.n;
+  std::vector<int64_t> off(nq + 1, 0);
+  for (int64_t k = 0; k < nq; ++k) off[k + 1] = off[k] + C->size[Oq.perm[k]];
+  Ordered O;
+  O.perm.resize(n);
+  O.pinv.resize(n);
+  O.parent.resize(n);
+  O.colcount.resize(n);
+  for (int64_t k = 0; k < nq; ++k) {
+    const int32_t c = Oq.perm[k];
+    const int64_t b = C->size[c];
+    for (int64_t t = 0; t < b; ++t) {
+      const int64_t j = off[k] + t;
+      O.perm[j] = C->cmem[C->cptr[c] + t];
+      O.parent[j] = t + 1 < b ? (int32_t)(j + 1) : (Oq.parent[k] < 0 ? -1 : (int32_t)off[Oq.parent[k]]);
+      O.colcount[j] = Oq.colcount[k] - t;
+    }
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    O.pinv[O.perm[j]] = (int32_t)j;
+    O.nnzL += O.colcount[j];
+    O.flops += O.colcount[j] * O.colcount[j];
+  }
+  return O;
 }
 
 }  // namespace
+
+// Pattern with every member's row replaced by the union of its class's rows
+// (classes adjacent in the quotient become dense blocks).
+Pattern expand_classes(const Pattern& A, const Condensed& C) {
+  Pattern B;
+  B.n = A.n;
+  B.rowptr.assign(A.n + 1, 0);
+  const int64_t nq = C.Q.n;
+  std::vector<int32_t> row;
+  std::vector<std::vector<int32_t>> rows(nq);
+  for (int64_t c = 0; c < nq; ++c) {
+    row.clear();
+    for (int64_t k = C.Q.rowptr[c]; k < C.Q.rowptr[c + 1]; ++k) {
+      const int32_t u = C.Q.colind[k];
+      row.insert(row.end(), C.cmem.begin() + C.cptr[u], C.cmem.begin() + C.cptr[u + 1]);
+    }
+    std::sort(row.begin(), row.end());
+    rows[c] = row;
+    for (int32_t q = C.cptr[c]; q < C.cptr[c + 1]; ++q) B.rowptr[C.cmem[q] + 1] = (int64_t)row.size();
+  }
+  for (int64_t i = 0; i < A.n; ++i) B.rowptr[i + 1] += B.rowptr[i];
+  B.colind.resize(B.rowptr[A.n]);
+  for (int64_t c = 0; c < nq; ++c)
+    for (int32_t q = C.cptr[c]; q < C.cptr[c + 1]; ++q)
+      std::copy(rows[c].begin(), rows[c].end(), B.colind.begin() + B.rowptr[C.cmem[q]]);
+  return B;
+}
+
+// One system's order: the requested dissection, or both candidates run
+// concurrently (they share only the read-only pattern) and the one with
+// fewer flops kept; `used` receives the method.  With a condensed graph whose
+// classes are not indistinguishable, the result (counts and lower adjacency)
+// describes the class-expanded pattern.
+Ordered choose_order(const Pattern& A, const SymOptions& opt, int& used) {
+  Condensed C;
+  std::string err;
+  const bool cond = condense(A, opt, C, err);
+  if (!err.empty()) throw std::invalid_argument(err);
+  const Condensed* cp = cond ? &C : nullptr;
+  Ordered O;
+  if (opt.ordering == 1 || opt.ordering == 2) {
+    used = opt.ordering;
+    O = order_candidate(A, cp, opt.ordering, opt.nd_leaf_size);
+  } else {
+    Ordered O2;
+    std::exception_ptr failed;
+    std::thread t2([&] {
+      try {
+        O2 = order_candidate(A, cp, 2, opt.nd_leaf_size);
+      } catch (...) {
+        failed = std::current_exception();
+      }
+    });
+    try {
+      O = order_candidate(A, cp, 1, opt.nd_leaf_size);
+    } catch (...) {
+      t2.join();
+      throw;
+    }
+    t2.join();
+    if (failed) std::rethrow_exception(failed);
+    used = 1;
+    if (O2.flops < O.flops) {
+      used = 2;
+      O = std::move(O2);
+    }
+  }
+  if (cond && !C.exact) {
+    lower_by_column(expand_classes(A, C), O.pinv, O.lptr, O.lind);
+  } else if (O.lptr.empty()) {
+    lower_by_column(A, O.pinv, O.lptr, O.lind);
+  }
+  return O;
+}
 
 int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
   const Pattern& A = S.A;
@@ -446,35 +666,56 @@ int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
 
   // 1. fill-reducing order: nested dissection (multilevel and/or level
   // structure), composed with an etree postorder; with both candidates the
-  // one with fewer factorization flops is kept.
+  // one with fewer factorization flops is kept.  The systems of a batch are
+  // ordered one by one, exactly as each would be alone, so that a system's
+  // ordering (and with it every later result) does not depend on the other
+  // systems; their postordered orders concatenated are a postorder of the
+  // block-diagonal union, which order_and_count keeps as it is.
   Ordered O;
-  if (opt.ordering == 1 || opt.ordering == 2) {
-    O = order_and_count(A, dissect(A, opt.ordering, opt.nd_leaf_size));
-    S.ordering_used = opt.ordering;
-  } else {
-    // both candidates, concurrently (they share only the read-only pattern)
-    Ordered O2;
+  if (S.nsys > 1) {
+    const int64_t nsys = S.nsys;
+    std::vector<std::vector<int32_t>> sub_perm(nsys);
+    std::vector<int> sub_used(nsys, 0);
+    std::atomic<int64_t> next{0};
     std::exception_ptr failed;
-    std::thread t2([&] {
-      try {
-        O2 = order_and_count(A, dissect(A, 2, opt.nd_leaf_size));
-      } catch (...) {
-        failed = std::current_exception();
+    std::mutex failed_mu;
+    auto worker = [&]() {
+      for (int64_t k = next++; k < nsys; k = next++) {
+        try {
+          const int64_t r0 = S.sys_ptr[k], r1 = S.sys_ptr[k + 1];
+          Pattern Ak;
+          Ak.n = r1 - r0;
+          Ak.rowptr.resize(Ak.n + 1);
+          const int64_t q0 = A.rowptr[r0];
+          for (int64_t i = 0; i <= Ak.n; ++i) Ak.rowptr[i] = A.rowptr[r0 + i] - q0;
+          Ak.colind.resize(A.rowptr[r1] - q0);
+          for (int64_t q = q0; q < A.rowptr[r1]; ++q) Ak.colind[q - q0] = (int32_t)(A.colind[q] - r0);
+          Ordered Ok = choose_order(Ak, opt, sub_used[k]);
+          sub_perm[k] = std::move(Ok.perm);
+        } catch (...) {
+          std::lock_guard<std::mutex> g(failed_mu);
+          if (!failed) failed = std::current_exception();
+        }
       }
-    });
-    try {
-      O = order_and_count(A, dissect(A, 1, opt.nd_leaf_size));
-    } catch (...) {
-      t2.join();
-      throw;
-    }
-    t2.join();
+    };
+    const int nw = (int)std::max<int64_t>(1, std::min<int64_t>(
+        nsys, std::max(1u, std::thread::hardware_concurrency()) / 2));
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nw; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto& t : pool) t.join();
     if (failed) std::rethrow_exception(failed);
-    S.ordering_used = 1;
-    if (O2.flops < O.flops) {
-      O = std::move(O2);
-      S.ordering_used = 2;
+    std::vector<int32_t> perm;
+    perm.reserve(n);
+    int used_mask = 0;
+    for (int64_t k = 0; k < nsys; ++k) {
+      for (int32_t v : sub_perm[k]) perm.push_back((int32_t)(v + S.sys_ptr[k]));
+      used_mask |= sub_used[k] > 0 ? 1 << (sub_used[k] - 1) : 0;
     }
+    O = order_and_count(A, perm);
+    S.ordering_used = used_mask;  // 1, 2, or 3 when the systems used both methods
+  } else {
+    O = choose_order(A, opt, S.ordering_used);
   }
   S.perm = std::move(O.perm);
   S.pinv = std::move(O.pinv);

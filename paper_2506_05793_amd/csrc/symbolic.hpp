@@ -13,6 +13,12 @@ namespace tacho {
 struct SymOptions {
   int nd_leaf_size = 8;
   int ordering = 0;  // 0: the better of 1 and 2 (fewer flops), 1: multilevel ND, 2: level-structure ND
+  // condensed graph: 0 indistinguishable vertices, 1 none, b >= 2 blocks of b
+  // consecutive rows; dof_map (n entries, condensed vertex of each row)
+  // overrides dof_block
+  int dof_block = 0;
+  const int32_t* dof_map = nullptr;
+  int64_t dof_map_n = 0;
 };
 
 // Pattern of the full symmetric matrix, validated, diagonal present.

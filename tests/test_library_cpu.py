@@ -149,6 +149,39 @@ def test_batch_is_block_diagonal_union():
     assert sorted(alone.tolist()) == sorted(a.colcount.tolist())
 
 
+def _dense_spd(n, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n))
+    return gen.dense_to_csr(M @ M.T + n * np.eye(n))
+
+
+@pytest.mark.parametrize("mix", ["grids", "grids_and_dense", "landice_and_grids"])
+def test_batch_orders_each_system_as_alone(mix):
+    """A system's symbolic result does not depend on the other systems of a
+    batch: its block of the batch permutation, its elimination tree, column
+    counts and supernodes equal those of the system analysed alone (a dense
+    system, whose rows all compress into one indistinguishable class, and a
+    multi-DOF mesh are the cases where ordering the union would differ)."""
+    mats = gen.batch_fv3d(3, seed=12, lo=5, hi=9)
+    if mix == "grids_and_dense":
+        mats = [mats[0], _dense_spd(90, 2), mats[1], mats[2]]
+    elif mix == "landice_and_grids":
+        mats = [gen.landice(7, 6, 3, seed=5), mats[0], mats[1]]
+    s = T.tacho_analyze_batch([(m.n, m.rowptr, m.colind) for m in mats])
+    a = T.tacho_get_symbolic(s)
+    off, soff = 0, 0
+    for m in mats:
+        b = T.tacho_get_symbolic(T.tacho_analyze(m.n, m.rowptr, m.colind))
+        np.testing.assert_array_equal(a.perm[off:off + m.n] - off, b.perm)
+        par = a.parent[off:off + m.n]
+        np.testing.assert_array_equal(np.where(par < 0, -1, par - off), b.parent)
+        np.testing.assert_array_equal(a.colcount[off:off + m.n], b.colcount)
+        ns = b.super_ptr.size - 1
+        np.testing.assert_array_equal(a.super_ptr[soff:soff + ns + 1] - off, b.super_ptr)
+        off += m.n
+        soff += ns
+
+
 @pytest.mark.parametrize("ordering", [0, 1, 2])
 def test_indistinguishable_dofs_stay_consecutive(ordering):
     """Both DOFs of a mesh node have equal pattern rows; the ordering works on
@@ -159,6 +192,81 @@ def test_indistinguishable_dofs_stay_consecutive(ordering):
     pinv[a.perm] = np.arange(A.n)
     assert np.all(pinv[1::2] == pinv[0::2] + 1)
 
+
+
+@pytest.mark.parametrize("ordering", [0, 1, 2])
+def test_condensed_block_size(ordering):
+    """dof_block = 2 on the 2-DOF land-ice mesh: the ordering runs on the node
+    graph, the elimination tree and column counts come from the condensed
+    graph (weighted), and the symbolic result is still bit-exact against the
+    oracle and equal to the automatic detection of indistinguishable rows."""
+    A = gen.landice(9, 8, 4, seed=3)
+    s, a, q = symbolic_matches_oracle(A, T.tacho_default_options(ordering=ordering, dof_block=2))
+    auto = T.tacho_get_symbolic(T.tacho_analyze(A.n, A.rowptr, A.colind,
+                                                T.tacho_default_options(ordering=ordering)))
+    np.testing.assert_array_equal(a.perm, auto.perm)
+    pinv = np.empty(A.n, np.int64)
+    pinv[a.perm] = np.arange(A.n)
+    assert np.all(pinv[1::2] == pinv[0::2] + 1)
+
+
+@pytest.mark.parametrize("case", ["pairs", "triples_ragged"])
+def test_condensed_user_map(case):
+    """A user DOF map whose groups are not indistinguishable (neighbouring grid
+    cells): the groups stay consecutive in the order and the structure is that
+    of the class-expanded pattern (each group's rows replaced by their union),
+    checked against the oracle's symbolic analysis of that pattern.  A map
+    whose groups are indistinguishable (the land-ice node pairs given
+    explicitly) gives the exact structure of A."""
+    import scipy.sparse as sp
+    A = gen.fv3d(9, 8, 7, seed=2)
+    if case == "pairs":
+        dmap = np.arange(A.n) // 2
+    else:  # groups of 3, the last one ragged, ids permuted
+        ids = np.arange(A.n) // 3
+        relabel = np.random.default_rng(1).permutation(ids.max() + 1)
+        dmap = relabel[ids]
+    # class-expanded pattern: G^T (G |A| G^T) G with G the group incidence
+    G = sp.csr_matrix((np.ones(A.n), (dmap, np.arange(A.n))))
+    Q = (G @ abs(A.to_scipy()) @ G.T)
+    E = (G.T @ Q @ G).tocsr()
+    E.data[:] = 1.0
+    E.sort_indices()
+    Abar = gen.matrices._from_scipy(E)
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(dof_map=dmap))
+    a = T.tacho_get_symbolic(s)
+    import oracle
+    parent, counts = oracle.symbolic(Abar, a.perm)
+    np.testing.assert_array_equal(a.parent, parent)
+    np.testing.assert_array_equal(a.colcount, counts)
+    pinv = np.empty(A.n, np.int64)
+    pinv[a.perm] = np.arange(A.n)
+    for g in np.unique(dmap):
+        pos = np.sort(pinv[dmap == g])
+        assert pos[-1] - pos[0] == pos.size - 1, g
+    L = gen.landice(7, 6, 3, seed=4)
+    symbolic_matches_oracle(L, T.tacho_default_options(dof_map=np.arange(L.n) // 2))
+
+
+def test_condensed_options_rejected():
+    A = gen.fv3d(5, 4, 3, seed=1)  # n = 60
+    for bad in ({"dof_block": 7}, {"dof_block": -1},
+                {"dof_map": np.full(A.n, A.n, np.int32)},          # id out of range
+                {"dof_map": np.arange(A.n) * 2},                   # unused ids
+                {"dof_map": np.arange(A.n - 1)}):                  # wrong length
+        if "dof_map" in bad and len(bad["dof_map"]) != A.n:
+            # the binding passes a pointer; the library reads n entries, so a
+            # short array is the caller's error the binding must catch
+            with pytest.raises(ValueError):
+                T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**bad))
+            continue
+        with pytest.raises(T.TachoError):
+            T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(**bad))
+    with pytest.raises(T.TachoError):
+        T.tacho_analyze_batch([(A.n, A.rowptr, A.colind)] * 2,
+                              T.tacho_default_options(dof_map=np.arange(A.n) // 2))
+    # no condensation at all: still exact
+    symbolic_matches_oracle(gen.landice(6, 5, 3, seed=2), T.tacho_default_options(dof_block=1))
 
 
 def test_plan_parameters_accepted_and_reserved_rejected():
@@ -181,17 +289,77 @@ def test_plan_parameters_accepted_and_reserved_rejected():
 def test_tuning_table_roundtrip(tmp_path):
     from paper_2506_05793_amd import autotune
     key = autotune.workload_key(262144, 1810432)
-    assert key == autotune.workload_key(262144, 1810432, 1, T.TACHO_FP64)
-    assert key != autotune.workload_key(262144, 1810432, 1, T.TACHO_FP32)
+    assert key == "n~2^18/deg7/fp64" == autotune.workload_key(262144, 1810432, T.TACHO_FP64)
+    assert autotune.workload_key(262144, 1810432, T.TACHO_FP32) == "n~2^18/deg7/fp32"
+    assert autotune.workload_key(880000, 44342896) == "n~2^20/deg50/fp64"
+    assert autotune.workload_key(370727, 100) == "n~2^18/deg0/fp64"   # 2^18.5 = 370727.6
+    assert autotune.workload_key(370728, 100) == "n~2^19/deg0/fp64"
     path = str(tmp_path / "t.json")
     tab = autotune.TuningTable(path)
     assert tab.get(key) is None
-    tab.put(key, {"u_range": 16, "chain_min": 4}, {"factor_ms": 1.0})
+    autotune.store(tab, 262144, 1810432, T.TACHO_FP64,
+                   {"u_range": 16, "chain_min": 4, "chain_inplace": -1, "asm_cols": 4,
+                    "solo_m": 128, "solve_level_fronts": 64}, {"factor_ms": 1.0}, order_too=True)
     tab.save()
-    assert autotune.TuningTable(path).get(key) == {"u_range": 16, "chain_min": 4}
-    opt = autotune.options_for(262144, 1810432, table=path, asm_cols=4)
-    assert (opt.u_range, opt.chain_min, opt.asm_cols) == (16, 4, 4)
-    assert autotune.options_for(1000, 5000, table=path).u_range == 0  # library default
+    assert autotune.TuningTable(path).get(key) == {"asm_cols": 4, "solo_m": 128,
+                                                   "solve_level_fronts": 64}
+    assert autotune.TuningTable(path).get("order/fp64") == {"u_range": 16, "chain_min": 4,
+                                                            "chain_inplace": -1}
+    assert autotune.tuned_params(1000, 5000, table=path) == {"u_range": 16, "chain_min": 4,
+                                                             "chain_inplace": -1}
+    assert autotune.tuned_params(1000, 5000, T.TACHO_FP32, table=path) == {}
+
+
+def _plan_of(sym):
+    q = T.tacho_query_symbolic(sym)
+    return {k: q["plan_" + k] for k in ("u_range", "chain_min", "solve_level_fronts", "asm_cols",
+                                       "solo_m", "chain_inplace")}
+
+
+def test_library_reads_tuning_table(tmp_path):
+    """The library's own table reader resolves the same parameters as the
+    Python table for the workload class and precision; explicit options win;
+    a malformed or missing table is an error; a system alone and the batch it
+    is part of get the same order-changing parameters."""
+    import json
+    from paper_2506_05793_amd import autotune
+    A = gen.fv3d(12, 11, 10, seed=7)
+    path = str(tmp_path / "t.json")
+    entries = {
+        autotune.workload_key(A.n, A.nnz, T.TACHO_FP64):
+            {"params": {"asm_cols": 16, "solo_m": 320, "solve_level_fronts": 64}, "info": {"x": [1, 2]}},
+        autotune.workload_key(A.n, A.nnz, T.TACHO_FP32):
+            {"params": {"asm_cols": 4, "solo_m": -1, "solve_level_fronts": 1024}, "info": {}},
+        "order/fp64": {"params": {"u_range": 4, "chain_min": 6, "chain_inplace": -1}, "info": {}},
+        "order/fp32": {"params": {"u_range": 16, "chain_min": -1, "chain_inplace": 0},
+                       "info": {"note": "a \"quoted\" note", "v": 1.5e-3, "ok": True, "n": None}},
+    }
+    json.dump(entries, open(path, "w"))
+    defaults = _plan_of(T.tacho_analyze(A.n, A.rowptr, A.colind))
+    assert defaults == {"u_range": 8, "chain_min": 3, "solve_level_fronts": 256, "asm_cols": 8,
+                        "solo_m": 192, "chain_inplace": 1}
+    for prec in (T.TACHO_FP64, T.TACHO_FP32):
+        want = dict(defaults)
+        want.update(autotune.tuned_params(A.n, A.nnz, prec, table=path))
+        want["chain_inplace"] = 1 if want["chain_inplace"] >= 0 else -1
+        s = T.tacho_analyze(A.n, A.rowptr, A.colind, autotune.options_for(A.n, A.nnz, prec, table=path))
+        assert _plan_of(s) == want, prec
+    s = T.tacho_analyze(A.n, A.rowptr, A.colind,
+                        autotune.options_for(A.n, A.nnz, T.TACHO_FP64, table=path, chain_min=2))
+    assert _plan_of(s)["chain_min"] == 2 and _plan_of(s)["u_range"] == 4
+    # alone and batched: same order-changing parameters
+    mats = gen.batch_fv3d(4, seed=3, lo=5, hi=8)
+    sb = T.tacho_analyze_batch([(m.n, m.rowptr, m.colind) for m in mats],
+                               autotune.options_for(1, 1, T.TACHO_FP64, table=path))
+    s1 = T.tacho_analyze(mats[0].n, mats[0].rowptr, mats[0].colind,
+                         autotune.options_for(1, 1, T.TACHO_FP64, table=path))
+    for k in autotune.ORDER_CHANGING:
+        assert _plan_of(sb)[k] == _plan_of(s1)[k]
+    bad = str(tmp_path / "bad.json")
+    open(bad, "w").write('{"order/fp64": {"params": {"u_range": 2.5}}}')
+    for p in (bad, str(tmp_path / "missing.json")):
+        with pytest.raises(T.TachoError):
+            T.tacho_analyze(A.n, A.rowptr, A.colind, T.tacho_default_options(autotune_path=p))
 
 
 def test_binding_rejects_bad_arguments():
