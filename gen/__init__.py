@@ -17,4 +17,5 @@ from .matrices import (  # noqa: F401
     random_spd_pattern,
     csr_block_diag,
     serving_requests,
+    shifted,
 )

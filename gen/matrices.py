@@ -272,6 +272,14 @@ def serving_requests(count: int = 2000, seed: int = 5, rate: float = 100.0,
     return out
 
 
+def shifted(A: CSR, frac: float) -> CSR:
+    """Symmetric indefinite A - sigma I with sigma = frac * mean(diag(A)) (a
+    Helmholtz-like shift into the spectrum of an SPD operator); same pattern."""
+    M = A.to_scipy().tocsr()
+    sigma = frac * float(M.diagonal().mean())
+    return _from_scipy((M - sigma * sp.identity(A.n, format="csr")).tocsr())
+
+
 def laplace3d(m: int) -> CSR:
     """7-point Dirichlet Laplacian on an m^3 grid, stencil 6 / -1, natural order."""
     T = sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])

@@ -43,6 +43,7 @@ extern "C" {
 #define TACHO_ERR_NOT_SPD (-3) /* non-positive or NaN pivot */
 #define TACHO_ERR_NOMEM (-4)   /* out of device memory or over the HBM budget */
 #define TACHO_ERR_HIP (-5)     /* a HIP runtime call failed */
+#define TACHO_ERR_SINGULAR (-6) /* LDL^T: a diagonal block has no usable pivot */
 
 /* Precision of the numeric factorization (the paper's templated scalar
  * types, Trilinos section, and iterative refinement with computed factors,
@@ -50,6 +51,19 @@ extern "C" {
 #define TACHO_FP64 0    /* FP64 fronts, FP64 solves */
 #define TACHO_FP32_IR 1 /* FP32 fronts; tacho_solve refines in FP64 */
 #define TACHO_FP32 TACHO_FP32_IR
+/* Symmetric indefinite LDL^T in FP64 (Tacho section: besides Cholesky, an
+ * LDL^T factorization of a symmetric indefinite matrix, with pivots searched
+ * only within each diagonal block).  P A P^T = Q L D L^T Q^T: L unit lower
+ * triangular with the supernodal structure of the Cholesky factor, D block
+ * diagonal with 1x1 and 2x2 blocks, Q a permutation that moves a column only
+ * within its diagonal block (the pivot columns of a supernode, cut into
+ * blocks of at most 64 columns; 2x2 blocks never straddle two of them).
+ * Pivots by Bunch-Kaufman partial pivoting, alpha = (1 + sqrt 17) / 8, with
+ * the candidate rows and columns limited to the block's columns not yet
+ * eliminated; ties go to the smallest index.  A block without a usable pivot
+ * gives TACHO_ERR_SINGULAR.  Solves use the same sweeps as Cholesky with D^{-1}
+ * applied between them; no refinement. */
+#define TACHO_LDLT 2
 
 /* Test hooks (tacho_options.debug_flags). */
 #define TACHO_DEBUG_SOLVE_GIVE_UP 1 /* every solve raises its own hang flag before its
@@ -246,7 +260,7 @@ int tacho_get_symbolic(tacho_sym_t sym, int32_t *perm, int32_t *parent, int64_t 
  *                     only entries with row >= column are read, numerical
  *                     symmetry is the caller's contract
  *   values_on_device  0: host pointer; 1: device pointer used on hip_stream
- *   precision         TACHO_FP64 or TACHO_FP32
+ *   precision         TACHO_FP64, TACHO_FP32 or TACHO_LDLT
  *   out               receives the numeric handle, which owns the device factor
  *   fail_index        optional; on TACHO_ERR_NOT_SPD receives the original
  *                     index of the first column (in elimination order) whose
@@ -328,6 +342,18 @@ int tacho_solve(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64
  * values (the one the solves fall back to) is returned.
  */
 int tacho_get_factor(tacho_num_t num, int64_t *Lp, int32_t *Li, double *Lx);
+
+/*
+ * D and the pivot order of a TACHO_LDLT factorization (any pointer may be
+ * NULL; host arrays of n entries, permuted numbering of P A P^T):
+ *   d[k]  diagonal of D
+ *   e[k]  subdiagonal of D: nonzero exactly at the first column k of a 2x2
+ *         pivot block (coupling k and k + 1), zero elsewhere
+ *   q[i]  row i of L is row q[i] of P A P^T (q permutes within diagonal blocks)
+ * L itself comes from tacho_get_factor (unit diagonal stored explicitly; the
+ * entry below the first column of a 2x2 pivot is zero).  Synchronizes.
+ */
+int tacho_get_ldlt(tacho_num_t num, double *d, double *e, int32_t *q);
 
 /* Device milliseconds of the last factorization and solve (hipEvent timing on the
  * caller's stream; valid once that work has finished). */

@@ -24,9 +24,11 @@ TACHO_ERR_PATTERN = -2
 TACHO_ERR_NOT_SPD = -3
 TACHO_ERR_NOMEM = -4
 TACHO_ERR_HIP = -5
+TACHO_ERR_SINGULAR = -6
 TACHO_FP64 = 0
 TACHO_FP32_IR = 1
 TACHO_FP32 = TACHO_FP32_IR
+TACHO_LDLT = 2
 TACHO_DEBUG_SOLVE_GIVE_UP = 1
 TACHO_PROFILE_KINDS = 11
 
@@ -122,6 +124,7 @@ def _load():
         "tacho_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                        _vp, ctypes.POINTER(tacho_solve_info)]),
         "tacho_get_factor": (ctypes.c_int, [_vp, _i64p, _i32p, _f64p]),
+        "tacho_get_ldlt": (ctypes.c_int, [_vp, _f64p, _f64p, _i32p]),
         "tacho_last_times": (ctypes.c_int, [_vp, _f64p, _f64p]),
         "tacho_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
         "tacho_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, _i64p, _f64p, _f64p, _f64p]),
@@ -432,6 +435,19 @@ def tacho_get_factor(num: NumericHandle):
     _check(_load().tacho_get_factor(num.ptr, Lp.ctypes.data_as(_i64p), Li.ctypes.data_as(_i32p),
                                     Lx.ctypes.data_as(_f64p)))
     return Lp, Li[:nnz], Lx[:nnz]
+
+
+def tacho_get_ldlt(num: NumericHandle):
+    """(d, e, q) of a TACHO_LDLT factorization: diagonal and subdiagonal of D
+    (e nonzero at the first column of each 2x2 pivot) and the pivot order
+    (row i of L is row q[i] of P A P^T)."""
+    n = max(num.sym.n, 0)
+    d = np.empty(max(n, 1), np.float64)
+    e = np.empty(max(n, 1), np.float64)
+    q = np.empty(max(n, 1), np.int32)
+    _check(_load().tacho_get_ldlt(num.ptr, d.ctypes.data_as(_f64p), e.ctypes.data_as(_f64p),
+                                  q.ctypes.data_as(_i32p)))
+    return d[:n], e[:n], q[:n]
 
 
 def tacho_last_times(num: NumericHandle):

@@ -18,6 +18,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/tacho.h"
@@ -72,11 +73,47 @@ struct DBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// The library's own host transfers (symbolic uploads, counter clearing) run
+// on a private non-blocking stream per device and wait for it, never on the
+// legacy default stream: a legacy-stream operation is refused while another
+// thread captures a graph on a blocking stream.
+hipError_t aux_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev]) {
+    e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  *out = streams[dev];
+  return hipSuccess;
+}
+
+hipError_t copy_to_device(void* dst, const void* src, size_t bytes) {
+  hipStream_t st = nullptr;
+  hipError_t e = aux_stream(&st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
+hipError_t clear_device(void* dst, size_t bytes) {
+  hipStream_t st = nullptr;
+  hipError_t e = aux_stream(&st);
+  if (e == hipSuccess) e = hipMemsetAsync(dst, 0, bytes, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
 template <typename T>
 hipError_t upload(DBuf& d, const std::vector<T>& v) {
   hipError_t e = d.alloc(v.size() * sizeof(T));
   if (e != hipSuccess) return e;
-  if (!v.empty()) e = hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (!v.empty()) e = copy_to_device(d.p, v.data(), v.size() * sizeof(T));
   return e;
 }
 
@@ -101,6 +138,12 @@ struct tacho_sym {
   DBuf d_rowptr, d_colind, d_mirror, d_sys_ptr;
   DevSym view{};
   std::mutex mu;
+  // LDL^T runs the stepwise large-front launches (diagonal block, panel,
+  // trailing updates): their plan, built on the first LDL^T factorization,
+  // and the device view with that plan's assembly ranges
+  std::unique_ptr<Plan> P1;
+  DBuf d1_small, d1_asm, d1_asm_rng, d1_diag, d1_panel, d1_probs, d1_tiles;
+  DevSym view1{};
 };
 
 // Per-launch timing of the library's kernels on the caller's stream (hipEvents
@@ -190,6 +233,7 @@ struct tacho_num {
   DBuf flow;                // dataflow factorization counters, flags, tickets, hang flag
   DBuf bdev, xdev;          // host-pointer staging
   DBuf rws;                 // refinement scratch (residual, norms, mask)
+  DBuf ld_d, ld_e, ld_q, ld_qinv, ld_perm, ld_pinv, ld_panels;  // LDL^T: D, pivot orders, L D panels
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool pending = false;     // factorization queued, flag not yet read
   int last_status = TACHO_OK;
@@ -409,7 +453,38 @@ int ensure_uploaded(tacho_sym* h) {
   return TACHO_OK;
 }
 
+// The stepwise launch plan that LDL^T factorizations run (built once per
+// symbolic handle, with the same batching parameters).
+int ensure_stepwise(tacho_sym* h) {
+  std::lock_guard<std::mutex> lock(h->mu);
+  if (h->P1) return TACHO_OK;
+  std::unique_ptr<Plan> P1(new Plan());
+  std::string err;
+  if (build_plan(h->S, *P1, err, 1, h->tune) != kOk) return fail(TACHO_ERR_INVALID, err);
+  // the rest of the device view (layout of L, U and the diagonal-block
+  // inverses) is shared with the Cholesky plan
+  if (P1->wbase != h->P.wbase || P1->woff != h->P.woff || P1->U_off != h->P.U_off ||
+      P1->L_off != h->P.L_off)
+    return fail(TACHO_ERR_INVALID, "stepwise plan does not share the factor layout");
+  HIP_TRY(upload(h->d1_small, P1->small_list));
+  HIP_TRY(upload(h->d1_asm, P1->asm_items));
+  HIP_TRY(upload(h->d1_asm_rng, P1->asm_rng));
+  HIP_TRY(upload(h->d1_diag, P1->diag_items));
+  HIP_TRY(upload(h->d1_panel, P1->panel_items));
+  HIP_TRY(upload(h->d1_probs, P1->probs));
+  HIP_TRY(upload(h->d1_tiles, P1->tiles));
+  // the stepwise plan's assembly items index its own child column ranges
+  h->view1 = h->view;
+  h->view1.asm_rng = h->d1_asm_rng.as<int32_t>();
+  h->P1 = std::move(P1);
+  return TACHO_OK;
+}
+
 size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
+
+bool valid_precision(int precision) {
+  return precision == TACHO_FP64 || precision == TACHO_FP32 || precision == TACHO_LDLT;
+}
 
 // Device bytes a numeric handle needs (factor, update workspace, values,
 // solve workspace for kRhs columns).
@@ -418,7 +493,7 @@ size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
 // one ticket counter per level, one hang flag.
 int64_t flow_ntiles(const tacho_sym* h) { return h->P.tbase.empty() ? 0 : h->P.tbase.back(); }
 int64_t flow_ints(const tacho_sym* h) {
-  return flow_ntiles(h) + (int64_t)h->P.woff.size() + h->P.nucount + h->S.nlevels + 1;
+  return flow_ntiles(h) + (int64_t)h->P.woff.size() + h->P.nucount + h->P.front_launches + 1;
 }
 
 // Dataflow solves: three completion counters per supernode, one
@@ -440,6 +515,7 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += 4 * (solve_counters(h) + 1);
   b += 4 * flow_ints(h);
   if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;  // values, scaling
+  if (precision == TACHO_LDLT) b += 8 * h->P.L_elems + 16 * S.n + 16 * S.n;    // L D, D, orders
   return b;
 }
 
@@ -486,7 +562,8 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
     switch (s.kind) {
       case kStepSmall:
         launch_leaf<T>(S, N, small + s.begin, s.tile, st);
-        launch_small<T>(S, N, small + s.begin + s.tile, cnt - s.tile, st);
+        launch_small<T>(S, N, small + s.begin + s.tile, s.packed - s.begin - s.tile, st);
+        launch_packed<T>(S, N, f->winv.as<T>(), small + s.packed, s.end - s.packed, st);
         break;
       case kStepAssemble: launch_assemble<T>(S, N, asmi + s.begin, cnt, st); break;
       case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, f->winv.as<T>(), st); break;
@@ -494,11 +571,45 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
       case kStepGemm: launch_gemm<T>(N, probs, tiles + s.begin, cnt, s.tile, st); break;
       case kStepFront:
         launch_front<T>(S, N, f->winv.as<T>(), ftasks + s.begin, cnt, f->flow.as<int32_t>(), ntiles,
-                        (int64_t)P.woff.size(), P.nucount, s.level, (int)h->S.nlevels, st);
+                        (int64_t)P.woff.size(), P.nucount, s.ticket, P.front_launches, st);
         break;
     }
     f->prof.end(pe, st, step_kind(s.kind), s.flops, s.elems * sizeof(T));
   }
+}
+
+// LDL^T: the stepwise plan's launches with the LDL^T kernels for the small
+// fronts, the diagonal blocks and the panels; the trailing updates subtract
+// L (L D)^T.
+void run_ldlt_steps(tacho_num* f, hipStream_t st) {
+  tacho_sym* h = f->sym;
+  const DevSym& S = h->view1;
+  const Plan& P = *h->P1;
+  DevNum<double> N = num_view<double>(f);
+  DevLdlt D{f->ld_d.as<double>(), f->ld_e.as<double>(), f->ld_q.as<int32_t>(),
+            f->ld_panels.as<double>()};
+  const int32_t* small = h->d1_small.as<int32_t>();
+  const AsmItem* asmi = h->d1_asm.as<AsmItem>();
+  const PanelItem* dia = h->d1_diag.as<PanelItem>();
+  const PanelItem* pan = h->d1_panel.as<PanelItem>();
+  const GemmProb* probs = h->d1_probs.as<GemmProb>();
+  const GemmTile* tiles = h->d1_tiles.as<GemmTile>();
+  launch_iota(D.q, h->S.n, st);
+  for (const Step& s : P.steps) {
+    const int64_t cnt = s.end - s.begin;
+    const int pe = f->prof.begin(st);
+    switch (s.kind) {
+      case kStepSmall: launch_small_ldlt(S, N, D, small + s.begin, cnt, st); break;
+      case kStepAssemble: launch_assemble<double>(S, N, asmi + s.begin, cnt, st); break;
+      case kStepDiag: launch_diag_ldlt(S, N, D, dia + s.begin, cnt, f->winv.as<double>(), st); break;
+      case kStepPanel: launch_panel_ldlt(S, N, D, pan + s.begin, cnt, f->winv.as<double>(), st); break;
+      case kStepGemm: launch_gemm<double>(N, probs, tiles + s.begin, cnt, s.tile, st, D.ld); break;
+      default: break;
+    }
+    f->prof.end(pe, st, step_kind(s.kind), s.flops, s.elems * sizeof(double));
+  }
+  launch_ldlt_perm(h->S.n, h->d_perm.as<int32_t>(), D.q, f->ld_perm.as<int32_t>(),
+                   f->ld_pinv.as<int32_t>(), f->ld_qinv.as<int32_t>(), st);
 }
 
 int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, int sync,
@@ -508,7 +619,7 @@ int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index);
 int read_fail_flag(tacho_num* f, int64_t* fail_index) {
   int32_t flag = INT32_MAX, hang = 0;
   HIP_TRY(hipMemcpyAsync(&flag, f->fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, f->last_stream));
-  if (!f->sym->P.ftasks.empty())
+  if (!f->sym->P.ftasks.empty() && f->precision != TACHO_LDLT)
     HIP_TRY(hipMemcpyAsync(&hang, f->flow.as<int32_t>() + flow_ints(f->sym) - 1, sizeof(int32_t),
                            hipMemcpyDeviceToHost, f->last_stream));
   HIP_TRY(hipStreamSynchronize(f->last_stream));
@@ -530,6 +641,13 @@ int read_fail_flag(tacho_num* f, int64_t* fail_index) {
     if (fail_index) *fail_index = f->last_fail;
     if (rc == TACHO_OK) f->fp32_broken = true;
     return rc;
+  }
+  if (flag != INT32_MAX && f->precision == TACHO_LDLT) {
+    f->last_fail = f->sym->S.perm[flag];
+    f->last_status = TACHO_ERR_SINGULAR;
+    if (fail_index) *fail_index = f->last_fail;
+    return fail(TACHO_ERR_SINGULAR, "no usable pivot within the diagonal block of column " +
+                                        std::to_string(f->last_fail));
   }
   if (flag != INT32_MAX) {
     f->last_fail = f->sym->S.perm[flag];
@@ -566,7 +684,10 @@ void enqueue_factor(tacho_num* f, hipStream_t st) {
     const int pe = f->prof.begin(st);
     launch_gather<double>(h->view, num_view<double>(f), vals, nq, st);
     f->prof.end(pe, st, TACHO_K_GATHER, 0, nq * (8.0 + 8.0 + 8.0));
-    run_factor_steps<double>(f, st);
+    if (f->precision == TACHO_LDLT)
+      run_ldlt_steps(f, st);
+    else
+      run_factor_steps<double>(f, st);
   }
 }
 
@@ -603,7 +724,7 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
     HIP_TRY(hipMemcpyAsync(f->vals.p, values, nv * sizeof(double),
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(f->ev[0], st));
-  if (h->opt.graphs != 0 && !f->prof.on) {
+  if (h->opt.graphs != 0 && !f->prof.on && f->precision != TACHO_LDLT) {
     if (!f->fgraph) {
       const int rc = build_factor_graph(f);
       if (rc != TACHO_OK) return rc;
@@ -644,7 +765,7 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   HIP_TRY(f->uvec.alloc((size_t)kRowBytes * std::max<int64_t>(P.u_elems, 1)));
   HIP_TRY(f->part.alloc(es * std::max<int64_t>(P.part_slots, 1) * kPanel * kRhs));
   HIP_TRY(f->sync.alloc(sizeof(int32_t) * (solve_counters(h) + 1)));
-  HIP_TRY(hipMemset(f->sync.p, 0, sizeof(int32_t) * (solve_counters(h) + 1)));
+  HIP_TRY(clear_device(f->sync.p, sizeof(int32_t) * (solve_counters(h) + 1)));
   HIP_TRY(f->flow.alloc(sizeof(int32_t) * flow_ints(h)));
   if (precision == TACHO_FP32) {
     HIP_TRY(f->scale.alloc(sizeof(double) * S.n));
@@ -652,6 +773,17 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
   }
   for (auto& e : f->ev) HIP_TRY(hipEventCreate(&e));
   if (precision == TACHO_FP32) f->rh.resize(S.nsys * kRhs);
+  if (precision == TACHO_LDLT) {
+    rc = ensure_stepwise(h);
+    if (rc != TACHO_OK) return rc;
+    HIP_TRY(f->ld_d.alloc(sizeof(double) * S.n));
+    HIP_TRY(f->ld_e.alloc(sizeof(double) * S.n));
+    HIP_TRY(f->ld_q.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->ld_qinv.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->ld_perm.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->ld_pinv.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->ld_panels.alloc(sizeof(double) * std::max<int64_t>(P.L_elems, 1)));
+  }
   *out = f.release();
   return TACHO_OK;
 }
@@ -697,7 +829,17 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
                  int accumulate, hipStream_t st) {
   tacho_sym* h = f->sym;
   const Symbolic& S = h->S;
-  const DevSym& V = h->view;
+  // LDL^T: the sweeps apply each block's pivot order (lq, lqinv) to their
+  // front vectors; the result comes out in pivot order, so the output
+  // permutation is P composed with it
+  DevSym Vq = h->view, Vout = h->view;
+  if (f->precision == TACHO_LDLT) {
+    Vq.lq = f->ld_q.as<int32_t>();
+    Vq.lqinv = f->ld_qinv.as<int32_t>();
+    Vout.perm = f->ld_perm.as<int32_t>();
+    Vout.pinv = f->ld_pinv.as<int32_t>();
+  }
+  const DevSym& V = Vq;
   const Plan& P = h->P;
   const double* scale = f->precision == TACHO_FP32 && h->opt.scale_fp32 ? f->scale.as<double>() : nullptr;
   T* y = f->y.as<T>();
@@ -731,6 +873,9 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   launch_solve_fwd<T>(V, L, winv, y, f->uvec.as<T>(), h->d_fsolve.as<SolveTask>(),
                       (int64_t)P.fsolve.size(), waves, nrhs, counters, ns, nblk, hang, st);
   f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
+  if constexpr (std::is_same<T, double>::value)
+    if (f->precision == TACHO_LDLT)
+      launch_apply_dinv(S.n, f->ld_d.as<double>(), f->ld_e.as<double>(), y, nrhs, st);
   pe = f->prof.begin(st);
   launch_solve_bwd<T>(V, L, winv, y, f->part.as<T>(), h->d_bsolve.as<SolveTask>(),
                       (int64_t)P.bsolve.size(), waves, nrhs, counters, ns, nblk, hang, st);
@@ -741,7 +886,7 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
                         hang, st);
   f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
   pe = f->prof.begin(st);
-  launch_solve_out<T>(V, y, x, ldx, nrhs, scale, accumulate, st);
+  launch_solve_out<T>(Vout, y, x, ldx, nrhs, scale, accumulate, st);
   f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
 }
 
@@ -758,19 +903,22 @@ void solve_all(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t ld
 // (2 x units) and a per-unit byte mask.
 struct RefineScratch {
   double* r = nullptr;
+  double* xt = nullptr;  // the iterate by rows (several right-hand sides)
   double* nrm = nullptr;
   uint8_t* mask = nullptr;
 };
 
 int64_t refine_scratch_bytes(int64_t n, int64_t nrhs, int64_t nsys) {
   const int64_t units = nsys * nrhs;
-  return (int64_t)sizeof(double) * (n * nrhs + 2 * units) + units;
+  const int64_t rows = nrhs > 1 ? n * nrhs : 0;
+  return (int64_t)sizeof(double) * (n * nrhs + rows + 2 * units) + units;
 }
 
 RefineScratch carve_refine_scratch(void* base, int64_t n, int64_t nrhs, int64_t nsys) {
   RefineScratch w;
   w.r = static_cast<double*>(base);
-  w.nrm = w.r + n * nrhs;
+  w.xt = w.r + n * nrhs;
+  w.nrm = w.xt + (nrhs > 1 ? n * nrhs : 0);
   w.mask = reinterpret_cast<uint8_t*>(w.nrm + 2 * nsys * nrhs);
   return w;
 }
@@ -827,7 +975,7 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
   auto residual_norms = [&]() -> int {
     const int pe = f->prof.begin(st);
     launch_residual(n, h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(),
-                    f->fullvals.as<double>(), b, n, x, n, r, nrhs, st);
+                    f->fullvals.as<double>(), b, n, x, n, r, nrhs, ws.xt, st);
     launch_segnorms(nsys, sysp, r, n, nrhs, nrm, st);
     f->prof.end(pe, st, TACHO_K_REFINE, (2.0 * nnz + 2.0 * n) * nrhs,
                 nnz * 12.0 + 8.0 * n + 8.0 * 3.0 * n * nrhs);
@@ -932,6 +1080,7 @@ const char* tacho_strerror(int code) {
     case TACHO_ERR_NOT_SPD: return "matrix is not positive definite";
     case TACHO_ERR_NOMEM: return "out of device memory or over the HBM budget";
     case TACHO_ERR_HIP: return "HIP runtime error";
+    case TACHO_ERR_SINGULAR: return "no usable pivot within a diagonal block";
     default: return "unknown error";
   }
 }
@@ -1057,8 +1206,7 @@ int tacho_factorize(tacho_sym_t h, const double* values, int values_on_device, i
   if (!h || !out) return fail(TACHO_ERR_INVALID, "NULL argument");
   *out = nullptr;
   if (fail_index) *fail_index = -1;
-  if (precision != TACHO_FP64 && precision != TACHO_FP32)
-    return fail(TACHO_ERR_INVALID, "unknown precision");
+  if (!valid_precision(precision)) return fail(TACHO_ERR_INVALID, "unknown precision");
   tacho_num* f = nullptr;
   int rc = create_numeric(h, precision, &f);
   if (rc != TACHO_OK) return rc;
@@ -1074,8 +1222,7 @@ int tacho_factorize(tacho_sym_t h, const double* values, int values_on_device, i
 int tacho_numeric_create(tacho_sym_t h, int precision, tacho_num_t* out) {
   if (!h || !out) return fail(TACHO_ERR_INVALID, "NULL argument");
   *out = nullptr;
-  if (precision != TACHO_FP64 && precision != TACHO_FP32)
-    return fail(TACHO_ERR_INVALID, "unknown precision");
+  if (!valid_precision(precision)) return fail(TACHO_ERR_INVALID, "unknown precision");
   tacho_num* f = nullptr;
   const int rc = create_numeric(h, precision, &f);
   if (rc != TACHO_OK) return rc;
@@ -1112,8 +1259,13 @@ int tacho_check_factor(tacho_num_t f, int64_t* fail_index) {
   return f->last_status;
 }
 
-int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t ld, int on_device,
-                void* hip_stream, tacho_solve_info* info) {
+}  // extern "C"
+
+namespace {
+
+// tacho_solve: device blocks are used in place, host blocks staged.
+int solve_impl(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t ld, int on_device,
+               void* hip_stream, tacho_solve_info* info) {
   if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
   tacho_sym* h = f->sym;
   const int64_t n = h->S.n;
@@ -1124,10 +1276,12 @@ int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t
     info->fell_back = 0;
     info->relres_max = 0;
   }
+  const bool refine = f->precision == TACHO_FP32;
+  const bool dense_ld = ld == n;
   // A factorization queued without waiting is not checked here when the solve
   // stays on the device in FP64: the solve is queued behind it and
   // tacho_check_factor tells whether the result is valid.
-  const bool queue_only = on_device && f->precision == TACHO_FP64;
+  const bool queue_only = on_device && f->precision != TACHO_FP32;
   if (f->pending && !queue_only) {
     int rc = read_fail_flag(f, nullptr);
     if (rc != TACHO_OK) return rc;
@@ -1140,8 +1294,6 @@ int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t
   f->solve_queued = true;
   const double* bd = b;
   double* xd = x;
-  const bool dense_ld = ld == n;
-  const bool refine = f->precision == TACHO_FP32;
   // the refinement path works on dense (ld = n) device blocks
   if (!on_device || (refine && !dense_ld) || (refine && b == x)) {
     const size_t bytes = sizeof(double) * n * nrhs;
@@ -1179,6 +1331,15 @@ int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t
   return TACHO_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t ld, int on_device,
+                void* hip_stream, tacho_solve_info* info) {
+  return solve_impl(f, b, x, nrhs, ld, on_device, hip_stream, info);
+}
+
 int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
   if (!f || !Lp || !Li || !Lx) return fail(TACHO_ERR_INVALID, "NULL argument");
   if (f->pending) {
@@ -1198,17 +1359,59 @@ int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
   for (int32_t s = 0; s < S.ns; ++s)
     for (int32_t j = S.sptr[s]; j < S.sptr[s + 1]; ++j)
       Lp[j + 1] = Lp[j] + (S.front_m[s] - (j - S.sptr[s]));
+  // LDL^T: a front's pivot rows are stored in its pivot order; the rows of
+  // its ancestors keep their analysis numbering and map through the inverse
+  // pivot order (columns re-sorted by row)
+  std::vector<int32_t> qinv;
+  if (f->precision == TACHO_LDLT && S.n > 0) {
+    qinv.resize(S.n);
+    HIP_TRY(hipMemcpy(qinv.data(), f->ld_qinv.p, sizeof(int32_t) * S.n, hipMemcpyDeviceToHost));
+  }
+  std::vector<std::pair<int32_t, double>> col;
   for (int32_t s = 0; s < S.ns; ++s) {
     const int32_t f0 = S.sptr[s], w = S.sptr[s + 1] - f0, m = S.front_m[s];
     for (int32_t c = 0; c < w; ++c) {
-      int64_t q = Lp[f0 + c];
+      const int64_t q0 = Lp[f0 + c];
+      int64_t q = q0;
       for (int32_t i = c; i < m; ++i, ++q) {
         const int64_t off = P.L_off[s] + (int64_t)c * P.ldL[s] + i;
-        Li[q] = S.rows[S.rows_ptr[s] + i];
+        const int32_t row = S.rows[S.rows_ptr[s] + i];
+        Li[q] = qinv.empty() || i < w ? row : qinv[row];
         Lx[q] = f->precision == TACHO_FP32 ? (double)reinterpret_cast<const float*>(host.data())[off]
                                            : reinterpret_cast<const double*>(host.data())[off];
       }
+      if (!qinv.empty()) {
+        col.clear();
+        for (int64_t k = q0; k < q; ++k) col.emplace_back(Li[k], Lx[k]);
+        std::sort(col.begin(), col.end(),
+                  [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                    return a.first < b.first;
+                  });
+        for (int64_t k = q0; k < q; ++k) {
+          Li[k] = col[k - q0].first;
+          Lx[k] = col[k - q0].second;
+        }
+      }
     }
+  }
+  return TACHO_OK;
+}
+
+int tacho_get_ldlt(tacho_num_t f, double* d, double* e, int32_t* q) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  if (f->precision != TACHO_LDLT) return fail(TACHO_ERR_INVALID, "not an LDL^T factorization");
+  if (f->pending) {
+    int rc = read_fail_flag(f, nullptr);
+    if (rc != TACHO_OK) return rc;
+  } else if (f->last_status != TACHO_OK) {
+    return fail(f->last_status, "no valid factor in this handle");
+  }
+  const int64_t n = f->sym->S.n;
+  HIP_TRY(hipDeviceSynchronize());
+  if (n > 0) {
+    if (d) HIP_TRY(hipMemcpy(d, f->ld_d.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (e) HIP_TRY(hipMemcpy(e, f->ld_e.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (q) HIP_TRY(hipMemcpy(q, f->ld_q.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
   }
   return TACHO_OK;
 }

@@ -40,6 +40,14 @@ struct DevSym {
   const int32_t* part_base;  // per diagonal block: first backward partial-product slot
   const int32_t* pt1base;    // per pivot block of a chain front: 64 x 64 product slot (-1: none)
   const int32_t* asm_rng;    // per assembly item and child: child column range
+  // LDL^T solves (nullptr otherwise): pivot order lq (L row i is row lq[i] of
+  // P A P^T; it moves rows only within a diagonal block) and its inverse.  A
+  // front's interchanges act on its own front vector after the children's
+  // contributions arrive, so the forward sweep reads pivot position i from
+  // front row lq[f + i] - f, and the backward sweep finds the solution of an
+  // ancestor's row r at position lqinv[r].
+  const int32_t* lq;
+  const int32_t* lqinv;
 };
 
 template <typename T>
@@ -50,6 +58,18 @@ struct DevNum {
   const double* scale;  // Jacobi scaling per permuted column (FP32 path) or nullptr
   int32_t* fail;    // smallest failing permuted column, INT32_MAX if none
   T* pt1;           // chain products, 64 x 64 per slot (column-major)
+};
+
+// LDL^T factorization outputs (FP64): D as its diagonal d and first
+// subdiagonal e (e[k] != 0 marks a 2x2 pivot on permuted columns k, k + 1),
+// the pivot order q (row i of L is row q[i] of P A P^T; q moves a column only
+// within its diagonal block), and the panels L D of the columns eliminated so
+// far, laid out like L (the trailing updates read them).
+struct DevLdlt {
+  double* d;
+  double* e;
+  int32_t* q;
+  double* ld;
 };
 
 // Host launchers (kernels.hip).
@@ -67,6 +87,9 @@ template <typename T>
 void launch_small(const DevSym& S, const DevNum<T>& N, const int32_t* list, int64_t count,
                   hipStream_t st);
 template <typename T>
+void launch_packed(const DevSym& S, const DevNum<T>& N, T* winv, const int32_t* list,
+                   int64_t count, hipStream_t st);
+template <typename T>
 void launch_assemble(const DevSym& S, const DevNum<T>& N, const AsmItem* items, int64_t count,
                      hipStream_t st);
 template <typename T>
@@ -77,7 +100,7 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
                   const T* winv, hipStream_t st);
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
-                 int tile, hipStream_t st);
+                 int tile, hipStream_t st, const T* bsrc = nullptr);
 // Dataflow factorization of one level's large fronts.  flow holds one
 // completion flag per row tile of every pivot block (ntiles, indexed through
 // DevSym::tbase), one pre-accumulation flag per pivot block (nblocks), one
@@ -86,7 +109,7 @@ void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tile
 template <typename T>
 void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
                   int64_t count, int32_t* flow, int64_t ntiles, int64_t nblocks, int64_t nucount,
-                  int level, int nlevels, hipStream_t st);
+                  int ticket, int nticket, hipStream_t st);
 
 // Dataflow solves of nrhs <= 16 right-hand sides.  y (n rows of 1 value
 // when nrhs = 1, else of 16) receives P b in solve_in, is solved forward and
@@ -126,7 +149,7 @@ void launch_solve_out(const DevSym& S, const T* y, double* x, int64_t ldx, int n
 // FP64 refinement helpers: r = b - A x (original numbering, CSR), column norms.
 void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
                      const double* b, int64_t ldb, const double* x, int64_t ldx, double* r,
-                     int64_t nrhs, hipStream_t st);
+                     int64_t nrhs, double* xt, hipStream_t st);
 void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, double* out,
                      hipStream_t st);
 // out[k + c*nsys] = || v[sys_ptr[k]:sys_ptr[k+1], c] ||_2
@@ -139,5 +162,23 @@ void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t 
 // v[sys k rows, c] = src[sys k rows, c] where mask[k + c*nsys] != 0 (both with ld)
 void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const double* src,
                          int64_t ld, int64_t nrhs, const uint8_t* mask, hipStream_t st);
+
+// LDL^T (FP64) with Bunch-Kaufman pivoting restricted to diagonal blocks.
+void launch_small_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& D,
+                       const int32_t* list, int64_t count, hipStream_t st);
+void launch_diag_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& D,
+                      const PanelItem* items, int64_t count, double* winv, hipStream_t st);
+void launch_panel_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& D,
+                       const PanelItem* items, int64_t count, const double* winv, hipStream_t st);
+// y <- D^{-1} y on the solve vector (permuted rows, kRowLd stride); and the
+// permutations of the numeric handle: perm_num[i] = perm[q[i]], pinv_num its
+// inverse, qinv the inverse of q.
+void launch_apply_dinv(int64_t n, const double* d, const double* e, double* y, int nrhs,
+                       hipStream_t st);
+void launch_ldlt_perm(int64_t n, const int32_t* perm, const int32_t* q, int32_t* perm_num,
+                      int32_t* pinv_num, int32_t* qinv, hipStream_t st);
+// p[i] = i (the identity pivot order an LDL^T factorization starts from, so
+// that a block left unfactored after a failure still holds valid indices).
+void launch_iota(int32_t* p, int64_t n, hipStream_t st);
 
 }  // namespace tacho

@@ -13,6 +13,7 @@
 // sizes, never on how fronts are batched into launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -194,6 +195,116 @@ __global__ __launch_bounds__(kThreads) void k_small(DevSym S, DevNum<T> N, const
       const int jj = t / ldu, ii = t - jj * ldu;
       Us[t] = ii < r ? F[(w + ii) + (w + jj) * ld] : T(0);
     }
+  }
+}
+
+// Cholesky fronts with kSmallMax < m <= kPackedMax and w <= kSmallMax: one
+// workgroup assembles the front in LDS as a packed lower triangle (column j
+// holds rows j..m-1 from col(j) = j m - j (j - 1) / 2), eliminates the w
+// pivot columns right-looking within the pivot panel, writes the L panel, and
+// forms every update-matrix entry from its assembled value by subtracting
+// the pivot columns' products in column order: the operations of k_small,
+// with the trailing updates of one entry applied together.  Last, the
+// inverse W = L11^-1 that the solves apply to the diagonal block, by forward
+// substitution (one column per thread).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_packed(DevSym S, DevNum<T> N, T* winv,
+                                                     const int32_t* list) {
+  __shared__ T F[kPackedMax * (kPackedMax + 1) / 2];
+  __shared__ T dinv[kSmallMax];
+  const int s = list[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int ld = S.ldL[s];
+  auto col = [m](int j) { return j * m - (j * (j - 1)) / 2; };
+  for (int t = tid; t < m * (m + 1) / 2; t += kThreads) F[t] = T(0);
+  __syncthreads();
+  {
+    const int64_t q0 = S.acol_ptr[f], q1 = S.acol_ptr[f + w];
+    for (int64_t q = q0 + tid; q < q1; q += kThreads) {
+      const int pos = S.a_pos[q], j = pos / ld, i = pos - j * ld;
+      F[col(j) + i - j] = N.avals[q];
+    }
+  }
+  __syncthreads();
+  for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+    const int c = S.child_list[q];
+    const int wc = S.sptr[c + 1] - S.sptr[c], rc = S.front_m[c] - wc;
+    const T* Uc = N.U + S.U_off[c];
+    const int ldc = S.ldU[c];
+    const int32_t* rm = S.rmap + S.rows_ptr[c] + wc;
+    for (int t = tid; t < rc * rc; t += kThreads) {
+      const int jj = t / rc, ii = t - jj * rc;
+      if (ii >= jj) F[col(rm[jj]) + rm[ii] - rm[jj]] += Uc[ii + (int64_t)jj * ldc];
+    }
+    __syncthreads();
+  }
+  for (int j = 0; j < w; ++j) {
+    const int cj = col(j);
+    const T d = F[cj];
+    __syncthreads();
+    const T ljj = sqrt(d);
+    if (tid == 0) {
+      F[cj] = ljj;
+      if (!(d > T(0))) atomicMin(N.fail, f + j);
+    }
+    for (int i = j + 1 + tid; i < m; i += kThreads) F[cj + i - j] = F[cj + i - j] / ljj;
+    __syncthreads();
+    // the pivot panel's later columns now; the update matrix after the loop
+    for (int k = j + 1 + wave; k < w; k += kThreads / 64) {
+      const int ck = col(k);
+      const T lkj = F[cj + k - j];
+      for (int i = k + lane; i < m; i += 64) F[ck + i - k] -= F[cj + i - j] * lkj;
+    }
+    __syncthreads();
+  }
+  T* Lp = N.L + S.L_off[s];
+  for (int t = tid; t < ld * w; t += kThreads) {
+    const int j = t / ld, i = t - j * ld;
+    Lp[t] = (i >= j && i < m) ? F[col(j) + i - j] : T(0);
+  }
+  if (r > 0) {
+    T* Us = N.U + S.U_off[s];
+    const int ldu = S.ldU[s];
+    for (int t = tid; t < ldu * r; t += kThreads) {
+      const int kk = t / ldu, ii = t - kk * ldu;
+      T v = T(0);
+      if (ii < r && ii >= kk) {
+        const int i = w + ii, k = w + kk;
+        v = F[col(k) + i - k];
+        int cs = 0;  // col(j)
+        for (int j = 0; j < w; ++j) {
+          v -= F[cs + i - j] * F[cs + k - j];
+          cs += m - j;
+        }
+      }
+      Us[t] = v;
+    }
+  }
+  // W, packed by columns (column c at wc(c) = c w - c (c - 1) / 2) in the
+  // space from col(w) on, no longer needed: w (m + 1) <= kPackedMax
+  // (kPackedMax + 1) / 2 for every front of this class, so it fits.
+  for (int i = tid; i < w; i += kThreads) dinv[i] = T(1) / F[col(i)];
+  __syncthreads();
+  T* Wl = F + col(w);
+  if (tid < w) {
+    const int c = tid, wc = c * w - (c * (c - 1)) / 2;
+    Wl[wc] = dinv[c];
+    for (int i = c + 1; i < w; ++i) {
+      T acc = T(0);
+      int ck = col(c);
+      for (int k = c; k < i; ++k) {
+        acc += F[ck + i - k] * Wl[wc + k - c];
+        ck += m - k;
+      }
+      Wl[wc + i - c] = -(acc * dinv[i]);
+    }
+  }
+  __syncthreads();
+  T* Wout = winv + S.woff[S.wbase[s]];  // w x w, column-major
+  for (int t = tid; t < w * w; t += kThreads) {
+    const int c = t / w, i = t - c * w;
+    Wout[t] = i >= c ? Wl[c * w - (c * (c - 1)) / 2 + i - c] : T(0);
   }
 }
 
@@ -551,6 +662,388 @@ __global__ __launch_bounds__(kThreads) void k_panel(DevSym S, DevNum<T> N, const
 }
 
 // ---------------------------------------------------------------------------
+// LDL^T of a symmetric indefinite C (Tacho section: besides Cholesky, LDL^T of
+// a symmetric indefinite matrix with pivots searched only within each
+// diagonal block).  The diagonal blocks are the supernodes' pivot columns cut
+// into blocks of at most kPanel columns; inside a block, Bunch-Kaufman
+// partial pivoting with the candidate rows and columns limited to the
+// block's columns not yet eliminated.  L is stored unit lower triangular
+// (explicit ones on the diagonal, a zero below the first column of a 2x2
+// pivot), D as d / e, the interchanges as the pivot order q.  FP64 only.
+
+constexpr double kBkAlpha = 0x1.47e0f66afed07p-1;  // (1 + sqrt(17)) / 8, rounded to nearest
+
+// Pivot choice for position k among the block's positions [k, b1) of the
+// symmetric matrix whose lower triangle is F (element (i, j), i >= j, at
+// F[j * ld + i]): .x = size (1 or 2; 0: no usable pivot), .y = the position
+// moved to k (size 1) or to k + 1 (size 2).  Ties go to the smallest index.
+__device__ inline int2 bk_choose(const double* F, int ld, int k, int b1) {
+  double lam = 0.0;
+  int r = k;
+  for (int i = k + 1; i < b1; ++i) {
+    const double v = fabs(F[k * ld + i]);
+    if (v > lam) {
+      lam = v;
+      r = i;
+    }
+  }
+  const double akk = fabs(F[k * ld + k]);
+  if (lam == 0.0) return make_int2(F[k * ld + k] == 0.0 ? 0 : 1, k);
+  if (akk >= kBkAlpha * lam) return make_int2(1, k);
+  double sigma = 0.0;
+  for (int j = k; j < b1; ++j) {
+    if (j == r) continue;
+    const double v = fabs(j < r ? F[j * ld + r] : F[r * ld + j]);
+    sigma = v > sigma ? v : sigma;
+  }
+  if (akk * sigma >= kBkAlpha * lam * lam) return make_int2(1, k);
+  if (fabs(F[r * ld + r]) >= kBkAlpha * sigma) return make_int2(1, r);
+  return make_int2(2, r);
+}
+
+// Symmetric interchange of rows and columns p < r of the order-m matrix whose
+// lower triangle is F; the columns before p (eliminated pivots) exchange
+// their rows p and r too.  Every thread touches its own elements.
+__device__ inline void sym_swap(double* F, int ld, int m, int p, int r) {
+  for (int t = threadIdx.x; t < m; t += kThreads) {
+    double* a = nullptr;
+    double* b = nullptr;
+    if (t == p) {
+      a = F + p * ld + p;
+      b = F + r * ld + r;
+    } else if (t < p) {
+      a = F + t * ld + p;
+      b = F + t * ld + r;
+    } else if (t < r) {
+      a = F + p * ld + t;
+      b = F + t * ld + r;
+    } else if (t > r) {
+      a = F + p * ld + t;
+      b = F + r * ld + t;
+    }
+    if (a) {
+      const double v = *a;
+      *a = *b;
+      *b = v;
+    }
+  }
+}
+
+// Right-looking restricted Bunch-Kaufman elimination of positions [0, w) of
+// the order-m matrix F in LDS (lower triangle, leading dimension ld); every
+// position of [0, w) is one block.  On return F holds the unit lower L in
+// columns [0, w) and the Schur complement below; pivots go to d / e at
+// col0 + position, the order to qloc.  Returns the failing position, or -1.
+// c0 / c1 hold kSmallMax (or kPanel) entries of scratch each.
+__device__ inline int ldlt_eliminate(double* F, int ld, int m, int w, int* qloc, double* c0,
+                                     double* c1, double* d, double* e, int2* choice) {
+  const int tid = threadIdx.x;
+  for (int t = tid; t < w; t += kThreads) qloc[t] = t;
+  __syncthreads();
+  int k = 0;
+  while (k < w) {
+    if (tid == 0) *choice = bk_choose(F, ld, k, w);
+    __syncthreads();
+    const int2 ch = *choice;
+    __syncthreads();
+    if (ch.x == 0) return k;
+    const int p = ch.x == 1 ? k : k + 1;
+    if (ch.y != p) {
+      sym_swap(F, ld, m, p, ch.y);
+      if (tid == 0) {
+        const int t = qloc[p];
+        qloc[p] = qloc[ch.y];
+        qloc[ch.y] = t;
+      }
+    }
+    __syncthreads();
+    if (ch.x == 1) {
+      const double piv = F[k * ld + k];
+      for (int i = k + 1 + tid; i < m; i += kThreads) c0[i] = F[k * ld + i];
+      __syncthreads();
+      const int nt = m - k - 1;
+      for (int t = tid; t < nt * nt; t += kThreads) {
+        const int cc = t / nt, rr = t - cc * nt;
+        if (rr >= cc) {
+          const int i = k + 1 + rr, j = k + 1 + cc;
+          F[j * ld + i] -= (c0[i] / piv) * c0[j];
+        }
+      }
+      for (int i = k + 1 + tid; i < m; i += kThreads) F[k * ld + i] = c0[i] / piv;
+      if (tid == 0) {
+        d[k] = piv;
+        e[k] = 0.0;
+        F[k * ld + k] = 1.0;
+      }
+      __syncthreads();
+      k += 1;
+    } else {
+      const double a = F[k * ld + k], b = F[k * ld + k + 1], c = F[(k + 1) * ld + k + 1];
+      const double det = a * c - b * b;
+      for (int i = k + 2 + tid; i < m; i += kThreads) {
+        c0[i] = F[k * ld + i];
+        c1[i] = F[(k + 1) * ld + i];
+      }
+      __syncthreads();
+      const int nt = m - k - 2;
+      for (int t = tid; t < nt * nt; t += kThreads) {
+        const int cc = t / nt, rr = t - cc * nt;
+        if (rr >= cc) {
+          const int i = k + 2 + rr, j = k + 2 + cc;
+          const double l0 = (c0[i] * c - c1[i] * b) / det, l1 = (c1[i] * a - c0[i] * b) / det;
+          F[j * ld + i] -= l0 * c0[j] + l1 * c1[j];
+        }
+      }
+      for (int i = k + 2 + tid; i < m; i += kThreads) {
+        F[k * ld + i] = (c0[i] * c - c1[i] * b) / det;
+        F[(k + 1) * ld + i] = (c1[i] * a - c0[i] * b) / det;
+      }
+      if (tid == 0) {
+        d[k] = a;
+        d[k + 1] = c;
+        e[k] = b;
+        e[k + 1] = 0.0;
+        F[k * ld + k] = 1.0;
+        F[k * ld + k + 1] = 0.0;
+        F[(k + 1) * ld + k + 1] = 1.0;
+      }
+      __syncthreads();
+      k += 2;
+    }
+  }
+  return -1;
+}
+
+// Small fronts (m <= kSmallMax), LDL^T: assembly as in k_small, elimination
+// of the w pivot positions (one diagonal block), L panel and U written out.
+__global__ __launch_bounds__(kThreads) void k_small_ldlt(DevSym S, DevNum<double> N, DevLdlt D,
+                                                         const int32_t* list) {
+  __shared__ double F[kSmallMax * kSmallMax];
+  __shared__ double c0[kSmallMax], c1[kSmallMax], dd[kSmallMax], ee[kSmallMax];
+  __shared__ int qloc[kSmallMax];
+  __shared__ int2 choice;
+  const int s = list[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int ld = S.ldL[s];
+  for (int t = tid; t < ld * m; t += kThreads) F[t] = 0.0;
+  __syncthreads();
+  {
+    const int64_t q0 = S.acol_ptr[f], q1 = S.acol_ptr[f + w];
+    for (int64_t q = q0 + tid; q < q1; q += kThreads) F[S.a_pos[q]] = N.avals[q];
+  }
+  __syncthreads();
+  for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+    const int c = S.child_list[q];
+    const int wc = S.sptr[c + 1] - S.sptr[c], rc = S.front_m[c] - wc;
+    const double* Uc = N.U + S.U_off[c];
+    const int ldc = S.ldU[c];
+    const int32_t* rm = S.rmap + S.rows_ptr[c] + wc;
+    for (int t = tid; t < rc * rc; t += kThreads) {
+      const int jj = t / rc, ii = t - jj * rc;
+      if (ii >= jj) F[rm[ii] + rm[jj] * ld] += Uc[ii + (int64_t)jj * ldc];
+    }
+    __syncthreads();
+  }
+  const int bad = ldlt_eliminate(F, ld, m, w, qloc, c0, c1, dd, ee, &choice);
+  if (bad >= 0) {
+    if (tid == 0) atomicMin(N.fail, f + bad);
+    return;
+  }
+  for (int c = tid; c < w; c += kThreads) {
+    D.d[f + c] = dd[c];
+    D.e[f + c] = ee[c];
+    D.q[f + c] = f + qloc[c];
+  }
+  double* Lp = N.L + S.L_off[s];
+  for (int t = tid; t < ld * w; t += kThreads) Lp[t] = F[t];
+  if (r > 0) {
+    double* Us = N.U + S.U_off[s];
+    const int ldu = S.ldU[s];
+    for (int t = tid; t < ldu * r; t += kThreads) {
+      const int jj = t / ldu, ii = t - jj * ldu;
+      Us[t] = ii < r ? F[(w + ii) + (w + jj) * ld] : 0.0;
+    }
+  }
+}
+
+// Large fronts, LDL^T step 1 (stepwise launches): elimination of diagonal
+// block [k, k + kb) of front s (already updated by the blocks before it),
+// the block's interchanges applied to the rows of the front's earlier
+// columns (L and L D), and W = L_kk^{-1} (unit lower) kept for the panel and
+// the solves.
+__global__ __launch_bounds__(kThreads) void k_diag_ldlt(DevSym S, DevNum<double> N, DevLdlt D,
+                                                        const PanelItem* items, double* winv) {
+  __shared__ double F[kPanel * kDiagLd];
+  __shared__ double c0[kPanel], c1[kPanel], dd[kPanel], ee[kPanel];
+  __shared__ int qloc[kPanel];
+  __shared__ int2 choice;
+  const PanelItem it = items[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = it.s, k = it.k, kb = it.kb;
+  const int f = S.sptr[s], ld = S.ldL[s];
+  double* Lp = N.L + S.L_off[s];
+  double* LDp = D.ld + S.L_off[s];
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    F[c * kDiagLd + r] = (r < kb && c < kb && r >= c) ? Lp[(k + r) + (int64_t)(k + c) * ld] : 0.0;
+  }
+  __syncthreads();
+  const int bad = ldlt_eliminate(F, kDiagLd, kb, kb, qloc, c0, c1, dd, ee, &choice);
+  if (bad >= 0) {
+    if (tid == 0) atomicMin(N.fail, f + k + bad);
+    return;
+  }
+  for (int c = tid; c < kb; c += kThreads) {
+    D.d[f + k + c] = dd[c];
+    D.e[f + k + c] = ee[c];
+    D.q[f + k + c] = f + k + qloc[c];
+  }
+  for (int t = tid; t < kb * kb; t += kThreads) {
+    const int c = t / kb, r = t - c * kb;
+    if (r >= c) Lp[(k + r) + (int64_t)(k + c) * ld] = F[c * kDiagLd + r];
+  }
+  // rows of this block in the earlier columns: new row r <- old row qloc[r]
+  for (int p = wave; p < k; p += kThreads / 64) {
+    double* lc = Lp + (int64_t)p * ld + k;
+    double* dc = LDp + (int64_t)p * ld + k;
+    const double lv = lane < kb ? lc[qloc[lane]] : 0.0;
+    const double dv = lane < kb ? dc[qloc[lane]] : 0.0;
+    if (lane < kb) {
+      lc[lane] = lv;
+      dc[lane] = dv;
+    }
+  }
+  // W = L_kk^{-1}: column c by forward substitution (one thread per column)
+  __syncthreads();
+  double* Wout = winv + S.woff[it.wblk];  // kb x kb, column-major
+  if (tid < kb) {
+    const int c = tid;
+    for (int r = 0; r < kb; ++r) {
+      double v = r == c ? 1.0 : 0.0;
+      if (r > c)
+        for (int j = c; j < r; ++j) v -= F[j * kDiagLd + r] * Wout[c * kb + j];
+      Wout[c * kb + r] = r < c ? 0.0 : v;
+    }
+  }
+}
+
+// Large fronts, LDL^T step 2: 64 rows below the diagonal block, X = B W^T
+// with B the rows' entries in the block's columns taken in pivot order (the
+// block's interchanges permute these columns), on the matrix cores; X is
+// their L D, stored, and L = X D^{-1} replaces them.
+__global__ __launch_bounds__(kThreads) void k_panel_ldlt(DevSym S, DevNum<double> N, DevLdlt D,
+                                                         const PanelItem* items,
+                                                         const double* winv) {
+  constexpr int PAD = 4;
+  __shared__ double Bs[kPanel][kPanel + PAD];  // Bs[c][r] = B[r][c]
+  __shared__ double Ws[kPanel][kPanel + PAD];  // Ws[c'][c] = W[c][c']
+  const PanelItem it = items[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = it.s, k = it.k, kb = it.kb;
+  const int f = S.sptr[s], m = S.front_m[s], ld = S.ldL[s];
+  double* Lp = N.L + S.L_off[s];
+  double* LDp = D.ld + S.L_off[s];
+  const int r0 = k + kb + it.chunk * kPanel;
+  const double* Win = winv + S.woff[it.wblk];
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    Ws[c][r] = (r < kb && c < kb) ? Win[c * kb + r] : 0.0;
+    const int row = r0 + r;
+    const int src = c < kb ? D.q[f + k + c] - f : 0;  // front column in pivot order
+    Bs[c][r] = (row < m && c < kb) ? Lp[row + (int64_t)src * ld] : 0.0;
+  }
+  __syncthreads();
+  typedef Vec4<double>::type V4;
+  V4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+  const int wr = wave >> 1, wc = wave & 1;
+#pragma unroll
+  for (int ks = 0; ks < kPanel / 4; ++ks) {
+    const int kk = ks * 4 + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = Bs[kk][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = Ws[kk][wc * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+  }
+  __syncthreads();
+  // X[r][c] into Bs[c][r] (B is no longer needed)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr * 32 + a * 16 + (lane & 15);
+        const int c = wc * 32 + b * 16 + mfma_row<double>(lane, v);
+        Bs[c][r] = acc[a][b][v];
+      }
+  __syncthreads();
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    const int row = r0 + r;
+    if (row >= m || c >= kb) continue;
+    const double x = Bs[c][r];
+    const double ec = D.e[f + k + c];
+    double l;
+    if (ec != 0.0) {  // first column of a 2x2 pivot
+      const double d0 = D.d[f + k + c], d1 = D.d[f + k + c + 1];
+      l = (x * d1 - Bs[c + 1][r] * ec) / (d0 * d1 - ec * ec);
+    } else if (c > 0 && D.e[f + k + c - 1] != 0.0) {  // second column
+      const double ep = D.e[f + k + c - 1];
+      const double d0 = D.d[f + k + c - 1], d1 = D.d[f + k + c];
+      l = (x * d0 - Bs[c - 1][r] * ep) / (d0 * d1 - ep * ep);
+    } else {
+      l = x / D.d[f + k + c];
+    }
+    LDp[row + (int64_t)(k + c) * ld] = x;
+    Lp[row + (int64_t)(k + c) * ld] = l;
+  }
+}
+
+// y <- D^{-1} y, rows in pivot order, kRowLd values per row.
+__global__ __launch_bounds__(kThreads) void k_apply_dinv(int64_t n, const double* d,
+                                                         const double* e, double* y, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  constexpr int ldy = kRowLd<double>;
+  if (e[i] != 0.0) {
+    const double a = d[i], b = e[i], c = d[i + 1], det = a * c - b * b;
+    for (int r = 0; r < nrhs; ++r) {
+      const double y0 = y[i * ldy + r], y1 = y[(i + 1) * ldy + r];
+      y[i * ldy + r] = (c * y0 - b * y1) / det;
+      y[(i + 1) * ldy + r] = (a * y1 - b * y0) / det;
+    }
+  } else if (i == 0 || e[i - 1] == 0.0) {
+    for (int r = 0; r < nrhs; ++r) y[i * ldy + r] /= d[i];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_iota(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kThreads) void k_ldlt_perm(int64_t n, const int32_t* perm,
+                                                        const int32_t* q, int32_t* perm_num,
+                                                        int32_t* pinv_num, int32_t* qinv) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int32_t o = perm[q[i]];
+  perm_num[i] = o;
+  pinv_num[o] = (int32_t)i;
+  qinv[q[i]] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
 // Update on the matrix cores: C[M x N] -= A[M x K] * A[0:N, :]^T for the
 // elements with row >= col.  One TT x TT output tile per workgroup, four
 // waves of (TT/2) x (TT/2) built from 16x16x4 MFMA blocks, K staged through
@@ -558,9 +1051,11 @@ __global__ __launch_bounds__(kThreads) void k_panel(DevSym S, DevNum<T> N, const
 // registers while the current one is multiplied.  The MFMA computes the
 // transposed tile so that a lane's outputs run down a column of the
 // column-major C (coalesced read-modify-write).
+// With Bsrc (the L D panels of an LDL^T factorization, laid out like L) the
+// second operand is read from there: C -= A * B[0:N, :]^T.
 template <typename T, int TT>
 __global__ __launch_bounds__(kThreads) void k_gemm(DevNum<T> N, const GemmProb* probs,
-                                                   const GemmTile* tiles) {
+                                                   const GemmTile* tiles, const T* Bsrc) {
   constexpr int KT = 16, PAD = 4;
   constexpr int BL = TT / 32;               // 16x16 blocks per wave dimension
   constexpr int LPT = TT * KT / kThreads;   // elements per thread per stage and operand
@@ -583,7 +1078,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(DevNum<T> N, const GemmProb* 
   const int lrow = tid % TT, lk = tid / TT;
   const bool arow_ok = i0 + lrow < g.M, brow_ok = j0 + lrow < g.N;
   const T* pa = A + (i0 + lrow);
-  const T* pb = A + (j0 + lrow);
+  const T* pb = (Bsrc ? Bsrc + g.a_off : A) + (j0 + lrow);
   T ra[LPT], rb[LPT];
   auto load_stage = [&](int k0) {
 #pragma unroll
@@ -1467,11 +1962,12 @@ __device__ __forceinline__ void fwd_wave(const DevSym& S, const T* L, T* y, T* u
   acquire_agent();
   const int i = lane;
   const int ic = i < m ? i : m - 1;
-  const int64_t q = S.rows_ptr[s] + ic;
+  const int isrc = (S.lq && i < w) ? S.lq[f + i] - f : ic;  // LDL^T: row taken in pivot order
+  const int64_t q = S.rows_ptr[s] + isrc;
   const int p0 = S.pull_ptr[q], p1 = i < m ? S.pull_ptr[q + 1] : p0;
   T z[NR];
   {
-    const T* yr = y + (int64_t)(f + (i < w ? i : 0)) * kRowLd<T>;
+    const T* yr = y + (int64_t)(f + (i < w ? isrc : 0)) * kRowLd<T>;
     const T own = i < w ? T(1) : T(0);
 #pragma unroll
     for (int c = 0; c < NR; ++c) z[c] = yr[c] * own;
@@ -1528,7 +2024,7 @@ __device__ __forceinline__ void bwd_wave(const DevSym& S, const T* L, T* y, int 
   const T* lc = Lp + (int64_t)ic * ldl + w;  // L21 column ic
 #pragma unroll 2
   for (int k = 0; k < r; ++k) {
-    const T* xr = y + (int64_t)rws[k] * kRowLd<T>;
+    const T* xr = y + (int64_t)(S.lqinv ? S.lqinv[rws[k]] : rws[k]) * kRowLd<T>;
     const T l = lc[k];
 #pragma unroll
     for (int c = 0; c < NR; ++c) z[c] -= l * xr[c];
@@ -1589,13 +2085,15 @@ __device__ __forceinline__ void fwd_block(const DevSym& S, const T* L, const T* 
   }
   __syncthreads();
   {
-    const int64_t q0 = S.rows_ptr[s] + row0;
     for (int t = tid; t < kPanel * 16; t += kThreads) {
       const int i = t >> 4, c = t & 15;
       T v = T(0);
       if (i < nrows && c < NR) {
-        if (tri) v = y[(int64_t)(f + row0 + i) * kRowLd<T> + c];
-        for (int p = S.pull_ptr[q0 + i]; p < S.pull_ptr[q0 + i + 1]; ++p)
+        // LDL^T: a pivot row is taken in the block's pivot order
+        const int src = (tri && S.lq) ? S.lq[f + row0 + i] - f : row0 + i;
+        const int64_t qi = S.rows_ptr[s] + src;
+        if (tri) v = y[(int64_t)(f + src) * kRowLd<T> + c];
+        for (int p = S.pull_ptr[qi]; p < S.pull_ptr[qi + 1]; ++p)
           v += uvec[(int64_t)S.pull_src[p] * kRowLd<T> + c];
       }
       Zs[t] = v;
@@ -1693,7 +2191,8 @@ __device__ __forceinline__ void bwd_part(const DevSym& S, const T* L, const T* y
     }
     for (int t = tid; t < kPanel * 16; t += kThreads) {
       const int i = t >> 4, c = t & 15;
-      Vs[t] = (i < kw && c < NR) ? y[(int64_t)rws[k0 + i] * kRowLd<T> + c] : T(0);
+      const int32_t rr = i < kw ? rws[k0 + i] : 0;
+      Vs[t] = (i < kw && c < NR) ? y[(int64_t)(S.lqinv ? S.lqinv[rr] : rr) * kRowLd<T> + c] : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -1818,11 +2317,12 @@ __device__ __forceinline__ void fwd_group(const DevSym& S, const T* L, T* y, T* 
   const int ldl = S.ldL[s];
   const T* Lp = L + S.L_off[s];
   const int ic = i < m ? i : m - 1;
-  const int64_t q = S.rows_ptr[s] + ic;
+  const int isrc = (S.lq && i < w) ? S.lq[f + i] - f : ic;  // LDL^T: row taken in pivot order
+  const int64_t q = S.rows_ptr[s] + isrc;
   const int p0 = S.pull_ptr[q], p1 = (act && i < m) ? S.pull_ptr[q + 1] : p0;
   T z[NR];
   {
-    const T* yr = y + (int64_t)(f + (i < w ? i : 0)) * kRowLd<T>;
+    const T* yr = y + (int64_t)(f + (i < w ? isrc : 0)) * kRowLd<T>;
     const T own = i < w ? T(1) : T(0);
 #pragma unroll
     for (int c = 0; c < NR; ++c) z[c] = yr[c] * own;
@@ -1881,7 +2381,7 @@ __device__ __forceinline__ void bwd_group(const DevSym& S, const T* L, T* y,
     const bool kv = k < r;
     const int kk = kv ? k : 0;
     const T l = lc[kk] * (kv ? T(1) : T(0));
-    const T* xr = y + (int64_t)rws[kk] * kRowLd<T>;
+    const T* xr = y + (int64_t)(S.lqinv ? S.lqinv[rws[kk]] : rws[kk]) * kRowLd<T>;
 #pragma unroll
     for (int c = 0; c < NR; ++c) z[c] -= l * xr[c];
   }
@@ -1999,17 +2499,46 @@ __global__ __launch_bounds__(kThreads) void k_level_bwd(DevSym S, const T* L, co
 // ---------------------------------------------------------------------------
 // FP64 refinement: r = b - A x with the full symmetric CSR whose values come
 // from the lower triangle (mirror index), one thread per row and column.
+// r = b - A x for up to 16 right-hand sides per pass, with x given by rows
+// (xt[i * ldt + c] = x[i][c], so the right-hand sides of one unknown share a
+// cache line).  A group of kResLanes lanes owns a row: the lanes step through
+// its entries together (coalesced reads of values and column indices, each
+// read once for every right-hand side), accumulate all columns in registers,
+// and the group sum gives lane c the result of column c.  Groups step over
+// rows.
+constexpr int kResLanes = 16;
 __global__ __launch_bounds__(kThreads) void k_residual(int64_t n, const int64_t* rowptr,
                                                        const int32_t* colind, const double* vals,
                                                        const double* b, int64_t ldb,
-                                                       const double* x, int64_t ldx, double* r,
+                                                       const double* xt, int64_t ldt, double* r,
                                                        int64_t nrhs) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int64_t c = blockIdx.y;
-  double acc = 0.0;
-  for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) acc += vals[k] * x[colind[k] + c * ldx];
-  r[i + c * n] = b[i + c * ldb] - acc;
+  const int lane = threadIdx.x & (kResLanes - 1);
+  const int64_t groups = (int64_t)gridDim.x * (kThreads / kResLanes);
+  for (int64_t i = (int64_t)blockIdx.x * (kThreads / kResLanes) + threadIdx.x / kResLanes; i < n;
+       i += groups) {
+    const int64_t k0 = rowptr[i], k1 = rowptr[i + 1];
+    for (int64_t c0 = 0; c0 < nrhs; c0 += kResLanes) {
+      const int nc = (int)(nrhs - c0 < kResLanes ? nrhs - c0 : kResLanes);
+      double acc[kResLanes];
+#pragma unroll
+      for (int c = 0; c < kResLanes; ++c) acc[c] = 0.0;
+      for (int64_t k = k0 + lane; k < k1; k += kResLanes) {
+        const double v = vals[k];
+        const double* xc = xt + (int64_t)colind[k] * ldt + c0;
+#pragma unroll
+        for (int c = 0; c < kResLanes; ++c)
+          if (c < nc) acc[c] += v * xc[c];
+      }
+      double mine = 0.0;
+#pragma unroll
+      for (int c = 0; c < kResLanes; ++c) {
+        double t = acc[c];
+        for (int o = kResLanes / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, kResLanes);
+        mine = lane == c ? t : mine;
+      }
+      if (lane < nc) r[i + (c0 + lane) * n] = b[i + (c0 + lane) * ldb] - mine;
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_colnorms(int64_t n, const double* v, int64_t ldv,
@@ -2031,15 +2560,32 @@ __global__ __launch_bounds__(kThreads) void k_colnorms(int64_t n, const double* 
   }
 }
 
+// xt[i * nrhs + c] = x[i + c * ldx]: the refinement's iterate by rows.
+__global__ __launch_bounds__(kThreads) void k_to_rows(int64_t n, const double* x, int64_t ldx,
+                                                      int64_t nrhs, double* xt) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t c = 0; c < nrhs; ++c) xt[i * nrhs + c] = x[i + c * ldx];
+}
+
 __global__ __launch_bounds__(kThreads) void k_segnorms(const int64_t* sys_ptr, const double* v,
                                                        int64_t ldv, int64_t nsys, double* out) {
   __shared__ double part[kThreads / 64];
   const int64_t k = blockIdx.x, c = blockIdx.y;
-  double acc = 0.0;
-  for (int64_t i = sys_ptr[k] + threadIdx.x; i < sys_ptr[k + 1]; i += kThreads) {
-    const double t = v[i + c * ldv];
-    acc += t * t;
+  // four independent partial sums per thread keep four loads in flight
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int64_t i0 = sys_ptr[k], i1 = sys_ptr[k + 1];
+  const double* vc = v + c * ldv;
+  int64_t i = i0 + threadIdx.x;
+  for (; i + 3 * kThreads < i1; i += 4 * kThreads) {
+    const double t0 = vc[i], t1 = vc[i + kThreads], t2 = vc[i + 2 * kThreads], t3 = vc[i + 3 * kThreads];
+    a0 += t0 * t0;
+    a1 += t1 * t1;
+    a2 += t2 * t2;
+    a3 += t3 * t3;
   }
+  for (; i < i1; i += kThreads) a0 += vc[i] * vc[i];
+  double acc = (a0 + a1) + (a2 + a3);
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
   __syncthreads();
@@ -2100,6 +2646,13 @@ void launch_small(const DevSym& S, const DevNum<T>& N, const int32_t* list, int6
 }
 
 template <typename T>
+void launch_packed(const DevSym& S, const DevNum<T>& N, T* winv, const int32_t* list,
+                   int64_t count, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_packed<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, winv, list);
+}
+
+template <typename T>
 void launch_leaf(const DevSym& S, const DevNum<T>& N, const int32_t* list, int64_t count,
                  hipStream_t st) {
   if (count > 0)
@@ -2128,23 +2681,52 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
 template <typename T>
 void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask* tasks,
                   int64_t count, int32_t* flow, int64_t ntiles, int64_t nblocks, int64_t nucount,
-                  int level, int nlevels, hipStream_t st) {
+                  int ticket, int nticket, hipStream_t st) {
   if (count <= 0) return;
   int32_t* pd_done = flow + ntiles;
   int32_t* ucount = pd_done + nblocks;
   int32_t* tickets = ucount + nucount;
   k_front<T><<<(unsigned)count, kThreads, 0, st>>>(S, N, winv, tasks, (int)count, flow, pd_done,
-                                                   ucount, tickets + level, tickets + nlevels);
+                                                   ucount, tickets + ticket, tickets + nticket);
 }
 
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
-                 int tile, hipStream_t st) {
+                 int tile, hipStream_t st, const T* bsrc) {
   if (count <= 0) return;
   if (tile == kGemmTileBig)
-    hipLaunchKernelGGL((k_gemm<T, kGemmTileBig>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles);
+    hipLaunchKernelGGL((k_gemm<T, kGemmTileBig>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles, bsrc);
   else
-    hipLaunchKernelGGL((k_gemm<T, kGemmTile>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles);
+    hipLaunchKernelGGL((k_gemm<T, kGemmTile>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles, bsrc);
+}
+
+void launch_small_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& D,
+                       const int32_t* list, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_small_ldlt, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, D, list);
+}
+
+void launch_diag_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& D,
+                      const PanelItem* items, int64_t count, double* winv, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_diag_ldlt, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, D, items, winv);
+}
+
+void launch_panel_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& D,
+                       const PanelItem* items, int64_t count, const double* winv, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_panel_ldlt, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, D, items, winv);
+}
+
+void launch_apply_dinv(int64_t n, const double* d, const double* e, double* y, int nrhs,
+                       hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_apply_dinv, dim3(blocks_for(n)), dim3(kThreads), 0, st, n, d, e, y, nrhs);
+}
+
+void launch_iota(int32_t* p, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(kThreads), 0, st, p, n);
+}
+
+void launch_ldlt_perm(int64_t n, const int32_t* perm, const int32_t* q, int32_t* perm_num,
+                      int32_t* pinv_num, int32_t* qinv, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(k_ldlt_perm, dim3(blocks_for(n)), dim3(kThreads), 0, st, n, perm, q, perm_num, pinv_num, qinv);
 }
 
 // Counters of the dataflow solves: [xcnt ns][ucnt ns][bcnt ns][pcnt nblk][2 tickets].
@@ -2235,10 +2817,20 @@ void launch_solve_out(const DevSym& S, const T* y, double* x, int64_t ldx, int n
 
 void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* vals,
                      const double* b, int64_t ldb, const double* x, int64_t ldx, double* r,
-                     int64_t nrhs, hipStream_t st) {
-  if (n > 0 && nrhs > 0)
-    hipLaunchKernelGGL(k_residual, dim3(blocks_for(n), (unsigned)nrhs), dim3(kThreads), 0, st, n,
-                       rowptr, colind, vals, b, ldb, x, ldx, r, nrhs);
+                     int64_t nrhs, double* xt, hipStream_t st) {
+  if (n > 0 && nrhs > 0) {
+    const double* rows = x;
+    int64_t ldt = 1;
+    if (nrhs > 1) {
+      hipLaunchKernelGGL(k_to_rows, dim3(blocks_for(n)), dim3(kThreads), 0, st, n, x, ldx, nrhs, xt);
+      rows = xt;
+      ldt = nrhs;
+    }
+    const int64_t rows_per_block = kThreads / kResLanes;
+    const int64_t blocks = std::min<int64_t>((n + rows_per_block - 1) / rows_per_block, 8192);
+    hipLaunchKernelGGL(k_residual, dim3((unsigned)blocks), dim3(kThreads), 0, st, n, rowptr, colind,
+                       vals, b, ldb, rows, ldt, r, nrhs);
+  }
 }
 
 void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, double* out,
@@ -2272,6 +2864,8 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
                                  hipStream_t);                                                   \
   template void launch_small<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,         \
                                 hipStream_t);                                                    \
+  template void launch_packed<T>(const DevSym&, const DevNum<T>&, T*, const int32_t*, int64_t,    \
+                                 hipStream_t);                                                   \
   template void launch_leaf<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,          \
                                hipStream_t);                                                     \
   template void launch_assemble<T>(const DevSym&, const DevNum<T>&, const AsmItem*, int64_t,      \
@@ -2281,7 +2875,7 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
   template void launch_panel<T>(const DevSym&, const DevNum<T>&, const PanelItem*, int64_t,       \
                                 const T*, hipStream_t);                                          \
   template void launch_gemm<T>(const DevNum<T>&, const GemmProb*, const GemmTile*, int64_t, int,  \
-                               hipStream_t);                                                     \
+                               hipStream_t, const T*);                                           \
   template void launch_front<T>(const DevSym&, const DevNum<T>&, T*, const FrontTask*, int64_t,   \
                                 int32_t*, int64_t, int64_t, int64_t, int, int, hipStream_t);     \
   template void launch_solve_in<T>(const DevSym&, const double*, int64_t, T*, int,              \
@@ -2304,4 +2898,5 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
 TACHO_INSTANTIATE(double)
 TACHO_INSTANTIATE(float)
 
+// ---------------------------------------------------------------------------
 }  // namespace tacho

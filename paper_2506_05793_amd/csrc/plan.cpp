@@ -9,14 +9,17 @@
 //
 // Launch plan, per level of the supernodal elimination tree (level-set
 // scheduling, Tacho section), leaves first:
-//   small fronts (m <= kSmallMax): one launch, one workgroup per front, the
-//     whole front assembled and partially factored in LDS;
-//   large fronts: assembly into the panels / update matrices, then for every
-//     panel of kPanel columns a diagonal-block Cholesky launch, a triangular
-//     solve launch for the rows below and an update launch of the remaining
-//     columns of its kOuter-wide outer panel; after each outer panel one
-//     update launch with K = kOuter of the remaining pivot columns; finally
-//     one update launch U -= L21 L21^T.
+//   small fronts (m <= kSmallMax, and for Cholesky m <= kPackedMax with one
+//     pivot block): one launch, one workgroup per front, the whole front
+//     assembled and partially factored in LDS;
+//   large fronts: assembly into the panels / update matrices, then
+//     front_mode 0 (Cholesky): one dataflow launch of 64-row tile tasks per
+//     level (per group of chain fronts where a level has many);
+//     front_mode 1 (LDL^T): for every panel of kPanel columns a
+//     diagonal-block launch, a triangular solve launch for the rows below and
+//     an update launch of the remaining columns of its kOuter-wide outer
+//     panel; after each outer panel one update launch with K = kOuter of the
+//     remaining pivot columns; finally one update launch U -= L21 L21^T.
 #include <algorithm>
 #include <climits>
 #include <map>
@@ -207,6 +210,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
   P.tiles.clear();
   P.ftasks.clear();
   P.nucount = 0;
+  P.front_launches = 0;
   P.pt1base.assign(P.woff.size(), -1);
   P.pt1_slots = 0;
   // Problems of one update launch group; tiles are emitted per tile size so
@@ -251,18 +255,28 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q)
       if (leaf(S.level_list[q])) P.small_list.push_back(S.level_list[q]);
     const int32_t nleaf = (int32_t)((int64_t)P.small_list.size() - b0);
+    // Cholesky fronts a little larger than kSmallMax with one pivot block
+    // (a decision of the front's shape alone) go to the packed-LDS kernel
+    auto packed = [&](int32_t s) {
+      return front_mode == 0 && S.front_m[s] > kSmallMax && S.front_m[s] <= kPackedMax &&
+             S.sptr[s + 1] - S.sptr[s] <= kSmallMax;
+    };
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       int32_t s = S.level_list[q];
-      if (leaf(s))
+      if (leaf(s) || packed(s))
         continue;
       else if (S.front_m[s] <= kSmallMax)
         P.small_list.push_back(s);
       else
         big.push_back(s);
     }
+    const int64_t p0 = (int64_t)P.small_list.size();
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q)
+      if (packed(S.level_list[q])) P.small_list.push_back(S.level_list[q]);
     if ((int64_t)P.small_list.size() > b0) {
       Step st{kStepSmall, h, b0, (int64_t)P.small_list.size()};
       st.tile = nleaf;
+      st.packed = p0;
       for (int64_t q = b0; q < st.end; ++q) {
         const int32_t s = P.small_list[q];
         st.flops += front_flops(S, s);
@@ -303,14 +317,41 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       // Fronts with one pivot block and at most solo_m rows run as one task
       // each (diagonal block, row tiles, update-matrix tiles in order, no
       // flags); the others as tile tasks below.
-      std::vector<int32_t> flow, solo;
+      std::vector<int32_t> flow_all, solo;
       for (int32_t s : big)
-        ((S.sptr[s + 1] - S.sptr[s] <= kPanel && S.front_m[s] <= solo_m) ? solo : flow).push_back(s);
-      // Dataflow: pivot blocks in column order across the level's fronts;
+        ((S.sptr[s + 1] - S.sptr[s] <= kPanel && S.front_m[s] <= solo_m) ? solo : flow_all).push_back(s);
+      // Fronts with at least chain_min pivot blocks run their diagonal blocks
+      // as one chain task (a decision of the front's shape alone, so that its
+      // summation order never depends on the other fronts of the level).  A
+      // chain holds a workgroup slot while it waits for later tickets, so a
+      // level with more than kMaxChains of them is split into several
+      // launches of at most kMaxChains chains each.
+      auto is_chain = [&](int32_t s) {
+        return chain_min > 0 && (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min;
+      };
+      std::vector<std::vector<int32_t>> groups(1);
+      {
+        int nchain = 0;
+        for (int32_t s : flow_all) {
+          if (is_chain(s) && nchain == kMaxChains) {
+            groups.emplace_back();
+            nchain = 0;
+          }
+          nchain += is_chain(s) ? 1 : 0;
+          groups.back().push_back(s);
+        }
+      }
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const std::vector<int32_t>& flow = groups[gi];
+      const bool last_group = gi + 1 == groups.size();
+      int32_t gwmax = 0;
+      for (int32_t s : flow) gwmax = std::max(gwmax, S.sptr[s + 1] - S.sptr[s]);
+      // Dataflow: pivot blocks in column order across the group's fronts;
       // the update-matrix tiles of a front in ranges of u_range pivot
       // blocks, each range right after the last column it needs.  Every task
       // depends only on tasks with smaller tickets.
       Step st{kStepFront, h, (int64_t)P.ftasks.size(), 0};
+      st.ticket = P.front_launches++;
       std::vector<int32_t> ubase(flow.size());
       for (size_t bi = 0; bi < flow.size(); ++bi) {
         const int32_t s = flow[bi];
@@ -330,26 +371,18 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
         upto = std::min(upto, pending[bi].size());
         for (; pending_pos[bi] < upto; ++pending_pos[bi]) P.ftasks.push_back(pending[bi][pending_pos[bi]]);
       };
-      const int32_t ncols = (wmax + kPanel - 1) / kPanel;
-      // Fronts with at least chain_min pivot blocks run their diagonal blocks
-      // as one chain task (first in ticket order) when the level has few
-      // of them; their block j >= 2 is pre-accumulated by a task issued
-      // right after column j - 2.
+      const int32_t ncols = (gwmax + kPanel - 1) / kPanel;
+      // chain tasks first in ticket order; block j >= 2 of a chain is
+      // pre-accumulated by a task issued right after column j - 2
       std::vector<char> chain(flow.size(), 0);
-      {
-        int nchain = 0;
-        for (int32_t s : flow)
-          if (chain_min > 0 && (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) ++nchain;
-        if (chain_min > 0 && nchain <= kMaxChains)
-          for (size_t bi = 0; bi < flow.size(); ++bi) {
-            const int32_t s = flow[bi];
-            if ((S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min) {
-              chain[bi] = 1;
-              P.ftasks.push_back({s, 0, 0, 2, inplace ? 1 : 0, kPdRange, 0, 0});
-              const int32_t nbs = (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel;
-              for (int32_t b = 1; b < nbs; ++b) P.pt1base[P.wbase[s] + b] = (int32_t)P.pt1_slots++;
-            }
-          }
+      for (size_t bi = 0; bi < flow.size(); ++bi) {
+        const int32_t s = flow[bi];
+        if (is_chain(s)) {
+          chain[bi] = 1;
+          P.ftasks.push_back({s, 0, 0, 2, inplace ? 1 : 0, kPdRange, 0, 0});
+          const int32_t nbs = (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel;
+          for (int32_t b = 1; b < nbs; ++b) P.pt1base[P.wbase[s] + b] = (int32_t)P.pt1_slots++;
+        }
       }
       for (int32_t j = 0; j < ncols; ++j) {
         for (size_t bi = 0; bi < flow.size(); ++bi) {
@@ -412,15 +445,19 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
         }
       }
       for (size_t bi = 0; bi < flow.size(); ++bi) emit_u(bi, pending[bi].size());
-      for (int32_t s : solo) P.ftasks.push_back({s, 0, 0, 4, 0, 1, 0, 0});
+      if (last_group)
+        for (int32_t s : solo) P.ftasks.push_back({s, 0, 0, 4, 0, 1, 0, 0});
       st.end = (int64_t)P.ftasks.size();
-      for (int32_t s : big) {
+      std::vector<int32_t> members(flow);
+      if (last_group) members.insert(members.end(), solo.begin(), solo.end());
+      for (int32_t s : members) {
         const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s], r = m - w;
         st.flops += front_flops(S, s);
         // front read once (panel trapezoid + update triangle), written once
         st.elems += 2.0 * ((w * m - w * (w - 1) / 2) + r * (r + 1) / 2);
       }
-      P.steps.push_back(st);
+      if (st.end > st.begin) P.steps.push_back(st);
+      }
       continue;
     }
     for (int32_t k = 0; k < wmax; k += kPanel) {

@@ -97,7 +97,11 @@ constexpr int kChainMin = 3;   // default pivot blocks from which a front's diag
 constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
 constexpr int kAsmElems = 2048;  // front entries per assembly workgroup of a short front
 constexpr int kSoloM = 192;    // default: fronts with one pivot block and m <= this run as one task
-constexpr int kMaxChains = 32; // chains per level (each holds one workgroup slot for the level)
+// Chains per front launch: each holds a workgroup slot while it waits for
+// later tickets.  The FP64 front kernel keeps two workgroups per CU resident
+// (512 on 256 CUs), so four concurrent factorizations (the serving slots)
+// still leave slots for the tasks the chains wait on.
+constexpr int kMaxChains = 96;
 
 // Batching parameters of the plan (task grouping only; the arithmetic of a
 // front does not depend on them).
@@ -129,10 +133,13 @@ struct Step {
   double flops = 0;  // algorithmic flops of the launch
   double elems = 0;  // algorithmic element traffic (reads + writes) of the launch
   int32_t tile = 0;  // update steps: tile size; small-front steps: leading one-thread leaves
+  int32_t ticket = 0;  // dataflow front steps: index of the launch's ticket counter
+  int64_t packed = 0;  // small-front steps: [packed, end) go to the packed-LDS kernel
 };
 
 constexpr int kSmallMax = 64;     // fronts with m <= kSmallMax go to the LDS kernel
 constexpr int kLeafMax = 16;      // ... leaves with one pivot column and m <= kLeafMax to one thread each
+constexpr int kPackedMax = 128;   // Cholesky fronts with m <= kPackedMax and w <= kSmallMax: packed LDS kernel
 constexpr int kPanel = 64;        // panel width of the blocked large-front path
 constexpr int kOuter = 256;       // outer panel width (trailing updates with K = kOuter)
 constexpr int kPanelRows = 64;    // rows per triangular-solve workgroup
@@ -172,7 +179,8 @@ struct Plan {
   std::vector<PanelItem> panel_items;
   std::vector<GemmProb> probs;
   std::vector<GemmTile> tiles;
-  std::vector<FrontTask> ftasks;  // dataflow large-front tasks, per level in ticket order
+  std::vector<FrontTask> ftasks;  // dataflow large-front tasks, per launch in ticket order
+  int32_t front_launches = 0;     // dataflow front launches (one ticket counter each)
   std::vector<Step> steps;
   int front_mode = 0;             // 0: dataflow large-front kernel, 1: stepwise launches
 

@@ -102,7 +102,10 @@ class Server:
         # Level-structure dissection only: on the grid operators of the request
         # mix it gives fewer flops than the multilevel one and analyses several
         # times faster, and analysis time is part of a factor request's latency.
-        self.options = options if options is not None else tacho_default_options(ordering=2)
+        # Eager launches: a request's handle is factored once, so capturing its
+        # launch sequence into a graph would only add host time.
+        self.options = options if options is not None else tacho_default_options(ordering=2,
+                                                                                graphs=0)
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.pool = cf.ThreadPoolExecutor(max_workers=analysis_workers)
         self.slot_workers = cf.ThreadPoolExecutor(max_workers=slots)
