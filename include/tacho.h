@@ -333,6 +333,28 @@ int tacho_solve(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64
                 int on_device, void *hip_stream, tacho_solve_info *info);
 
 /*
+ * tacho_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, queued on hip_stream, that calls no hipMalloc/hipFree.
+ *   b, x   DEVICE pointers, n x nrhs column-major with leading dimension
+ *          ld >= n.  With an FP64 factor x may equal b.  With an FP32 factor
+ *          (refinement) ld must equal n, x must differ from b, nrhs <= 16,
+ *          and the refinement's scratch (8 n nrhs bytes of residual, as many
+ *          again for the iterate by rows when nrhs > 1, 17 nsystems nrhs
+ *          bytes of norms and mask) must fit the library's fixed device
+ *          array of 64 MiB per GPU; otherwise TACHO_ERR_INVALID.
+ * The scratch array is shared by every call on a GPU and keeps the last
+ * call's contents: calls that overlap on one GPU (different streams or
+ * threads) race and must be serialized by the caller.  If refinement would
+ * need the FP64 fallback factor and the handle does not hold one yet (an
+ * FP32 breakdown or stall), the call returns TACHO_ERR_NOMEM instead of
+ * allocating it; tacho_solve then does the fallback.  Blocking behaviour and
+ * `info` are those of tacho_solve with on_device = 1.
+ */
+int tacho_solve_noalloc(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64_t ld,
+                        void *hip_stream, tacho_solve_info *info);
+
+/*
  * Copy the factor L (of P A P^T, FP64 or FP32 widened to FP64) to host CSC
  * arrays as stored: Lp int64[n+1], Li int32[nnz_factor], Lx
  * float64[nnz_factor]; every column sorted ascending with the diagonal

@@ -123,6 +123,8 @@ def _load():
         "tacho_check_factor": (ctypes.c_int, [_vp, _i64p]),
         "tacho_solve": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
                                        _vp, ctypes.POINTER(tacho_solve_info)]),
+        "tacho_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64,
+                                               _vp, ctypes.POINTER(tacho_solve_info)]),
         "tacho_get_factor": (ctypes.c_int, [_vp, _i64p, _i32p, _f64p]),
         "tacho_get_ldlt": (ctypes.c_int, [_vp, _f64p, _f64p, _i32p]),
         "tacho_last_times": (ctypes.c_int, [_vp, _f64p, _f64p]),
@@ -419,6 +421,25 @@ def tacho_solve(num: NumericHandle, b, x=None, stream=None, with_info: bool = Fa
     addr = (lambda a: a.ctypes.data) if on_dev == 0 else (lambda a: a.data_ptr())
     rc = lib.tacho_solve(num.ptr, addr(b), addr(x), int(nrhs), int(ld), on_dev,
                          _stream_ptr(stream), ctypes.byref(info))
+    _check(rc)
+    if with_info:
+        return x, _info_dict(num, info, rr, fb, nrhs)
+    return x
+
+
+def tacho_solve_noalloc(num: NumericHandle, b, x, stream=None, with_info: bool = False):
+    """tacho_solve without device allocation: ``b`` and ``x`` are device tensors
+    (column-major n x nrhs, float64) that the caller owns."""
+    lib = _load()
+    if not (_is_torch(b) and _is_torch(x)):
+        raise TypeError("tacho_solve_noalloc takes device tensors b and x")
+    n = num.sym.n
+    if b.stride(0) != 1 or (b.dim() == 2 and b.shape[1] > 1 and b.stride(1) < n):
+        raise ValueError("b: expected a column-major block (no copy is made)")
+    b, x, nrhs, ld, on_dev = _solve_args(num, b, x)
+    info, rr, fb = _solve_info(num, nrhs)
+    rc = lib.tacho_solve_noalloc(num.ptr, b.data_ptr(), x.data_ptr(), int(nrhs), int(ld),
+                                 _stream_ptr(stream), ctypes.byref(info))
     _check(rc)
     if with_info:
         return x, _info_dict(num, info, rr, fb, nrhs)

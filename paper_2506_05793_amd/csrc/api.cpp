@@ -616,7 +616,7 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
              int64_t* fail_index);
 int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index);
 
-int read_fail_flag(tacho_num* f, int64_t* fail_index) {
+int read_fail_flag(tacho_num* f, int64_t* fail_index, bool may_allocate = true) {
   int32_t flag = INT32_MAX, hang = 0;
   HIP_TRY(hipMemcpyAsync(&flag, f->fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, f->last_stream));
   if (!f->sym->P.ftasks.empty() && f->precision != TACHO_LDLT)
@@ -635,6 +635,11 @@ int read_fail_flag(tacho_num* f, int64_t* fail_index) {
     // factors, which do not depend on it.
     f->fp32_fail_col = flag;
     int64_t fi = -1;
+    if (!f->fallback && !may_allocate) {
+      f->last_status = TACHO_ERR_NOMEM;
+      return fail(TACHO_ERR_NOMEM, "the FP32 factorization broke down and its FP64 fallback "
+                                   "factor would need device memory; use tacho_solve");
+    }
     const int rc = fp64_fallback(f, f->last_stream, &fi);
     f->last_status = rc;
     f->last_fail = rc == TACHO_OK ? -1 : fi;
@@ -1263,9 +1268,11 @@ int tacho_check_factor(tacho_num_t f, int64_t* fail_index) {
 
 namespace {
 
-// tacho_solve: device blocks are used in place, host blocks staged.
+// tacho_solve and tacho_solve_noalloc.  With `noalloc` the caller's blocks
+// are on the device and used in place, and the refinement scratch is the
+// file-scope device array of kernels.hip instead of the handle's buffer.
 int solve_impl(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t ld, int on_device,
-               void* hip_stream, tacho_solve_info* info) {
+               void* hip_stream, tacho_solve_info* info, bool noalloc) {
   if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
   tacho_sym* h = f->sym;
   const int64_t n = h->S.n;
@@ -1278,12 +1285,25 @@ int solve_impl(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t 
   }
   const bool refine = f->precision == TACHO_FP32;
   const bool dense_ld = ld == n;
+  if (noalloc) {
+    if (refine && (!dense_ld || b == x))
+      return fail(TACHO_ERR_INVALID, "tacho_solve_noalloc with an FP32 factor needs ld == n "
+                                     "and x != b");
+    if (refine && nrhs > kRhs)
+      return fail(TACHO_ERR_INVALID, "tacho_solve_noalloc with an FP32 factor takes at most 16 "
+                                     "right-hand sides");
+    if (refine && refine_scratch_bytes(n, nrhs, h->S.nsys) > (int64_t)kNoAllocScratchBytes)
+      return fail(TACHO_ERR_INVALID, "refinement scratch of " +
+                                         std::to_string(refine_scratch_bytes(n, nrhs, h->S.nsys)) +
+                                         " bytes exceeds the no-allocation maximum of " +
+                                         std::to_string(kNoAllocScratchBytes));
+  }
   // A factorization queued without waiting is not checked here when the solve
   // stays on the device in FP64: the solve is queued behind it and
   // tacho_check_factor tells whether the result is valid.
   const bool queue_only = on_device && f->precision != TACHO_FP32;
   if (f->pending && !queue_only) {
-    int rc = read_fail_flag(f, nullptr);
+    int rc = read_fail_flag(f, nullptr, !noalloc);
     if (rc != TACHO_OK) return rc;
   } else if (!f->pending && f->last_status != TACHO_OK) {
     return fail(f->last_status, "no valid factor in this handle");
@@ -1308,10 +1328,16 @@ int solve_impl(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t 
   const int64_t ldi = (bd == b) ? ld : n;
   HIP_TRY(hipEventRecord(f->ev[2], st));
   if (refine) {
-    const int64_t need = refine_scratch_bytes(n, nrhs, h->S.nsys);
-    if (f->rws.bytes < (size_t)need) HIP_TRY(f->rws.alloc(need));
+    void* base = nullptr;
+    if (noalloc) {
+      HIP_TRY(noalloc_scratch(&base));
+    } else {
+      const int64_t need = refine_scratch_bytes(n, nrhs, h->S.nsys);
+      if (f->rws.bytes < (size_t)need) HIP_TRY(f->rws.alloc(need));
+      base = f->rws.p;
+    }
     const int rc = refine_solve(f, bd, xd, nrhs, st, info,
-                                carve_refine_scratch(f->rws.p, n, nrhs, h->S.nsys), true);
+                                carve_refine_scratch(base, n, nrhs, h->S.nsys), !noalloc);
     if (rc != TACHO_OK) return rc;
   } else {
     solve_all<double>(f, bd, ldi, xd, (xd == x) ? ld : n, nrhs, 0, st);
@@ -1337,7 +1363,12 @@ extern "C" {
 
 int tacho_solve(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t ld, int on_device,
                 void* hip_stream, tacho_solve_info* info) {
-  return solve_impl(f, b, x, nrhs, ld, on_device, hip_stream, info);
+  return solve_impl(f, b, x, nrhs, ld, on_device, hip_stream, info, false);
+}
+
+int tacho_solve_noalloc(tacho_num_t f, const double* b, double* x, int64_t nrhs, int64_t ld,
+                        void* hip_stream, tacho_solve_info* info) {
+  return solve_impl(f, b, x, nrhs, ld, 1, hip_stream, info, true);
 }
 
 int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {

@@ -181,4 +181,10 @@ void launch_ldlt_perm(int64_t n, const int32_t* perm, const int32_t* q, int32_t*
 // that a block left unfactored after a failure still holds valid indices).
 void launch_iota(int32_t* p, int64_t n, hipStream_t st);
 
+// Scratch of the no-allocation entry points: a file-scope device array of
+// kNoAllocScratchBytes per GPU.  Returns its address on the current device
+// (looked up once per device).  Calls that overlap on one GPU share it.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch(void** ptr);
+
 }  // namespace tacho

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "device.hpp"
 
@@ -2899,4 +2900,33 @@ TACHO_INSTANTIATE(double)
 TACHO_INSTANTIATE(float)
 
 // ---------------------------------------------------------------------------
+// Device scratch of the entry points that allocate nothing: one file-scope
+// array per GPU (the runtime gives every device its own copy when it loads
+// the code object; each holds it until the process ends).  In host code the
+// array's name is not a device address: its address on a device comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+
+namespace {
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace tacho
