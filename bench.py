@@ -193,6 +193,39 @@ def summarize(r, flops, tol, rho1, rho16, solve_bytes1, solve_bytes16):
     return out
 
 
+def pinv_resident(T, torch, num, A, B1, B16, X1, X16, b1, b16, solve_bytes1, solve_bytes16, tol,
+                  reps=10):
+    """Partitioned-inverse solves on the resident factor of ``num``: the
+    setup (inverse panels) once, then 1- and 16-RHS solves; the handle goes
+    back to the default variant afterwards."""
+    import numpy as np
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T.tacho_set_solve_variant(num, T.TACHO_SOLVE_PARTITIONED_INVERSE)
+    out = {"setup_ms": (time.perf_counter() - t0) * 1e3}
+    for k, B, X, b, sb in ((1, B1, X1, b1, solve_bytes1), (16, B16, X16, b16, solve_bytes16)):
+        ts, iters = [], 0
+        for it in range(reps + 2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = T.tacho_solve(num, B, X, with_info=True)
+            torch.cuda.synchronize()
+            if it >= 2:
+                ts.append((time.perf_counter() - t) * 1e3)
+                iters = max(iters, info["iters"])
+        rho = float(residual(A, X.cpu().numpy(), b).max())
+        ms = float(np.median(ts))
+        out[f"solve_nrhs{k}_ms_p50"] = ms
+        out[f"solve_nrhs{k}_ms_p99"] = pct(ts, 99)
+        out[f"resident_rhs_solves_per_s_nrhs{k}"] = k * 1e3 / ms if rho <= tol else None
+        out[f"solve_nrhs{k}_hbm_frac"] = sb / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS
+        out[f"rel_residual_nrhs{k}"] = rho
+        if num.precision == T.TACHO_FP32:
+            out[f"refine_iters{k}"] = iters
+    T.tacho_set_solve_variant(num, T.TACHO_SOLVE_BLOCK_INVERSE)
+    return out
+
+
 FACTOR_KERNELS = ("k_small", "k_assemble", "k_diag", "k_panel", "k_gemm", "k_gather", "k_front")
 SOLVE_KERNELS = ("k_fwd", "k_bwd", "k_permute")
 
@@ -514,6 +547,13 @@ def single_system(T, torch, A, tag, args, profile=True, steps=None, warmup=None)
         f"{s64['solve_nrhs16_ms_p50']:.2f} ms, rho {s64['rel_residual_nrhs1']:.1e}/"
         f"{s64['rel_residual_nrhs16']:.1e}")
     prof64 = kernel_profile(T, torch, num64, vals, B1, B16, X1, X16) if profile else None
+    if not args.no_pinv:
+        s64["partitioned_inverse"] = pinv_resident(T, torch, num64, A, B1, B16, X1, X16, b1, b16,
+                                                   sbytes(8, 1), sbytes(8, 16), 1e-12)
+        pv = s64["partitioned_inverse"]
+        log(f"[bench] {tag} FP64 partitioned inverse: setup {pv['setup_ms']:.1f} ms, solve1 "
+            f"{pv['solve_nrhs1_ms_p50']:.2f} ms, solve16 {pv['solve_nrhs16_ms_p50']:.2f} ms, rho "
+            f"{pv['rel_residual_nrhs1']:.1e}")
     if not args.no_mixed:
         log(f"[bench] {tag} mixed: FP32 factor + FP64 refinement")
         num32 = T.tacho_factorize(sym32, vals, T.TACHO_FP32)
@@ -531,6 +571,13 @@ def single_system(T, torch, A, tag, args, profile=True, steps=None, warmup=None)
             f"{mixed['solve_nrhs1_ms_p50']:.2f} ms, rho {mixed['rel_residual_nrhs1']:.1e}, "
             f"error vs FP64 {mixed['rel_error_vs_fp64_nrhs1']:.1e}")
         prof32 = kernel_profile(T, torch, num32, vals, B1, B16, Y1, Y16) if profile else None
+        if not args.no_pinv:
+            mixed["partitioned_inverse"] = pinv_resident(T, torch, num32, A, B1, B16, Y1, Y16, b1,
+                                                         b16, sbytes(4, 1), sbytes(4, 16), 1e-10)
+            pv = mixed["partitioned_inverse"]
+            log(f"[bench] {tag} mixed partitioned inverse: setup {pv['setup_ms']:.1f} ms, solve1 "
+                f"{pv['solve_nrhs1_ms_p50']:.2f} ms, solve16 {pv['solve_nrhs16_ms_p50']:.2f} ms, "
+                f"rho {pv['rel_residual_nrhs1']:.1e}")
         del num32
     else:
         prof32 = None
@@ -591,6 +638,8 @@ def main():
     ap.add_argument("--mixed-frac", type=float, default=0.5,
                     help="serve: fraction of factor requests in FP32 + refinement")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-pinv", action="store_true",
+                    help="skip the partitioned-inverse resident-solve measurement")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the plan parameters of the workload (FP64 and FP32) on the "
                          "device and store them in the package's tuning table")

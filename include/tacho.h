@@ -355,6 +355,33 @@ int tacho_solve_noalloc(tacho_num_t num, const double *b, double *x, int64_t nrh
                         void *hip_stream, tacho_solve_info *info);
 
 /*
+ * Solve variant (Tacho section, the SpTRSV variants).  Both apply inverses of
+ * diagonal blocks:
+ *   TACHO_SOLVE_BLOCK_INVERSE (default): each supernode's diagonal part in
+ *     64-column blocks with their stored inverses (the inverted-diagonal-block
+ *     variant); the blocks of one supernode follow each other.
+ *   TACHO_SOLVE_PARTITIONED_INVERSE: the partitioned inverse, L^-1 as the
+ *     product over the levels of the inverses of L's level-l part; every
+ *     supernode's panel [L11; L21] becomes [L11^-1; L21 L11^-1], and a sweep
+ *     is one merged matrix-vector product per supernode, one gather and one
+ *     product launch per level.  Its setup costs about the factorization's
+ *     off-diagonal work (sum over supernodes of m w^2 flops) and as much
+ *     device memory again as the factor L (plus 128 n bytes); its accuracy
+ *     depends on the condition of each supernode's L11.
+ * tacho_set_solve_variant selects the variant of later tacho_solve calls on
+ * `num`.  Choosing TACHO_SOLVE_PARTITIONED_INVERSE waits for the handle's
+ * factorization, builds the inverse panels on hip_stream and waits for them;
+ * every later factorization of the handle (tacho_refactorize) rebuilds them on
+ * its stream.  Cholesky handles (TACHO_FP64, TACHO_FP32) only: TACHO_LDLT
+ * returns TACHO_ERR_INVALID, as does an unknown variant; TACHO_ERR_NOMEM if
+ * the extra memory exceeds options.hbm_budget_bytes.  An FP32 handle's
+ * refinement solves use it too; its FP64 fallback factor keeps the default.
+ */
+#define TACHO_SOLVE_BLOCK_INVERSE 2
+#define TACHO_SOLVE_PARTITIONED_INVERSE 3
+int tacho_set_solve_variant(tacho_num_t num, int variant, void *hip_stream);
+
+/*
  * Copy the factor L (of P A P^T, FP64 or FP32 widened to FP64) to host CSC
  * arrays as stored: Lp int64[n+1], Li int32[nnz_factor], Lx
  * float64[nnz_factor]; every column sorted ascending with the diagonal
@@ -401,7 +428,8 @@ int tacho_last_times(tacho_num_t num, double *factor_ms, double *solve_ms);
 #define TACHO_K_PERMUTE 8     /* right-hand side / solution permutation */
 #define TACHO_K_REFINE 9      /* FP64 residual and norms of the refinement */
 #define TACHO_K_FRONT 10      /* dataflow factorization of a level's large fronts */
-#define TACHO_PROFILE_KINDS 11
+#define TACHO_K_PINV 11       /* partitioned-inverse setup (tacho_set_solve_variant) */
+#define TACHO_PROFILE_KINDS 12
 
 /* enable = 1 clears the counters and starts recording; 0 stops. */
 int tacho_profile(tacho_num_t num, int enable);

@@ -30,7 +30,9 @@ TACHO_FP32_IR = 1
 TACHO_FP32 = TACHO_FP32_IR
 TACHO_LDLT = 2
 TACHO_DEBUG_SOLVE_GIVE_UP = 1
-TACHO_PROFILE_KINDS = 11
+TACHO_PROFILE_KINDS = 12
+TACHO_SOLVE_BLOCK_INVERSE = 2
+TACHO_SOLVE_PARTITIONED_INVERSE = 3
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -125,6 +127,7 @@ def _load():
                                        _vp, ctypes.POINTER(tacho_solve_info)]),
         "tacho_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64,
                                                _vp, ctypes.POINTER(tacho_solve_info)]),
+        "tacho_set_solve_variant": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
         "tacho_get_factor": (ctypes.c_int, [_vp, _i64p, _i32p, _f64p]),
         "tacho_get_ldlt": (ctypes.c_int, [_vp, _f64p, _f64p, _i32p]),
         "tacho_last_times": (ctypes.c_int, [_vp, _f64p, _f64p]),
@@ -444,6 +447,12 @@ def tacho_solve_noalloc(num: NumericHandle, b, x, stream=None, with_info: bool =
     if with_info:
         return x, _info_dict(num, info, rr, fb, nrhs)
     return x
+
+
+def tacho_set_solve_variant(num: NumericHandle, variant: int, stream=None) -> None:
+    """Select the solve variant of later solves on ``num``
+    (TACHO_SOLVE_BLOCK_INVERSE or TACHO_SOLVE_PARTITIONED_INVERSE)."""
+    _check(_load().tacho_set_solve_variant(num.ptr, int(variant), _stream_ptr(stream)))
 
 
 def tacho_get_factor(num: NumericHandle):

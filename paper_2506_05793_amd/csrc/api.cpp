@@ -144,6 +144,9 @@ struct tacho_sym {
   std::unique_ptr<Plan> P1;
   DBuf d1_small, d1_asm, d1_asm_rng, d1_diag, d1_panel, d1_probs, d1_tiles;
   DevSym view1{};
+  // partitioned-inverse solves: their plan, built on first use
+  std::unique_ptr<PinvPlan> Q;
+  DBuf dq_setup, dq_frow, dq_bcol;
 };
 
 // Per-launch timing of the library's kernels on the caller's stream (hipEvents
@@ -245,6 +248,8 @@ struct tacho_num {
   hipStream_t last_solve_stream = nullptr;  // stream of the last solve (queued or finished)
   bool solve_queued = false;      // a solve was queued without reading its hang flag
   hipGraphExec_t fgraph = nullptr;  // captured factorization launch sequence
+  int solve_variant = TACHO_SOLVE_BLOCK_INVERSE;
+  DBuf Z, yfwd;                   // partitioned inverse (layout of L) and forward result rows
   ~tacho_num() {
     if (fgraph) (void)hipGraphExecDestroy(fgraph);
     for (auto& e : ev)
@@ -480,6 +485,20 @@ int ensure_stepwise(tacho_sym* h) {
   return TACHO_OK;
 }
 
+int ensure_pinv(tacho_sym* h) {
+  std::lock_guard<std::mutex> lock(h->mu);
+  if (h->Q) return TACHO_OK;
+  std::unique_ptr<PinvPlan> Q(new PinvPlan());
+  build_pinv_plan(h->S, *Q);
+  if ((int64_t)Q->setup.size() > INT32_MAX || (int64_t)Q->frow.size() > INT32_MAX)
+    return fail(TACHO_ERR_INVALID, "too many partitioned-inverse tiles");
+  HIP_TRY(upload(h->dq_setup, Q->setup));
+  HIP_TRY(upload(h->dq_frow, Q->frow));
+  HIP_TRY(upload(h->dq_bcol, Q->bcol));
+  h->Q = std::move(Q);
+  return TACHO_OK;
+}
+
 size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
 
 bool valid_precision(int precision) {
@@ -667,6 +686,24 @@ int read_fail_flag(tacho_num* f, int64_t* fail_index, bool may_allocate = true) 
   return TACHO_OK;
 }
 
+// Partitioned-inverse setup for the factor in f: Z = [I; L21] per front,
+// then the right-to-left block-column steps of the plan.
+template <typename T>
+void run_pinv_setup(tacho_num* f, hipStream_t st) {
+  tacho_sym* h = f->sym;
+  const PinvPlan& Q = *h->Q;
+  const DevSym& S = h->view;
+  T* Z = f->Z.as<T>();
+  const T* L = f->L.as<T>();
+  const int pe = f->prof.begin(st);
+  launch_pinv_init<T>(S, Z, L, h->dq_bcol.as<FrontTile>(), (int64_t)Q.bcol.size(), st);
+  const PinvTask* tasks = h->dq_setup.as<PinvTask>();
+  for (size_t q = 0; q + 1 < Q.setup_ptr.size(); ++q)
+    launch_pinv_step<T>(S, Z, L, f->winv.as<T>(), tasks + Q.setup_ptr[q],
+                        Q.setup_ptr[q + 1] - Q.setup_ptr[q], st);
+  f->prof.end(pe, st, TACHO_K_PINV, Q.flops, 3.0 * sizeof(T) * (double)h->P.L_elems);
+}
+
 // Device work of one factorization after the values are resident: failure
 // flag reset, value gather (and for FP32 the scaling and the FP64 values of
 // the refinement residual), then every level's launches.
@@ -739,6 +776,12 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
     enqueue_factor(f, st);
   }
   HIP_TRY(hipEventRecord(f->ev[1], st));
+  if (f->solve_variant == TACHO_SOLVE_PARTITIONED_INVERSE) {
+    if (f->precision == TACHO_FP32)
+      run_pinv_setup<float>(f, st);
+    else
+      run_pinv_setup<double>(f, st);
+  }
   HIP_TRY(hipGetLastError());
   f->pending = true;
   f->last_stream = st;
@@ -867,6 +910,31 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   // sweep gives up at once (the kernels still run to the end)
   if (h->opt.debug_flags & TACHO_DEBUG_SOLVE_GIVE_UP) launch_fill_i32(hang, 1, 1, st);
   f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
+  if (f->solve_variant == TACHO_SOLVE_PARTITIONED_INVERSE) {
+    // one gather and one merged product per level and sweep; the forward
+    // result goes to yfwd, the solution back into y
+    const PinvPlan& Q = *h->Q;
+    const T* Z = f->Z.as<T>();
+    T* yf = f->yfwd.as<T>();
+    T* uv = f->uvec.as<T>();
+    const int32_t* lv = h->d_levels.as<int32_t>();
+    const FrontTile* fr = h->dq_frow.as<FrontTile>();
+    const FrontTile* bc = h->dq_bcol.as<FrontTile>();
+    pe = f->prof.begin(st);
+    for (int32_t lvl = 0; lvl < S.nlevels; ++lvl)
+      launch_pinv_fwd<T>(V, Z, y, yf, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
+                         fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl], nrhs, st);
+    f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
+    pe = f->prof.begin(st);
+    for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl)
+      launch_pinv_bwd<T>(V, Z, yf, y, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
+                         bc + Q.bcol_ptr[lvl], Q.bcol_ptr[lvl + 1] - Q.bcol_ptr[lvl], nrhs, st);
+    f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
+    pe = f->prof.begin(st);
+    launch_solve_out<T>(Vout, y, x, ldx, nrhs, scale, accumulate, st);
+    f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
+    return;
+  }
   const WaveItem* items = h->d_lwave.as<WaveItem>();
   const int32_t* large = h->d_llarge.as<int32_t>();
   pe = f->prof.begin(st);
@@ -1371,6 +1439,45 @@ int tacho_solve_noalloc(tacho_num_t f, const double* b, double* x, int64_t nrhs,
   return solve_impl(f, b, x, nrhs, ld, 1, hip_stream, info, true);
 }
 
+int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  if (variant != TACHO_SOLVE_BLOCK_INVERSE && variant != TACHO_SOLVE_PARTITIONED_INVERSE)
+    return fail(TACHO_ERR_INVALID, "unknown solve variant " + std::to_string(variant));
+  if (variant == f->solve_variant) return TACHO_OK;
+  if (variant == TACHO_SOLVE_BLOCK_INVERSE) {
+    f->solve_variant = variant;
+    return TACHO_OK;
+  }
+  if (f->precision == TACHO_LDLT)
+    return fail(TACHO_ERR_INVALID, "the partitioned inverse needs a Cholesky factor");
+  if (f->pending) {
+    const int rc = read_fail_flag(f, nullptr);
+    if (rc != TACHO_OK) return rc;
+  } else if (f->last_status != TACHO_OK) {
+    return fail(f->last_status, "no valid factor in this handle");
+  }
+  tacho_sym* h = f->sym;
+  const size_t es = elem_size(f->precision);
+  const size_t zbytes = es * (size_t)std::max<int64_t>(h->P.L_elems, 1);
+  const size_t ybytes = (size_t)kRowBytes * (size_t)std::max<int64_t>(h->S.n, 1);
+  if (h->opt.hbm_budget_bytes > 0 &&
+      (uint64_t)numeric_bytes(h, f->precision) + zbytes + ybytes > h->opt.hbm_budget_bytes)
+    return fail(TACHO_ERR_NOMEM, "the partitioned inverse would exceed the HBM budget");
+  int rc = ensure_pinv(h);
+  if (rc != TACHO_OK) return rc;
+  if (f->Z.bytes < zbytes) HIP_TRY(f->Z.alloc(zbytes));
+  if (f->yfwd.bytes < ybytes) HIP_TRY(f->yfwd.alloc(ybytes));
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (f->precision == TACHO_FP32)
+    run_pinv_setup<float>(f, st);
+  else
+    run_pinv_setup<double>(f, st);
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipGetLastError());
+  f->solve_variant = variant;
+  return TACHO_OK;
+}
+
 int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
   if (!f || !Lp || !Li || !Lx) return fail(TACHO_ERR_INVALID, "NULL argument");
   if (f->pending) {
@@ -1487,7 +1594,7 @@ int tacho_profile_read(tacho_num_t f, int kind, int64_t* launches, double* ms, d
 const char* tacho_kernel_name(int kind) {
   static const char* names[TACHO_PROFILE_KINDS] = {
       "k_small", "k_assemble", "k_diag", "k_panel", "k_gemm",
-      "k_gather", "k_fwd", "k_bwd", "k_permute", "k_residual", "k_front"};
+      "k_gather", "k_fwd", "k_bwd", "k_permute", "k_residual", "k_front", "k_pinv"};
   return kind >= 0 && kind < TACHO_PROFILE_KINDS ? names[kind] : "unknown";
 }
 

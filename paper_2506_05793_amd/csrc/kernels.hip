@@ -2498,6 +2498,258 @@ __global__ __launch_bounds__(kThreads) void k_level_bwd(DevSym S, const T* L, co
 }
 
 // ---------------------------------------------------------------------------
+// Partitioned inverse (SpTRSV variant 3 of the Tacho section).  Z holds, in
+// the layout of L, every supernode's [L11^-1; L21 L11^-1] (PinvPlan).
+
+// Z = [I; L21] before the setup steps: one workgroup per 64-column tile of a
+// front (rows past m stay zero).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pinv_init(DevSym S, T* Z, const T* L,
+                                                        const FrontTile* tiles) {
+  const FrontTile ft = tiles[blockIdx.x];
+  const int s = ft.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s], c0 = kPanel * ft.t, kb = min(kPanel, w - c0);
+  const T* Lp = L + S.L_off[s];
+  T* Zp = Z + S.L_off[s];
+  for (int t = threadIdx.x; t < ld * kb; t += kThreads) {
+    const int c = t / ld, r = t - c * ld;
+    const int64_t q = r + (int64_t)(c0 + c) * ld;
+    Zp[q] = r < w ? (r == c0 + c ? T(1) : T(0)) : (r < m ? Lp[q] : T(0));
+  }
+}
+
+// One setup task (PinvTask): tile (a, i) of front s, 64 x 64, wave v owning
+// rows 16v..16v+15.  R_ai -= Z_aj L_ji on the matrix cores; when block
+// column i has all its terms, Z_ai = R_ai W_ii, with W_ii the stored inverse
+// of the diagonal block, or for a front without one (m <= kSmallMax, one
+// block) by substitution through L_ii, columns right to left.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pinv_step(DevSym S, T* Z, const T* L,
+                                                        const T* winv, const PinvTask* tasks) {
+  typedef typename Vec4<T>::type V4;
+  __shared__ T Rs[kPanel][kPanel + 1];
+  const PinvTask tk = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s];
+  const T* Lp = L + S.L_off[s];
+  T* Zp = Z + S.L_off[s];
+  const int r0 = kPanel * tk.a, nrows = min(kPanel, m - r0);
+  const int c0 = kPanel * tk.i, kbi = min(kPanel, w - c0);
+  const int li = 16 * wave + (lane & 15), lk = lane >> 4, col = lane & 15;
+  V4 acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * wave + mfma_row<T>(lane, v), cc = 16 * nb + col;
+      acc[nb][v] = (row < nrows && cc < kbi) ? Zp[(r0 + row) + (int64_t)(c0 + cc) * ld] : T(0);
+    }
+  if (tk.j >= 0) {
+    const int j0 = kPanel * tk.j, kbj = min(kPanel, w - j0);
+    const int arow = r0 + min(li, nrows - 1);
+    const T amask = li < nrows ? T(1) : T(0);
+#pragma unroll 4
+    for (int q = 0; q < 16; ++q) {
+      const int k = 4 * q + lk, kc = j0 + min(k, kbj - 1);
+      const T av = -Zp[arow + (int64_t)kc * ld] * (k < kbj ? amask : T(0));
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int cc = 16 * nb + col;
+        const T bv = Lp[kc + (int64_t)(c0 + min(cc, kbi - 1)) * ld] * ((k < kbj && cc < kbi) ? T(1) : T(0));
+        acc[nb] = mfma16(av, bv, acc[nb]);
+      }
+    }
+  }
+  if (tk.j < 0 || tk.i == tk.j - 1) {
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Rs[16 * wave + mfma_row<T>(lane, v)][16 * nb + col] = acc[nb][v];
+    __syncthreads();
+    if (S.wbase[s] >= 0) {
+      const T* Wb = winv + S.woff[S.wbase[s] + tk.i];  // W[k][c] = Wb[c * kbi + k]
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) acc[nb] = V4{0, 0, 0, 0};
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int k = 4 * q + lk;
+        const T av = Rs[li][k];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const int cc = 16 * nb + col;
+          const bool ok = k < kbi && cc < kbi;
+          const T bv = Wb[ok ? cc * kbi + k : 0] * (ok ? T(1) : T(0));
+          acc[nb] = mfma16(av, bv, acc[nb]);
+        }
+      }
+    } else {
+      if (tid < nrows) {
+        for (int c = kbi - 1; c >= 0; --c) {
+          T v = Rs[tid][c];
+          for (int k = c + 1; k < kbi; ++k) v -= Rs[tid][k] * Lp[(c0 + k) + (int64_t)(c0 + c) * ld];
+          Rs[tid][c] = v / Lp[(c0 + c) + (int64_t)(c0 + c) * ld];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[nb][v] = Rs[16 * wave + mfma_row<T>(lane, v)][16 * nb + col];
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * wave + mfma_row<T>(lane, v), cc = 16 * nb + col;
+      if (row < nrows && cc < kbi) Zp[(r0 + row) + (int64_t)(c0 + cc) * ld] = acc[nb][v];
+    }
+}
+
+// Forward sweep, one level, step 1: each front's vector z = [y_s; 0] plus
+// its children's update vectors (pull map), written back over y_s (pivot
+// rows) and u_s (the other rows).  One workgroup per front.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_gather_fwd(DevSym S, T* y, T* uvec,
+                                                              const int32_t* fronts) {
+  const int s = fronts[blockIdx.x];
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  for (int i = threadIdx.x; i < m; i += kThreads) {
+    const int64_t q = S.rows_ptr[s] + i;
+    T z[NR];
+    {
+      const T* yr = y + (int64_t)(f + (i < w ? i : 0)) * kRowLd<T>;
+      const T own = i < w ? T(1) : T(0);
+#pragma unroll
+      for (int c = 0; c < NR; ++c) z[c] = yr[c] * own;
+    }
+    for (int p = S.pull_ptr[q]; p < S.pull_ptr[q + 1]; ++p) {
+      const T* ur = uvec + (int64_t)S.pull_src[p] * kRowLd<T>;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) z[c] += ur[c];
+    }
+    T* out = i < w ? y + (int64_t)(f + i) * kRowLd<T> : uvec + (S.u_off[s] + (i - w)) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) out[c] = z[c];
+  }
+}
+
+// Forward sweep, one level, step 2: 64 rows of Z_s times z_s (pivot rows of
+// y) on the matrix cores (16 rows x 16 right-hand sides per wave); rows < w
+// are the front's solution rows (to yout), the others are subtracted from
+// the update vector in place.  Rows of Z11 see only columns up to their own.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_fwd(DevSym S, const T* Z, const T* y, T* yout,
+                                                       T* uvec, const FrontTile* tiles) {
+  typedef typename Vec4<T>::type V4;
+  const FrontTile ft = tiles[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s = ft.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s];
+  const T* Zp = Z + S.L_off[s];
+  const int r0 = kPanel * ft.t, nrows = min(kPanel, m - r0);
+  const int kend = min(w, r0 + kPanel);
+  const int li = 16 * wave + (lane & 15), lk = lane >> 4, col = lane & 15;
+  const int arow = r0 + min(li, nrows - 1);
+  const T amask = li < nrows ? T(1) : T(0);
+  const int bcol = col < NR ? col : NR - 1;
+  const T cmask = col < NR ? T(1) : T(0);
+  V4 acc = V4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < kend; k0 += kPanel) {
+    T a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = k0 + 4 * q + lk;
+      a[q] = Zp[arow + (int64_t)min(k, kend - 1) * ld] * (k < kend ? amask : T(0));
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = k0 + 4 * q + lk;
+      const T b = y[(int64_t)(f + min(k, kend - 1)) * kRowLd<T> + bcol] * (k < kend ? cmask : T(0));
+      acc = mfma16(a[q], b, acc);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int i = r0 + 16 * wave + mfma_row<T>(lane, v);
+    if (i - r0 < nrows && col < NR) {
+      if (i < w) {
+        yout[(int64_t)(f + i) * kRowLd<T> + col] = acc[v];
+      } else {
+        T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T> + col;
+        *ur = *ur - acc[v];
+      }
+    }
+  }
+}
+
+// Backward sweep, one level, step 1: the solution rows the fronts' other
+// rows refer to (their ancestors', final), gathered into the update vectors.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_gather_bwd(DevSym S, const T* x, T* uvec,
+                                                              const int32_t* fronts) {
+  const int s = fronts[blockIdx.x];
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int32_t* rws = S.rows + S.rows_ptr[s];
+  for (int i = w + threadIdx.x; i < m; i += kThreads) {
+    const T* xr = x + (int64_t)rws[i] * kRowLd<T>;
+    T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) ur[c] = xr[c];
+  }
+}
+
+// Backward sweep, one level, step 2: columns [64t, 64t + kb) of the front's
+// solution, x = Z11^T yfwd_s - Z21^T x_rows, over the rows from 64t on in
+// chunks of 64 (Z tiles staged through LDS with coalesced column reads).
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, const T* yfwd,
+                                                       const T* uvec, T* x,
+                                                       const FrontTile* tiles) {
+  typedef typename Vec4<T>::type V4;
+  __shared__ T Ls[kPanel * kDiagLd];
+  __shared__ T Vs[kPanel * 16];
+  const FrontTile ft = tiles[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = ft.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s];
+  const T* Zp = Z + S.L_off[s];
+  const int c0 = kPanel * ft.t, kb = min(kPanel, w - c0);
+  const int li = 16 * wave + (lane & 15), lk = lane >> 4, col = lane & 15;
+  V4 acc = V4{0, 0, 0, 0};
+  for (int i0 = c0; i0 < m; i0 += kPanel) {
+    const int kw = min(kPanel, m - i0);
+    const int rr = min(lane, kw - 1);
+    const T rmask = lane < kw ? T(1) : T(0);
+#pragma unroll
+    for (int c4 = 0; c4 < 16; ++c4) {
+      const int cc = wave * 16 + c4;
+      Ls[cc * kDiagLd + lane] = Zp[(i0 + rr) + (int64_t)(c0 + min(cc, kb - 1)) * ld] * (cc < kb ? rmask : T(0));
+    }
+    for (int t = tid; t < kPanel * 16; t += kThreads) {
+      const int i = i0 + (t >> 4), c = t & 15;
+      T v = T(0);
+      if (i < m && c < NR)
+        v = i < w ? yfwd[(int64_t)(f + i) * kRowLd<T> + c] : -uvec[(S.u_off[s] + (i - w)) * kRowLd<T> + c];
+      Vs[t] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = 4 * q + lk;
+      acc = mfma16(Ls[li * kDiagLd + i], Vs[i * 16 + col], acc);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int c = 16 * wave + mfma_row<T>(lane, v);
+    if (c < kb && col < NR) x[(int64_t)(f + c0 + c) * kRowLd<T> + col] = acc[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 refinement: r = b - A x with the full symmetric CSR whose values come
 // from the lower triangle (mirror index), one thread per row and column.
 // r = b - A x for up to 16 right-hand sides per pass, with x given by rows
@@ -2807,6 +3059,47 @@ void launch_level_bwd(const DevSym& S, const T* L, const T* winv, T* y, T* part,
 }
 
 template <typename T>
+void launch_pinv_init(const DevSym& S, T* Z, const T* L, const FrontTile* tiles, int64_t count,
+                      hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_pinv_init<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, Z, L, tiles);
+}
+
+template <typename T>
+void launch_pinv_step(const DevSym& S, T* Z, const T* L, const T* winv, const PinvTask* tasks,
+                      int64_t count, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_pinv_step<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, Z, L, winv, tasks);
+}
+
+template <typename T>
+void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
+                     int64_t nfronts, const FrontTile* tiles, int64_t ntiles, int nrhs,
+                     hipStream_t st) {
+  if (nfronts <= 0) return;
+  if (nrhs == 1) {
+    hipLaunchKernelGGL((k_pinv_gather_fwd<T, 1>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, y, uvec, fronts);
+    hipLaunchKernelGGL((k_pinv_fwd<T, 1>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tiles);
+  } else {
+    hipLaunchKernelGGL((k_pinv_gather_fwd<T, 16>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, y, uvec, fronts);
+    hipLaunchKernelGGL((k_pinv_fwd<T, 16>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tiles);
+  }
+}
+
+template <typename T>
+void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, T* uvec,
+                     const int32_t* fronts, int64_t nfronts, const FrontTile* tiles,
+                     int64_t ntiles, int nrhs, hipStream_t st) {
+  if (nfronts <= 0) return;
+  if (nrhs == 1) {
+    hipLaunchKernelGGL((k_pinv_gather_bwd<T, 1>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, x, uvec, fronts);
+    hipLaunchKernelGGL((k_pinv_bwd<T, 1>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, yfwd, uvec, x, tiles);
+  } else {
+    hipLaunchKernelGGL((k_pinv_gather_bwd<T, 16>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, x, uvec, fronts);
+    hipLaunchKernelGGL((k_pinv_bwd<T, 16>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, yfwd, uvec, x, tiles);
+  }
+}
+
+template <typename T>
 void launch_solve_out(const DevSym& S, const T* y, double* x, int64_t ldx, int nrhs,
                       const double* scale, int accumulate, hipStream_t st) {
   if (S.n <= 0) return;
@@ -2867,6 +3160,14 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
                                 hipStream_t);                                                    \
   template void launch_packed<T>(const DevSym&, const DevNum<T>&, T*, const int32_t*, int64_t,    \
                                  hipStream_t);                                                   \
+  template void launch_pinv_init<T>(const DevSym&, T*, const T*, const FrontTile*, int64_t,       \
+                                    hipStream_t);                                                \
+  template void launch_pinv_step<T>(const DevSym&, T*, const T*, const T*, const PinvTask*,       \
+                                    int64_t, hipStream_t);                                       \
+  template void launch_pinv_fwd<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t,  \
+                                   const FrontTile*, int64_t, int, hipStream_t);                 \
+  template void launch_pinv_bwd<T>(const DevSym&, const T*, const T*, T*, T*, const int32_t*,     \
+                                   int64_t, const FrontTile*, int64_t, int, hipStream_t);        \
   template void launch_leaf<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,          \
                                hipStream_t);                                                     \
   template void launch_assemble<T>(const DevSym&, const DevNum<T>&, const AsmItem*, int64_t,      \

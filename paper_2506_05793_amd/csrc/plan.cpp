@@ -707,4 +707,47 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
   return kOk;
 }
 
+void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
+  const int32_t ns = S.ns;
+  Q.setup.clear();
+  Q.setup_ptr.assign(1, 0);
+  Q.flops = 0;
+  int32_t nbmax = 0;
+  for (int32_t s = 0; s < ns; ++s) nbmax = std::max(nbmax, (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel);
+  for (int32_t q = 0; q < nbmax; ++q) {
+    for (int32_t s = 0; s < ns; ++s) {
+      const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+      const int32_t nb = (w + kPanel - 1) / kPanel, nt = (m + kPanel - 1) / kPanel;
+      if (q >= nb) continue;
+      if (q == 0) {
+        for (int32_t a = nb - 1; a < nt; ++a) Q.setup.push_back({s, a, nb - 1, -1});
+        continue;
+      }
+      const int32_t j = nb - q;  // finished by the previous launch
+      for (int32_t i = 0; i < j; ++i) {
+        if (i == j - 1) Q.setup.push_back({s, j - 1, i, -1});  // nothing from block j
+        for (int32_t a = j; a < nt; ++a) {
+          Q.setup.push_back({s, a, i, j});
+          Q.flops += 2.0 * kPanel * kPanel * std::min<int32_t>(kPanel, w - j * kPanel);
+        }
+      }
+    }
+    Q.setup_ptr.push_back((int64_t)Q.setup.size());
+  }
+  Q.frow.clear();
+  Q.bcol.clear();
+  Q.frow_ptr.assign(1, 0);
+  Q.bcol_ptr.assign(1, 0);
+  for (int32_t h = 0; h < S.nlevels; ++h) {
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      const int32_t s = S.level_list[q];
+      const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+      for (int32_t a = 0; a * kPanel < m; ++a) Q.frow.push_back({s, a});
+      for (int32_t c = 0; c * kPanel < w; ++c) Q.bcol.push_back({s, c});
+    }
+    Q.frow_ptr.push_back((int64_t)Q.frow.size());
+    Q.bcol_ptr.push_back((int64_t)Q.bcol.size());
+  }
+}
+
 }  // namespace tacho

@@ -227,4 +227,34 @@ TACHO_HOST_DEVICE inline int front_row_tile(int w, int j, int r) {
 int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode = 0,
                const PlanTuning& tune = PlanTuning());
 
+// Partitioned inverse (SpTRSV variant 3 of the Tacho section).  Every
+// supernode's panel [L11; L21] (m x w, the layout of L) is replaced in a
+// second buffer by Z = [L11^-1; L21 L11^-1], the solution of Z L11 = [I; L21],
+// so that a sweep applies one product per supernode.  Z is formed right to
+// left in 64-column blocks j: Z_j = (B_j - sum_{k > j} Z_k L_kj) W_j with W_j
+// = L_jj^-1 the factorization's diagonal-block inverse and B = [I; L21].
+// Row tile a (rows [64a, 64a + 64) of the panel) of block column i is
+// nonzero only for a >= i, and Z_ak is nonzero only for a >= k.
+struct PinvTask {
+  int32_t s, a, i, j;  // tile (a, i) of front s: R_ai -= Z_aj L_ji, then Z_ai = R_ai W_ii if
+                       // i == j - 1; j < 0: Z_ai = R_ai W_ii alone
+};
+struct FrontTile {
+  int32_t s, t;  // front s, 64-row (forward) or 64-column (backward) tile t
+};
+struct PinvPlan {
+  // setup: launch q runs tasks [setup_ptr[q], setup_ptr[q + 1]); launch 0
+  // scales every front's last block column, launch q >= 1 applies the block
+  // column finished by launch q - 1
+  std::vector<PinvTask> setup;
+  std::vector<int64_t> setup_ptr;
+  // solves, per level h: the row tiles [frow_ptr[h], frow_ptr[h + 1]) of the
+  // level's fronts (forward) and their column tiles [bcol_ptr[h], ...)
+  std::vector<FrontTile> frow, bcol;
+  std::vector<int64_t> frow_ptr, bcol_ptr;
+  double flops = 0;  // setup flops (2 per multiply-add of the tile products)
+};
+
+void build_pinv_plan(const Symbolic& S, PinvPlan& Q);
+
 }  // namespace tacho
