@@ -582,7 +582,8 @@ void run_factor_steps(tacho_num* f, hipStream_t st) {
       case kStepSmall:
         launch_leaf<T>(S, N, small + s.begin, s.tile, st);
         launch_small<T>(S, N, small + s.begin + s.tile, s.packed - s.begin - s.tile, st);
-        launch_packed<T>(S, N, f->winv.as<T>(), small + s.packed, s.end - s.packed, st);
+        launch_packed<T>(S, N, f->winv.as<T>(), small + s.packed, s.packed_big - s.packed, false, st);
+        launch_packed<T>(S, N, f->winv.as<T>(), small + s.packed_big, s.end - s.packed_big, true, st);
         break;
       case kStepAssemble: launch_assemble<T>(S, N, asmi + s.begin, cnt, st); break;
       case kStepDiag: launch_diag<T>(S, N, dia + s.begin, cnt, f->winv.as<T>(), st); break;

@@ -86,9 +86,10 @@ void launch_leaf(const DevSym& S, const DevNum<T>& N, const int32_t* list, int64
 template <typename T>
 void launch_small(const DevSym& S, const DevNum<T>& N, const int32_t* list, int64_t count,
                   hipStream_t st);
+// big: the kernel for fronts up to kPackedMax rows, else up to kPackedMid
 template <typename T>
 void launch_packed(const DevSym& S, const DevNum<T>& N, T* winv, const int32_t* list,
-                   int64_t count, hipStream_t st);
+                   int64_t count, bool big, hipStream_t st);
 // Partitioned inverse (PinvPlan): Z = [I; L21] per front, the setup steps,
 // and one level of each sweep (gather, then the merged product).
 template <typename T>

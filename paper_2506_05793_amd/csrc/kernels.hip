@@ -208,10 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_small(DevSym S, DevNum<T> N, const
 // with the trailing updates of one entry applied together.  Last, the
 // inverse W = L11^-1 that the solves apply to the diagonal block, by forward
 // substitution (one column per thread).
-template <typename T>
+template <typename T, int MAXM>
 __global__ __launch_bounds__(kThreads) void k_packed(DevSym S, DevNum<T> N, T* winv,
                                                      const int32_t* list) {
-  __shared__ T F[kPackedMax * (kPackedMax + 1) / 2];
+  __shared__ T F[MAXM * (MAXM + 1) / 2];
   __shared__ T dinv[kSmallMax];
   const int s = list[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -283,8 +283,8 @@ __global__ __launch_bounds__(kThreads) void k_packed(DevSym S, DevNum<T> N, T* w
     }
   }
   // W, packed by columns (column c at wc(c) = c w - c (c - 1) / 2) in the
-  // space from col(w) on, no longer needed: w (m + 1) <= kPackedMax
-  // (kPackedMax + 1) / 2 for every front of this class, so it fits.
+  // space from col(w) on, no longer needed: the plan sends a front here only
+  // if w (m + 1) <= MAXM (MAXM + 1) / 2, so it fits.
   for (int i = tid; i < w; i += kThreads) dinv[i] = T(1) / F[col(i)];
   __syncthreads();
   T* Wl = F + col(w);
@@ -2900,9 +2900,12 @@ void launch_small(const DevSym& S, const DevNum<T>& N, const int32_t* list, int6
 
 template <typename T>
 void launch_packed(const DevSym& S, const DevNum<T>& N, T* winv, const int32_t* list,
-                   int64_t count, hipStream_t st) {
-  if (count > 0)
-    hipLaunchKernelGGL(k_packed<T>, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, winv, list);
+                   int64_t count, bool big, hipStream_t st) {
+  if (count <= 0) return;
+  if (big)
+    hipLaunchKernelGGL((k_packed<T, kPackedMax>), dim3((unsigned)count), dim3(kThreads), 0, st, S, N, winv, list);
+  else
+    hipLaunchKernelGGL((k_packed<T, kPackedMid>), dim3((unsigned)count), dim3(kThreads), 0, st, S, N, winv, list);
 }
 
 template <typename T>
@@ -3159,7 +3162,7 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
   template void launch_small<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,         \
                                 hipStream_t);                                                    \
   template void launch_packed<T>(const DevSym&, const DevNum<T>&, T*, const int32_t*, int64_t,    \
-                                 hipStream_t);                                                   \
+                                 bool, hipStream_t);                                             \
   template void launch_pinv_init<T>(const DevSym&, T*, const T*, const FrontTile*, int64_t,       \
                                     hipStream_t);                                                \
   template void launch_pinv_step<T>(const DevSym&, T*, const T*, const T*, const PinvTask*,       \

@@ -270,13 +270,23 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       else
         big.push_back(s);
     }
+    // the smaller-LDS instance holds the front and, after it, the inverse of
+    // its diagonal block: w (m + 1) entries
+    auto packed_mid = [&](int32_t s) {
+      const int64_t m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s];
+      return m <= kPackedMid && w * (m + 1) <= (int64_t)kPackedMid * (kPackedMid + 1) / 2;
+    };
     const int64_t p0 = (int64_t)P.small_list.size();
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q)
-      if (packed(S.level_list[q])) P.small_list.push_back(S.level_list[q]);
+      if (packed(S.level_list[q]) && packed_mid(S.level_list[q])) P.small_list.push_back(S.level_list[q]);
+    const int64_t p1 = (int64_t)P.small_list.size();
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q)
+      if (packed(S.level_list[q]) && !packed_mid(S.level_list[q])) P.small_list.push_back(S.level_list[q]);
     if ((int64_t)P.small_list.size() > b0) {
       Step st{kStepSmall, h, b0, (int64_t)P.small_list.size()};
       st.tile = nleaf;
       st.packed = p0;
+      st.packed_big = p1;
       for (int64_t q = b0; q < st.end; ++q) {
         const int32_t s = P.small_list[q];
         st.flops += front_flops(S, s);

@@ -134,12 +134,17 @@ struct Step {
   double elems = 0;  // algorithmic element traffic (reads + writes) of the launch
   int32_t tile = 0;  // update steps: tile size; small-front steps: leading one-thread leaves
   int32_t ticket = 0;  // dataflow front steps: index of the launch's ticket counter
-  int64_t packed = 0;  // small-front steps: [packed, end) go to the packed-LDS kernel
+  int64_t packed = 0;      // small-front steps: [packed, packed_big) go to the packed-LDS
+  int64_t packed_big = 0;  // kernel for m <= kPackedMid, [packed_big, end) to the larger one
 };
 
 constexpr int kSmallMax = 64;     // fronts with m <= kSmallMax go to the LDS kernel
 constexpr int kLeafMax = 16;      // ... leaves with one pivot column and m <= kLeafMax to one thread each
 constexpr int kPackedMax = 128;   // Cholesky fronts with m <= kPackedMax and w <= kSmallMax: packed LDS kernel
+constexpr int kPackedMid = 96;    // ... its smaller-LDS instance: m <= kPackedMid, w (m + 1) <= 96 * 97 / 2
+// every front of the class (w <= kSmallMax) fits with its diagonal-block inverse
+static_assert(kPackedMax * (kPackedMax + 1) / 2 >= kSmallMax * (kPackedMax + 1),
+              "packed front and inverse exceed the LDS array");
 constexpr int kPanel = 64;        // panel width of the blocked large-front path
 constexpr int kOuter = 256;       // outer panel width (trailing updates with K = kOuter)
 constexpr int kPanelRows = 64;    // rows per triangular-solve workgroup
