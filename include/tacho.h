@@ -366,7 +366,8 @@ int tacho_solve_noalloc(tacho_num_t num, const double *b, double *x, int64_t nrh
  *     is one merged matrix-vector product per supernode, one gather and one
  *     product launch per level.  Its setup costs about the factorization's
  *     off-diagonal work (sum over supernodes of m w^2 flops) and as much
- *     device memory again as the factor L (plus 128 n bytes); its accuracy
+ *     device memory again as the factor L (plus 128 n bytes and the sweeps'
+ *     partial products of long supernodes); its accuracy
  *     depends on the condition of each supernode's L11.
  * tacho_set_solve_variant selects the variant of later tacho_solve calls on
  * `num`.  Choosing TACHO_SOLVE_PARTITIONED_INVERSE waits for the handle's

@@ -146,7 +146,7 @@ struct tacho_sym {
   DevSym view1{};
   // partitioned-inverse solves: their plan, built on first use
   std::unique_ptr<PinvPlan> Q;
-  DBuf dq_setup, dq_frow, dq_bcol;
+  DBuf dq_setup, dq_tiles, dq_frow, dq_bcol;
 };
 
 // Per-launch timing of the library's kernels on the caller's stream (hipEvents
@@ -250,6 +250,7 @@ struct tacho_num {
   hipGraphExec_t fgraph = nullptr;  // captured factorization launch sequence
   int solve_variant = TACHO_SOLVE_BLOCK_INVERSE;
   DBuf Z, yfwd;                   // partitioned inverse (layout of L) and forward result rows
+  DBuf zpart, zcnt;               // its sweeps' chunk partial products and arrival counters
   ~tacho_num() {
     if (fgraph) (void)hipGraphExecDestroy(fgraph);
     for (auto& e : ev)
@@ -493,6 +494,7 @@ int ensure_pinv(tacho_sym* h) {
   if ((int64_t)Q->setup.size() > INT32_MAX || (int64_t)Q->frow.size() > INT32_MAX)
     return fail(TACHO_ERR_INVALID, "too many partitioned-inverse tiles");
   HIP_TRY(upload(h->dq_setup, Q->setup));
+  HIP_TRY(upload(h->dq_tiles, Q->tiles));
   HIP_TRY(upload(h->dq_frow, Q->frow));
   HIP_TRY(upload(h->dq_bcol, Q->bcol));
   h->Q = std::move(Q);
@@ -697,7 +699,7 @@ void run_pinv_setup(tacho_num* f, hipStream_t st) {
   T* Z = f->Z.as<T>();
   const T* L = f->L.as<T>();
   const int pe = f->prof.begin(st);
-  launch_pinv_init<T>(S, Z, L, h->dq_bcol.as<FrontTile>(), (int64_t)Q.bcol.size(), st);
+  launch_pinv_init<T>(S, Z, L, h->dq_tiles.as<FrontTile>(), (int64_t)Q.tiles.size(), st);
   const PinvTask* tasks = h->dq_setup.as<PinvTask>();
   for (size_t q = 0; q + 1 < Q.setup_ptr.size(); ++q)
     launch_pinv_step<T>(S, Z, L, f->winv.as<T>(), tasks + Q.setup_ptr[q],
@@ -919,17 +921,19 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
     T* yf = f->yfwd.as<T>();
     T* uv = f->uvec.as<T>();
     const int32_t* lv = h->d_levels.as<int32_t>();
-    const FrontTile* fr = h->dq_frow.as<FrontTile>();
-    const FrontTile* bc = h->dq_bcol.as<FrontTile>();
+    const PinvSweepTask* fr = h->dq_frow.as<PinvSweepTask>();
+    const PinvSweepTask* bc = h->dq_bcol.as<PinvSweepTask>();
+    T* part = f->zpart.as<T>();
+    int32_t* cnt = f->zcnt.as<int32_t>();
     pe = f->prof.begin(st);
     for (int32_t lvl = 0; lvl < S.nlevels; ++lvl)
       launch_pinv_fwd<T>(V, Z, y, yf, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
-                         fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl], nrhs, st);
+                         fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl], part, cnt, nrhs, st);
     f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
     pe = f->prof.begin(st);
     for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl)
-      launch_pinv_bwd<T>(V, Z, yf, y, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
-                         bc + Q.bcol_ptr[lvl], Q.bcol_ptr[lvl + 1] - Q.bcol_ptr[lvl], nrhs, st);
+      launch_pinv_bwd<T>(V, Z, yf, y, bc + Q.bcol_ptr[lvl], Q.bcol_ptr[lvl + 1] - Q.bcol_ptr[lvl], part,
+                         cnt, nrhs, st);
     f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
     pe = f->prof.begin(st);
     launch_solve_out<T>(Vout, y, x, ldx, nrhs, scale, accumulate, st);
@@ -1468,6 +1472,15 @@ int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
   if (rc != TACHO_OK) return rc;
   if (f->Z.bytes < zbytes) HIP_TRY(f->Z.alloc(zbytes));
   if (f->yfwd.bytes < ybytes) HIP_TRY(f->yfwd.alloc(ybytes));
+  {
+    const int64_t slots = std::max<int64_t>(h->Q->slots, 1);
+    const size_t pbytes = es * (size_t)slots * kPanel * kRhs, cbytes = sizeof(int32_t) * (size_t)slots;
+    if (f->zpart.bytes < pbytes) HIP_TRY(f->zpart.alloc(pbytes));
+    if (f->zcnt.bytes < cbytes) {
+      HIP_TRY(f->zcnt.alloc(cbytes));
+      HIP_TRY(clear_device(f->zcnt.p, cbytes));
+    }
+  }
   hipStream_t st = (hipStream_t)hip_stream;
   if (f->precision == TACHO_FP32)
     run_pinv_setup<float>(f, st);

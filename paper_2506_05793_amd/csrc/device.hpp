@@ -91,7 +91,7 @@ template <typename T>
 void launch_packed(const DevSym& S, const DevNum<T>& N, T* winv, const int32_t* list,
                    int64_t count, bool big, hipStream_t st);
 // Partitioned inverse (PinvPlan): Z = [I; L21] per front, the setup steps,
-// and one level of each sweep (gather, then the merged product).
+// and one level of each sweep (forward: gather, then the merged product).
 template <typename T>
 void launch_pinv_init(const DevSym& S, T* Z, const T* L, const FrontTile* tiles, int64_t count,
                       hipStream_t st);
@@ -100,12 +100,11 @@ void launch_pinv_step(const DevSym& S, T* Z, const T* L, const T* winv, const Pi
                       int64_t count, hipStream_t st);
 template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
-                     int64_t nfronts, const FrontTile* tiles, int64_t ntiles, int nrhs,
-                     hipStream_t st);
+                     int64_t nfronts, const PinvSweepTask* tasks, int64_t ntasks, T* part,
+                     int32_t* cnt, int nrhs, hipStream_t st);
 template <typename T>
-void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, T* uvec,
-                     const int32_t* fronts, int64_t nfronts, const FrontTile* tiles,
-                     int64_t ntiles, int nrhs, hipStream_t st);
+void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const PinvSweepTask* tasks,
+                     int64_t ntasks, T* part, int32_t* cnt, int nrhs, hipStream_t st);
 template <typename T>
 void launch_assemble(const DevSym& S, const DevNum<T>& N, const AsmItem* items, int64_t count,
                      hipStream_t st);

@@ -2635,41 +2635,80 @@ __global__ __launch_bounds__(kThreads) void k_pinv_gather_fwd(DevSym S, T* y, T*
   }
 }
 
+// Partial product of a chunked sweep task: chunk c of the tile stores its
+// 64 x 16 values in slot + c; the chunk that arrives last (per-tile counter,
+// which only ever grows by the tile's chunk count per sweep) reads them all
+// back and returns their sum in chunk order in `acc` (true), the others
+// return false.
+template <typename T>
+__device__ inline bool pinv_reduce(typename Vec4<T>::type& acc, T* part, int32_t* cnt, int slot,
+                                   int c, int nch, int* s_last) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15;
+  T* P = part + (int64_t)slot * (kPanel * 16);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    P[(int64_t)c * (kPanel * 16) + (16 * wave + mfma_row<T>(lane, v)) * 16 + col] = acc[v];
+  publish_barrier();
+  if (tid == 0) {
+    release_agent();
+    const int old = __hip_atomic_fetch_add(cnt + slot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_last = (old + 1) % nch == 0;
+    if (*s_last) acquire_agent();
+  }
+  __syncthreads();
+  if (!*s_last) return false;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int idx = (16 * wave + mfma_row<T>(lane, v)) * 16 + col;
+    T sum = T(0);
+    for (int q = 0; q < nch; ++q) sum += P[(int64_t)q * (kPanel * 16) + idx];
+    acc[v] = sum;
+  }
+  return true;
+}
+
 // Forward sweep, one level, step 2: 64 rows of Z_s times z_s (pivot rows of
-// y) on the matrix cores (16 rows x 16 right-hand sides per wave); rows < w
-// are the front's solution rows (to yout), the others are subtracted from
-// the update vector in place.  Rows of Z11 see only columns up to their own.
+// y) on the matrix cores (16 rows x 16 right-hand sides per wave), over one
+// chunk of the columns; rows < w are the front's solution rows (to yout),
+// the others are subtracted from the update vector in place.  Rows of Z11
+// see only the columns up to their own.
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_pinv_fwd(DevSym S, const T* Z, const T* y, T* yout,
-                                                       T* uvec, const FrontTile* tiles) {
+                                                       T* uvec, const PinvSweepTask* tasks,
+                                                       T* part, int32_t* cnt) {
   typedef typename Vec4<T>::type V4;
-  const FrontTile ft = tiles[blockIdx.x];
+  __shared__ int s_last;
+  const PinvSweepTask tk = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int s = ft.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
   const int ld = S.ldL[s];
   const T* Zp = Z + S.L_off[s];
-  const int r0 = kPanel * ft.t, nrows = min(kPanel, m - r0);
+  const int r0 = kPanel * tk.t, nrows = min(kPanel, m - r0);
   const int kend = min(w, r0 + kPanel);
+  const int klo = tk.c * kPinvChunk, khi = min(kend, klo + kPinvChunk);
   const int li = 16 * wave + (lane & 15), lk = lane >> 4, col = lane & 15;
   const int arow = r0 + min(li, nrows - 1);
   const T amask = li < nrows ? T(1) : T(0);
   const int bcol = col < NR ? col : NR - 1;
   const T cmask = col < NR ? T(1) : T(0);
   V4 acc = V4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < kend; k0 += kPanel) {
+  for (int k0 = klo; k0 < khi; k0 += kPanel) {
     T a[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = k0 + 4 * q + lk;
-      a[q] = Zp[arow + (int64_t)min(k, kend - 1) * ld] * (k < kend ? amask : T(0));
+      a[q] = Zp[arow + (int64_t)min(k, khi - 1) * ld] * (k < khi ? amask : T(0));
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = k0 + 4 * q + lk;
-      const T b = y[(int64_t)(f + min(k, kend - 1)) * kRowLd<T> + bcol] * (k < kend ? cmask : T(0));
+      const T b = y[(int64_t)(f + min(k, khi - 1)) * kRowLd<T> + bcol] * (k < khi ? cmask : T(0));
       acc = mfma16(a[q], b, acc);
     }
   }
+  if (tk.slot >= 0 &&
+      !pinv_reduce<T>(acc, part, cnt, tk.slot, tk.c, (kend + kPinvChunk - 1) / kPinvChunk, &s_last))
+    return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = r0 + 16 * wave + mfma_row<T>(lane, v);
@@ -2684,42 +2723,30 @@ __global__ __launch_bounds__(kThreads) void k_pinv_fwd(DevSym S, const T* Z, con
   }
 }
 
-// Backward sweep, one level, step 1: the solution rows the fronts' other
-// rows refer to (their ancestors', final), gathered into the update vectors.
+// Backward sweep, one level: columns [64t, 64t + kb) of the front's
+// solution, x = Z11^T yfwd_s - Z21^T x_rows, over one chunk of the rows from
+// 64t on (Z tiles staged through LDS with coalesced column reads; the rows'
+// solutions, final once the ancestors are done, read in place).
 template <typename T, int NR>
-__global__ __launch_bounds__(kThreads) void k_pinv_gather_bwd(DevSym S, const T* x, T* uvec,
-                                                              const int32_t* fronts) {
-  const int s = fronts[blockIdx.x];
-  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
-  const int32_t* rws = S.rows + S.rows_ptr[s];
-  for (int i = w + threadIdx.x; i < m; i += kThreads) {
-    const T* xr = x + (int64_t)rws[i] * kRowLd<T>;
-    T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T>;
-#pragma unroll
-    for (int c = 0; c < NR; ++c) ur[c] = xr[c];
-  }
-}
-
-// Backward sweep, one level, step 2: columns [64t, 64t + kb) of the front's
-// solution, x = Z11^T yfwd_s - Z21^T x_rows, over the rows from 64t on in
-// chunks of 64 (Z tiles staged through LDS with coalesced column reads).
-template <typename T, int NR>
-__global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, const T* yfwd,
-                                                       const T* uvec, T* x,
-                                                       const FrontTile* tiles) {
+__global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, const T* yfwd, T* x,
+                                                       const PinvSweepTask* tasks, T* part,
+                                                       int32_t* cnt) {
   typedef typename Vec4<T>::type V4;
   __shared__ T Ls[kPanel * kDiagLd];
   __shared__ T Vs[kPanel * 16];
-  const FrontTile ft = tiles[blockIdx.x];
+  __shared__ int s_last;
+  const PinvSweepTask tk = tasks[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int s = ft.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
   const int ld = S.ldL[s];
   const T* Zp = Z + S.L_off[s];
-  const int c0 = kPanel * ft.t, kb = min(kPanel, w - c0);
+  const int32_t* rws = S.rows + S.rows_ptr[s];
+  const int c0 = kPanel * tk.t, kb = min(kPanel, w - c0);
+  const int ilo = c0 + tk.c * kPinvChunk, ihi = min(m, ilo + kPinvChunk);
   const int li = 16 * wave + (lane & 15), lk = lane >> 4, col = lane & 15;
   V4 acc = V4{0, 0, 0, 0};
-  for (int i0 = c0; i0 < m; i0 += kPanel) {
-    const int kw = min(kPanel, m - i0);
+  for (int i0 = ilo; i0 < ihi; i0 += kPanel) {
+    const int kw = min(kPanel, ihi - i0);
     const int rr = min(lane, kw - 1);
     const T rmask = lane < kw ? T(1) : T(0);
 #pragma unroll
@@ -2730,8 +2757,8 @@ __global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, con
     for (int t = tid; t < kPanel * 16; t += kThreads) {
       const int i = i0 + (t >> 4), c = t & 15;
       T v = T(0);
-      if (i < m && c < NR)
-        v = i < w ? yfwd[(int64_t)(f + i) * kRowLd<T> + c] : -uvec[(S.u_off[s] + (i - w)) * kRowLd<T> + c];
+      if (i < ihi && c < NR)
+        v = i < w ? yfwd[(int64_t)(f + i) * kRowLd<T> + c] : -x[(int64_t)rws[i] * kRowLd<T> + c];
       Vs[t] = v;
     }
     __syncthreads();
@@ -2742,6 +2769,9 @@ __global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, con
     }
     __syncthreads();
   }
+  if (tk.slot >= 0 &&
+      !pinv_reduce<T>(acc, part, cnt, tk.slot, tk.c, (m - c0 + kPinvChunk - 1) / kPinvChunk, &s_last))
+    return;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int c = 16 * wave + mfma_row<T>(lane, v);
@@ -3076,30 +3106,26 @@ void launch_pinv_step(const DevSym& S, T* Z, const T* L, const T* winv, const Pi
 
 template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
-                     int64_t nfronts, const FrontTile* tiles, int64_t ntiles, int nrhs,
-                     hipStream_t st) {
+                     int64_t nfronts, const PinvSweepTask* tasks, int64_t ntasks, T* part,
+                     int32_t* cnt, int nrhs, hipStream_t st) {
   if (nfronts <= 0) return;
   if (nrhs == 1) {
     hipLaunchKernelGGL((k_pinv_gather_fwd<T, 1>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, y, uvec, fronts);
-    hipLaunchKernelGGL((k_pinv_fwd<T, 1>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tiles);
+    hipLaunchKernelGGL((k_pinv_fwd<T, 1>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part, cnt);
   } else {
     hipLaunchKernelGGL((k_pinv_gather_fwd<T, 16>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, y, uvec, fronts);
-    hipLaunchKernelGGL((k_pinv_fwd<T, 16>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tiles);
+    hipLaunchKernelGGL((k_pinv_fwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part, cnt);
   }
 }
 
 template <typename T>
-void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, T* uvec,
-                     const int32_t* fronts, int64_t nfronts, const FrontTile* tiles,
-                     int64_t ntiles, int nrhs, hipStream_t st) {
-  if (nfronts <= 0) return;
-  if (nrhs == 1) {
-    hipLaunchKernelGGL((k_pinv_gather_bwd<T, 1>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, x, uvec, fronts);
-    hipLaunchKernelGGL((k_pinv_bwd<T, 1>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, yfwd, uvec, x, tiles);
-  } else {
-    hipLaunchKernelGGL((k_pinv_gather_bwd<T, 16>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, x, uvec, fronts);
-    hipLaunchKernelGGL((k_pinv_bwd<T, 16>), dim3((unsigned)ntiles), dim3(kThreads), 0, st, S, Z, yfwd, uvec, x, tiles);
-  }
+void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const PinvSweepTask* tasks,
+                     int64_t ntasks, T* part, int32_t* cnt, int nrhs, hipStream_t st) {
+  if (ntasks <= 0) return;
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_pinv_bwd<T, 1>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part, cnt);
+  else
+    hipLaunchKernelGGL((k_pinv_bwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part, cnt);
 }
 
 template <typename T>
@@ -3168,9 +3194,10 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
   template void launch_pinv_step<T>(const DevSym&, T*, const T*, const T*, const PinvTask*,       \
                                     int64_t, hipStream_t);                                       \
   template void launch_pinv_fwd<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t,  \
-                                   const FrontTile*, int64_t, int, hipStream_t);                 \
-  template void launch_pinv_bwd<T>(const DevSym&, const T*, const T*, T*, T*, const int32_t*,     \
-                                   int64_t, const FrontTile*, int64_t, int, hipStream_t);        \
+                                   const PinvSweepTask*, int64_t, T*, int32_t*, int,             \
+                                   hipStream_t);                                                 \
+  template void launch_pinv_bwd<T>(const DevSym&, const T*, const T*, T*, const PinvSweepTask*,   \
+                                   int64_t, T*, int32_t*, int, hipStream_t);                     \
   template void launch_leaf<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,          \
                                hipStream_t);                                                     \
   template void launch_assemble<T>(const DevSym&, const DevNum<T>&, const AsmItem*, int64_t,      \

@@ -744,16 +744,28 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
     }
     Q.setup_ptr.push_back((int64_t)Q.setup.size());
   }
+  Q.tiles.clear();
+  for (int32_t s = 0; s < ns; ++s)
+    for (int32_t c = 0; c * kPanel < S.sptr[s + 1] - S.sptr[s]; ++c) Q.tiles.push_back({s, c});
   Q.frow.clear();
   Q.bcol.clear();
   Q.frow_ptr.assign(1, 0);
   Q.bcol_ptr.assign(1, 0);
+  Q.slots = 0;
+  auto add = [&](std::vector<PinvSweepTask>& v, int32_t s, int32_t t, int32_t len) {
+    const int32_t nch = (len + kPinvChunk - 1) / kPinvChunk;
+    const int32_t slot = nch > 1 ? (int32_t)Q.slots : -1;
+    if (nch > 1) Q.slots += nch;
+    for (int32_t c = 0; c < nch; ++c) v.push_back({s, t, c, slot});
+  };
   for (int32_t h = 0; h < S.nlevels; ++h) {
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       const int32_t s = S.level_list[q];
       const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
-      for (int32_t a = 0; a * kPanel < m; ++a) Q.frow.push_back({s, a});
-      for (int32_t c = 0; c * kPanel < w; ++c) Q.bcol.push_back({s, c});
+      // forward: rows of Z11 see only the columns up to their own
+      for (int32_t a = 0; a * kPanel < m; ++a) add(Q.frow, s, a, std::min(w, (a + 1) * kPanel));
+      // backward: Z is zero above a column's diagonal
+      for (int32_t c = 0; c * kPanel < w; ++c) add(Q.bcol, s, c, m - c * kPanel);
     }
     Q.frow_ptr.push_back((int64_t)Q.frow.size());
     Q.bcol_ptr.push_back((int64_t)Q.bcol.size());

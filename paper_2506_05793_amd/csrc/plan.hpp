@@ -245,19 +245,30 @@ struct PinvTask {
                        // i == j - 1; j < 0: Z_ai = R_ai W_ii alone
 };
 struct FrontTile {
-  int32_t s, t;  // front s, 64-row (forward) or 64-column (backward) tile t
+  int32_t s, t;  // front s, 64-column tile t
 };
+// A sweep task: tile t of front s (forward: 64 rows, backward: 64 columns),
+// the chunk c of its reduction dimension (kPinvChunk columns forward, rows
+// backward).  A tile with one chunk writes its result itself (slot < 0);
+// otherwise chunk c stores a partial product in slot + c, and the last of
+// the tile's chunks to finish adds them in chunk order and writes the result.
+struct PinvSweepTask {
+  int32_t s, t, c, slot;
+};
+constexpr int kPinvChunk = 512;
 struct PinvPlan {
   // setup: launch q runs tasks [setup_ptr[q], setup_ptr[q + 1]); launch 0
   // scales every front's last block column, launch q >= 1 applies the block
-  // column finished by launch q - 1
+  // column finished by launch q - 1; `tiles` lists every 64-column tile
   std::vector<PinvTask> setup;
   std::vector<int64_t> setup_ptr;
-  // solves, per level h: the row tiles [frow_ptr[h], frow_ptr[h + 1]) of the
-  // level's fronts (forward) and their column tiles [bcol_ptr[h], ...)
-  std::vector<FrontTile> frow, bcol;
+  std::vector<FrontTile> tiles;
+  // solves, per level h: forward tasks [frow_ptr[h], frow_ptr[h + 1]) and
+  // backward tasks [bcol_ptr[h], bcol_ptr[h + 1])
+  std::vector<PinvSweepTask> frow, bcol;
   std::vector<int64_t> frow_ptr, bcol_ptr;
-  double flops = 0;  // setup flops (2 per multiply-add of the tile products)
+  int64_t slots = 0;  // partial-product slots (and arrival counters) of the sweeps
+  double flops = 0;   // setup flops (2 per multiply-add of the tile products)
 };
 
 void build_pinv_plan(const Symbolic& S, PinvPlan& Q);
