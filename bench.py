@@ -407,6 +407,48 @@ def kernel_stats_summary(stats_csv, out_md, title, command, top=20):
     print("\n".join(lines))
 
 
+def overlap_summary(trace_csv, out_md, title, command):
+    """Device concurrency of a kernel trace: the time during which kernels of
+    two or more queues run at once, and per queue its busy time."""
+    import csv
+    ev = []
+    busy = {}
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            q = r.get("Queue_Id") or r.get("Stream_Id")
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            if b <= a:
+                continue
+            ev.append((a, 1, q))
+            ev.append((b, -1, q))
+            busy[q] = busy.get(q, 0) + (b - a)
+    ev.sort(key=lambda e: (e[0], e[1]))
+    active = {}
+    t_prev, any_ns, multi_ns, depth_ns = None, 0, 0, 0
+    for t, d, q in ev:
+        if t_prev is not None:
+            nq = sum(1 for v in active.values() if v > 0)
+            if nq >= 1:
+                any_ns += t - t_prev
+            if nq >= 2:
+                multi_ns += t - t_prev
+            depth_ns += nq * (t - t_prev)
+        active[q] = active.get(q, 0) + d
+        t_prev = t
+    span = (ev[-1][0] - ev[0][0]) if ev else 0
+    lines = [f"# {title}", "", "Command:", "", "```", command, "```", "",
+             f"Trace span {span / 1e6:.1f} ms; a kernel running {any_ns / 1e6:.1f} ms; kernels of "
+             f"two or more queues at once {multi_ns / 1e6:.1f} ms "
+             f"({100.0 * multi_ns / max(any_ns, 1):.1f}% of the busy time); average queues "
+             f"busy while any is {depth_ns / max(any_ns, 1):.2f}.", "",
+             "| queue | kernel busy ms |", "|---|---|"]
+    for q, v in sorted(busy.items(), key=lambda kv: -kv[1]):
+        lines.append(f"| {q} | {v / 1e6:.1f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"wrote {out_md}")
+
+
 def mfma_summary(csv_path, out_md, title, command):
     """MFMA busy fraction and executed MFMA flops per kernel from one
     rocprofv3 --pmc run of SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F64,
@@ -655,6 +697,8 @@ def main():
                          "from two counter runs and exit")
     ap.add_argument("--kernel-summary", nargs=4, metavar=("STATS_CSV", "OUT_MD", "TITLE", "COMMAND"),
                     help="write a markdown kernel summary from rocprofv3 stats and exit")
+    ap.add_argument("--overlap-summary", nargs=4, metavar=("TRACE_CSV", "OUT_MD", "TITLE", "COMMAND"),
+                    help="write the device-concurrency summary of a kernel trace and exit")
     ap.add_argument("--mfma-summary", nargs=4, metavar=("CSV", "OUT_MD", "TITLE", "COMMAND"),
                     help="write the MFMA utilization summary from one counter run and exit")
     args = ap.parse_args()
@@ -666,6 +710,9 @@ def main():
         return
     if args.mfma_summary:
         mfma_summary(*args.mfma_summary)
+        return
+    if args.overlap_summary:
+        overlap_summary(*args.overlap_summary)
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: every workload is measured on one MI355X "

@@ -340,9 +340,10 @@ int tacho_solve(tacho_num_t num, const double *b, double *x, int64_t nrhs, int64
  *          ld >= n.  With an FP64 factor x may equal b.  With an FP32 factor
  *          (refinement) ld must equal n, x must differ from b, nrhs <= 16,
  *          and the refinement's scratch (8 n nrhs bytes of residual, as many
- *          again for the iterate by rows when nrhs > 1, 17 nsystems nrhs
- *          bytes of norms and mask) must fit the library's fixed device
- *          array of 64 MiB per GPU; otherwise TACHO_ERR_INVALID.
+ *          again for the iterate by rows when nrhs > 1, 1041 nsystems nrhs
+ *          bytes of norms, their partial sums and a mask) must fit the
+ *          library's fixed device array of 64 MiB per GPU; otherwise
+ *          TACHO_ERR_INVALID.
  * The scratch array is shared by every call on a GPU and keeps the last
  * call's contents: calls that overlap on one GPU (different streams or
  * threads) race and must be serialized by the caller.  If refinement would

@@ -983,13 +983,14 @@ struct RefineScratch {
   double* r = nullptr;
   double* xt = nullptr;  // the iterate by rows (several right-hand sides)
   double* nrm = nullptr;
+  double* npart = nullptr;  // partial sums of the norms
   uint8_t* mask = nullptr;
 };
 
 int64_t refine_scratch_bytes(int64_t n, int64_t nrhs, int64_t nsys) {
   const int64_t units = nsys * nrhs;
   const int64_t rows = nrhs > 1 ? n * nrhs : 0;
-  return (int64_t)sizeof(double) * (n * nrhs + rows + 2 * units) + units;
+  return (int64_t)sizeof(double) * (n * nrhs + rows + (2 + kNormParts) * units) + units;
 }
 
 RefineScratch carve_refine_scratch(void* base, int64_t n, int64_t nrhs, int64_t nsys) {
@@ -997,7 +998,8 @@ RefineScratch carve_refine_scratch(void* base, int64_t n, int64_t nrhs, int64_t 
   w.r = static_cast<double*>(base);
   w.xt = w.r + n * nrhs;
   w.nrm = w.xt + (nrhs > 1 ? n * nrhs : 0);
-  w.mask = reinterpret_cast<uint8_t*>(w.nrm + 2 * nsys * nrhs);
+  w.npart = w.nrm + 2 * nsys * nrhs;
+  w.mask = reinterpret_cast<uint8_t*>(w.npart + kNormParts * nsys * nrhs);
   return w;
 }
 
@@ -1043,7 +1045,7 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
   }
   int64_t active = 0;
   for (int64_t u = 0; u < units; ++u) active += H.bad[u] ? 0 : 1;
-  launch_segnorms(nsys, sysp, b, n, nrhs, nrm + units, st);
+  launch_segnorms(nsys, sysp, b, n, nrhs, nrm + units, ws.npart, st);
   if (active > 0) solve_all<float>(f, b, n, x, n, nrhs, 0, st);
   const double tol = h->opt.refine_tol > 0 ? h->opt.refine_tol : 1e-10;
   const int maxit = h->opt.refine_max > 0 ? h->opt.refine_max : 10;
@@ -1054,7 +1056,7 @@ int refine_solve(tacho_num* f, const double* b, double* x, int64_t nrhs, hipStre
     const int pe = f->prof.begin(st);
     launch_residual(n, h->d_rowptr.as<int64_t>(), h->d_colind.as<int32_t>(),
                     f->fullvals.as<double>(), b, n, x, n, r, nrhs, ws.xt, st);
-    launch_segnorms(nsys, sysp, r, n, nrhs, nrm, st);
+    launch_segnorms(nsys, sysp, r, n, nrhs, nrm, ws.npart, st);
     f->prof.end(pe, st, TACHO_K_REFINE, (2.0 * nnz + 2.0 * n) * nrhs,
                 nnz * 12.0 + 8.0 * n + 8.0 * 3.0 * n * nrhs);
     HIP_TRY(hipMemcpyAsync(hn, nrm, sizeof(double) * 2 * units, hipMemcpyDeviceToHost, st));

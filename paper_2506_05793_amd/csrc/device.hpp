@@ -168,9 +168,12 @@ void launch_residual(int64_t n, const int64_t* rowptr, const int32_t* colind, co
                      int64_t nrhs, double* xt, hipStream_t st);
 void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, double* out,
                      hipStream_t st);
-// out[k + c*nsys] = || v[sys_ptr[k]:sys_ptr[k+1], c] ||_2
+// out[k + c*nsys] = || v[sys_ptr[k]:sys_ptr[k+1], c] ||_2, each summed in
+// kNormParts parts (partial: kNormParts doubles per (system, column))
+// added in a fixed order
+constexpr int kNormParts = 128;
 void launch_segnorms(int64_t nsys, const int64_t* sys_ptr, const double* v, int64_t ldv,
-                     int64_t nrhs, double* out, hipStream_t st);
+                     int64_t nrhs, double* out, double* partial, hipStream_t st);
 // v[sys k rows, c] = 0 where mask[k + c*nsys] != 0
 void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t ldv, int64_t nrhs,
                        const uint8_t* mask, hipStream_t st);

@@ -2851,13 +2851,19 @@ __global__ __launch_bounds__(kThreads) void k_to_rows(int64_t n, const double* x
   for (int64_t c = 0; c < nrhs; ++c) xt[i * nrhs + c] = x[i + c * ldx];
 }
 
-__global__ __launch_bounds__(kThreads) void k_segnorms(const int64_t* sys_ptr, const double* v,
-                                                       int64_t ldv, int64_t nsys, double* out) {
+// Norms of each (system, column) segment of v in two passes, both in a fixed
+// order: kNormParts workgroups per segment each sum the squares of one part
+// (four independent partial sums per thread keep four loads in flight), then
+// one thread per segment adds the parts in order.
+__global__ __launch_bounds__(kThreads) void k_segnorms_part(const int64_t* sys_ptr, const double* v,
+                                                            int64_t ldv, int64_t nsys,
+                                                            double* partial) {
   __shared__ double part[kThreads / 64];
-  const int64_t k = blockIdx.x, c = blockIdx.y;
-  // four independent partial sums per thread keep four loads in flight
+  const int64_t u = blockIdx.x / kNormParts, p = blockIdx.x % kNormParts;
+  const int64_t k = u % nsys, c = u / nsys;
+  const int64_t s0 = sys_ptr[k], len = sys_ptr[k + 1] - s0;
+  const int64_t i0 = s0 + len * p / kNormParts, i1 = s0 + len * (p + 1) / kNormParts;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  const int64_t i0 = sys_ptr[k], i1 = sys_ptr[k + 1];
   const double* vc = v + c * ldv;
   int64_t i = i0 + threadIdx.x;
   for (; i + 3 * kThreads < i1; i += 4 * kThreads) {
@@ -2875,8 +2881,17 @@ __global__ __launch_bounds__(kThreads) void k_segnorms(const int64_t* sys_ptr, c
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int q = 0; q < kThreads / 64; ++q) t += part[q];
-    out[k + c * nsys] = sqrt(t);
+    partial[blockIdx.x] = t;
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_segnorms_sum(const double* partial, int64_t units,
+                                                           double* out) {
+  const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (u >= units) return;
+  double t = 0.0;
+  for (int p = 0; p < kNormParts; ++p) t += partial[u * kNormParts + p];
+  out[u] = sqrt(t);
 }
 
 __global__ __launch_bounds__(kThreads) void k_zero_units(const int64_t* sys_ptr, double* v,
@@ -3162,10 +3177,13 @@ void launch_colnorms(int64_t n, const double* v, int64_t ldv, int64_t nrhs, doub
 }
 
 void launch_segnorms(int64_t nsys, const int64_t* sys_ptr, const double* v, int64_t ldv,
-                     int64_t nrhs, double* out, hipStream_t st) {
-  if (nsys > 0 && nrhs > 0)
-    hipLaunchKernelGGL(k_segnorms, dim3((unsigned)nsys, (unsigned)nrhs), dim3(kThreads), 0, st,
-                       sys_ptr, v, ldv, nsys, out);
+                     int64_t nrhs, double* out, double* partial, hipStream_t st) {
+  const int64_t units = nsys * nrhs;
+  if (units <= 0) return;
+  hipLaunchKernelGGL(k_segnorms_part, dim3((unsigned)(units * kNormParts)), dim3(kThreads), 0, st,
+                     sys_ptr, v, ldv, nsys, partial);
+  hipLaunchKernelGGL(k_segnorms_sum, dim3(blocks_for(units)), dim3(kThreads), 0, st, partial, units,
+                     out);
 }
 
 void launch_zero_units(int64_t nsys, const int64_t* sys_ptr, double* v, int64_t ldv, int64_t nrhs,
