@@ -146,7 +146,7 @@ struct tacho_sym {
   DevSym view1{};
   // partitioned-inverse solves: their plan, built on first use
   std::unique_ptr<PinvPlan> Q;
-  DBuf dq_setup, dq_tiles, dq_frow, dq_bcol;
+  DBuf dq_setup, dq_tiles, dq_frow, dq_bcol, dq_small, dq_large;
 };
 
 // Per-launch timing of the library's kernels on the caller's stream (hipEvents
@@ -497,6 +497,8 @@ int ensure_pinv(tacho_sym* h) {
   HIP_TRY(upload(h->dq_tiles, Q->tiles));
   HIP_TRY(upload(h->dq_frow, Q->frow));
   HIP_TRY(upload(h->dq_bcol, Q->bcol));
+  HIP_TRY(upload(h->dq_small, Q->small));
+  HIP_TRY(upload(h->dq_large, Q->large));
   h->Q = std::move(Q);
   return TACHO_OK;
 }
@@ -920,20 +922,27 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
     const T* Z = f->Z.as<T>();
     T* yf = f->yfwd.as<T>();
     T* uv = f->uvec.as<T>();
-    const int32_t* lv = h->d_levels.as<int32_t>();
+    const int32_t* sm = h->dq_small.as<int32_t>();
+    const int32_t* lg = h->dq_large.as<int32_t>();
     const PinvSweepTask* fr = h->dq_frow.as<PinvSweepTask>();
     const PinvSweepTask* bc = h->dq_bcol.as<PinvSweepTask>();
     T* part = f->zpart.as<T>();
     int32_t* cnt = f->zcnt.as<int32_t>();
     pe = f->prof.begin(st);
-    for (int32_t lvl = 0; lvl < S.nlevels; ++lvl)
-      launch_pinv_fwd<T>(V, Z, y, yf, uv, lv + S.level_ptr[lvl], S.level_ptr[lvl + 1] - S.level_ptr[lvl],
+    for (int32_t lvl = 0; lvl < S.nlevels; ++lvl) {
+      launch_pinv_small<T>(V, Z, y, yf, uv, sm + Q.small_ptr[lvl], Q.small_ptr[lvl + 1] - Q.small_ptr[lvl],
+                           true, nrhs, st);
+      launch_pinv_fwd<T>(V, Z, y, yf, uv, lg + Q.large_ptr[lvl], Q.large_ptr[lvl + 1] - Q.large_ptr[lvl],
                          fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl], part, cnt, nrhs, st);
+    }
     f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
     pe = f->prof.begin(st);
-    for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl)
+    for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl) {
+      launch_pinv_small<T>(V, Z, y, yf, uv, sm + Q.small_ptr[lvl], Q.small_ptr[lvl + 1] - Q.small_ptr[lvl],
+                           false, nrhs, st);
       launch_pinv_bwd<T>(V, Z, yf, y, bc + Q.bcol_ptr[lvl], Q.bcol_ptr[lvl + 1] - Q.bcol_ptr[lvl], part,
                          cnt, nrhs, st);
+    }
     f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
     pe = f->prof.begin(st);
     launch_solve_out<T>(Vout, y, x, ldx, nrhs, scale, accumulate, st);

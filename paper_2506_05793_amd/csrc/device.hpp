@@ -98,6 +98,11 @@ void launch_pinv_init(const DevSym& S, T* Z, const T* L, const FrontTile* tiles,
 template <typename T>
 void launch_pinv_step(const DevSym& S, T* Z, const T* L, const T* winv, const PinvTask* tasks,
                       int64_t count, hipStream_t st);
+// the fronts of PinvPlan::small, one wave each: forward (y, yfwd, uvec) or
+// backward (solution into y)
+template <typename T>
+void launch_pinv_small(const DevSym& S, const T* Z, T* y, T* yfwd, T* uvec, const int32_t* fronts,
+                       int64_t count, bool forward, int nrhs, hipStream_t st);
 template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
                      int64_t nfronts, const PinvSweepTask* tasks, int64_t ntasks, T* part,

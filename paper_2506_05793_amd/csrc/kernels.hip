@@ -2635,6 +2635,111 @@ __global__ __launch_bounds__(kThreads) void k_pinv_gather_fwd(DevSym S, T* y, T*
   }
 }
 
+// Sweeps of a front with m <= kPinvSmallM and w <= kSmallMax by one wave
+// (four fronts per workgroup), lane l holding front rows l and l + 64.
+// Forward: gather z (own rows of y, children's update vectors), then
+// out = Z_s z_s from registers (pivot entries broadcast from their lanes);
+// rows < w go to yout, the others are z - out in the update vector.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_small_fwd(DevSym S, const T* Z, T* y, T* yout,
+                                                             T* uvec, const int32_t* fronts,
+                                                             int count) {
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (idx >= count) return;
+  const int s = fronts[idx];
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s];
+  const T* Zp = Z + S.L_off[s];
+  T z[2][NR], out[2][NR];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int i = lane + 64 * t;
+    const int ic = i < m ? i : m - 1;
+    const int64_t q = S.rows_ptr[s] + ic;
+    const T* yr = y + (int64_t)(f + (i < w ? i : 0)) * kRowLd<T>;
+    const T own = i < w ? T(1) : T(0);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      z[t][c] = yr[c] * own;
+      out[t][c] = T(0);
+    }
+    const int p0 = S.pull_ptr[q], p1 = i < m ? S.pull_ptr[q + 1] : p0;
+    for (int p = p0; p < p1; ++p) {
+      const T* ur = uvec + (int64_t)S.pull_src[p] * kRowLd<T>;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) z[t][c] += ur[c];
+    }
+  }
+#pragma unroll 4
+  for (int k = 0; k < w; ++k) {
+    T zk[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) zk[c] = readlane(z[0][c], k);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int i = lane + 64 * t;
+      const bool ok = i < m && (i >= w || k <= i);
+      const T zik = Zp[(ok ? i : k) + (int64_t)k * ld] * (ok ? T(1) : T(0));
+#pragma unroll
+      for (int c = 0; c < NR; ++c) out[t][c] += zik * zk[c];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int i = lane + 64 * t;
+    if (i < w) {
+      T* yr = yout + (int64_t)(f + i) * kRowLd<T>;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) yr[c] = out[t][c];
+    } else if (i < m) {
+      T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T>;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) ur[c] = z[t][c] - out[t][c];
+    }
+  }
+}
+
+// Backward, same fronts: lane j < w forms x_j = sum_i Z[i][j] v_i with
+// v = [yfwd_s; -x_rows] held by the lanes of the rows and broadcast.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_small_bwd(DevSym S, const T* Z, const T* yfwd,
+                                                             T* x, const int32_t* fronts,
+                                                             int count) {
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (idx >= count) return;
+  const int s = fronts[idx];
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s];
+  const T* Zp = Z + S.L_off[s];
+  const int32_t* rws = S.rows + S.rows_ptr[s];
+  T v[2][NR], acc[NR];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int i = lane + 64 * t;
+    const T* src = i < w ? yfwd + (int64_t)(f + i) * kRowLd<T>
+                         : x + (int64_t)rws[i < m ? i : m - 1] * kRowLd<T>;
+    const T sg = i < w ? T(1) : (i < m ? T(-1) : T(0));
+#pragma unroll
+    for (int c = 0; c < NR; ++c) v[t][c] = src[c] * sg;
+  }
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = T(0);
+  const int jc = lane < w ? lane : 0;
+  const T jmask = lane < w ? T(1) : T(0);
+  for (int i = 0; i < m; ++i) {
+    const T zij = Zp[i + (int64_t)jc * ld] * jmask;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) acc[c] += zij * readlane(i < 64 ? v[0][c] : v[1][c], i & 63);
+  }
+  if (lane < w) {
+    T* xr = x + (int64_t)(f + lane) * kRowLd<T>;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xr[c] = acc[c];
+  }
+}
+
 // Partial product of a chunked sweep task: chunk c of the tile stores its
 // 64 x 16 values in slot + c; the chunk that arrives last (per-tile counter,
 // which only ever grows by the tile's chunk count per sweep) reads them all
@@ -3120,6 +3225,24 @@ void launch_pinv_step(const DevSym& S, T* Z, const T* L, const T* winv, const Pi
 }
 
 template <typename T>
+void launch_pinv_small(const DevSym& S, const T* Z, T* y, T* yfwd, T* uvec, const int32_t* fronts,
+                       int64_t count, bool forward, int nrhs, hipStream_t st) {
+  if (count <= 0) return;
+  const unsigned grid = (unsigned)((count + kThreads / 64 - 1) / (kThreads / 64));
+  if (forward) {
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_pinv_small_fwd<T, 1>), dim3(grid), dim3(kThreads), 0, st, S, Z, y, yfwd, uvec, fronts, (int)count);
+    else
+      hipLaunchKernelGGL((k_pinv_small_fwd<T, 16>), dim3(grid), dim3(kThreads), 0, st, S, Z, y, yfwd, uvec, fronts, (int)count);
+  } else {
+    if (nrhs == 1)
+      hipLaunchKernelGGL((k_pinv_small_bwd<T, 1>), dim3(grid), dim3(kThreads), 0, st, S, Z, yfwd, y, fronts, (int)count);
+    else
+      hipLaunchKernelGGL((k_pinv_small_bwd<T, 16>), dim3(grid), dim3(kThreads), 0, st, S, Z, yfwd, y, fronts, (int)count);
+  }
+}
+
+template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
                      int64_t nfronts, const PinvSweepTask* tasks, int64_t ntasks, T* part,
                      int32_t* cnt, int nrhs, hipStream_t st) {
@@ -3211,6 +3334,8 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
                                     hipStream_t);                                                \
   template void launch_pinv_step<T>(const DevSym&, T*, const T*, const T*, const PinvTask*,       \
                                     int64_t, hipStream_t);                                       \
+  template void launch_pinv_small<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t, \
+                                     bool, int, hipStream_t);                                    \
   template void launch_pinv_fwd<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t,  \
                                    const PinvSweepTask*, int64_t, T*, int32_t*, int,             \
                                    hipStream_t);                                                 \

@@ -751,6 +751,10 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
   Q.bcol.clear();
   Q.frow_ptr.assign(1, 0);
   Q.bcol_ptr.assign(1, 0);
+  Q.small.clear();
+  Q.large.clear();
+  Q.small_ptr.assign(1, 0);
+  Q.large_ptr.assign(1, 0);
   Q.slots = 0;
   auto add = [&](std::vector<PinvSweepTask>& v, int32_t s, int32_t t, int32_t len) {
     const int32_t nch = (len + kPinvChunk - 1) / kPinvChunk;
@@ -762,6 +766,11 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       const int32_t s = S.level_list[q];
       const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
+      if (m <= kPinvSmallM && w <= kSmallMax) {
+        Q.small.push_back(s);
+        continue;
+      }
+      Q.large.push_back(s);
       // forward: rows of Z11 see only the columns up to their own
       for (int32_t a = 0; a * kPanel < m; ++a) add(Q.frow, s, a, std::min(w, (a + 1) * kPanel));
       // backward: Z is zero above a column's diagonal
@@ -769,6 +778,8 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
     }
     Q.frow_ptr.push_back((int64_t)Q.frow.size());
     Q.bcol_ptr.push_back((int64_t)Q.bcol.size());
+    Q.small_ptr.push_back((int64_t)Q.small.size());
+    Q.large_ptr.push_back((int64_t)Q.large.size());
   }
 }
 

@@ -256,6 +256,7 @@ struct PinvSweepTask {
   int32_t s, t, c, slot;
 };
 constexpr int kPinvChunk = 512;
+constexpr int kPinvSmallM = 128;  // wave-per-front sweeps: two rows per lane
 struct PinvPlan {
   // setup: launch q runs tasks [setup_ptr[q], setup_ptr[q + 1]); launch 0
   // scales every front's last block column, launch q >= 1 applies the block
@@ -263,8 +264,13 @@ struct PinvPlan {
   std::vector<PinvTask> setup;
   std::vector<int64_t> setup_ptr;
   std::vector<FrontTile> tiles;
-  // solves, per level h: forward tasks [frow_ptr[h], frow_ptr[h + 1]) and
-  // backward tasks [bcol_ptr[h], bcol_ptr[h + 1])
+  // solves, per level h: fronts with at most kPinvSmallM rows and kSmallMax
+  // pivot columns [small_ptr[h], small_ptr[h + 1]) of `small` (one wave
+  // each, both sweeps); the other fronts [large_ptr[h], ...) of `large`, their
+  // forward tasks [frow_ptr[h], frow_ptr[h + 1]) and backward tasks
+  // [bcol_ptr[h], bcol_ptr[h + 1])
+  std::vector<int32_t> small, large;
+  std::vector<int64_t> small_ptr, large_ptr;
   std::vector<PinvSweepTask> frow, bcol;
   std::vector<int64_t> frow_ptr, bcol_ptr;
   int64_t slots = 0;  // partial-product slots (and arrival counters) of the sweeps
