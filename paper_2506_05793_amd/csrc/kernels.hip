@@ -1243,6 +1243,159 @@ __device__ inline bool flag_set(const int32_t* flag) {
   return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
+// Update-matrix block task (kind 5): the kUBlock x kUBlock block (tk.t, tk.j)
+// of U_s loses sum_p L(a rows, p) L(b rows, p)^T over the pivot blocks
+// [p0, p1), formed on the matrix cores.  Both operands are staged through
+// double-buffered LDS 16 columns at a time (the next stage prefetched into
+// registers while the current one is multiplied), and each wave owns a 64 x 64
+// quadrant, so a staged byte feeds twice the products it feeds in a 64 x 64
+// tile.  Per output entry the products are added in the same column order as
+// in a 64 x 64 tile.  The block's ranges are applied in order (counter ui).
+template <typename T>
+__device__ __forceinline__ void front_ublock(const DevSym& S, const DevNum<T>& N, const FrontTask& tk,
+                                             T* lds, const int32_t* tile_done, int32_t* ucount,
+                                             int32_t* hang, int* s_ready) {
+  constexpr int UB = kUBlock, UK = 16, PAD = 4, QB = UB / 2 / 16;  // 16 x 16 tiles per quadrant side
+  constexpr int RS = kThreads / UB;          // k rows covered per load round
+  constexpr int SL = UB * UK / kThreads;     // staged elements per thread and operand
+  typedef typename Vec4<T>::type V4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int s = tk.s;
+  const int w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s], ld = S.ldL[s], wb = S.wbase[s];
+  const T* Lp = N.L + S.L_off[s];
+  T* Cu = N.U + S.U_off[s];
+  const int ldc = S.ldU[s];
+  const int a0 = w + tk.t * UB, b0 = w + tk.j * UB;  // front rows of the block's rows / columns
+  const int arows = min(UB, m - a0), bcols = min(UB, m - b0);
+  const int kstart = tk.p0 * kPanel, K = min(w, tk.p1 * kPanel);
+  // the upper right quadrant of a diagonal block lies above the diagonal
+  const bool idle = tk.t == tk.j && wr == 0 && wc == 1;
+  V4 acc[QB][QB];
+#pragma unroll
+  for (int a = 0; a < QB; ++a)
+#pragma unroll
+    for (int b = 0; b < QB; ++b) acc[a][b] = V4{0, 0, 0, 0};
+  T* As = lds;  // [2][UK][UB + PAD]: As[buf][k][row]
+  T* Bs = lds + 2 * UK * (UB + PAD);
+  const int lrow = tid % UB, lk = tid / UB;
+  const bool aok = lrow < arows, bok = lrow < bcols;
+  const T* pa = Lp + a0 + lrow;
+  const T* pb = Lp + b0 + lrow;
+  T ra[SL], rb[SL];
+  // Pivot blocks [0, ready) are known complete (see the front kernel).
+  int ready = kstart / kPanel;
+  const int nblk = (K + kPanel - 1) / kPanel;
+  auto rows_done = [&](int p, int r0, int nr, bool wait) {
+    const int32_t* fl = tile_done + S.tbase[wb + p];
+    const int t1 = front_row_tile(w, p, r0 + nr - 1);
+    for (int t = front_row_tile(w, p, r0); t <= t1; ++t) {
+      if (wait)
+        wait_at_least(fl + t, 1, hang);
+      else if (!flag_set(fl + t))
+        return false;
+    }
+    return true;
+  };
+  auto block_done = [&](int p, bool wait) {
+    return rows_done(p, a0, arows, wait) && rows_done(p, b0, bcols, wait);
+  };
+  auto load_stage = [&](int st) {
+    const int k0 = kstart + st * UK;
+    if (k0 % kPanel == 0 && k0 / kPanel >= ready) {
+      if (tid == 0) {
+        int q = k0 / kPanel;
+        block_done(q, true);
+        ++q;
+        while (q < nblk && block_done(q, false)) ++q;
+        acquire_agent();
+        *s_ready = q;
+      }
+      __syncthreads();
+      ready = *s_ready;
+    }
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+      const int kg = k0 + lk + RS * u;
+      const bool kok = kg < K;
+      const T xa = *((aok && kok) ? pa + (int64_t)kg * ld : Lp);
+      const T xb = *((bok && kok) ? pb + (int64_t)kg * ld : Lp);
+      ra[u] = ((aok && kok) ? T(1) : T(0)) * xa;
+      rb[u] = ((bok && kok) ? T(1) : T(0)) * xb;
+    }
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < SL; ++u) {
+      As[(buf * UK + lk + RS * u) * (UB + PAD) + lrow] = ra[u];
+      Bs[(buf * UK + lk + RS * u) * (UB + PAD) + lrow] = rb[u];
+    }
+  };
+  const int nstage = (K - kstart + UK - 1) / UK;
+  if (nstage > 0) {
+    load_stage(0);
+    store_stage(0);
+    __syncthreads();
+  }
+  for (int st = 0; st < nstage; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nstage) load_stage(st + 1);
+    if (!idle) {
+#pragma unroll
+      for (int ks = 0; ks < UK / 4; ++ks) {
+        const int kr = buf * UK + ks * 4 + (lane >> 4);
+        T av[QB], bv[QB];
+#pragma unroll
+        for (int a = 0; a < QB; ++a) av[a] = As[kr * (UB + PAD) + wr * (UB / 2) + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) bv[b] = Bs[kr * (UB + PAD) + wc * (UB / 2) + b * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < QB; ++a)
+#pragma unroll
+          for (int b = 0; b < QB; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+      }
+    }
+    if (st + 1 < nstage) store_stage(buf ^ 1);
+    __syncthreads();
+  }
+  if (tk.rk > 0) {
+    if (tid == 0) {
+      wait_at_least(ucount + tk.ui, tk.rk, hang);
+      acquire_agent();
+    }
+    __syncthreads();
+  }
+  // U <- U - acc over the block's lower part, one row of 16 x 16 tiles at a
+  // time; masked-off entries read the block's first entry (the loads of a
+  // row issue before their first use)
+  const int gi0 = tk.t * UB, gj0 = tk.j * UB;
+#pragma unroll
+  for (int a = 0; a < QB; ++a) {
+    const int i = wr * (UB / 2) + a * 16 + (lane & 15);
+    T f[QB][4];
+#pragma unroll
+    for (int b = 0; b < QB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = wc * (UB / 2) + b * 16 + mfma_row<T>(lane, v);
+        const bool ok = i < arows && jj < bcols && gi0 + i >= gj0 + jj;
+        f[b][v] = *(ok ? Cu + (gi0 + i) + (int64_t)(gj0 + jj) * ldc : Cu);
+      }
+#pragma unroll
+    for (int b = 0; b < QB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = wc * (UB / 2) + b * 16 + mfma_row<T>(lane, v);
+        if (i < arows && jj < bcols && gi0 + i >= gj0 + jj)
+          st_out(&Cu[(gi0 + i) + (int64_t)(gj0 + jj) * ldc], f[b][v] - acc[a][b][v]);
+      }
+  }
+  if (tk.p1 * kPanel < w) {  // a later range of this block follows
+    publish_barrier();
+    if (tid == 0) set_flag(ucount + tk.ui, tk.rk + 1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Dataflow factorization of the large fronts of one level (one launch).
 // Left-looking over 64-column pivot blocks: the task of pivot block j, row
@@ -1261,7 +1414,7 @@ __device__ inline bool flag_set(const int32_t* flag) {
 // every task depends only on tasks with smaller tickets; those belong to
 // workgroups that already run, so the waits end (and are bounded anyway).
 template <typename T>
-__global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T* winv,
+__global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevSym S, DevNum<T> N, T* winv,
                                                     const FrontTask* tasks, int count,
                                                     int32_t* tile_done, int32_t* pd_done,
                                                     int32_t* ucount, int32_t* counter,
@@ -1270,7 +1423,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   constexpr int RSTEP = kThreads / TT;     // k rows covered per load round
   constexpr int STAGE = TT * (TT + PAD);   // one operand, double-buffered half blocks
   constexpr int POST = 2 * kPanel * kDiagLd + 3 * kSub * kSub;
-  constexpr int LDS = POST > 2 * STAGE ? POST : 2 * STAGE;
+  constexpr int UBLDS = 4 * 16 * (kUBlock + PAD);  // update-matrix block stages
+  constexpr int LDS0 = POST > 2 * STAGE ? POST : 2 * STAGE;
+  constexpr int LDS = LDS0 > UBLDS ? LDS0 : UBLDS;
   typedef typename Vec4<T>::type V4;
   __shared__ T lds[LDS];
   __shared__ int s_ticket, s_ready;
@@ -1281,6 +1436,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_front(DevSym S, DevNum<T> N, T*
   const int ticket = s_ticket;
   if (ticket >= count) return;
   const FrontTask tk = tasks[ticket];
+  if (tk.kind == 5) {
+    front_ublock<T>(S, N, tk, lds, tile_done, ucount, hang, &s_ready);
+    return;
+  }
   const int s = tk.s;
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], ld = S.ldL[s];
   const int wb = S.wbase[s];

@@ -362,11 +362,18 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       // depends only on tasks with smaller tickets.
       Step st{kStepFront, h, (int64_t)P.ftasks.size(), 0};
       st.ticket = P.front_launches++;
+      // Update matrices of more than 64 rows go in kUBlock x kUBlock blocks
+      // (twice the products per operand byte of a 64 x 64 tile; a decision
+      // of the front's shape alone).
+      auto ublock = [&](int32_t s) {
+        return S.front_m[s] - (S.sptr[s + 1] - S.sptr[s]) > kPanel ? kUBlock : kPanel;
+      };
       std::vector<int32_t> ubase(flow.size());
       for (size_t bi = 0; bi < flow.size(); ++bi) {
         const int32_t s = flow[bi];
         const int32_t r = S.front_m[s] - (S.sptr[s + 1] - S.sptr[s]);
-        const int32_t nt = (r + kPanel - 1) / kPanel;
+        const int32_t ub = ublock(s);
+        const int32_t nt = (r + ub - 1) / ub;
         ubase[bi] = (int32_t)P.nucount;
         P.nucount += (int64_t)nt * (nt + 1) / 2;
       }
@@ -432,19 +439,20 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
           const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
           const int32_t pb = (w + kPanel - 1) / kPanel;
           if (r <= 0) continue;
+          const int32_t ub = ublock(s);
           if (j < pb && ((j + 1) % urange == 0 || j + 1 == pb)) {
             // range ending at column j: queue its tasks
             const int32_t rk = j / urange, p0 = rk * urange, p1 = j + 1;
-            const int32_t nt = (r + kPanel - 1) / kPanel;
+            const int32_t nt = (r + ub - 1) / ub;
             for (int32_t b = 0; b < nt; ++b)
               for (int32_t a = b; a < nt; ++a) {
                 const int32_t ui = ubase[bi] + a * (a + 1) / 2 + b;
-                pending[bi].push_back({s, b, a, 1, p0, p1, ui, rk});
+                pending[bi].push_back({s, b, a, ub == kUBlock ? 5 : 1, p0, p1, ui, rk});
               }
           }
           // release the queued tasks of the range that ended u_range columns
           // ago in proportion to the columns passed since
-          const int32_t per = (int32_t)((r + kPanel - 1) / kPanel);
+          const int32_t per = (int32_t)((r + ub - 1) / ub);
           const size_t range_tasks = (size_t)per * (per + 1) / 2;
           if (j >= urange) {
             const int32_t rk = (j - urange) / urange;       // range being released

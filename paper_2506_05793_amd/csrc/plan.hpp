@@ -81,7 +81,9 @@ struct GemmTile {
 // rk-th such range of block j (ranges cover the blocks before j - 1, the
 // last one is [j - 2, j - 1) and they are applied in order), for the chain.
 // kind 4: the whole front s (one pivot block): the diagonal block, its row
-// tiles and the update-matrix tiles, in order, by one workgroup.
+// tiles and the update-matrix tiles, in order, by one workgroup.  kind 5:
+// as kind 1 for a block of kUBlock x kUBlock entries (rows kUBlock t..,
+// columns kUBlock j..), used for every update matrix of more than 64 rows.
 // A kind 0 task of a chain front
 // has p0 = 1 or 2: its rows that are row tile 1 of block j + 1 also get
 // their product with row tile 1 of block j, for the chain's step j + 1,
@@ -93,6 +95,7 @@ struct FrontTask {
 };
 
 constexpr int kURange = 8;     // default pivot blocks per update-matrix task
+constexpr int kUBlock = 128;   // rows and columns of an update-matrix block task (kind 5)
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
 constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
 constexpr int kAsmElems = 2048;  // front entries per assembly workgroup of a short front
@@ -168,7 +171,7 @@ struct Plan {
   // dataflow factorization: per pivot block the index of its first row tile's
   // completion flag (prefix sums of front_block_tiles; one entry past the end)
   std::vector<int32_t> tbase;
-  int64_t nucount = 0;  // update-matrix tile counters (one per tile of every large front)
+  int64_t nucount = 0;  // update-matrix task counters (one per tile or block of every large front)
   // chain fronts: per pivot block j >= 1 (woff indexing) a 64 x 64 slot for the
   // product of block j - 1's rows of row tile 1 of block j with row tile 1 of
   // block j - 1 (-1: none)
