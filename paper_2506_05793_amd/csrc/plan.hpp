@@ -155,7 +155,7 @@ constexpr int kAsmCols = 8;       // front columns per assembly workgroup
 constexpr int kGemmTile = 64;     // output tile of the update kernel
 constexpr int kGemmTileBig = 128; // output tile for large updates
 constexpr int64_t kGemmBigMin = 256 * 256;  // M*N from which the large tile is used
-constexpr int kLdAlign = 4;       // leading dimensions rounded to this many elements
+constexpr int kLdAlign = 16;      // leading dimensions rounded to this many elements (128-byte FP64 columns)
 
 struct Plan {
   // memory layout (elements; identical for FP32 and FP64)
