@@ -1251,10 +1251,13 @@ __device__ inline bool flag_set(const int32_t* flag) {
 // quadrant, so a staged byte feeds twice the products it feeds in a 64 x 64
 // tile.  Per output entry the products are added in the same column order as
 // in a 64 x 64 tile.  The block's ranges are applied in order (counter ui).
+//
+// With local set the block belongs to a whole-front task whose own earlier
+// steps wrote the operands: nothing is awaited or published.
 template <typename T>
 __device__ __forceinline__ void front_ublock(const DevSym& S, const DevNum<T>& N, const FrontTask& tk,
                                              T* lds, const int32_t* tile_done, int32_t* ucount,
-                                             int32_t* hang, int* s_ready) {
+                                             int32_t* hang, int* s_ready, bool local) {
   constexpr int UB = kUBlock, UK = 16, PAD = 4, QB = UB / 2 / 16;  // 16 x 16 tiles per quadrant side
   constexpr int RS = kThreads / UB;          // k rows covered per load round
   constexpr int SL = UB * UK / kThreads;     // staged elements per thread and operand
@@ -1302,7 +1305,7 @@ __device__ __forceinline__ void front_ublock(const DevSym& S, const DevNum<T>& N
   };
   auto load_stage = [&](int st) {
     const int k0 = kstart + st * UK;
-    if (k0 % kPanel == 0 && k0 / kPanel >= ready) {
+    if (!local && k0 % kPanel == 0 && k0 / kPanel >= ready) {
       if (tid == 0) {
         int q = k0 / kPanel;
         block_done(q, true);
@@ -1436,10 +1439,11 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
   const int ticket = s_ticket;
   if (ticket >= count) return;
   const FrontTask tk = tasks[ticket];
-  if (tk.kind == 5) {
-    front_ublock<T>(S, N, tk, lds, tile_done, ucount, hang, &s_ready);
-    return;
-  }
+  // Update-matrix blocks run after the other steps, from one call site (one
+  // inlined copy): the task's own block (kind 5) or, for a whole-front task
+  // of an update matrix of more than 64 rows, all of them.
+  bool ublocks = tk.kind == 5;
+  if (!ublocks) {
   const int s = tk.s;
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], ld = S.ldL[s];
   const int wb = S.wbase[s];
@@ -1456,9 +1460,10 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
   asm volatile("" : "+v"(lane));
   const bool utile = mode == 1;
   const bool pre = mode == 3;
-  // whole-front task: every operand comes from this workgroup's own earlier
-  // steps, so there are no flags to wait for or raise
-  const bool solo = tk.kind == 4;
+  // whole-front or whole-panel task: every operand comes from this
+  // workgroup's own earlier steps, so there are no flags to wait for or
+  // raise between them
+  const bool solo = tk.kind == 4 || tk.kind == 6;
   const bool diag = (mode == 0 && tt == 0) || pre;
   const int c0 = tj * TT;
   const int kb = utile ? TT : min(TT, w - c0);
@@ -2000,13 +2005,17 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
   // solves its row tile 1, which is block j + 1's last operand.  Other
   // kinds run one step.  (One call site keeps a single inlined copy.)
   // A whole-front task (kind 4, one pivot block) runs the diagonal step,
-  // the steps of row tiles 2.. and then the update-matrix tiles.
-  const int nrt = tk.kind == 4 ? max(1, front_block_tiles(m, w, 0) - 1) : 0;
-  const int nut = tk.kind == 4 ? (m - w + TT - 1) / TT : 0;
-  const int nsteps = tk.kind == 2 ? (w + TT - 1) / TT : tk.kind == 4 ? nrt + nut * (nut + 1) / 2 : 1;
+  // the steps of row tiles 2.. and then the update matrix: one 64 x 64
+  // tile, or kUBlock x kUBlock blocks when it has more than 64 rows.  A
+  // whole-panel task (kind 6) runs the same steps up to the update matrix
+  // and then raises the flags of all its row tiles at once.
+  const bool whole = tk.kind == 4 || tk.kind == 6;
+  const int nrt = whole ? max(1, front_block_tiles(m, w, 0) - 1) : 0;
+  const int nut = tk.kind == 4 && m - w <= TT ? (m - w + TT - 1) / TT : 0;
+  const int nsteps = tk.kind == 2 ? (w + TT - 1) / TT : whole ? nrt + nut * (nut + 1) / 2 : 1;
   for (int it = 0; it < nsteps; ++it) {
     int mode = 0, tj = tk.j, tt = tk.t, kstart = 0, kend = tk.j * TT;
-    if (tk.kind == 4) {
+    if (whole) {
       if (it < nrt) {
         tj = 0;
         tt = it == 0 ? 0 : it + 1;
@@ -2037,6 +2046,32 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
       kend = tk.p1 * TT;
     }
     step(mode, tj, tt, kstart, kend);
+  }
+  if (tk.kind == 6) {
+    publish_barrier();
+    if (tid == 0) {
+      release_agent();
+      int32_t* done = tile_done + S.tbase[wb];
+      const int nt = front_block_tiles(m, w, 0);
+      for (int t = 0; t < nt; ++t) __hip_atomic_store(done + t, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  ublocks = tk.kind == 4 && m - w > TT;
+  }
+  if (!ublocks) return;
+  // a whole-front task: blocks (a, b), a >= b, in row-major lower order, on
+  // the row tiles its own steps stored (visible to it after local_publish)
+  const int r = S.front_m[tk.s] - (S.sptr[tk.s + 1] - S.sptr[tk.s]);
+  const int nub = tk.kind == 5 ? 1 : (r + kUBlock - 1) / kUBlock;
+  const int nblk = tk.kind == 5 ? 1 : nub * (nub + 1) / 2;
+  for (int q = 0; q < nblk; ++q) {
+    FrontTask u = tk;
+    if (tk.kind != 5) {
+      int a = 0;
+      while ((a + 1) * (a + 2) / 2 <= q) ++a;
+      u = FrontTask{tk.s, q - a * (a + 1) / 2, a, 5, 0, 1, 0, 0};
+    }
+    front_ublock<T>(S, N, u, lds, tile_done, ucount, hang, &s_ready, tk.kind != 5);
   }
 }
 

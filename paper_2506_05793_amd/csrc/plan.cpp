@@ -339,6 +339,12 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       auto is_chain = [&](int32_t s) {
         return chain_min > 0 && (S.sptr[s + 1] - S.sptr[s] + kPanel - 1) / kPanel >= chain_min;
       };
+      // A front with one pivot block and at most kPanelTaskMax rows factors
+      // its whole panel in one task (no flags between its row tiles); its
+      // update matrix is left to the update-matrix tasks.
+      auto whole_panel = [&](int32_t s) {
+        return S.sptr[s + 1] - S.sptr[s] <= kPanel && S.front_m[s] <= kPanelTaskMax;
+      };
       std::vector<std::vector<int32_t>> groups(1);
       {
         int nchain = 0;
@@ -406,6 +412,10 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
           const int32_t s = flow[bi];
           const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
           if (j * kPanel >= w) continue;
+          if (whole_panel(s)) {
+            P.ftasks.push_back({s, 0, 0, 6, 0, 0, 0, 0});
+            continue;
+          }
           // the diagonal task (t = 0) also produces row tile 1
           const int nt = front_block_tiles(m, w, j);
           for (int t = chain[bi] ? 2 : 0; t < nt; ++t)

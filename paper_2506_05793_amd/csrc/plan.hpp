@@ -84,6 +84,9 @@ struct GemmTile {
 // tiles and the update-matrix tiles, in order, by one workgroup.  kind 5:
 // as kind 1 for a block of kUBlock x kUBlock entries (rows kUBlock t..,
 // columns kUBlock j..), used for every update matrix of more than 64 rows.
+// kind 6: the whole panel of front s (one pivot block, at most
+// kPanelTaskMax rows): the diagonal block and all row tiles, in order, by one
+// workgroup, which then raises the flags of all its row tiles.
 // A kind 0 task of a chain front
 // has p0 = 1 or 2: its rows that are row tile 1 of block j + 1 also get
 // their product with row tile 1 of block j, for the chain's step j + 1,
@@ -96,6 +99,7 @@ struct FrontTask {
 
 constexpr int kURange = 8;     // default pivot blocks per update-matrix task
 constexpr int kUBlock = 128;   // rows and columns of an update-matrix block task (kind 5)
+constexpr int kPanelTaskMax = 1024;  // rows of the largest front whose panel is one task (kind 6)
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
 constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
 constexpr int kAsmElems = 2048;  // front entries per assembly workgroup of a short front
