@@ -39,7 +39,7 @@ struct DevSym {
   const int32_t* pull_src;   // update-vector entry of each source
   const int32_t* part_base;  // per diagonal block: first backward partial-product slot
   const int32_t* pt1base;    // per pivot block of a chain front: 64 x 64 product slot (-1: none)
-  const int32_t* asm_rng;    // per assembly item and child: child column range
+  const int32_t* asm_rng;    // per assembly item and child: child column and row ranges
   // LDL^T solves (nullptr otherwise): pivot order lq (L row i is row lq[i] of
   // P A P^T; it moves rows only within a diagonal block) and its inverse.  A
   // front's interchanges act on its own front vector after the children's

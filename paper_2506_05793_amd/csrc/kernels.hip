@@ -355,73 +355,76 @@ __global__ __launch_bounds__(kThreads) void k_leaf(DevSym S, DevNum<T> N, const 
 }
 
 // ---------------------------------------------------------------------------
-// Large fronts, assembly: the workgroup owns front columns [c0, c1).  It
-// zeroes them, writes the A entries, then adds every child's update matrix
-// (ascending child order).  The child's relative map is increasing, so the
-// child columns landing in [c0, c1) form one contiguous range.
+// Large fronts, assembly: the workgroup owns the entries of front s in
+// columns [c0, c1) and front rows [r0, r1) (at most kAsmTile).  It sums them
+// in LDS -- zero, the A entries, then every child's update matrix in
+// ascending child order -- and writes each entry once.  The child's
+// relative map is increasing, so its columns landing in [c0, c1) and its
+// rows landing in [r0, r1) are contiguous ranges (from the plan).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_assemble(DevSym S, DevNum<T> N,
                                                        const AsmItem* items) {
+  __shared__ T tile[kAsmTile];  // tile[(c - c0) nr + (row - r0)]
   const AsmItem it = items[blockIdx.x];
   const int tid = threadIdx.x;
   const int s = it.s;
   const int f = S.sptr[s], w = S.sptr[s + 1] - f;
   const int ldl = S.ldL[s], ldu = S.ldU[s];
+  const int nr = it.r1 - it.r0, nc = it.c1 - it.c0;
   T* Lp = N.L + S.L_off[s];
   T* Us = w < S.front_m[s] ? N.U + S.U_off[s] : nullptr;
-  for (int c = it.c0; c < it.c1; ++c) {
-    if (c < w) {
-      for (int i = tid; i < ldl; i += kThreads) Lp[i + (int64_t)c * ldl] = T(0);
-    } else {
-      // U is used by 64 x 64 tiles on and below the diagonal only (the
-      // front kernel's update tiles, the parent's lower-triangle pull).
-      for (int i = ((c - w) & ~(kPanel - 1)) + tid; i < ldu; i += kThreads)
-        Us[i + (int64_t)(c - w) * ldu] = T(0);
+  for (int t = tid; t < nr * nc; t += kThreads) tile[t] = T(0);
+  __syncthreads();
+  for (int c = it.c0; c < min(it.c1, w); ++c) {
+    const int64_t q0 = S.acol_ptr[f + c], q1 = S.acol_ptr[f + c + 1];
+    for (int64_t q = q0 + tid; q < q1; q += kThreads) {
+      const int row = (int)(S.a_pos[q] - (int64_t)c * ldl);
+      if (row >= it.r0 && row < it.r1) tile[(c - it.c0) * nr + row - it.r0] = N.avals[q];
     }
   }
   __syncthreads();
-  if (it.c0 < w) {
-    const int64_t q0 = S.acol_ptr[f + it.c0], q1 = S.acol_ptr[f + min(it.c1, w)];
-    for (int64_t q = q0 + tid; q < q1; q += kThreads) Lp[S.a_pos[q]] = N.avals[q];
-  }
-  __syncthreads();
-  // children's update matrices, ascending child order: the columns of child
-  // c that land in [c0, c1) come from the plan; one wave per child column,
-  // rows in lanes, four rows per lane fetched before their sums are stored
-  // (the row map is injective, so they are distinct targets)
-  const int32_t* rg = S.asm_rng + 2 * (int64_t)it.rbase;
+  // one wave per child column, rows in lanes, four rows per lane fetched
+  // before their sums are stored (the row map is injective, so the targets
+  // of one child are distinct)
+  const int32_t* rg = S.asm_rng + 4 * (int64_t)it.rbase;
   const int lane = tid & 63, wave = tid >> 6;
-  for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q, rg += 2) {
-    const int lo = rg[0], hi = rg[1];
-    if (lo >= hi) continue;  // same for the whole workgroup
+  for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q, rg += 4) {
+    const int lo = rg[0], hi = rg[1], ilo = rg[2], ihi = rg[3];
+    if (lo >= hi || ilo >= ihi) continue;  // same for the whole workgroup
     const int c = S.child_list[q];
-    const int wc = S.sptr[c + 1] - S.sptr[c], rc = S.front_m[c] - wc;
+    const int wc = S.sptr[c + 1] - S.sptr[c];
     const T* Uc = N.U + S.U_off[c];
     const int ldc = S.ldU[c];
     const int32_t* rm = S.rmap + S.rows_ptr[c] + wc;
     for (int jj = lo + wave; jj < hi; jj += kThreads / 64) {
-      const int tc = rm[jj];
-      // target column: front rows [0, m) of L, or rows [w, m) of U
-      T* col = tc < w ? Lp + (int64_t)tc * ldl : Us + (int64_t)(tc - w) * ldu;
-      const int roff = tc < w ? 0 : w;
+      T* col = tile + (rm[jj] - it.c0) * nr - it.r0;  // indexed by front row
       const T* src = Uc + (int64_t)jj * ldc;
-      for (int i0 = jj + lane; i0 < rc; i0 += 4 * 64) {
+      for (int i0 = max(jj, ilo) + lane; i0 < ihi; i0 += 4 * 64) {
         int tr[4];
-        T v[4], old[4];
+        T v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ii = i0 + 64 * u;
-          tr[u] = ii < rc ? rm[ii] - roff : -1;
-          v[u] = ii < rc ? src[ii] : T(0);
+          tr[u] = ii < ihi ? rm[ii] : -1;
+          v[u] = ii < ihi ? src[ii] : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) old[u] = tr[u] >= 0 ? col[tr[u]] : T(0);
-#pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (tr[u] >= 0) col[tr[u]] = old[u] + v[u];
+          if (tr[u] >= 0) col[tr[u]] += v[u];
       }
     }
     __syncthreads();
+  }
+  // Write-out: panel columns rows [0, ldl), update-matrix columns from row
+  // (c - w) & ~63 of U (what the front kernel's tiles and the parent's
+  // lower-triangle pull read).
+  for (int t = tid; t < nr * nc; t += kThreads) {
+    const int cc = t / nr, row = it.r0 + (t - cc * nr), c = it.c0 + cc;
+    if (c < w) {
+      if (row < ldl) Lp[row + (int64_t)c * ldl] = tile[t];
+    } else if (row >= w + ((c - w) & ~(kPanel - 1)) && row < w + ldu) {
+      Us[(row - w) + (int64_t)(c - w) * ldu] = tile[t];
+    }
   }
 }
 

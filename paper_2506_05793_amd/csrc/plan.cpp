@@ -298,25 +298,44 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
     int64_t a0 = (int64_t)P.asm_items.size();
     int32_t wmax = 0;
     for (int32_t s : big) {
-      int32_t m = S.front_m[s];
-      // at least asm_cols columns per workgroup, more for short fronts (about
-      // kAsmElems front entries, at most 64 columns)
-      const int32_t cols = std::max(asm_cols, std::min<int32_t>(64, kAsmElems / std::max(m, 1)));
-      for (int32_t c = 0; c < m; c += cols) {
-        const int32_t c1 = std::min(m, c + cols);
-        const int32_t rbase = (int32_t)(P.asm_rng.size() / 2);
-        for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
-          // child rows (front positions in s, ascending) past its pivots
-          const int32_t ch = S.child_list[q];
-          const int32_t wc = S.sptr[ch + 1] - S.sptr[ch];
-          const int32_t* rm = S.rmap.data() + S.rows_ptr[ch] + wc;
-          const int32_t rc = S.front_m[ch] - wc;
-          P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, c) - rm));
-          P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, c1) - rm));
+      const int32_t m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s];
+      // front row space: the panel's rows [0, ldL), the update matrix's
+      // rows [w, w + ldU); a U column c is kept from row w + ((c - w) & ~63)
+      const int32_t R = m > w ? std::max(P.ldL[s], w + P.ldU[s]) : P.ldL[s];
+      // Blocks of columns of full height when kAsmTile entries hold at
+      // least one column (as many columns as fit, at most 64); otherwise
+      // asm_cols columns in chunks of rows.
+      for (int32_t c = 0; c < m;) {
+        const int32_t r0 = c < w ? 0 : w + ((c - w) & ~(kPanel - 1));
+        const int32_t height = R - r0;
+        int32_t cols, rows;
+        if (height <= kAsmTile) {
+          cols = std::min(std::min(64, kAsmTile / height), m - c);
+          rows = height;
+        } else {
+          cols = std::min(std::min(asm_cols, 64), m - c);
+          rows = kAsmTile / cols;
         }
-        P.asm_items.push_back({s, c, c1, rbase});
+        const int32_t c1 = c + cols;
+        for (int32_t ra = r0; ra < R; ra += rows) {
+          const int32_t rb = std::min(R, ra + rows);
+          const int32_t rbase = (int32_t)(P.asm_rng.size() / 4);
+          for (int32_t q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+            // child rows (front positions in s, ascending) past its pivots
+            const int32_t ch = S.child_list[q];
+            const int32_t wc = S.sptr[ch + 1] - S.sptr[ch];
+            const int32_t* rm = S.rmap.data() + S.rows_ptr[ch] + wc;
+            const int32_t rc = S.front_m[ch] - wc;
+            P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, c) - rm));
+            P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, c1) - rm));
+            P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, ra) - rm));
+            P.asm_rng.push_back((int32_t)(std::lower_bound(rm, rm + rc, rb) - rm));
+          }
+          P.asm_items.push_back({s, c, c1, rbase, ra, rb});
+        }
+        c = c1;
       }
-      wmax = std::max(wmax, S.sptr[s + 1] - S.sptr[s]);
+      wmax = std::max(wmax, w);
     }
     {
       Step st{kStepAssemble, h, a0, (int64_t)P.asm_items.size()};

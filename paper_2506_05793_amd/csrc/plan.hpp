@@ -9,11 +9,14 @@
 
 namespace tacho {
 
-// Work item of the large-front assembly: columns [c0, c1) of front s; for
-// the q-th child of s, the child's update-matrix columns that land in
-// [c0, c1) are [asm_rng[2 (rbase + q)], asm_rng[2 (rbase + q) + 1]).
+// Work item of the large-front assembly: the entries of front s in columns
+// [c0, c1) and front rows [r0, r1) (at most kAsmTile of them, summed in LDS
+// and written once); for the q-th child of s, the child's update-matrix
+// columns that land in [c0, c1) are [asm_rng[4 (rbase + q)],
+// asm_rng[4 (rbase + q) + 1]) and its rows that land in [r0, r1) are
+// [asm_rng[4 (rbase + q) + 2], asm_rng[4 (rbase + q) + 3]).
 struct AsmItem {
-  int32_t s, c0, c1, rbase;
+  int32_t s, c0, c1, rbase, r0, r1;
 };
 
 // Work item of the panel kernels: diagonal block [k, k+kb) of front s (one
@@ -102,7 +105,7 @@ constexpr int kUBlock = 128;   // rows and columns of an update-matrix block tas
 constexpr int kPanelTaskMax = 1024;  // rows of the largest front whose panel is one task (kind 6)
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
 constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
-constexpr int kAsmElems = 2048;  // front entries per assembly workgroup of a short front
+constexpr int kAsmTile = 4096;   // front entries per assembly work item (its LDS tile)
 constexpr int kSoloM = 192;    // default: fronts with one pivot block and m <= this run as one task
 // Chains per front launch: each holds a workgroup slot while it waits for
 // later tickets.  The FP64 front kernel keeps two workgroups per CU resident
@@ -155,7 +158,7 @@ static_assert(kPackedMax * (kPackedMax + 1) / 2 >= kSmallMax * (kPackedMax + 1),
 constexpr int kPanel = 64;        // panel width of the blocked large-front path
 constexpr int kOuter = 256;       // outer panel width (trailing updates with K = kOuter)
 constexpr int kPanelRows = 64;    // rows per triangular-solve workgroup
-constexpr int kAsmCols = 8;       // front columns per assembly workgroup
+constexpr int kAsmCols = 8;       // front columns per assembly work item of a tall front
 constexpr int kGemmTile = 64;     // output tile of the update kernel
 constexpr int kGemmTileBig = 128; // output tile for large updates
 constexpr int64_t kGemmBigMin = 256 * 256;  // M*N from which the large tile is used
@@ -215,7 +218,7 @@ struct Plan {
   std::vector<int32_t> llarge;
   std::vector<int64_t> llarge_ptr;
   std::vector<int32_t> pull_ptr, pull_src;
-  // assembly: per item and child, the child's column range (see AsmItem)
+  // assembly: per item and child, the child's column and row ranges (see AsmItem)
   std::vector<int32_t> asm_rng;
   // backward partial products: per diagonal block (woff indexing) the first
   // of its ceil(r / kBwdChunk) slots of kPanel x 16 elements
