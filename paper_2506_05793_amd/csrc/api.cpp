@@ -933,7 +933,7 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
       launch_pinv_small<T>(V, Z, y, yf, uv, sm + Q.small_ptr[lvl], Q.small_ptr[lvl + 1] - Q.small_ptr[lvl],
                            true, nrhs, st);
       launch_pinv_fwd<T>(V, Z, y, yf, uv, lg + Q.large_ptr[lvl], Q.large_ptr[lvl + 1] - Q.large_ptr[lvl],
-                         fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl], part, cnt, nrhs, st);
+                         Q.gchunks[lvl], fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl], part, cnt, nrhs, st);
     }
     f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
     pe = f->prof.begin(st);

@@ -105,7 +105,7 @@ void launch_pinv_small(const DevSym& S, const T* Z, T* y, T* yfwd, T* uvec, cons
                        int64_t count, bool forward, int nrhs, hipStream_t st);
 template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
-                     int64_t nfronts, const PinvSweepTask* tasks, int64_t ntasks, T* part,
+                     int64_t nfronts, int gchunks, const PinvSweepTask* tasks, int64_t ntasks, T* part,
                      int32_t* cnt, int nrhs, hipStream_t st);
 template <typename T>
 void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const PinvSweepTask* tasks,

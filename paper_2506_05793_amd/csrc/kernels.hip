@@ -25,6 +25,7 @@ namespace tacho {
 namespace {
 
 constexpr int kThreads = 256;
+static_assert(kPinvGatherRows == kThreads, "the forward gather takes one front row per thread");
 constexpr int kDiagLd = kPanel + 1;  // LDS leading dimension of diagonal blocks
 
 // Row stride of the solve vectors (y and the update vectors): one 128-byte
@@ -1324,23 +1325,25 @@ __device__ __forceinline__ void front_ublock(const DevSym& S, const DevNum<T>& N
     for (int u = 0; u < SL; ++u) {
       const int kg = k0 + lk + RS * u;
       const bool kok = kg < K;
-      const T xa = *((aok && kok) ? pa + (int64_t)kg * ld : Lp);
-      const T xb = *((bok && kok) ? pb + (int64_t)kg * ld : Lp);
-      ra[u] = ((aok && kok) ? T(1) : T(0)) * xa;
-      rb[u] = ((bok && kok) ? T(1) : T(0)) * xb;
+      ra[u] = *((aok && kok) ? pa + (int64_t)kg * ld : Lp);
+      rb[u] = *((bok && kok) ? pb + (int64_t)kg * ld : Lp);
     }
   };
-  auto store_stage = [&](int buf) {
+  // masked-off values become zero only here, so that the loads of the
+  // next stage stay in flight while the current one is multiplied
+  auto store_stage = [&](int buf, int st) {
+    const int k0 = kstart + st * UK;
 #pragma unroll
     for (int u = 0; u < SL; ++u) {
-      As[(buf * UK + lk + RS * u) * (UB + PAD) + lrow] = ra[u];
-      Bs[(buf * UK + lk + RS * u) * (UB + PAD) + lrow] = rb[u];
+      const bool kok = k0 + lk + RS * u < K;
+      As[(buf * UK + lk + RS * u) * (UB + PAD) + lrow] = (aok && kok) ? ra[u] : T(0);
+      Bs[(buf * UK + lk + RS * u) * (UB + PAD) + lrow] = (bok && kok) ? rb[u] : T(0);
     }
   };
   const int nstage = (K - kstart + UK - 1) / UK;
   if (nstage > 0) {
     load_stage(0);
-    store_stage(0);
+    store_stage(0, 0);
     __syncthreads();
   }
   for (int st = 0; st < nstage; ++st) {
@@ -1361,7 +1364,7 @@ __device__ __forceinline__ void front_ublock(const DevSym& S, const DevNum<T>& N
           for (int b = 0; b < QB; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
       }
     }
-    if (st + 1 < nstage) store_stage(buf ^ 1);
+    if (st + 1 < nstage) store_stage(buf ^ 1, st + 1);
     __syncthreads();
   }
   if (tk.rk > 0) {
@@ -1809,23 +1812,25 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
       for (int u = 0; u < SLPT; ++u) {
         const int kg = k0 + lk + RSTEP * u;
         const bool kok = kg < K;
-        const T xa = *((aok && kok) ? pa + (int64_t)kg * ld : (const T*)Lp);
-        const T xb = *((bok && kok) ? pb + (int64_t)kg * ld : (const T*)Lp);
-        ra[u] = ((aok && kok) ? T(1) : T(0)) * xa;
-        rb[u] = ((bok && kok) ? T(1) : T(0)) * xb;
+        ra[u] = *((aok && kok) ? pa + (int64_t)kg * ld : (const T*)Lp);
+        rb[u] = *((bok && kok) ? pb + (int64_t)kg * ld : (const T*)Lp);
       }
     };
-    auto store_stage = [&](int buf) {
+    // masked-off values become zero only here, so that the loads of the
+    // next stage stay in flight while the current one is multiplied
+    auto store_stage = [&](int buf, int st) {
+      const int k0 = kstart + st * KT;
 #pragma unroll
       for (int u = 0; u < SLPT; ++u) {
-        As[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = ra[u];
-        Bs[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = rb[u];
+        const bool kok = k0 + lk + RSTEP * u < K;
+        As[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = (aok && kok) ? ra[u] : T(0);
+        Bs[(buf * KT + lk + RSTEP * u) * (TT + PAD) + lrow] = (bok && kok) ? rb[u] : T(0);
       }
     };
     const int nstage = (K - kstart + KT - 1) / KT;
     if (nstage > 0) {
       load_stage(0);
-      store_stage(0);
+      store_stage(0, 0);
       __syncthreads();
     }
     for (int st = 0; st < nstage; ++st) {
@@ -1855,7 +1860,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
             for (int b = 0; b < BL; ++b) dacc[a][b] = mfma16(bv[b], yv[a], dacc[a][b]);
         }
       }
-      if (st + 1 < nstage) store_stage(buf ^ 1);
+      if (st + 1 < nstage) store_stage(buf ^ 1, st + 1);
       __syncthreads();
     }
   }
@@ -2806,13 +2811,15 @@ __global__ __launch_bounds__(kThreads) void k_pinv_step(DevSym S, T* Z, const T*
 
 // Forward sweep, one level, step 1: each front's vector z = [y_s; 0] plus
 // its children's update vectors (pull map), written back over y_s (pivot
-// rows) and u_s (the other rows).  One workgroup per front.
+// rows) and u_s (the other rows).  gridDim.y workgroups per front,
+// interleaved by kThreads rows.
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_pinv_gather_fwd(DevSym S, T* y, T* uvec,
                                                               const int32_t* fronts) {
   const int s = fronts[blockIdx.x];
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
-  for (int i = threadIdx.x; i < m; i += kThreads) {
+  // rows [kThreads y, ...) of the front, kThreads gridDim.y apart
+  for (int i = blockIdx.y * kThreads + threadIdx.x; i < m; i += kThreads * gridDim.y) {
     const int64_t q = S.rows_ptr[s] + i;
     T z[NR];
     {
@@ -3079,6 +3086,150 @@ __global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, con
     const int c = 16 * wave + mfma_row<T>(lane, v);
     if (c < kb && col < NR) x[(int64_t)(f + c0 + c) * kRowLd<T> + col] = acc[v];
   }
+}
+
+// Partial products of a one-right-hand-side sweep task: value idx (0..63) of
+// chunk c goes to slot + c (threads with own set); the last of the tile's
+// nch chunks to arrive adds them in chunk order into v and returns true.
+template <typename T>
+__device__ inline bool pinv_reduce1(T& v, bool own, int idx, T* part, int32_t* cnt, int slot, int c,
+                                    int nch, int* s_last) {
+  T* P = part + (int64_t)slot * (kPanel * 16);
+  if (own) P[(int64_t)c * (kPanel * 16) + idx] = v;
+  publish_barrier();
+  if (threadIdx.x == 0) {
+    release_agent();
+    const int old = __hip_atomic_fetch_add(cnt + slot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *s_last = (old + 1) % nch == 0;
+    if (*s_last) acquire_agent();
+  }
+  __syncthreads();
+  if (!*s_last) return false;
+  if (own) {
+    T sum = T(0);
+    for (int q = 0; q < nch; ++q) sum += P[(int64_t)q * (kPanel * 16) + idx];
+    v = sum;
+  }
+  return true;
+}
+
+// Forward sweep, one level, step 2, one right-hand side, on the vector
+// units: one lane per row of the 64-row tile, the chunk's columns in four
+// contiguous quarters (one per wave), 32 column loads in flight per lane;
+// the quarters are added in wave order.  Same outputs as k_pinv_fwd.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pinv_fwd1(DevSym S, const T* Z, const T* y, T* yout,
+                                                        T* uvec, const PinvSweepTask* tasks, T* part,
+                                                        int32_t* cnt) {
+  constexpr int U = 32;
+  __shared__ T xs[kPinvChunk];
+  __shared__ T red[kThreads / 64][kPanel];
+  __shared__ int s_last;
+  const PinvSweepTask tk = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s];
+  const int r0 = kPanel * tk.t, nrows = min(kPanel, m - r0);
+  const int kend = min(w, r0 + kPanel);
+  const int klo = tk.c * kPinvChunk, khi = min(kend, klo + kPinvChunk);
+  for (int k = klo + tid; k < khi; k += kThreads) xs[k - klo] = y[(int64_t)(f + k) * kRowLd<T>];
+  __syncthreads();
+  const int n = khi - klo, per = (n + 4 * U - 1) / (4 * U) * U;
+  const int q0 = min(n, wave * per), q1 = min(n, q0 + per);
+  const T* zr = Z + S.L_off[s] + r0 + min(lane, nrows - 1) + (int64_t)klo * ld;
+  T acc = T(0);
+  for (int k = q0; k < q1; k += U) {
+    T z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) z[u] = zr[(int64_t)min(k + u, q1 - 1) * ld];
+    __builtin_amdgcn_sched_barrier(0);  // all U loads in flight before the first use
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T xv = xs[min(k + u, q1 - 1)];
+      acc += z[u] * (k + u < q1 ? xv : T(0));
+    }
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  T v = T(0);
+  if (wave == 0) v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  if (tk.slot >= 0 && !pinv_reduce1<T>(v, wave == 0, lane, part, cnt, tk.slot, tk.c,
+                                       (kend + kPinvChunk - 1) / kPinvChunk, &s_last))
+    return;
+  if (wave == 0 && lane < nrows) {
+    const int i = r0 + lane;
+    if (i < w) {
+      yout[(int64_t)(f + i) * kRowLd<T>] = v;
+    } else {
+      T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T>;
+      *ur = *ur - v;
+    }
+  }
+}
+
+// Backward sweep, one level, one right-hand side, on the vector units:
+// columns [64t, 64t + kb) of the front's solution, x = Z11^T yfwd_s - Z21^T
+// x_rows over one chunk of the rows from 64t on.  One lane per row, 16 of
+// the block's columns per wave, two 64-row groups (32 column loads) in flight
+// per lane; every column's 64 lane sums are added in a fixed order.  Same
+// outputs as k_pinv_bwd.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pinv_bwd1(DevSym S, const T* Z, const T* yfwd, T* x,
+                                                        const PinvSweepTask* tasks, T* part,
+                                                        int32_t* cnt) {
+  __shared__ T vs[kPinvChunk];
+  __shared__ T red[kPanel][kPanel + 1];  // [column][lane]
+  __shared__ T red2[kPanel][4];
+  __shared__ int s_last;
+  const PinvSweepTask tk = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int ld = S.ldL[s];
+  const int32_t* rws = S.rows + S.rows_ptr[s];
+  const int c0 = kPanel * tk.t, kb = min(kPanel, w - c0);
+  const int ilo = c0 + tk.c * kPinvChunk, ihi = min(m, ilo + kPinvChunk);
+  for (int i = ilo + tid; i < ihi; i += kThreads)
+    vs[i - ilo] = i < w ? yfwd[(int64_t)(f + i) * kRowLd<T>] : -x[(int64_t)rws[i] * kRowLd<T>];
+  __syncthreads();
+  const int cb = wave * 16;
+  const T* zc = Z + S.L_off[s] + (int64_t)c0 * ld;
+  T acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = T(0);
+  for (int i0 = ilo; i0 < ihi; i0 += 2 * kPanel) {
+    T z[2][16], v[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int i = i0 + g * kPanel + lane;
+      const int ic = min(i, ihi - 1);
+      v[g] = vs[ic - ilo] * (i < ihi ? T(1) : T(0));
+#pragma unroll
+      for (int u = 0; u < 16; ++u) z[g][u] = zc[ic + (int64_t)min(cb + u, kb - 1) * ld];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // all 32 loads in flight before the first use
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] += z[g][u] * v[g];
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) red[cb + u][lane] = acc[u];
+  __syncthreads();
+  {
+    // four threads per column, 16 lanes each, then the four in order
+    const int c = tid >> 2, pq = tid & 3;
+    T sum = T(0);
+#pragma unroll
+    for (int l = 0; l < 16; ++l) sum += red[c][pq * 16 + l];
+    red2[c][pq] = sum;
+  }
+  __syncthreads();
+  T v = T(0);
+  if (tid < kPanel) v = ((red2[tid][0] + red2[tid][1]) + red2[tid][2]) + red2[tid][3];
+  if (tk.slot >= 0 && !pinv_reduce1<T>(v, tid < kPanel, tid, part, cnt, tk.slot, tk.c,
+                                       (m - c0 + kPinvChunk - 1) / kPinvChunk, &s_last))
+    return;
+  if (tid < kb) x[(int64_t)(f + c0 + tid) * kRowLd<T>] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -3441,14 +3592,15 @@ void launch_pinv_small(const DevSym& S, const T* Z, T* y, T* yfwd, T* uvec, cons
 
 template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
-                     int64_t nfronts, const PinvSweepTask* tasks, int64_t ntasks, T* part,
+                     int64_t nfronts, int gchunks, const PinvSweepTask* tasks, int64_t ntasks, T* part,
                      int32_t* cnt, int nrhs, hipStream_t st) {
   if (nfronts <= 0) return;
+  const dim3 ggrid((unsigned)nfronts, (unsigned)std::max(1, gchunks));
   if (nrhs == 1) {
-    hipLaunchKernelGGL((k_pinv_gather_fwd<T, 1>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, y, uvec, fronts);
-    hipLaunchKernelGGL((k_pinv_fwd<T, 1>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part, cnt);
+    hipLaunchKernelGGL((k_pinv_gather_fwd<T, 1>), ggrid, dim3(kThreads), 0, st, S, y, uvec, fronts);
+    hipLaunchKernelGGL((k_pinv_fwd1<T>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part, cnt);
   } else {
-    hipLaunchKernelGGL((k_pinv_gather_fwd<T, 16>), dim3((unsigned)nfronts), dim3(kThreads), 0, st, S, y, uvec, fronts);
+    hipLaunchKernelGGL((k_pinv_gather_fwd<T, 16>), ggrid, dim3(kThreads), 0, st, S, y, uvec, fronts);
     hipLaunchKernelGGL((k_pinv_fwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part, cnt);
   }
 }
@@ -3458,7 +3610,7 @@ void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const Pin
                      int64_t ntasks, T* part, int32_t* cnt, int nrhs, hipStream_t st) {
   if (ntasks <= 0) return;
   if (nrhs == 1)
-    hipLaunchKernelGGL((k_pinv_bwd<T, 1>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part, cnt);
+    hipLaunchKernelGGL((k_pinv_bwd1<T>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part, cnt);
   else
     hipLaunchKernelGGL((k_pinv_bwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part, cnt);
 }
@@ -3534,7 +3686,7 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
   template void launch_pinv_small<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t, \
                                      bool, int, hipStream_t);                                    \
   template void launch_pinv_fwd<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t,  \
-                                   const PinvSweepTask*, int64_t, T*, int32_t*, int,             \
+                                   int, const PinvSweepTask*, int64_t, T*, int32_t*, int,        \
                                    hipStream_t);                                                 \
   template void launch_pinv_bwd<T>(const DevSym&, const T*, const T*, T*, const PinvSweepTask*,   \
                                    int64_t, T*, int32_t*, int, hipStream_t);                     \

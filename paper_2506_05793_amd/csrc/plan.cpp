@@ -793,6 +793,7 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
   Q.small_ptr.assign(1, 0);
   Q.large_ptr.assign(1, 0);
   Q.slots = 0;
+  Q.gchunks.clear();
   auto add = [&](std::vector<PinvSweepTask>& v, int32_t s, int32_t t, int32_t len) {
     const int32_t nch = (len + kPinvChunk - 1) / kPinvChunk;
     const int32_t slot = nch > 1 ? (int32_t)Q.slots : -1;
@@ -800,6 +801,7 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
     for (int32_t c = 0; c < nch; ++c) v.push_back({s, t, c, slot});
   };
   for (int32_t h = 0; h < S.nlevels; ++h) {
+    int32_t gch = 1;
     for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
       const int32_t s = S.level_list[q];
       const int32_t w = S.sptr[s + 1] - S.sptr[s], m = S.front_m[s];
@@ -808,6 +810,7 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
         continue;
       }
       Q.large.push_back(s);
+      gch = std::max(gch, std::min(kPinvGatherMax, (m + kPinvGatherRows - 1) / kPinvGatherRows));
       // forward: rows of Z11 see only the columns up to their own
       for (int32_t a = 0; a * kPanel < m; ++a) add(Q.frow, s, a, std::min(w, (a + 1) * kPanel));
       // backward: Z is zero above a column's diagonal
@@ -817,6 +820,7 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
     Q.bcol_ptr.push_back((int64_t)Q.bcol.size());
     Q.small_ptr.push_back((int64_t)Q.small.size());
     Q.large_ptr.push_back((int64_t)Q.large.size());
+    Q.gchunks.push_back(gch);
   }
 }
 

@@ -267,6 +267,8 @@ struct PinvSweepTask {
 };
 constexpr int kPinvChunk = 512;
 constexpr int kPinvSmallM = 128;  // wave-per-front sweeps: two rows per lane
+constexpr int kPinvGatherRows = 256;  // front rows per workgroup of the forward gather (its threads)
+constexpr int kPinvGatherMax = 16;    // workgroups per front of the forward gather
 struct PinvPlan {
   // setup: launch q runs tasks [setup_ptr[q], setup_ptr[q + 1]); launch 0
   // scales every front's last block column, launch q >= 1 applies the block
@@ -283,6 +285,9 @@ struct PinvPlan {
   std::vector<int64_t> small_ptr, large_ptr;
   std::vector<PinvSweepTask> frow, bcol;
   std::vector<int64_t> frow_ptr, bcol_ptr;
+  // per level: workgroups per large front of the forward gather (one per
+  // kPinvGatherRows rows of its largest front, at most kPinvGatherMax)
+  std::vector<int32_t> gchunks;
   int64_t slots = 0;  // partial-product slots (and arrival counters) of the sweeps
   double flops = 0;   // setup flops (2 per multiply-add of the tile products)
 };
