@@ -146,7 +146,7 @@ struct tacho_sym {
   DevSym view1{};
   // partitioned-inverse solves: their plan, built on first use
   std::unique_ptr<PinvPlan> Q;
-  DBuf dq_setup, dq_tiles, dq_frow, dq_bcol, dq_small, dq_large;
+  DBuf dq_setup, dq_tiles, dq_frow, dq_bcol, dq_fsum, dq_bsum, dq_small, dq_large;
 };
 
 // Per-launch timing of the library's kernels on the caller's stream (hipEvents
@@ -250,7 +250,7 @@ struct tacho_num {
   hipGraphExec_t fgraph = nullptr;  // captured factorization launch sequence
   int solve_variant = TACHO_SOLVE_BLOCK_INVERSE;
   DBuf Z, yfwd;                   // partitioned inverse (layout of L) and forward result rows
-  DBuf zpart, zcnt;               // its sweeps' chunk partial products and arrival counters
+  DBuf zpart;                     // its sweeps' chunk partial products
   ~tacho_num() {
     if (fgraph) (void)hipGraphExecDestroy(fgraph);
     for (auto& e : ev)
@@ -497,6 +497,8 @@ int ensure_pinv(tacho_sym* h) {
   HIP_TRY(upload(h->dq_tiles, Q->tiles));
   HIP_TRY(upload(h->dq_frow, Q->frow));
   HIP_TRY(upload(h->dq_bcol, Q->bcol));
+  HIP_TRY(upload(h->dq_fsum, Q->fsum));
+  HIP_TRY(upload(h->dq_bsum, Q->bsum));
   HIP_TRY(upload(h->dq_small, Q->small));
   HIP_TRY(upload(h->dq_large, Q->large));
   h->Q = std::move(Q);
@@ -926,22 +928,24 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
     const int32_t* lg = h->dq_large.as<int32_t>();
     const PinvSweepTask* fr = h->dq_frow.as<PinvSweepTask>();
     const PinvSweepTask* bc = h->dq_bcol.as<PinvSweepTask>();
+    const PinvSweepTask* fs = h->dq_fsum.as<PinvSweepTask>();
+    const PinvSweepTask* bs = h->dq_bsum.as<PinvSweepTask>();
     T* part = f->zpart.as<T>();
-    int32_t* cnt = f->zcnt.as<int32_t>();
     pe = f->prof.begin(st);
     for (int32_t lvl = 0; lvl < S.nlevels; ++lvl) {
       launch_pinv_small<T>(V, Z, y, yf, uv, sm + Q.small_ptr[lvl], Q.small_ptr[lvl + 1] - Q.small_ptr[lvl],
                            true, nrhs, st);
       launch_pinv_fwd<T>(V, Z, y, yf, uv, lg + Q.large_ptr[lvl], Q.large_ptr[lvl + 1] - Q.large_ptr[lvl],
-                         Q.gchunks[lvl], fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl], part, cnt, nrhs, st);
+                         Q.gchunks[lvl], fr + Q.frow_ptr[lvl], Q.frow_ptr[lvl + 1] - Q.frow_ptr[lvl],
+                         fs + Q.fsum_ptr[lvl], Q.fsum_ptr[lvl + 1] - Q.fsum_ptr[lvl], part, nrhs, st);
     }
     f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
     pe = f->prof.begin(st);
     for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl) {
       launch_pinv_small<T>(V, Z, y, yf, uv, sm + Q.small_ptr[lvl], Q.small_ptr[lvl + 1] - Q.small_ptr[lvl],
                            false, nrhs, st);
-      launch_pinv_bwd<T>(V, Z, yf, y, bc + Q.bcol_ptr[lvl], Q.bcol_ptr[lvl + 1] - Q.bcol_ptr[lvl], part,
-                         cnt, nrhs, st);
+      launch_pinv_bwd<T>(V, Z, yf, y, bc + Q.bcol_ptr[lvl], Q.bcol_ptr[lvl + 1] - Q.bcol_ptr[lvl],
+                         bs + Q.bsum_ptr[lvl], Q.bsum_ptr[lvl + 1] - Q.bsum_ptr[lvl], part, nrhs, st);
     }
     f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * lentries * nrhs, es * (lentries + 2.0 * rows * nrhs));
     pe = f->prof.begin(st);
@@ -1485,12 +1489,8 @@ int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
   if (f->yfwd.bytes < ybytes) HIP_TRY(f->yfwd.alloc(ybytes));
   {
     const int64_t slots = std::max<int64_t>(h->Q->slots, 1);
-    const size_t pbytes = es * (size_t)slots * kPanel * kRhs, cbytes = sizeof(int32_t) * (size_t)slots;
+    const size_t pbytes = es * (size_t)slots * kPanel * kRhs;
     if (f->zpart.bytes < pbytes) HIP_TRY(f->zpart.alloc(pbytes));
-    if (f->zcnt.bytes < cbytes) {
-      HIP_TRY(f->zcnt.alloc(cbytes));
-      HIP_TRY(clear_device(f->zcnt.p, cbytes));
-    }
   }
   hipStream_t st = (hipStream_t)hip_stream;
   if (f->precision == TACHO_FP32)

@@ -105,11 +105,12 @@ void launch_pinv_small(const DevSym& S, const T* Z, T* y, T* yfwd, T* uvec, cons
                        int64_t count, bool forward, int nrhs, hipStream_t st);
 template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
-                     int64_t nfronts, int gchunks, const PinvSweepTask* tasks, int64_t ntasks, T* part,
-                     int32_t* cnt, int nrhs, hipStream_t st);
+                     int64_t nfronts, int gchunks, const PinvSweepTask* tasks, int64_t ntasks,
+                     const PinvSweepTask* sums, int64_t nsums, T* part, int nrhs, hipStream_t st);
 template <typename T>
 void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const PinvSweepTask* tasks,
-                     int64_t ntasks, T* part, int32_t* cnt, int nrhs, hipStream_t st);
+                     int64_t ntasks, const PinvSweepTask* sums, int64_t nsums, T* part, int nrhs,
+                     hipStream_t st);
 template <typename T>
 void launch_assemble(const DevSym& S, const DevNum<T>& N, const AsmItem* items, int64_t count,
                      hipStream_t st);

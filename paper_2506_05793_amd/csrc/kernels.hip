@@ -2944,36 +2944,56 @@ __global__ __launch_bounds__(kThreads) void k_pinv_small_bwd(DevSym S, const T* 
   }
 }
 
-// Partial product of a chunked sweep task: chunk c of the tile stores its
-// 64 x 16 values in slot + c; the chunk that arrives last (per-tile counter,
-// which only ever grows by the tile's chunk count per sweep) reads them all
-// back and returns their sum in chunk order in `acc` (true), the others
-// return false.
+// Partial product of one chunk of a sweep tile with several chunks (the
+// matrix-core layout of the tile's 64 x 16 results): value (i, col) goes to
+// part[slot kPanel 16 + i 16 + col].
 template <typename T>
-__device__ inline bool pinv_reduce(typename Vec4<T>::type& acc, T* part, int32_t* cnt, int slot,
-                                   int c, int nch, int* s_last) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, col = lane & 15;
+__device__ inline void pinv_partial(const typename Vec4<T>::type& acc, T* part, int slot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   T* P = part + (int64_t)slot * (kPanel * 16);
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
-    P[(int64_t)c * (kPanel * 16) + (16 * wave + mfma_row<T>(lane, v)) * 16 + col] = acc[v];
-  publish_barrier();
-  if (tid == 0) {
-    release_agent();
-    const int old = __hip_atomic_fetch_add(cnt + slot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *s_last = (old + 1) % nch == 0;
-    if (*s_last) acquire_agent();
-  }
-  __syncthreads();
-  if (!*s_last) return false;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int idx = (16 * wave + mfma_row<T>(lane, v)) * 16 + col;
+  for (int v = 0; v < 4; ++v) P[(16 * wave + mfma_row<T>(lane, v)) * 16 + (lane & 15)] = acc[v];
+}
+
+// Sum tasks of a sweep (a launch after the chunks'): tile t of front s had
+// tk.c chunks; their partial products (slots tk.slot, tk.slot + 1, ...) are
+// added in chunk order and written as a one-chunk tile writes its result.
+// Forward: rows of Z11 to yout, the others subtracted from the update vector.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_fsum(DevSym S, T* yout, T* uvec,
+                                                        const PinvSweepTask* tasks, const T* part) {
+  const PinvSweepTask tk = tasks[blockIdx.x];
+  const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
+  const int r0 = kPanel * tk.t, nrows = min(kPanel, m - r0);
+  for (int q = threadIdx.x; q < nrows * NR; q += kThreads) {
+    const int li = q / NR, col = q - li * NR;
+    const T* P = part + (int64_t)tk.slot * (kPanel * 16) + li * 16 + col;
     T sum = T(0);
-    for (int q = 0; q < nch; ++q) sum += P[(int64_t)q * (kPanel * 16) + idx];
-    acc[v] = sum;
+    for (int c = 0; c < tk.c; ++c) sum += P[(int64_t)c * (kPanel * 16)];
+    const int i = r0 + li;
+    if (i < w) {
+      yout[(int64_t)(f + i) * kRowLd<T> + col] = sum;
+    } else {
+      T* ur = uvec + (S.u_off[s] + (i - w)) * kRowLd<T> + col;
+      *ur = *ur - sum;
+    }
   }
-  return true;
+}
+
+// Backward: columns [64t, 64t + kb) of the front's solution.
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_pinv_bsum(DevSym S, T* x, const PinvSweepTask* tasks,
+                                                        const T* part) {
+  const PinvSweepTask tk = tasks[blockIdx.x];
+  const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f;
+  const int c0 = kPanel * tk.t, kb = min(kPanel, w - c0);
+  for (int q = threadIdx.x; q < kb * NR; q += kThreads) {
+    const int c = q / NR, col = q - c * NR;
+    const T* P = part + (int64_t)tk.slot * (kPanel * 16) + c * 16 + col;
+    T sum = T(0);
+    for (int k = 0; k < tk.c; ++k) sum += P[(int64_t)k * (kPanel * 16)];
+    x[(int64_t)(f + c0 + c) * kRowLd<T> + col] = sum;
+  }
 }
 
 // Forward sweep, one level, step 2: 64 rows of Z_s times z_s (pivot rows of
@@ -2984,9 +3004,8 @@ __device__ inline bool pinv_reduce(typename Vec4<T>::type& acc, T* part, int32_t
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_pinv_fwd(DevSym S, const T* Z, const T* y, T* yout,
                                                        T* uvec, const PinvSweepTask* tasks,
-                                                       T* part, int32_t* cnt) {
+                                                       T* part) {
   typedef typename Vec4<T>::type V4;
-  __shared__ int s_last;
   const PinvSweepTask tk = tasks[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
@@ -3015,9 +3034,10 @@ __global__ __launch_bounds__(kThreads) void k_pinv_fwd(DevSym S, const T* Z, con
       acc = mfma16(a[q], b, acc);
     }
   }
-  if (tk.slot >= 0 &&
-      !pinv_reduce<T>(acc, part, cnt, tk.slot, tk.c, (kend + kPinvChunk - 1) / kPinvChunk, &s_last))
+  if (tk.slot >= 0) {
+    pinv_partial<T>(acc, part, tk.slot + tk.c);
     return;
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int i = r0 + 16 * wave + mfma_row<T>(lane, v);
@@ -3038,12 +3058,10 @@ __global__ __launch_bounds__(kThreads) void k_pinv_fwd(DevSym S, const T* Z, con
 // solutions, final once the ancestors are done, read in place).
 template <typename T, int NR>
 __global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, const T* yfwd, T* x,
-                                                       const PinvSweepTask* tasks, T* part,
-                                                       int32_t* cnt) {
+                                                       const PinvSweepTask* tasks, T* part) {
   typedef typename Vec4<T>::type V4;
   __shared__ T Ls[kPanel * kDiagLd];
   __shared__ T Vs[kPanel * 16];
-  __shared__ int s_last;
   const PinvSweepTask tk = tasks[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
@@ -3078,39 +3096,15 @@ __global__ __launch_bounds__(kThreads) void k_pinv_bwd(DevSym S, const T* Z, con
     }
     __syncthreads();
   }
-  if (tk.slot >= 0 &&
-      !pinv_reduce<T>(acc, part, cnt, tk.slot, tk.c, (m - c0 + kPinvChunk - 1) / kPinvChunk, &s_last))
+  if (tk.slot >= 0) {
+    pinv_partial<T>(acc, part, tk.slot + tk.c);
     return;
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int c = 16 * wave + mfma_row<T>(lane, v);
     if (c < kb && col < NR) x[(int64_t)(f + c0 + c) * kRowLd<T> + col] = acc[v];
   }
-}
-
-// Partial products of a one-right-hand-side sweep task: value idx (0..63) of
-// chunk c goes to slot + c (threads with own set); the last of the tile's
-// nch chunks to arrive adds them in chunk order into v and returns true.
-template <typename T>
-__device__ inline bool pinv_reduce1(T& v, bool own, int idx, T* part, int32_t* cnt, int slot, int c,
-                                    int nch, int* s_last) {
-  T* P = part + (int64_t)slot * (kPanel * 16);
-  if (own) P[(int64_t)c * (kPanel * 16) + idx] = v;
-  publish_barrier();
-  if (threadIdx.x == 0) {
-    release_agent();
-    const int old = __hip_atomic_fetch_add(cnt + slot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *s_last = (old + 1) % nch == 0;
-    if (*s_last) acquire_agent();
-  }
-  __syncthreads();
-  if (!*s_last) return false;
-  if (own) {
-    T sum = T(0);
-    for (int q = 0; q < nch; ++q) sum += P[(int64_t)q * (kPanel * 16) + idx];
-    v = sum;
-  }
-  return true;
 }
 
 // Forward sweep, one level, step 2, one right-hand side, on the vector
@@ -3119,12 +3113,10 @@ __device__ inline bool pinv_reduce1(T& v, bool own, int idx, T* part, int32_t* c
 // the quarters are added in wave order.  Same outputs as k_pinv_fwd.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_pinv_fwd1(DevSym S, const T* Z, const T* y, T* yout,
-                                                        T* uvec, const PinvSweepTask* tasks, T* part,
-                                                        int32_t* cnt) {
-  constexpr int U = 32;
+                                                        T* uvec, const PinvSweepTask* tasks, T* part) {
+  constexpr int U = 16;
   __shared__ T xs[kPinvChunk];
   __shared__ T red[kThreads / 64][kPanel];
-  __shared__ int s_last;
   const PinvSweepTask tk = tasks[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
@@ -3153,9 +3145,10 @@ __global__ __launch_bounds__(kThreads) void k_pinv_fwd1(DevSym S, const T* Z, co
   __syncthreads();
   T v = T(0);
   if (wave == 0) v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-  if (tk.slot >= 0 && !pinv_reduce1<T>(v, wave == 0, lane, part, cnt, tk.slot, tk.c,
-                                       (kend + kPinvChunk - 1) / kPinvChunk, &s_last))
+  if (tk.slot >= 0) {
+    if (wave == 0) part[(int64_t)(tk.slot + tk.c) * (kPanel * 16) + lane * 16] = v;
     return;
+  }
   if (wave == 0 && lane < nrows) {
     const int i = r0 + lane;
     if (i < w) {
@@ -3175,12 +3168,10 @@ __global__ __launch_bounds__(kThreads) void k_pinv_fwd1(DevSym S, const T* Z, co
 // outputs as k_pinv_bwd.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_pinv_bwd1(DevSym S, const T* Z, const T* yfwd, T* x,
-                                                        const PinvSweepTask* tasks, T* part,
-                                                        int32_t* cnt) {
+                                                        const PinvSweepTask* tasks, T* part) {
   __shared__ T vs[kPinvChunk];
   __shared__ T red[kPanel][kPanel + 1];  // [column][lane]
   __shared__ T red2[kPanel][4];
-  __shared__ int s_last;
   const PinvSweepTask tk = tasks[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = tk.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s];
@@ -3226,9 +3217,10 @@ __global__ __launch_bounds__(kThreads) void k_pinv_bwd1(DevSym S, const T* Z, co
   __syncthreads();
   T v = T(0);
   if (tid < kPanel) v = ((red2[tid][0] + red2[tid][1]) + red2[tid][2]) + red2[tid][3];
-  if (tk.slot >= 0 && !pinv_reduce1<T>(v, tid < kPanel, tid, part, cnt, tk.slot, tk.c,
-                                       (m - c0 + kPinvChunk - 1) / kPinvChunk, &s_last))
+  if (tk.slot >= 0) {
+    if (tid < kPanel) part[(int64_t)(tk.slot + tk.c) * (kPanel * 16) + tid * 16] = v;
     return;
+  }
   if (tid < kb) x[(int64_t)(f + c0 + tid) * kRowLd<T>] = v;
 }
 
@@ -3592,27 +3584,37 @@ void launch_pinv_small(const DevSym& S, const T* Z, T* y, T* yfwd, T* uvec, cons
 
 template <typename T>
 void launch_pinv_fwd(const DevSym& S, const T* Z, T* y, T* yout, T* uvec, const int32_t* fronts,
-                     int64_t nfronts, int gchunks, const PinvSweepTask* tasks, int64_t ntasks, T* part,
-                     int32_t* cnt, int nrhs, hipStream_t st) {
+                     int64_t nfronts, int gchunks, const PinvSweepTask* tasks, int64_t ntasks,
+                     const PinvSweepTask* sums, int64_t nsums, T* part, int nrhs, hipStream_t st) {
   if (nfronts <= 0) return;
   const dim3 ggrid((unsigned)nfronts, (unsigned)std::max(1, gchunks));
   if (nrhs == 1) {
     hipLaunchKernelGGL((k_pinv_gather_fwd<T, 1>), ggrid, dim3(kThreads), 0, st, S, y, uvec, fronts);
-    hipLaunchKernelGGL((k_pinv_fwd1<T>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part, cnt);
+    hipLaunchKernelGGL((k_pinv_fwd1<T>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part);
+    if (nsums > 0)
+      hipLaunchKernelGGL((k_pinv_fsum<T, 1>), dim3((unsigned)nsums), dim3(kThreads), 0, st, S, yout, uvec, sums, (const T*)part);
   } else {
     hipLaunchKernelGGL((k_pinv_gather_fwd<T, 16>), ggrid, dim3(kThreads), 0, st, S, y, uvec, fronts);
-    hipLaunchKernelGGL((k_pinv_fwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part, cnt);
+    hipLaunchKernelGGL((k_pinv_fwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, y, yout, uvec, tasks, part);
+    if (nsums > 0)
+      hipLaunchKernelGGL((k_pinv_fsum<T, 16>), dim3((unsigned)nsums), dim3(kThreads), 0, st, S, yout, uvec, sums, (const T*)part);
   }
 }
 
 template <typename T>
 void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const PinvSweepTask* tasks,
-                     int64_t ntasks, T* part, int32_t* cnt, int nrhs, hipStream_t st) {
+                     int64_t ntasks, const PinvSweepTask* sums, int64_t nsums, T* part, int nrhs,
+                     hipStream_t st) {
   if (ntasks <= 0) return;
-  if (nrhs == 1)
-    hipLaunchKernelGGL((k_pinv_bwd1<T>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part, cnt);
-  else
-    hipLaunchKernelGGL((k_pinv_bwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part, cnt);
+  if (nrhs == 1) {
+    hipLaunchKernelGGL((k_pinv_bwd1<T>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part);
+    if (nsums > 0)
+      hipLaunchKernelGGL((k_pinv_bsum<T, 1>), dim3((unsigned)nsums), dim3(kThreads), 0, st, S, x, sums, (const T*)part);
+  } else {
+    hipLaunchKernelGGL((k_pinv_bwd<T, 16>), dim3((unsigned)ntasks), dim3(kThreads), 0, st, S, Z, yfwd, x, tasks, part);
+    if (nsums > 0)
+      hipLaunchKernelGGL((k_pinv_bsum<T, 16>), dim3((unsigned)nsums), dim3(kThreads), 0, st, S, x, sums, (const T*)part);
+  }
 }
 
 template <typename T>
@@ -3686,10 +3688,10 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
   template void launch_pinv_small<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t, \
                                      bool, int, hipStream_t);                                    \
   template void launch_pinv_fwd<T>(const DevSym&, const T*, T*, T*, T*, const int32_t*, int64_t,  \
-                                   int, const PinvSweepTask*, int64_t, T*, int32_t*, int,        \
-                                   hipStream_t);                                                 \
+                                   int, const PinvSweepTask*, int64_t, const PinvSweepTask*,     \
+                                   int64_t, T*, int, hipStream_t);                               \
   template void launch_pinv_bwd<T>(const DevSym&, const T*, const T*, T*, const PinvSweepTask*,   \
-                                   int64_t, T*, int32_t*, int, hipStream_t);                     \
+                                   int64_t, const PinvSweepTask*, int64_t, T*, int, hipStream_t); \
   template void launch_leaf<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,          \
                                hipStream_t);                                                     \
   template void launch_assemble<T>(const DevSym&, const DevNum<T>&, const AsmItem*, int64_t,      \

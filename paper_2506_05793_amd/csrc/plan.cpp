@@ -794,10 +794,18 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
   Q.large_ptr.assign(1, 0);
   Q.slots = 0;
   Q.gchunks.clear();
-  auto add = [&](std::vector<PinvSweepTask>& v, int32_t s, int32_t t, int32_t len) {
+  Q.fsum.clear();
+  Q.bsum.clear();
+  Q.fsum_ptr.assign(1, 0);
+  Q.bsum_ptr.assign(1, 0);
+  auto add = [&](std::vector<PinvSweepTask>& v, std::vector<PinvSweepTask>& sum, int32_t s, int32_t t,
+                 int32_t len) {
     const int32_t nch = (len + kPinvChunk - 1) / kPinvChunk;
     const int32_t slot = nch > 1 ? (int32_t)Q.slots : -1;
-    if (nch > 1) Q.slots += nch;
+    if (nch > 1) {
+      Q.slots += nch;
+      sum.push_back({s, t, nch, slot});
+    }
     for (int32_t c = 0; c < nch; ++c) v.push_back({s, t, c, slot});
   };
   for (int32_t h = 0; h < S.nlevels; ++h) {
@@ -812,15 +820,17 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
       Q.large.push_back(s);
       gch = std::max(gch, std::min(kPinvGatherMax, (m + kPinvGatherRows - 1) / kPinvGatherRows));
       // forward: rows of Z11 see only the columns up to their own
-      for (int32_t a = 0; a * kPanel < m; ++a) add(Q.frow, s, a, std::min(w, (a + 1) * kPanel));
+      for (int32_t a = 0; a * kPanel < m; ++a) add(Q.frow, Q.fsum, s, a, std::min(w, (a + 1) * kPanel));
       // backward: Z is zero above a column's diagonal
-      for (int32_t c = 0; c * kPanel < w; ++c) add(Q.bcol, s, c, m - c * kPanel);
+      for (int32_t c = 0; c * kPanel < w; ++c) add(Q.bcol, Q.bsum, s, c, m - c * kPanel);
     }
     Q.frow_ptr.push_back((int64_t)Q.frow.size());
     Q.bcol_ptr.push_back((int64_t)Q.bcol.size());
     Q.small_ptr.push_back((int64_t)Q.small.size());
     Q.large_ptr.push_back((int64_t)Q.large.size());
     Q.gchunks.push_back(gch);
+    Q.fsum_ptr.push_back((int64_t)Q.fsum.size());
+    Q.bsum_ptr.push_back((int64_t)Q.bsum.size());
   }
 }
 

@@ -260,8 +260,9 @@ struct FrontTile {
 // A sweep task: tile t of front s (forward: 64 rows, backward: 64 columns),
 // the chunk c of its reduction dimension (kPinvChunk columns forward, rows
 // backward).  A tile with one chunk writes its result itself (slot < 0);
-// otherwise chunk c stores a partial product in slot + c, and the last of
-// the tile's chunks to finish adds them in chunk order and writes the result.
+// otherwise chunk c stores a partial product in slot slot + c, and a sum
+// task {s, t, nch, slot} of the next launch adds the tile's nch partial
+// products in chunk order and writes the result.
 struct PinvSweepTask {
   int32_t s, t, c, slot;
 };
@@ -285,10 +286,14 @@ struct PinvPlan {
   std::vector<int64_t> small_ptr, large_ptr;
   std::vector<PinvSweepTask> frow, bcol;
   std::vector<int64_t> frow_ptr, bcol_ptr;
+  // per level: sum tasks of the tiles with several chunks [fsum_ptr[h],
+  // fsum_ptr[h + 1]) forward, [bsum_ptr[h], ...) backward
+  std::vector<PinvSweepTask> fsum, bsum;
+  std::vector<int64_t> fsum_ptr, bsum_ptr;
   // per level: workgroups per large front of the forward gather (one per
   // kPinvGatherRows rows of its largest front, at most kPinvGatherMax)
   std::vector<int32_t> gchunks;
-  int64_t slots = 0;  // partial-product slots (and arrival counters) of the sweeps
+  int64_t slots = 0;  // partial-product slots of the sweeps
   double flops = 0;   // setup flops (2 per multiply-add of the tile products)
 };
 
