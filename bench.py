@@ -803,8 +803,9 @@ def autotune_workload(args, T, A, tag):
     landice = tag == "landice200"
     cands = dict(autotune.CANDIDATES)
     if landice:  # analysis takes seconds here: a reduced candidate set
-        cands = {"u_range": (4, 8, 16, 32, 64), "chain_min": (2, 3, 4, 6, 8, -1), "chain_inplace": (0, -1),
-                 "asm_cols": (4, 8), "solo_m": (-1, 128, 192), "solve_level_fronts": (64, 256, 1024)}
+        cands = {"chain_min": (2, 3, 4, 6, 8, -1), "chain_inplace": (0, -1),
+                 "asm_cols": (4, 8, 16), "solo_m": (-1, 128, 192, 256, 384),
+                 "solve_level_fronts": (64, 256, 1024)}
     for prec, name in ((T.TACHO_FP64, "fp64"), (T.TACHO_FP32, "fp32")):
         fixed = {} if landice else autotune.tuned_params(1, 1, prec)  # order entry only
         c = {k: v for k, v in cands.items() if landice or k in autotune.ORDER_NEUTRAL}

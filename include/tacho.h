@@ -109,14 +109,18 @@ typedef struct {
    * u_range, chain_min and chain_inplace change the order in which a front's
    * contributions are summed, so results agree to rounding.  The autotuner
    * of the Python package times candidates on the device. */
-  int32_t u_range;           /* pivot blocks per update-matrix range task (default 8) */
+  int32_t u_range;           /* pivot blocks per update-matrix range task (default 8);
+                                the dataflow plan forms update matrices in a launch of
+                                their own after the panels, over all pivot blocks at
+                                once, so it takes no ranges and this has no effect there */
   int32_t chain_min;         /* fronts with at least this many 64-column pivot blocks
                                 run their diagonal blocks as one chain task (default 3;
                                 negative: never) */
   int32_t solve_level_fronts; /* solve levels below the last level with more than
                                 this many fronts run level by level (default 256) */
-  int32_t asm_cols;          /* front columns per assembly workgroup, at least (default 8;
-                                short fronts get up to 2048 / m columns, at most 64) */
+  int32_t asm_cols;          /* front columns per assembly work item of a front taller
+                                than 4096 rows (default 8; shorter fronts get whole
+                                columns, as many as fit in 4096 entries, at most 64) */
   int32_t solo_m;            /* fronts with one pivot block (w <= 64) and at most this
                                 many rows run as one task each, without completion
                                 flags (default 192; negative: never) */

@@ -8,12 +8,14 @@ top their own kernels; where the boundary between the two regimes lies
 depends on the matrix and the device):
 
 * ``u_range`` - pivot blocks per update-matrix range task of the dataflow
-  front kernel;
+  front kernel (the current plan forms update matrices in a launch of their
+  own, over all pivot blocks, so it is kept in the table but not searched);
 * ``chain_min`` - fronts with at least this many pivot blocks run their
   diagonal blocks as one chain task (negative: never);
 * ``solve_level_fronts`` - solve levels below the last level with more than
   this many fronts run level by level, the rest as one dataflow launch;
-* ``asm_cols`` - front columns per assembly workgroup;
+* ``asm_cols`` - front columns per assembly work item of a front taller than
+  the assembly tile;
 * ``solo_m`` - fronts with one pivot block and at most this many rows run as
   one task each (negative: never);
 * ``chain_inplace`` - chain fronts: the product for the next diagonal block's
@@ -49,7 +51,7 @@ from . import (TACHO_FP64, tacho_analyze, tacho_default_options, tacho_factorize
 DEFAULTS = {"u_range": 8, "chain_min": 3, "solve_level_fronts": 256, "asm_cols": 8,
             "solo_m": 192, "chain_inplace": 0}
 CANDIDATES = {
-    "u_range": (4, 8, 16),
+    "u_range": (8,),
     "chain_min": (2, 3, 4, 6, -1),
     "solve_level_fronts": (64, 256, 1024),
     "asm_cols": (4, 8, 16),

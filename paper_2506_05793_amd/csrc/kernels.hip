@@ -1446,9 +1446,10 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
   if (ticket >= count) return;
   const FrontTask tk = tasks[ticket];
   // Update-matrix blocks run after the other steps, from one call site (one
-  // inlined copy): the task's own block (kind 5) or, for a whole-front task
-  // of an update matrix of more than 64 rows, all of them.
-  bool ublocks = tk.kind == 5;
+  // inlined copy): the task's own block (kind 5, or kind 7 in a launch of
+  // its own, which awaits nothing) or, for a whole-front task of an update
+  // matrix of more than 64 rows, all of them.
+  bool ublocks = tk.kind == 5 || tk.kind == 7;
   if (!ublocks) {
   const int s = tk.s;
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], ld = S.ldL[s];
@@ -2069,12 +2070,13 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
   if (!ublocks) return;
   // a whole-front task: blocks (a, b), a >= b, in row-major lower order, on
   // the row tiles its own steps stored (visible to it after local_publish)
+  const bool whole = tk.kind == 4;
   const int r = S.front_m[tk.s] - (S.sptr[tk.s + 1] - S.sptr[tk.s]);
-  const int nub = tk.kind == 5 ? 1 : (r + kUBlock - 1) / kUBlock;
-  const int nblk = tk.kind == 5 ? 1 : nub * (nub + 1) / 2;
+  const int nub = whole ? (r + kUBlock - 1) / kUBlock : 1;
+  const int nblk = whole ? nub * (nub + 1) / 2 : 1;
   for (int q = 0; q < nblk; ++q) {
     FrontTask u = tk;
-    if (tk.kind != 5) {
+    if (whole) {
       int a = 0;
       while ((a + 1) * (a + 2) / 2 <= q) ++a;
       u = FrontTask{tk.s, q - a * (a + 1) / 2, a, 5, 0, 1, 0, 0};

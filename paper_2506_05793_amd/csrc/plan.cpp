@@ -467,7 +467,7 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
           const int32_t s = flow[bi];
           const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
           const int32_t pb = (w + kPanel - 1) / kPanel;
-          if (r <= 0) continue;
+          if (r <= 0 || kUSplit) continue;
           const int32_t ub = ublock(s);
           if (j < pb && ((j + 1) % urange == 0 || j + 1 == pb)) {
             // range ending at column j: queue its tasks
@@ -499,11 +499,31 @@ int build_plan(const Symbolic& S, Plan& P, std::string& err, int front_mode,
       if (last_group) members.insert(members.end(), solo.begin(), solo.end());
       for (int32_t s : members) {
         const double m = S.front_m[s], w = S.sptr[s + 1] - S.sptr[s], r = m - w;
-        st.flops += front_flops(S, s);
+        const bool split = kUSplit && std::find(flow.begin(), flow.end(), s) != flow.end();
+        st.flops += front_flops(S, s) - (split ? w * r * r : 0.0);
         // front read once (panel trapezoid + update triangle), written once
-        st.elems += 2.0 * ((w * m - w * (w - 1) / 2) + r * (r + 1) / 2);
+        st.elems += 2.0 * ((w * m - w * (w - 1) / 2) + (split ? 0.0 : r * (r + 1) / 2));
       }
       if (st.end > st.begin) P.steps.push_back(st);
+      if (kUSplit) {
+        // the update matrices of the group's flow fronts, in a launch of
+        // their own once every panel is done: kUBlock x kUBlock blocks over
+        // all pivot columns, no flags; blocks sharing rows get neighbouring
+        // tickets
+        Step us{kStepFront, h, (int64_t)P.ftasks.size(), 0};
+        us.ticket = P.front_launches++;
+        for (int32_t s : flow) {
+          const int32_t w = S.sptr[s + 1] - S.sptr[s], r = S.front_m[s] - w;
+          if (r <= 0) continue;
+          const int32_t nt = (r + kUBlock - 1) / kUBlock, pb = (w + kPanel - 1) / kPanel;
+          for (int32_t a = 0; a < nt; ++a)
+            for (int32_t b = 0; b <= a; ++b) P.ftasks.push_back({s, b, a, 7, 0, pb, 0, 0});
+          us.flops += (double)w * r * r;
+          us.elems += (double)r * w + (double)r * (r + 1);
+        }
+        us.end = (int64_t)P.ftasks.size();
+        if (us.end > us.begin) P.steps.push_back(us);
+      }
       }
       continue;
     }

@@ -90,6 +90,9 @@ struct GemmTile {
 // kind 6: the whole panel of front s (one pivot block, at most
 // kPanelTaskMax rows): the diagonal block and all row tiles, in order, by one
 // workgroup, which then raises the flags of all its row tiles.
+// kind 7: update-matrix block (t, j) of front s (as kind 5) over all its
+// pivot blocks [0, p1), in a launch after the one that factors the panels
+// (nothing awaited or published).
 // A kind 0 task of a chain front
 // has p0 = 1 or 2: its rows that are row tile 1 of block j + 1 also get
 // their product with row tile 1 of block j, for the chain's step j + 1,
@@ -103,6 +106,7 @@ struct FrontTask {
 constexpr int kURange = 8;     // default pivot blocks per update-matrix task
 constexpr int kUBlock = 128;   // rows and columns of an update-matrix block task (kind 5)
 constexpr int kPanelTaskMax = 1024;  // rows of the largest front whose panel is one task (kind 6)
+constexpr bool kUSplit = true;  // update matrices of the flow fronts in a launch after their panels'
 constexpr int kChainMin = 3;   // default pivot blocks from which a front's diagonal blocks form a chain
 constexpr int kPdRange = 4;    // pivot blocks per pre-accumulation range of a chain's diagonal block
 constexpr int kAsmTile = 4096;   // front entries per assembly work item (its LDS tile)
