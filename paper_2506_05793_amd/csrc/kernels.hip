@@ -3259,9 +3259,12 @@ __global__ __launch_bounds__(kThreads) void k_residual(int64_t n, const int64_t*
         for (int c = 0; c < kResLanes; ++c)
           if (c < nc) acc[c] += v * xc[c];
       }
+      // group sums of the columns in use only (nc is the same for the whole
+      // workgroup, so the skipped columns cost nothing)
       double mine = 0.0;
 #pragma unroll
       for (int c = 0; c < kResLanes; ++c) {
+        if (c >= nc) break;
         double t = acc[c];
         for (int o = kResLanes / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, kResLanes);
         mine = lane == c ? t : mine;
