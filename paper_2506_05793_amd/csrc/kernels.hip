@@ -1530,6 +1530,8 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
         }
   };
   auto fold_dacc = [&]() {
+    // on the chain's critical path: all loads in flight before the first use
+    T vd[BL][BL][4];
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
@@ -1538,8 +1540,18 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
         for (int v = 0; v < 4; ++v) {
           const int i = oi(a), jj = oj(b, v);
           const bool md = i < kb && jj < kb && i >= jj;
-          const T vd = *(md ? dbase + (i + jj * ld) : (const T*)Lp);
-          dacc[a][b][v] = (md ? T(1) : T(0)) * (vd - dacc[a][b][v]);
+          vd[a][b][v] = *(md ? dbase + (i + jj * ld) : (const T*)Lp);
+        }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int a = 0; a < BL; ++a)
+#pragma unroll
+      for (int b = 0; b < BL; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = oi(a), jj = oj(b, v);
+          const bool md = i < kb && jj < kb && i >= jj;
+          dacc[a][b][v] = (md ? T(1) : T(0)) * (vd[a][b][v] - dacc[a][b][v]);
         }
   };
   auto fold_f = [&]() {
