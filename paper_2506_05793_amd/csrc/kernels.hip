@@ -1512,6 +1512,33 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 8 ? 2 : 3) void k_front(DevS
   const int tri_off = utile ? (tt - tj) * TT : INT_MAX / 2;  // U: keep gi >= gj
   const T* dbase = Lp + c0 + (int64_t)c0 * ld;
   auto fold_acc = [&]() {
+    if constexpr (sizeof(T) == 8) {
+      // FP64: all loads in flight before the first use (on the chain's
+      // critical path); the FP32 instance has no registers to spare for it
+      T va[BL][BL][4];
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = oi(a), jj = oj(b, v);
+            const bool ma = i < arows && jj < fcols && i + tri_off >= jj;
+            va[a][b][v] = *(ma ? fbase + (i + jj * fld) : (const T*)Lp);
+          }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int a = 0; a < BL; ++a)
+#pragma unroll
+        for (int b = 0; b < BL; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = oi(a), jj = oj(b, v);
+            const bool ma = i < arows && jj < fcols && i + tri_off >= jj;
+            acc[a][b][v] = (ma ? T(1) : T(0)) * (va[a][b][v] - acc[a][b][v]);
+          }
+      return;
+    }
 #pragma unroll
     for (int a = 0; a < BL; ++a)
 #pragma unroll
