@@ -374,17 +374,27 @@ int tacho_solve_noalloc(tacho_num_t num, const double *b, double *x, int64_t nrh
  *     device memory again as the factor L (plus 128 n bytes and the sweeps'
  *     partial products of long supernodes); its accuracy
  *     depends on the condition of each supernode's L11.
+ *   TACHO_SOLVE_LEVEL_CSR: the same partitioned inverse stored as one
+ *     compressed-sparse-row matrix per level and sweep (rows of the solve
+ *     vector, 32-bit column indices), one sparse matrix-vector product per
+ *     level and sweep on the whole solve vector (no gathers, no update
+ *     vectors; an ancestor row adds the terms of all the level's fronts that
+ *     hold it, in front order).  Its setup is the partitioned inverse's plus
+ *     a copy; it keeps the inverse panels and adds about twice nnz(L) entries
+ *     of (value, index) (rows of both sweeps).
  * tacho_set_solve_variant selects the variant of later tacho_solve calls on
- * `num`.  Choosing TACHO_SOLVE_PARTITIONED_INVERSE waits for the handle's
- * factorization, builds the inverse panels on hip_stream and waits for them;
- * every later factorization of the handle (tacho_refactorize) rebuilds them on
- * its stream.  Cholesky handles (TACHO_FP64, TACHO_FP32) only: TACHO_LDLT
+ * `num`.  Choosing TACHO_SOLVE_PARTITIONED_INVERSE or TACHO_SOLVE_LEVEL_CSR
+ * waits for the handle's factorization, builds the inverse panels (and the
+ * CSR copy) on hip_stream and waits for them; every later factorization of
+ * the handle (tacho_refactorize) rebuilds them on its stream.  The CSR
+ * form needs 2 n < 2^31.  Cholesky handles (TACHO_FP64, TACHO_FP32) only: TACHO_LDLT
  * returns TACHO_ERR_INVALID, as does an unknown variant; TACHO_ERR_NOMEM if
  * the extra memory exceeds options.hbm_budget_bytes.  An FP32 handle's
  * refinement solves use it too; its FP64 fallback factor keeps the default.
  */
 #define TACHO_SOLVE_BLOCK_INVERSE 2
 #define TACHO_SOLVE_PARTITIONED_INVERSE 3
+#define TACHO_SOLVE_LEVEL_CSR 4
 int tacho_set_solve_variant(tacho_num_t num, int variant, void *hip_stream);
 
 /*

@@ -33,6 +33,7 @@ TACHO_DEBUG_SOLVE_GIVE_UP = 1
 TACHO_PROFILE_KINDS = 12
 TACHO_SOLVE_BLOCK_INVERSE = 2
 TACHO_SOLVE_PARTITIONED_INVERSE = 3
+TACHO_SOLVE_LEVEL_CSR = 4
 
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -451,7 +452,8 @@ def tacho_solve_noalloc(num: NumericHandle, b, x, stream=None, with_info: bool =
 
 def tacho_set_solve_variant(num: NumericHandle, variant: int, stream=None) -> None:
     """Select the solve variant of later solves on ``num``
-    (TACHO_SOLVE_BLOCK_INVERSE or TACHO_SOLVE_PARTITIONED_INVERSE)."""
+    (TACHO_SOLVE_BLOCK_INVERSE, TACHO_SOLVE_PARTITIONED_INVERSE or
+    TACHO_SOLVE_LEVEL_CSR)."""
     _check(_load().tacho_set_solve_variant(num.ptr, int(variant), _stream_ptr(stream)))
 
 

@@ -147,6 +147,9 @@ struct tacho_sym {
   // partitioned-inverse solves: their plan, built on first use
   std::unique_ptr<PinvPlan> Q;
   DBuf dq_setup, dq_tiles, dq_frow, dq_bcol, dq_fsum, dq_bsum, dq_small, dq_large;
+  // level CSR form of the partitioned inverse (built on first use)
+  std::unique_ptr<LevelCsr> C;
+  DBuf dc_rows, dc_rptr, dc_segs;
 };
 
 // Per-launch timing of the library's kernels on the caller's stream (hipEvents
@@ -249,8 +252,10 @@ struct tacho_num {
   bool solve_queued = false;      // a solve was queued without reading its hang flag
   hipGraphExec_t fgraph = nullptr;  // captured factorization launch sequence
   int solve_variant = TACHO_SOLVE_BLOCK_INVERSE;
+  bool csr_pending = false;  // the level CSR copy is being set up for a variant switch
   DBuf Z, yfwd;                   // partitioned inverse (layout of L) and forward result rows
   DBuf zpart;                     // its sweeps' chunk partial products
+  DBuf cvals, ccols;              // level CSR form of Z (TACHO_SOLVE_LEVEL_CSR)
   ~tacho_num() {
     if (fgraph) (void)hipGraphExecDestroy(fgraph);
     for (auto& e : ev)
@@ -693,6 +698,20 @@ int read_fail_flag(tacho_num* f, int64_t* fail_index, bool may_allocate = true) 
   return TACHO_OK;
 }
 
+int ensure_level_csr(tacho_sym* h) {
+  std::lock_guard<std::mutex> lock(h->mu);
+  if (h->C) return TACHO_OK;
+  if (2 * h->S.n >= (int64_t)INT32_MAX)
+    return fail(TACHO_ERR_INVALID, "the level CSR form needs 2 n below 2^31");
+  std::unique_ptr<LevelCsr> C(new LevelCsr());
+  build_level_csr(h->S, *C);
+  HIP_TRY(upload(h->dc_rows, C->rows));
+  HIP_TRY(upload(h->dc_rptr, C->rptr));
+  HIP_TRY(upload(h->dc_segs, C->segs));
+  h->C = std::move(C);
+  return TACHO_OK;
+}
+
 // Partitioned-inverse setup for the factor in f: Z = [I; L21] per front,
 // then the right-to-left block-column steps of the plan.
 template <typename T>
@@ -709,6 +728,13 @@ void run_pinv_setup(tacho_num* f, hipStream_t st) {
     launch_pinv_step<T>(S, Z, L, f->winv.as<T>(), tasks + Q.setup_ptr[q],
                         Q.setup_ptr[q + 1] - Q.setup_ptr[q], st);
   f->prof.end(pe, st, TACHO_K_PINV, Q.flops, 3.0 * sizeof(T) * (double)h->P.L_elems);
+  if (f->solve_variant == TACHO_SOLVE_LEVEL_CSR || f->csr_pending) {
+    const LevelCsr& C = *h->C;
+    const int pc = f->prof.begin(st);
+    launch_csr_fill<T>(S, Z, h->dc_segs.as<CsrSeg>(), (int64_t)C.segs.size(), f->ccols.as<int32_t>(),
+                       f->cvals.as<T>(), st);
+    f->prof.end(pc, st, TACHO_K_PINV, 0, (sizeof(T) * 2.0 + 4.0) * (double)C.nnz);
+  }
 }
 
 // Device work of one factorization after the values are resident: failure
@@ -783,7 +809,7 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
     enqueue_factor(f, st);
   }
   HIP_TRY(hipEventRecord(f->ev[1], st));
-  if (f->solve_variant == TACHO_SOLVE_PARTITIONED_INVERSE) {
+  if (f->solve_variant == TACHO_SOLVE_PARTITIONED_INVERSE || f->solve_variant == TACHO_SOLVE_LEVEL_CSR) {
     if (f->precision == TACHO_FP32)
       run_pinv_setup<float>(f, st);
     else
@@ -917,6 +943,36 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   // sweep gives up at once (the kernels still run to the end)
   if (h->opt.debug_flags & TACHO_DEBUG_SOLVE_GIVE_UP) launch_fill_i32(hang, 1, 1, st);
   f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
+  if (f->solve_variant == TACHO_SOLVE_LEVEL_CSR) {
+    // one CSR product per level and sweep on the whole solve vector:
+    // forward, the level's ancestor rows of y get the -Z21 y terms and its
+    // pivot rows Z11 y go to yfwd; backward, x = Z11^T yfwd - Z21^T x for
+    // the level's pivot rows, back into y
+    const LevelCsr& C = *h->C;
+    const int32_t* rws = h->dc_rows.as<int32_t>();
+    const int64_t* rp = h->dc_rptr.as<int64_t>();
+    const int32_t* cc = f->ccols.as<int32_t>();
+    const T* cv = f->cvals.as<T>();
+    T* yf = f->yfwd.as<T>();
+    const int64_t n = S.n;
+    pe = f->prof.begin(st);
+    for (int32_t lvl = 0; lvl < S.nlevels; ++lvl) {
+      launch_level_spmv<T>(rws, rp, cc, cv, C.fwd_ptr[2 * lvl], C.fwd_ptr[2 * lvl + 1], n, y, y, y, true,
+                           nrhs, st);
+      launch_level_spmv<T>(rws, rp, cc, cv, C.fwd_ptr[2 * lvl + 1], C.fwd_ptr[2 * lvl + 2], n, y, y, yf,
+                           false, nrhs, st);
+    }
+    const double half = (double)C.nnz / 2;  // about half the entries per sweep
+    f->prof.end(pe, st, TACHO_K_FORWARD, 2.0 * half * nrhs, (es + 4.0) * half + es * 2.0 * rows * nrhs);
+    pe = f->prof.begin(st);
+    for (int32_t lvl = S.nlevels - 1; lvl >= 0; --lvl)
+      launch_level_spmv<T>(rws, rp, cc, cv, C.b_ptr[lvl], C.b_ptr[lvl + 1], n, yf, y, y, false, nrhs, st);
+    f->prof.end(pe, st, TACHO_K_BACKWARD, 2.0 * half * nrhs, (es + 4.0) * half + es * 2.0 * rows * nrhs);
+    pe = f->prof.begin(st);
+    launch_solve_out<T>(Vout, y, x, ldx, nrhs, scale, accumulate, st);
+    f->prof.end(pe, st, TACHO_K_PERMUTE, 0, (double)S.n * (8.0 * nrhs + es * width) + 4.0 * S.n);
+    return;
+  }
   if (f->solve_variant == TACHO_SOLVE_PARTITIONED_INVERSE) {
     // one gather and one merged product per level and sweep; the forward
     // result goes to yfwd, the solution back into y
@@ -1461,7 +1517,8 @@ int tacho_solve_noalloc(tacho_num_t f, const double* b, double* x, int64_t nrhs,
 
 int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
   if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
-  if (variant != TACHO_SOLVE_BLOCK_INVERSE && variant != TACHO_SOLVE_PARTITIONED_INVERSE)
+  if (variant != TACHO_SOLVE_BLOCK_INVERSE && variant != TACHO_SOLVE_PARTITIONED_INVERSE &&
+      variant != TACHO_SOLVE_LEVEL_CSR)
     return fail(TACHO_ERR_INVALID, "unknown solve variant " + std::to_string(variant));
   if (variant == f->solve_variant) return TACHO_OK;
   if (variant == TACHO_SOLVE_BLOCK_INVERSE) {
@@ -1480,11 +1537,23 @@ int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
   const size_t es = elem_size(f->precision);
   const size_t zbytes = es * (size_t)std::max<int64_t>(h->P.L_elems, 1);
   const size_t ybytes = (size_t)kRowBytes * (size_t)std::max<int64_t>(h->S.n, 1);
+  const bool csr = variant == TACHO_SOLVE_LEVEL_CSR;
+  int rc = TACHO_OK;
+  if (csr) {
+    rc = ensure_level_csr(h);
+    if (rc != TACHO_OK) return rc;
+  }
+  const size_t cbytes = csr ? (es + sizeof(int32_t)) * (size_t)std::max<int64_t>(h->C->nnz, 1) : 0;
   if (h->opt.hbm_budget_bytes > 0 &&
-      (uint64_t)numeric_bytes(h, f->precision) + zbytes + ybytes > h->opt.hbm_budget_bytes)
+      (uint64_t)numeric_bytes(h, f->precision) + zbytes + ybytes + cbytes > h->opt.hbm_budget_bytes)
     return fail(TACHO_ERR_NOMEM, "the partitioned inverse would exceed the HBM budget");
-  int rc = ensure_pinv(h);
+  rc = ensure_pinv(h);
   if (rc != TACHO_OK) return rc;
+  if (csr) {
+    if (f->cvals.bytes < es * (size_t)h->C->nnz) HIP_TRY(f->cvals.alloc(es * (size_t)h->C->nnz));
+    if (f->ccols.bytes < sizeof(int32_t) * (size_t)h->C->nnz)
+      HIP_TRY(f->ccols.alloc(sizeof(int32_t) * (size_t)h->C->nnz));
+  }
   if (f->Z.bytes < zbytes) HIP_TRY(f->Z.alloc(zbytes));
   if (f->yfwd.bytes < ybytes) HIP_TRY(f->yfwd.alloc(ybytes));
   {
@@ -1493,10 +1562,12 @@ int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
     if (f->zpart.bytes < pbytes) HIP_TRY(f->zpart.alloc(pbytes));
   }
   hipStream_t st = (hipStream_t)hip_stream;
+  f->csr_pending = csr;
   if (f->precision == TACHO_FP32)
     run_pinv_setup<float>(f, st);
   else
     run_pinv_setup<double>(f, st);
+  f->csr_pending = false;
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipGetLastError());
   f->solve_variant = variant;

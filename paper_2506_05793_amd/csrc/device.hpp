@@ -112,6 +112,13 @@ void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const Pin
                      int64_t ntasks, const PinvSweepTask* sums, int64_t nsums, T* part, int nrhs,
                      hipStream_t st);
 template <typename T>
+void launch_csr_fill(const DevSym& S, const T* Z, const CsrSeg* segs, int64_t count, int32_t* cols,
+                     T* vals, hipStream_t st);
+template <typename T>
+void launch_level_spmv(const int32_t* rows, const int64_t* rptr, const int32_t* cols, const T* vals,
+                       int64_t r0, int64_t r1, int64_t n, const T* a, const T* b, T* out, bool beta,
+                       int nrhs, hipStream_t st);
+template <typename T>
 void launch_assemble(const DevSym& S, const DevNum<T>& N, const AsmItem* items, int64_t count,
                      hipStream_t st);
 template <typename T>

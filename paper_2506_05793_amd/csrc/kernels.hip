@@ -3266,6 +3266,80 @@ __global__ __launch_bounds__(kThreads) void k_pinv_bwd1(DevSym S, const T* Z, co
 }
 
 // ---------------------------------------------------------------------------
+// Level CSR form of the partitioned inverse (SpTRSV variant 4 of the Tacho
+// section): the inverse panels Z copied into one CSR per level and sweep,
+// then one sparse matrix-vector product per level.
+//
+// Copy of the segments (one front's part of one CSR row; a wave each):
+// forward pivot row (kind 0): row k of Z11 up to its diagonal, columns f + t;
+// forward ancestor row (kind 1): row k of Z21, negated, columns f + t;
+// backward row (kind 2) of pivot column c: column c of Z_s from row c down,
+// the Z11 part reading yfwd (column f + row), the Z21 part negated and
+// reading the solution (column n + solve row).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_csr_fill(DevSym S, const T* Z, const CsrSeg* segs,
+                                                       int64_t count, int32_t* cols, T* vals) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (g >= count) return;
+  const CsrSeg sg = segs[g];
+  const int s = sg.s, f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], ld = S.ldL[s];
+  const T* Zp = Z + S.L_off[s];
+  if (sg.kind == 2) {
+    const int c = sg.k;
+    const int32_t* rws = S.rows + S.rows_ptr[s];
+    for (int t = lane; t < m - c; t += 64) {
+      const int kr = c + t;
+      const T z = Zp[kr + (int64_t)c * ld];
+      vals[sg.pos + t] = kr < w ? z : -z;
+      cols[sg.pos + t] = kr < w ? f + kr : (int32_t)S.n + rws[kr];
+    }
+  } else {
+    const int len = sg.kind == 0 ? sg.k + 1 : w;
+    for (int t = lane; t < len; t += 64) {
+      const T z = Zp[sg.k + (int64_t)t * ld];
+      vals[sg.pos + t] = sg.kind == 0 ? z : -z;
+      cols[sg.pos + t] = f + t;
+    }
+  }
+}
+
+// CSR rows [r0, r1) of one level: out[rows[r]] = (beta ? out[rows[r]] : 0)
+// + sum_k vals[k] v(cols[k]), with v(c) = a[c] for c < n and b[c - n]
+// otherwise (solve rows of kRowLd values, NR of them used).  A group of
+// kSpmvLanes lanes owns a row: the lanes stride its entries (coalesced values
+// and indices), each accumulating NR columns, and the group adds its
+// partial sums in a fixed order (xor butterfly).
+constexpr int kSpmvLanes = 16;
+template <typename T, int NR>
+__global__ __launch_bounds__(kThreads) void k_level_spmv(const int32_t* rows, const int64_t* rptr,
+                                                         const int32_t* cols, const T* vals,
+                                                         int64_t r0, int64_t r1, int64_t n,
+                                                         const T* a, const T* b, T* out, int beta) {
+  const int lane = threadIdx.x & (kSpmvLanes - 1);
+  const int64_t r = r0 + (int64_t)blockIdx.x * (kThreads / kSpmvLanes) + threadIdx.x / kSpmvLanes;
+  if (r >= r1) return;  // whole groups
+  const int64_t k0 = rptr[r], k1 = rptr[r + 1];
+  T acc[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] = T(0);
+  for (int64_t k = k0 + lane; k < k1; k += kSpmvLanes) {
+    const int64_t c = cols[k];
+    const T v = vals[k];
+    const T* src = c < n ? a + c * kRowLd<T> : b + (c - n) * kRowLd<T>;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] += v * src[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+    for (int o = kSpmvLanes / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o, kSpmvLanes);
+  T* dst = out + (int64_t)rows[r] * kRowLd<T>;
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+    if (lane == q) dst[q] = (beta ? dst[q] : T(0)) + acc[q];
+}
+
+// ---------------------------------------------------------------------------
 // FP64 refinement: r = b - A x with the full symmetric CSR whose values come
 // from the lower triangle (mirror index), one thread per row and column.
 // r = b - A x for up to 16 right-hand sides per pass, with x given by rows
@@ -3662,6 +3736,28 @@ void launch_pinv_bwd(const DevSym& S, const T* Z, const T* yfwd, T* x, const Pin
 }
 
 template <typename T>
+void launch_csr_fill(const DevSym& S, const T* Z, const CsrSeg* segs, int64_t count, int32_t* cols,
+                     T* vals, hipStream_t st) {
+  if (count <= 0) return;
+  const int64_t per = kThreads / 64;
+  hipLaunchKernelGGL(k_csr_fill<T>, dim3((unsigned)((count + per - 1) / per)), dim3(kThreads), 0, st, S, Z,
+                     segs, count, cols, vals);
+}
+
+template <typename T>
+void launch_level_spmv(const int32_t* rows, const int64_t* rptr, const int32_t* cols, const T* vals,
+                       int64_t r0, int64_t r1, int64_t n, const T* a, const T* b, T* out, bool beta,
+                       int nrhs, hipStream_t st) {
+  if (r1 <= r0) return;
+  const int64_t per = kThreads / kSpmvLanes;
+  const dim3 grid((unsigned)((r1 - r0 + per - 1) / per));
+  if (nrhs == 1)
+    hipLaunchKernelGGL((k_level_spmv<T, 1>), grid, dim3(kThreads), 0, st, rows, rptr, cols, vals, r0, r1, n, a, b, out, (int)beta);
+  else
+    hipLaunchKernelGGL((k_level_spmv<T, 16>), grid, dim3(kThreads), 0, st, rows, rptr, cols, vals, r0, r1, n, a, b, out, (int)beta);
+}
+
+template <typename T>
 void launch_solve_out(const DevSym& S, const T* y, double* x, int64_t ldx, int nrhs,
                       const double* scale, int accumulate, hipStream_t st) {
   if (S.n <= 0) return;
@@ -3736,6 +3832,11 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
                                    int64_t, T*, int, hipStream_t);                               \
   template void launch_pinv_bwd<T>(const DevSym&, const T*, const T*, T*, const PinvSweepTask*,   \
                                    int64_t, const PinvSweepTask*, int64_t, T*, int, hipStream_t); \
+  template void launch_csr_fill<T>(const DevSym&, const T*, const CsrSeg*, int64_t, int32_t*, T*,  \
+                                   hipStream_t);                                                 \
+  template void launch_level_spmv<T>(const int32_t*, const int64_t*, const int32_t*, const T*,     \
+                                     int64_t, int64_t, int64_t, const T*, const T*, T*, bool, int, \
+                                     hipStream_t);                                               \
   template void launch_leaf<T>(const DevSym&, const DevNum<T>&, const int32_t*, int64_t,          \
                                hipStream_t);                                                     \
   template void launch_assemble<T>(const DevSym&, const DevNum<T>&, const AsmItem*, int64_t,      \

@@ -21,6 +21,7 @@
 //     panel; after each outer panel one update launch with K = kOuter of the
 //     remaining pivot columns; finally one update launch U -= L21 L21^T.
 #include <algorithm>
+#include <array>
 #include <climits>
 #include <map>
 #include <set>
@@ -852,6 +853,64 @@ void build_pinv_plan(const Symbolic& S, PinvPlan& Q) {
     Q.fsum_ptr.push_back((int64_t)Q.fsum.size());
     Q.bsum_ptr.push_back((int64_t)Q.bsum.size());
   }
+}
+
+void build_level_csr(const Symbolic& S, LevelCsr& C) {
+  C.rows.clear();
+  C.rptr.assign(1, 0);
+  C.segs.clear();
+  C.fwd_ptr.clear();
+  C.b_ptr.clear();
+  int64_t pos = 0;
+  auto add_row = [&](int32_t row) {
+    C.rows.push_back(row);
+    C.rptr.push_back(pos);
+  };
+  std::vector<std::array<int32_t, 3>> anc;  // (ancestor row, front, local row)
+  // forward matrices of every level (ancestor rows, then pivot rows)
+  for (int32_t h = 0; h < S.nlevels; ++h) {
+    C.fwd_ptr.push_back((int64_t)C.rows.size());
+    anc.clear();
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      const int32_t s = S.level_list[q];
+      const int32_t w = S.sptr[s + 1] - S.sptr[s];
+      for (int32_t k = w; k < S.front_m[s]; ++k) anc.push_back({S.rows[S.rows_ptr[s] + k], s, k});
+    }
+    std::sort(anc.begin(), anc.end());  // by row, then front
+    for (size_t a = 0; a < anc.size();) {
+      const int32_t row = anc[a][0];
+      for (; a < anc.size() && anc[a][0] == row; ++a) {
+        const int32_t s = anc[a][1];
+        C.segs.push_back({pos, s, anc[a][2], 1, 0});
+        pos += S.sptr[s + 1] - S.sptr[s];
+      }
+      add_row(row);
+    }
+    C.fwd_ptr.push_back((int64_t)C.rows.size());
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      const int32_t s = S.level_list[q];
+      for (int32_t c = 0; c < S.sptr[s + 1] - S.sptr[s]; ++c) {
+        C.segs.push_back({pos, s, c, 0, 0});
+        pos += c + 1;
+        add_row(S.sptr[s] + c);
+      }
+    }
+  }
+  C.fwd_ptr.push_back((int64_t)C.rows.size());
+  // backward matrices
+  for (int32_t h = 0; h < S.nlevels; ++h) {
+    C.b_ptr.push_back((int64_t)C.rows.size());
+    for (int32_t q = S.level_ptr[h]; q < S.level_ptr[h + 1]; ++q) {
+      const int32_t s = S.level_list[q];
+      for (int32_t c = 0; c < S.sptr[s + 1] - S.sptr[s]; ++c) {
+        C.segs.push_back({pos, s, c, 2, 0});
+        pos += S.front_m[s] - c;
+        add_row(S.sptr[s] + c);
+      }
+    }
+  }
+  C.b_ptr.push_back((int64_t)C.rows.size());
+  C.nnz = pos;
 }
 
 }  // namespace tacho

@@ -303,4 +303,31 @@ struct PinvPlan {
 
 void build_pinv_plan(const Symbolic& S, PinvPlan& Q);
 
+// Level CSR form of the partitioned inverse (SpTRSV variant 4 of the Tacho
+// section): for every level, the inverse of L's level part as sparse rows
+// over the solve vector, one sparse matrix-vector product per level and
+// sweep.  All matrices live back to back in one CSR (row r holds entries
+// [rptr[r], rptr[r + 1]) and acts on solve row rows[r]).  Level h's forward
+// ancestor rows are CSR rows [fwd_ptr[2h], fwd_ptr[2h + 1]) (y[i] += the
+// sum of -Z21 y over the level's pivot columns, every front of the level
+// whose rows hold i in ascending order), its forward pivot rows
+// [fwd_ptr[2h + 1], fwd_ptr[2h + 2]) (yfwd[p] = Z11 y), its backward rows
+// [b_ptr[h], b_ptr[h + 1]) (x[j] = Z11^T yfwd - Z21^T x, where a column
+// index c >= n stands for x[c - n]).  The values come from the inverse
+// panels Z, copied by segments, a segment being one front's part of a row.
+struct CsrSeg {
+  int64_t pos;     // first entry of the segment
+  int32_t s, k;    // front; local row (forward) or local column (backward)
+  int32_t kind;    // 0 forward pivot row, 1 forward ancestor row, 2 backward row
+  int32_t pad;
+};
+struct LevelCsr {
+  std::vector<int32_t> rows;
+  std::vector<int64_t> rptr;
+  std::vector<int64_t> fwd_ptr, b_ptr;
+  std::vector<CsrSeg> segs;
+  int64_t nnz = 0;
+};
+void build_level_csr(const Symbolic& S, LevelCsr& C);
+
 }  // namespace tacho
