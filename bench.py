@@ -194,14 +194,15 @@ def summarize(r, flops, tol, rho1, rho16, solve_bytes1, solve_bytes16):
 
 
 def pinv_resident(T, torch, num, A, B1, B16, X1, X16, b1, b16, solve_bytes1, solve_bytes16, tol,
-                  reps=10):
-    """Partitioned-inverse solves on the resident factor of ``num``: the
-    setup (inverse panels) once, then 1- and 16-RHS solves; the handle goes
-    back to the default variant afterwards."""
+                  reps=10, variant=None):
+    """Partitioned-inverse solves on the resident factor of ``num`` (merged
+    products, or with ``variant`` the level CSR form): the setup (inverse
+    panels) once, then 1- and 16-RHS solves; the handle goes back to the
+    default variant afterwards."""
     import numpy as np
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    T.tacho_set_solve_variant(num, T.TACHO_SOLVE_PARTITIONED_INVERSE)
+    T.tacho_set_solve_variant(num, variant or T.TACHO_SOLVE_PARTITIONED_INVERSE)
     out = {"setup_ms": (time.perf_counter() - t0) * 1e3}
     for k, B, X, b, sb in ((1, B1, X1, b1, solve_bytes1), (16, B16, X16, b16, solve_bytes16)):
         ts, iters = [], 0
@@ -594,6 +595,13 @@ def single_system(T, torch, A, tag, args, profile=True, steps=None, warmup=None)
                                                    sbytes(8, 1), sbytes(8, 16), 1e-12)
         pv = s64["partitioned_inverse"]
         log(f"[bench] {tag} FP64 partitioned inverse: setup {pv['setup_ms']:.1f} ms, solve1 "
+            f"{pv['solve_nrhs1_ms_p50']:.2f} ms, solve16 {pv['solve_nrhs16_ms_p50']:.2f} ms, rho "
+            f"{pv['rel_residual_nrhs1']:.1e}")
+        s64["level_csr"] = pinv_resident(T, torch, num64, A, B1, B16, X1, X16, b1, b16,
+                                         sbytes(8, 1), sbytes(8, 16), 1e-12, reps=5,
+                                         variant=T.TACHO_SOLVE_LEVEL_CSR)
+        pv = s64["level_csr"]
+        log(f"[bench] {tag} FP64 level CSR: setup {pv['setup_ms']:.1f} ms, solve1 "
             f"{pv['solve_nrhs1_ms_p50']:.2f} ms, solve16 {pv['solve_nrhs16_ms_p50']:.2f} ms, rho "
             f"{pv['rel_residual_nrhs1']:.1e}")
     if not args.no_mixed:
