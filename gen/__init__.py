@@ -18,4 +18,5 @@ from .matrices import (  # noqa: F401
     csr_block_diag,
     serving_requests,
     shifted,
+    nonsymmetric,
 )

@@ -280,6 +280,21 @@ def shifted(A: CSR, frac: float) -> CSR:
     return _from_scipy((M - sigma * sp.identity(A.n, format="csr")).tocsr())
 
 
+def nonsymmetric(A: CSR, skew: float, seed: int) -> CSR:
+    """Same pattern, nonsymmetric values: every off-diagonal pair (i, j), (j, i)
+    becomes a_ij (1 + skew u), a_ji (1 - skew u) with u uniform in [-1, 1]
+    drawn per pair (a convection-like perturbation of a symmetric operator)."""
+    M = A.to_scipy().tocoo()
+    rng = np.random.default_rng(seed)
+    lo, hi = np.minimum(M.row, M.col), np.maximum(M.row, M.col)
+    key = lo.astype(np.int64) * A.n + hi
+    uniq, inv = np.unique(key, return_inverse=True)
+    u = rng.uniform(-1.0, 1.0, uniq.size)[inv]
+    sign = np.where(M.row < M.col, 1.0, np.where(M.row > M.col, -1.0, 0.0))
+    data = M.data * (1.0 + skew * sign * u)
+    return _from_scipy(sp.csr_matrix((data, (M.row, M.col)), shape=M.shape))
+
+
 def laplace3d(m: int) -> CSR:
     """7-point Dirichlet Laplacian on an m^3 grid, stencil 6 / -1, natural order."""
     T = sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1])

@@ -1,7 +1,8 @@
 """ORACLE -- test infrastructure, not part of the product.
 
 Plain FP64 CPU sparse Cholesky (C, single thread, no FMA contraction), a dense
-restricted-pivoting LDL^T (``oracle.ldlt``, numpy) and the checks built on
+restricted-pivoting LDL^T (``oracle.ldlt``, numpy), a dense LU with the same
+restricted row pivoting (``oracle.lu``, numpy) and the checks built on
 them.  Only the tests, ``__graft_entry__.smoke()`` and the
 benchmark's CPU-baseline leg may import this package.  It shares no code with
 the GPU library; the only thing both sides receive is the seeded input from
