@@ -64,6 +64,20 @@ extern "C" {
  * gives TACHO_ERR_SINGULAR.  Solves use the same sweeps as Cholesky with D^{-1}
  * applied between them; no refinement. */
 #define TACHO_LDLT 2
+/* LU of a general (nonsymmetric-valued) matrix with a symmetric pattern, FP64
+ * (paper, Tacho section: LU is among the factorization types, pivots are
+ * searched only within each diagonal block).  values hold every stored entry
+ * of the caller's pattern (the analysis symmetrizes the pattern; entries it
+ * adds are zero).  Q P A P^T = L U with L unit lower triangular, U upper
+ * triangular and Q a row permutation that moves a row only within its
+ * diagonal block (the same blocks as TACHO_LDLT: relaxed supernodes cut into
+ * pieces of at most 64 columns); the pivot of column k is the entry of largest
+ * magnitude among the block's rows k and below (ties to the first row); rows
+ * below the block are never candidates.  A column whose candidates are all
+ * zero gives TACHO_ERR_SINGULAR (fail_index: its original column).  Solves use
+ * the Cholesky sweeps, forward on L and backward on U; no refinement, block
+ * inverse solve variant only. */
+#define TACHO_LU 3
 
 /* Test hooks (tacho_options.debug_flags). */
 #define TACHO_DEBUG_SOLVE_GIVE_UP 1 /* every solve raises its own hang flag before its
@@ -264,7 +278,7 @@ int tacho_get_symbolic(tacho_sym_t sym, int32_t *perm, int32_t *parent, int64_t 
  *                     only entries with row >= column are read, numerical
  *                     symmetry is the caller's contract
  *   values_on_device  0: host pointer; 1: device pointer used on hip_stream
- *   precision         TACHO_FP64, TACHO_FP32 or TACHO_LDLT
+ *   precision         TACHO_FP64, TACHO_FP32, TACHO_LDLT or TACHO_LU
  *   out               receives the numeric handle, which owns the device factor
  *   fail_index        optional; on TACHO_ERR_NOT_SPD receives the original
  *                     index of the first column (in elimination order) whose
@@ -419,6 +433,19 @@ int tacho_get_factor(tacho_num_t num, int64_t *Lp, int32_t *Li, double *Lx);
  * entry below the first column of a 2x2 pivot is zero).  Synchronizes.
  */
 int tacho_get_ldlt(tacho_num_t num, double *d, double *e, int32_t *q);
+
+/*
+ * U and the row order of a TACHO_LU factorization (host arrays, permuted
+ * numbering of P A P^T):
+ *   Up, Ui, Ux  U^T in the layout of tacho_get_factor (Up: n + 1 column
+ *               pointers, column c lists U's row c: column indices j >= c of U
+ *               in ascending order, the diagonal first; all three NULL, or all
+ *               three sized like tacho_get_factor's)
+ *   q[i]        row i of L U is row q[i] of P A P^T (NULL: not returned)
+ * L comes from tacho_get_factor (unit diagonal stored explicitly, rows in the
+ * order of L U).  Synchronizes.  TACHO_ERR_INVALID for other precisions.
+ */
+int tacho_get_lu(tacho_num_t num, int64_t *Up, int32_t *Ui, double *Ux, int32_t *q);
 
 /* Device milliseconds of the last factorization and solve (hipEvent timing on the
  * caller's stream; valid once that work has finished). */

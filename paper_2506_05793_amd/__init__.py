@@ -29,6 +29,7 @@ TACHO_FP64 = 0
 TACHO_FP32_IR = 1
 TACHO_FP32 = TACHO_FP32_IR
 TACHO_LDLT = 2
+TACHO_LU = 3
 TACHO_DEBUG_SOLVE_GIVE_UP = 1
 TACHO_PROFILE_KINDS = 12
 TACHO_SOLVE_BLOCK_INVERSE = 2
@@ -131,6 +132,7 @@ def _load():
         "tacho_set_solve_variant": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
         "tacho_get_factor": (ctypes.c_int, [_vp, _i64p, _i32p, _f64p]),
         "tacho_get_ldlt": (ctypes.c_int, [_vp, _f64p, _f64p, _i32p]),
+        "tacho_get_lu": (ctypes.c_int, [_vp, _i64p, _i32p, _f64p, _i32p]),
         "tacho_last_times": (ctypes.c_int, [_vp, _f64p, _f64p]),
         "tacho_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
         "tacho_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, _i64p, _f64p, _f64p, _f64p]),
@@ -480,6 +482,20 @@ def tacho_get_ldlt(num: NumericHandle):
     _check(_load().tacho_get_ldlt(num.ptr, d.ctypes.data_as(_f64p), e.ctypes.data_as(_f64p),
                                   q.ctypes.data_as(_i32p)))
     return d[:n], e[:n], q[:n]
+
+
+def tacho_get_lu(num: NumericHandle):
+    """(Up, Ui, Ux, q) of a TACHO_LU factorization: U^T as CSC arrays (column c
+    holds U's row c) and the row order (row i of L U is row q[i] of P A P^T)."""
+    info = tacho_query_symbolic(num.sym)
+    n, nnz = info["n"], info["nnz_factor"]
+    Up = np.empty(n + 1, np.int64)
+    Ui = np.empty(max(nnz, 1), np.int32)
+    Ux = np.empty(max(nnz, 1), np.float64)
+    q = np.empty(max(n, 1), np.int32)
+    _check(_load().tacho_get_lu(num.ptr, Up.ctypes.data_as(_i64p), Ui.ctypes.data_as(_i32p),
+                                Ux.ctypes.data_as(_f64p), q.ctypes.data_as(_i32p)))
+    return Up, Ui[:nnz], Ux[:nnz], q[:n]
 
 
 def tacho_last_times(num: NumericHandle):

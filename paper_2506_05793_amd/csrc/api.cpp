@@ -143,6 +143,7 @@ struct tacho_sym {
   // and the device view with that plan's assembly ranges
   std::unique_ptr<Plan> P1;
   DBuf d1_small, d1_asm, d1_asm_rng, d1_diag, d1_panel, d1_probs, d1_tiles;
+  DBuf d_lu_lo, d_lu_up;  // LU: caller indices of each A entry and of its transposed twin
   DevSym view1{};
   // partitioned-inverse solves: their plan, built on first use
   std::unique_ptr<PinvPlan> Q;
@@ -240,6 +241,7 @@ struct tacho_num {
   DBuf bdev, xdev;          // host-pointer staging
   DBuf rws;                 // refinement scratch (residual, norms, mask)
   DBuf ld_d, ld_e, ld_q, ld_qinv, ld_perm, ld_pinv, ld_panels;  // LDL^T: D, pivot orders, L D panels
+  DBuf lu_t, lu_u2, lu_avals, lu_vinv;  // LU: U^T panels, upper update halves, upper A entries, (U_kk^T)^{-1}
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   bool pending = false;     // factorization queued, flag not yet read
   int last_status = TACHO_OK;
@@ -466,6 +468,16 @@ int ensure_uploaded(tacho_sym* h) {
 
 // The stepwise launch plan that LDL^T factorizations run (built once per
 // symbolic handle, with the same batching parameters).
+// LU value maps (built once per symbolic handle, on first use).
+int ensure_lu_maps(tacho_sym* h) {
+  if (h->d_lu_lo.p) return TACHO_OK;
+  std::vector<int64_t> lo, up;
+  lu_value_sources(h->S, lo, up);
+  HIP_TRY(upload(h->d_lu_lo, lo));
+  HIP_TRY(upload(h->d_lu_up, up));
+  return TACHO_OK;
+}
+
 int ensure_stepwise(tacho_sym* h) {
   std::lock_guard<std::mutex> lock(h->mu);
   if (h->P1) return TACHO_OK;
@@ -513,7 +525,8 @@ int ensure_pinv(tacho_sym* h) {
 size_t elem_size(int precision) { return precision == TACHO_FP32 ? 4 : 8; }
 
 bool valid_precision(int precision) {
-  return precision == TACHO_FP64 || precision == TACHO_FP32 || precision == TACHO_LDLT;
+  return precision == TACHO_FP64 || precision == TACHO_FP32 || precision == TACHO_LDLT ||
+         precision == TACHO_LU;
 }
 
 // Device bytes a numeric handle needs (factor, update workspace, values,
@@ -546,6 +559,8 @@ int64_t numeric_bytes(const tacho_sym* h, int precision) {
   b += 4 * flow_ints(h);
   if (precision == TACHO_FP32) b += 8 * (int64_t)S.A.colind.size() + 8 * S.n;  // values, scaling
   if (precision == TACHO_LDLT) b += 8 * h->P.L_elems + 16 * S.n + 16 * S.n;    // L D, D, orders
+  if (precision == TACHO_LU)  // U^T panels and update halves, upper values and maps, V blocks, orders
+    b += 8 * h->P.L_elems + 8 * h->P.U_elems + 24 * (int64_t)S.a_src.size() + 8 * P.W_elems + 16 * S.n;
   return b;
 }
 
@@ -643,6 +658,57 @@ void run_ldlt_steps(tacho_num* f, hipStream_t st) {
                    f->ld_pinv.as<int32_t>(), f->ld_qinv.as<int32_t>(), st);
 }
 
+// LU: the stepwise plan's launches with the LU kernels; assembly and
+// trailing updates run once for the L half and once for the U^T half
+// (C -= L (U^T)^T there, C -= U^T L^T here).
+void run_lu_steps(tacho_num* f, hipStream_t st) {
+  tacho_sym* h = f->sym;
+  const DevSym& S = h->view1;
+  const Plan& P = *h->P1;
+  DevNum<double> N = num_view<double>(f);
+  DevNum<double> Nt = N;
+  Nt.L = f->lu_t.as<double>();
+  Nt.U = f->lu_u2.as<double>();
+  Nt.avals = f->lu_avals.as<double>();
+  int32_t* q = f->ld_q.as<int32_t>();
+  double* winv = f->winv.as<double>();
+  double* vinv = f->lu_vinv.as<double>();
+  const int32_t* small = h->d1_small.as<int32_t>();
+  const AsmItem* asmi = h->d1_asm.as<AsmItem>();
+  const PanelItem* dia = h->d1_diag.as<PanelItem>();
+  const PanelItem* pan = h->d1_panel.as<PanelItem>();
+  const GemmProb* probs = h->d1_probs.as<GemmProb>();
+  const GemmTile* tiles = h->d1_tiles.as<GemmTile>();
+  launch_iota(q, h->S.n, st);
+  for (const Step& s : P.steps) {
+    const int64_t cnt = s.end - s.begin;
+    const int pe = f->prof.begin(st);
+    double mult = 1.0;
+    switch (s.kind) {
+      case kStepSmall: launch_small_lu(S, N, Nt, q, small + s.begin, cnt, st); break;
+      case kStepAssemble:
+        launch_assemble<double>(S, N, asmi + s.begin, cnt, st);
+        launch_assemble<double>(S, Nt, asmi + s.begin, cnt, st);
+        mult = 2.0;
+        break;
+      case kStepDiag: launch_diag_lu(S, N, Nt, q, dia + s.begin, cnt, winv, vinv, st); break;
+      case kStepPanel:
+        launch_panel_lu(S, N, Nt, q, pan + s.begin, cnt, winv, vinv, st);
+        mult = 2.0;
+        break;
+      case kStepGemm:
+        launch_gemm<double>(N, probs, tiles + s.begin, cnt, s.tile, st, Nt.L);
+        launch_gemm<double>(Nt, probs, tiles + s.begin, cnt, s.tile, st, N.L);
+        mult = 2.0;
+        break;
+      default: break;
+    }
+    f->prof.end(pe, st, step_kind(s.kind), mult * s.flops, mult * s.elems * sizeof(double));
+  }
+  launch_ldlt_perm(h->S.n, h->d_perm.as<int32_t>(), q, f->ld_perm.as<int32_t>(),
+                   f->ld_pinv.as<int32_t>(), f->ld_qinv.as<int32_t>(), st);
+}
+
 int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, int sync,
              int64_t* fail_index);
 int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index);
@@ -650,7 +716,7 @@ int fp64_fallback(tacho_num* f, hipStream_t st, int64_t* fail_index);
 int read_fail_flag(tacho_num* f, int64_t* fail_index, bool may_allocate = true) {
   int32_t flag = INT32_MAX, hang = 0;
   HIP_TRY(hipMemcpyAsync(&flag, f->fail.p, sizeof(int32_t), hipMemcpyDeviceToHost, f->last_stream));
-  if (!f->sym->P.ftasks.empty() && f->precision != TACHO_LDLT)
+  if (!f->sym->P.ftasks.empty() && f->precision != TACHO_LDLT && f->precision != TACHO_LU)
     HIP_TRY(hipMemcpyAsync(&hang, f->flow.as<int32_t>() + flow_ints(f->sym) - 1, sizeof(int32_t),
                            hipMemcpyDeviceToHost, f->last_stream));
   HIP_TRY(hipStreamSynchronize(f->last_stream));
@@ -678,7 +744,7 @@ int read_fail_flag(tacho_num* f, int64_t* fail_index, bool may_allocate = true) 
     if (rc == TACHO_OK) f->fp32_broken = true;
     return rc;
   }
-  if (flag != INT32_MAX && f->precision == TACHO_LDLT) {
+  if (flag != INT32_MAX && (f->precision == TACHO_LDLT || f->precision == TACHO_LU)) {
     f->last_fail = f->sym->S.perm[flag];
     f->last_status = TACHO_ERR_SINGULAR;
     if (fail_index) *fail_index = f->last_fail;
@@ -757,10 +823,21 @@ void enqueue_factor(tacho_num* f, hipStream_t st) {
     run_factor_steps<float>(f, st);
   } else {
     const int pe = f->prof.begin(st);
-    launch_gather<double>(h->view, num_view<double>(f), vals, nq, st);
-    f->prof.end(pe, st, TACHO_K_GATHER, 0, nq * (8.0 + 8.0 + 8.0));
+    DevSym G = h->view;
+    if (f->precision == TACHO_LU) G.a_src = h->d_lu_lo.as<int64_t>();
+    launch_gather<double>(G, num_view<double>(f), vals, nq, st);
+    if (f->precision == TACHO_LU) {
+      DevNum<double> Nt = num_view<double>(f);
+      Nt.avals = f->lu_avals.as<double>();
+      G.a_src = h->d_lu_up.as<int64_t>();
+      launch_gather<double>(G, Nt, vals, nq, st);
+    }
+    f->prof.end(pe, st, TACHO_K_GATHER, 0,
+                (f->precision == TACHO_LU ? 2.0 : 1.0) * nq * (8.0 + 8.0 + 8.0));
     if (f->precision == TACHO_LDLT)
       run_ldlt_steps(f, st);
+    else if (f->precision == TACHO_LU)
+      run_lu_steps(f, st);
     else
       run_factor_steps<double>(f, st);
   }
@@ -799,7 +876,7 @@ int refactor(tacho_num* f, const double* values, int on_device, hipStream_t st, 
     HIP_TRY(hipMemcpyAsync(f->vals.p, values, nv * sizeof(double),
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
   HIP_TRY(hipEventRecord(f->ev[0], st));
-  if (h->opt.graphs != 0 && !f->prof.on && f->precision != TACHO_LDLT) {
+  if (h->opt.graphs != 0 && !f->prof.on && f->precision != TACHO_LDLT && f->precision != TACHO_LU) {
     if (!f->fgraph) {
       const int rc = build_factor_graph(f);
       if (rc != TACHO_OK) return rc;
@@ -865,6 +942,20 @@ int create_numeric(tacho_sym* h, int precision, tacho_num** out) {
     HIP_TRY(f->ld_pinv.alloc(sizeof(int32_t) * S.n));
     HIP_TRY(f->ld_panels.alloc(sizeof(double) * std::max<int64_t>(P.L_elems, 1)));
   }
+  if (precision == TACHO_LU) {
+    rc = ensure_stepwise(h);
+    if (rc != TACHO_OK) return rc;
+    rc = ensure_lu_maps(h);
+    if (rc != TACHO_OK) return rc;
+    HIP_TRY(f->ld_q.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->ld_qinv.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->ld_perm.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->ld_pinv.alloc(sizeof(int32_t) * S.n));
+    HIP_TRY(f->lu_t.alloc(sizeof(double) * std::max<int64_t>(P.L_elems, 1)));
+    HIP_TRY(f->lu_u2.alloc(sizeof(double) * std::max<int64_t>(P.U_elems, 1)));
+    HIP_TRY(f->lu_avals.alloc(sizeof(double) * std::max<size_t>(S.a_src.size(), 1)));
+    HIP_TRY(f->lu_vinv.alloc(sizeof(double) * std::max<int64_t>(P.W_elems, 1)));
+  }
   *out = f.release();
   return TACHO_OK;
 }
@@ -914,11 +1005,21 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   // front vectors; the result comes out in pivot order, so the output
   // permutation is P composed with it
   DevSym Vq = h->view, Vout = h->view;
-  if (f->precision == TACHO_LDLT) {
+  if (f->precision == TACHO_LDLT || f->precision == TACHO_LU) {
     Vq.lq = f->ld_q.as<int32_t>();
     Vq.lqinv = f->ld_qinv.as<int32_t>();
     Vout.perm = f->ld_perm.as<int32_t>();
     Vout.pinv = f->ld_pinv.as<int32_t>();
+  }
+  // LU: the forward sweeps take the pivot rows in pivot order (L, W); the
+  // backward sweeps run on U^T with V = (U_kk^T)^{-1}, read the ancestors'
+  // solutions in the analysis order and leave the result in that order
+  DevSym Vb = Vq;
+  if (f->precision == TACHO_LU) {
+    Vq.lqinv = nullptr;
+    Vb.lq = nullptr;
+    Vb.lqinv = nullptr;
+    Vout = h->view;
   }
   const DevSym& V = Vq;
   const Plan& P = h->P;
@@ -926,6 +1027,12 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
   T* y = f->y.as<T>();
   const T* L = f->L.as<T>();
   const T* winv = f->winv.as<T>();
+  const T* Lb = L;
+  const T* winvb = winv;
+  if (f->precision == TACHO_LU) {
+    Lb = f->lu_t.as<T>();
+    winvb = f->lu_vinv.as<T>();
+  }
   const double es = sizeof(T);
   const int width = nrhs == 1 ? 1 : kRhs;  // values per row of y and of the update vectors
   const int64_t ns = S.ns, nblk = (int64_t)P.woff.size();
@@ -1024,10 +1131,10 @@ void solve_sweep(tacho_num* f, const double* b, int64_t ldb, double* x, int64_t 
     if (f->precision == TACHO_LDLT)
       launch_apply_dinv(S.n, f->ld_d.as<double>(), f->ld_e.as<double>(), y, nrhs, st);
   pe = f->prof.begin(st);
-  launch_solve_bwd<T>(V, L, winv, y, f->part.as<T>(), h->d_bsolve.as<SolveTask>(),
+  launch_solve_bwd<T>(Vb, Lb, winvb, y, f->part.as<T>(), h->d_bsolve.as<SolveTask>(),
                       (int64_t)P.bsolve.size(), waves, nrhs, counters, ns, nblk, hang, st);
   for (int32_t lvl = P.solve_split - 1; lvl >= 0; --lvl)
-    launch_level_bwd<T>(V, L, winv, y, f->part.as<T>(), items + P.lwave_ptr[lvl],
+    launch_level_bwd<T>(Vb, Lb, winvb, y, f->part.as<T>(), items + P.lwave_ptr[lvl],
                         P.lwave_ptr[lvl + 1] - P.lwave_ptr[lvl], large + P.llarge_ptr[lvl],
                         P.llarge_ptr[lvl + 1] - P.llarge_ptr[lvl], waves, nrhs, counters, ns, nblk,
                         hang, st);
@@ -1525,7 +1632,7 @@ int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
     f->solve_variant = variant;
     return TACHO_OK;
   }
-  if (f->precision == TACHO_LDLT)
+  if (f->precision == TACHO_LDLT || f->precision == TACHO_LU)
     return fail(TACHO_ERR_INVALID, "the partitioned inverse needs a Cholesky factor");
   if (f->pending) {
     const int rc = read_fail_flag(f, nullptr);
@@ -1574,30 +1681,23 @@ int tacho_set_solve_variant(tacho_num_t f, int variant, void* hip_stream) {
   return TACHO_OK;
 }
 
-int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
-  if (!f || !Lp || !Li || !Lx) return fail(TACHO_ERR_INVALID, "NULL argument");
-  if (f->pending) {
-    int rc = read_fail_flag(f, nullptr);
-    if (rc != TACHO_OK) return rc;
-  }
-  // after an FP32 pivot breakdown the FP32 factor is not valid: the FP64
-  // factor of the same values is the one the solves fall back to
-  if (f->fp32_broken && f->fallback) f = f->fallback;
+// Panels of one factor half (L, or U^T of an LU factorization) as CSC by
+// permuted column.  remap: a front's pivot rows are stored in its pivot
+// order, the rows of its ancestors keep their analysis numbering and map
+// through the inverse pivot order (columns re-sorted by row).
+int export_panels(tacho_num* f, const DBuf& src, bool remap, int64_t* Lp, int32_t* Li, double* Lx) {
   const Symbolic& S = f->sym->S;
   const Plan& P = f->sym->P;
   const size_t es = elem_size(f->precision);
   std::vector<char> host(es * P.L_elems);
   HIP_TRY(hipDeviceSynchronize());
-  if (!host.empty()) HIP_TRY(hipMemcpy(host.data(), f->L.p, host.size(), hipMemcpyDeviceToHost));
+  if (!host.empty()) HIP_TRY(hipMemcpy(host.data(), src.p, host.size(), hipMemcpyDeviceToHost));
   Lp[0] = 0;
   for (int32_t s = 0; s < S.ns; ++s)
     for (int32_t j = S.sptr[s]; j < S.sptr[s + 1]; ++j)
       Lp[j + 1] = Lp[j] + (S.front_m[s] - (j - S.sptr[s]));
-  // LDL^T: a front's pivot rows are stored in its pivot order; the rows of
-  // its ancestors keep their analysis numbering and map through the inverse
-  // pivot order (columns re-sorted by row)
   std::vector<int32_t> qinv;
-  if (f->precision == TACHO_LDLT && S.n > 0) {
+  if (remap && S.n > 0) {
     qinv.resize(S.n);
     HIP_TRY(hipMemcpy(qinv.data(), f->ld_qinv.p, sizeof(int32_t) * S.n, hipMemcpyDeviceToHost));
   }
@@ -1627,6 +1727,40 @@ int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
         }
       }
     }
+  }
+  return TACHO_OK;
+}
+
+int tacho_get_factor(tacho_num_t f, int64_t* Lp, int32_t* Li, double* Lx) {
+  if (!f || !Lp || !Li || !Lx) return fail(TACHO_ERR_INVALID, "NULL argument");
+  if (f->pending) {
+    int rc = read_fail_flag(f, nullptr);
+    if (rc != TACHO_OK) return rc;
+  }
+  // after an FP32 pivot breakdown the FP32 factor is not valid: the FP64
+  // factor of the same values is the one the solves fall back to
+  if (f->fp32_broken && f->fallback) f = f->fallback;
+  return export_panels(f, f->L, f->precision == TACHO_LDLT || f->precision == TACHO_LU, Lp, Li, Lx);
+}
+
+int tacho_get_lu(tacho_num_t f, int64_t* Up, int32_t* Ui, double* Ux, int32_t* q) {
+  if (!f) return fail(TACHO_ERR_INVALID, "NULL handle");
+  if (f->precision != TACHO_LU) return fail(TACHO_ERR_INVALID, "not an LU factorization");
+  if (f->pending) {
+    int rc = read_fail_flag(f, nullptr);
+    if (rc != TACHO_OK) return rc;
+  } else if (f->last_status != TACHO_OK) {
+    return fail(f->last_status, "no valid factor in this handle");
+  }
+  const int64_t n = f->sym->S.n;
+  if (q && n > 0) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(q, f->ld_q.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  }
+  if (Up || Ui || Ux) {
+    if (!Up || !Ui || !Ux) return fail(TACHO_ERR_INVALID, "Up, Ui and Ux go together");
+    // U's columns keep the analysis order: no remapping
+    return export_panels(f, f->lu_t, false, Up, Ui, Ux);
   }
   return TACHO_OK;
 }

@@ -207,6 +207,17 @@ void launch_panel_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& 
 // inverse, qinv the inverse of q.
 void launch_apply_dinv(int64_t n, const double* d, const double* e, double* y, int nrhs,
                        hipStream_t st);
+// LU (restricted row pivoting): N is the L half (L panels, lower update
+// matrices, lower A entries), Nt the U^T half laid out the same way; q gets
+// the row order (row i of L U is row q[i] of P A P^T).
+void launch_small_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt,
+                     int32_t* q, const int32_t* list, int64_t count, hipStream_t st);
+void launch_diag_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt, int32_t* q,
+                    const PanelItem* items, int64_t count, double* winv, double* vinv,
+                    hipStream_t st);
+void launch_panel_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt,
+                     const int32_t* q, const PanelItem* items, int64_t count, const double* winv,
+                     const double* vinv, hipStream_t st);
 void launch_ldlt_perm(int64_t n, const int32_t* perm, const int32_t* q, int32_t* perm_num,
                       int32_t* pinv_num, int32_t* qinv, hipStream_t st);
 // p[i] = i (the identity pivot order an LDL^T factorization starts from, so

@@ -1049,6 +1049,277 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_perm(int64_t n, const int32_t
 }
 
 // ---------------------------------------------------------------------------
+// LU of a matrix with a symmetric pattern, row pivoting restricted to the
+// diagonal blocks.  A front is kept as two halves laid out like a Cholesky
+// front: the L half (N: unit lower L panel, lower triangle of the update
+// matrix, the lower A entries) and the U^T half (Nt: U^T panel, the update
+// matrix's upper triangle stored transposed, the upper A entries
+// transposed).  The assembly and the trailing updates run once per half with
+// the halves' roles swapped; the diagonal entries live in the L half (the
+// U^T half's diagonal is never read before the factorization stores U's
+// diagonal there).
+
+// Right-looking elimination of columns [0, w) of the order-m matrix F in LDS
+// (all entries, column-major, leading dimension ld), the pivot of column k
+// being the largest magnitude among rows [k, w) (ties to the first row).
+// Rows are interchanged over all m columns.  On return F holds L (below the
+// diagonal, unit diagonal implied) and U (on and above) in columns / rows
+// [0, w) and the Schur complement in [w, m)^2; the order goes to qloc.
+// Returns the first column without a usable pivot, or -1.
+__device__ inline int lu_eliminate(double* F, int ld, int m, int w, int* qloc, int* piv) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  for (int t = tid; t < w; t += kThreads) qloc[t] = t;
+  __syncthreads();
+  for (int k = 0; k < w; ++k) {
+    if (tid < 64) {
+      const int i = k + lane;
+      double v = i < w ? fabs(F[i + k * ld]) : -1.0;
+      int idx = i;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(idx, o, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+          v = ov;
+          idx = oi;
+        }
+      }
+      if (lane == 0) *piv = v > 0.0 ? idx : -1;
+    }
+    __syncthreads();
+    const int p = *piv;
+    if (p < 0) return k;
+    if (p != k) {
+      for (int t = tid; t < m; t += kThreads) {
+        const double a = F[k + t * ld];
+        F[k + t * ld] = F[p + t * ld];
+        F[p + t * ld] = a;
+      }
+      if (tid == 0) {
+        const int t = qloc[k];
+        qloc[k] = qloc[p];
+        qloc[p] = t;
+      }
+    }
+    __syncthreads();
+    const double pv = F[k + k * ld];
+    for (int i = k + 1 + tid; i < m; i += kThreads) F[i + k * ld] = F[i + k * ld] / pv;
+    __syncthreads();
+    const int nt = m - k - 1;
+    for (int t = tid; t < nt * nt; t += kThreads) {
+      const int cc = t / nt, rr = t - cc * nt;
+      const int i = k + 1 + rr, j = k + 1 + cc;
+      F[i + j * ld] -= F[i + k * ld] * F[k + j * ld];
+    }
+    __syncthreads();
+  }
+  return -1;
+}
+
+// Small fronts (m <= kSmallMax), LU: both halves assembled into one full
+// matrix in LDS, the w pivot columns eliminated, L and U^T panels and both
+// update-matrix halves written out.
+__global__ __launch_bounds__(kThreads) void k_small_lu(DevSym S, DevNum<double> N,
+                                                       DevNum<double> Nt, int32_t* qout,
+                                                       const int32_t* list) {
+  __shared__ double F[kSmallMax * kSmallMax];
+  __shared__ int qloc[kSmallMax];
+  __shared__ int piv;
+  const int s = list[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
+  const int ld = S.ldL[s];
+  for (int t = tid; t < ld * m; t += kThreads) F[t] = 0.0;
+  __syncthreads();
+  {
+    const int64_t q0 = S.acol_ptr[f], q1 = S.acol_ptr[f + w];
+    for (int64_t q = q0 + tid; q < q1; q += kThreads) {
+      const int pos = S.a_pos[q];
+      const int c = pos / ld, i = pos - c * ld;  // front row i >= column c
+      F[pos] = N.avals[q];
+      if (i != c) F[c + i * ld] = Nt.avals[q];
+    }
+  }
+  __syncthreads();
+  for (int q = S.child_ptr[s]; q < S.child_ptr[s + 1]; ++q) {
+    const int c = S.child_list[q];
+    const int wc = S.sptr[c + 1] - S.sptr[c], rc = S.front_m[c] - wc;
+    const double* Uc = N.U + S.U_off[c];
+    const double* Vc = Nt.U + S.U_off[c];
+    const int ldc = S.ldU[c];
+    const int32_t* rm = S.rmap + S.rows_ptr[c] + wc;
+    for (int t = tid; t < rc * rc; t += kThreads) {
+      const int jj = t / rc, ii = t - jj * rc;
+      if (ii >= jj) F[rm[ii] + rm[jj] * ld] += Uc[ii + (int64_t)jj * ldc];
+      if (ii > jj) F[rm[jj] + rm[ii] * ld] += Vc[ii + (int64_t)jj * ldc];
+    }
+    __syncthreads();
+  }
+  const int bad = lu_eliminate(F, ld, m, w, qloc, &piv);
+  if (bad >= 0) {
+    if (tid == 0) atomicMin(N.fail, f + bad);
+    return;
+  }
+  for (int c = tid; c < w; c += kThreads) qout[f + c] = f + qloc[c];
+  double* Lp = N.L + S.L_off[s];
+  double* Tp = Nt.L + S.L_off[s];
+  for (int t = tid; t < ld * w; t += kThreads) {
+    const int c = t / ld, i = t - c * ld;
+    Lp[t] = i > c ? F[t] : (i == c ? 1.0 : 0.0);
+    Tp[t] = (i >= c && i < m) ? F[c + i * ld] : 0.0;
+  }
+  if (r > 0) {
+    double* Us = N.U + S.U_off[s];
+    double* Vs = Nt.U + S.U_off[s];
+    const int ldu = S.ldU[s];
+    for (int t = tid; t < ldu * r; t += kThreads) {
+      const int jj = t / ldu, ii = t - jj * ldu;
+      Us[t] = ii < r ? F[(w + ii) + (w + jj) * ld] : 0.0;
+      Vs[t] = ii < r ? F[(w + jj) + (w + ii) * ld] : 0.0;
+    }
+  }
+}
+
+// Large fronts, LU step 1: diagonal block [k, k + kb) of front s (already
+// updated by the blocks before it; its lower part from the L half, its upper
+// part from the U^T half) factored with row interchanges inside the block;
+// the interchanges applied to the block's rows of L's earlier columns;
+// W = L_kk^{-1} (unit lower) and V = (U_kk^T)^{-1} (lower) kept for the
+// panels and the solves.  The block's rows of U in later columns are
+// permuted by the panel step (it reads them in pivot order).
+__global__ __launch_bounds__(kThreads) void k_diag_lu(DevSym S, DevNum<double> N,
+                                                      DevNum<double> Nt, int32_t* qout,
+                                                      const PanelItem* items, double* winv,
+                                                      double* vinv) {
+  __shared__ double F[kPanel * kDiagLd];
+  __shared__ int qloc[kPanel];
+  __shared__ int piv;
+  const PanelItem it = items[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = it.s, k = it.k, kb = it.kb;
+  const int f = S.sptr[s], ld = S.ldL[s];
+  double* Lp = N.L + S.L_off[s];
+  double* Tp = Nt.L + S.L_off[s];
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    double v = 0.0;
+    if (r < kb && c < kb)
+      v = r >= c ? Lp[(k + r) + (int64_t)(k + c) * ld] : Tp[(k + c) + (int64_t)(k + r) * ld];
+    F[c * kDiagLd + r] = v;
+  }
+  __syncthreads();
+  const int bad = lu_eliminate(F, kDiagLd, kb, kb, qloc, &piv);
+  if (bad >= 0) {
+    if (tid == 0) atomicMin(N.fail, f + k + bad);
+    return;
+  }
+  for (int c = tid; c < kb; c += kThreads) qout[f + k + c] = f + k + qloc[c];
+  for (int t = tid; t < kb * kb; t += kThreads) {
+    const int c = t / kb, r = t - c * kb;
+    if (r >= c) {
+      Lp[(k + r) + (int64_t)(k + c) * ld] = r > c ? F[c * kDiagLd + r] : 1.0;
+      Tp[(k + r) + (int64_t)(k + c) * ld] = F[r * kDiagLd + c];  // U^T(r, c) = U(c, r)
+    }
+  }
+  // rows of this block in L's earlier columns: new row r <- old row qloc[r]
+  for (int p = wave; p < k; p += kThreads / 64) {
+    double* lc = Lp + (int64_t)p * ld + k;
+    const double lv = lane < kb ? lc[qloc[lane]] : 0.0;
+    if (lane < kb) lc[lane] = lv;
+  }
+  __syncthreads();
+  // W column c (threads 0..kb-1) and V column c (threads 64..64+kb-1) by
+  // forward substitution; U^T_kk(r, j) = F(j, r)
+  double* Wout = winv + S.woff[it.wblk];
+  double* Vout = vinv + S.woff[it.wblk];
+  if (tid < kb) {
+    const int c = tid;
+    for (int r = 0; r < kb; ++r) {
+      double v = r == c ? 1.0 : 0.0;
+      if (r > c)
+        for (int j = c; j < r; ++j) v -= F[j * kDiagLd + r] * Wout[c * kb + j];
+      Wout[c * kb + r] = r < c ? 0.0 : v;
+    }
+  } else if (tid >= 64 && tid < 64 + kb) {
+    const int c = tid - 64;
+    for (int r = 0; r < kb; ++r) {
+      double v = r == c ? 1.0 : 0.0;
+      if (r >= c) {
+        for (int j = c; j < r; ++j) v -= F[r * kDiagLd + j] * Vout[c * kb + j];
+        v = v / F[r * kDiagLd + r];
+      }
+      Vout[c * kb + r] = r < c ? 0.0 : v;
+    }
+  }
+}
+
+// Large fronts, LU step 2: 64 rows below the diagonal block, on the matrix
+// cores.  blockIdx.y = 0: L21 = F21 U_kk^{-1} = B V^T with B the rows' L-half
+// entries; blockIdx.y = 1: U12^T = (Q F12)^T L_kk^{-T} = B W^T with B the
+// rows' U^T-half entries in the block's columns taken in pivot order.  The
+// result replaces the block's columns of the same rows.
+__global__ __launch_bounds__(kThreads) void k_panel_lu(DevSym S, DevNum<double> N,
+                                                       DevNum<double> Nt, const int32_t* q,
+                                                       const PanelItem* items,
+                                                       const double* winv, const double* vinv) {
+  constexpr int PAD = 4;
+  __shared__ double Bs[kPanel][kPanel + PAD];  // Bs[c][r] = B[r][c]
+  __shared__ double Ws[kPanel][kPanel + PAD];  // Ws[c'][c] = M[c][c']
+  const PanelItem it = items[blockIdx.x];
+  const bool upper = blockIdx.y == 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = it.s, k = it.k, kb = it.kb;
+  const int f = S.sptr[s], m = S.front_m[s], ld = S.ldL[s];
+  double* Pp = (upper ? Nt.L : N.L) + S.L_off[s];
+  const double* Min = (upper ? winv : vinv) + S.woff[it.wblk];
+  const int r0 = k + kb + it.chunk * kPanel;
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    Ws[c][r] = (r < kb && c < kb) ? Min[c * kb + r] : 0.0;
+    const int row = r0 + r;
+    const int src = c < kb ? (upper ? q[f + k + c] - f : k + c) : 0;
+    Bs[c][r] = (row < m && c < kb) ? Pp[row + (int64_t)src * ld] : 0.0;
+  }
+  __syncthreads();
+  typedef Vec4<double>::type V4;
+  V4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = V4{0, 0, 0, 0};
+  const int wr = wave >> 1, wc = wave & 1;
+#pragma unroll
+  for (int ks = 0; ks < kPanel / 4; ++ks) {
+    const int kk = ks * 4 + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = Bs[kk][wr * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = Ws[kk][wc * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(bv[b], av[a], acc[a][b]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr * 32 + a * 16 + (lane & 15);
+        const int c = wc * 32 + b * 16 + mfma_row<double>(lane, v);
+        Bs[c][r] = acc[a][b][v];
+      }
+  __syncthreads();
+  for (int t = tid; t < kPanel * kPanel; t += kThreads) {
+    const int c = t / kPanel, r = t - c * kPanel;
+    const int row = r0 + r;
+    if (row < m && c < kb) Pp[row + (int64_t)(k + c) * ld] = Bs[c][r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Update on the matrix cores: C[M x N] -= A[M x K] * A[0:N, :]^T for the
 // elements with row >= col.  One TT x TT output tile per workgroup, four
 // waves of (TT/2) x (TT/2) built from 16x16x4 MFMA blocks, K staged through
@@ -3586,6 +3857,27 @@ void launch_apply_dinv(int64_t n, const double* d, const double* e, double* y, i
 
 void launch_iota(int32_t* p, int64_t n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_iota, dim3(blocks_for(n)), dim3(kThreads), 0, st, p, n);
+}
+
+void launch_small_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt,
+                     int32_t* q, const int32_t* list, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_small_lu, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, Nt, q, list);
+}
+
+void launch_diag_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt, int32_t* q,
+                    const PanelItem* items, int64_t count, double* winv, double* vinv,
+                    hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_diag_lu, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, Nt, q, items, winv,
+                       vinv);
+}
+
+void launch_panel_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt,
+                     const int32_t* q, const PanelItem* items, int64_t count, const double* winv,
+                     const double* vinv, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_panel_lu, dim3((unsigned)count, 2), dim3(kThreads), 0, st, S, N, Nt, q, items,
+                       winv, vinv);
 }
 
 void launch_ldlt_perm(int64_t n, const int32_t* perm, const int32_t* q, int32_t* perm_num,

@@ -876,4 +876,34 @@ int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err) {
   return kOk;
 }
 
+// LU of a matrix with a symmetric pattern: for every A entry q of the
+// assembly maps (the lower triangle of C = P A P^T, in the maps' order), the
+// caller's index of C(row, col) (lo) and of its transposed twin C(col, row)
+// (up; -1 on the diagonal and where the caller's pattern lacks the entry).
+// The loop visits the entries in the order the maps were filled.
+void lu_value_sources(const Symbolic& S, std::vector<int64_t>& lo, std::vector<int64_t>& up) {
+  const Pattern& A = S.A;
+  const int64_t n = A.n;
+  lo.assign(S.acol_ptr[n], -1);
+  up.assign(S.acol_ptr[n], -1);
+  std::vector<int64_t> pos(S.acol_ptr.begin(), S.acol_ptr.end() - 1);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t k = A.rowptr[r]; k < A.rowptr[r + 1]; ++k) {
+      const int32_t c = A.colind[k];
+      if (r < c) continue;
+      const int32_t a = S.pinv[r], b = S.pinv[c];
+      const int64_t q = pos[std::min(a, b)]++;
+      int64_t twin = -1;
+      if (r != c) {
+        const int32_t* b0 = A.colind.data() + A.rowptr[c];
+        const int32_t* e0 = A.colind.data() + A.rowptr[c + 1];
+        const int32_t* p = std::lower_bound(b0, e0, (int32_t)r);
+        if (p != e0 && *p == (int32_t)r) twin = A.src[A.rowptr[c] + (p - b0)];
+      }
+      // C(a, b) = A(r, c) and C(b, a) = A(c, r)
+      lo[q] = a >= b ? A.src[k] : twin;
+      up[q] = a >= b ? twin : A.src[k];
+    }
+}
+
 }  // namespace tacho

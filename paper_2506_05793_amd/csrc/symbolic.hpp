@@ -85,4 +85,6 @@ bool compress_indistinguishable(const Pattern& A, Pattern& Q, std::vector<int32_
 
 int analyze_pattern(Symbolic& S, const SymOptions& opt, std::string& err);
 
+void lu_value_sources(const Symbolic& S, std::vector<int64_t>& lo, std::vector<int64_t>& up);
+
 }  // namespace tacho
