@@ -643,8 +643,44 @@ def single_system(T, torch, A, tag, args, profile=True, steps=None, warmup=None)
         roof = rec["roofline"]
         log(f"[bench] {tag} dominant {roof['kernel']}: {roof['achieved']:.2f} {roof['unit']} "
             f"({100 * roof['frac']:.1f}% of peak)")
+    if not args.no_lu and tag == "landice200":
+        lu = lu_leg(T, torch, A, sym64, B1, B16, X1, X16, b1, b16, max(3, steps // 4), 1, sbytes)
+        rec["lu"] = lu
+        log(f"[bench] {tag} LU factor {lu['factor_ms_p50']:.2f} ms ({lu['factor_tflops']:.2f} "
+            f"TFLOP/s), solve1 {lu['solve_nrhs1_ms_p50']:.2f} ms, solve16 "
+            f"{lu['solve_nrhs16_ms_p50']:.2f} ms, rho {lu['rel_residual_nrhs1']:.1e}, "
+            f"interchanges {lu['row_interchanges']}, dominant {lu['roofline']['kernel']} "
+            f"{100 * lu['roofline']['frac']:.1f}% of peak")
     del num64
     return rec
+
+
+def lu_leg(T, torch, A, sym, B1, B16, X1, X16, b1, b16, steps, warmup, sbytes):
+    """LU (restricted row pivoting) of the same pattern with nonsymmetric
+    values (each off-diagonal pair skewed by up to 30%), on the FP64 analysis:
+    refactorization + 1-RHS + 16-RHS solve steps, flops counted as
+    2 sum eta_j^2 (the update runs on both halves), and its kernel profile."""
+    import numpy as np
+    import gen
+    An = gen.nonsymmetric(A, 0.3, seed=11)
+    assert np.array_equal(An.rowptr, A.rowptr) and np.array_equal(An.colind, A.colind)
+    vals = torch.from_numpy(An.values).cuda()
+    q = T.tacho_query_symbolic(sym)
+    t0 = time.perf_counter()
+    num = T.tacho_factorize(sym, vals, T.TACHO_LU)
+    first_s = time.perf_counter() - t0
+    r = run_steps(T, torch, num, vals, B1, B16, X1, X16, steps, warmup)
+    x1, x16 = X1.cpu().numpy(), X16.cpu().numpy()
+    out = summarize(r, 2 * q["flops"], 1e-10, float(residual(An, x1, b1).max()),
+                    float(residual(An, x16, b16).max()), 2 * sbytes(8, 1), 2 * sbytes(8, 16))
+    _, _, _, order = T.tacho_get_lu(num)
+    out["row_interchanges"] = int((order != np.arange(A.n)).sum())
+    out["first_factorization_s_host"] = first_s
+    prof = kernel_profile(T, torch, num, vals, B1, B16, X1, X16)
+    out["roofline"] = roofline(prof, False, {})
+    out["kernels"] = prof
+    del num
+    return out
 
 
 def gen_rhs(n, k):
@@ -688,6 +724,8 @@ def main():
     ap.add_argument("--mixed-frac", type=float, default=0.5,
                     help="serve: fraction of factor requests in FP32 + refinement")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-lu", action="store_true",
+                    help="skip the LU measurement (land-ice pattern, nonsymmetric values)")
     ap.add_argument("--no-pinv", action="store_true",
                     help="skip the partitioned-inverse resident-solve measurement")
     ap.add_argument("--autotune", action="store_true",
@@ -799,6 +837,9 @@ def main():
         "kernels_fp64": rec.get("kernels_fp64"),
         "kernels_mixed": rec.get("kernels_mixed"),
     }
+    if rec.get("lu"):
+        line["lu"] = {k: v for k, v in rec["lu"].items() if k != "kernels"}
+        line["kernels_lu"] = rec["lu"]["kernels"]
     print(json.dumps(line), flush=True)
 
 

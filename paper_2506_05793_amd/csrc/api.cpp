@@ -705,6 +705,7 @@ void run_lu_steps(tacho_num* f, hipStream_t st) {
     }
     f->prof.end(pe, st, step_kind(s.kind), mult * s.flops, mult * s.elems * sizeof(double));
   }
+  launch_lu_rowperm(S, N, q, dia, (int64_t)P.diag_items.size(), st);
   launch_ldlt_perm(h->S.n, h->d_perm.as<int32_t>(), q, f->ld_perm.as<int32_t>(),
                    f->ld_pinv.as<int32_t>(), f->ld_qinv.as<int32_t>(), st);
 }

@@ -215,6 +215,8 @@ void launch_small_lu(const DevSym& S, const DevNum<double>& N, const DevNum<doub
 void launch_diag_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt, int32_t* q,
                     const PanelItem* items, int64_t count, double* winv, double* vinv,
                     hipStream_t st);
+void launch_lu_rowperm(const DevSym& S, const DevNum<double>& N, const int32_t* q,
+                       const PanelItem* items, int64_t count, hipStream_t st);
 void launch_panel_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt,
                      const int32_t* q, const PanelItem* items, int64_t count, const double* winv,
                      const double* vinv, hipStream_t st);

@@ -1059,61 +1059,83 @@ __global__ __launch_bounds__(kThreads) void k_ldlt_perm(int64_t n, const int32_t
 // U^T half's diagonal is never read before the factorization stores U's
 // diagonal there).
 
+// Pivot of one column by wave 0 (lane = row, a = the lane's entry): the
+// largest magnitude among lanes [lo, hi), ties to the first; *piv = its row
+// (-1 if all are zero), *pval = its signed value.
+__device__ inline void lu_pick(double a, int lane, int lo, int hi, int* piv, double* pval) {
+  double v = (lane >= lo && lane < hi) ? fabs(a) : -1.0;
+  int idx = lane;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  const double sv = __shfl(a, idx, 64);
+  if (lane == 0) {
+    *piv = v > 0.0 ? idx : -1;
+    *pval = sv;
+  }
+}
+
 // Right-looking elimination of columns [0, w) of the order-m matrix F in LDS
-// (all entries, column-major, leading dimension ld), the pivot of column k
-// being the largest magnitude among rows [k, w) (ties to the first row).
-// Rows are interchanged over all m columns.  On return F holds L (below the
-// diagonal, unit diagonal implied) and U (on and above) in columns / rows
-// [0, w) and the Schur complement in [w, m)^2; the order goes to qloc.
-// Returns the first column without a usable pivot, or -1.
-__device__ inline int lu_eliminate(double* F, int ld, int m, int w, int* qloc, int* piv) {
-  const int tid = threadIdx.x, lane = tid & 63;
+// (m <= 64; all entries, column-major, leading dimension ld), the pivot of
+// column k being the largest magnitude among rows [k, w) (ties to the first
+// row).  Rows are interchanged over all m columns.  On return F holds L
+// (below the diagonal, unit diagonal implied) and U (on and above) in
+// columns / rows [0, w) and the Schur complement in [w, m)^2; the order goes
+// to qloc.  Returns the first column without a usable pivot, or -1.
+// Two barriers per column: interchange + scaling, then the rank-1 update
+// (lane = row, waves stride the columns), during which wave 0 picks the
+// next pivot from the column it has just updated.
+__device__ inline int lu_eliminate(double* F, int ld, int m, int w, int* qloc, int* piv,
+                                   double* pval) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int t = tid; t < w; t += kThreads) qloc[t] = t;
+  if (wave == 0) lu_pick(lane < m ? F[lane] : 0.0, lane, 0, w, piv, pval);
   __syncthreads();
   for (int k = 0; k < w; ++k) {
-    if (tid < 64) {
-      const int i = k + lane;
-      double v = i < w ? fabs(F[i + k * ld]) : -1.0;
-      int idx = i;
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(v, o, 64);
-        const int oi = __shfl_xor(idx, o, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-          v = ov;
-          idx = oi;
-        }
-      }
-      if (lane == 0) *piv = v > 0.0 ? idx : -1;
-    }
-    __syncthreads();
     const int p = *piv;
     if (p < 0) return k;
+    const double pv = *pval;
     if (p != k) {
-      for (int t = tid; t < m; t += kThreads) {
-        const double a = F[k + t * ld];
-        F[k + t * ld] = F[p + t * ld];
-        F[p + t * ld] = a;
-      }
+      for (int t = tid; t < m; t += kThreads)
+        if (t != k) {
+          const double a = F[k + t * ld];
+          F[k + t * ld] = F[p + t * ld];
+          F[p + t * ld] = a;
+        }
       if (tid == 0) {
         const int t = qloc[k];
         qloc[k] = qloc[p];
         qloc[p] = t;
       }
     }
-    __syncthreads();
-    const double pv = F[k + k * ld];
-    for (int i = k + 1 + tid; i < m; i += kThreads) F[i + k * ld] = F[i + k * ld] / pv;
-    __syncthreads();
-    const int nt = m - k - 1;
-    for (int t = tid; t < nt * nt; t += kThreads) {
-      const int cc = t / nt, rr = t - cc * nt;
-      const int i = k + 1 + rr, j = k + 1 + cc;
-      F[i + j * ld] -= F[i + k * ld] * F[k + j * ld];
+    // column k: the pivot moves to row k, the old diagonal to row p
+    for (int i = k + 1 + tid; i < m; i += kThreads) {
+      if (i == p) {
+        const double a = F[k + k * ld];
+        F[k + k * ld] = pv;
+        F[p + k * ld] = a / pv;
+      } else {
+        F[i + k * ld] = F[i + k * ld] / pv;
+      }
     }
+    __syncthreads();
+    if (lane > k && lane < m) {
+      const double l = F[lane + k * ld];
+      for (int j = k + 1 + wave; j < m; j += kThreads / 64) F[lane + j * ld] -= l * F[k + j * ld];
+    }
+    if (wave == 0 && k + 1 < w)
+      lu_pick((lane > k && lane < m) ? F[lane + (k + 1) * ld] : 0.0, lane, k + 1, w, piv, pval);
     __syncthreads();
   }
   return -1;
 }
+
+static_assert(kSmallMax <= 64 && kPanel <= 64, "lu_eliminate maps the rows to one wave's lanes");
 
 // Small fronts (m <= kSmallMax), LU: both halves assembled into one full
 // matrix in LDS, the w pivot columns eliminated, L and U^T panels and both
@@ -1124,6 +1146,7 @@ __global__ __launch_bounds__(kThreads) void k_small_lu(DevSym S, DevNum<double> 
   __shared__ double F[kSmallMax * kSmallMax];
   __shared__ int qloc[kSmallMax];
   __shared__ int piv;
+  __shared__ double pval;
   const int s = list[blockIdx.x];
   const int tid = threadIdx.x;
   const int f = S.sptr[s], w = S.sptr[s + 1] - f, m = S.front_m[s], r = m - w;
@@ -1154,7 +1177,7 @@ __global__ __launch_bounds__(kThreads) void k_small_lu(DevSym S, DevNum<double> 
     }
     __syncthreads();
   }
-  const int bad = lu_eliminate(F, ld, m, w, qloc, &piv);
+  const int bad = lu_eliminate(F, ld, m, w, qloc, &piv, &pval);
   if (bad >= 0) {
     if (tid == 0) atomicMin(N.fail, f + bad);
     return;
@@ -1191,8 +1214,10 @@ __global__ __launch_bounds__(kThreads) void k_diag_lu(DevSym S, DevNum<double> N
                                                       const PanelItem* items, double* winv,
                                                       double* vinv) {
   __shared__ double F[kPanel * kDiagLd];
+  __shared__ double Xs[2 * kPanel * kDiagLd];  // W, then V, row-major by r
   __shared__ int qloc[kPanel];
   __shared__ int piv;
+  __shared__ double pval;
   const PanelItem it = items[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = it.s, k = it.k, kb = it.kb;
@@ -1207,7 +1232,7 @@ __global__ __launch_bounds__(kThreads) void k_diag_lu(DevSym S, DevNum<double> N
     F[c * kDiagLd + r] = v;
   }
   __syncthreads();
-  const int bad = lu_eliminate(F, kDiagLd, kb, kb, qloc, &piv);
+  const int bad = lu_eliminate(F, kDiagLd, kb, kb, qloc, &piv, &pval);
   if (bad >= 0) {
     if (tid == 0) atomicMin(N.fail, f + k + bad);
     return;
@@ -1220,34 +1245,62 @@ __global__ __launch_bounds__(kThreads) void k_diag_lu(DevSym S, DevNum<double> N
       Tp[(k + r) + (int64_t)(k + c) * ld] = F[r * kDiagLd + c];  // U^T(r, c) = U(c, r)
     }
   }
-  // rows of this block in L's earlier columns: new row r <- old row qloc[r]
-  for (int p = wave; p < k; p += kThreads / 64) {
-    double* lc = Lp + (int64_t)p * ld + k;
-    const double lv = lane < kb ? lc[qloc[lane]] : 0.0;
-    if (lane < kb) lc[lane] = lv;
-  }
-  __syncthreads();
-  // W column c (threads 0..kb-1) and V column c (threads 64..64+kb-1) by
-  // forward substitution; U^T_kk(r, j) = F(j, r)
-  double* Wout = winv + S.woff[it.wblk];
-  double* Vout = vinv + S.woff[it.wblk];
-  if (tid < kb) {
-    const int c = tid;
+  // (the block's rows of L's earlier columns are permuted by k_lu_rowperm
+  // once the factorization is done: nothing reads them before)
+  // W column c (wave 0, lane c) and V column c (wave 1, lane c) by forward
+  // substitution into LDS (U^T_kk(r, j) = F(j, r)), then written out
+  if (wave < 2 && lane < kb) {
+    const int c = lane;
+    double* X = Xs + wave * kPanel * kDiagLd;  // X[r * kDiagLd + c]
     for (int r = 0; r < kb; ++r) {
       double v = r == c ? 1.0 : 0.0;
-      if (r > c)
-        for (int j = c; j < r; ++j) v -= F[j * kDiagLd + r] * Wout[c * kb + j];
-      Wout[c * kb + r] = r < c ? 0.0 : v;
-    }
-  } else if (tid >= 64 && tid < 64 + kb) {
-    const int c = tid - 64;
-    for (int r = 0; r < kb; ++r) {
-      double v = r == c ? 1.0 : 0.0;
-      if (r >= c) {
-        for (int j = c; j < r; ++j) v -= F[r * kDiagLd + j] * Vout[c * kb + j];
+      if (wave == 0) {
+        if (r > c)
+          for (int j = c; j < r; ++j) v -= F[j * kDiagLd + r] * X[j * kDiagLd + c];
+      } else if (r >= c) {
+        for (int j = c; j < r; ++j) v -= F[r * kDiagLd + j] * X[j * kDiagLd + c];
         v = v / F[r * kDiagLd + r];
       }
-      Vout[c * kb + r] = r < c ? 0.0 : v;
+      X[r * kDiagLd + c] = r < c ? 0.0 : v;
+    }
+  }
+  __syncthreads();
+  double* Wout = winv + S.woff[it.wblk];
+  double* Vout = vinv + S.woff[it.wblk];
+  for (int t = tid; t < kb * kb; t += kThreads) {
+    const int c = t / kb, r = t - c * kb;
+    Wout[t] = Xs[r * kDiagLd + c];
+    Vout[t] = Xs[kPanel * kDiagLd + r * kDiagLd + c];
+  }
+}
+
+// After the LU factorization: the interchanges of every diagonal block
+// applied to its rows of L's earlier columns.  One workgroup per diagonal
+// block (s, k, kb); wave v handles the block's columns k + v, k + v + 4, ...
+// and, for each, the later blocks of the front, four at a time (their rows
+// move only within their block: new row kk + r <- old row q[f + kk + r] - f).
+__global__ __launch_bounds__(kThreads) void k_lu_rowperm(DevSym S, DevNum<double> N,
+                                                         const int32_t* q,
+                                                         const PanelItem* items) {
+  const PanelItem it = items[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s = it.s, f = S.sptr[s], w = S.sptr[s + 1] - f, ld = S.ldL[s];
+  double* Lp = N.L + S.L_off[s];
+  const int first = it.k + kPanel;  // the blocks after this one
+  for (int p = it.k + wave; p < it.k + it.kb; p += kThreads / 64) {
+    double* lc = Lp + (int64_t)p * ld;
+    for (int kk = first; kk < w; kk += 4 * kPanel) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = kk + u * kPanel + lane;
+        v[u] = row < w ? lc[q[f + row] - f] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = kk + u * kPanel + lane;
+        if (row < w) lc[row] = v[u];
+      }
     }
   }
 }
@@ -3870,6 +3923,11 @@ void launch_diag_lu(const DevSym& S, const DevNum<double>& N, const DevNum<doubl
   if (count > 0)
     hipLaunchKernelGGL(k_diag_lu, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, Nt, q, items, winv,
                        vinv);
+}
+
+void launch_lu_rowperm(const DevSym& S, const DevNum<double>& N, const int32_t* q,
+                       const PanelItem* items, int64_t count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_lu_rowperm, dim3((unsigned)count), dim3(kThreads), 0, st, S, N, q, items);
 }
 
 void launch_panel_lu(const DevSym& S, const DevNum<double>& N, const DevNum<double>& Nt,
