@@ -697,8 +697,7 @@ void run_lu_steps(tacho_num* f, hipStream_t st) {
         mult = 2.0;
         break;
       case kStepGemm:
-        launch_gemm<double>(N, probs, tiles + s.begin, cnt, s.tile, st, Nt.L);
-        launch_gemm<double>(Nt, probs, tiles + s.begin, cnt, s.tile, st, N.L);
+        launch_gemm<double>(N, probs, tiles + s.begin, cnt, s.tile, st, Nt.L, &Nt, N.L);
         mult = 2.0;
         break;
       default: break;

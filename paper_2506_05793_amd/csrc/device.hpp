@@ -129,7 +129,8 @@ void launch_panel(const DevSym& S, const DevNum<T>& N, const PanelItem* items, i
                   const T* winv, hipStream_t st);
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
-                 int tile, hipStream_t st, const T* bsrc = nullptr);
+                 int tile, hipStream_t st, const T* bsrc = nullptr, const DevNum<T>* N2 = nullptr,
+                 const T* bsrc2 = nullptr);
 // Dataflow factorization of one level's large fronts.  flow holds one
 // completion flag per row tile of every pivot block (ntiles, indexed through
 // DevSym::tbase), one pre-accumulation flag per pivot block (nblocks), one

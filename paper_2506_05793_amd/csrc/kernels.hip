@@ -1382,9 +1382,16 @@ __global__ __launch_bounds__(kThreads) void k_panel_lu(DevSym S, DevNum<double> 
 // column-major C (coalesced read-modify-write).
 // With Bsrc (the L D panels of an LDL^T factorization, laid out like L) the
 // second operand is read from there: C -= A * B[0:N, :]^T.
+// A paired launch (gridDim.y = 2) runs the same tiles a second time on
+// (N2, Bsrc2): the two halves of an LU front.
 template <typename T, int TT>
 __global__ __launch_bounds__(kThreads) void k_gemm(DevNum<T> N, const GemmProb* probs,
-                                                   const GemmTile* tiles, const T* Bsrc) {
+                                                   const GemmTile* tiles, const T* Bsrc,
+                                                   DevNum<T> N2, const T* Bsrc2) {
+  if (blockIdx.y != 0) {
+    N = N2;
+    Bsrc = Bsrc2;
+  }
   constexpr int KT = 16, PAD = 4;
   constexpr int BL = TT / 32;               // 16x16 blocks per wave dimension
   constexpr int LPT = TT * KT / kThreads;   // elements per thread per stage and operand
@@ -3880,12 +3887,14 @@ void launch_front(const DevSym& S, const DevNum<T>& N, T* winv, const FrontTask*
 
 template <typename T>
 void launch_gemm(const DevNum<T>& N, const GemmProb* probs, const GemmTile* tiles, int64_t count,
-                 int tile, hipStream_t st, const T* bsrc) {
+                 int tile, hipStream_t st, const T* bsrc, const DevNum<T>* N2, const T* bsrc2) {
   if (count <= 0) return;
+  const dim3 grid((unsigned)count, N2 ? 2 : 1);
+  const DevNum<T>& M2 = N2 ? *N2 : N;
   if (tile == kGemmTileBig)
-    hipLaunchKernelGGL((k_gemm<T, kGemmTileBig>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles, bsrc);
+    hipLaunchKernelGGL((k_gemm<T, kGemmTileBig>), grid, dim3(kThreads), 0, st, N, probs, tiles, bsrc, M2, bsrc2);
   else
-    hipLaunchKernelGGL((k_gemm<T, kGemmTile>), dim3((unsigned)count), dim3(kThreads), 0, st, N, probs, tiles, bsrc);
+    hipLaunchKernelGGL((k_gemm<T, kGemmTile>), grid, dim3(kThreads), 0, st, N, probs, tiles, bsrc, M2, bsrc2);
 }
 
 void launch_small_ldlt(const DevSym& S, const DevNum<double>& N, const DevLdlt& D,
@@ -4196,7 +4205,7 @@ void launch_select_units(int64_t nsys, const int64_t* sys_ptr, double* v, const 
   template void launch_panel<T>(const DevSym&, const DevNum<T>&, const PanelItem*, int64_t,       \
                                 const T*, hipStream_t);                                          \
   template void launch_gemm<T>(const DevNum<T>&, const GemmProb*, const GemmTile*, int64_t, int,  \
-                               hipStream_t, const T*);                                           \
+                               hipStream_t, const T*, const DevNum<T>*, const T*);               \
   template void launch_front<T>(const DevSym&, const DevNum<T>&, T*, const FrontTask*, int64_t,   \
                                 int32_t*, int64_t, int64_t, int64_t, int, int, hipStream_t);     \
   template void launch_solve_in<T>(const DevSym&, const double*, int64_t, T*, int,              \
